@@ -1,0 +1,223 @@
+"""CPU oracle for barrier-filtered contact evaluation (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the GPU library
+(``paper_2510_10256_amd``); both read the same seeded inputs from ``synth``.
+
+The arithmetic lives in ``oracle.cpp`` (plain C++17, double precision, with
+binary128 re-evaluation inside the guard band of each threshold decision).
+This module is argument marshalling plus the plain assembly of the per-pair
+results (sums over pairs, Sec. 3 and App. A: the global energy, gradient and
+Hessian fed to the Newton solve).
+
+Functions whose parity is not pinned by an independent check: none; see
+``tests/test_oracle_pins.py`` for the pin of each function.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.cpp")
+
+F_FILTERED, F_ACTIVE, F_INFEASIBLE, F_EXTENDED = 1, 2, 4, 8
+PT, EE = 0, 1
+
+# distance sub-case codes (see oracle.cpp): kind of formula per code
+CASE_KIND = np.array([0, 0, 0, 1, 1, 1, 2, 0, 0, 0, 0, 1, 1, 1, 1, 3], np.int32)
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with g++ (OpenMP, binary128 via libquadmath)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-shared", "-fPIC",
+               _SRC, "-o", _SO + ".tmp", "-lquadmath"]
+        subprocess.run(cmd, check=True)
+        os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+class _Scene(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("nv", C.c_int64), ("ne", C.c_int64), ("nt", C.c_int64),
+                ("edges", C.c_void_p), ("tris", C.c_void_p), ("ref", C.c_void_p),
+                ("h", C.c_double), ("eta", C.c_double), ("kappa", C.c_double),
+                ("filter_mode", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = C.CDLL(_SO)
+        P = C.c_void_p
+        L.orc_precompute.argtypes = [C.POINTER(_Scene), P, P, P, C.c_int32]
+        L.orc_precompute.restype = C.c_int32
+        L.orc_evaluate.argtypes = [C.POINTER(_Scene), P, C.c_int32, C.c_int32, C.c_int32]
+        L.orc_evaluate.restype = C.c_void_p
+        L.orc_count.argtypes = [P]
+        L.orc_count.restype = C.c_int64
+        L.orc_get.argtypes = [P] * 14
+        L.orc_free.argtypes = [P]
+        L.orc_pair_distance.argtypes = [C.c_int32, P, P, P]
+        L.orc_case_distance.argtypes = [C.c_int32, P, P, P, P]
+        L.orc_pair_barrier.argtypes = [C.c_int32, P, C.c_double, C.c_double, C.c_double,
+                                       P, P, P, P, P, C.c_int32]
+        L.orc_barrier_scalar.argtypes = [C.c_double, C.c_double, C.c_double, P, P, P]
+        L.orc_psd_project.argtypes = [C.c_int32, P, P, P]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def _scene_struct(scene, filter_mode=0, eta=None, kappa=None):
+    keep = []
+    edges = np.ascontiguousarray(scene.edges, np.int32)
+    tris = np.ascontiguousarray(scene.tris, np.int32)
+    ref = np.ascontiguousarray(scene.ref, np.float64)
+    keep += [edges, tris, ref]
+    s = _Scene(0 if scene.kind == "rod" else 1, scene.n_verts, scene.n_edges,
+               scene.n_tris if scene.kind == "shell" else 0,
+               _p(edges), _p(tris) if tris.size else None, _p(ref),
+               float(scene.h), float(scene.eta if eta is None else eta),
+               float(scene.kappa if kappa is None else kappa), int(filter_mode))
+    return s, keep
+
+
+def precompute(scene, filter_mode=0):
+    """Components (numbered by smallest vertex) and per-component d_min^2, d_min."""
+    s, keep = _scene_struct(scene, filter_mode)
+    comp = np.zeros(scene.n_verts, np.int32)
+    cap = scene.n_verts
+    dmin2 = np.zeros(cap, np.float64)
+    dmin = np.zeros(cap, np.float64)
+    nc = lib().orc_precompute(C.byref(s), _p(comp), _p(dmin2), _p(dmin), cap)
+    return comp, dmin2[:nc].copy(), dmin[:nc].copy()
+
+
+def evaluate(scene, x=None, mode=1, derivs=True, filter_mode=0, eta=None, kappa=None,
+             nthreads=0):
+    """Every pair of the universe with d < h, sorted by (ptype, i, j).
+
+    Returns a dict of numpy arrays: ptype, i, j, verts[n,4], code, flags, d, a,
+    eta, E, G[n,12], Hraw[n,12,12], Hpsd[n,12,12] (derivative arrays are zero
+    for inactive pairs; E is +inf for infeasible active pairs).
+    """
+    x = np.ascontiguousarray(scene.x if x is None else x, np.float64)
+    s, keep = _scene_struct(scene, filter_mode, eta, kappa)
+    L = lib()
+    h = L.orc_evaluate(C.byref(s), _p(x), int(mode), int(bool(derivs)), int(nthreads))
+    try:
+        n = L.orc_count(h)
+        out = dict(ptype=np.zeros(n, np.int32), i=np.zeros(n, np.int32), j=np.zeros(n, np.int32),
+                   verts=np.zeros((n, 4), np.int32), code=np.zeros(n, np.int32),
+                   flags=np.zeros(n, np.int32), d=np.zeros(n), a=np.zeros(n), eta=np.zeros(n),
+                   E=np.zeros(n), G=np.zeros((n, 12)))
+        if derivs:
+            out["Hraw"] = np.zeros((n, 12, 12))
+            out["Hpsd"] = np.zeros((n, 12, 12))
+        L.orc_get(h, _p(out["ptype"]), _p(out["i"]), _p(out["j"]), _p(out["verts"]),
+                  _p(out["code"]), _p(out["flags"]), _p(out["d"]), _p(out["a"]),
+                  _p(out["eta"]), _p(out["E"]), _p(out["G"]),
+                  _p(out.get("Hraw")), _p(out.get("Hpsd")))
+    finally:
+        L.orc_free(h)
+    return out
+
+
+def counts(res):
+    f = res["flags"]
+    return dict(n_c=int(f.size), n_filt=int(((f & F_FILTERED) != 0).sum()),
+                n_act=int(((f & F_ACTIVE) != 0).sum()),
+                n_infeasible=int(((f & F_INFEASIBLE) != 0).sum()))
+
+
+def pair_distance(ptype, X):
+    X = np.ascontiguousarray(X, np.float64).reshape(12)
+    D = np.zeros(1)
+    code = np.zeros(1, np.int32)
+    lib().orc_pair_distance(int(ptype), _p(X), _p(D), _p(code))
+    return float(D[0]), int(code[0])
+
+
+def case_distance(code, X):
+    """(D in double, D in binary128 as hi + lo doubles) for one sub-case formula."""
+    X = np.ascontiguousarray(X, np.float64).reshape(12)
+    o = np.zeros(3)
+    lib().orc_case_distance(int(code), _p(X), _p(o[0:1]), _p(o[1:2]), _p(o[2:3]))
+    return float(o[0]), float(o[1]), float(o[2])
+
+
+def pair_barrier(ptype, X, a, eta, kappa=1.0, quad=False):
+    X = np.ascontiguousarray(X, np.float64).reshape(12)
+    E = np.zeros(1)
+    G = np.zeros(12)
+    Hraw = np.zeros((12, 12))
+    Hpsd = np.zeros((12, 12))
+    code = np.zeros(1, np.int32)
+    lib().orc_pair_barrier(int(ptype), _p(X), float(a), float(eta), float(kappa),
+                           _p(E), _p(G), _p(Hraw), _p(Hpsd), _p(code), int(bool(quad)))
+    return dict(E=float(E[0]), G=G, Hraw=Hraw, Hpsd=Hpsd, code=int(code[0]))
+
+
+def barrier_scalar(d, a, eta):
+    o = np.zeros(3)
+    lib().orc_barrier_scalar(float(d), float(a), float(eta), _p(o[0:1]), _p(o[1:2]), _p(o[2:3]))
+    return float(o[0]), float(o[1]), float(o[2])
+
+
+def psd_project(A):
+    A = np.ascontiguousarray(A, np.float64)
+    n = A.shape[0]
+    Ap = np.zeros_like(A)
+    ev = np.zeros(n)
+    lib().orc_psd_project(int(n), _p(A), _p(Ap), _p(ev))
+    return Ap, ev
+
+
+def assemble(res, n_verts):
+    """Plain sums of the active pairs' results (row-major BSR with 3x3 blocks).
+
+    Every active pair contributes its 12-vector to the gradient of its four
+    stencil vertices, and all 16 3x3 blocks of its projected Hessian to the
+    block pattern of its four stencil vertices.  Returns E, g[V,3] and the BSR
+    arrays row_ptr[V+1], col[nnzb], val[nnzb,3,3] with columns sorted per row.
+    """
+    act = (res["flags"] & F_ACTIVE) != 0
+    feas = act & ((res["flags"] & F_INFEASIBLE) == 0)
+    E = float(np.sum(res["E"][act])) if act.any() else 0.0
+    g = np.zeros((n_verts, 3))
+    blocks = {}
+    idx = np.nonzero(feas)[0]
+    for k in idx:
+        vs = res["verts"][k]
+        G = res["G"][k].reshape(4, 3)
+        H = res["Hpsd"][k]
+        for r in range(4):
+            g[vs[r]] += G[r]
+            for c in range(4):
+                key = (int(vs[r]), int(vs[c]))
+                blk = H[3 * r:3 * r + 3, 3 * c:3 * c + 3]
+                if key in blocks:
+                    blocks[key] = blocks[key] + blk
+                else:
+                    blocks[key] = blk.copy()
+    keys = sorted(blocks)
+    row_ptr = np.zeros(n_verts + 1, np.int64)
+    for (r, c) in keys:
+        row_ptr[r + 1] += 1
+    row_ptr = np.cumsum(row_ptr)
+    col = np.array([c for (_, c) in keys], np.int32)
+    val = np.array([blocks[k] for k in keys]).reshape(-1, 3, 3) if keys else np.zeros((0, 3, 3))
+    return dict(E=E, g=g, row_ptr=row_ptr, col=col, val=val)
