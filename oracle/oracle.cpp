@@ -42,6 +42,9 @@
 
 typedef __float128 f128;
 
+// relative width of an exact tie in the extended-precision decisions
+static const double kTie = 1e-24;
+
 namespace {
 
 // ---------------------------------------------------------------------------
@@ -171,7 +174,12 @@ inline Dist point_segment(const double* p, const double* e0, const double* e1,
   return {D_pe(p, e0, e1), code_pe};
 }
 
-inline void keep_min(Dist& best, Dist c) { if (c.D < best.D) best = c; }
+// A later candidate replaces the current one only when it is closer by more
+// than a relative 1e-12: candidates that tie (up to rounding) keep the first
+// listed, so the choice of formula at region boundaries (e.g. exactly
+// parallel edges, where several point-segment sub-cases give the same
+// distance) is fixed by the listing order.
+inline void keep_min(Dist& best, Dist c) { if (c.D < best.D * (1.0 - 1e-12)) best = c; }
 
 Dist classify_pt(const double* X) {
   const double *p = X, *t0 = X + 3, *t1 = X + 6, *t2 = X + 9;
@@ -224,14 +232,17 @@ inline Dist classify(int ptype, const double* X) { return ptype == 0 ? classify_
 // of sub-case `code` at the double inputs X, where T is an exact squared
 // threshold (Tq, with Td its double approximation).  Outside a 1e-9 relative
 // band the double value D decides; inside it, the formula is re-evaluated in
-// binary128 and compared with Tq.
+// binary128.  A value within 1e-24 (relative) of T is a tie -- exact ties of
+// the geometry (lattice-aligned primitives) reach the formulas' divisions as
+// rounding noise of that size -- and a tie counts as d = thr: not below it,
+// but at most it.
 bool decide(int code, const double* X, double D, double Td, f128 Tq, bool lt, bool* used_ext) {
   if (std::fabs(D - Td) > 1e-9 * Td) return lt ? (D < Td) : (D <= Td);
   if (used_ext) *used_ext = true;
   f128 Xq[12];
   for (int k = 0; k < 12; ++k) Xq[k] = (f128)X[k];
   f128 Dq = D_case<f128>(code, Xq);
-  return lt ? (Dq < Tq) : (Dq <= Tq);
+  return lt ? (Dq < Tq * (1 - (f128)kTie)) : (Dq <= Tq * (1 + (f128)kTie));
 }
 inline f128 sq(double v) { return (f128)v * (f128)v; }  // exact square of a double
 
@@ -468,7 +479,7 @@ bool is_filtered(const Mesh& m, int ptype, int i, int j) {
   f128 q;
   ref_dist<f128>(m, ptype, i, j, &q, &g);
   f128 hq = (f128)m.h * (f128)m.h;
-  return q > 0 && q < hq;
+  return q > hq * (f128)kTie && q < hq * (1 - (f128)kTie);
 }
 
 // Incident pairs share a vertex and are not in the pair universe.
@@ -495,7 +506,9 @@ void compute_dmin(Mesh& m, int nc) {
   std::vector<std::vector<f128>> best(T, std::vector<f128>(nc, (f128)INFINITY));
   std::vector<std::vector<double>> best_rod(T, std::vector<double>(nc, std::numeric_limits<double>::infinity()));
   struct Box { double lo0, hi0, lo1, hi1; int id; };
-  const double lim = m.h * (1.0 + 1e-12);
+  double rmax = 0.0;
+  for (int64_t k = 0; k < (m.kind == 0 ? m.nv : 2 * m.nv); ++k) rmax = std::max(rmax, std::fabs(m.ref[k]));
+  const double lim = m.h * (1.0 + 1e-12) + 1e-14 * rmax;
   auto R0 = [&](int v) { return m.kind == 0 ? m.ref[v] : m.ref[2 * v]; };
   auto R1 = [&](int v) { return m.kind == 0 ? 0.0 : m.ref[2 * v + 1]; };
   auto make_box = [&](const int32_t* vs, int n, int id) {
@@ -724,7 +737,11 @@ void* orc_evaluate(const orc_scene* s, const double* x, int32_t mode, int32_t de
   for (int64_t e = 0; e < m.ne; ++e) { P p; p.id = (int)e; prim_box(m, x, 1, (int)e, p.lo, p.hi); egs.push_back(p); }
   if (m.kind == 1)
     for (int64_t t = 0; t < m.nt; ++t) { P p; p.id = (int)t; prim_box(m, x, 2, (int)t, p.lo, p.hi); trs.push_back(p); }
-  const double lim = m.h * (1.0 + 1e-12);
+  // pruning slack: the gaps are rounded double differences, so allow a few
+  // ulps of the largest coordinate beyond h
+  double amax = 0.0;
+  for (int64_t k = 0; k < 3 * m.nv; ++k) amax = std::max(amax, std::fabs(x[k]));
+  const double lim = m.h * (1.0 + 1e-12) + 1e-14 * amax;
   auto near = [&](const P& a, const P& b) {
     for (int c = 0; c < 3; ++c)
       if (std::max(b.lo[c] - a.hi[c], a.lo[c] - b.hi[c]) >= lim) return false;

@@ -339,6 +339,7 @@ def fold_profile(total_len, gaps, radius=750.0, l_mid=6000.0, l_conv=2500.0,
 def folded_cloth(seed: int = BASE_SEED + 2000, n: int = 256, ell: float = 500.0,
                  gaps=(940.0, 960.0, 980.0), n_sines: int = 8, amp=(200.0, 1500.0),
                  wavelength=(15000.0, 60000.0), ramp: float = 4000.0,
+                 shear: float = 150.0, shear_len: float = 23000.0,
                  h: float = 1000.0, dhat: float = 100.0, **fold_kw) -> Scene:
     """n x n vertex grid with rest coordinates u = ell*(i, j) (exact integers) and
     one diagonal pattern: 2(n-1)^2 triangles, 3(n-1)^2 + 2(n-1) edges.
@@ -347,7 +348,9 @@ def folded_cloth(seed: int = BASE_SEED + 2000, n: int = 256, ell: float = 500.0,
     bring layers into the active band), u2 -> Y = u2, and a seeded sum of
     ``n_sines`` plane sinusoids (amplitude U(amp), wavelength log-U(wavelength),
     random direction and phase) is added to Z outside the fold bands with a
-    smoothstep ramp of length ``ramp``.
+    smoothstep ramp of length ``ramp``.  An in-plane shear
+    Y = u2 + shear * sin(2 pi u1 / shear_len) keeps the stacked layers of a
+    fold from lining up vertex-for-vertex.
     """
     rng = np.random.default_rng(seed)
     total = (n - 1) * ell
@@ -372,7 +375,8 @@ def folded_cloth(seed: int = BASE_SEED + 2000, n: int = 256, ell: float = 500.0,
                            / lam[k] + phase[k])
     X = np.broadcast_to(prof[:, 0:1], U1.shape)
     Z = prof[:, 1:2] + w[:, None] * H
-    x = np.stack([X, U2, Z], -1).reshape(-1, 3)
+    Y = U2 + shear * np.sin(2.0 * math.pi * U1 / shear_len)
+    x = np.stack([X, Y, Z], -1).reshape(-1, 3)
     ref = np.stack([U1, U2], -1).reshape(-1, 2)
     # topology: v = i*n + j
     ii, jj = np.meshgrid(np.arange(n - 1), np.arange(n - 1), indexing="ij")
