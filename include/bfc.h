@@ -1,0 +1,190 @@
+/*
+ * bfc.h -- C ABI of libbfc: barrier-filtered contact evaluation for thickened
+ * rods and shells on one MI355X (gfx950).
+ *
+ * The method (Gomez-Nogales, Chen, Martin, Garces, Kaufman, "Unlocking
+ * Thickness Modeling for Codimensional Contact Simulation"):
+ *   - contact stencils are point-triangle and edge-edge pairs of a rod
+ *     (edge-edge only) or shell mesh (Sec. 3, first paragraphs);
+ *   - in a precomputation, stencil pairs of one connected component whose
+ *     reference (parametric-space) distance dbar lies in (0, h) are labelled,
+ *     and d_min is the smallest such distance (Sec. 3.2);
+ *   - each pair then keeps fixed barrier parameters: activation h with
+ *     offset eta, or activation d_min with no offset for labelled pairs
+ *     (Eq. 4; Eq. 1 when eta = 0);
+ *   - the barrier is the IPC log barrier of Eq. 2 with the biphasic offset of
+ *     Eq. 3, b(d, a, eta) = -(d-a)^2 ln((d-eta)/(a-eta)) for eta < d < a;
+ *   - the broad phase uses the full activation h for every pair (Sec. 3.3,
+ *     last paragraph);
+ *   - a projected Newton solver consumes the energy, gradient and per-pair
+ *     PSD-projected Hessian (App. A).
+ *
+ * Units are the caller's; all lengths must use one unit.
+ *
+ * Memory and streams.  Positions and every output buffer are device memory
+ * owned by the caller (suffix _d); host arrays carry suffix _h and are copied
+ * during the call that takes them.  A scene owns device memory for its copy
+ * of the topology, its precomputed filter data and its scratch space; it is
+ * allocated by bf_scene_create and bf_scene_reserve only, never by the four
+ * per-step calls.  Every call enqueues its work on the given stream (a
+ * hipStream_t passed as void*, NULL = default stream) and returns without
+ * synchronising unless stated.  Calls on one scene must not overlap.
+ *
+ * Errors.  Argument and state errors return synchronously with a status code
+ * and a thread-local message (bf_last_error).  Conditions found on the device
+ * (capacity overflow, infeasible pair, spin limit) set bits in the scene's
+ * device status word, read by bf_status_word (which synchronises).  On
+ * overflow the device counters still hold the required size so the caller
+ * can grow its buffers and call again.
+ */
+#ifndef BFC_H
+#define BFC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bf_scene bf_scene;
+
+typedef enum {
+  BF_OK = 0,
+  BF_E_ARG = 1,      /* invalid argument (null pointer, bad size or enum) */
+  BF_E_NOMEM = 2,    /* device allocation failed in create/reserve */
+  BF_E_DEVICE = 3,   /* a HIP runtime call failed */
+  BF_E_CAPACITY = 4, /* a caller buffer is too small (synchronous checks) */
+  BF_E_STATE = 5     /* call order violated */
+} bf_status;
+
+enum { BF_ROD = 0, BF_SHELL = 1 };
+enum { BF_FP64 = 0, BF_MIXED = 1 };
+enum { BF_FILTER_PAPER = 0, BF_FILTER_NONE = 1 };
+
+/* device status word bits */
+enum {
+  BF_S_CAND_OVERFLOW = 1u << 0,   /* candidate list capacity exceeded */
+  BF_S_ACT_OVERFLOW = 1u << 1,    /* active list capacity exceeded */
+  BF_S_INFEASIBLE = 1u << 2,      /* some active pair has d <= eta (energy +inf) */
+  BF_S_BSR_OVERFLOW = 1u << 3,    /* BSR block capacity exceeded */
+  BF_S_HASH_OVERFLOW = 1u << 4,   /* assembly hash table full (scene scratch too small) */
+  BF_S_GRID_COARSENED = 1u << 5   /* informational: grid cell size raised to fit the cell cap */
+};
+
+/* Pair types. */
+enum { BF_PT = 0, BF_EE = 1 };
+
+/* Per-active-pair flag bits. */
+enum { BF_F_FILTERED = 1, BF_F_INFEASIBLE = 4 };
+
+typedef struct {
+  double h;        /* thickness: activation distance of unfiltered pairs (Sec. 3) */
+  double eta;      /* biphasic offset of unfiltered pairs, 0 <= eta < h (Eq. 3) */
+  double kappa;    /* barrier stiffness multiplying every pair energy (> 0) */
+  int32_t prec;    /* BF_FP64, or BF_MIXED: FP32 bulk with FP64 near thresholds */
+  int32_t filter;  /* BF_FILTER_PAPER (Eq. 4) or BF_FILTER_NONE (offset barrier everywhere) */
+} bf_params;
+
+typedef struct {
+  int32_t kind;           /* BF_ROD or BF_SHELL */
+  int64_t n_verts;        /* V >= 2 */
+  int64_t n_edges;        /* E >= 1; shells: every triangle edge exactly once */
+  int64_t n_tris;         /* F (0 for rods) */
+  const int32_t* edges_h; /* [E,2] vertex ids */
+  const int32_t* tris_h;  /* [F,3] vertex ids (NULL for rods) */
+  const double* ref_h;    /* rest parameters: rods [V] arc length; shells [V,2] rest 2D coords */
+} bf_mesh_desc;
+
+/* Candidate or active pair list (structure of arrays, device memory).
+ * Point-triangle pairs: i = vertex, j = triangle.  Edge-edge: i < j edge ids. */
+typedef struct {
+  int32_t* i_d;
+  int32_t* j_d;
+  uint8_t* type_d;   /* BF_PT / BF_EE */
+  int64_t cap;       /* capacity of the three arrays */
+  int64_t* count_d;  /* [1] pairs written; if > cap, the size required */
+} bf_pairs;
+
+typedef struct {
+  bf_pairs p;           /* active pairs */
+  uint8_t* code_d;      /* [cap] distance sub-case (which features are closest) */
+  uint8_t* flags_d;     /* [cap] BF_F_* bits */
+  double* dist_d;       /* [cap] distance d */
+  int64_t* counters_d;  /* [4]: N_c (pairs with d < h), N_filt (filtered among them),
+                           N_act (active), N_infeasible */
+} bf_active;
+
+/* Per-active-pair results, row k for active pair k.  The 12 DOFs are the
+ * pair's four stencil vertices in the order (point, t0, t1, t2) or
+ * (a0, a1, b0, b1), xyz each. */
+typedef struct {
+  double* E_d;  /* [cap] kappa * b (+inf for infeasible pairs) */
+  double* G_d;  /* [cap,12] gradient */
+  double* H_d;  /* [cap,78] projected Hessian, packed upper triangle, row-major (i <= j) */
+  int64_t cap;
+} bf_local;
+
+/* Block sparse (3x3) matrix, rows = vertices, columns sorted in each row. */
+typedef struct {
+  int32_t* row_ptr_d;  /* [V+1] */
+  int32_t* col_d;      /* [cap] */
+  double* val_d;       /* [cap,9] row-major 3x3 blocks */
+  int64_t cap;
+  int64_t* nnzb_d;     /* [1] blocks written; if > cap, the number required */
+} bf_bsr;
+
+/* Create a scene: copies the topology and rest parameters to the device,
+ * labels connected components and computes d_min per component (Sec. 3.2).
+ * cand_cap / act_cap size the scene scratch used by the per-step calls
+ * (assembly hash table, scan space); they bound the pair counts the scene
+ * can process without bf_scene_reserve.  Synchronises the stream. */
+bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int64_t cand_cap,
+                          int64_t act_cap, void* stream, bf_scene** out);
+
+/* Grow the scene scratch to hold at least cand_cap candidates / act_cap
+ * active pairs (allocates; not for use inside captured graphs). */
+bf_status bf_scene_reserve(bf_scene* s, int64_t cand_cap, int64_t act_cap);
+
+bf_status bf_scene_destroy(bf_scene* s);
+
+/* Precompute results: component of each vertex, number of components, and
+ * per-component d_min^2 / d_min (+inf where no stencil pair is closer than
+ * h).  comp_h [V], dmin2_h / dmin_h [cap_c].  Synchronises. */
+bf_status bf_scene_info(bf_scene* s, int32_t* comp_h, int32_t* n_comp, double* dmin2_h,
+                        double* dmin_h, int32_t cap_c);
+
+/* Broad phase at the full activation distance h (Sec. 3.3): writes every
+ * non-incident pair whose bounding boxes, inflated by h, overlap.  The list
+ * is a superset of the pairs with d < h.  x_d: [V,3] FP64 positions. */
+bf_status build_candidates(bf_scene* s, const double* x_d, bf_pairs* cand, void* stream);
+
+/* Narrow phase and filter (Eq. 4): for each candidate computes the distance,
+ * counts it when d < h, assigns (a, eta) = (d_min, 0) to stencil pairs with
+ * 0 < dbar < h and (h, eta) otherwise, and compacts the active pairs (d < a)
+ * into act.  Threshold decisions are exact for the FP64 inputs (double
+ * precision with a double-double re-evaluation inside a guard band). */
+bf_status filter_pairs(bf_scene* s, const double* x_d, const bf_pairs* cand, bf_active* act,
+                       void* stream);
+
+/* Barrier energy, gradient and PSD-projected Hessian of every active pair
+ * (Eq. 2, Eq. 3; projection: eigenvalues clamped at zero). */
+bf_status eval_barrier(bf_scene* s, const double* x_d, const bf_active* act, bf_local* out,
+                       void* stream);
+
+/* Assembly: E_d[1] = sum of pair energies (+inf if any pair is infeasible),
+ * g_d[V,3] = sum of pair gradients, H = sum of pair Hessian blocks over the
+ * 4x4 vertex blocks of every feasible active pair's stencil. */
+bf_status assemble_grad_hess(bf_scene* s, const bf_active* act, const bf_local* loc, double* E_d,
+                             double* g_d, bf_bsr* H, void* stream);
+
+/* Device status word (BF_S_* bits) accumulated since the last clear;
+ * synchronises the stream the scene last used.  clear != 0 resets it. */
+bf_status bf_status_word(bf_scene* s, uint32_t* bits_h, int32_t clear);
+
+/* Message of the last non-OK return on this thread. */
+const char* bf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BFC_H */

@@ -1,0 +1,289 @@
+"""ctypes binding of libbfc (argument marshalling only).
+
+Every step of the contact path runs in the library's HIP kernels; this module
+allocates the caller-owned device buffers as torch tensors, passes their
+pointers and the current HIP stream, and reads results back on request.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_ROOT = os.path.dirname(_HERE)
+LIB_PATH = os.path.join(_HERE, "libbfc.so")
+SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("bfc_kernels.hip", "bfc_api.hip")]
+
+BF_OK = 0
+BF_ROD, BF_SHELL = 0, 1
+BF_FP64, BF_MIXED = 0, 1
+BF_FILTER_PAPER, BF_FILTER_NONE = 0, 1
+BF_S_CAND_OVERFLOW, BF_S_ACT_OVERFLOW, BF_S_INFEASIBLE = 1, 2, 4
+BF_S_BSR_OVERFLOW, BF_S_HASH_OVERFLOW, BF_S_GRID_COARSENED = 8, 16, 32
+BF_F_FILTERED, BF_F_INFEASIBLE = 1, 4
+
+EXPORTED = ["bf_scene_create", "bf_scene_reserve", "bf_scene_destroy", "bf_scene_info", "build_candidates",
+            "filter_pairs", "eval_barrier", "assemble_grad_hess", "bf_status_word", "bf_last_error"]
+
+
+def build(verbose: bool = False) -> str:
+    """Compile libbfc.so for gfx950 with hipcc (in-tree)."""
+    cmd = ["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-I", os.path.join(_ROOT, "include"), *SOURCES, "-o", LIB_PATH + ".tmp"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + r.stderr)
+    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+class Params(C.Structure):
+    _fields_ = [("h", C.c_double), ("eta", C.c_double), ("kappa", C.c_double),
+                ("prec", C.c_int32), ("filter", C.c_int32)]
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_verts", C.c_int64), ("n_edges", C.c_int64), ("n_tris", C.c_int64),
+                ("edges_h", C.c_void_p), ("tris_h", C.c_void_p), ("ref_h", C.c_void_p)]
+
+
+class Pairs(C.Structure):
+    _fields_ = [("i_d", C.c_void_p), ("j_d", C.c_void_p), ("type_d", C.c_void_p), ("cap", C.c_int64),
+                ("count_d", C.c_void_p)]
+
+
+class Active(C.Structure):
+    _fields_ = [("p", Pairs), ("code_d", C.c_void_p), ("flags_d", C.c_void_p), ("dist_d", C.c_void_p),
+                ("counters_d", C.c_void_p)]
+
+
+class Local(C.Structure):
+    _fields_ = [("E_d", C.c_void_p), ("G_d", C.c_void_p), ("H_d", C.c_void_p), ("cap", C.c_int64)]
+
+
+class Bsr(C.Structure):
+    _fields_ = [("row_ptr_d", C.c_void_p), ("col_d", C.c_void_p), ("val_d", C.c_void_p), ("cap", C.c_int64),
+                ("nnzb_d", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libbfc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it first (__graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.bf_scene_create.argtypes = [C.POINTER(MeshDesc), C.POINTER(Params), C.c_int64, C.c_int64, P,
+                                      C.POINTER(P)]
+        L.bf_scene_reserve.argtypes = [P, C.c_int64, C.c_int64]
+        L.bf_scene_destroy.argtypes = [P]
+        L.bf_scene_info.argtypes = [P, P, P, P, P, C.c_int32]
+        L.build_candidates.argtypes = [P, P, C.POINTER(Pairs), P]
+        L.filter_pairs.argtypes = [P, P, C.POINTER(Pairs), C.POINTER(Active), P]
+        L.eval_barrier.argtypes = [P, P, C.POINTER(Active), C.POINTER(Local), P]
+        L.assemble_grad_hess.argtypes = [P, C.POINTER(Active), C.POINTER(Local), P, P, C.POINTER(Bsr), P]
+        L.bf_status_word.argtypes = [P, C.POINTER(C.c_uint32), C.c_int32]
+        L.bf_last_error.restype = C.c_char_p
+        for name in EXPORTED[:-1]:
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != BF_OK:
+        raise RuntimeError(f"{what} failed ({rc}): {lib().bf_last_error().decode()}")
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class ContactScene:
+    """One mesh resident on the GPU plus the caller-owned buffers of a step.
+
+    ``step(x)`` enqueues build_candidates -> filter_pairs -> eval_barrier ->
+    assemble_grad_hess on the current torch stream.  Capacities start from
+    size estimates and grow when the device reports an overflow (``run``
+    retries the step; ``step`` never synchronises).
+    """
+
+    def __init__(self, scene, prec=BF_FP64, filter_mode=BF_FILTER_PAPER, kappa=None, eta=None,
+                 cand_cap=None, act_cap=None, bsr_cap=None, device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.kind = BF_ROD if scene.kind == "rod" else BF_SHELL
+        self.nv, self.ne = scene.n_verts, scene.n_edges
+        self.nt = scene.n_tris if self.kind == BF_SHELL else 0
+        self.h = float(scene.h)
+        self.eta = float(scene.eta if eta is None else eta)
+        self.kappa = float(scene.kappa if kappa is None else kappa)
+        nprims = self.ne + self.nt + (self.nv if self.kind == BF_SHELL else 0)
+        self.cand_cap = int(cand_cap or max(4096, 40 * nprims))
+        self.act_cap = int(act_cap or max(4096, 4 * nprims))
+        self.bsr_cap = int(bsr_cap or max(4096, 8 * self.act_cap))
+        self._edges = np.ascontiguousarray(scene.edges, np.int32)
+        self._tris = np.ascontiguousarray(scene.tris, np.int32) if self.nt else None
+        self._ref = np.ascontiguousarray(scene.ref, np.float64)
+        desc = MeshDesc(self.kind, self.nv, self.ne, self.nt, self._edges.ctypes.data,
+                        self._tris.ctypes.data if self.nt else None, self._ref.ctypes.data)
+        prm = Params(self.h, self.eta, self.kappa, int(prec), int(filter_mode))
+        self.prec, self.filter_mode = int(prec), int(filter_mode)
+        h = C.c_void_p()
+        _check(lib().bf_scene_create(C.byref(desc), C.byref(prm), self.cand_cap, self.act_cap,
+                                     C.c_void_p(self._stream()), C.byref(h)), "bf_scene_create")
+        self.handle = h
+        self._alloc()
+
+    # -- buffers -------------------------------------------------------------
+    def _stream(self):
+        return self.torch.cuda.current_stream(self.device).cuda_stream
+
+    def _alloc(self):
+        t, dev = self.torch, self.device
+        z = lambda n, dt: t.zeros(n, dtype=dt, device=dev)
+        self.c_i, self.c_j, self.c_t = z(self.cand_cap, t.int32), z(self.cand_cap, t.int32), z(self.cand_cap, t.uint8)
+        self.c_n = z(1, t.int64)
+        self.a_i, self.a_j, self.a_t = z(self.act_cap, t.int32), z(self.act_cap, t.int32), z(self.act_cap, t.uint8)
+        self.a_n = z(1, t.int64)
+        self.a_code, self.a_flags = z(self.act_cap, t.uint8), z(self.act_cap, t.uint8)
+        self.a_dist = z(self.act_cap, t.float64)
+        self.counters = z(4, t.int64)
+        self.l_E, self.l_G, self.l_H = z(self.act_cap, t.float64), z((self.act_cap, 12), t.float64), \
+            z((self.act_cap, 78), t.float64)
+        self.E = z(1, t.float64)
+        self.g = z((self.nv, 3), t.float64)
+        self.row_ptr = z(self.nv + 1, t.int32)
+        self.col = z(self.bsr_cap, t.int32)
+        self.val = z((self.bsr_cap, 9), t.float64)
+        self.nnzb = z(1, t.int64)
+        self._cand = Pairs(self.c_i.data_ptr(), self.c_j.data_ptr(), self.c_t.data_ptr(), self.cand_cap,
+                           self.c_n.data_ptr())
+        self._act = Active(Pairs(self.a_i.data_ptr(), self.a_j.data_ptr(), self.a_t.data_ptr(), self.act_cap,
+                                 self.a_n.data_ptr()),
+                           self.a_code.data_ptr(), self.a_flags.data_ptr(), self.a_dist.data_ptr(),
+                           self.counters.data_ptr())
+        self._loc = Local(self.l_E.data_ptr(), self.l_G.data_ptr(), self.l_H.data_ptr(), self.act_cap)
+        self._bsr = Bsr(self.row_ptr.data_ptr(), self.col.data_ptr(), self.val.data_ptr(), self.bsr_cap,
+                        self.nnzb.data_ptr())
+
+    # -- the four calls -------------------------------------------------------
+    def build_candidates(self, x):
+        _check(lib().build_candidates(self.handle, _ptr(x), C.byref(self._cand), C.c_void_p(self._stream())),
+               "build_candidates")
+
+    def filter_pairs(self, x):
+        _check(lib().filter_pairs(self.handle, _ptr(x), C.byref(self._cand), C.byref(self._act),
+                                  C.c_void_p(self._stream())), "filter_pairs")
+
+    def eval_barrier(self, x):
+        _check(lib().eval_barrier(self.handle, _ptr(x), C.byref(self._act), C.byref(self._loc),
+                                  C.c_void_p(self._stream())), "eval_barrier")
+
+    def assemble_grad_hess(self):
+        _check(lib().assemble_grad_hess(self.handle, C.byref(self._act), C.byref(self._loc), _ptr(self.E),
+                                        _ptr(self.g), C.byref(self._bsr), C.c_void_p(self._stream())),
+               "assemble_grad_hess")
+
+    def step(self, x):
+        """Enqueue one pass of the whole path on the current stream (no sync)."""
+        self.build_candidates(x)
+        self.filter_pairs(x)
+        self.eval_barrier(x)
+        self.assemble_grad_hess()
+
+    def status(self, clear=True):
+        v = C.c_uint32(0)
+        _check(lib().bf_status_word(self.handle, C.byref(v), int(clear)), "bf_status_word")
+        return int(v.value)
+
+    def run(self, x, max_tries=4):
+        """Step, then grow any overflowing buffer and step again (synchronises)."""
+        x = self._as_x(x)
+        for _ in range(max_tries):
+            self.step(x)
+            st = self.status(clear=True)
+            over = st & (BF_S_CAND_OVERFLOW | BF_S_ACT_OVERFLOW | BF_S_BSR_OVERFLOW | BF_S_HASH_OVERFLOW)
+            if not over:
+                return st
+            nc, na, nb = int(self.c_n.item()), int(self.a_n.item()), int(self.nnzb.item())
+            grow = False
+            if nc > self.cand_cap:
+                self.cand_cap = nc + nc // 4 + 1024
+                grow = True
+            if na > self.act_cap or (st & BF_S_HASH_OVERFLOW):
+                self.act_cap = max(na + na // 4 + 1024, self.act_cap * 2 if st & BF_S_HASH_OVERFLOW else 0)
+                grow = True
+            if nb > self.bsr_cap or (st & BF_S_ACT_OVERFLOW):
+                self.bsr_cap = max(nb + nb // 4 + 1024, 8 * self.act_cap)
+                grow = True
+            if grow:
+                _check(lib().bf_scene_reserve(self.handle, self.cand_cap, self.act_cap), "bf_scene_reserve")
+                self._alloc()
+        raise RuntimeError("buffers kept overflowing")
+
+    def _as_x(self, x):
+        t = self.torch
+        if not isinstance(x, t.Tensor):
+            x = t.as_tensor(np.ascontiguousarray(x, np.float64))
+        x = x.to(device=self.device, dtype=t.float64).contiguous()
+        assert x.shape == (self.nv, 3)
+        return x
+
+    # -- results ----------------------------------------------------------------
+    def info(self):
+        comp = np.zeros(self.nv, np.int32)
+        nc = C.c_int32(0)
+        _check(lib().bf_scene_info(self.handle, comp.ctypes.data, C.byref(nc), None, None, 0), "bf_scene_info")
+        d2 = np.zeros(nc.value)
+        d = np.zeros(nc.value)
+        _check(lib().bf_scene_info(self.handle, None, None, d2.ctypes.data, d.ctypes.data, nc.value),
+               "bf_scene_info")
+        return comp, d2, d
+
+    def counts(self):
+        c = self.counters.cpu().numpy()
+        return dict(n_bp=int(self.c_n.item()), n_c=int(c[0]), n_filt=int(c[1]), n_act=int(c[2]),
+                    n_infeasible=int(c[3]), nnzb=int(self.nnzb.item()))
+
+    def results(self):
+        """Copy the step's outputs to host numpy arrays (synchronises)."""
+        self.torch.cuda.synchronize(self.device)
+        na = min(int(self.a_n.item()), self.act_cap)
+        nc = min(int(self.c_n.item()), self.cand_cap)
+        nb = min(int(self.nnzb.item()), self.bsr_cap)
+        H = self.l_H[:na].cpu().numpy()
+        iu = np.triu_indices(12)
+        Hf = np.zeros((na, 12, 12))
+        Hf[:, iu[0], iu[1]] = H
+        Hf[:, iu[1], iu[0]] = H
+        return dict(
+            cand=np.stack([self.c_t[:nc].cpu().numpy().astype(np.int32), self.c_i[:nc].cpu().numpy(),
+                           self.c_j[:nc].cpu().numpy()], 1),
+            ptype=self.a_t[:na].cpu().numpy().astype(np.int32), i=self.a_i[:na].cpu().numpy(),
+            j=self.a_j[:na].cpu().numpy(), code=self.a_code[:na].cpu().numpy().astype(np.int32),
+            flags=self.a_flags[:na].cpu().numpy().astype(np.int32), d=self.a_dist[:na].cpu().numpy(),
+            E=self.l_E[:na].cpu().numpy(), G=self.l_G[:na].cpu().numpy(), Hpsd=Hf,
+            E_total=float(self.E.item()), g=self.g.cpu().numpy(),
+            row_ptr=self.row_ptr.cpu().numpy().astype(np.int64), col=self.col[:nb].cpu().numpy(),
+            val=self.val[:nb].cpu().numpy().reshape(-1, 3, 3), counts=self.counts())
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().bf_scene_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,394 @@
+// C ABI of libbfc: scene lifecycle, argument checks, workspace, and the four
+// per-step calls of the contact path (build_candidates, filter_pairs,
+// eval_barrier, assemble_grad_hess).  See include/bfc.h.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "bfc_kernels.h"
+
+using namespace bfc;
+
+struct bf_scene {
+  bf_params prm;
+  int kind = 0, nv = 0, ne = 0, nt = 0, nc = 0;
+  int* d_edges = nullptr;
+  int* d_tris = nullptr;
+  double* d_ref = nullptr;
+  int* d_comp = nullptr;
+  double* d_dmin = nullptr;
+  double* d_thr2 = nullptr;
+  unsigned* d_status = nullptr;
+  std::vector<int> comp_h;
+  std::vector<double> dmin2_h, dmin_h;
+  BroadWs bw{};
+  AsmWs aw{};
+  long long act_cap = 0;
+  std::vector<void*> allocs;      // scene-lifetime allocations
+  std::vector<void*> asm_allocs;  // assembly scratch (regrown by reserve)
+  hipStream_t last = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+bf_status fail(bf_status s, const char* msg) {
+  g_err = msg;
+  return s;
+}
+bf_status fail_hip(hipError_t e, const char* where) {
+  g_err = std::string(where) + ": " + hipGetErrorString(e);
+  return BF_E_DEVICE;
+}
+
+template <class T> T* dalloc(std::vector<void*>& list, size_t n, hipError_t* err) {
+  void* p = nullptr;
+  size_t bytes = n * sizeof(T);
+  if (bytes == 0) bytes = sizeof(T);
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    *err = e;
+    return nullptr;
+  }
+  list.push_back(p);
+  return (T*)p;
+}
+
+long long next_pow2(long long v) {
+  long long p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+SceneDev dev_view(const bf_scene* s) {
+  SceneDev S;
+  S.kind = s->kind;
+  S.nv = s->nv;
+  S.ne = s->ne;
+  S.nt = s->nt;
+  S.edges = s->d_edges;
+  S.tris = s->d_tris;
+  S.ref = s->d_ref;
+  S.comp = s->d_comp;
+  S.dmin = s->d_dmin;
+  S.thr2 = s->d_thr2;
+  S.h = s->prm.h;
+  S.eta = s->prm.eta;
+  S.kappa = s->prm.kappa;
+  S.filter = s->prm.filter;
+  S.mixed = s->prm.prec == BF_MIXED;
+  return S;
+}
+
+bf_status alloc_asm(bf_scene* s, long long act_cap) {
+  for (void* p : s->asm_allocs) (void)hipFree(p);
+  s->asm_allocs.clear();
+  hipError_t e = hipSuccess;
+  AsmWs A{};
+  long long ec = 16 * act_cap;
+  A.hash_size = next_pow2(std::max(1024LL, 8 * act_cap));
+  A.keys = dalloc<unsigned long long>(s->asm_allocs, A.hash_size, &e);
+  A.slot_pos = dalloc<int>(s->asm_allocs, A.hash_size, &e);
+  A.entry_slot = dalloc<int>(s->asm_allocs, ec, &e);
+  A.rowcnt = dalloc<int>(s->asm_allocs, s->nv + 1, &e);
+  A.rowfill = dalloc<int>(s->asm_allocs, s->nv, &e);
+  A.tmpcol = dalloc<int>(s->asm_allocs, ec, &e);
+  A.epart = dalloc<double>(s->asm_allocs, 256, &e);
+  A.scan_tmp = dalloc<int>(s->asm_allocs, scan_parts(s->nv + 1) + 16, &e);
+  if (e != hipSuccess) return fail(BF_E_NOMEM, "bf_scene_reserve: device allocation failed");
+  s->aw = A;
+  s->act_cap = act_cap;
+  return BF_OK;
+}
+
+void free_list(std::vector<void*>& l) {
+  for (void* p : l) (void)hipFree(p);
+  l.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bf_last_error(void) { return g_err.c_str(); }
+
+bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int64_t cand_cap, int64_t act_cap,
+                          void* stream, bf_scene** out) {
+  if (!mesh || !params || !out) return fail(BF_E_ARG, "bf_scene_create: null argument");
+  *out = nullptr;
+  if (mesh->kind != BF_ROD && mesh->kind != BF_SHELL) return fail(BF_E_ARG, "bf_scene_create: bad kind");
+  if (mesh->n_verts < 2 || mesh->n_edges < 1 || !mesh->edges_h || !mesh->ref_h)
+    return fail(BF_E_ARG, "bf_scene_create: need >= 2 vertices, >= 1 edge, edges and rest parameters");
+  if (mesh->kind == BF_SHELL && (mesh->n_tris < 1 || !mesh->tris_h))
+    return fail(BF_E_ARG, "bf_scene_create: shells need triangles");
+  if (mesh->n_verts > (1LL << 30) || mesh->n_edges > (1LL << 30) || mesh->n_tris > (1LL << 30))
+    return fail(BF_E_ARG, "bf_scene_create: mesh too large (> 2^30 primitives)");
+  if (!(params->h > 0.0) || !(params->eta >= 0.0) || !(params->eta < params->h) || !(params->kappa > 0.0) ||
+      !std::isfinite(params->h))
+    return fail(BF_E_ARG, "bf_scene_create: need h > 0, 0 <= eta < h, kappa > 0");
+  if (params->prec != BF_FP64 && params->prec != BF_MIXED) return fail(BF_E_ARG, "bf_scene_create: bad prec");
+  if (params->filter != BF_FILTER_PAPER && params->filter != BF_FILTER_NONE)
+    return fail(BF_E_ARG, "bf_scene_create: bad filter mode");
+  if (cand_cap < 1 || act_cap < 1) return fail(BF_E_ARG, "bf_scene_create: capacities must be >= 1");
+  int nv = (int)mesh->n_verts, ne = (int)mesh->n_edges, nt = mesh->kind == BF_SHELL ? (int)mesh->n_tris : 0;
+  for (long long k = 0; k < 2LL * ne; ++k)
+    if (mesh->edges_h[k] < 0 || mesh->edges_h[k] >= nv) return fail(BF_E_ARG, "bf_scene_create: edge vertex out of range");
+  for (long long k = 0; k < 3LL * nt; ++k)
+    if (mesh->tris_h[k] < 0 || mesh->tris_h[k] >= nv) return fail(BF_E_ARG, "bf_scene_create: triangle vertex out of range");
+  for (int e = 0; e < ne; ++e)
+    if (mesh->edges_h[2 * e] == mesh->edges_h[2 * e + 1]) return fail(BF_E_ARG, "bf_scene_create: degenerate edge");
+
+  hipStream_t st = (hipStream_t)stream;
+  bf_scene* s = new bf_scene;
+  s->prm = *params;
+  s->kind = mesh->kind;
+  s->nv = nv;
+  s->ne = ne;
+  s->nt = nt;
+  s->last = st;
+  hipError_t e = hipSuccess;
+  int nref = s->kind == BF_ROD ? nv : 2 * nv;
+  s->d_edges = dalloc<int>(s->allocs, 2LL * ne, &e);
+  s->d_tris = dalloc<int>(s->allocs, std::max(3LL * nt, 3LL), &e);
+  s->d_ref = dalloc<double>(s->allocs, nref, &e);
+  s->d_comp = dalloc<int>(s->allocs, nv, &e);
+  s->d_status = dalloc<unsigned>(s->allocs, 4, &e);
+  int np = ne + nt + (s->kind == BF_SHELL ? nv : 0);
+  BroadWs& W = s->bw;
+  W.max_cells = (int)std::min<long long>(std::max<long long>(4096, 2LL * np), 1LL << 26);
+  long long nscan = 2LL * W.max_cells + 1;
+  W.box = dalloc<Box>(s->allocs, np, &e);
+  W.cell_of = dalloc<int>(s->allocs, ne + nt, &e);
+  W.bounds = dalloc<unsigned>(s->allocs, 8, &e);
+  W.grid = dalloc<Grid>(s->allocs, 1, &e);
+  W.cell_cnt = dalloc<int>(s->allocs, nscan, &e);
+  W.cell_start = dalloc<int>(s->allocs, nscan, &e);
+  W.sorted_id = dalloc<int>(s->allocs, ne + nt, &e);
+  W.sorted_box = dalloc<Box>(s->allocs, ne + nt, &e);
+  W.scan_tmp = dalloc<int>(s->allocs, std::max(scan_parts(nscan), scan_parts(nv + 1)) + 16, &e);
+  if (e != hipSuccess) {
+    free_list(s->allocs);
+    delete s;
+    return fail(BF_E_NOMEM, "bf_scene_create: device allocation failed");
+  }
+  hipError_t he;
+  if ((he = hipMemcpyAsync(s->d_edges, mesh->edges_h, sizeof(int) * 2LL * ne, hipMemcpyHostToDevice, st)) ||
+      (nt && (he = hipMemcpyAsync(s->d_tris, mesh->tris_h, sizeof(int) * 3LL * nt, hipMemcpyHostToDevice, st))) ||
+      (he = hipMemcpyAsync(s->d_ref, mesh->ref_h, sizeof(double) * nref, hipMemcpyHostToDevice, st)) ||
+      (he = hipMemsetAsync(s->d_status, 0, 4 * sizeof(unsigned), st))) {
+    free_list(s->allocs);
+    delete s;
+    return fail_hip(he, "bf_scene_create: upload");
+  }
+
+  // --- precompute (Sec. 3.2): components ------------------------------------
+  std::vector<void*> tmp;
+  int* lab = dalloc<int>(tmp, nv, &e);
+  int* flag = dalloc<int>(tmp, nv, &e);
+  int* scan = dalloc<int>(tmp, nv, &e);
+  int* changed = dalloc<int>(tmp, 1, &e);
+  if (e != hipSuccess) {
+    free_list(tmp);
+    free_list(s->allocs);
+    delete s;
+    return fail(BF_E_NOMEM, "bf_scene_create: device allocation failed");
+  }
+  SceneDev S = dev_view(s);
+  int nc = run_components(S, lab, flag, scan, s->d_comp, W.scan_tmp, changed, st);
+  free_list(tmp);
+  if (nc <= 0) {
+    free_list(s->allocs);
+    delete s;
+    return fail(BF_E_DEVICE, "bf_scene_create: component labelling failed");
+  }
+  s->nc = nc;
+  s->comp_h.resize(nv);
+  s->d_dmin = dalloc<double>(s->allocs, nc, &e);
+  s->d_thr2 = dalloc<double>(s->allocs, 2LL * nc, &e);
+
+  // --- precompute: d_min per component over stencil pairs with 0 < dbar < h,
+  // found by the same broad phase run on the rest parameters lifted to 3D
+  std::vector<unsigned long long> best(nc, 0x7ff0000000000000ull);  // +inf
+  long long cap = std::max<long long>(cand_cap, 1024);
+  for (int attempt = 0; attempt < 4; ++attempt) {
+    std::vector<void*> t2;
+    double* xref = dalloc<double>(t2, 3LL * nv, &e);
+    int* ci = dalloc<int>(t2, cap, &e);
+    int* cj = dalloc<int>(t2, cap, &e);
+    unsigned char* ct = dalloc<unsigned char>(t2, cap, &e);
+    long long* cnt = dalloc<long long>(t2, 1, &e);
+    unsigned long long* dbest = dalloc<unsigned long long>(t2, nc, &e);
+    if (e != hipSuccess) {
+      free_list(t2);
+      free_list(s->allocs);
+      delete s;
+      return fail(BF_E_NOMEM, "bf_scene_create: device allocation failed");
+    }
+    S = dev_view(s);
+    run_lift_ref(S, xref, st);
+    run_broad(S, xref, W, ci, cj, ct, cap, cnt, s->d_status, st);
+    (void)hipMemcpyAsync(dbest, best.data(), sizeof(unsigned long long) * nc, hipMemcpyHostToDevice, st);
+    run_refmin(S, ci, cj, ct, cnt, cap, dbest, st);
+    long long hcnt = 0;
+    (void)hipMemcpyAsync(&hcnt, cnt, sizeof(long long), hipMemcpyDeviceToHost, st);
+    std::vector<unsigned long long> got(nc);
+    (void)hipMemcpyAsync(got.data(), dbest, sizeof(unsigned long long) * nc, hipMemcpyDeviceToHost, st);
+    (void)hipMemcpyAsync(s->comp_h.data(), s->d_comp, sizeof(int) * nv, hipMemcpyDeviceToHost, st);
+    he = hipStreamSynchronize(st);
+    free_list(t2);
+    if (he != hipSuccess) {
+      free_list(s->allocs);
+      delete s;
+      return fail_hip(he, "bf_scene_create: precompute");
+    }
+    if (hcnt <= cap) {
+      best = got;
+      break;
+    }
+    cap = hcnt + hcnt / 8 + 1024;
+    if (attempt == 3) {
+      free_list(s->allocs);
+      delete s;
+      return fail(BF_E_CAPACITY, "bf_scene_create: rest-space candidate list kept overflowing");
+    }
+  }
+  s->dmin2_h.assign(nc, INFINITY);
+  s->dmin_h.assign(nc, INFINITY);
+  std::vector<double> thr2(2LL * nc, INFINITY);
+  for (int c = 0; c < nc; ++c) {
+    double v;
+    std::memcpy(&v, &best[c], sizeof(double));
+    if (!(v < INFINITY)) {
+      thr2[2 * c + 1] = 0.0;
+      continue;
+    }
+    if (s->kind == BF_ROD) {  // the minimum gap; threshold its exact square
+      s->dmin_h[c] = v;
+      s->dmin2_h[c] = v * v;
+      thr2[2 * c] = v * v;
+      thr2[2 * c + 1] = std::fma(v, v, -(v * v));
+    } else {                  // canonical d_min^2 (rounded once); d_min its IEEE sqrt
+      s->dmin2_h[c] = v;
+      s->dmin_h[c] = std::sqrt(v);
+      thr2[2 * c] = v;
+      thr2[2 * c + 1] = 0.0;
+    }
+  }
+  if ((he = hipMemcpyAsync(s->d_dmin, s->dmin_h.data(), sizeof(double) * nc, hipMemcpyHostToDevice, st)) ||
+      (he = hipMemcpyAsync(s->d_thr2, thr2.data(), sizeof(double) * 2 * nc, hipMemcpyHostToDevice, st)) ||
+      (he = hipMemsetAsync(s->d_status, 0, 4 * sizeof(unsigned), st)) || (he = hipStreamSynchronize(st))) {
+    free_list(s->allocs);
+    delete s;
+    return fail_hip(he, "bf_scene_create: upload d_min");
+  }
+  bf_status r = alloc_asm(s, act_cap);
+  if (r != BF_OK) {
+    free_list(s->allocs);
+    delete s;
+    return r;
+  }
+  *out = s;
+  return BF_OK;
+}
+
+bf_status bf_scene_reserve(bf_scene* s, int64_t cand_cap, int64_t act_cap) {
+  (void)cand_cap;
+  if (!s || act_cap < 1) return fail(BF_E_ARG, "bf_scene_reserve: bad argument");
+  if (act_cap <= s->act_cap) return BF_OK;
+  hipError_t he = hipDeviceSynchronize();
+  if (he != hipSuccess) return fail_hip(he, "bf_scene_reserve");
+  return alloc_asm(s, act_cap);
+}
+
+bf_status bf_scene_destroy(bf_scene* s) {
+  if (!s) return BF_OK;
+  (void)hipDeviceSynchronize();
+  free_list(s->asm_allocs);
+  free_list(s->allocs);
+  delete s;
+  return BF_OK;
+}
+
+bf_status bf_scene_info(bf_scene* s, int32_t* comp_h, int32_t* n_comp, double* dmin2_h, double* dmin_h,
+                        int32_t cap_c) {
+  if (!s) return fail(BF_E_ARG, "bf_scene_info: null scene");
+  if (comp_h) std::memcpy(comp_h, s->comp_h.data(), sizeof(int) * s->nv);
+  if (n_comp) *n_comp = s->nc;
+  for (int c = 0; c < s->nc && c < cap_c; ++c) {
+    if (dmin2_h) dmin2_h[c] = s->dmin2_h[c];
+    if (dmin_h) dmin_h[c] = s->dmin_h[c];
+  }
+  return BF_OK;
+}
+
+bf_status build_candidates(bf_scene* s, const double* x_d, bf_pairs* cand, void* stream) {
+  if (!s || !x_d || !cand || !cand->i_d || !cand->j_d || !cand->type_d || !cand->count_d || cand->cap < 1)
+    return fail(BF_E_ARG, "build_candidates: null argument or capacity < 1");
+  hipStream_t st = (hipStream_t)stream;
+  s->last = st;
+  run_broad(dev_view(s), x_d, s->bw, cand->i_d, cand->j_d, cand->type_d, cand->cap, (long long*)cand->count_d,
+            s->d_status, st);
+  hipError_t he = hipGetLastError();
+  return he == hipSuccess ? BF_OK : fail_hip(he, "build_candidates");
+}
+
+bf_status filter_pairs(bf_scene* s, const double* x_d, const bf_pairs* cand, bf_active* act, void* stream) {
+  if (!s || !x_d || !cand || !act || !cand->count_d || !act->p.i_d || !act->p.j_d || !act->p.type_d ||
+      !act->p.count_d || !act->code_d || !act->flags_d || !act->dist_d || !act->counters_d || act->p.cap < 1)
+    return fail(BF_E_ARG, "filter_pairs: null argument or capacity < 1");
+  hipStream_t st = (hipStream_t)stream;
+  s->last = st;
+  run_narrow(dev_view(s), x_d, cand->i_d, cand->j_d, cand->type_d, (const long long*)cand->count_d, cand->cap,
+             act->p.i_d, act->p.j_d, act->p.type_d, act->code_d, act->flags_d, act->dist_d, act->p.cap,
+             (long long*)act->p.count_d, (long long*)act->counters_d, s->d_status, st);
+  hipError_t he = hipGetLastError();
+  return he == hipSuccess ? BF_OK : fail_hip(he, "filter_pairs");
+}
+
+bf_status eval_barrier(bf_scene* s, const double* x_d, const bf_active* act, bf_local* out, void* stream) {
+  if (!s || !x_d || !act || !out || !out->E_d || !out->G_d || !out->H_d || !act->p.count_d)
+    return fail(BF_E_ARG, "eval_barrier: null argument");
+  if (out->cap < act->p.cap) return fail(BF_E_CAPACITY, "eval_barrier: local capacity below active capacity");
+  hipStream_t st = (hipStream_t)stream;
+  s->last = st;
+  run_eval(dev_view(s), x_d, act->p.i_d, act->p.j_d, act->p.type_d, act->code_d, act->flags_d,
+           (const long long*)act->p.count_d, act->p.cap, out->E_d, out->G_d, out->H_d, st);
+  hipError_t he = hipGetLastError();
+  return he == hipSuccess ? BF_OK : fail_hip(he, "eval_barrier");
+}
+
+bf_status assemble_grad_hess(bf_scene* s, const bf_active* act, const bf_local* loc, double* E_d, double* g_d,
+                             bf_bsr* H, void* stream) {
+  if (!s || !act || !loc || !E_d || !g_d || !H || !H->row_ptr_d || !H->col_d || !H->val_d || !H->nnzb_d ||
+      H->cap < 1 || !act->p.count_d)
+    return fail(BF_E_ARG, "assemble_grad_hess: null argument or capacity < 1");
+  if (act->p.cap > s->act_cap)
+    return fail(BF_E_CAPACITY, "assemble_grad_hess: active capacity exceeds the scene reserve (bf_scene_reserve)");
+  hipStream_t st = (hipStream_t)stream;
+  s->last = st;
+  run_assemble(dev_view(s), act->p.i_d, act->p.j_d, act->p.type_d, act->flags_d, (const long long*)act->p.count_d,
+               act->p.cap, loc->E_d, loc->G_d, loc->H_d, E_d, g_d, H->row_ptr_d, H->col_d, H->val_d, H->cap,
+               (long long*)H->nnzb_d, s->aw, s->act_cap, s->d_status, st);
+  hipError_t he = hipGetLastError();
+  return he == hipSuccess ? BF_OK : fail_hip(he, "assemble_grad_hess");
+}
+
+bf_status bf_status_word(bf_scene* s, uint32_t* bits_h, int32_t clear) {
+  if (!s || !bits_h) return fail(BF_E_ARG, "bf_status_word: null argument");
+  hipError_t he = hipStreamSynchronize(s->last);
+  if (he != hipSuccess) return fail_hip(he, "bf_status_word");
+  unsigned v = 0;
+  he = hipMemcpy(&v, s->d_status, sizeof(unsigned), hipMemcpyDeviceToHost);
+  if (he != hipSuccess) return fail_hip(he, "bf_status_word");
+  *bits_h = v;
+  if (clear) {
+    he = hipMemset(s->d_status, 0, sizeof(unsigned));
+    if (he != hipSuccess) return fail_hip(he, "bf_status_word");
+  }
+  return BF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,51 @@
+// Host-side launchers of the libbfc kernels (defined in bfc_kernels.hip).
+#pragma once
+#include "bfc.h"
+#include "bfc_internal.h"
+
+namespace bfc {
+
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = 256 * SCAN_ITEMS;
+
+// number of scan partials needed for n elements
+inline long long scan_parts(long long n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
+
+void scan_excl(const int* in, int* out, const int* n_dev, int n_max, int* tmp, hipStream_t st);
+
+// Broad phase over the positions x (FP64 [V,3]) at inflation S.h.
+void run_broad(const SceneDev& S, const double* x, const BroadWs& W, int* oi, int* oj, unsigned char* ot,
+               long long cap, long long* count, unsigned* status, hipStream_t st);
+
+// Narrow phase, filter and compaction.
+void run_narrow(const SceneDev& S, const double* x, const int* ci, const int* cj, const unsigned char* ct,
+                const long long* ccount, long long ccap, int* ai, int* aj, unsigned char* at, unsigned char* acode,
+                unsigned char* aflags, double* adist, long long acap, long long* act_count, long long* counters,
+                unsigned* status, hipStream_t st);
+
+// Per-pair barrier, gradient and projected Hessian.
+void run_eval(const SceneDev& S, const double* x, const int* ai, const int* aj, const unsigned char* at,
+              const unsigned char* acode, const unsigned char* aflags, const long long* act_count, long long acap,
+              double* E, double* G, double* H, hipStream_t st);
+
+// Energy sum, gradient and BSR Hessian.
+void run_assemble(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,
+                  const unsigned char* aflags, const long long* act_count, long long acap, const double* E,
+                  const double* G, const double* H, double* E_out, double* g, int* row_ptr, int* col, double* val,
+                  long long bsr_cap, long long* nnzb, const AsmWs& A, long long act_cap_ws, unsigned* status,
+                  hipStream_t st);
+
+// Connected components (numbered by smallest vertex); synchronous.  Returns
+// the number of components, or -1 on a HIP error.
+int run_components(const SceneDev& S, int* lab, int* flag, int* scan, int* comp, int* scan_tmp, int* d_changed,
+                   hipStream_t st);
+
+// Lift rest parameters to 3D points (rods (s,0,0); shells (u1,u2,0)).
+void run_lift_ref(const SceneDev& S, double* xref, hipStream_t st);
+
+// Per-component minimum of the reference distance over stencil pairs with
+// 0 < dbar < h among the candidates (rods: gap; shells: dbar^2 rounded).
+void run_refmin(const SceneDev& S, const int* ci, const int* cj, const unsigned char* ct, const long long* count,
+                long long cap, unsigned long long* best, hipStream_t st);
+
+}  // namespace bfc
