@@ -66,9 +66,7 @@ enum {
   BF_S_CAND_OVERFLOW = 1u << 0,   /* candidate list capacity exceeded */
   BF_S_ACT_OVERFLOW = 1u << 1,    /* active list capacity exceeded */
   BF_S_INFEASIBLE = 1u << 2,      /* some active pair has d <= eta (energy +inf) */
-  BF_S_BSR_OVERFLOW = 1u << 3,    /* BSR block capacity exceeded */
-  BF_S_HASH_OVERFLOW = 1u << 4,   /* assembly hash table full (scene scratch too small) */
-  BF_S_GRID_COARSENED = 1u << 5   /* informational: grid cell size raised to fit the cell cap */
+  BF_S_BSR_OVERFLOW = 1u << 3    /* BSR block capacity exceeded */
 };
 
 /* Pair types. */
@@ -136,13 +134,15 @@ typedef struct {
 /* Create a scene: copies the topology and rest parameters to the device,
  * labels connected components and computes d_min per component (Sec. 3.2).
  * cand_cap / act_cap size the scene scratch used by the per-step calls
- * (assembly hash table, scan space); they bound the pair counts the scene
- * can process without bf_scene_reserve.  Synchronises the stream. */
+ * (narrow-phase staging, assembly incidence lists); they bound the candidate
+ * and active capacities the scene accepts without bf_scene_reserve.
+ * Synchronises the stream. */
 bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int64_t cand_cap,
                           int64_t act_cap, void* stream, bf_scene** out);
 
 /* Grow the scene scratch to hold at least cand_cap candidates / act_cap
- * active pairs (allocates; not for use inside captured graphs). */
+ * active pairs (allocates and synchronises the device; not for use inside
+ * captured graphs). */
 bf_status bf_scene_reserve(bf_scene* s, int64_t cand_cap, int64_t act_cap);
 
 bf_status bf_scene_destroy(bf_scene* s);

@@ -22,7 +22,7 @@ BF_ROD, BF_SHELL = 0, 1
 BF_FP64, BF_MIXED = 0, 1
 BF_FILTER_PAPER, BF_FILTER_NONE = 0, 1
 BF_S_CAND_OVERFLOW, BF_S_ACT_OVERFLOW, BF_S_INFEASIBLE = 1, 2, 4
-BF_S_BSR_OVERFLOW, BF_S_HASH_OVERFLOW, BF_S_GRID_COARSENED = 8, 16, 32
+BF_S_BSR_OVERFLOW = 8
 BF_F_FILTERED, BF_F_INFEASIBLE = 1, 4
 
 EXPORTED = ["bf_scene_create", "bf_scene_reserve", "bf_scene_destroy", "bf_scene_info", "build_candidates",
@@ -212,7 +212,7 @@ class ContactScene:
         for _ in range(max_tries):
             self.step(x)
             st = self.status(clear=True)
-            over = st & (BF_S_CAND_OVERFLOW | BF_S_ACT_OVERFLOW | BF_S_BSR_OVERFLOW | BF_S_HASH_OVERFLOW)
+            over = st & (BF_S_CAND_OVERFLOW | BF_S_ACT_OVERFLOW | BF_S_BSR_OVERFLOW)
             if not over:
                 return st
             nc, na, nb = int(self.c_n.item()), int(self.a_n.item()), int(self.nnzb.item())
@@ -220,8 +220,8 @@ class ContactScene:
             if nc > self.cand_cap:
                 self.cand_cap = nc + nc // 4 + 1024
                 grow = True
-            if na > self.act_cap or (st & BF_S_HASH_OVERFLOW):
-                self.act_cap = max(na + na // 4 + 1024, self.act_cap * 2 if st & BF_S_HASH_OVERFLOW else 0)
+            if na > self.act_cap:
+                self.act_cap = na + na // 4 + 1024
                 grow = True
             if nb > self.bsr_cap or (st & BF_S_ACT_OVERFLOW):
                 self.bsr_cap = max(nb + nb // 4 + 1024, 8 * self.act_cap)

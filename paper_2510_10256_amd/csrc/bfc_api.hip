@@ -24,10 +24,12 @@ struct bf_scene {
   std::vector<int> comp_h;
   std::vector<double> dmin2_h, dmin_h;
   BroadWs bw{};
+  StageWs sw{};
   AsmWs aw{};
   long long act_cap = 0;
-  std::vector<void*> allocs;      // scene-lifetime allocations
-  std::vector<void*> asm_allocs;  // assembly scratch (regrown by reserve)
+  std::vector<void*> allocs;        // scene-lifetime allocations
+  std::vector<void*> asm_allocs;    // assembly scratch (regrown by reserve)
+  std::vector<void*> stage_allocs;  // narrow-phase staging (regrown by reserve)
   hipStream_t last = nullptr;
 };
 
@@ -88,17 +90,17 @@ bf_status alloc_asm(bf_scene* s, long long act_cap) {
   s->asm_allocs.clear();
   hipError_t e = hipSuccess;
   AsmWs A{};
-  long long ec = 16 * act_cap;
-  A.hash_size = next_pow2(std::max(1024LL, 8 * act_cap));
-  A.keys = dalloc<unsigned long long>(s->asm_allocs, A.hash_size, &e);
-  A.slot_pos = dalloc<int>(s->asm_allocs, A.hash_size, &e);
-  A.entry_slot = dalloc<int>(s->asm_allocs, ec, &e);
+  A.inc_cnt = dalloc<int>(s->asm_allocs, s->nv + 1, &e);
+  A.inc_off = dalloc<int>(s->asm_allocs, s->nv + 1, &e);
+  A.inc = dalloc<int>(s->asm_allocs, 4 * act_cap, &e);
+  A.colbuf = dalloc<int>(s->asm_allocs, 16 * act_cap, &e);
   A.rowcnt = dalloc<int>(s->asm_allocs, s->nv + 1, &e);
-  A.rowfill = dalloc<int>(s->asm_allocs, s->nv, &e);
-  A.tmpcol = dalloc<int>(s->asm_allocs, ec, &e);
   A.epart = dalloc<double>(s->asm_allocs, 256, &e);
   A.scan_tmp = dalloc<int>(s->asm_allocs, scan_parts(s->nv + 1) + 16, &e);
   if (e != hipSuccess) return fail(BF_E_NOMEM, "bf_scene_reserve: device allocation failed");
+  if (hipMemset(A.inc_cnt, 0, sizeof(int) * (s->nv + 1)) != hipSuccess ||
+      hipMemset(A.rowcnt, 0, sizeof(int) * (s->nv + 1)) != hipSuccess)
+    return fail(BF_E_DEVICE, "bf_scene_reserve: clearing the incidence counts failed");
   s->aw = A;
   s->act_cap = act_cap;
   return BF_OK;
@@ -107,6 +109,25 @@ bf_status alloc_asm(bf_scene* s, long long act_cap) {
 void free_list(std::vector<void*>& l) {
   for (void* p : l) (void)hipFree(p);
   l.clear();
+}
+
+bf_status alloc_stage(bf_scene* s, long long cand_cap) {
+  free_list(s->stage_allocs);
+  hipError_t e = hipSuccess;
+  StageWs W{};
+  long long G = (cand_cap + NW_TILE - 1) / NW_TILE;
+  W.si = dalloc<int>(s->stage_allocs, G * NW_TILE, &e);
+  W.sj = dalloc<int>(s->stage_allocs, G * NW_TILE, &e);
+  W.sm = dalloc<unsigned>(s->stage_allocs, G * NW_TILE, &e);
+  W.sd = dalloc<double>(s->stage_allocs, G * NW_TILE, &e);
+  W.kcnt = dalloc<int>(s->stage_allocs, 3 * G + 1, &e);
+  W.kofs = dalloc<int>(s->stage_allocs, 3 * G + 1, &e);
+  W.ccnt = dalloc<int>(s->stage_allocs, 3 * G, &e);
+  W.scan_tmp = dalloc<int>(s->stage_allocs, scan_parts(3 * G + 1) + 16, &e);
+  if (e != hipSuccess) return fail(BF_E_NOMEM, "bf_scene_reserve: device allocation failed");
+  W.cap = G * NW_TILE;
+  s->sw = W;
+  return BF_OK;
 }
 
 }  // namespace
@@ -160,15 +181,20 @@ bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int
   BroadWs& W = s->bw;
   W.max_cells = (int)std::min<long long>(std::max<long long>(4096, 2LL * np), 1LL << 26);
   long long nscan = 2LL * W.max_cells + 1;
+  long long nq = (long long)(s->kind == BF_SHELL ? nv + ne : ne) * PQ_T + 1;
   W.box = dalloc<Box>(s->allocs, np, &e);
   W.cell_of = dalloc<int>(s->allocs, ne + nt, &e);
-  W.bounds = dalloc<unsigned>(s->allocs, 8, &e);
+  W.part = dalloc<float>(s->allocs, 8LL * BOUNDS_BLOCKS, &e);
+  W.done = dalloc<unsigned>(s->allocs, 1, &e);
   W.grid = dalloc<Grid>(s->allocs, 1, &e);
   W.cell_cnt = dalloc<int>(s->allocs, nscan, &e);
   W.cell_start = dalloc<int>(s->allocs, nscan, &e);
   W.sorted_id = dalloc<int>(s->allocs, ne + nt, &e);
   W.sorted_box = dalloc<Box>(s->allocs, ne + nt, &e);
-  W.scan_tmp = dalloc<int>(s->allocs, std::max(scan_parts(nscan), scan_parts(nv + 1)) + 16, &e);
+  W.pair_cnt = dalloc<int>(s->allocs, nq, &e);
+  W.pair_bsum = dalloc<int>(s->allocs, nq / 256 + 2, &e);
+  W.pair_boff = dalloc<int>(s->allocs, nq / 256 + 2, &e);
+  W.scan_tmp = dalloc<int>(s->allocs, std::max(std::max(scan_parts(nscan), scan_parts(nv + 1)), scan_parts(nq)) + 16, &e);
   if (e != hipSuccess) {
     free_list(s->allocs);
     delete s;
@@ -178,7 +204,9 @@ bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int
   if ((he = hipMemcpyAsync(s->d_edges, mesh->edges_h, sizeof(int) * 2LL * ne, hipMemcpyHostToDevice, st)) ||
       (nt && (he = hipMemcpyAsync(s->d_tris, mesh->tris_h, sizeof(int) * 3LL * nt, hipMemcpyHostToDevice, st))) ||
       (he = hipMemcpyAsync(s->d_ref, mesh->ref_h, sizeof(double) * nref, hipMemcpyHostToDevice, st)) ||
-      (he = hipMemsetAsync(s->d_status, 0, 4 * sizeof(unsigned), st))) {
+      (he = hipMemsetAsync(s->d_status, 0, 4 * sizeof(unsigned), st)) ||
+      (he = hipMemsetAsync(W.cell_cnt, 0, sizeof(int) * nscan, st)) ||
+      (he = hipMemsetAsync(W.done, 0, sizeof(unsigned), st))) {
     free_list(s->allocs);
     delete s;
     return fail_hip(he, "bf_scene_create: upload");
@@ -285,7 +313,10 @@ bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int
     return fail_hip(he, "bf_scene_create: upload d_min");
   }
   bf_status r = alloc_asm(s, act_cap);
+  if (r == BF_OK) r = alloc_stage(s, cand_cap);
   if (r != BF_OK) {
+    free_list(s->asm_allocs);
+    free_list(s->stage_allocs);
     free_list(s->allocs);
     delete s;
     return r;
@@ -295,18 +326,21 @@ bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int
 }
 
 bf_status bf_scene_reserve(bf_scene* s, int64_t cand_cap, int64_t act_cap) {
-  (void)cand_cap;
-  if (!s || act_cap < 1) return fail(BF_E_ARG, "bf_scene_reserve: bad argument");
-  if (act_cap <= s->act_cap) return BF_OK;
+  if (!s || act_cap < 1 || cand_cap < 1) return fail(BF_E_ARG, "bf_scene_reserve: bad argument");
+  if (act_cap <= s->act_cap && cand_cap <= s->sw.cap) return BF_OK;
   hipError_t he = hipDeviceSynchronize();
   if (he != hipSuccess) return fail_hip(he, "bf_scene_reserve");
-  return alloc_asm(s, act_cap);
+  bf_status r = BF_OK;
+  if (act_cap > s->act_cap) r = alloc_asm(s, act_cap);
+  if (r == BF_OK && cand_cap > s->sw.cap) r = alloc_stage(s, cand_cap);
+  return r;
 }
 
 bf_status bf_scene_destroy(bf_scene* s) {
   if (!s) return BF_OK;
   (void)hipDeviceSynchronize();
   free_list(s->asm_allocs);
+  free_list(s->stage_allocs);
   free_list(s->allocs);
   delete s;
   return BF_OK;
@@ -339,9 +373,11 @@ bf_status filter_pairs(bf_scene* s, const double* x_d, const bf_pairs* cand, bf_
   if (!s || !x_d || !cand || !act || !cand->count_d || !act->p.i_d || !act->p.j_d || !act->p.type_d ||
       !act->p.count_d || !act->code_d || !act->flags_d || !act->dist_d || !act->counters_d || act->p.cap < 1)
     return fail(BF_E_ARG, "filter_pairs: null argument or capacity < 1");
+  if (cand->cap > s->sw.cap)
+    return fail(BF_E_CAPACITY, "filter_pairs: candidate capacity exceeds the scene reserve (bf_scene_reserve)");
   hipStream_t st = (hipStream_t)stream;
   s->last = st;
-  run_narrow(dev_view(s), x_d, cand->i_d, cand->j_d, cand->type_d, (const long long*)cand->count_d, cand->cap,
+  run_narrow(dev_view(s), x_d, cand->i_d, cand->j_d, cand->type_d, (const long long*)cand->count_d, cand->cap, s->sw,
              act->p.i_d, act->p.j_d, act->p.type_d, act->code_d, act->flags_d, act->dist_d, act->p.cap,
              (long long*)act->p.count_d, (long long*)act->counters_d, s->d_status, st);
   hipError_t he = hipGetLastError();
@@ -371,7 +407,7 @@ bf_status assemble_grad_hess(bf_scene* s, const bf_active* act, const bf_local* 
   s->last = st;
   run_assemble(dev_view(s), act->p.i_d, act->p.j_d, act->p.type_d, act->flags_d, (const long long*)act->p.count_d,
                act->p.cap, loc->E_d, loc->G_d, loc->H_d, E_d, g_d, H->row_ptr_d, H->col_d, H->val_d, H->cap,
-               (long long*)H->nnzb_d, s->aw, s->act_cap, s->d_status, st);
+               (long long*)H->nnzb_d, s->aw, s->d_status, st);
   hipError_t he = hipGetLastError();
   return he == hipSuccess ? BF_OK : fail_hip(he, "assemble_grad_hess");
 }

@@ -36,11 +36,43 @@ template <int N> __device__ __forceinline__ constexpr int uix(int i, int j) {
   return i <= j ? i * N - (i * (i - 1)) / 2 + (j - i) : j * N - (j * (j - 1)) / 2 + (i - j);
 }
 
+// Round-robin (tournament) orderings of the index pairs of a 6 x 6 and a
+// 9 x 9 matrix: every pair once per sweep, the pairs of one round disjoint,
+// so the rotations of a round commute and their angles can be computed
+// independently (instruction-level parallelism instead of one long chain).
+// -1 marks a bye.
+template <int N> struct Sched;
+template <> struct Sched<6> {
+  static constexpr int R = 5, K = 3;
+};
+template <> struct Sched<9> {
+  static constexpr int R = 9, K = 4;
+};
+__device__ __forceinline__ constexpr int sched_idx(int n, int r, int k, int w) {
+  constexpr int S6[5][3][2] = {{{0, 5}, {1, 4}, {2, 3}}, {{0, 4}, {3, 5}, {1, 2}}, {{0, 3}, {2, 4}, {1, 5}},
+                               {{0, 2}, {1, 3}, {4, 5}}, {{0, 1}, {2, 5}, {3, 4}}};
+  constexpr int S9[9][4][2] = {{{1, 8}, {2, 7}, {3, 6}, {4, 5}}, {{0, 8}, {1, 6}, {2, 5}, {3, 4}},
+                               {{0, 7}, {6, 8}, {1, 4}, {2, 3}}, {{0, 6}, {5, 7}, {4, 8}, {1, 2}},
+                               {{0, 5}, {4, 6}, {3, 7}, {2, 8}}, {{0, 4}, {3, 5}, {2, 6}, {1, 7}},
+                               {{0, 3}, {2, 4}, {1, 5}, {7, 8}}, {{0, 2}, {1, 3}, {5, 8}, {6, 7}},
+                               {{0, 1}, {3, 8}, {4, 7}, {5, 6}}};
+  return n == 6 ? S6[r][k][w] : S9[r][k][w];
+}
+
 // Cyclic Jacobi eigen-decomposition of the symmetric N x N matrix A (upper
-// triangle, destroyed) followed by A+ = V max(L, 0) V^T written to P (upper).
-// Converges when the off-diagonal mass is below 1e-32 of the Frobenius mass.
+// triangle, destroyed) in round-robin order, followed by
+// A+ = V max(L, 0) V^T written to P (upper).  Converges when the
+// off-diagonal mass is below 1e-32 of the Frobenius mass.
+//
+// A rotation angle only decides how much of a_pq a rotation removes, not the
+// exactness of the similarity transform, so the angles are computed in FP32
+// on the matrix scaled to unit Frobenius norm (fast reciprocal and square
+// root); the rotation (c, s) is then made orthogonal to FP64 precision
+// (c = (1 + t^2)^-1/2 by Newton steps in FP64) and applied with the full
+// 2 x 2 update, since a_pq' is no longer exactly zero.  Near convergence
+// each sweep still shrinks the off-diagonal mass by the FP32 angle accuracy.
 template <int N> __device__ __forceinline__ void psd_jacobi(double* A, double* P) {
-  constexpr int NU = N * (N + 1) / 2;
+  constexpr int R = Sched<N>::R, K = Sched<N>::K;
   double V[N][N];
 #pragma unroll
   for (int i = 0; i < N; ++i)
@@ -51,7 +83,8 @@ template <int N> __device__ __forceinline__ void psd_jacobi(double* A, double* P
   for (int i = 0; i < N; ++i)
 #pragma unroll
     for (int j = i; j < N; ++j) fro += (i == j ? 1.0 : 2.0) * A[uix<N>(i, j)] * A[uix<N>(i, j)];
-  for (int sweep = 0; sweep < 15; ++sweep) {
+  const double inv = fro > 0.0 ? 1.0 / sqrt(fro) : 0.0;
+  for (int sweep = 0; sweep < 20; ++sweep) {
     double off = 0.0;
 #pragma unroll
     for (int i = 0; i < N; ++i)
@@ -59,31 +92,49 @@ template <int N> __device__ __forceinline__ void psd_jacobi(double* A, double* P
       for (int j = i + 1; j < N; ++j) off += A[uix<N>(i, j)] * A[uix<N>(i, j)];
     if (!(off > 1e-32 * fro)) break;
 #pragma unroll
-    for (int p = 0; p < N - 1; ++p) {
+    for (int r = 0; r < R; ++r) {
+      double cs[K], sn[K];
 #pragma unroll
-      for (int q = p + 1; q < N; ++q) {
+      for (int k = 0; k < K; ++k) {  // independent rotation angles of this round
+        const int p = sched_idx(N, r, k, 0), q = sched_idx(N, r, k, 1);
+        if (p < 0) {
+          cs[k] = 1.0; sn[k] = 0.0;
+          continue;
+        }
         double apq = A[uix<N>(p, q)];
-        if (apq != 0.0) {
-          double tau = (A[uix<N>(q, q)] - A[uix<N>(p, p)]) / (2.0 * apq);
-          double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          double c = 1.0 / sqrt(1.0 + t * t);
-          double s = t * c;
-          A[uix<N>(p, p)] -= t * apq;
-          A[uix<N>(q, q)] += t * apq;
-          A[uix<N>(p, q)] = 0.0;
+        float num = (float)((A[uix<N>(q, q)] - A[uix<N>(p, p)]) * inv);
+        float den = (float)(2.0 * apq * inv);
+        float tau = num * __builtin_amdgcn_rcpf(den);
+        float tf = __builtin_amdgcn_rcpf(fabsf(tau) + __builtin_amdgcn_sqrtf(fmaf(tau, tau, 1.0f)));
+        tf = tau < 0.0f ? -tf : tf;
+        double t = (apq != 0.0 && den != 0.0 && tf == tf) ? (double)tf : 0.0;
+        double x = fma(t, t, 1.0);
+        double c = (double)__builtin_amdgcn_rsqf((float)x);
+        c = c * (1.5 - 0.5 * x * c * c);  // Newton steps for x^-1/2
+        c = c * (1.5 - 0.5 * x * c * c);
+        cs[k] = c; sn[k] = t * c;
+      }
 #pragma unroll
-          for (int k = 0; k < N; ++k) {
-            if (k == p || k == q) continue;
-            double akp = A[uix<N>(k, p)], akq = A[uix<N>(k, q)];
-            A[uix<N>(k, p)] = c * akp - s * akq;
-            A[uix<N>(k, q)] = s * akp + c * akq;
-          }
+      for (int k = 0; k < K; ++k) {  // apply them (disjoint index pairs commute)
+        const int p = sched_idx(N, r, k, 0), q = sched_idx(N, r, k, 1);
+        if (p < 0) continue;
+        const double c = cs[k], s = sn[k];
+        double app = A[uix<N>(p, p)], aqq = A[uix<N>(q, q)], apq = A[uix<N>(p, q)];
+        A[uix<N>(p, p)] = c * c * app - 2.0 * c * s * apq + s * s * aqq;
+        A[uix<N>(q, q)] = s * s * app + 2.0 * c * s * apq + c * c * aqq;
+        A[uix<N>(p, q)] = c * s * (app - aqq) + (c * c - s * s) * apq;
 #pragma unroll
-          for (int k = 0; k < N; ++k) {
-            double vkp = V[k][p], vkq = V[k][q];
-            V[k][p] = c * vkp - s * vkq;
-            V[k][q] = s * vkp + c * vkq;
-          }
+        for (int m = 0; m < N; ++m) {
+          if (m == p || m == q) continue;
+          double amp = A[uix<N>(m, p)], amq = A[uix<N>(m, q)];
+          A[uix<N>(m, p)] = c * amp - s * amq;
+          A[uix<N>(m, q)] = s * amp + c * amq;
+        }
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+          double vmp = V[m][p], vmq = V[m][q];
+          V[m][p] = c * vmp - s * vmq;
+          V[m][q] = s * vmp + c * vmq;
         }
       }
     }
@@ -100,17 +151,14 @@ template <int N> __device__ __forceinline__ void psd_jacobi(double* A, double* P
       for (int k = 0; k < N; ++k) acc += V[i][k] * lam[k] * V[j][k];
       P[uix<N>(i, j)] = acc;
     }
-  (void)NU;
 }
 
 // Output helpers: packed upper triangle of the 12 x 12 Hessian.
-__device__ __forceinline__ int hix(int I, int J) { return I * 12 - (I * (I - 1)) / 2 + (J - I); }
+__device__ __forceinline__ int hix(int I, int J) { return I <= J ? I * 12 - (I * (I - 1)) / 2 + (J - I) : hix(J, I); }
 
-struct PairOut {
-  double E;
-  double G[12];
-  double H[78];
-};
+// Select one of four vertices without indexing a register array at run time
+// (which would place it in scratch memory).
+__device__ __forceinline__ d3 pick4(const d3* P, int s) { return pick<double>(P, s); }
 
 // Scale factors of the barrier chain rule on D:
 //   g_y = cg * dD,  H_y = c1 * dD dD^T + c2 * d2D
@@ -137,41 +185,50 @@ __device__ __forceinline__ Chain chain_coeffs(double D, double a, double eta, do
   return ch;
 }
 
+// Row k of the per-pair outputs: E, G[12], packed H[78].
+struct OutRow {
+  double* E;
+  double* G;
+  double* H;
+};
+__device__ __forceinline__ void zero_row(OutRow o) {
+#pragma unroll
+  for (int q = 0; q < 12; ++q) o.G[q] = 0.0;
+#pragma unroll
+  for (int q = 0; q < 78; ++q) o.H[q] = 0.0;
+}
+
 // ---- PP: closed-form projection ------------------------------------------
 // H_y = c1 (2r)(2r)^T + 2 c2 I has eigenvalue kappa b'' along r and kappa b'/d
 // across it; the projection keeps the positive parts.
 __device__ __forceinline__ void eval_pp(const d3* P, int s0, int s1, double a, double eta, double kappa,
-                                        PairOut& o) {
-  d3 r = P[s0] - P[s1];
+                                        OutRow o) {
+  d3 r = pick4(P, s0) - pick4(P, s1);
   double D = dot(r, r);
   Chain ch = chain_coeffs(D, a, eta, kappa);
-  o.E = ch.E;
+  *o.E = ch.E;
+  zero_row(o);
   if (ch.zero) return;
-  double g[3] = {2.0 * ch.cg * r.x, 2.0 * ch.cg * r.y, 2.0 * ch.cg * r.z};
-  double lr = 4.0 * ch.c1 * D + 2.0 * ch.c2;  // eigenvalue along r
-  double lt = 2.0 * ch.c2;                    // eigenvalue across r
-  lr = fmax(lr, 0.0);
-  lt = fmax(lt, 0.0);
   double rr[3] = {r.x, r.y, r.z};
-  double M[3][3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) M[i][j] = (lr - lt) * rr[i] * rr[j] / D + (i == j ? lt : 0.0);
+  double lr = fmax(4.0 * ch.c1 * D + 2.0 * ch.c2, 0.0);  // eigenvalue along r
+  double lt = fmax(2.0 * ch.c2, 0.0);                    // eigenvalue across r
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    o.G[3 * s0 + i] = g[i];
-    o.G[3 * s1 + i] = -g[i];
+    double g = 2.0 * ch.cg * rr[i];
+    o.G[3 * s0 + i] = g;
+    o.G[3 * s1 + i] = -g;
   }
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
+      double m = (lr - lt) * rr[i] * rr[j] / D + (i == j ? lt : 0.0);
       int I0 = 3 * s0 + i, I1 = 3 * s1 + i, J0 = 3 * s0 + j, J1 = 3 * s1 + j;
-      if (I0 <= J0) o.H[hix(I0, J0)] = M[i][j];
-      if (I1 <= J1) o.H[hix(I1, J1)] = M[i][j];
-      if (I0 <= J1) o.H[hix(I0, J1)] = -M[i][j];
-      if (I1 <= J0) o.H[hix(I1, J0)] = -M[i][j];
+      if (i <= j) {
+        o.H[hix(I0, J0)] = m;
+        o.H[hix(I1, J1)] = m;
+      }
+      o.H[hix(I0, J1)] = -m;  // s0 < s1 for every PP code, so (I0, J1) is in the upper triangle
     }
 }
 
@@ -180,78 +237,64 @@ __device__ __forceinline__ void eval_pp(const d3* P, int s0, int s1, double a, d
 // w1 = (1, -1, 0)/sqrt2, w2 = (1, 1, -2)/sqrt6.  With y = (r, e) = Y x the
 // coupling b = Y W is [[sqrt2, 0], [1/sqrt2, -3/sqrt6]].
 __device__ __forceinline__ void eval_pe(const d3* P, int sp, int se0, int se1, double a, double eta,
-                                        double kappa, PairOut& o) {
+                                        double kappa, OutRow o) {
   const double S2 = 1.4142135623730951, IS2 = 0.70710678118654752, IS6 = 0.40824829046386302;
-  d3 r = P[sp] - P[se0], e = P[se1] - P[se0];
+  d3 xp = pick4(P, sp), x0 = pick4(P, se0), x1 = pick4(P, se1);
+  d3 r = xp - x0, e = x1 - x0;
   double s = dot(r, e), m = dot(e, e), im = 1.0 / m;
   d3 c = cross(r, e);
   double D = dot(c, c) * im;
   Chain ch = chain_coeffs(D, a, eta, kappa);
-  o.E = ch.E;
+  *o.E = ch.E;
+  zero_row(o);
   if (ch.zero) return;
   double rv[3] = {r.x, r.y, r.z}, ev[3] = {e.x, e.y, e.z};
-  // gradient of D in y
   double gr[3], ge[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     gr[i] = 2.0 * rv[i] - 2.0 * s * im * ev[i];
     ge[i] = -2.0 * s * im * rv[i] + 2.0 * s * s * im * im * ev[i];
   }
-  // Hessian blocks of D in y
-  double Hrr[3][3], Hre[3][3], Hee[3][3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      double dl = i == j ? 1.0 : 0.0;
-      Hrr[i][j] = 2.0 * dl - 2.0 * im * ev[i] * ev[j];
-      Hre[i][j] = -2.0 * im * ev[i] * rv[j] - 2.0 * s * im * dl + 4.0 * s * im * im * ev[i] * ev[j];
-      Hee[i][j] = -2.0 * im * rv[i] * rv[j] + 4.0 * s * im * im * (rv[i] * ev[j] + ev[i] * rv[j]) +
-                  2.0 * s * s * im * im * dl - 8.0 * s * s * im * im * im * ev[i] * ev[j];
-    }
-  // energy Hessian in y: Hy = c1 g g^T + c2 H
   double Yrr[3][3], Yre[3][3], Yee[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      Yrr[i][j] = ch.c1 * gr[i] * gr[j] + ch.c2 * Hrr[i][j];
-      Yre[i][j] = ch.c1 * gr[i] * ge[j] + ch.c2 * Hre[i][j];
-      Yee[i][j] = ch.c1 * ge[i] * ge[j] + ch.c2 * Hee[i][j];
+      double dl = i == j ? 1.0 : 0.0;
+      double hrr = 2.0 * dl - 2.0 * im * ev[i] * ev[j];
+      double hre = -2.0 * im * ev[i] * rv[j] - 2.0 * s * im * dl + 4.0 * s * im * im * ev[i] * ev[j];
+      double hee = -2.0 * im * rv[i] * rv[j] + 4.0 * s * im * im * (rv[i] * ev[j] + ev[i] * rv[j]) +
+                   2.0 * s * s * im * im * dl - 8.0 * s * s * im * im * im * ev[i] * ev[j];
+      Yrr[i][j] = ch.c1 * gr[i] * gr[j] + ch.c2 * hrr;
+      Yre[i][j] = ch.c1 * gr[i] * ge[j] + ch.c2 * hre;
+      Yee[i][j] = ch.c1 * ge[i] * ge[j] + ch.c2 * hee;
     }
-  // reduced A = (b x I)^T Hy (b x I), blocks alpha,beta in {1,2}:
-  // b[r] = (S2, 0), b[e] = (IS2, -3 IS6)
-  const double br1 = S2, br2 = 0.0, be1 = IS2, be2 = -3.0 * IS6;
+  const double br[2] = {S2, 0.0}, be[2] = {IS2, -3.0 * IS6};
   double A[21];
 #pragma unroll
   for (int al = 0; al < 2; ++al)
 #pragma unroll
-    for (int be = al; be < 2; ++be) {
-      double ra = al == 0 ? br1 : br2, ea = al == 0 ? be1 : be2;
-      double rb = be == 0 ? br1 : br2, eb = be == 0 ? be1 : be2;
+    for (int bt = al; bt < 2; ++bt)
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-          int I = 3 * al + i, J = 3 * be + j;
+          int I = 3 * al + i, J = 3 * bt + j;
           if (I > J) continue;
-          A[uix<6>(I, J)] = ra * rb * Yrr[i][j] + ra * eb * Yre[i][j] + ea * rb * Yre[j][i] + ea * eb * Yee[i][j];
+          A[uix<6>(I, J)] = br[al] * br[bt] * Yrr[i][j] + br[al] * be[bt] * Yre[i][j] +
+                            be[al] * br[bt] * Yre[j][i] + be[al] * be[bt] * Yee[i][j];
         }
-    }
   double Ap[21];
   psd_jacobi<6>(A, Ap);
-  // gradient: x-gradient of slot k = sum over y-vectors of Y[y][k] * g_y
-  // Y rows: r = (1, -1, 0), e = (0, -1, 1) on (p, e0, e1)
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
+  for (int i = 0; i < 3; ++i) {  // Y rows: r = (1, -1, 0), e = (0, -1, 1) on (p, e0, e1)
     double grx = ch.cg * gr[i], gex = ch.cg * ge[i];
     o.G[3 * sp + i] = grx;
     o.G[3 * se0 + i] = -grx - gex;
     o.G[3 * se1 + i] = gex;
   }
-  // back to slots: H+[s][t] = sum W[s][al] W[t][be] A+[al][be]
-  const int sl[3] = {sp, se0, se1};
   const double W[3][2] = {{IS2, IS6}, {-IS2, IS6}, {0.0, -2.0 * IS6}};
+  const int sl[3] = {sp, se0, se1};
 #pragma unroll
   for (int u = 0; u < 3; ++u)
 #pragma unroll
@@ -260,14 +303,13 @@ __device__ __forceinline__ void eval_pe(const d3* P, int sp, int se0, int se1, d
       for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-          int I = 3 * sl[u] + i, J = 3 * sl[w] + j;
-          if (I > J) continue;
+          if (3 * u + i > 3 * w + j) continue;  // each unordered entry once
           double acc = 0.0;
 #pragma unroll
           for (int al = 0; al < 2; ++al)
 #pragma unroll
-            for (int be = 0; be < 2; ++be) acc += W[u][al] * W[w][be] * Ap[uix<6>(3 * al + i, 3 * be + j)];
-          o.H[hix(I, J)] = acc;
+            for (int bt = 0; bt < 2; ++bt) acc += W[u][al] * W[w][bt] * Ap[uix<6>(3 * al + i, 3 * bt + j)];
+          o.H[hix(3 * sl[u] + i, 3 * sl[w] + j)] = acc;
         }
 }
 
@@ -278,7 +320,7 @@ __device__ __forceinline__ void eval_pe(const d3* P, int sp, int se0, int se1, d
 //   PT (r = p-t0, u = t1-t0, v = t2-t0):  r (0,1,1)  u (-1,1,0)  v (-1,0,1)
 //   EE (r = a0-b0, u = a1-a0, v = b1-b0): r (1,0,1)  u (0,-1,-1) v (0,-1,1)
 __device__ __forceinline__ void eval_tri(const d3* P, bool is_pt, double a, double eta, double kappa,
-                                         PairOut& o) {
+                                         OutRow o) {
   d3 r, u, v;
   if (is_pt) {
     r = P[0] - P[1]; u = P[2] - P[1]; v = P[3] - P[1];
@@ -289,28 +331,26 @@ __device__ __forceinline__ void eval_tri(const d3* P, bool is_pt, double a, doub
   double s = dot(r, n), m = dot(n, n), im = 1.0 / m;
   double D = s * s * im;
   Chain ch = chain_coeffs(D, a, eta, kappa);
-  o.E = ch.E;
-  if (ch.zero) return;
+  *o.E = ch.E;
+  if (ch.zero) {
+    zero_row(o);
+    return;
+  }
   double uu = dot(u, u), vv = dot(v, v), uv = dot(u, v);
-  // gradients of s and m in y = (r, u, v)
   d3 gs[3] = {n, cross(v, r), cross(r, u)};
   d3 gm[3] = {{0.0, 0.0, 0.0}, 2.0 * (vv * u - uv * v), 2.0 * (uu * v - uv * u)};
-  // dD = (2 s / m) gs - (s^2/m^2) gm
   const double ks = 2.0 * s * im, km = -s * s * im * im;
   double g[9];
 #pragma unroll
   for (int b = 0; b < 3; ++b)
 #pragma unroll
     for (int i = 0; i < 3; ++i) g[3 * b + i] = ks * comp(gs[b], i) + km * comp(gm[b], i);
-  // d2D = (2/m) gs gs^T + (2s/m) Hs - (2s/m^2)(gs gm^T + gm gs^T) - (s^2/m^2) Hm + (2 s^2/m^3) gm gm^T
   const double k_ss = 2.0 * im, k_hs = 2.0 * s * im, k_sm = -2.0 * s * im * im, k_hm = -s * s * im * im,
                k_mm = 2.0 * s * s * im * im * im;
-  // Hs blocks: [r,u] = -[v]x, [r,v] = [u]x, [u,v] = -[r]x (and transposes)
   double Sru[3][3], Srv[3][3], Suv[3][3];
   skew(v, Sru, -1.0);
   skew(u, Srv, 1.0);
   skew(r, Suv, -1.0);
-  // energy Hessian in y, blocks Y[b][c] (b <= c): Hy = c1 g g^T + c2 d2D
   double Y[3][3][3][3];
 #pragma unroll
   for (int b = 0; b < 3; ++b)
@@ -332,27 +372,25 @@ __device__ __forceinline__ void eval_tri(const d3* P, bool is_pt, double a, doub
           double d2 = k_ss * gsi * gsj + k_hs * hs + k_sm * (gsi * gmj + gmi * gsj) + k_hm * hm + k_mm * gmi * gmj;
           Y[b][c][i][j] = ch.c1 * g[3 * b + i] * g[3 * c + j] + ch.c2 * d2;
         }
-  // couplings
   const float BPT[3][3] = {{0, 1, 1}, {-1, 1, 0}, {-1, 0, 1}};
   const float BEE[3][3] = {{1, 0, 1}, {0, -1, -1}, {0, -1, 1}};
   double A[45];
 #pragma unroll
   for (int al = 0; al < 3; ++al)
 #pragma unroll
-    for (int be = al; be < 3; ++be)
+    for (int bt = al; bt < 3; ++bt)
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-          int I = 3 * al + i, J = 3 * be + j;
+          int I = 3 * al + i, J = 3 * bt + j;
           if (I > J) continue;
           double acc = 0.0;
 #pragma unroll
           for (int b = 0; b < 3; ++b)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-              double w = (double)(is_pt ? BPT[b][al] * BPT[c][be] : BEE[b][al] * BEE[c][be]);
-              // Y[b][c][i][j] for b <= c, Y[c][b][j][i] otherwise
+              double w = (double)(is_pt ? BPT[b][al] * BPT[c][bt] : BEE[b][al] * BEE[c][bt]);
               double y = b <= c ? Y[b][c][i][j] : Y[c][b][j][i];
               acc += w * y;
             }
@@ -360,29 +398,21 @@ __device__ __forceinline__ void eval_tri(const d3* P, bool is_pt, double a, doub
         }
   double Ap[45];
   psd_jacobi<9>(A, Ap);
-  // gradient in slots: Y rows per pair type
-  double gr[3], gu[3], gv[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    gr[i] = ch.cg * g[i];
-    gu[i] = ch.cg * g[3 + i];
-    gv[i] = ch.cg * g[6 + i];
-  }
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
+    double gr = ch.cg * g[i], gu = ch.cg * g[3 + i], gv = ch.cg * g[6 + i];
     if (is_pt) {  // r = p - t0, u = t1 - t0, v = t2 - t0
-      o.G[i] = gr[i];
-      o.G[3 + i] = -gr[i] - gu[i] - gv[i];
-      o.G[6 + i] = gu[i];
-      o.G[9 + i] = gv[i];
+      o.G[i] = gr;
+      o.G[3 + i] = -gr - gu - gv;
+      o.G[6 + i] = gu;
+      o.G[9 + i] = gv;
     } else {      // r = a0 - b0, u = a1 - a0, v = b1 - b0
-      o.G[i] = gr[i] - gu[i];
-      o.G[3 + i] = gu[i];
-      o.G[6 + i] = -gr[i] - gv[i];
-      o.G[9 + i] = gv[i];
+      o.G[i] = gr - gu;
+      o.G[3 + i] = gu;
+      o.G[6 + i] = -gr - gv;
+      o.G[9 + i] = gv;
     }
   }
-  // back to slots through the Hadamard basis
   const float W[4][3] = {{0.5f, 0.5f, 0.5f}, {0.5f, -0.5f, -0.5f}, {-0.5f, 0.5f, -0.5f}, {-0.5f, -0.5f, 0.5f}};
 #pragma unroll
   for (int st = 0; st < 4; ++st)
@@ -398,20 +428,14 @@ __device__ __forceinline__ void eval_tri(const d3* P, bool is_pt, double a, doub
 #pragma unroll
           for (int al = 0; al < 3; ++al)
 #pragma unroll
-            for (int be = 0; be < 3; ++be)
-              acc += (double)(W[st][al] * W[tt][be]) * Ap[uix<9>(3 * al + i, 3 * be + j)];
+            for (int bt = 0; bt < 3; ++bt)
+              acc += (double)(W[st][al] * W[tt][bt]) * Ap[uix<9>(3 * al + i, 3 * bt + j)];
           o.H[hix(I, J)] = acc;
         }
 }
 
 // Evaluate one active pair with the sub-case `code` fixed by the narrow phase.
-__device__ __forceinline__ void eval_pair(const d3* P, int code, double a, double eta, double kappa,
-                                          PairOut& o) {
-  o.E = 0.0;
-#pragma unroll
-  for (int k = 0; k < 12; ++k) o.G[k] = 0.0;
-#pragma unroll
-  for (int k = 0; k < 78; ++k) o.H[k] = 0.0;
+__device__ __forceinline__ void eval_pair(const d3* P, int code, double a, double eta, double kappa, OutRow o) {
   int kind = case_kind(code);
   if (kind == K_PT || kind == K_EE) {
     eval_tri(P, kind == K_PT, a, eta, kappa, o);

@@ -141,14 +141,26 @@ template <class T> __device__ __forceinline__ T sqd_tri(V3<T> r, V3<T> u, V3<T> 
   T s = dot(r, n);
   return s * s / dot(n, n);
 }
+// one of four vertices, chosen by value selects (indexing the array with a
+// run-time slot, or selecting between element addresses, would keep the
+// array in scratch memory)
+template <class T> __device__ __forceinline__ T sel4(int s, T a, T b, T c, T d) {
+  T lo = s == 0 ? a : b;
+  T hi = s == 2 ? c : d;
+  return s < 2 ? lo : hi;
+}
+template <class T> __device__ __forceinline__ V3<T> pick(const V3<T>* P, int s) {
+  const V3<T> p0 = P[0], p1 = P[1], p2 = P[2], p3 = P[3];
+  return {sel4(s, p0.x, p1.x, p2.x, p3.x), sel4(s, p0.y, p1.y, p2.y, p3.y), sel4(s, p0.z, p1.z, p2.z, p3.z)};
+}
 template <class T> __device__ __forceinline__ T sqd_case(int code, const V3<T>* P) {
   int k = case_kind(code);
   if (k == K_PT) return sqd_tri(P[0] - P[1], P[2] - P[1], P[3] - P[1]);
   if (k == K_EE) return sqd_tri(P[0] - P[2], P[1] - P[0], P[3] - P[2]);
   int s0, s1, s2;
   case_slots(code, s0, s1, s2);
-  if (k == K_PP) return sqd_pp(P[s0], P[s1]);
-  return sqd_pe(P[s0], P[s1], P[s2]);
+  if (k == K_PP) return sqd_pp(pick(P, s0), pick(P, s1));
+  return sqd_pe(pick(P, s0), pick(P, s1), pick(P, s2));
 }
 
 // ---------------------------------------------------------------------------

@@ -43,30 +43,44 @@ struct SceneDev {
 // Broad-phase scratch (device pointers inside the scene workspace).
 struct BroadWs {
   Box* box;          // [NP] per primitive (edges, triangles, points)
-  int* cell_of;      // [NP] sub-cell id of stored primitives
-  unsigned* bounds;  // [8] ordered-float min xyz, max xyz, max extent, spare
+  int* cell_of;      // [NS] sub-cell id of stored primitives
+  float* part;       // [8 * BOUNDS_BLOCKS] per-block bounds
+  unsigned* done;    // [1] block counter of the last-block reduction (zero between launches)
   Grid* grid;        // [1]
-  int* cell_cnt;     // [2*max_cells + 1]
+  int* cell_cnt;     // [2*max_cells + 1], zero between steps
   int* cell_start;   // [2*max_cells + 1]
   int* sorted_id;    // [NS] stored primitives in cell order
   Box* sorted_box;   // [NS]
+  int* pair_cnt;     // [NQ * PQ_T] pairs per (query, cell subset)
+  int* pair_bsum;    // [work-groups + 1] pairs per work-group of the count pass
+  int* pair_boff;    // [work-groups + 1] their exclusive scan
   int* scan_tmp;     // [scan partials]
   int max_cells;
 };
 
-// Assembly scratch.
-struct AsmWs {
-  unsigned long long* keys;  // [S] hash table of (row << 32 | col)
-  int* slot_pos;             // [S] BSR position of each occupied slot
-  int* entry_slot;           // [16 * act_cap]
-  int* rowcnt;               // [V + 1]
-  int* rowfill;              // [V]
-  int* tmpcol;               // [16 * act_cap] unsorted columns per row
-  double* epart;             // [partials] energy partial sums
+// Narrow-phase staging: active pairs compacted per tile before the final copy.
+struct StageWs {
+  int* si;       // [cand cap]
+  int* sj;       // [cand cap]
+  unsigned* sm;  // [cand cap] type | code << 8 | flags << 16
+  double* sd;    // [cand cap] distance
+  int* kcnt;     // [3 * G + 1] per-kind counts per tile (kind-major)
+  int* kofs;     // [3 * G + 1] their exclusive scan
+  int* ccnt;     // [3 * G] per-tile N_c, N_filt, N_infeasible
   int* scan_tmp;
-  long long hash_size;       // power of two
+  long long cap; // staging capacity in candidates
 };
 
-static const unsigned long long kEmpty = ~0ull;
+// Assembly scratch.
+struct AsmWs {
+  int* inc_cnt;   // [V + 1] incidence entries per vertex, zero between steps
+  int* inc_off;   // [V + 1] their exclusive scan
+  int* inc;       // [4 * act_cap] entries 4k + s grouped by vertex
+  int* colbuf;    // [16 * act_cap] stencil vertices of each entry's pair (row columns, sorted per row)
+  int* rowcnt;    // [V + 1] distinct columns per row
+  double* epart;  // [256] energy partial sums
+  int* scan_tmp;
+};
+
 
 }  // namespace bfc

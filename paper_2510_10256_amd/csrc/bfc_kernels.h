@@ -7,6 +7,11 @@ namespace bfc {
 
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = 256 * SCAN_ITEMS;
+constexpr int SCAN1_MAX = 1 << 14;     // arrays up to this length are scanned by one work-group
+constexpr int PQ_T = 4;                // threads per broad-phase query
+constexpr int NW_ITEMS = 4;            // candidates per thread in the narrow phase
+constexpr int NW_TILE = 256 * NW_ITEMS;
+constexpr int BOUNDS_BLOCKS = 512;     // cap on k_bounds work-groups (partials of the last-block reduction)
 
 // number of scan partials needed for n elements
 inline long long scan_parts(long long n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
@@ -19,9 +24,9 @@ void run_broad(const SceneDev& S, const double* x, const BroadWs& W, int* oi, in
 
 // Narrow phase, filter and compaction.
 void run_narrow(const SceneDev& S, const double* x, const int* ci, const int* cj, const unsigned char* ct,
-                const long long* ccount, long long ccap, int* ai, int* aj, unsigned char* at, unsigned char* acode,
-                unsigned char* aflags, double* adist, long long acap, long long* act_count, long long* counters,
-                unsigned* status, hipStream_t st);
+                const long long* ccount, long long ccap, const StageWs& W, int* ai, int* aj, unsigned char* at,
+                unsigned char* acode, unsigned char* aflags, double* adist, long long acap, long long* act_count,
+                long long* counters, unsigned* status, hipStream_t st);
 
 // Per-pair barrier, gradient and projected Hessian.
 void run_eval(const SceneDev& S, const double* x, const int* ai, const int* aj, const unsigned char* at,
@@ -32,8 +37,7 @@ void run_eval(const SceneDev& S, const double* x, const int* ai, const int* aj, 
 void run_assemble(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,
                   const unsigned char* aflags, const long long* act_count, long long acap, const double* E,
                   const double* G, const double* H, double* E_out, double* g, int* row_ptr, int* col, double* val,
-                  long long bsr_cap, long long* nnzb, const AsmWs& A, long long act_cap_ws, unsigned* status,
-                  hipStream_t st);
+                  long long bsr_cap, long long* nnzb, const AsmWs& A, unsigned* status, hipStream_t st);
 
 // Connected components (numbered by smallest vertex); synchronous.  Returns
 // the number of components, or -1 on a HIP error.

@@ -1,10 +1,13 @@
 // Kernels of libbfc (gfx950, wave64).
 //
-//   broad phase   : k_begin, k_bounds, k_grid, k_zero_i, k_count, scan, k_scatter, k_pairs
-//   narrow phase  : k_narrow      (distance, filter of Eq. 4, exact thresholds, ballot compaction)
+//   broad phase   : k_bounds, k_count, scan, k_scatter, k_pair_count, scan, k_pair_emit
+//   narrow phase  : k_narrow, scan, k_compact (distance, filter of Eq. 4, exact thresholds,
+//                   ballot compaction by distance kind)
 //   evaluation    : k_eval        (Eq. 2/3 barrier, derivatives, PSD projection)
 //   assembly      : k_esum*, k_grad, k_asm_*
 //   precompute    : k_cc_*, k_refmin (components and d_min, Sec. 3.2)
+#include <algorithm>
+
 #include "bfc_kernels.h"
 #include "bfc_eval.h"
 
@@ -129,7 +132,49 @@ __global__ __launch_bounds__(256) void k_scan_down(const int* in, int* out, cons
   }
 }
 
+// one work-group scan for short arrays (n <= SCAN1_MAX)
+__global__ __launch_bounds__(1024) void k_scan1(const int* in, int* out, const int* n_dev, int n_const) {
+  int n = n_dev ? *n_dev : n_const;
+  __shared__ int ws[16];
+  __shared__ int carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < n; base += 1024 * SCAN_ITEMS) {
+    int v[SCAN_ITEMS];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+      int i = base + threadIdx.x * SCAN_ITEMS + k;
+      v[k] = i < n ? in[i] : 0;
+      s += v[k];
+    }
+    int x = wave_incl_scan(s);
+    int w = threadIdx.x >> 6;
+    if (lane_id() == 63) ws[w] = x;
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int k = 0; k < 16; ++k) {
+      if (k < w) off += ws[k];
+      tot += ws[k];
+    }
+    int run = carry + off + x - s;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+      int i = base + threadIdx.x * SCAN_ITEMS + k;
+      if (i < n) out[i] = run;
+      run += v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) carry += tot;
+    __syncthreads();
+  }
+}
+
 void scan_excl(const int* in, int* out, const int* n_dev, int n_max, int* tmp, hipStream_t st) {
+  if (n_max <= SCAN1_MAX) {
+    hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, st, in, out, n_dev, n_max);
+    return;
+  }
   int nb = (n_max + SCAN_TILE - 1) / SCAN_TILE;
   if (nb < 1) nb = 1;
   hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(256), 0, st, in, n_dev, n_max, tmp);
@@ -157,12 +202,6 @@ __global__ void k_zero_d(double* a, const long long* n_dev, long long n_const, l
 // Primitive numbering: [0, E) edges, [E, E+F) triangles, [E+F, E+F+V) points
 // (shells only).  Edges and triangles are stored in the grid; points and
 // edges query it.
-__global__ void k_begin(unsigned* bounds, long long* cand_count) {
-  if (threadIdx.x < 3) bounds[threadIdx.x] = 0xffffffffu;      // min: largest key
-  else if (threadIdx.x < 7) bounds[threadIdx.x] = 0u;           // max / extent: smallest key
-  if (threadIdx.x == 0 && cand_count) *cand_count = 0;
-}
-
 __device__ __forceinline__ int prim_verts(const SceneDev& S, int p, int* v) {
   if (p < S.ne) { v[0] = S.edges[2 * p]; v[1] = S.edges[2 * p + 1]; return 2; }
   if (p < S.ne + S.nt) {
@@ -174,58 +213,17 @@ __device__ __forceinline__ int prim_verts(const SceneDev& S, int p, int* v) {
   return 1;
 }
 
-__global__ __launch_bounds__(256) void k_bounds(SceneDev S, const double* x, int np, Box* box, unsigned* bounds) {
-  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, ext = 0.0f;
-  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += grid_stride()) {
-    int v[3];
-    int nvx = prim_verts(S, p, v);
-    double l[3] = {INFINITY, INFINITY, INFINITY}, h[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int k = 0; k < nvx; ++k)
-      for (int a = 0; a < 3; ++a) {
-        double c = x[3 * v[k] + a];
-        l[a] = fmin(l[a], c);
-        h[a] = fmax(h[a], c);
-      }
-    Box b;
-    for (int a = 0; a < 3; ++a) {
-      b.lo[a] = __double2float_rd(l[a]);
-      b.hi[a] = __double2float_ru(h[a]);
-      lo[a] = fminf(lo[a], b.lo[a]);
-      hi[a] = fmaxf(hi[a], b.hi[a]);
-      ext = fmaxf(ext, __double2float_ru((double)b.hi[a] - (double)b.lo[a]));
-    }
-    box[p] = b;
-  }
-  // wave reduction, then one atomic per wave
-  for (int o = 32; o > 0; o >>= 1) {
-    for (int a = 0; a < 3; ++a) {
-      lo[a] = fminf(lo[a], __shfl_xor(lo[a], o, 64));
-      hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], o, 64));
-    }
-    ext = fmaxf(ext, __shfl_xor(ext, o, 64));
-  }
-  if (lane_id() == 0) {
-    for (int a = 0; a < 3; ++a) {
-      if (lo[a] <= hi[a]) {
-        atomicMin(&bounds[a], f2ord(lo[a]));
-        atomicMax(&bounds[3 + a], f2ord(hi[a]));
-      }
-    }
-    atomicMax(&bounds[6], f2ord(ext));
-  }
-}
-
-__global__ void k_grid(const unsigned* bounds, double h, int max_cells, Grid* g) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Grid parameters from the scene bounds and the largest primitive box side.
+__device__ void make_grid(const float* lo_f, const float* hi_f, float ext_f, double h, int max_cells, Grid* g) {
   double lo[3], hi[3], span[3], amax = 0.0;
   for (int a = 0; a < 3; ++a) {
-    lo[a] = (double)ord2f(bounds[a]);
-    hi[a] = (double)ord2f(bounds[3 + a]);
+    lo[a] = (double)lo_f[a];
+    hi[a] = (double)hi_f[a];
     if (!(hi[a] >= lo[a])) { lo[a] = 0.0; hi[a] = 0.0; }
     span[a] = hi[a] - lo[a];
     amax = fmax(amax, fmax(fabs(lo[a]), fabs(hi[a])));
   }
-  double ext = (double)ord2f(bounds[6]);
+  double ext = (double)ext_f;
   if (!(ext >= 0.0)) ext = 0.0;
   double cell = (ext + h) * 1.001 + 1e-6 * (1.0 + amax);
   int coarse = 0;
@@ -253,6 +251,92 @@ __global__ void k_grid(const unsigned* bounds, double h, int max_cells, Grid* g)
   g->ncells = (int)tot;
   g->nscan = 2 * (int)tot + 1;
   g->coarsened = coarse;
+}
+
+// Boxes of all primitives (FP32, rounded outward) and, in the last block to
+// finish, the reduction of the per-block bounds and the grid parameters.
+// The last block also clears the candidate counter of this step.
+__global__ __launch_bounds__(256) void k_bounds(SceneDev S, const double* x, int np, Box* box, float* part,
+                                                unsigned* done, double h, int max_cells, Grid* grid,
+                                                long long* cand_count) {
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, ext = 0.0f;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += grid_stride()) {
+    int v[3];
+    int nvx = prim_verts(S, p, v);
+    double l[3] = {INFINITY, INFINITY, INFINITY}, hh[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int k = 0; k < nvx; ++k)
+      for (int a = 0; a < 3; ++a) {
+        double c = x[3 * v[k] + a];
+        l[a] = fmin(l[a], c);
+        hh[a] = fmax(hh[a], c);
+      }
+    Box b;
+    for (int a = 0; a < 3; ++a) {
+      b.lo[a] = __double2float_rd(l[a]);
+      b.hi[a] = __double2float_ru(hh[a]);
+      lo[a] = fminf(lo[a], b.lo[a]);
+      hi[a] = fmaxf(hi[a], b.hi[a]);
+      ext = fmaxf(ext, __double2float_ru((double)b.hi[a] - (double)b.lo[a]));
+    }
+    box[p] = b;
+  }
+  __shared__ float red[4][7];
+  __shared__ int last;
+  for (int o = 32; o > 0; o >>= 1) {
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = fminf(lo[a], __shfl_xor(lo[a], o, 64));
+      hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], o, 64));
+    }
+    ext = fmaxf(ext, __shfl_xor(ext, o, 64));
+  }
+  int w = threadIdx.x >> 6;
+  if (lane_id() == 0) {
+    for (int a = 0; a < 3; ++a) { red[w][a] = lo[a]; red[w][3 + a] = hi[a]; }
+    red[w][6] = ext;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float r[7];
+    for (int a = 0; a < 7; ++a) r[a] = red[0][a];
+    for (int k = 1; k < 4; ++k) {
+      for (int a = 0; a < 3; ++a) { r[a] = fminf(r[a], red[k][a]); r[3 + a] = fmaxf(r[3 + a], red[k][3 + a]); }
+      r[6] = fmaxf(r[6], red[k][6]);
+    }
+    for (int a = 0; a < 7; ++a) part[8 * blockIdx.x + a] = r[a];
+    __threadfence();
+    last = atomicAdd(done, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  // last block: reduce the partials of all blocks (one per thread, then a
+  // wave reduction and a 4-wave combine)
+  __threadfence();
+  float r[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, 0.0f};
+  const volatile float* vp = part;
+  for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x) {
+    for (int a = 0; a < 3; ++a) { r[a] = fminf(r[a], vp[8 * b + a]); r[3 + a] = fmaxf(r[3 + a], vp[8 * b + 3 + a]); }
+    r[6] = fmaxf(r[6], vp[8 * b + 6]);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    for (int a = 0; a < 3; ++a) {
+      r[a] = fminf(r[a], __shfl_xor(r[a], o, 64));
+      r[3 + a] = fmaxf(r[3 + a], __shfl_xor(r[3 + a], o, 64));
+    }
+    r[6] = fmaxf(r[6], __shfl_xor(r[6], o, 64));
+  }
+  __syncthreads();
+  if (lane_id() == 0)
+    for (int a = 0; a < 7; ++a) red[w][a] = r[a];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < 4; ++k) {
+      for (int a = 0; a < 3; ++a) { r[a] = fminf(r[a], red[k][a]); r[3 + a] = fmaxf(r[3 + a], red[k][3 + a]); }
+      r[6] = fmaxf(r[6], red[k][6]);
+    }
+    make_grid(r, r + 3, r[6], h, max_cells, grid);
+    if (cand_count) *cand_count = 0;
+    *done = 0u;
+  }
 }
 
 __device__ __forceinline__ void cell_coords(const Grid& g, const Box& b, int* c) {
@@ -305,91 +389,114 @@ __device__ __forceinline__ bool boxes_near(const Box& a, const Box& b, double h)
   return true;
 }
 
-// Visit every stored primitive of sub-list `sub` (0 edges, 1 triangles) in the
-// cells adjacent to the query's cell whose box is within h of the query box
-// and that forms a non-incident pair; emit (or count) it.
+// Visit the stored primitives of the sub-list for the query (triangles for a
+// point, edges for an edge) in the neighbour cells c = sub, sub + PQ_T, ...
+// of the 27 cells around the query's cell; count, or emit at `pos`, every
+// non-incident pair whose boxes are within h.
 template <bool EMIT>
 __device__ __forceinline__ int visit_pairs(const SceneDev& S, const Grid& g, const int* cell_start,
                                            const int* sorted_id, const Box* sorted_box, double hf, int qtype,
-                                           int qid, const Box& qb, const int* qv, long long pos, long long cap,
-                                           int* oi, int* oj, unsigned char* ot, unsigned* status) {
+                                           int qid, const Box& qb, const int* qv, int sub, long long pos,
+                                           long long cap, int* oi, int* oj, unsigned char* ot, unsigned* status) {
   int c[3];
   cell_coords(g, qb, c);
   int cnt = 0;
   int sub_type = qtype == BF_PT ? 1 : 0;
-  int z0 = max(c[2] - 1, 0), z1 = min(c[2] + 1, g.n[2] - 1);
-  int y0 = max(c[1] - 1, 0), y1 = min(c[1] + 1, g.n[1] - 1);
-  int x0 = max(c[0] - 1, 0), x1 = min(c[0] + 1, g.n[0] - 1);
-  for (int cz = z0; cz <= z1; ++cz)
-    for (int cy = y0; cy <= y1; ++cy)
-      for (int cx = x0; cx <= x1; ++cx) {
-        int sub = 2 * cell_lin(g, cx, cy, cz) + sub_type;
-        int b = cell_start[sub], e = cell_start[sub + 1];
-        for (int k = b; k < e; ++k) {
-          Box rb = sorted_box[k];
-          if (!boxes_near(qb, rb, hf)) continue;
-          int r = sorted_id[k];
-          if (qtype == BF_EE) {
-            if (r <= qid) continue;
-            int r0 = S.edges[2 * r], r1 = S.edges[2 * r + 1];
-            if (r0 == qv[0] || r0 == qv[1] || r1 == qv[0] || r1 == qv[1]) continue;
-          } else {
-            int t = r - S.ne;
-            int t0 = S.tris[3 * t], t1 = S.tris[3 * t + 1], t2 = S.tris[3 * t + 2];
-            if (t0 == qid || t1 == qid || t2 == qid) continue;
-            r = t;
-          }
-          if (EMIT) {
-            long long p = pos + cnt;
-            if (p < cap) {
-              oi[p] = qid;
-              oj[p] = r;
-              ot[p] = (unsigned char)qtype;
-            } else {
-              atomicOr(status, (unsigned)BF_S_CAND_OVERFLOW);
-            }
-          }
-          ++cnt;
+  for (int nb = sub; nb < 27; nb += PQ_T) {
+    int cx = c[0] + nb % 3 - 1, cy = c[1] + (nb / 3) % 3 - 1, cz = c[2] + nb / 9 - 1;
+    if (cx < 0 || cy < 0 || cz < 0 || cx >= g.n[0] || cy >= g.n[1] || cz >= g.n[2]) continue;
+    int sl = 2 * cell_lin(g, cx, cy, cz) + sub_type;
+    int b = cell_start[sl], e = cell_start[sl + 1];
+    for (int k = b; k < e; ++k) {
+      Box rb = sorted_box[k];
+      if (!boxes_near(qb, rb, hf)) continue;
+      int r = sorted_id[k];
+      if (qtype == BF_EE) {
+        if (r <= qid) continue;
+        int r0 = S.edges[2 * r], r1 = S.edges[2 * r + 1];
+        if (r0 == qv[0] || r0 == qv[1] || r1 == qv[0] || r1 == qv[1]) continue;
+      } else {
+        int t = r - S.ne;
+        int t0 = S.tris[3 * t], t1 = S.tris[3 * t + 1], t2 = S.tris[3 * t + 2];
+        if (t0 == qid || t1 == qid || t2 == qid) continue;
+        r = t;
+      }
+      if (EMIT) {
+        long long p = pos + cnt;
+        if (p < cap) {
+          oi[p] = qid;
+          oj[p] = r;
+          ot[p] = (unsigned char)qtype;
+        } else {
+          atomicOr(status, (unsigned)BF_S_CAND_OVERFLOW);
         }
       }
+      ++cnt;
+    }
+  }
   return cnt;
 }
 
-__global__ __launch_bounds__(256) void k_pairs(SceneDev S, int nquery, const Box* box, const Grid* gp,
-                                               const int* cell_start, const int* sorted_id, const Box* sorted_box,
-                                               double hf, int* oi, int* oj, unsigned char* ot, long long cap,
-                                               unsigned long long* count, unsigned* status) {
-  Grid g = *gp;
-  // wave-uniform loop so that all lanes take part in the scans
-  for (int base = blockIdx.x * blockDim.x; base < nquery; base += grid_stride()) {
-    int q = base + threadIdx.x;
-    int qtype = BF_EE, qid = 0, qv[2] = {-1, -1};
-    Box qb;
-    bool valid = q < nquery;
-    if (valid) {
-      if (S.kind == 1 && q < S.nv) {  // point query against triangles
-        qtype = BF_PT;
-        qid = q;
-        qb = box[S.ne + S.nt + q];
-      } else {                         // edge query against edges with larger id
-        qid = S.kind == 1 ? q - S.nv : q;
-        qb = box[qid];
-        qv[0] = S.edges[2 * qid];
-        qv[1] = S.edges[2 * qid + 1];
-      }
-    }
-    int cnt = valid ? visit_pairs<false>(S, g, cell_start, sorted_id, sorted_box, hf, qtype, qid, qb, qv, 0, 0,
-                                         nullptr, nullptr, nullptr, nullptr)
-                    : 0;
-    long long incl = wave_incl_scan((long long)cnt);
-    long long tot = __shfl(incl, 63, 64);
-    long long wbase = 0;
-    if (lane_id() == 63 && tot > 0) wbase = (long long)atomicAdd(count, (unsigned long long)tot);
-    wbase = __shfl(wbase, 63, 64);
-    if (valid && cnt > 0)
-      visit_pairs<true>(S, g, cell_start, sorted_id, sorted_box, hf, qtype, qid, qb, qv, wbase + incl - cnt, cap,
-                        oi, oj, ot, status);
+__device__ __forceinline__ void query_of(const SceneDev& S, const Box* box, int q, int& qtype, int& qid, Box& qb,
+                                         int* qv) {
+  if (S.kind == 1 && q < S.nv) {  // point query against triangles
+    qtype = BF_PT;
+    qid = q;
+    qb = box[S.ne + S.nt + q];
+    qv[0] = qv[1] = -1;
+  } else {                         // edge query against edges with a larger id
+    qtype = BF_EE;
+    qid = S.kind == 1 ? q - S.nv : q;
+    qb = box[qid];
+    qv[0] = S.edges[2 * qid];
+    qv[1] = S.edges[2 * qid + 1];
   }
+}
+
+// pass 1: pair count of every (query, neighbour-cell subset) thread, and the
+// total of each work-group in bsum[block] (bsum[nblocks] = 0)
+__global__ __launch_bounds__(256) void k_pair_count(SceneDev S, int nquery, const Box* box, const Grid* gp,
+                                                    const int* cell_start, const int* sorted_id, const Box* sorted_box,
+                                                    double hf, int* cnt, int* bsum) {
+  Grid g = *gp;
+  int nt = nquery * PQ_T;
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int c = 0;
+  if (t < nt) {
+    int qtype, qid, qv[2];
+    Box qb;
+    query_of(S, box, t / PQ_T, qtype, qid, qb, qv);
+    c = visit_pairs<false>(S, g, cell_start, sorted_id, sorted_box, hf, qtype, qid, qb, qv, t % PQ_T, 0, 0, nullptr,
+                           nullptr, nullptr, nullptr);
+    cnt[t] = c;
+  }
+  int tot;
+  block_excl_scan256(c, &tot);
+  if (threadIdx.x == 0) {
+    bsum[blockIdx.x] = tot;
+    if (blockIdx.x == 0) bsum[gridDim.x] = 0;
+  }
+}
+
+// pass 2: offsets from the scanned work-group totals plus an in-group scan;
+// emit in query-major order (no atomics)
+__global__ __launch_bounds__(256) void k_pair_emit(SceneDev S, int nquery, const Box* box, const Grid* gp,
+                                                   const int* cell_start, const int* sorted_id, const Box* sorted_box,
+                                                   double hf, const int* cnt, const int* boff, int* oi, int* oj,
+                                                   unsigned char* ot, long long cap, long long* count,
+                                                   unsigned* status) {
+  Grid g = *gp;
+  int nt = nquery * PQ_T;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *count = (long long)boff[gridDim.x];
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int c = t < nt ? cnt[t] : 0;
+  int off = boff[blockIdx.x] + block_excl_scan256(c, nullptr);
+  if (c == 0) return;
+  int qtype, qid, qv[2];
+  Box qb;
+  query_of(S, box, t / PQ_T, qtype, qid, qb, qv);
+  visit_pairs<true>(S, g, cell_start, sorted_id, sorted_box, hf, qtype, qid, qb, qv, t % PQ_T, off, cap, oi, oj, ot,
+                    status);
 }
 
 // ---------------------------------------------------------------------------
@@ -469,17 +576,37 @@ __device__ __forceinline__ bool is_filtered(const SceneDev& S, int type, const i
   return dd_lt(m, qq) && dd_lt(qq, hh - m);
 }
 
+// Order of the active list by distance kind: 9 x 9 systems (PT, EE) first,
+// then 6 x 6 (PE), then the closed form (PP), so the evaluation kernel's
+// waves are uniform and the heaviest start first.
+__device__ __forceinline__ int kind_rank(int code) {
+  int k = case_kind(code);
+  return (k == K_PT || k == K_EE) ? 0 : (k == K_PE ? 1 : 2);
+}
+
+// Pass 1 of the narrow phase: tile b = candidates [b*NW_TILE, (b+1)*NW_TILE).
+// Active pairs are compacted inside the tile by kind, in candidate order,
+// into the staging arrays; per-kind counts go to kcnt[K*G + b] and the
+// tile's N_c / N_filt / N_infeasible to ccnt[3b..3b+2].  No global atomics.
 __global__ __launch_bounds__(256) void k_narrow(SceneDev S, const double* x, const int* ci, const int* cj,
                                                 const unsigned char* ct, const long long* cand_count, long long ccap,
-                                                int* ai, int* aj, unsigned char* at, unsigned char* acode,
-                                                unsigned char* aflags, double* adist, long long acap,
-                                                unsigned long long* act_count, unsigned long long* counters,
-                                                unsigned* status) {
+                                                StageWs W) {
   long long n = *cand_count;
   if (n > ccap) n = ccap;
+  const int G = gridDim.x;
+  const long long base = (long long)blockIdx.x * NW_TILE;
   const dd h2 = dd_sq(S.h), e2 = dd_sq(S.eta);
-  for (long long base = (long long)blockIdx.x * blockDim.x; base < n; base += grid_stride()) {
-    long long k = base + threadIdx.x;
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  __shared__ int wc[NW_ITEMS][4][3];
+  __shared__ int cc[4][3];
+  int ri[NW_ITEMS], rj[NW_ITEMS], rk[NW_ITEMS], lr[NW_ITEMS];
+  unsigned rm[NW_ITEMS];
+  double rd[NW_ITEMS];
+  bool act[NW_ITEMS];
+  int c_nc = 0, c_f = 0, c_inf = 0;
+#pragma unroll
+  for (int it = 0; it < NW_ITEMS; ++it) {
+    long long k = base + it * 256 + threadIdx.x;
     bool nc = false, filt = false, active = false, infeas = false;
     int type = 0, i = 0, j = 0, code = 0;
     double D = 0.0;
@@ -508,33 +635,98 @@ __global__ __launch_bounds__(256) void k_narrow(SceneDev S, const double* x, con
         if (active) infeas = eta > 0.0 ? decide_sq(code, P, D, e2, false) : !(D > 0.0);
       }
     }
-    unsigned long long m_nc = __ballot(nc), m_f = __ballot(nc && filt), m_a = __ballot(active),
-                       m_i = __ballot(infeas);
-    if (lane_id() == 0) {
-      if (m_nc) atomicAdd(&counters[0], (unsigned long long)__popcll(m_nc));
-      if (m_f) atomicAdd(&counters[1], (unsigned long long)__popcll(m_f));
-      if (m_a) atomicAdd(&counters[2], (unsigned long long)__popcll(m_a));
-      if (m_i) {
-        atomicAdd(&counters[3], (unsigned long long)__popcll(m_i));
-        atomicOr(status, (unsigned)BF_S_INFEASIBLE);
+    c_nc += nc; c_f += nc && filt; c_inf += infeas;
+    act[it] = active;
+    rk[it] = active ? kind_rank(code) : 3;
+    ri[it] = i; rj[it] = j;
+    rm[it] = (unsigned)type | ((unsigned)code << 8) |
+             ((unsigned)((filt ? BF_F_FILTERED : 0) | (infeas ? BF_F_INFEASIBLE : 0)) << 16);
+    rd[it] = sqrt(D);
+#pragma unroll
+    for (int K = 0; K < 3; ++K) {
+      unsigned long long m = __ballot(rk[it] == K);
+      if (lane == 0) wc[it][w][K] = __popcll(m);
+      if (rk[it] == K) lr[it] = lanes_below(m);
+    }
+  }
+  c_nc = wave_sum(c_nc); c_f = wave_sum(c_f); c_inf = wave_sum(c_inf);
+  if (lane == 0) { cc[w][0] = c_nc; cc[w][1] = c_f; cc[w][2] = c_inf; }
+  __syncthreads();
+  int tot[3] = {0, 0, 0};
+#pragma unroll
+  for (int it = 0; it < NW_ITEMS; ++it)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int K = 0; K < 3; ++K) tot[K] += wc[it][q][K];
+  const int koff[3] = {0, tot[0], tot[0] + tot[1]};
+#pragma unroll
+  for (int it = 0; it < NW_ITEMS; ++it) {
+    if (!act[it]) continue;
+    int K = rk[it];
+    int off = koff[K] + lr[it];
+    for (int i2 = 0; i2 < NW_ITEMS; ++i2)
+      for (int q = 0; q < 4; ++q)
+        if (i2 < it || (i2 == it && q < w)) off += wc[i2][q][K];
+    long long p = base + off;
+    W.si[p] = ri[it];
+    W.sj[p] = rj[it];
+    W.sm[p] = rm[it];
+    W.sd[p] = rd[it];
+  }
+  if (threadIdx.x == 0) {
+    for (int K = 0; K < 3; ++K) W.kcnt[K * G + blockIdx.x] = tot[K];
+    if (blockIdx.x == 0) W.kcnt[3 * G] = 0;
+    int a = 0, b = 0, c = 0;
+    for (int q = 0; q < 4; ++q) { a += cc[q][0]; b += cc[q][1]; c += cc[q][2]; }
+    W.ccnt[3 * blockIdx.x] = a;
+    W.ccnt[3 * blockIdx.x + 1] = b;
+    W.ccnt[3 * blockIdx.x + 2] = c;
+  }
+}
+
+// Pass 2: copy each tile's staged pairs to their kind-major position
+// kofs[K*G + b] + r of the active list; block 0 also writes the counters.
+__global__ __launch_bounds__(256) void k_compact(StageWs W, int G, int* ai, int* aj, unsigned char* at,
+                                                 unsigned char* acode, unsigned char* aflags, double* adist,
+                                                 long long acap, long long* act_count, long long* counters,
+                                                 unsigned* status) {
+  const int b = blockIdx.x;
+  const long long base = (long long)b * NW_TILE;
+  int koff = 0;
+  for (int K = 0; K < 3; ++K) {
+    int cnt = W.kcnt[K * G + b];
+    long long dst = W.kofs[K * G + b];
+    for (int r = threadIdx.x; r < cnt; r += blockDim.x) {
+      long long src = base + koff + r, d = dst + r;
+      if (d < acap) {
+        unsigned m = W.sm[src];
+        ai[d] = W.si[src];
+        aj[d] = W.sj[src];
+        at[d] = (unsigned char)(m & 0xff);
+        acode[d] = (unsigned char)((m >> 8) & 0xff);
+        aflags[d] = (unsigned char)((m >> 16) & 0xff);
+        adist[d] = W.sd[src];
       }
     }
-    if (m_a) {
-      int leader = __ffsll((long long)m_a) - 1;
-      unsigned long long wb = 0;
-      if (lane_id() == leader) wb = atomicAdd(act_count, (unsigned long long)__popcll(m_a));
-      wb = __shfl(wb, leader, 64);
-      if (active) {
-        long long pos = (long long)wb + lanes_below(m_a);
-        if (pos < acap) {
-          ai[pos] = i; aj[pos] = j; at[pos] = (unsigned char)type;
-          acode[pos] = (unsigned char)code;
-          aflags[pos] = (unsigned char)((filt ? BF_F_FILTERED : 0) | (infeas ? BF_F_INFEASIBLE : 0));
-          adist[pos] = sqrt(D);
-        } else {
-          atomicOr(status, (unsigned)BF_S_ACT_OVERFLOW);
-        }
-      }
+    koff += cnt;
+  }
+  if (b == 0) {
+    __shared__ long long red[3][256];
+    long long a = 0, f = 0, c = 0;
+    for (int q = threadIdx.x; q < G; q += blockDim.x) {
+      a += W.ccnt[3 * q]; f += W.ccnt[3 * q + 1]; c += W.ccnt[3 * q + 2];
+    }
+    red[0][threadIdx.x] = a; red[1][threadIdx.x] = f; red[2][threadIdx.x] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      long long A = 0, F = 0, C = 0;
+      for (int q = 0; q < (int)blockDim.x; ++q) { A += red[0][q]; F += red[1][q]; C += red[2][q]; }
+      long long nact = W.kofs[3 * G];
+      counters[0] = A; counters[1] = F; counters[2] = nact; counters[3] = C;
+      *act_count = nact;
+      if (nact > acap) atomicOr(status, (unsigned)BF_S_ACT_OVERFLOW);
+      if (C > 0) atomicOr(status, (unsigned)BF_S_INFEASIBLE);
     }
   }
 }
@@ -542,40 +734,51 @@ __global__ __launch_bounds__(256) void k_narrow(SceneDev S, const double* x, con
 // ---------------------------------------------------------------------------
 // Barrier evaluation (Eq. 2, Eq. 3) and PSD projection
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(128) void k_eval(SceneDev S, const double* x, const int* ai, const int* aj,
-                                              const unsigned char* at, const unsigned char* acode,
-                                              const unsigned char* aflags, const unsigned long long* act_count,
-                                              long long acap, double* E, double* G, double* H) {
+// One wave per work-group; every lane evaluates one pair into its row of an
+// LDS tile (E, G[12], H[78]), and the wave then writes the tile's contiguous
+// rows of E, G and H with coalesced stores.
+__global__ __launch_bounds__(64) void k_eval(SceneDev S, const double* x, const int* ai, const int* aj,
+                                             const unsigned char* at, const unsigned char* acode,
+                                             const unsigned char* aflags, const unsigned long long* act_count,
+                                             long long acap, double* E, double* G, double* H) {
+  __shared__ double tE[64], tG[64 * 12], tH[64 * 78];
   long long n = (long long)*act_count;
   if (n > acap) n = acap;
-  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += grid_stride()) {
-    int type = at[k], code = acode[k], fl = aflags[k];
-    int v[4];
-    pair_verts(S, type, ai[k], aj[k], v);
-    PairOut o;
-    if (fl & BF_F_INFEASIBLE) {
-      o.E = INFINITY;
-#pragma unroll
-      for (int q = 0; q < 12; ++q) o.G[q] = 0.0;
-#pragma unroll
-      for (int q = 0; q < 78; ++q) o.H[q] = 0.0;
-    } else {
-      d3 P[4] = {load3(x, v[0]), load3(x, v[1]), load3(x, v[2]), load3(x, v[3])};
-      double a, eta;
-      if (fl & BF_F_FILTERED) { a = S.dmin[S.comp[v[0]]]; eta = 0.0; }
-      else { a = S.h; eta = S.eta; }
-      eval_pair(P, code, a, eta, S.kappa, o);
+  const int lane = threadIdx.x;
+  for (long long k0 = (long long)blockIdx.x * 64; k0 < n; k0 += (long long)gridDim.x * 64) {
+    long long k = k0 + lane;
+    OutRow o{tE + lane, tG + 12 * lane, tH + 78 * lane};
+    if (k < n) {
+      int type = at[k], code = acode[k], fl = aflags[k];
+      int v[4];
+      pair_verts(S, type, ai[k], aj[k], v);
+      if (fl & BF_F_INFEASIBLE) {
+        *o.E = INFINITY;
+        zero_row(o);
+      } else {
+        d3 P[4] = {load3(x, v[0]), load3(x, v[1]), load3(x, v[2]), load3(x, v[3])};
+        double a, eta;
+        if (fl & BF_F_FILTERED) { a = S.dmin[S.comp[v[0]]]; eta = 0.0; }
+        else { a = S.h; eta = S.eta; }
+        eval_pair(P, code, a, eta, S.kappa, o);
+      }
     }
-    E[k] = o.E;
-#pragma unroll
-    for (int q = 0; q < 12; ++q) G[12 * k + q] = o.G[q];
-#pragma unroll
-    for (int q = 0; q < 78; ++q) H[78 * k + q] = o.H[q];
+    __syncthreads();
+    int rows = (int)min((long long)64, n - k0);
+    if (lane < rows) E[k0 + lane] = tE[lane];
+    for (int q = lane; q < rows * 12; q += 64) G[12 * k0 + q] = tG[q];
+    for (int q = lane; q < rows * 78; q += 64) H[78 * k0 + q] = tH[q];
+    __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
-// Assembly
+// Assembly (owner computes): every stencil vertex of every feasible active
+// pair gets an incidence entry 4k + s (pair k, slot s).  A counting sort
+// groups the entries by vertex; one thread per vertex then sums its gradient
+// and assembles its BSR row.  No floating-point atomics, and every sum is
+// taken in increasing entry order, so the result does not depend on thread
+// timing.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_esum(const double* E, const unsigned long long* act_count, long long acap,
                                               double* part) {
@@ -599,9 +802,9 @@ __global__ __launch_bounds__(256) void k_esum_final(const double* part, int npar
   if (threadIdx.x == 0) *out = (ws[0] + ws[1]) + (ws[2] + ws[3]);
 }
 
-__global__ __launch_bounds__(256) void k_grad(SceneDev S, const int* ai, const int* aj, const unsigned char* at,
-                                              const unsigned char* aflags, const unsigned long long* act_count,
-                                              long long acap, const double* G, double* g) {
+__global__ __launch_bounds__(256) void k_inc_count(SceneDev S, const int* ai, const int* aj, const unsigned char* at,
+                                                   const unsigned char* aflags, const unsigned long long* act_count,
+                                                   long long acap, int* inc_cnt) {
   long long n = (long long)*act_count;
   if (n > acap) n = acap;
   for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += grid_stride()) {
@@ -609,49 +812,135 @@ __global__ __launch_bounds__(256) void k_grad(SceneDev S, const int* ai, const i
     int v[4];
     pair_verts(S, at[k], ai[k], aj[k], v);
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        double val = G[12 * k + 3 * s + a];
-        if (val != 0.0) unsafeAtomicAdd(&g[3 * v[s] + a], val);
-      }
+    for (int s = 0; s < 4; ++s) atomicAdd(&inc_cnt[v[s]], 1);
   }
 }
 
-__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
-  z ^= z >> 33; z *= 0xff51afd7ed558ccdull;
-  z ^= z >> 33; z *= 0xc4ceb9fe1a85ec53ull;
-  z ^= z >> 33;
-  return z;
-}
-
-// Insert the 16 (row, col) blocks of every feasible active pair; count new
-// keys per row.
-__global__ __launch_bounds__(256) void k_asm_insert(SceneDev S, const int* ai, const int* aj, const unsigned char* at,
-                                                    const unsigned char* aflags,
-                                                    const unsigned long long* act_count, long long acap,
-                                                    unsigned long long* keys, long long hsize, int* entry_slot,
-                                                    int* rowcnt, unsigned* status) {
+// scatter the entries into their vertex segments; returns the counts to zero
+__global__ __launch_bounds__(256) void k_inc_fill(SceneDev S, const int* ai, const int* aj, const unsigned char* at,
+                                                  const unsigned char* aflags, const unsigned long long* act_count,
+                                                  long long acap, int* inc_cnt, const int* inc_off, int* inc) {
   long long n = (long long)*act_count;
   if (n > acap) n = acap;
-  unsigned long long mask = (unsigned long long)hsize - 1;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < 16 * n; e += grid_stride()) {
-    long long k = e >> 4;
-    int b = (int)(e & 15);
-    if (aflags[k] & BF_F_INFEASIBLE) { entry_slot[e] = -1; continue; }
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += grid_stride()) {
+    if (aflags[k] & BF_F_INFEASIBLE) continue;
     int v[4];
     pair_verts(S, at[k], ai[k], aj[k], v);
-    unsigned long long key = ((unsigned long long)(unsigned)v[b >> 2] << 32) | (unsigned)v[b & 3];
-    unsigned long long h = mix64(key) & mask;
-    int slot = -1;
-    for (long long probe = 0; probe < hsize; ++probe) {
-      unsigned long long prev = atomicCAS(&keys[h], kEmpty, key);
-      if (prev == kEmpty) { slot = (int)h; atomicAdd(&rowcnt[v[b >> 2]], 1); break; }
-      if (prev == key) { slot = (int)h; break; }
-      h = (h + 1) & mask;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      int pos = inc_off[v[s]] + atomicSub(&inc_cnt[v[s]], 1) - 1;
+      inc[pos] = (int)(4 * k + s);
     }
-    if (slot < 0) atomicOr(status, (unsigned)BF_S_HASH_OVERFLOW);
-    entry_slot[e] = slot;
+  }
+}
+
+// Bitonic sort of a[0..P) (P a power of two) by the one wave of the block.
+__device__ __forceinline__ void wave_bitonic(int* a, int P) {
+  for (int k = 2; k <= P; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < P; i += 64) {
+        int l = i ^ j;
+        if (l > i) {
+          int x = a[i], y = a[l];
+          bool up = (i & k) == 0;
+          if ((x > y) == up) { a[i] = y; a[l] = x; }
+        }
+      }
+      __syncthreads();
+    }
+}
+__device__ __forceinline__ int pow2_at_least(int n) {
+  int p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+// Rows with more candidate columns than this fall back to one lane and
+// global memory (correct, slower; a vertex in more than 128 active pairs).
+// The small tile keeps many waves resident: the row kernels are latency bound.
+constexpr int ROW_LDS = 512;
+
+__device__ void isort_global(int* a, int m) {
+  for (int i = 1; i < m; ++i) {
+    int x = a[i], j = i - 1;
+    while (j >= 0 && a[j] > x) { a[j + 1] = a[j]; --j; }
+    a[j + 1] = x;
+  }
+}
+
+// Pass A, one wave per vertex v: sort its incidence entries (deterministic
+// sums), sum its gradient in that order, and store its distinct columns
+// (the stencil vertices of its pairs) sorted at colbuf[4 * inc_off[v] ...];
+// rowcnt[v] = their number.
+__global__ __launch_bounds__(64) void k_row_a(SceneDev S, const int* ai, const int* aj, const unsigned char* at,
+                                              const int* inc_off, int* inc, const double* G, double* g, int* colbuf,
+                                              int* rowcnt) {
+  __shared__ int buf[ROW_LDS];
+  __shared__ int ent[ROW_LDS / 4];
+  const int lane = threadIdx.x;
+  for (int v = blockIdx.x; v < S.nv; v += gridDim.x) {
+    const int b = inc_off[v], m = inc_off[v + 1] - b;
+    int* cb = colbuf + 4LL * b;
+    if (4 * m > ROW_LDS) {  // rare: serial fallback in global memory
+      if (lane == 0) {
+        isort_global(inc + b, m);
+        double gx = 0.0, gy = 0.0, gz = 0.0;
+        for (int q = 0; q < m; ++q) {
+          int e = inc[b + q], k = e >> 2, s = e & 3;
+          gx += G[12LL * k + 3 * s]; gy += G[12LL * k + 3 * s + 1]; gz += G[12LL * k + 3 * s + 2];
+          int vv[4];
+          pair_verts(S, at[k], ai[k], aj[k], vv);
+          for (int c = 0; c < 4; ++c) cb[4 * q + c] = vv[c];
+        }
+        g[3 * v] = gx; g[3 * v + 1] = gy; g[3 * v + 2] = gz;
+        isort_global(cb, 4 * m);
+        int u = 0;
+        for (int q = 0; q < 4 * m; ++q)
+          if (q == 0 || cb[q] != cb[q - 1]) cb[u++] = cb[q];
+        rowcnt[v] = u;
+      }
+      __syncthreads();
+      continue;
+    }
+    const int Pm = pow2_at_least(m > 0 ? m : 1);
+    for (int q = lane; q < Pm; q += 64) ent[q] = q < m ? inc[b + q] : 0x7fffffff;
+    __syncthreads();
+    wave_bitonic(ent, Pm);
+    // gradient in entry order: each lane sums a contiguous run, then the runs
+    // are combined in lane order
+    const int per = (m + 63) / 64;
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int q = lane * per; q < m && q < (lane + 1) * per; ++q) {
+      int e = ent[q], k = e >> 2, s = e & 3;
+      gx += G[12LL * k + 3 * s]; gy += G[12LL * k + 3 * s + 1]; gz += G[12LL * k + 3 * s + 2];
+    }
+    for (int o = 1; o < 64; o <<= 1) {  // ordered tree: lane i adds lane i+o
+      double tx = __shfl_down(gx, o, 64), ty = __shfl_down(gy, o, 64), tz = __shfl_down(gz, o, 64);
+      if ((lane & (2 * o - 1)) == 0) { gx += tx; gy += ty; gz += tz; }
+    }
+    if (lane == 0) { g[3 * v] = gx; g[3 * v + 1] = gy; g[3 * v + 2] = gz; }
+    for (int q = lane; q < m; q += 64) inc[b + q] = ent[q];
+    const int n = 4 * m, P = pow2_at_least(n > 0 ? n : 1);
+    for (int q = lane; q < m; q += 64) {
+      int k = ent[q] >> 2;
+      int vv[4];
+      pair_verts(S, at[k], ai[k], aj[k], vv);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) buf[4 * q + c] = vv[c];
+    }
+    for (int q = n + lane; q < P; q += 64) buf[q] = 0x7fffffff;
+    __syncthreads();
+    wave_bitonic(buf, P);
+    int u = 0;
+    for (int base = 0; base < n; base += 64) {
+      int i = base + lane;
+      bool first = i < n && (i == 0 || buf[i] != buf[i - 1]);
+      unsigned long long msk = __ballot(first);
+      if (first) cb[u + lanes_below(msk)] = buf[i];
+      u += __popcll(msk);
+    }
+    if (lane == 0) rowcnt[v] = u;
+    __syncthreads();
   }
 }
 
@@ -663,53 +952,59 @@ __global__ void k_asm_nnzb(const int* row_ptr, int nv, long long* nnzb, long lon
   }
 }
 
-__global__ __launch_bounds__(256) void k_asm_fillseg(const unsigned long long* keys, long long hsize, const int* row_ptr,
-                                                     int* rowfill, int* tmpcol, long long cap) {
-  for (long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x; s < hsize; s += grid_stride()) {
-    unsigned long long key = keys[s];
-    if (key == kEmpty) continue;
-    int row = (int)(key >> 32);
-    int pos = row_ptr[row] + atomicAdd(&rowfill[row], 1);
-    if (pos < cap) tmpcol[pos] = (int)(key & 0xffffffffu);
-  }
-}
-
-__global__ __launch_bounds__(256) void k_asm_rank(const unsigned long long* keys, long long hsize, const int* row_ptr,
-                                                  const int* tmpcol, int* slot_pos, int* col_out, long long cap) {
-  for (long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x; s < hsize; s += grid_stride()) {
-    unsigned long long key = keys[s];
-    if (key == kEmpty) continue;
-    int row = (int)(key >> 32), col = (int)(key & 0xffffffffu);
-    int lo = row_ptr[row], hi = row_ptr[row + 1];
-    if (hi > cap) { slot_pos[s] = -1; continue; }
-    int rank = 0;
-    for (int q = lo; q < hi; ++q) rank += tmpcol[q] < col ? 1 : 0;
-    slot_pos[s] = lo + rank;
-    col_out[lo + rank] = col;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_asm_vals(const unsigned long long* act_count, long long acap,
-                                                  const unsigned char* aflags, const int* entry_slot,
-                                                  const int* slot_pos, const double* H, double* val) {
-  long long n = (long long)*act_count;
-  if (n > acap) n = acap;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < 16 * n; e += grid_stride()) {
-    int slot = entry_slot[e];
-    if (slot < 0) continue;
-    int pos = slot_pos[slot];
-    if (pos < 0) continue;
-    long long k = e >> 4;
-    int b = (int)(e & 15), sr = b >> 2, sc = b & 3;
-    const double* Hk = H + 78 * k;
+// Pass B, one wave per vertex v: the row's entries and their stencil
+// vertices are staged in LDS; every lane owns some of the row's columns,
+// writes them and sums their 3x3 blocks over the entries in sorted order.
+__global__ __launch_bounds__(64) void k_row_b(SceneDev S, const int* ai, const int* aj, const unsigned char* at,
+                                              const int* inc_off, const int* inc, const int* colbuf, const double* H,
+                                              const int* row_ptr, int* col, double* val, long long cap) {
+  __shared__ int es[ROW_LDS / 4];
+  __shared__ int vs[ROW_LDS];
+  const int lane = threadIdx.x;
+  for (int v = blockIdx.x; v < S.nv; v += gridDim.x) {
+    const int b = inc_off[v], m = inc_off[v + 1] - b;
+    const int r0 = row_ptr[v], r1 = row_ptr[v + 1];
+    if (r1 > cap) continue;  // overflow: reported by k_asm_nnzb (uniform across the wave)
+    const bool staged = 4 * m <= ROW_LDS;
+    if (staged) {
+      for (int q = lane; q < m; q += 64) {
+        int e = inc[b + q], k = e >> 2;
+        es[q] = e;
+        int vv[4];
+        pair_verts(S, at[k], ai[k], aj[k], vv);
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        int I = 3 * sr + i, J = 3 * sc + j;
-        double hv = I <= J ? Hk[hix(I, J)] : Hk[hix(J, I)];
-        if (hv != 0.0) unsafeAtomicAdd(&val[9 * (long long)pos + 3 * i + j], hv);
+        for (int c = 0; c < 4; ++c) vs[4 * q + c] = vv[c];
       }
+    }
+    __syncthreads();
+    const int* cb = colbuf + 4LL * b;
+    for (int t = lane; t < r1 - r0; t += 64) {
+      const int c = cb[t];
+      col[r0 + t] = c;
+      double blk[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+      for (int q = 0; q < m; ++q) {
+        int e, vv[4];
+        if (staged) {
+          e = es[q];
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) vv[cc] = vs[4 * q + cc];
+        } else {
+          e = inc[b + q];
+          pair_verts(S, at[e >> 2], ai[e >> 2], aj[e >> 2], vv);
+        }
+        int sc = vv[0] == c ? 0 : vv[1] == c ? 1 : vv[2] == c ? 2 : vv[3] == c ? 3 : -1;
+        if (sc < 0) continue;
+        const int k = e >> 2, sr = e & 3;
+        const double* Hk = H + 78LL * k;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) blk[3 * i + j] += Hk[hix(3 * sr + i, 3 * sc + j)];
+      }
+#pragma unroll
+      for (int q = 0; q < 9; ++q) val[9LL * (r0 + t) + q] = blk[q];
+    }
+    __syncthreads();
   }
 }
 
@@ -821,66 +1116,61 @@ void run_broad(const SceneDev& S, const double* x, const BroadWs& W, int* oi, in
   int nquery = S.kind == 1 ? S.nv + S.ne : S.ne;
   int nscan_max = 2 * W.max_cells + 1;
   const int* nscan_dev = &W.grid->nscan;
-  hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, st, W.bounds, count);
-  hipLaunchKernelGGL(k_bounds, dim3(nblocks(np)), dim3(256), 0, st, S, x, np, W.box, W.bounds);
-  hipLaunchKernelGGL(k_grid, dim3(1), dim3(64), 0, st, W.bounds, S.h, W.max_cells, W.grid);
-  hipLaunchKernelGGL(k_zero_i, dim3(nblocks(nscan_max)), dim3(256), 0, st, W.cell_cnt, nscan_dev, 0LL);
+  hipLaunchKernelGGL(k_bounds, dim3(nblocks(np, 256, BOUNDS_BLOCKS)), dim3(256), 0, st, S, x, np, W.box, W.part,
+                     W.done, S.h, W.max_cells, W.grid, count);
+  // cell counts are zero on entry: the scatter below returns them to zero
   hipLaunchKernelGGL(k_count, dim3(nblocks(nstored)), dim3(256), 0, st, nstored, S.ne, W.box, W.grid, W.cell_cnt,
                      W.cell_of);
   scan_excl(W.cell_cnt, W.cell_start, nscan_dev, nscan_max, W.scan_tmp, st);
   hipLaunchKernelGGL(k_scatter, dim3(nblocks(nstored)), dim3(256), 0, st, nstored, W.box, W.cell_of, W.cell_cnt,
                      W.cell_start, W.sorted_id, W.sorted_box);
-  hipLaunchKernelGGL(k_pairs, dim3(nblocks(nquery)), dim3(256), 0, st, S, nquery, W.box, W.grid, W.cell_start,
-                     W.sorted_id, W.sorted_box, S.h, oi, oj, ot, cap, (unsigned long long*)count,
-                     status);
+  int nt = nquery * PQ_T;
+  int nb = (nt + 255) / 256;  // one thread per (query, cell subset): no grid-stride here
+  hipLaunchKernelGGL(k_pair_count, dim3(nb), dim3(256), 0, st, S, nquery, W.box, W.grid, W.cell_start, W.sorted_id,
+                     W.sorted_box, S.h, W.pair_cnt, W.pair_bsum);
+  scan_excl(W.pair_bsum, W.pair_boff, nullptr, nb + 1, W.scan_tmp, st);
+  hipLaunchKernelGGL(k_pair_emit, dim3(nb), dim3(256), 0, st, S, nquery, W.box, W.grid, W.cell_start, W.sorted_id,
+                     W.sorted_box, S.h, W.pair_cnt, W.pair_boff, oi, oj, ot, cap, count, status);
 }
 
 void run_narrow(const SceneDev& S, const double* x, const int* ci, const int* cj, const unsigned char* ct,
-                const long long* ccount, long long ccap, int* ai, int* aj, unsigned char* at, unsigned char* acode,
-                unsigned char* aflags, double* adist, long long acap, long long* act_count, long long* counters,
-                unsigned* status, hipStream_t st) {
-  hipLaunchKernelGGL(k_zero_ll, dim3(1), dim3(64), 0, st, act_count, 1, counters, 4);
-  hipLaunchKernelGGL(k_narrow, dim3(nblocks(ccap)), dim3(256), 0, st, S, x, ci, cj, ct, ccount, ccap, ai, aj, at,
-                     acode, aflags, adist, acap, (unsigned long long*)act_count, (unsigned long long*)counters,
-                     status);
+                const long long* ccount, long long ccap, const StageWs& W, int* ai, int* aj, unsigned char* at,
+                unsigned char* acode, unsigned char* aflags, double* adist, long long acap, long long* act_count,
+                long long* counters, unsigned* status, hipStream_t st) {
+  int G = (int)((ccap + NW_TILE - 1) / NW_TILE);
+  hipLaunchKernelGGL(k_narrow, dim3(G), dim3(256), 0, st, S, x, ci, cj, ct, ccount, ccap, W);
+  scan_excl(W.kcnt, W.kofs, nullptr, 3 * G + 1, W.scan_tmp, st);
+  hipLaunchKernelGGL(k_compact, dim3(G), dim3(256), 0, st, W, G, ai, aj, at, acode, aflags, adist, acap, act_count,
+                     counters, status);
 }
 
 void run_eval(const SceneDev& S, const double* x, const int* ai, const int* aj, const unsigned char* at,
               const unsigned char* acode, const unsigned char* aflags, const long long* act_count, long long acap,
               double* E, double* G, double* H, hipStream_t st) {
-  hipLaunchKernelGGL(k_eval, dim3(nblocks(acap, 128, 16384)), dim3(128), 0, st, S, x, ai, aj, at, acode, aflags,
+  hipLaunchKernelGGL(k_eval, dim3(nblocks(acap, 64, 65535)), dim3(64), 0, st, S, x, ai, aj, at, acode, aflags,
                      (const unsigned long long*)act_count, acap, E, G, H);
 }
 
 void run_assemble(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,
                   const unsigned char* aflags, const long long* act_count, long long acap, const double* E,
                   const double* G, const double* H, double* E_out, double* g, int* row_ptr, int* col, double* val,
-                  long long bsr_cap, long long* nnzb, const AsmWs& A, long long act_cap_ws, unsigned* status,
-                  hipStream_t st) {
+                  long long bsr_cap, long long* nnzb, const AsmWs& A, unsigned* status, hipStream_t st) {
   const unsigned long long* nact = (const unsigned long long*)act_count;
-  long long n16 = 16 * acap;
   hipLaunchKernelGGL(k_esum, dim3(256), dim3(256), 0, st, E, nact, acap, A.epart);
   hipLaunchKernelGGL(k_esum_final, dim3(1), dim3(256), 0, st, A.epart, 256, E_out);
-  hipLaunchKernelGGL(k_zero_d, dim3(nblocks(3LL * S.nv)), dim3(256), 0, st, g, (const long long*)nullptr,
-                     3LL * S.nv, 1LL, 3LL * S.nv);
-  hipLaunchKernelGGL(k_grad, dim3(nblocks(acap)), dim3(256), 0, st, S, ai, aj, at, aflags, nact, acap, G, g);
-  hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(A.hash_size)), dim3(256), 0, st, A.keys, A.hash_size, kEmpty);
-  hipLaunchKernelGGL(k_zero_i, dim3(nblocks(S.nv + 1)), dim3(256), 0, st, A.rowcnt, (const int*)nullptr,
-                     (long long)S.nv + 1);
-  hipLaunchKernelGGL(k_zero_i, dim3(nblocks(S.nv)), dim3(256), 0, st, A.rowfill, (const int*)nullptr,
-                     (long long)S.nv);
-  hipLaunchKernelGGL(k_asm_insert, dim3(nblocks(n16)), dim3(256), 0, st, S, ai, aj, at, aflags, nact, acap, A.keys,
-                     A.hash_size, A.entry_slot, A.rowcnt, status);
+  // incidence counts are zero on entry: k_inc_fill returns them to zero
+  hipLaunchKernelGGL(k_inc_count, dim3(nblocks(acap)), dim3(256), 0, st, S, ai, aj, at, aflags, nact, acap,
+                     A.inc_cnt);
+  scan_excl(A.inc_cnt, A.inc_off, nullptr, S.nv + 1, A.scan_tmp, st);
+  hipLaunchKernelGGL(k_inc_fill, dim3(nblocks(acap)), dim3(256), 0, st, S, ai, aj, at, aflags, nact, acap, A.inc_cnt,
+                     A.inc_off, A.inc);
+  int rows_grid = (int)std::min(S.nv, 1 << 20);
+  hipLaunchKernelGGL(k_row_a, dim3(rows_grid), dim3(64), 0, st, S, ai, aj, at, A.inc_off, A.inc, G, g, A.colbuf,
+                     A.rowcnt);
   scan_excl(A.rowcnt, row_ptr, nullptr, S.nv + 1, A.scan_tmp, st);
   hipLaunchKernelGGL(k_asm_nnzb, dim3(1), dim3(64), 0, st, row_ptr, S.nv, nnzb, bsr_cap, status);
-  hipLaunchKernelGGL(k_asm_fillseg, dim3(nblocks(A.hash_size)), dim3(256), 0, st, A.keys, A.hash_size, row_ptr,
-                     A.rowfill, A.tmpcol, 16 * act_cap_ws);
-  hipLaunchKernelGGL(k_asm_rank, dim3(nblocks(A.hash_size)), dim3(256), 0, st, A.keys, A.hash_size, row_ptr,
-                     A.tmpcol, A.slot_pos, col, bsr_cap);
-  hipLaunchKernelGGL(k_zero_d, dim3(nblocks(9 * bsr_cap)), dim3(256), 0, st, val, (const long long*)nnzb, 0LL, 9LL,
-                     bsr_cap);
-  hipLaunchKernelGGL(k_asm_vals, dim3(nblocks(n16)), dim3(256), 0, st, nact, acap, aflags, A.entry_slot, A.slot_pos,
-                     H, val);
+  hipLaunchKernelGGL(k_row_b, dim3(rows_grid), dim3(64), 0, st, S, ai, aj, at, A.inc_off, A.inc, A.colbuf, H, row_ptr,
+                     col, val, bsr_cap);
 }
 
 int run_components(const SceneDev& S, int* lab, int* flag, int* scan, int* comp, int* scan_tmp, int* d_changed,
