@@ -32,8 +32,8 @@ FP64_PEAK_TFLOPS = 78.6
 # the map back to 12 DOFs (0.4k / 0.7k).
 FLOPS_PER_KIND = {0: 150.0, 1: 2700.0, 2: 8000.0, 3: 8000.0}
 # Algorithmic bytes of one active pair in eval_barrier: pair ids, type, code,
-# flags (11 B), four FP64 vertices (96 B), and E, G[12], packed H[78] (728 B).
-EVAL_BYTES_PER_PAIR = 11 + 96 + 728
+# flags (11 B), four FP64 vertices (96 B), and E, G[12], H[12 x 12] (1256 B).
+EVAL_BYTES_PER_PAIR = 11 + 96 + 8 + 96 + 1152
 KIND_OF_CODE = np.array([0, 0, 0, 1, 1, 1, 2, 0, 0, 0, 0, 1, 1, 1, 1, 3])
 
 
@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--graph", type=int, default=1, help="replay the step as a captured HIP graph")
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -110,6 +112,16 @@ def main():
         else:
             cs.step(x)
 
+    if args.copy_mib > 0:
+        # a copy of known size: its FETCH_SIZE / WRITE_SIZE counters convert
+        # the counters of the path's kernels to bytes
+        src = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
@@ -160,7 +172,8 @@ def main():
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = None
-    roof["units"] = {"active_pairs": n_act, "bytes": bytes_, "fp64_flops": flops}
+    roof["units"] = {"active_pairs": n_act, "bytes": bytes_, "fp64_flops": flops,
+                     "pairs_by_kind": {k: int(np.sum(kinds == q)) for q, k in enumerate(["PP", "PE", "PT", "EE"])}}
 
     out = {
         "metric": "filtered contact pairs evaluated/s (dist+filter+grad+Hessian); p50/p99 latency",

@@ -114,11 +114,13 @@ typedef struct {
 
 /* Per-active-pair results, row k for active pair k.  The 12 DOFs are the
  * pair's four stencil vertices in the order (point, t0, t1, t2) or
- * (a0, a1, b0, b1), xyz each. */
+ * (a0, a1, b0, b1), xyz each.  H is stored in full (symmetric, row-major) so
+ * that the three rows of one stencil vertex are 36 contiguous doubles: the
+ * assembly reads each pair's Hessian once per stencil vertex, in one piece. */
 typedef struct {
   double* E_d;  /* [cap] kappa * b (+inf for infeasible pairs) */
   double* G_d;  /* [cap,12] gradient */
-  double* H_d;  /* [cap,78] projected Hessian, packed upper triangle, row-major (i <= j) */
+  double* H_d;  /* [cap,144] projected 12 x 12 Hessian, row-major */
   int64_t cap;
 } bf_local;
 

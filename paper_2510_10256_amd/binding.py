@@ -159,7 +159,7 @@ class ContactScene:
         self.a_dist = z(self.act_cap, t.float64)
         self.counters = z(4, t.int64)
         self.l_E, self.l_G, self.l_H = z(self.act_cap, t.float64), z((self.act_cap, 12), t.float64), \
-            z((self.act_cap, 78), t.float64)
+            z((self.act_cap, 144), t.float64)
         self.E = z(1, t.float64)
         self.g = z((self.nv, 3), t.float64)
         self.row_ptr = z(self.nv + 1, t.int32)
@@ -261,11 +261,7 @@ class ContactScene:
         na = min(int(self.a_n.item()), self.act_cap)
         nc = min(int(self.c_n.item()), self.cand_cap)
         nb = min(int(self.nnzb.item()), self.bsr_cap)
-        H = self.l_H[:na].cpu().numpy()
-        iu = np.triu_indices(12)
-        Hf = np.zeros((na, 12, 12))
-        Hf[:, iu[0], iu[1]] = H
-        Hf[:, iu[1], iu[0]] = H
+        Hf = self.l_H[:na].cpu().numpy().reshape(-1, 12, 12)
         return dict(
             cand=np.stack([self.c_t[:nc].cpu().numpy().astype(np.int32), self.c_i[:nc].cpu().numpy(),
                            self.c_j[:nc].cpu().numpy()], 1),

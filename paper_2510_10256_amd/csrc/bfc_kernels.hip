@@ -735,8 +735,8 @@ __global__ __launch_bounds__(256) void k_compact(StageWs W, int G, int* ai, int*
 // Barrier evaluation (Eq. 2, Eq. 3) and PSD projection
 // ---------------------------------------------------------------------------
 // One wave per work-group; every lane evaluates one pair into its row of an
-// LDS tile (E, G[12], H[78]), and the wave then writes the tile's contiguous
-// rows of E, G and H with coalesced stores.
+// LDS tile (E, G[12], upper triangle of H), and the wave then writes the
+// tile's contiguous rows of E, G and the full 12 x 12 H with coalesced stores.
 __global__ __launch_bounds__(64) void k_eval(SceneDev S, const double* x, const int* ai, const int* aj,
                                              const unsigned char* at, const unsigned char* acode,
                                              const unsigned char* aflags, const unsigned long long* act_count,
@@ -767,7 +767,11 @@ __global__ __launch_bounds__(64) void k_eval(SceneDev S, const double* x, const 
     int rows = (int)min((long long)64, n - k0);
     if (lane < rows) E[k0 + lane] = tE[lane];
     for (int q = lane; q < rows * 12; q += 64) G[12 * k0 + q] = tG[q];
-    for (int q = lane; q < rows * 78; q += 64) H[78 * k0 + q] = tH[q];
+    for (int q = lane; q < rows * 144; q += 64) {  // full 12 x 12 rows from the packed tile
+      const int r = q / 144, e = q - 144 * r, i = e / 12, j = e - 12 * i;
+      const int lo = min(i, j), hi = max(i, j);
+      H[144 * k0 + q] = tH[78 * r + lo * 12 - (lo * (lo - 1)) / 2 + (hi - lo)];
+    }
     __syncthreads();
   }
 }
@@ -834,11 +838,30 @@ __global__ __launch_bounds__(256) void k_inc_fill(SceneDev S, const int* ai, con
   }
 }
 
-// Bitonic sort of a[0..P) (P a power of two) by the one wave of the block.
-__device__ __forceinline__ void wave_bitonic(int* a, int P) {
+// ---- per-row assembly ------------------------------------------------------
+// A row with m incidence entries takes one of three paths: m <= ROW_L in the
+// registers of one wave, m <= ROW_M in one wave's LDS, m <= ROW_H by a
+// 256-thread block in LDS; beyond ROW_H one lane works in global memory
+// (correct, slow).  Cloth rows reach a few hundred entries, rod rows a few.
+constexpr int ROW_L = 32;
+constexpr int ROW_M = 256;
+constexpr int ROW_M_TAB = 4 * ROW_M;  // hash slots: at least the row's 4m candidate columns
+constexpr int ROW_H = 2048;
+constexpr int ROW_H_TAB = 4 * ROW_H;
+constexpr int EMPTY = -1;
+constexpr int PAD = 0x7fffffff;
+
+__device__ __forceinline__ int pow2_at_least(int n) {
+  int p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+// Bitonic sort of a[0..P) (P a power of two) by the NT threads of the block.
+template <int NT> __device__ __forceinline__ void team_bitonic(int* a, int P) {
   for (int k = 2; k <= P; k <<= 1)
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < P; i += 64) {
+      for (int i = threadIdx.x; i < P; i += NT) {
         int l = i ^ j;
         if (l > i) {
           int x = a[i], y = a[l];
@@ -849,16 +872,60 @@ __device__ __forceinline__ void wave_bitonic(int* a, int P) {
       __syncthreads();
     }
 }
-__device__ __forceinline__ int pow2_at_least(int n) {
-  int p = 1;
-  while (p < n) p <<= 1;
-  return p;
+
+// Bitonic sorts across the lanes of a wave: 64 values (one per lane) and
+// 128 values (element i in lane i & 63, register i >> 6).
+__device__ __forceinline__ int wave_sort64(int x) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int k = 2; k <= 64; k <<= 1)
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      int y = __shfl_xor(x, j, 64);
+      bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
+      x = keep_min ? min(x, y) : max(x, y);
+    }
+  return x;
+}
+__device__ __forceinline__ void wave_sort128(int& a0, int& a1) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int k = 2; k <= 128; k <<= 1)
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j == 64) {
+        int lo = min(a0, a1), hi = max(a0, a1);
+        a0 = lo; a1 = hi;
+        continue;
+      }
+      int b0 = __shfl_xor(a0, j, 64), b1 = __shfl_xor(a1, j, 64);
+      bool lower = (lane & j) == 0;
+      bool min0 = lower == ((lane & k) == 0), min1 = lower == (((lane + 64) & k) == 0);
+      a0 = min0 ? min(a0, b0) : max(a0, b0);
+      a1 = min1 ? min(a1, b1) : max(a1, b1);
+    }
 }
 
-// Rows with more candidate columns than this fall back to one lane and
-// global memory (correct, slower; a vertex in more than 128 active pairs).
-// The small tile keeps many waves resident: the row kernels are latency bound.
-constexpr int ROW_LDS = 512;
+// Sum across the wave in a fixed order (lane i adds lane i + o); lane 0 has the total.
+__device__ __forceinline__ void wave_ordered_sum3(double& x, double& y, double& z) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    double tx = __shfl_down(x, o, 64), ty = __shfl_down(y, o, 64), tz = __shfl_down(z, o, 64);
+    if ((lane & (2 * o - 1)) == 0) { x += tx; y += ty; z += tz; }
+  }
+}
+
+// Insert key into an LDS open-addressing set of T slots (T a power of two
+// larger than or equal to the number of distinct keys ever inserted).
+__device__ __forceinline__ void set_insert(int* tab, int T, int key) {
+  unsigned h = ((unsigned)key * 0x9E3779B1u) & (unsigned)(T - 1);
+  while (true) {
+    int old = atomicCAS(&tab[h], EMPTY, key);
+    if (old == EMPTY || old == key) return;
+    h = (h + 1) & (unsigned)(T - 1);
+  }
+}
 
 __device__ void isort_global(int* a, int m) {
   for (int i = 1; i < m; ++i) {
@@ -868,79 +935,194 @@ __device__ void isort_global(int* a, int m) {
   }
 }
 
-// Pass A, one wave per vertex v: sort its incidence entries (deterministic
-// sums), sum its gradient in that order, and store its distinct columns
-// (the stencil vertices of its pairs) sorted at colbuf[4 * inc_off[v] ...];
-// rowcnt[v] = their number.
+// One lane, global memory: sort the entries, sum the gradient, store the
+// distinct sorted columns.
+__device__ void row_a_serial(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at, int v, int b,
+                             int m, int* inc, const double* G, double* g, int* cb, int* rowcnt) {
+  isort_global(inc + b, m);
+  double gx = 0.0, gy = 0.0, gz = 0.0;
+  for (int q = 0; q < m; ++q) {
+    int e = inc[b + q], k = e >> 2, s = e & 3;
+    gx += G[12LL * k + 3 * s]; gy += G[12LL * k + 3 * s + 1]; gz += G[12LL * k + 3 * s + 2];
+    int vv[4];
+    pair_verts(S, at[k], ai[k], aj[k], vv);
+    for (int c = 0; c < 4; ++c) cb[4 * q + c] = vv[c];
+  }
+  g[3 * v] = gx; g[3 * v + 1] = gy; g[3 * v + 2] = gz;
+  isort_global(cb, 4 * m);
+  int u = 0;
+  for (int q = 0; q < 4 * m; ++q)
+    if (q == 0 || cb[q] != cb[q - 1]) cb[u++] = cb[q];
+  rowcnt[v] = u;
+}
+
+// Pass A, rows with m <= ROW_M, one wave per row: sort the row's incidence
+// entries (so every sum below runs in a fixed order), sum its gradient,
+// and store its distinct columns (the stencil vertices of its pairs) sorted
+// at colbuf[4 * inc_off[v] ...]; rowcnt[v] = their number.
 __global__ __launch_bounds__(64) void k_row_a(SceneDev S, const int* ai, const int* aj, const unsigned char* at,
                                               const int* inc_off, int* inc, const double* G, double* g, int* colbuf,
                                               int* rowcnt) {
-  __shared__ int buf[ROW_LDS];
-  __shared__ int ent[ROW_LDS / 4];
+  __shared__ int ent[ROW_M];
+  __shared__ int tab[ROW_M_TAB];
   const int lane = threadIdx.x;
   for (int v = blockIdx.x; v < S.nv; v += gridDim.x) {
     const int b = inc_off[v], m = inc_off[v + 1] - b;
+    if (m > ROW_M) continue;  // block path
     int* cb = colbuf + 4LL * b;
-    if (4 * m > ROW_LDS) {  // rare: serial fallback in global memory
-      if (lane == 0) {
-        isort_global(inc + b, m);
-        double gx = 0.0, gy = 0.0, gz = 0.0;
-        for (int q = 0; q < m; ++q) {
-          int e = inc[b + q], k = e >> 2, s = e & 3;
-          gx += G[12LL * k + 3 * s]; gy += G[12LL * k + 3 * s + 1]; gz += G[12LL * k + 3 * s + 2];
-          int vv[4];
-          pair_verts(S, at[k], ai[k], aj[k], vv);
-          for (int c = 0; c < 4; ++c) cb[4 * q + c] = vv[c];
-        }
-        g[3 * v] = gx; g[3 * v + 1] = gy; g[3 * v + 2] = gz;
-        isort_global(cb, 4 * m);
-        int u = 0;
-        for (int q = 0; q < 4 * m; ++q)
-          if (q == 0 || cb[q] != cb[q - 1]) cb[u++] = cb[q];
-        rowcnt[v] = u;
+    if (m <= ROW_L) {
+      // registers: entry q in lane q, candidate column 4q + t in lane
+      // (4q + t) & 63, register (4q + t) >> 6
+      int e = lane < m ? inc[b + lane] : PAD;
+      e = wave_sort64(e);
+      double gx = 0.0, gy = 0.0, gz = 0.0;
+      int vv[4] = {PAD, PAD, PAD, PAD};
+      if (lane < m) {
+        inc[b + lane] = e;
+        const int k = e >> 2, s = e & 3;
+        gx = G[12LL * k + 3 * s]; gy = G[12LL * k + 3 * s + 1]; gz = G[12LL * k + 3 * s + 2];
+        pair_verts(S, at[k], ai[k], aj[k], vv);
       }
-      __syncthreads();
+      wave_ordered_sum3(gx, gy, gz);
+      if (lane == 0) { g[3 * v] = gx; g[3 * v + 1] = gy; g[3 * v + 2] = gz; }
+      const int t = lane & 3, q0 = lane >> 2, q1 = 16 + (lane >> 2);
+      int w0 = __shfl(vv[0], q0, 64), w1 = __shfl(vv[1], q0, 64), w2 = __shfl(vv[2], q0, 64),
+          w3 = __shfl(vv[3], q0, 64);
+      int c0 = t == 0 ? w0 : t == 1 ? w1 : t == 2 ? w2 : w3;
+      w0 = __shfl(vv[0], q1, 64); w1 = __shfl(vv[1], q1, 64); w2 = __shfl(vv[2], q1, 64); w3 = __shfl(vv[3], q1, 64);
+      int c1 = t == 0 ? w0 : t == 1 ? w1 : t == 2 ? w2 : w3;
+      wave_sort128(c0, c1);
+      const int p0 = __shfl_up(c0, 1, 64), last0 = __shfl(c0, 63, 64);
+      int p1 = __shfl_up(c1, 1, 64);
+      if (lane == 0) p1 = last0;
+      const bool f0 = c0 != PAD && (lane == 0 || c0 != p0);
+      const bool f1 = c1 != PAD && c1 != p1;
+      const unsigned long long m0 = __ballot(f0), m1 = __ballot(f1);
+      const int u0 = __popcll(m0);
+      if (f0) cb[lanes_below(m0)] = c0;
+      if (f1) cb[u0 + lanes_below(m1)] = c1;
+      if (lane == 0) rowcnt[v] = u0 + __popcll(m1);
       continue;
     }
-    const int Pm = pow2_at_least(m > 0 ? m : 1);
-    for (int q = lane; q < Pm; q += 64) ent[q] = q < m ? inc[b + q] : 0x7fffffff;
+    // LDS, one wave
+    const int Pm = pow2_at_least(m);
+    for (int q = lane; q < Pm; q += 64) ent[q] = q < m ? inc[b + q] : PAD;
+    const int T = min(ROW_M_TAB, pow2_at_least(8 * m));
+    for (int q = lane; q < T; q += 64) tab[q] = EMPTY;
     __syncthreads();
-    wave_bitonic(ent, Pm);
-    // gradient in entry order: each lane sums a contiguous run, then the runs
-    // are combined in lane order
-    const int per = (m + 63) / 64;
+    team_bitonic<64>(ent, Pm);
+    const int per = (m + 63) / 64;  // gradient: contiguous runs, combined in lane order
     double gx = 0.0, gy = 0.0, gz = 0.0;
     for (int q = lane * per; q < m && q < (lane + 1) * per; ++q) {
       int e = ent[q], k = e >> 2, s = e & 3;
       gx += G[12LL * k + 3 * s]; gy += G[12LL * k + 3 * s + 1]; gz += G[12LL * k + 3 * s + 2];
     }
-    for (int o = 1; o < 64; o <<= 1) {  // ordered tree: lane i adds lane i+o
-      double tx = __shfl_down(gx, o, 64), ty = __shfl_down(gy, o, 64), tz = __shfl_down(gz, o, 64);
-      if ((lane & (2 * o - 1)) == 0) { gx += tx; gy += ty; gz += tz; }
-    }
+    wave_ordered_sum3(gx, gy, gz);
     if (lane == 0) { g[3 * v] = gx; g[3 * v + 1] = gy; g[3 * v + 2] = gz; }
-    for (int q = lane; q < m; q += 64) inc[b + q] = ent[q];
-    const int n = 4 * m, P = pow2_at_least(n > 0 ? n : 1);
     for (int q = lane; q < m; q += 64) {
-      int k = ent[q] >> 2;
+      int e = ent[q], k = e >> 2;
+      inc[b + q] = e;
       int vv[4];
       pair_verts(S, at[k], ai[k], aj[k], vv);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) buf[4 * q + c] = vv[c];
+      for (int c = 0; c < 4; ++c) set_insert(tab, T, vv[c]);
     }
-    for (int q = n + lane; q < P; q += 64) buf[q] = 0x7fffffff;
     __syncthreads();
-    wave_bitonic(buf, P);
-    int u = 0;
-    for (int base = 0; base < n; base += 64) {
-      int i = base + lane;
-      bool first = i < n && (i == 0 || buf[i] != buf[i - 1]);
-      unsigned long long msk = __ballot(first);
-      if (first) cb[u + lanes_below(msk)] = buf[i];
+    int u = 0;  // compact the set in place (a chunk is read before any of it is written)
+    for (int c = 0; c < T; c += 64) {
+      int x = tab[c + lane];
+      bool ok = x != EMPTY;
+      unsigned long long msk = __ballot(ok);
+      if (ok) tab[u + lanes_below(msk)] = x;
       u += __popcll(msk);
     }
+    const int P = pow2_at_least(u > 0 ? u : 1);
+    for (int q = u + lane; q < P; q += 64) tab[q] = PAD;
+    __syncthreads();
+    team_bitonic<64>(tab, P);
+    for (int q = lane; q < u; q += 64) cb[q] = tab[q];
     if (lane == 0) rowcnt[v] = u;
     __syncthreads();
+  }
+}
+
+// Rows with m > ROW_M (passes A and B): one 256-thread block per row.
+// Block j of G looks at rows j, j + G, j + 2G, ... (rows with many entries
+// cluster in space, and so in vertex numbering) and works on the large ones
+// one after another.
+__device__ __forceinline__ int big_rows(const int* inc_off, int nv, int* list, int base) {
+  const int v = blockIdx.x + (long long)gridDim.x * (base + threadIdx.x) < nv
+                    ? (int)(blockIdx.x + (long long)gridDim.x * (base + threadIdx.x)) : -1;
+  const int m = v >= 0 ? inc_off[v + 1] - inc_off[v] : 0;
+  int nbig;
+  const int off = block_excl_scan256(m > ROW_M ? 1 : 0, &nbig);
+  if (m > ROW_M) list[off] = v;
+  __syncthreads();
+  return nbig;
+}
+
+__global__ __launch_bounds__(256) void k_row_a_big(SceneDev S, const int* ai, const int* aj, const unsigned char* at,
+                                                   const int* inc_off, int* inc, const double* G, double* g,
+                                                   int* colbuf, int* rowcnt) {
+  __shared__ int ent[ROW_H];
+  __shared__ int tab[ROW_H_TAB];
+  __shared__ int list[256];
+  __shared__ double gs[4][3];
+  const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
+  const int per = (S.nv - (int)blockIdx.x + (int)gridDim.x - 1) / (int)gridDim.x;
+  for (int base = 0; base < per; base += 256) {
+    const int nbig = big_rows(inc_off, S.nv, list, base);
+    for (int r = 0; r < nbig; ++r) {
+      const int v = list[r];
+      const int b = inc_off[v], m = inc_off[v + 1] - b;
+      int* cb = colbuf + 4LL * b;
+      if (m > ROW_H) {
+        if (tid == 0) row_a_serial(S, ai, aj, at, v, b, m, inc, G, g, cb, rowcnt);
+        __syncthreads();
+        continue;
+      }
+      const int Pm = pow2_at_least(m);
+      for (int q = tid; q < Pm; q += 256) ent[q] = q < m ? inc[b + q] : PAD;
+      const int T = min(ROW_H_TAB, pow2_at_least(8 * m));
+      for (int q = tid; q < T; q += 256) tab[q] = EMPTY;
+      __syncthreads();
+      team_bitonic<256>(ent, Pm);
+      const int run = (m + 255) / 256;
+      double gx = 0.0, gy = 0.0, gz = 0.0;
+      for (int q = tid * run; q < m && q < (tid + 1) * run; ++q) {
+        int e = ent[q], k = e >> 2, s = e & 3;
+        gx += G[12LL * k + 3 * s]; gy += G[12LL * k + 3 * s + 1]; gz += G[12LL * k + 3 * s + 2];
+      }
+      wave_ordered_sum3(gx, gy, gz);
+      if (lane == 0) { gs[w][0] = gx; gs[w][1] = gy; gs[w][2] = gz; }
+      for (int q = tid; q < m; q += 256) {
+        int e = ent[q], k = e >> 2;
+        inc[b + q] = e;
+        int vv[4];
+        pair_verts(S, at[k], ai[k], aj[k], vv);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) set_insert(tab, T, vv[c]);
+      }
+      __syncthreads();
+      if (tid == 0)
+        for (int a = 0; a < 3; ++a) g[3 * v + a] = ((gs[0][a] + gs[1][a]) + gs[2][a]) + gs[3][a];
+      int u = 0;
+      for (int c = 0; c < T; c += 256) {
+        int x = tab[c + tid];
+        int tot;
+        int o = block_excl_scan256(x != EMPTY ? 1 : 0, &tot);  // synchronises: the chunk is read
+        if (x != EMPTY) tab[u + o] = x;
+        u += tot;
+        __syncthreads();
+      }
+      const int P = pow2_at_least(u > 0 ? u : 1);
+      for (int q = u + tid; q < P; q += 256) tab[q] = PAD;
+      __syncthreads();
+      team_bitonic<256>(tab, P);
+      for (int q = tid; q < u; q += 256) cb[q] = tab[q];
+      if (tid == 0) rowcnt[v] = u;
+      __syncthreads();
+    }
   }
 }
 
@@ -952,57 +1134,107 @@ __global__ void k_asm_nnzb(const int* row_ptr, int nv, long long* nnzb, long lon
   }
 }
 
-// Pass B, one wave per vertex v: the row's entries and their stencil
-// vertices are staged in LDS; every lane owns some of the row's columns,
-// writes them and sums their 3x3 blocks over the entries in sorted order.
+// Slot (0..3) of vertex c in a pair's stencil, -1 if absent.
+__device__ __forceinline__ int slot_of(const int* vv, int c) {
+  return vv[0] == c ? 0 : vv[1] == c ? 1 : vv[2] == c ? 2 : vv[3] == c ? 3 : -1;
+}
+
+// Pass B of one row by the NT threads of the block.  Every thread owns up to
+// two of the row's columns per pass (2 NT columns a pass).  The row's entries
+// are taken CH = NT / 2 at a time: two threads per entry load the entry's
+// band (rows 3s..3s+2 of its pair's 12 x 12 Hessian: 36 contiguous doubles)
+// into LDS beside the pair's stencil vertices; each owner then adds the 3x3
+// blocks of its columns from LDS, entries in sorted order.
+template <int NT>
+__device__ __forceinline__ void row_b(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,
+                                      const int* inc, int b, int m, const int* cb, int r0, int u, const double* H,
+                                      int* col, double* val, int* vs, double* band) {
+  constexpr int CH = NT / 2;
+  const int tid = threadIdx.x;
+  for (int cbase = 0; cbase < u; cbase += 2 * NT) {
+    const int ca = cbase + tid < u ? cb[cbase + tid] : EMPTY;
+    const int cz = cbase + NT + tid < u ? cb[cbase + NT + tid] : EMPTY;
+    double A[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, Z[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int qc = 0; qc < m; qc += CH) {
+      const int nq = min(CH, m - qc);
+      const int q = tid >> 1, half = tid & 1;
+      if (q < nq) {
+        const int e = inc[b + qc + q], k = e >> 2;
+        const double* src = H + 144LL * k + 36 * (e & 3) + 18 * half;
+        double* dst = band + 36 * q + 18 * half;
+#pragma unroll
+        for (int o = 0; o < 18; ++o) dst[o] = src[o];
+        if (half == 0) {
+          int vv[4];
+          pair_verts(S, at[k], ai[k], aj[k], vv);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) vs[4 * q + c] = vv[c];
+        }
+      }
+      __syncthreads();
+      for (int r = 0; r < nq; ++r) {
+        const int w[4] = {vs[4 * r], vs[4 * r + 1], vs[4 * r + 2], vs[4 * r + 3]};
+        const double* bq = band + 36 * r;
+        const int sa = slot_of(w, ca), sz = slot_of(w, cz);
+        if (sa >= 0) {
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) A[3 * i + j] += bq[12 * i + 3 * sa + j];
+        }
+        if (sz >= 0) {
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) Z[3 * i + j] += bq[12 * i + 3 * sz + j];
+        }
+      }
+      __syncthreads();
+    }
+    if (ca != EMPTY) {
+      col[r0 + cbase + tid] = ca;
+#pragma unroll
+      for (int o = 0; o < 9; ++o) val[9LL * (r0 + cbase + tid) + o] = A[o];
+    }
+    if (cz != EMPTY) {
+      col[r0 + cbase + NT + tid] = cz;
+#pragma unroll
+      for (int o = 0; o < 9; ++o) val[9LL * (r0 + cbase + NT + tid) + o] = Z[o];
+    }
+  }
+}
+
+// Pass B, rows with m <= ROW_M, one wave per row.
 __global__ __launch_bounds__(64) void k_row_b(SceneDev S, const int* ai, const int* aj, const unsigned char* at,
                                               const int* inc_off, const int* inc, const int* colbuf, const double* H,
                                               const int* row_ptr, int* col, double* val, long long cap) {
-  __shared__ int es[ROW_LDS / 4];
-  __shared__ int vs[ROW_LDS];
-  const int lane = threadIdx.x;
+  __shared__ int vs[4 * 32];
+  __shared__ double band[32 * 36];
   for (int v = blockIdx.x; v < S.nv; v += gridDim.x) {
     const int b = inc_off[v], m = inc_off[v + 1] - b;
+    if (m > ROW_M) continue;  // block path
     const int r0 = row_ptr[v], r1 = row_ptr[v + 1];
-    if (r1 > cap) continue;  // overflow: reported by k_asm_nnzb (uniform across the wave)
-    const bool staged = 4 * m <= ROW_LDS;
-    if (staged) {
-      for (int q = lane; q < m; q += 64) {
-        int e = inc[b + q], k = e >> 2;
-        es[q] = e;
-        int vv[4];
-        pair_verts(S, at[k], ai[k], aj[k], vv);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) vs[4 * q + c] = vv[c];
-      }
-    }
-    __syncthreads();
-    const int* cb = colbuf + 4LL * b;
-    for (int t = lane; t < r1 - r0; t += 64) {
-      const int c = cb[t];
-      col[r0 + t] = c;
-      double blk[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-      for (int q = 0; q < m; ++q) {
-        int e, vv[4];
-        if (staged) {
-          e = es[q];
-#pragma unroll
-          for (int cc = 0; cc < 4; ++cc) vv[cc] = vs[4 * q + cc];
-        } else {
-          e = inc[b + q];
-          pair_verts(S, at[e >> 2], ai[e >> 2], aj[e >> 2], vv);
-        }
-        int sc = vv[0] == c ? 0 : vv[1] == c ? 1 : vv[2] == c ? 2 : vv[3] == c ? 3 : -1;
-        if (sc < 0) continue;
-        const int k = e >> 2, sr = e & 3;
-        const double* Hk = H + 78LL * k;
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-          for (int j = 0; j < 3; ++j) blk[3 * i + j] += Hk[hix(3 * sr + i, 3 * sc + j)];
-      }
-#pragma unroll
-      for (int q = 0; q < 9; ++q) val[9LL * (r0 + t) + q] = blk[q];
+    if (r1 > cap) continue;   // overflow: reported by k_asm_nnzb
+    row_b<64>(S, ai, aj, at, inc, b, m, colbuf + 4LL * b, r0, r1 - r0, H, col, val, vs, band);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_row_b_big(SceneDev S, const int* ai, const int* aj, const unsigned char* at,
+                                                   const int* inc_off, const int* inc, const int* colbuf,
+                                                   const double* H, const int* row_ptr, int* col, double* val,
+                                                   long long cap) {
+  __shared__ int vs[4 * 128];
+  __shared__ double band[128 * 36];
+  __shared__ int list[256];
+  const int per = (S.nv - (int)blockIdx.x + (int)gridDim.x - 1) / (int)gridDim.x;
+  for (int base = 0; base < per; base += 256) {
+    const int nbig = big_rows(inc_off, S.nv, list, base);
+    for (int r = 0; r < nbig; ++r) {
+      const int v = list[r];
+      const int b = inc_off[v], m = inc_off[v + 1] - b;
+      const int r0 = row_ptr[v], r1 = row_ptr[v + 1];
+      if (r1 > cap) continue;  // uniform across the block
+      row_b<256>(S, ai, aj, at, inc, b, m, colbuf + 4LL * b, r0, r1 - r0, H, col, val, vs, band);
     }
     __syncthreads();
   }
@@ -1059,22 +1291,44 @@ __global__ __launch_bounds__(256) void k_refmin(SceneDev S, const int* ci, const
                                                 const long long* count, long long cap, unsigned long long* best) {
   long long n = *count;
   if (n > cap) n = cap;
-  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += grid_stride()) {
-    int v[4];
-    pair_verts(S, ct[k], ci[k], cj[k], v);
-    if (S.comp[v[0]] != S.comp[v[2]]) continue;
-    double val;
-    if (S.kind == 0) {
-      double sa0 = S.ref[v[0]], sa1 = S.ref[v[1]], sb0 = S.ref[v[2]], sb1 = S.ref[v[3]];
-      double gap = fmax(fmin(sb0, sb1) - fmax(sa0, sa1), fmin(sa0, sa1) - fmax(sb0, sb1));
-      if (!(gap > 0.0 && gap < S.h)) continue;
-      val = gap;
-    } else {
-      dd q = ref_sqdist_q(S, ct[k], v);
-      if (!(dd_lt(dd_of(0.0), q) && dd_lt(q, dd_sq(S.h)))) continue;
-      val = q.hi + q.lo;  // round to nearest double
+  const long long n_up = (n + 63) / 64 * 64;  // whole waves iterate together
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n_up; k += grid_stride()) {
+    int c = -1;
+    unsigned long long key = ~0ull;
+    if (k < n) {
+      int v[4];
+      pair_verts(S, ct[k], ci[k], cj[k], v);
+      if (S.comp[v[0]] == S.comp[v[2]]) {
+        double val = -1.0;
+        if (S.kind == 0) {
+          double sa0 = S.ref[v[0]], sa1 = S.ref[v[1]], sb0 = S.ref[v[2]], sb1 = S.ref[v[3]];
+          double gap = fmax(fmin(sb0, sb1) - fmax(sa0, sa1), fmin(sa0, sa1) - fmax(sb0, sb1));
+          if (gap > 0.0 && gap < S.h) val = gap;
+        } else {
+          dd q = ref_sqdist_q(S, ct[k], v);
+          if (dd_lt(dd_of(0.0), q) && dd_lt(q, dd_sq(S.h))) val = q.hi + q.lo;  // round to nearest double
+        }
+        if (val >= 0.0) {
+          c = S.comp[v[0]];
+          key = (unsigned long long)__double_as_longlong(val);
+        }
+      }
     }
-    atomicMin(&best[S.comp[v[0]]], (unsigned long long)__double_as_longlong(val));
+    // one atomic per wave when every contributing lane has the same component
+    const int first = __ffsll((long long)__ballot(c >= 0)) - 1;
+    const int c0 = __shfl(c, first < 0 ? 0 : first, 64);
+    const bool uniform = __ballot(c >= 0 && c != c0) == 0ull;
+    if (uniform) {
+      unsigned long long mk = key;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long y = __shfl_xor(mk, o, 64);
+        mk = y < mk ? y : mk;
+      }
+      if (lane_id() == 0 && c0 >= 0) atomicMin(&best[c0], mk);
+    } else if (c >= 0) {
+      atomicMin(&best[c], key);
+    }
   }
 }
 
@@ -1165,12 +1419,17 @@ void run_assemble(const SceneDev& S, const int* ai, const int* aj, const unsigne
   hipLaunchKernelGGL(k_inc_fill, dim3(nblocks(acap)), dim3(256), 0, st, S, ai, aj, at, aflags, nact, acap, A.inc_cnt,
                      A.inc_off, A.inc);
   int rows_grid = (int)std::min(S.nv, 1 << 20);
+  int big_grid = (int)std::max(1, std::min((S.nv + 15) / 16, 4096));  // ~16 rows per block
   hipLaunchKernelGGL(k_row_a, dim3(rows_grid), dim3(64), 0, st, S, ai, aj, at, A.inc_off, A.inc, G, g, A.colbuf,
+                     A.rowcnt);
+  hipLaunchKernelGGL(k_row_a_big, dim3(big_grid), dim3(256), 0, st, S, ai, aj, at, A.inc_off, A.inc, G, g, A.colbuf,
                      A.rowcnt);
   scan_excl(A.rowcnt, row_ptr, nullptr, S.nv + 1, A.scan_tmp, st);
   hipLaunchKernelGGL(k_asm_nnzb, dim3(1), dim3(64), 0, st, row_ptr, S.nv, nnzb, bsr_cap, status);
   hipLaunchKernelGGL(k_row_b, dim3(rows_grid), dim3(64), 0, st, S, ai, aj, at, A.inc_off, A.inc, A.colbuf, H, row_ptr,
                      col, val, bsr_cap);
+  hipLaunchKernelGGL(k_row_b_big, dim3(big_grid), dim3(256), 0, st, S, ai, aj, at, A.inc_off, A.inc, A.colbuf, H,
+                     row_ptr, col, val, bsr_cap);
 }
 
 int run_components(const SceneDev& S, int* lab, int* flag, int* scan, int* comp, int* scan_tmp, int* d_changed,
