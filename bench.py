@@ -42,8 +42,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="woven_patch", choices=["woven_patch", "folded_cloth", "helix_loop_rod"])
-    ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--workload", default="woven_patch",
+                    choices=["woven_patch", "folded_cloth", "helix_loop_rod", "batch64"])
+    ap.add_argument("--prec", default=None, choices=["fp64", "mixed"],
+                    help="default: fp64 for one scene, mixed for the batch")
+    ap.add_argument("--lanes", type=int, default=0, help="batch: concurrent streams in the graph (0 = tune)")
+    ap.add_argument("--tune", type=int, default=1, help="batch: tune threads per broad-phase query per scene")
     ap.add_argument("--graph", type=int, default=1, help="replay the step as a captured HIP graph")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -69,15 +73,140 @@ def cpu_baseline(sc, n_c_gpu):
                       f"(swept enumeration, FP64, derivatives and projection of every active pair)"}
 
 
+def eval_roofline(ms, n_act, kinds, label):
+    """Roofline of the per-pair evaluation kernel from its measured time."""
+    flops = float(sum(FLOPS_PER_KIND[int(k)] * int(np.sum(kinds == k)) for k in range(4)))
+    bytes_ = float(EVAL_BYTES_PER_PAIR * n_act)
+    t_hbm = bytes_ / (HBM_PEAK_GBS * 1e9)
+    t_fp = flops / (FP64_PEAK_TFLOPS * 1e12)
+    if t_hbm >= t_fp:
+        roof = {"kernel": label, "bound": "hbm", "achieved": bytes_ / (ms * 1e-3) / 1e9,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    else:
+        roof = {"kernel": label, "bound": "alu", "achieved": flops / (ms * 1e-3) / 1e12,
+                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["units"] = {"active_pairs": int(n_act), "bytes": bytes_, "fp64_flops": flops,
+                     "pairs_by_kind": {k: int(np.sum(kinds == q)) for q, k in enumerate(["PP", "PE", "PT", "EE"])}}
+    return roof
+
+
+def bench_batch(args):
+    """64 independent yarn / cloth patches (1k-64k primitives, log-uniform),
+    stepped together by one graph launch."""
+    import torch
+    import synth
+    import paper_2510_10256_amd as bfc
+
+    prec_name = args.prec or "mixed"
+    prec = bfc.BF_FP64 if prec_name == "fp64" else bfc.BF_MIXED
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    scenes = synth.batch_scenes()
+    css, xs = [], []
+    for sc in scenes:
+        cs = bfc.ContactScene(sc, prec=prec, device=dev)
+        x = torch.tensor(sc.x, dtype=torch.float64, device=dev)
+        cs.run(x)
+        if args.tune:
+            cs.tune(x)
+        css.append(cs)
+        xs.append(x)
+    counts = [cs.counts() for cs in css]
+    n_c = sum(c["n_c"] for c in counts)
+    n_act = sum(c["n_act"] for c in counts)
+    stream = torch.cuda.current_stream(dev)
+    # per-scene evaluation kernel times (eager, one scene at a time) for the roofline
+    eval_ms, kinds = 0.0, []
+    for cs, x, c in zip(css, xs, counts):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ts = []
+        for _ in range(5):
+            e0.record(stream)
+            cs.eval_barrier(x)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        eval_ms += float(np.median(ts))
+        kinds.append(KIND_OF_CODE[cs.a_code[:c["n_act"]].cpu().numpy()])
+    kinds = np.concatenate(kinds)
+
+    def timed(batch, steps, warmup):
+        for _ in range(warmup):
+            batch.step()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        t_start = time.perf_counter()
+        ev[0].record(stream)
+        for k in range(steps):
+            batch.step()
+            ev[k + 1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        return wall * 1e3 / steps, np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
+
+    seq = bfc.Batch(css, xs, lanes=1)
+    seq_ms, _ = timed(seq, max(5, args.steps // 4), 2)
+    seq.close()
+    batch = bfc.Batch(css, xs, lanes=args.lanes)
+    setup_s = time.perf_counter() - t0
+    ms_per_step, step_ms = timed(batch, args.steps, args.warmup)
+    for cs, c in zip(css, counts):
+        st = cs.status(clear=True)
+        assert not (st & (bfc.BF_S_CAND_OVERFLOW | bfc.BF_S_ACT_OVERFLOW | bfc.BF_S_BSR_OVERFLOW)), st
+        assert cs.counts() == c
+    out = {
+        "metric": "filtered contact pairs evaluated/s (dist+filter+grad+Hessian); p50/p99 latency",
+        "value": n_c / (ms_per_step * 1e-3),
+        "unit": "pairs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "p50_ms": float(np.percentile(step_ms, 50)), "p99_ms": float(np.percentile(step_ms, 99)),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded generator)",
+        "config": {"workload": "batch64: 64 yarn / cloth patches, 1k-64k primitives each (log-uniform), "
+                               "one graph launch per step",
+                   "scenes": len(css), "primitives": int(sum(sc.n_prims for sc in scenes)),
+                   "N_c": n_c, "N_act": n_act, "lanes": batch.lanes,
+                   "pq_choices": {str(q): int(sum(cs.pq == q for cs in css)) for q in (2, 4, 8)},
+                   "precision": prec_name},
+        "active_pairs_per_s": n_act / (ms_per_step * 1e-3),
+        "one_lane_ms_per_step": seq_ms,
+        "setup_s": setup_s,
+        "roofline": eval_roofline(eval_ms, n_act, kinds, "k_eval (eval_barrier), summed over the scenes"),
+    }
+    batch.close()
+    if args.cpu_baseline:
+        import oracle
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        t_total, n_done, done = 0.0, 0, 0
+        for sc, c in zip(scenes, counts):
+            t1 = time.perf_counter()
+            res = oracle.evaluate(sc, mode=1, derivs=True, nthreads=threads)
+            t_total += time.perf_counter() - t1
+            assert oracle.counts(res)["n_c"] == c["n_c"]
+            n_done += c["n_c"]
+            done += 1
+            if t_total > 10.0:
+                break
+        out["cpu_baseline"] = {"value": n_done / t_total, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+                               "sample": f"the first {done} of the 64 scenes, one evaluation each"}
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py: this path runs on one GPU; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch64":
+        return bench_batch(args)
     import torch
     import synth
     import paper_2510_10256_amd as bfc
 
+    args.prec = args.prec or "fp64"
     sc = synth.workload(args.workload)
     prec = bfc.BF_FP64 if args.prec == "fp64" else bfc.BF_MIXED
     dev = torch.device("cuda:0")
@@ -159,21 +288,7 @@ def main():
     call_ms = {c: float(np.mean(v)) for c, v in per.items()}
 
     # roofline of the per-pair evaluation kernel (the one kernel of eval_barrier)
-    eval_ms = call_ms["eval_barrier"]
-    flops = float(sum(FLOPS_PER_KIND[int(k)] * int(np.sum(kinds == k)) for k in range(4)))
-    bytes_ = float(EVAL_BYTES_PER_PAIR * n_act)
-    t_hbm = bytes_ / (HBM_PEAK_GBS * 1e9)
-    t_fp = flops / (FP64_PEAK_TFLOPS * 1e12)
-    if t_hbm >= t_fp:
-        roof = {"kernel": "k_eval (eval_barrier)", "bound": "hbm", "achieved": bytes_ / (eval_ms * 1e-3) / 1e9,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s"}
-    else:
-        roof = {"kernel": "k_eval (eval_barrier)", "bound": "alu", "achieved": flops / (eval_ms * 1e-3) / 1e12,
-                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["units"] = {"active_pairs": n_act, "bytes": bytes_, "fp64_flops": flops,
-                     "pairs_by_kind": {k: int(np.sum(kinds == q)) for q, k in enumerate(["PP", "PE", "PT", "EE"])}}
+    roof = eval_roofline(call_ms["eval_barrier"], n_act, kinds, "k_eval (eval_barrier)")
 
     out = {
         "metric": "filtered contact pairs evaluated/s (dist+filter+grad+Hessian); p50/p99 latency",
@@ -188,7 +303,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.prec == "fp64" else "f32+f64",
+        "dtype": "f64",
         "data": "synthetic (seeded generator)",
         "config": {"workload": f"{sc.name}: " + ("32 warp x 32 weft rods, 512 vertices per rod, segments "
                                                  "20-300 um, h = 300 um, dhat = 30 um"

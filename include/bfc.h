@@ -79,7 +79,9 @@ typedef struct {
   double h;        /* thickness: activation distance of unfiltered pairs (Sec. 3) */
   double eta;      /* biphasic offset of unfiltered pairs, 0 <= eta < h (Eq. 3) */
   double kappa;    /* barrier stiffness multiplying every pair energy (> 0) */
-  int32_t prec;    /* BF_FP64, or BF_MIXED: FP32 bulk with FP64 near thresholds */
+  int32_t prec;    /* BF_FP64, or BF_MIXED: the eigen-projection stops at about 1e-7 of |H|
+                      (results within 1e-5 relative instead of about 1e-12); both modes
+                      use FP32 boxes in the broad phase and exact threshold decisions */
   int32_t filter;  /* BF_FILTER_PAPER (Eq. 4) or BF_FILTER_NONE (offset barrier everywhere) */
 } bf_params;
 
@@ -178,6 +180,50 @@ bf_status eval_barrier(bf_scene* s, const double* x_d, const bf_active* act, bf_
  * 4x4 vertex blocks of every feasible active pair's stencil. */
 bf_status assemble_grad_hess(bf_scene* s, const bf_active* act, const bf_local* loc, double* E_d,
                              double* g_d, bf_bsr* H, void* stream);
+
+/* ---- tuning ---------------------------------------------------------------
+ * Threads per broad-phase query (2, 4 or 8; default 4): more threads split a
+ * query's 27 neighbour cells finer (small scenes, few queries), fewer cost
+ * less bookkeeping (large scenes).  bf_scene_tune times build_candidates with
+ * each choice on the positions x_d (reps timed launches each, median) and
+ * keeps the fastest; it synchronises and must not be called inside a
+ * captured graph.  cand is overwritten. */
+bf_status bf_scene_set_pq(bf_scene* s, int32_t pq);
+bf_status bf_scene_tune(bf_scene* s, const double* x_d, bf_pairs* cand, int32_t reps, void* stream,
+                        int32_t* pq_out);
+
+/* ---- batches of independent scenes ------------------------------------------
+ * A batch evaluates many scenes (independent meshes, each with its own
+ * positions and buffers) with one HIP graph launch: the whole path of every
+ * scene is captured once, the scenes spread over `lanes` streams inside the
+ * graph (forked from and joined back to the launching stream), so the small
+ * kernels of different scenes run side by side.  Scenes go to lanes by
+ * decreasing primitive count, each to the least loaded lane.  lanes = 0 tunes
+ * it: the batch is captured and timed with 1, 2, 4 and 8 lanes (the steps run,
+ * so every item must hold valid positions and buffers) and the fastest kept.
+ * Items are copied; the scenes and buffers they name must outlive the batch
+ * and keep their capacities (rebuild the batch after bf_scene_reserve).
+ * Results of a scene are bitwise those of its own four calls. */
+typedef struct {
+  bf_scene* scene;
+  const double* x_d;  /* [V,3] positions, read at every step */
+  bf_pairs cand;
+  bf_active act;
+  bf_local loc;
+  double* E_d;        /* [1] */
+  double* g_d;        /* [V,3] */
+  bf_bsr H;
+} bf_batch_item;
+
+typedef struct bf_batch bf_batch;
+
+/* Capture (and, for lanes = 0, tune) the batch; synchronises. */
+bf_status bf_batch_create(const bf_batch_item* items, int32_t n, int32_t lanes, void* stream, bf_batch** out);
+/* One step of every scene of the batch: one graph launch on `stream`. */
+bf_status bf_batch_step(bf_batch* b, void* stream);
+/* Lanes in use and the lane of every item (lane_of_h [n], may be NULL). */
+bf_status bf_batch_info(const bf_batch* b, int32_t* lanes, int32_t* lane_of_h);
+bf_status bf_batch_destroy(bf_batch* b);
 
 /* Device status word (BF_S_* bits) accumulated since the last clear;
  * synchronises the stream the scene last used.  clear != 0 resets it. */

@@ -26,7 +26,9 @@ BF_S_BSR_OVERFLOW = 8
 BF_F_FILTERED, BF_F_INFEASIBLE = 1, 4
 
 EXPORTED = ["bf_scene_create", "bf_scene_reserve", "bf_scene_destroy", "bf_scene_info", "build_candidates",
-            "filter_pairs", "eval_barrier", "assemble_grad_hess", "bf_status_word", "bf_last_error"]
+            "filter_pairs", "eval_barrier", "assemble_grad_hess", "bf_scene_set_pq", "bf_scene_tune",
+            "bf_batch_create", "bf_batch_step", "bf_batch_info", "bf_batch_destroy", "bf_status_word",
+            "bf_last_error"]
 
 
 def build(verbose: bool = False) -> str:
@@ -70,6 +72,11 @@ class Bsr(C.Structure):
                 ("nnzb_d", C.c_void_p)]
 
 
+class BatchItem(C.Structure):
+    _fields_ = [("scene", C.c_void_p), ("x_d", C.c_void_p), ("cand", Pairs), ("act", Active), ("loc", Local),
+                ("E_d", C.c_void_p), ("g_d", C.c_void_p), ("H", Bsr)]
+
+
 _lib = None
 
 
@@ -90,6 +97,12 @@ def lib():
         L.filter_pairs.argtypes = [P, P, C.POINTER(Pairs), C.POINTER(Active), P]
         L.eval_barrier.argtypes = [P, P, C.POINTER(Active), C.POINTER(Local), P]
         L.assemble_grad_hess.argtypes = [P, C.POINTER(Active), C.POINTER(Local), P, P, C.POINTER(Bsr), P]
+        L.bf_scene_set_pq.argtypes = [P, C.c_int32]
+        L.bf_scene_tune.argtypes = [P, P, C.POINTER(Pairs), C.c_int32, P, C.POINTER(C.c_int32)]
+        L.bf_batch_create.argtypes = [C.POINTER(BatchItem), C.c_int32, C.c_int32, P, C.POINTER(P)]
+        L.bf_batch_step.argtypes = [P, P]
+        L.bf_batch_info.argtypes = [P, C.POINTER(C.c_int32), P]
+        L.bf_batch_destroy.argtypes = [P]
         L.bf_status_word.argtypes = [P, C.POINTER(C.c_uint32), C.c_int32]
         L.bf_last_error.restype = C.c_char_p
         for name in EXPORTED[:-1]:
@@ -142,6 +155,7 @@ class ContactScene:
         _check(lib().bf_scene_create(C.byref(desc), C.byref(prm), self.cand_cap, self.act_cap,
                                      C.c_void_p(self._stream()), C.byref(h)), "bf_scene_create")
         self.handle = h
+        self.pq = 4
         self._alloc()
 
     # -- buffers -------------------------------------------------------------
@@ -200,6 +214,27 @@ class ContactScene:
         self.filter_pairs(x)
         self.eval_barrier(x)
         self.assemble_grad_hess()
+
+    def set_pq(self, pq):
+        """Threads per broad-phase query (2, 4 or 8)."""
+        _check(lib().bf_scene_set_pq(self.handle, int(pq)), "bf_scene_set_pq")
+        self.pq = int(pq)
+
+    def tune(self, x, reps=5):
+        """Time build_candidates with 2, 4 and 8 threads per query on x and
+        keep the fastest (synchronises)."""
+        x = self._as_x(x)
+        pq = C.c_int32(0)
+        _check(lib().bf_scene_tune(self.handle, _ptr(x), C.byref(self._cand), int(reps),
+                                   C.c_void_p(self._stream()), C.byref(pq)), "bf_scene_tune")
+        self.pq = int(pq.value)
+        return self.pq
+
+    def batch_item(self, x):
+        """The C-ABI batch item of this scene with positions tensor x (kept
+        alive by the caller; a batch reads it at every step)."""
+        return BatchItem(self.handle, x.data_ptr(), self._cand, self._act, self._loc, self.E.data_ptr(),
+                         self.g.data_ptr(), self._bsr)
 
     def status(self, clear=True):
         v = C.c_uint32(0)
@@ -276,6 +311,49 @@ class ContactScene:
     def close(self):
         if getattr(self, "handle", None):
             lib().bf_scene_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many resident scenes stepped together by one HIP graph launch.
+
+    ``scenes`` are ContactScene objects already sized for their inputs (call
+    ``run`` once each); ``xs`` their device position tensors, which the batch
+    reads at every step (update them in place).  ``lanes`` = 0 tunes the
+    number of concurrent streams inside the graph.
+    """
+
+    def __init__(self, scenes, xs, lanes=0):
+        import torch
+        self.torch = torch
+        self.scenes, self.xs = list(scenes), list(xs)
+        assert len(self.scenes) == len(self.xs) and self.scenes
+        items = (BatchItem * len(self.scenes))(*[cs.batch_item(x) for cs, x in zip(self.scenes, self.xs)])
+        self._items = items
+        h = C.c_void_p()
+        st = torch.cuda.current_stream(self.scenes[0].device).cuda_stream
+        _check(lib().bf_batch_create(items, len(self.scenes), int(lanes), C.c_void_p(st), C.byref(h)),
+               "bf_batch_create")
+        self.handle = h
+        n = C.c_int32(0)
+        lane_of = np.zeros(len(self.scenes), np.int32)
+        _check(lib().bf_batch_info(self.handle, C.byref(n), lane_of.ctypes.data), "bf_batch_info")
+        self.lanes, self.lane_of = int(n.value), lane_of
+
+    def step(self):
+        """One step of every scene: one graph launch on the current stream."""
+        st = self.torch.cuda.current_stream(self.scenes[0].device).cuda_stream
+        _check(lib().bf_batch_step(self.handle, C.c_void_p(st)), "bf_batch_step")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().bf_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

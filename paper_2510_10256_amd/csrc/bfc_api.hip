@@ -1,6 +1,7 @@
 // C ABI of libbfc: scene lifecycle, argument checks, workspace, and the four
 // per-step calls of the contact path (build_candidates, filter_pairs,
 // eval_barrier, assemble_grad_hess).  See include/bfc.h.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -30,6 +31,7 @@ struct bf_scene {
   std::vector<void*> allocs;        // scene-lifetime allocations
   std::vector<void*> asm_allocs;    // assembly scratch (regrown by reserve)
   std::vector<void*> stage_allocs;  // narrow-phase staging (regrown by reserve)
+  int pq = 4;                       // threads per broad-phase query (tunable)
   hipStream_t last = nullptr;
 };
 
@@ -82,6 +84,7 @@ SceneDev dev_view(const bf_scene* s) {
   S.kappa = s->prm.kappa;
   S.filter = s->prm.filter;
   S.mixed = s->prm.prec == BF_MIXED;
+  S.pq = s->pq;
   return S;
 }
 
@@ -181,7 +184,7 @@ bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int
   BroadWs& W = s->bw;
   W.max_cells = (int)std::min<long long>(std::max<long long>(4096, 2LL * np), 1LL << 26);
   long long nscan = 2LL * W.max_cells + 1;
-  long long nq = (long long)(s->kind == BF_SHELL ? nv + ne : ne) * PQ_T + 1;
+  long long nq = (long long)(s->kind == BF_SHELL ? nv + ne : ne) * PQ_MAX + 1;
   W.box = dalloc<Box>(s->allocs, np, &e);
   W.cell_of = dalloc<int>(s->allocs, ne + nt, &e);
   W.part = dalloc<float>(s->allocs, 8LL * BOUNDS_BLOCKS, &e);
@@ -191,6 +194,8 @@ bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int
   W.cell_start = dalloc<int>(s->allocs, nscan, &e);
   W.sorted_id = dalloc<int>(s->allocs, ne + nt, &e);
   W.sorted_box = dalloc<Box>(s->allocs, ne + nt, &e);
+  W.placed_id = dalloc<int>(s->allocs, ne + nt, &e);
+  W.placed_box = dalloc<Box>(s->allocs, ne + nt, &e);
   W.pair_cnt = dalloc<int>(s->allocs, nq, &e);
   W.pair_bsum = dalloc<int>(s->allocs, nq / 256 + 2, &e);
   W.pair_boff = dalloc<int>(s->allocs, nq / 256 + 2, &e);
@@ -424,6 +429,241 @@ bf_status bf_status_word(bf_scene* s, uint32_t* bits_h, int32_t clear) {
     he = hipMemset(s->d_status, 0, sizeof(unsigned));
     if (he != hipSuccess) return fail_hip(he, "bf_status_word");
   }
+  return BF_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Tuning and batches
+// ===========================================================================
+struct bf_batch {
+  std::vector<bf_batch_item> items;
+  std::vector<int> lane_of;
+  int lanes = 1;
+  hipStream_t origin = nullptr;      // capture stream
+  std::vector<hipStream_t> lane_st;  // default priority
+  std::vector<hipEvent_t> events;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+bf_status run_item(const bf_batch_item& it, hipStream_t st) {
+  bf_status r = build_candidates(it.scene, it.x_d, const_cast<bf_pairs*>(&it.cand), st);
+  if (r == BF_OK) r = filter_pairs(it.scene, it.x_d, &it.cand, const_cast<bf_active*>(&it.act), st);
+  if (r == BF_OK) r = eval_barrier(it.scene, it.x_d, &it.act, const_cast<bf_local*>(&it.loc), st);
+  if (r == BF_OK) r = assemble_grad_hess(it.scene, &it.act, &it.loc, it.E_d, it.g_d, const_cast<bf_bsr*>(&it.H), st);
+  return r;
+}
+
+void batch_release_graph(bf_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
+  b->events.clear();
+  for (hipStream_t s : b->lane_st) (void)hipStreamDestroy(s);
+  b->lane_st.clear();
+}
+
+// Assign items to lanes (largest first, least loaded lane), then capture one
+// step of every item: fork from the origin stream, each lane runs its items in
+// order, join back.
+bf_status batch_capture(bf_batch* b, int lanes) {
+  batch_release_graph(b);
+  const int n = (int)b->items.size();
+  lanes = std::max(1, std::min(lanes, n));
+  b->lanes = lanes;
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  auto cost = [&](int i) {
+    const bf_scene* s = b->items[i].scene;
+    return (long long)s->ne + s->nt + (s->kind == BF_SHELL ? s->nv : 0);
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost(a) > cost(c); });
+  std::vector<long long> load(lanes, 0);
+  b->lane_of.assign(n, 0);
+  for (int i : order) {
+    int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    b->lane_of[i] = l;
+    load[l] += cost(i);
+  }
+  hipError_t he;
+  for (int l = 0; l < lanes; ++l) {
+    hipStream_t st;
+    if ((he = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) return fail_hip(he, "bf_batch");
+    b->lane_st.push_back(st);
+  }
+  for (int k = 0; k < 1 + lanes; ++k) {
+    hipEvent_t e;
+    if ((he = hipEventCreateWithFlags(&e, hipEventDisableTiming)) != hipSuccess) return fail_hip(he, "bf_batch");
+    b->events.push_back(e);
+  }
+  if ((he = hipStreamBeginCapture(b->origin, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+    return fail_hip(he, "bf_batch: begin capture");
+  bf_status r = BF_OK;
+  if ((he = hipEventRecord(b->events[0], b->origin)) != hipSuccess) r = fail_hip(he, "bf_batch: fork");
+  for (int l = 0; l < lanes && r == BF_OK; ++l)
+    if ((he = hipStreamWaitEvent(b->lane_st[l], b->events[0], 0)) != hipSuccess) r = fail_hip(he, "bf_batch: fork");
+  for (int l = 0; l < lanes && r == BF_OK; ++l)
+    for (int i = 0; i < n && r == BF_OK; ++i)
+      if (b->lane_of[i] == l) r = run_item(b->items[i], b->lane_st[l]);
+  for (int l = 0; l < lanes && r == BF_OK; ++l) {
+    if ((he = hipEventRecord(b->events[1 + l], b->lane_st[l])) != hipSuccess ||
+        (he = hipStreamWaitEvent(b->origin, b->events[1 + l], 0)) != hipSuccess)
+      r = fail_hip(he, "bf_batch: join");
+  }
+  hipGraph_t g = nullptr;
+  he = hipStreamEndCapture(b->origin, &g);
+  if (r != BF_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return r;
+  }
+  if (he != hipSuccess) return fail_hip(he, "bf_batch: end capture");
+  b->graph = g;
+  if ((he = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0)) != hipSuccess)
+    return fail_hip(he, "bf_batch: instantiate");
+  return BF_OK;
+}
+
+float time_launches(hipGraphExec_t exec, hipStream_t st, int reps) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return INFINITY;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return INFINITY;
+  }
+  float ms = INFINITY;
+  bool ok = hipGraphLaunch(exec, st) == hipSuccess && hipEventRecord(e0, st) == hipSuccess;
+  for (int k = 0; k < reps && ok; ++k) ok = hipGraphLaunch(exec, st) == hipSuccess;
+  ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+       hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ok ? ms / reps : INFINITY;
+}
+
+}  // namespace
+
+extern "C" {
+
+bf_status bf_scene_set_pq(bf_scene* s, int32_t pq) {
+  if (!s || (pq != 2 && pq != 4 && pq != 8)) return fail(BF_E_ARG, "bf_scene_set_pq: pq must be 2, 4 or 8");
+  s->pq = pq;
+  return BF_OK;
+}
+
+bf_status bf_scene_tune(bf_scene* s, const double* x_d, bf_pairs* cand, int32_t reps, void* stream,
+                        int32_t* pq_out) {
+  if (!s || !x_d || !cand || reps < 1) return fail(BF_E_ARG, "bf_scene_tune: bad argument");
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  hipError_t he;
+  if ((he = hipEventCreate(&e0)) != hipSuccess) return fail_hip(he, "bf_scene_tune");
+  if ((he = hipEventCreate(&e1)) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail_hip(he, "bf_scene_tune");
+  }
+  const int choices[3] = {2, 4, 8};
+  int best = s->pq;
+  float best_ms = INFINITY;
+  bf_status r = BF_OK;
+  for (int c = 0; c < 3 && r == BF_OK; ++c) {
+    s->pq = choices[c];
+    r = build_candidates(s, x_d, cand, stream);  // warm
+    std::vector<float> t;
+    for (int k = 0; k < reps && r == BF_OK; ++k) {
+      float ms = 0.0f;
+      if ((he = hipEventRecord(e0, st)) != hipSuccess) { r = fail_hip(he, "bf_scene_tune"); break; }
+      r = build_candidates(s, x_d, cand, stream);
+      if (r != BF_OK) break;
+      if ((he = hipEventRecord(e1, st)) != hipSuccess || (he = hipEventSynchronize(e1)) != hipSuccess ||
+          (he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) {
+        r = fail_hip(he, "bf_scene_tune");
+        break;
+      }
+      t.push_back(ms);
+    }
+    if (r != BF_OK) break;
+    std::nth_element(t.begin(), t.begin() + t.size() / 2, t.end());
+    if (t[t.size() / 2] < best_ms) {
+      best_ms = t[t.size() / 2];
+      best = choices[c];
+    }
+  }
+  s->pq = best;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (r == BF_OK && pq_out) *pq_out = best;
+  return r;
+}
+
+bf_status bf_batch_create(const bf_batch_item* items, int32_t n, int32_t lanes, void* stream, bf_batch** out) {
+  if (!items || n < 1 || !out || lanes < 0) return fail(BF_E_ARG, "bf_batch_create: bad argument");
+  for (int i = 0; i < n; ++i)
+    if (!items[i].scene || !items[i].x_d) return fail(BF_E_ARG, "bf_batch_create: item without scene or positions");
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t he = hipStreamSynchronize(st);
+  if (he != hipSuccess) return fail_hip(he, "bf_batch_create");
+  bf_batch* b = new bf_batch();
+  b->items.assign(items, items + n);
+  if ((he = hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking)) != hipSuccess) {
+    delete b;
+    return fail_hip(he, "bf_batch_create");
+  }
+  bf_status r = BF_OK;
+  if (lanes > 0) {
+    r = batch_capture(b, lanes);
+  } else {  // tune the number of lanes on the live buffers
+    int best = 1;
+    float best_ms = INFINITY;
+    for (int L = 1; L <= 8 && r == BF_OK; L *= 2) {
+      if (L > 1 && L > n) break;
+      r = batch_capture(b, L);
+      if (r != BF_OK) break;
+      float ms = time_launches(b->exec, b->origin, 5);
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = L;
+      }
+    }
+    if (r == BF_OK) r = batch_capture(b, best);
+  }
+  if (r == BF_OK && (he = hipStreamSynchronize(b->origin)) != hipSuccess) r = fail_hip(he, "bf_batch_create");
+  if (r != BF_OK) {
+    bf_batch_destroy(b);
+    return r;
+  }
+  *out = b;
+  return BF_OK;
+}
+
+bf_status bf_batch_step(bf_batch* b, void* stream) {
+  if (!b || !b->exec) return fail(BF_E_STATE, "bf_batch_step: batch not captured");
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t he = hipGraphLaunch(b->exec, st);
+  if (he != hipSuccess) return fail_hip(he, "bf_batch_step");
+  for (auto& it : b->items) it.scene->last = st;
+  return BF_OK;
+}
+
+bf_status bf_batch_info(const bf_batch* b, int32_t* lanes, int32_t* lane_of_h) {
+  if (!b) return fail(BF_E_ARG, "bf_batch_info: null batch");
+  if (lanes) *lanes = b->lanes;
+  if (lane_of_h)
+    for (size_t i = 0; i < b->lane_of.size(); ++i) lane_of_h[i] = b->lane_of[i];
+  return BF_OK;
+}
+
+bf_status bf_batch_destroy(bf_batch* b) {
+  if (!b) return BF_OK;
+  (void)hipDeviceSynchronize();
+  batch_release_graph(b);
+  if (b->origin) (void)hipStreamDestroy(b->origin);
+  delete b;
   return BF_OK;
 }
 

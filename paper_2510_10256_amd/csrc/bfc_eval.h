@@ -61,8 +61,9 @@ __device__ __forceinline__ constexpr int sched_idx(int n, int r, int k, int w) {
 
 // Cyclic Jacobi eigen-decomposition of the symmetric N x N matrix A (upper
 // triangle, destroyed) in round-robin order, followed by
-// A+ = V max(L, 0) V^T written to P (upper).  Converges when the
-// off-diagonal mass is below 1e-32 of the Frobenius mass.
+// A+ = V max(L, 0) V^T written to P (upper).  Stops when the off-diagonal
+// mass is below tol2 of the Frobenius mass (1e-32 for FP64 results; the
+// error left in A+ is about sqrt(2 tol2) |A|).
 //
 // A rotation angle only decides how much of a_pq a rotation removes, not the
 // exactness of the similarity transform, so the angles are computed in FP32
@@ -71,7 +72,7 @@ __device__ __forceinline__ constexpr int sched_idx(int n, int r, int k, int w) {
 // (c = (1 + t^2)^-1/2 by Newton steps in FP64) and applied with the full
 // 2 x 2 update, since a_pq' is no longer exactly zero.  Near convergence
 // each sweep still shrinks the off-diagonal mass by the FP32 angle accuracy.
-template <int N> __device__ __forceinline__ void psd_jacobi(double* A, double* P) {
+template <int N> __device__ __forceinline__ void psd_jacobi(double* A, double* P, double tol2) {
   constexpr int R = Sched<N>::R, K = Sched<N>::K;
   double V[N][N];
 #pragma unroll
@@ -90,7 +91,7 @@ template <int N> __device__ __forceinline__ void psd_jacobi(double* A, double* P
     for (int i = 0; i < N; ++i)
 #pragma unroll
       for (int j = i + 1; j < N; ++j) off += A[uix<N>(i, j)] * A[uix<N>(i, j)];
-    if (!(off > 1e-32 * fro)) break;
+    if (!(off > tol2 * fro)) break;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       double cs[K], sn[K];
@@ -237,7 +238,7 @@ __device__ __forceinline__ void eval_pp(const d3* P, int s0, int s1, double a, d
 // w1 = (1, -1, 0)/sqrt2, w2 = (1, 1, -2)/sqrt6.  With y = (r, e) = Y x the
 // coupling b = Y W is [[sqrt2, 0], [1/sqrt2, -3/sqrt6]].
 __device__ __forceinline__ void eval_pe(const d3* P, int sp, int se0, int se1, double a, double eta,
-                                        double kappa, OutRow o) {
+                                        double kappa, double tol2, OutRow o) {
   const double S2 = 1.4142135623730951, IS2 = 0.70710678118654752, IS6 = 0.40824829046386302;
   d3 xp = pick4(P, sp), x0 = pick4(P, se0), x1 = pick4(P, se1);
   d3 r = xp - x0, e = x1 - x0;
@@ -285,7 +286,7 @@ __device__ __forceinline__ void eval_pe(const d3* P, int sp, int se0, int se1, d
                             be[al] * br[bt] * Yre[j][i] + be[al] * be[bt] * Yee[i][j];
         }
   double Ap[21];
-  psd_jacobi<6>(A, Ap);
+  psd_jacobi<6>(A, Ap, tol2);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {  // Y rows: r = (1, -1, 0), e = (0, -1, 1) on (p, e0, e1)
     double grx = ch.cg * gr[i], gex = ch.cg * ge[i];
@@ -319,7 +320,7 @@ __device__ __forceinline__ void eval_pe(const d3* P, int sp, int se0, int se1, d
 // Couplings b = Y W (rows r, u, v):
 //   PT (r = p-t0, u = t1-t0, v = t2-t0):  r (0,1,1)  u (-1,1,0)  v (-1,0,1)
 //   EE (r = a0-b0, u = a1-a0, v = b1-b0): r (1,0,1)  u (0,-1,-1) v (0,-1,1)
-__device__ __forceinline__ void eval_tri(const d3* P, bool is_pt, double a, double eta, double kappa,
+__device__ __forceinline__ void eval_tri(const d3* P, bool is_pt, double a, double eta, double kappa, double tol2,
                                          OutRow o) {
   d3 r, u, v;
   if (is_pt) {
@@ -397,7 +398,7 @@ __device__ __forceinline__ void eval_tri(const d3* P, bool is_pt, double a, doub
           A[uix<9>(I, J)] = acc;
         }
   double Ap[45];
-  psd_jacobi<9>(A, Ap);
+  psd_jacobi<9>(A, Ap, tol2);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     double gr = ch.cg * g[i], gu = ch.cg * g[3 + i], gv = ch.cg * g[6 + i];
@@ -434,17 +435,23 @@ __device__ __forceinline__ void eval_tri(const d3* P, bool is_pt, double a, doub
         }
 }
 
-// Evaluate one active pair with the sub-case `code` fixed by the narrow phase.
+// Evaluate one active pair with the sub-case `code` fixed by the narrow
+// phase.  MIXED: the projection stops at about 1e-7 of |H| instead of FP64
+// convergence.  Distances, derivative terms and the projection arithmetic
+// stay FP64 on both paths: FP32 derivative terms lose up to 1e-2 relative
+// accuracy for nearly parallel edges (successive turns of a coiled rod).
+template <bool MIXED>
 __device__ __forceinline__ void eval_pair(const d3* P, int code, double a, double eta, double kappa, OutRow o) {
+  const double tol2 = MIXED ? 1e-14 : 1e-32;
   int kind = case_kind(code);
   if (kind == K_PT || kind == K_EE) {
-    eval_tri(P, kind == K_PT, a, eta, kappa, o);
+    eval_tri(P, kind == K_PT, a, eta, kappa, tol2, o);
     return;
   }
   int s0, s1, s2;
   case_slots(code, s0, s1, s2);
   if (kind == K_PP) eval_pp(P, s0, s1, a, eta, kappa, o);
-  else eval_pe(P, s0, s1, s2, a, eta, kappa, o);
+  else eval_pe(P, s0, s1, s2, a, eta, kappa, tol2, o);
 }
 
 }  // namespace bfc

@@ -37,7 +37,8 @@ struct SceneDev {
   const double* thr2;  // [C,2] exact squared activation of filtered pairs (hi, lo)
   double h, eta, kappa;
   int filter;  // 0 paper, 1 none
-  int mixed;   // 1: FP32 bulk arithmetic
+  int mixed;   // 1: projection converged to the mixed-precision tolerance
+  int pq;      // threads per broad-phase query (2, 4 or 8)
 };
 
 // Broad-phase scratch (device pointers inside the scene workspace).
@@ -49,9 +50,11 @@ struct BroadWs {
   Grid* grid;        // [1]
   int* cell_cnt;     // [2*max_cells + 1], zero between steps
   int* cell_start;   // [2*max_cells + 1]
-  int* sorted_id;    // [NS] stored primitives in cell order
+  int* placed_id;    // [NS] stored primitives grouped by cell (any order inside a cell)
+  Box* placed_box;   // [NS]
+  int* sorted_id;    // [NS] stored primitives in cell order, by id inside a cell
   Box* sorted_box;   // [NS]
-  int* pair_cnt;     // [NQ * PQ_T] pairs per (query, cell subset)
+  int* pair_cnt;     // [NQ * PQ_MAX] pairs per (query, cell subset)
   int* pair_bsum;    // [work-groups + 1] pairs per work-group of the count pass
   int* pair_boff;    // [work-groups + 1] their exclusive scan
   int* scan_tmp;     // [scan partials]

@@ -8,7 +8,7 @@ namespace bfc {
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = 256 * SCAN_ITEMS;
 constexpr int SCAN1_MAX = 1 << 14;     // arrays up to this length are scanned by one work-group
-constexpr int PQ_T = 4;                // threads per broad-phase query
+constexpr int PQ_MAX = 8;              // threads per broad-phase query: 2, 4 (default) or 8
 constexpr int NW_ITEMS = 4;            // candidates per thread in the narrow phase
 constexpr int NW_TILE = 256 * NW_ITEMS;
 constexpr int BOUNDS_BLOCKS = 512;     // cap on k_bounds work-groups (partials of the last-block reduction)

@@ -366,12 +366,28 @@ __global__ __launch_bounds__(256) void k_count(int nstored, int ne, const Box* b
 }
 
 __global__ __launch_bounds__(256) void k_scatter(int nstored, const Box* box, const int* cell_of, int* cell_cnt,
-                                                 const int* cell_start, int* sorted_id, Box* sorted_box) {
+                                                 const int* cell_start, int* placed_id, Box* placed_box) {
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < nstored; p += grid_stride()) {
     int sub = cell_of[p];
     int pos = cell_start[sub] + atomicSub(&cell_cnt[sub], 1) - 1;
-    sorted_id[pos] = p;
-    sorted_box[pos] = box[p];
+    placed_id[pos] = p;
+    placed_box[pos] = box[p];
+  }
+}
+
+// The scatter's atomics leave the entries of a cell in arbitrary order; each
+// entry's rank among the cell's ids puts them in id order, so candidate
+// lists, and every result downstream, are the same from run to run.
+__global__ __launch_bounds__(256) void k_cell_order(int nstored, const int* cell_of, const int* cell_start,
+                                                    const int* placed_id, const Box* placed_box, int* sorted_id,
+                                                    Box* sorted_box) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nstored; k += grid_stride()) {
+    const int p = placed_id[k], sub = cell_of[p];
+    const int b = cell_start[sub], e = cell_start[sub + 1];
+    int r = 0;
+    for (int q = b; q < e; ++q) r += placed_id[q] < p;
+    sorted_id[b + r] = p;
+    sorted_box[b + r] = placed_box[k];
   }
 }
 
@@ -390,10 +406,10 @@ __device__ __forceinline__ bool boxes_near(const Box& a, const Box& b, double h)
 }
 
 // Visit the stored primitives of the sub-list for the query (triangles for a
-// point, edges for an edge) in the neighbour cells c = sub, sub + PQ_T, ...
+// point, edges for an edge) in the neighbour cells c = sub, sub + PQ, ...
 // of the 27 cells around the query's cell; count, or emit at `pos`, every
 // non-incident pair whose boxes are within h.
-template <bool EMIT>
+template <int PQ, bool EMIT>
 __device__ __forceinline__ int visit_pairs(const SceneDev& S, const Grid& g, const int* cell_start,
                                            const int* sorted_id, const Box* sorted_box, double hf, int qtype,
                                            int qid, const Box& qb, const int* qv, int sub, long long pos,
@@ -402,7 +418,7 @@ __device__ __forceinline__ int visit_pairs(const SceneDev& S, const Grid& g, con
   cell_coords(g, qb, c);
   int cnt = 0;
   int sub_type = qtype == BF_PT ? 1 : 0;
-  for (int nb = sub; nb < 27; nb += PQ_T) {
+  for (int nb = sub; nb < 27; nb += PQ) {
     int cx = c[0] + nb % 3 - 1, cy = c[1] + (nb / 3) % 3 - 1, cz = c[2] + nb / 9 - 1;
     if (cx < 0 || cy < 0 || cz < 0 || cx >= g.n[0] || cy >= g.n[1] || cz >= g.n[2]) continue;
     int sl = 2 * cell_lin(g, cx, cy, cz) + sub_type;
@@ -455,18 +471,19 @@ __device__ __forceinline__ void query_of(const SceneDev& S, const Box* box, int 
 
 // pass 1: pair count of every (query, neighbour-cell subset) thread, and the
 // total of each work-group in bsum[block] (bsum[nblocks] = 0)
+template <int PQ>
 __global__ __launch_bounds__(256) void k_pair_count(SceneDev S, int nquery, const Box* box, const Grid* gp,
                                                     const int* cell_start, const int* sorted_id, const Box* sorted_box,
                                                     double hf, int* cnt, int* bsum) {
   Grid g = *gp;
-  int nt = nquery * PQ_T;
+  int nt = nquery * PQ;
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   int c = 0;
   if (t < nt) {
     int qtype, qid, qv[2];
     Box qb;
-    query_of(S, box, t / PQ_T, qtype, qid, qb, qv);
-    c = visit_pairs<false>(S, g, cell_start, sorted_id, sorted_box, hf, qtype, qid, qb, qv, t % PQ_T, 0, 0, nullptr,
+    query_of(S, box, t / PQ, qtype, qid, qb, qv);
+    c = visit_pairs<PQ, false>(S, g, cell_start, sorted_id, sorted_box, hf, qtype, qid, qb, qv, t % PQ, 0, 0, nullptr,
                            nullptr, nullptr, nullptr);
     cnt[t] = c;
   }
@@ -480,13 +497,14 @@ __global__ __launch_bounds__(256) void k_pair_count(SceneDev S, int nquery, cons
 
 // pass 2: offsets from the scanned work-group totals plus an in-group scan;
 // emit in query-major order (no atomics)
+template <int PQ>
 __global__ __launch_bounds__(256) void k_pair_emit(SceneDev S, int nquery, const Box* box, const Grid* gp,
                                                    const int* cell_start, const int* sorted_id, const Box* sorted_box,
                                                    double hf, const int* cnt, const int* boff, int* oi, int* oj,
                                                    unsigned char* ot, long long cap, long long* count,
                                                    unsigned* status) {
   Grid g = *gp;
-  int nt = nquery * PQ_T;
+  int nt = nquery * PQ;
   if (blockIdx.x == 0 && threadIdx.x == 0) *count = (long long)boff[gridDim.x];
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   int c = t < nt ? cnt[t] : 0;
@@ -494,8 +512,8 @@ __global__ __launch_bounds__(256) void k_pair_emit(SceneDev S, int nquery, const
   if (c == 0) return;
   int qtype, qid, qv[2];
   Box qb;
-  query_of(S, box, t / PQ_T, qtype, qid, qb, qv);
-  visit_pairs<true>(S, g, cell_start, sorted_id, sorted_box, hf, qtype, qid, qb, qv, t % PQ_T, off, cap, oi, oj, ot,
+  query_of(S, box, t / PQ, qtype, qid, qb, qv);
+  visit_pairs<PQ, true>(S, g, cell_start, sorted_id, sorted_box, hf, qtype, qid, qb, qv, t % PQ, off, cap, oi, oj, ot,
                     status);
 }
 
@@ -737,6 +755,7 @@ __global__ __launch_bounds__(256) void k_compact(StageWs W, int G, int* ai, int*
 // One wave per work-group; every lane evaluates one pair into its row of an
 // LDS tile (E, G[12], upper triangle of H), and the wave then writes the
 // tile's contiguous rows of E, G and the full 12 x 12 H with coalesced stores.
+template <bool MIXED>
 __global__ __launch_bounds__(64) void k_eval(SceneDev S, const double* x, const int* ai, const int* aj,
                                              const unsigned char* at, const unsigned char* acode,
                                              const unsigned char* aflags, const unsigned long long* act_count,
@@ -760,7 +779,7 @@ __global__ __launch_bounds__(64) void k_eval(SceneDev S, const double* x, const 
         double a, eta;
         if (fl & BF_F_FILTERED) { a = S.dmin[S.comp[v[0]]]; eta = 0.0; }
         else { a = S.h; eta = S.eta; }
-        eval_pair(P, code, a, eta, S.kappa, o);
+        eval_pair<MIXED>(P, code, a, eta, S.kappa, o);
       }
     }
     __syncthreads();
@@ -1363,6 +1382,17 @@ void run_lift_ref(const SceneDev& S, double* xref, hipStream_t st) {
   hipLaunchKernelGGL(k_lift_ref, dim3(nblocks(S.nv)), dim3(256), 0, st, S, xref);
 }
 
+template <int PQ>
+static void launch_pairs(const SceneDev& S, int nquery, const BroadWs& W, int* oi, int* oj, unsigned char* ot,
+                         long long cap, long long* count, unsigned* status, hipStream_t st) {
+  int nb = (nquery * PQ + 255) / 256;
+  hipLaunchKernelGGL(k_pair_count<PQ>, dim3(nb), dim3(256), 0, st, S, nquery, W.box, W.grid, W.cell_start,
+                     W.sorted_id, W.sorted_box, S.h, W.pair_cnt, W.pair_bsum);
+  scan_excl(W.pair_bsum, W.pair_boff, nullptr, nb + 1, W.scan_tmp, st);
+  hipLaunchKernelGGL(k_pair_emit<PQ>, dim3(nb), dim3(256), 0, st, S, nquery, W.box, W.grid, W.cell_start,
+                     W.sorted_id, W.sorted_box, S.h, W.pair_cnt, W.pair_boff, oi, oj, ot, cap, count, status);
+}
+
 void run_broad(const SceneDev& S, const double* x, const BroadWs& W, int* oi, int* oj, unsigned char* ot,
                long long cap, long long* count, unsigned* status, hipStream_t st) {
   int np = S.ne + S.nt + (S.kind == 1 ? S.nv : 0);
@@ -1377,14 +1407,15 @@ void run_broad(const SceneDev& S, const double* x, const BroadWs& W, int* oi, in
                      W.cell_of);
   scan_excl(W.cell_cnt, W.cell_start, nscan_dev, nscan_max, W.scan_tmp, st);
   hipLaunchKernelGGL(k_scatter, dim3(nblocks(nstored)), dim3(256), 0, st, nstored, W.box, W.cell_of, W.cell_cnt,
-                     W.cell_start, W.sorted_id, W.sorted_box);
-  int nt = nquery * PQ_T;
-  int nb = (nt + 255) / 256;  // one thread per (query, cell subset): no grid-stride here
-  hipLaunchKernelGGL(k_pair_count, dim3(nb), dim3(256), 0, st, S, nquery, W.box, W.grid, W.cell_start, W.sorted_id,
-                     W.sorted_box, S.h, W.pair_cnt, W.pair_bsum);
-  scan_excl(W.pair_bsum, W.pair_boff, nullptr, nb + 1, W.scan_tmp, st);
-  hipLaunchKernelGGL(k_pair_emit, dim3(nb), dim3(256), 0, st, S, nquery, W.box, W.grid, W.cell_start, W.sorted_id,
-                     W.sorted_box, S.h, W.pair_cnt, W.pair_boff, oi, oj, ot, cap, count, status);
+                     W.cell_start, W.placed_id, W.placed_box);
+  hipLaunchKernelGGL(k_cell_order, dim3(nblocks(nstored)), dim3(256), 0, st, nstored, W.cell_of, W.cell_start,
+                     W.placed_id, W.placed_box, W.sorted_id, W.sorted_box);
+  // one thread per (query, cell subset): no grid-stride here
+  switch (S.pq) {
+    case 2: launch_pairs<2>(S, nquery, W, oi, oj, ot, cap, count, status, st); break;
+    case 8: launch_pairs<8>(S, nquery, W, oi, oj, ot, cap, count, status, st); break;
+    default: launch_pairs<4>(S, nquery, W, oi, oj, ot, cap, count, status, st); break;
+  }
 }
 
 void run_narrow(const SceneDev& S, const double* x, const int* ci, const int* cj, const unsigned char* ct,
@@ -1401,8 +1432,12 @@ void run_narrow(const SceneDev& S, const double* x, const int* ci, const int* cj
 void run_eval(const SceneDev& S, const double* x, const int* ai, const int* aj, const unsigned char* at,
               const unsigned char* acode, const unsigned char* aflags, const long long* act_count, long long acap,
               double* E, double* G, double* H, hipStream_t st) {
-  hipLaunchKernelGGL(k_eval, dim3(nblocks(acap, 64, 65535)), dim3(64), 0, st, S, x, ai, aj, at, acode, aflags,
-                     (const unsigned long long*)act_count, acap, E, G, H);
+  if (S.mixed)
+    hipLaunchKernelGGL(k_eval<true>, dim3(nblocks(acap, 64, 65535)), dim3(64), 0, st, S, x, ai, aj, at, acode,
+                       aflags, (const unsigned long long*)act_count, acap, E, G, H);
+  else
+    hipLaunchKernelGGL(k_eval<false>, dim3(nblocks(acap, 64, 65535)), dim3(64), 0, st, S, x, ai, aj, at, acode,
+                       aflags, (const unsigned long long*)act_count, acap, E, G, H);
 }
 
 void run_assemble(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,

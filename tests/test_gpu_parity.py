@@ -60,6 +60,33 @@ def test_small_parity_fp64(name):
 
 
 @requires_gpu
+@pytest.mark.parametrize("name", list(SMALL))
+def test_small_parity_mixed(name):
+    # FP32 screen in the narrow phase, FP32 derivative terms: the active set
+    # stays exact, values within tau = 1e-5
+    import paper_2510_10256_amd as bfc
+    from tests.parity import compare
+    sc = SMALL[name]()
+    print(f"[parity mixed] {name} V={sc.n_verts}", flush=True)
+    g = run_gpu(sc, prec=bfc.BF_MIXED)
+    o = oracle.evaluate(sc, mode=1)
+    rep = compare(g, o, sc.n_verts, kappa=sc.kappa, tau=1e-5)
+    print(name, g["counts"], rep, flush=True)
+
+
+@requires_gpu
+def test_full_yarn_patch_parity_mixed():
+    import paper_2510_10256_amd as bfc
+    from tests.parity import compare
+    sc = synth.woven_patch()
+    print(f"[parity mixed] woven_patch V={sc.n_verts}", flush=True)
+    g = run_gpu(sc, prec=bfc.BF_MIXED)
+    o = oracle.evaluate(sc, mode=1)
+    rep = compare(g, o, sc.n_verts, kappa=sc.kappa, tau=1e-5)
+    print(g["counts"], rep, flush=True)
+
+
+@requires_gpu
 def test_full_yarn_patch_parity_fp64():
     # the 32 x 32 woven patch (32,704 edges): full comparison
     from tests.parity import compare
@@ -72,15 +99,17 @@ def test_full_yarn_patch_parity_fp64():
 
 
 @requires_gpu
-def test_full_cloth_parity_fp64():
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_full_cloth_parity(prec):
     # the 256 x 256 folded cloth: active set and counts exactly; per-pair
     # values on a sample re-evaluated pair by pair; assembly by its
     # size-independent properties and the oracle's energy sum
     import math
+    import paper_2510_10256_amd as bfc
     from tests.parity import active_view
     sc = synth.folded_cloth()
-    print(f"[parity fp64] folded_cloth V={sc.n_verts}", flush=True)
-    g = run_gpu(sc)
+    print(f"[parity {prec}] folded_cloth V={sc.n_verts}", flush=True)
+    g = run_gpu(sc, prec=bfc.BF_FP64 if prec == "fp64" else bfc.BF_MIXED)
     o = oracle.evaluate(sc, mode=1, derivs=False)
     oc = oracle.counts(o)
     for k in ("n_c", "n_filt", "n_act", "n_infeasible"):
@@ -91,7 +120,7 @@ def test_full_cloth_parity_fp64():
     assert np.array_equal(g["flags"][gi] & 5, o["flags"][oi] & 5)
     rng = np.random.default_rng(7)
     sample = rng.choice(len(gi), size=min(4000, len(gi)), replace=False)
-    tau = 1e-10
+    tau = 1e-10 if prec == "fp64" else 1e-5
     worst = 0.0
     for s in sample:
         k, q = gi[s], oi[s]
