@@ -26,7 +26,8 @@
  * during the call that takes them.  A scene owns device memory for its copy
  * of the topology, its precomputed filter data and its scratch space; it is
  * allocated by bf_scene_create and bf_scene_reserve only, never by the four
- * per-step calls.  Every call enqueues its work on the given stream (a
+ * per-step calls; it is stream-ordered memory (allocated on the stream given
+ * to bf_scene_create, freed by bf_scene_destroy on the scene's last stream).  Every call enqueues its work on the given stream (a
  * hipStream_t passed as void*, NULL = default stream) and returns without
  * synchronising unless stated.  Calls on one scene must not overlap.
  *
@@ -149,6 +150,9 @@ bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int
  * captured graphs). */
 bf_status bf_scene_reserve(bf_scene* s, int64_t cand_cap, int64_t act_cap);
 
+/* Frees the scene's device memory in stream order after the work last
+ * enqueued for it (on the stream of its last call or batch launch); work of
+ * the scene on any other stream must be complete.  Does not synchronise. */
 bf_status bf_scene_destroy(bf_scene* s);
 
 /* Precompute results: component of each vertex, number of components, and
@@ -223,6 +227,7 @@ bf_status bf_batch_create(const bf_batch_item* items, int32_t n, int32_t lanes, 
 bf_status bf_batch_step(bf_batch* b, void* stream);
 /* Lanes in use and the lane of every item (lane_of_h [n], may be NULL). */
 bf_status bf_batch_info(const bf_batch* b, int32_t* lanes, int32_t* lane_of_h);
+/* Waits for the batch's last launch, then frees it (the scenes stay). */
 bf_status bf_batch_destroy(bf_batch* b);
 
 /* Device status word (BF_S_* bits) accumulated since the last clear;

@@ -48,11 +48,16 @@ bf_status fail_hip(hipError_t e, const char* where) {
   return BF_E_DEVICE;
 }
 
+// Scene memory is stream-ordered (hipMallocAsync / hipFreeAsync on the
+// stream of the call that creates, regrows or destroys it), so destroying a
+// scene never waits for work of other scenes on other streams.
+thread_local hipStream_t g_alloc_stream = nullptr;
+
 template <class T> T* dalloc(std::vector<void*>& list, size_t n, hipError_t* err) {
   void* p = nullptr;
   size_t bytes = n * sizeof(T);
   if (bytes == 0) bytes = sizeof(T);
-  hipError_t e = hipMalloc(&p, bytes);
+  hipError_t e = hipMallocAsync(&p, bytes, g_alloc_stream);
   if (e != hipSuccess) {
     *err = e;
     return nullptr;
@@ -88,9 +93,13 @@ SceneDev dev_view(const bf_scene* s) {
   return S;
 }
 
+void free_list(std::vector<void*>& l, hipStream_t st = g_alloc_stream) {
+  for (void* p : l) (void)hipFreeAsync(p, st);
+  l.clear();
+}
+
 bf_status alloc_asm(bf_scene* s, long long act_cap) {
-  for (void* p : s->asm_allocs) (void)hipFree(p);
-  s->asm_allocs.clear();
+  free_list(s->asm_allocs);
   hipError_t e = hipSuccess;
   AsmWs A{};
   A.inc_cnt = dalloc<int>(s->asm_allocs, s->nv + 1, &e);
@@ -101,17 +110,13 @@ bf_status alloc_asm(bf_scene* s, long long act_cap) {
   A.epart = dalloc<double>(s->asm_allocs, 256, &e);
   A.scan_tmp = dalloc<int>(s->asm_allocs, scan_parts(s->nv + 1) + 16, &e);
   if (e != hipSuccess) return fail(BF_E_NOMEM, "bf_scene_reserve: device allocation failed");
-  if (hipMemset(A.inc_cnt, 0, sizeof(int) * (s->nv + 1)) != hipSuccess ||
-      hipMemset(A.rowcnt, 0, sizeof(int) * (s->nv + 1)) != hipSuccess)
+  if (hipMemsetAsync(A.inc_cnt, 0, sizeof(int) * (s->nv + 1), g_alloc_stream) != hipSuccess ||
+      hipMemsetAsync(A.rowcnt, 0, sizeof(int) * (s->nv + 1), g_alloc_stream) != hipSuccess ||
+      hipStreamSynchronize(g_alloc_stream) != hipSuccess)
     return fail(BF_E_DEVICE, "bf_scene_reserve: clearing the incidence counts failed");
   s->aw = A;
   s->act_cap = act_cap;
   return BF_OK;
-}
-
-void free_list(std::vector<void*>& l) {
-  for (void* p : l) (void)hipFree(p);
-  l.clear();
 }
 
 bf_status alloc_stage(bf_scene* s, long long cand_cap) {
@@ -166,6 +171,7 @@ bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int
     if (mesh->edges_h[2 * e] == mesh->edges_h[2 * e + 1]) return fail(BF_E_ARG, "bf_scene_create: degenerate edge");
 
   hipStream_t st = (hipStream_t)stream;
+  g_alloc_stream = st;
   bf_scene* s = new bf_scene;
   s->prm = *params;
   s->kind = mesh->kind;
@@ -335,18 +341,20 @@ bf_status bf_scene_reserve(bf_scene* s, int64_t cand_cap, int64_t act_cap) {
   if (act_cap <= s->act_cap && cand_cap <= s->sw.cap) return BF_OK;
   hipError_t he = hipDeviceSynchronize();
   if (he != hipSuccess) return fail_hip(he, "bf_scene_reserve");
+  g_alloc_stream = nullptr;
   bf_status r = BF_OK;
   if (act_cap > s->act_cap) r = alloc_asm(s, act_cap);
   if (r == BF_OK && cand_cap > s->sw.cap) r = alloc_stage(s, cand_cap);
+  if (r == BF_OK && (he = hipDeviceSynchronize()) != hipSuccess) return fail_hip(he, "bf_scene_reserve");
   return r;
 }
 
 bf_status bf_scene_destroy(bf_scene* s) {
   if (!s) return BF_OK;
-  (void)hipDeviceSynchronize();
-  free_list(s->asm_allocs);
-  free_list(s->stage_allocs);
-  free_list(s->allocs);
+  // freed in stream order after the work last enqueued for the scene
+  free_list(s->asm_allocs, s->last);
+  free_list(s->stage_allocs, s->last);
+  free_list(s->allocs, s->last);
   delete s;
   return BF_OK;
 }
@@ -446,6 +454,7 @@ struct bf_batch {
   std::vector<hipEvent_t> events;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;         // recorded after every launch
 };
 
 namespace {
@@ -610,7 +619,9 @@ bf_status bf_batch_create(const bf_batch_item* items, int32_t n, int32_t lanes, 
   if (he != hipSuccess) return fail_hip(he, "bf_batch_create");
   bf_batch* b = new bf_batch();
   b->items.assign(items, items + n);
-  if ((he = hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking)) != hipSuccess) {
+  if ((he = hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking)) != hipSuccess ||
+      (he = hipEventCreateWithFlags(&b->done, hipEventDisableTiming)) != hipSuccess) {
+    if (b->origin) (void)hipStreamDestroy(b->origin);
     delete b;
     return fail_hip(he, "bf_batch_create");
   }
@@ -645,6 +656,7 @@ bf_status bf_batch_step(bf_batch* b, void* stream) {
   if (!b || !b->exec) return fail(BF_E_STATE, "bf_batch_step: batch not captured");
   hipStream_t st = (hipStream_t)stream;
   hipError_t he = hipGraphLaunch(b->exec, st);
+  if (he == hipSuccess) he = hipEventRecord(b->done, st);
   if (he != hipSuccess) return fail_hip(he, "bf_batch_step");
   for (auto& it : b->items) it.scene->last = st;
   return BF_OK;
@@ -660,8 +672,10 @@ bf_status bf_batch_info(const bf_batch* b, int32_t* lanes, int32_t* lane_of_h) {
 
 bf_status bf_batch_destroy(bf_batch* b) {
   if (!b) return BF_OK;
-  (void)hipDeviceSynchronize();
+  if (b->done) (void)hipEventSynchronize(b->done);  // the last launch only
+  if (b->origin) (void)hipStreamSynchronize(b->origin);
   batch_release_graph(b);
+  if (b->done) (void)hipEventDestroy(b->done);
   if (b->origin) (void)hipStreamDestroy(b->origin);
   delete b;
   return BF_OK;

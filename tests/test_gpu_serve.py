@@ -1,0 +1,45 @@
+"""Serving loop on the GPU: requests overlap on the device, scenes are evicted
+and re-created under a small HBM budget, and every result equals, bitwise,
+the same request evaluated alone."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+requires_gpu = pytest.mark.skipif(not torch.cuda.is_available(), reason="no GPU")
+
+
+@requires_gpu
+def test_served_results_equal_alone():
+    import paper_2510_10256_amd as bfc
+    from paper_2510_10256_amd.serve import Server, request_maker, run_closed_loop, scene_bytes, scene_caps
+    scenes = [synth.woven_patch(seed=40 + k, n_warp=2 + k % 3, n_weft=3, verts_per_rod=48 + 16 * k)
+              if k % 2 == 0 else synth.folded_cloth(seed=40 + k, n=24 + 8 * k, gaps=()) for k in range(8)]
+    sizes = [scene_bytes(sc, *scene_caps(sc)) for sc in scenes]
+    budget = int(2.5 * np.median(sizes)) + max(sizes)  # a few scenes at a time: eviction binds
+    print(f"[serve] {len(scenes)} scenes, budget {budget} B", flush=True)
+    server = Server(scenes, budget_bytes=budget, slots=3, prec=bfc.BF_MIXED, keep_grad=True)
+    make = request_maker(scenes, seed=99)
+    done, wall = run_closed_loop(server, make, n_requests=40, inflight=8)
+    torch.cuda.synchronize()
+    print(f"[serve] {len(done)} requests in {wall:.2f} s, created {server.created}, evicted {server.evicted}",
+          flush=True)
+    assert len(done) == 40 and server.evicted > 0
+    assert server.adm.used <= budget
+    # every result against the same request alone
+    for req in done:
+        sc = scenes[req.sid]
+        cand, act, bsr = scene_caps(sc)
+        cs = bfc.ContactScene(sc, prec=bfc.BF_MIXED, cand_cap=cand, act_cap=act, bsr_cap=bsr, device="cuda:0")
+        x = torch.tensor(req.x, dtype=torch.float64, device="cuda:0")
+        cs.run(x)
+        r = cs.results()
+        cs.close()
+        assert req.E == r["E_total"], (req.rid, req.E, r["E_total"])
+        for k in ("n_c", "n_filt", "n_act", "n_infeasible", "nnzb"):
+            assert req.counts[k] == r["counts"][k], (req.rid, k)
+        assert np.array_equal(req.g.numpy(), r["g"]), req.rid
+    server.close()
