@@ -51,7 +51,9 @@ def parse():
     ap.add_argument("--budget-gib", type=float, default=2.0, help="serve: HBM budget of resident scenes")
     ap.add_argument("--slots", type=int, default=4, help="serve: requests on the device at once")
     ap.add_argument("--requests", type=int, default=300, help="serve: requests per open-loop run")
-    ap.add_argument("--graph", type=int, default=1, help="replay the step as a captured HIP graph")
+    ap.add_argument("--graph", type=int, default=-1,
+                    help="1: replay the step as a captured HIP graph; 0: eager launches (the assembly's structure "
+                         "then overlaps the evaluation on a second stream); -1: time both, report the faster")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (calibrates HBM byte counters)")
@@ -293,7 +295,7 @@ def main():
 
     stream = torch.cuda.current_stream(dev)
     graph = None
-    if args.graph:
+    if args.graph != 0:
         # one step captured as a graph (every launch is on the current stream,
         # no host synchronisation and no allocation inside the step)
         side = torch.cuda.Stream(device=dev)
@@ -307,12 +309,6 @@ def main():
             cs.step(x)
         torch.cuda.synchronize()
 
-    def one_step():
-        if graph is not None:
-            graph.replay()
-        else:
-            cs.step(x)
-
     if args.copy_mib > 0:
         # a copy of known size: its FETCH_SIZE / WRITE_SIZE counters convert
         # the counters of the path's kernels to bytes
@@ -323,25 +319,39 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    for _ in range(args.warmup):
-        one_step()
-    torch.cuda.synchronize()
+    def timed(use_graph):
+        """W warm-up steps, then K timed steps (wall clock and per-step events)."""
+        def one_step():
+            if use_graph:
+                graph.replay()
+            else:
+                cs.step(x)
+        for _ in range(args.warmup):
+            one_step()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        ev[0].record(stream)
+        for k in range(args.steps):
+            one_step()
+            ev[k + 1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        return wall * 1e3 / args.steps, np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]), wall
+
+    # graph replay, and eager launches (where the assembly's structure runs
+    # on the scene's second stream beside the evaluation kernel)
+    modes = {}
+    if args.graph != 0:
+        modes["graph"] = timed(True)
+    if args.graph != 1:
+        modes["eager"] = timed(False)
+    launch = min(modes, key=lambda m: modes[m][0])
+    ms_per_step, step_ms, wall = modes[launch]
     st = cs.status(clear=True)
     assert not (st & (bfc.BF_S_CAND_OVERFLOW | bfc.BF_S_ACT_OVERFLOW | bfc.BF_S_BSR_OVERFLOW)), st
     assert cs.counts() == counts, (cs.counts(), counts)
-
-    # timed region: K whole steps
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    ev[0].record(stream)
-    for k in range(args.steps):
-        one_step()
-        ev[k + 1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    step_ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
-    ms_per_step = wall * 1e3 / args.steps
 
     # per-call durations on the launching stream (eager, after the timed region)
     calls = ["build_candidates", "filter_pairs", "eval_barrier", "assemble_grad_hess"]
@@ -359,8 +369,29 @@ def main():
             per[c].append(e[q].elapsed_time(e[q + 1]))
     call_ms = {c: float(np.mean(v)) for c, v in per.items()}
 
-    # roofline of the per-pair evaluation kernel (the one kernel of eval_barrier)
-    roof = eval_roofline(call_ms["eval_barrier"], n_act, kinds, "k_eval (eval_barrier)")
+    # roofline of the per-pair evaluation kernel: eval_barrier captured alone
+    # (under capture it launches only k_eval), replays timed with events
+    eval_graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream(device=dev)
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        cs.eval_barrier(x)
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(eval_graph):
+        cs.eval_barrier(x)
+    torch.cuda.synchronize()
+    reps = max(20, args.steps // 2)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    eval_graph.replay()
+    e0.record(stream)
+    for _ in range(reps):
+        eval_graph.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    eval_ms = e0.elapsed_time(e1) / reps
+    roof = eval_roofline(eval_ms, n_act, kinds, "k_eval (eval_barrier)")
+    roof["kernel_ms"] = eval_ms
 
     out = {
         "metric": "filtered contact pairs evaluated/s (dist+filter+grad+Hessian); p50/p99 latency",
@@ -382,10 +413,12 @@ def main():
                                                  if sc.name == "woven_patch" else sc.name),
                    "n_verts": sc.n_verts, "n_edges": sc.n_edges, "n_tris": sc.n_tris,
                    "N_bp": counts["n_bp"], "N_c": n_c, "N_filt": counts["n_filt"], "N_act": n_act,
-                   "nnzb": counts["nnzb"], "graph": bool(args.graph), "precision": args.prec},
+                   "nnzb": counts["nnzb"], "launch": launch, "precision": args.prec},
         "active_pairs_per_s": n_act / (ms_per_step * 1e-3),
         "call_ms": call_ms,
-        "setup_s": time.perf_counter() - t0 - wall,
+        "launch": launch,
+        "ms_per_step_by_launch": {m: v[0] for m, v in modes.items()},
+        "setup_s": time.perf_counter() - t0 - sum(v[2] for v in modes.values()),
         "roofline": roof,
     }
     if args.cpu_baseline:

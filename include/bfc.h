@@ -175,13 +175,22 @@ bf_status filter_pairs(bf_scene* s, const double* x_d, const bf_pairs* cand, bf_
                        void* stream);
 
 /* Barrier energy, gradient and PSD-projected Hessian of every active pair
- * (Eq. 2, Eq. 3; projection: eigenvalues clamped at zero). */
+ * (Eq. 2, Eq. 3; projection: eigenvalues clamped at zero).  While the
+ * evaluation kernel runs, the scene's internal stream (forked from `stream`
+ * and joined back into it before the call returns) builds the structure of
+ * the assembly for this active list (incidence lists, sorted columns of
+ * every row), so that assemble_grad_hess only adds values.  While `stream`
+ * is being captured into a graph there is no fork: assemble_grad_hess then
+ * builds the structure itself. */
 bf_status eval_barrier(bf_scene* s, const double* x_d, const bf_active* act, bf_local* out,
                        void* stream);
 
 /* Assembly: E_d[1] = sum of pair energies (+inf if any pair is infeasible),
  * g_d[V,3] = sum of pair gradients, H = sum of pair Hessian blocks over the
- * 4x4 vertex blocks of every feasible active pair's stencil. */
+ * 4x4 vertex blocks of every feasible active pair's stencil.  loc must hold
+ * what this scene's last eval_barrier wrote for the same active list (the
+ * energy total is taken from that call's per-tile sums).  Every sum runs in a
+ * fixed order: results are bitwise repeatable. */
 bf_status assemble_grad_hess(bf_scene* s, const bf_active* act, const bf_local* loc, double* E_d,
                              double* g_d, bf_bsr* H, void* stream);
 

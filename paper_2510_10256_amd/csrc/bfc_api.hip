@@ -33,6 +33,12 @@ struct bf_scene {
   std::vector<void*> stage_allocs;  // narrow-phase staging (regrown by reserve)
   int pq = 4;                       // threads per broad-phase query (tunable)
   hipStream_t last = nullptr;
+  // eval_barrier runs the structural part of the assembly on `side`, beside
+  // the evaluation kernel; assemble_grad_hess then only adds the values
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool prepared = false;             // structure built for the active list at prepared_for
+  const void* prepared_for = nullptr;
 };
 
 namespace {
@@ -107,7 +113,7 @@ bf_status alloc_asm(bf_scene* s, long long act_cap) {
   A.inc = dalloc<int>(s->asm_allocs, 4 * act_cap, &e);
   A.colbuf = dalloc<int>(s->asm_allocs, 16 * act_cap, &e);
   A.rowcnt = dalloc<int>(s->asm_allocs, s->nv + 1, &e);
-  A.epart = dalloc<double>(s->asm_allocs, 256, &e);
+  A.epart = dalloc<double>(s->asm_allocs, (act_cap + 63) / 64 + 1, &e);
   A.scan_tmp = dalloc<int>(s->asm_allocs, scan_parts(s->nv + 1) + 16, &e);
   if (e != hipSuccess) return fail(BF_E_NOMEM, "bf_scene_reserve: device allocation failed");
   if (hipMemsetAsync(A.inc_cnt, 0, sizeof(int) * (s->nv + 1), g_alloc_stream) != hipSuccess ||
@@ -204,7 +210,6 @@ bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int
   W.placed_box = dalloc<Box>(s->allocs, ne + nt, &e);
   W.pair_cnt = dalloc<int>(s->allocs, nq, &e);
   W.pair_bsum = dalloc<int>(s->allocs, nq / 256 + 2, &e);
-  W.pair_boff = dalloc<int>(s->allocs, nq / 256 + 2, &e);
   W.scan_tmp = dalloc<int>(s->allocs, std::max(std::max(scan_parts(nscan), scan_parts(nv + 1)), scan_parts(nq)) + 16, &e);
   if (e != hipSuccess) {
     free_list(s->allocs);
@@ -325,7 +330,14 @@ bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int
   }
   bf_status r = alloc_asm(s, act_cap);
   if (r == BF_OK) r = alloc_stage(s, cand_cap);
+  if (r == BF_OK && ((he = hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking)) != hipSuccess ||
+                     (he = hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming)) != hipSuccess ||
+                     (he = hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming)) != hipSuccess))
+    r = fail_hip(he, "bf_scene_create: side stream");
   if (r != BF_OK) {
+    if (s->ev_join) (void)hipEventDestroy(s->ev_join);
+    if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+    if (s->side) (void)hipStreamDestroy(s->side);
     free_list(s->asm_allocs);
     free_list(s->stage_allocs);
     free_list(s->allocs);
@@ -351,10 +363,14 @@ bf_status bf_scene_reserve(bf_scene* s, int64_t cand_cap, int64_t act_cap) {
 
 bf_status bf_scene_destroy(bf_scene* s) {
   if (!s) return BF_OK;
-  // freed in stream order after the work last enqueued for the scene
+  // freed in stream order after the work last enqueued for the scene (work
+  // on the side stream always joins back into that stream)
   free_list(s->asm_allocs, s->last);
   free_list(s->stage_allocs, s->last);
   free_list(s->allocs, s->last);
+  if (s->ev_join) (void)hipEventDestroy(s->ev_join);
+  if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+  if (s->side) (void)hipStreamDestroy(s->side);
   delete s;
   return BF_OK;
 }
@@ -390,6 +406,7 @@ bf_status filter_pairs(bf_scene* s, const double* x_d, const bf_pairs* cand, bf_
     return fail(BF_E_CAPACITY, "filter_pairs: candidate capacity exceeds the scene reserve (bf_scene_reserve)");
   hipStream_t st = (hipStream_t)stream;
   s->last = st;
+  s->prepared = false;
   run_narrow(dev_view(s), x_d, cand->i_d, cand->j_d, cand->type_d, (const long long*)cand->count_d, cand->cap, s->sw,
              act->p.i_d, act->p.j_d, act->p.type_d, act->code_d, act->flags_d, act->dist_d, act->p.cap,
              (long long*)act->p.count_d, (long long*)act->counters_d, s->d_status, st);
@@ -403,9 +420,34 @@ bf_status eval_barrier(bf_scene* s, const double* x_d, const bf_active* act, bf_
   if (out->cap < act->p.cap) return fail(BF_E_CAPACITY, "eval_barrier: local capacity below active capacity");
   hipStream_t st = (hipStream_t)stream;
   s->last = st;
-  run_eval(dev_view(s), x_d, act->p.i_d, act->p.j_d, act->p.type_d, act->code_d, act->flags_d,
-           (const long long*)act->p.count_d, act->p.cap, out->E_d, out->G_d, out->H_d, st);
-  hipError_t he = hipGetLastError();
+  const SceneDev S = dev_view(s);
+  hipError_t he = hipSuccess;
+  // the assembly's structure needs the active list only: build it on the
+  // side stream while the evaluation kernel runs, join before returning.
+  // Not while the stream is being captured into a graph: a batch capture that
+  // forked the side stream from inside a lane crashed in the runtime, so
+  // captured steps build the structure in assemble_grad_hess instead.
+  hipStreamCaptureStatus cap_status = hipStreamCaptureStatusNone;
+  if ((he = hipStreamIsCapturing(st, &cap_status)) != hipSuccess) return fail_hip(he, "eval_barrier");
+  const bool fits = act->p.cap <= s->act_cap;
+  const bool fork = fits && cap_status == hipStreamCaptureStatusNone && act->flags_d && act->p.i_d &&
+                    act->p.j_d && act->p.type_d;
+  if (fork) {
+    if ((he = hipEventRecord(s->ev_fork, st)) != hipSuccess || (he = hipStreamWaitEvent(s->side, s->ev_fork, 0)))
+      return fail_hip(he, "eval_barrier: fork");
+    run_asm_structure(S, act->p.i_d, act->p.j_d, act->p.type_d, act->flags_d, (const long long*)act->p.count_d,
+                      act->p.cap, s->aw, s->side);
+  }
+  run_eval(S, x_d, act->p.i_d, act->p.j_d, act->p.type_d, act->code_d, act->flags_d,
+           (const long long*)act->p.count_d, act->p.cap, out->E_d, out->G_d, out->H_d, fits ? s->aw.epart : nullptr,
+           st);
+  if (fork) {
+    if ((he = hipEventRecord(s->ev_join, s->side)) != hipSuccess || (he = hipStreamWaitEvent(st, s->ev_join, 0)))
+      return fail_hip(he, "eval_barrier: join");
+    s->prepared = true;
+    s->prepared_for = act->p.i_d;
+  }
+  he = hipGetLastError();
   return he == hipSuccess ? BF_OK : fail_hip(he, "eval_barrier");
 }
 
@@ -418,9 +460,14 @@ bf_status assemble_grad_hess(bf_scene* s, const bf_active* act, const bf_local* 
     return fail(BF_E_CAPACITY, "assemble_grad_hess: active capacity exceeds the scene reserve (bf_scene_reserve)");
   hipStream_t st = (hipStream_t)stream;
   s->last = st;
-  run_assemble(dev_view(s), act->p.i_d, act->p.j_d, act->p.type_d, act->flags_d, (const long long*)act->p.count_d,
-               act->p.cap, loc->E_d, loc->G_d, loc->H_d, E_d, g_d, H->row_ptr_d, H->col_d, H->val_d, H->cap,
-               (long long*)H->nnzb_d, s->aw, s->d_status, st);
+  const SceneDev S = dev_view(s);
+  if (!(s->prepared && s->prepared_for == act->p.i_d))
+    run_asm_structure(S, act->p.i_d, act->p.j_d, act->p.type_d, act->flags_d, (const long long*)act->p.count_d,
+                      act->p.cap, s->aw, st);
+  s->prepared = false;
+  run_asm_values(S, act->p.i_d, act->p.j_d, act->p.type_d, (const long long*)act->p.count_d, act->p.cap, loc->G_d,
+                 loc->H_d, E_d, g_d, H->row_ptr_d, H->col_d, H->val_d, H->cap, (long long*)H->nnzb_d, s->aw,
+                 s->d_status, st);
   hipError_t he = hipGetLastError();
   return he == hipSuccess ? BF_OK : fail_hip(he, "assemble_grad_hess");
 }

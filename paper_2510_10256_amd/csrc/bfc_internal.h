@@ -56,7 +56,6 @@ struct BroadWs {
   Box* sorted_box;   // [NS]
   int* pair_cnt;     // [NQ * PQ_MAX] pairs per (query, cell subset)
   int* pair_bsum;    // [work-groups + 1] pairs per work-group of the count pass
-  int* pair_boff;    // [work-groups + 1] their exclusive scan
   int* scan_tmp;     // [scan partials]
   int max_cells;
 };
@@ -81,7 +80,7 @@ struct AsmWs {
   int* inc;       // [4 * act_cap] entries 4k + s grouped by vertex
   int* colbuf;    // [16 * act_cap] stencil vertices of each entry's pair (row columns, sorted per row)
   int* rowcnt;    // [V + 1] distinct columns per row
-  double* epart;  // [256] energy partial sums
+  double* epart;  // [act_cap / 64 + 1] energy of each 64-pair tile of the evaluation
   int* scan_tmp;
 };
 

@@ -31,16 +31,20 @@ void run_narrow(const SceneDev& S, const double* x, const int* ci, const int* cj
 // Per-pair barrier, gradient and projected Hessian.
 void run_eval(const SceneDev& S, const double* x, const int* ai, const int* aj, const unsigned char* at,
               const unsigned char* acode, const unsigned char* aflags, const long long* act_count, long long acap,
-              double* E, double* G, double* H, hipStream_t st);
+              double* E, double* G, double* H, double* epart, hipStream_t st);
 
-// Energy sum, gradient and BSR Hessian.
-void run_assemble(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,
-                  const unsigned char* aflags, const long long* act_count, long long acap, const double* E,
-                  const double* G, const double* H, double* E_out, double* g, int* row_ptr, int* col, double* val,
-                  long long bsr_cap, long long* nnzb, const AsmWs& A, unsigned* status, hipStream_t st);
+// Assembly, structural part: needs the active list only (incidence lists,
+// sorted entries, distinct columns per row).
+void run_asm_structure(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,
+                       const unsigned char* aflags, const long long* act_count, long long acap, const AsmWs& A,
+                       hipStream_t st);
 
-// Connected components (numbered by smallest vertex); synchronous.  Returns
-// the number of components, or -1 on a HIP error.
+// Assembly, numerical part: row pointers, blocks, gradient and energy.
+void run_asm_values(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,
+                    const long long* act_count, long long acap, const double* G, const double* H, double* E_out,
+                    double* g, int* row_ptr, int* col, double* val, long long bsr_cap, long long* nnzb,
+                    const AsmWs& A, unsigned* status, hipStream_t st);
+
 int run_components(const SceneDev& S, int* lab, int* flag, int* scan, int* comp, int* scan_tmp, int* d_changed,
                    hipStream_t st);
 

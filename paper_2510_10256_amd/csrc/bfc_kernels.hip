@@ -4,7 +4,8 @@
 //   narrow phase  : k_narrow, scan, k_compact (distance, filter of Eq. 4, exact thresholds,
 //                   ballot compaction by distance kind)
 //   evaluation    : k_eval        (Eq. 2/3 barrier, derivatives, PSD projection)
-//   assembly      : k_esum*, k_grad, k_asm_*
+//   assembly      : k_inc_count (with the energy partials), scan, k_inc_fill,
+//                   k_row_a / k_row_a_big, scan, k_row_b / k_row_b_big
 //   precompute    : k_cc_*, k_refmin (components and d_min, Sec. 3.2)
 #include <algorithm>
 
@@ -47,6 +48,16 @@ template <class T> __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// Sum across the wave in a fixed order (lane i adds lane i + o); lane 0 has the total.
+__device__ __forceinline__ void wave_ordered_sum3(double& x, double& y, double& z) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    double tx = __shfl_down(x, o, 64), ty = __shfl_down(y, o, 64), tz = __shfl_down(z, o, 64);
+    if ((lane & (2 * o - 1)) == 0) { x += tx; y += ty; z += tz; }
+  }
+}
+
 // exclusive scan across a block of 256 threads (4 waves)
 __device__ __forceinline__ int block_excl_scan256(int v, int* total) {
   __shared__ int ws[4];
@@ -64,6 +75,17 @@ __device__ __forceinline__ int block_excl_scan256(int v, int* total) {
   __syncthreads();
   if (total) *total = tot;
   return off + x - v;
+}
+
+// sum across a block of 256 threads (4 waves); every thread gets the total
+__device__ __forceinline__ long long block_sum256(long long v) {
+  __shared__ long long ws[4];
+  v = wave_sum(v);
+  if (lane_id() == 0) ws[threadIdx.x >> 6] = v;
+  __syncthreads();
+  long long t = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+  __syncthreads();
+  return t;
 }
 
 // ---------------------------------------------------------------------------
@@ -500,15 +522,21 @@ __global__ __launch_bounds__(256) void k_pair_count(SceneDev S, int nquery, cons
 template <int PQ>
 __global__ __launch_bounds__(256) void k_pair_emit(SceneDev S, int nquery, const Box* box, const Grid* gp,
                                                    const int* cell_start, const int* sorted_id, const Box* sorted_box,
-                                                   double hf, const int* cnt, const int* boff, int* oi, int* oj,
+                                                   double hf, const int* cnt, const int* bsum, int* oi, int* oj,
                                                    unsigned char* ot, long long cap, long long* count,
                                                    unsigned* status) {
   Grid g = *gp;
   int nt = nquery * PQ;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *count = (long long)boff[gridDim.x];
+  // this block's offset: the pairs of all earlier blocks of the count pass
+  // (block 0 also sums them all: the candidate count)
+  const int upto = blockIdx.x == 0 ? (int)gridDim.x : (int)blockIdx.x;
+  long long part = 0;
+  for (int q = threadIdx.x; q < upto; q += blockDim.x) part += bsum[q];
+  const long long before = block_sum256(part);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *count = before;
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   int c = t < nt ? cnt[t] : 0;
-  int off = boff[blockIdx.x] + block_excl_scan256(c, nullptr);
+  int off = (blockIdx.x == 0 ? 0 : (int)before) + block_excl_scan256(c, nullptr);
   if (c == 0) return;
   int qtype, qid, qv[2];
   Box qb;
@@ -759,7 +787,7 @@ template <bool MIXED>
 __global__ __launch_bounds__(64) void k_eval(SceneDev S, const double* x, const int* ai, const int* aj,
                                              const unsigned char* at, const unsigned char* acode,
                                              const unsigned char* aflags, const unsigned long long* act_count,
-                                             long long acap, double* E, double* G, double* H) {
+                                             long long acap, double* E, double* G, double* H, double* epart) {
   __shared__ double tE[64], tG[64 * 12], tH[64 * 78];
   long long n = (long long)*act_count;
   if (n > acap) n = acap;
@@ -785,6 +813,11 @@ __global__ __launch_bounds__(64) void k_eval(SceneDev S, const double* x, const 
     __syncthreads();
     int rows = (int)min((long long)64, n - k0);
     if (lane < rows) E[k0 + lane] = tE[lane];
+    {  // the tile's energy, summed in a fixed order (partials of the total)
+      double e = lane < rows ? tE[lane] : 0.0, y = 0.0, z = 0.0;
+      wave_ordered_sum3(e, y, z);
+      if (lane == 0 && epart) epart[k0 / 64] = e;
+    }
     for (int q = lane; q < rows * 12; q += 64) G[12 * k0 + q] = tG[q];
     for (int q = lane; q < rows * 144; q += 64) {  // full 12 x 12 rows from the packed tile
       const int r = q / 144, e = q - 144 * r, i = e / 12, j = e - 12 * i;
@@ -803,28 +836,7 @@ __global__ __launch_bounds__(64) void k_eval(SceneDev S, const double* x, const 
 // taken in increasing entry order, so the result does not depend on thread
 // timing.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_esum(const double* E, const unsigned long long* act_count, long long acap,
-                                              double* part) {
-  long long n = (long long)*act_count;
-  if (n > acap) n = acap;
-  double s = 0.0;
-  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += grid_stride()) s += E[k];
-  s = wave_sum(s);
-  __shared__ double ws[4];
-  if (lane_id() == 0) ws[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) part[blockIdx.x] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
-}
-__global__ __launch_bounds__(256) void k_esum_final(const double* part, int nparts, double* out) {
-  double s = 0.0;
-  for (int k = threadIdx.x; k < nparts; k += blockDim.x) s += part[k];
-  s = wave_sum(s);
-  __shared__ double ws[4];
-  if (lane_id() == 0) ws[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) *out = (ws[0] + ws[1]) + (ws[2] + ws[3]);
-}
-
+// Incidence counts of the feasible active pairs' stencil vertices.
 __global__ __launch_bounds__(256) void k_inc_count(SceneDev S, const int* ai, const int* aj, const unsigned char* at,
                                                    const unsigned char* aflags, const unsigned long long* act_count,
                                                    long long acap, int* inc_cnt) {
@@ -837,6 +849,17 @@ __global__ __launch_bounds__(256) void k_inc_count(SceneDev S, const int* ai, co
 #pragma unroll
     for (int s = 0; s < 4; ++s) atomicAdd(&inc_cnt[v[s]], 1);
   }
+}
+
+// Total energy from the per-tile partials, in a fixed order (one wave).
+__device__ __forceinline__ void energy_total(const double* epart, long long ntiles, double* E_out) {
+  const int lane = lane_id();
+  const long long per = (ntiles + 63) / 64;
+  double e = 0.0;
+  for (long long q = lane * per; q < ntiles && q < (lane + 1) * per; ++q) e += epart[q];
+  double y = 0.0, z = 0.0;
+  wave_ordered_sum3(e, y, z);
+  if (lane == 0) *E_out = e;
 }
 
 // scatter the entries into their vertex segments; returns the counts to zero
@@ -925,16 +948,6 @@ __device__ __forceinline__ void wave_sort128(int& a0, int& a1) {
     }
 }
 
-// Sum across the wave in a fixed order (lane i adds lane i + o); lane 0 has the total.
-__device__ __forceinline__ void wave_ordered_sum3(double& x, double& y, double& z) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    double tx = __shfl_down(x, o, 64), ty = __shfl_down(y, o, 64), tz = __shfl_down(z, o, 64);
-    if ((lane & (2 * o - 1)) == 0) { x += tx; y += ty; z += tz; }
-  }
-}
-
 // Insert key into an LDS open-addressing set of T slots (T a power of two
 // larger than or equal to the number of distinct keys ever inserted).
 __device__ __forceinline__ void set_insert(int* tab, int T, int key) {
@@ -954,34 +967,31 @@ __device__ void isort_global(int* a, int m) {
   }
 }
 
-// One lane, global memory: sort the entries, sum the gradient, store the
-// distinct sorted columns.
-__device__ void row_a_serial(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at, int v, int b,
-                             int m, int* inc, const double* G, double* g, int* cb, int* rowcnt) {
+// One lane, global memory: sort the entries and store the distinct sorted
+// columns; *count = their number.
+__device__ void row_a_serial(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at, int b, int m,
+                             int* inc, int* cb, int* count) {
   isort_global(inc + b, m);
-  double gx = 0.0, gy = 0.0, gz = 0.0;
   for (int q = 0; q < m; ++q) {
-    int e = inc[b + q], k = e >> 2, s = e & 3;
-    gx += G[12LL * k + 3 * s]; gy += G[12LL * k + 3 * s + 1]; gz += G[12LL * k + 3 * s + 2];
+    int k = inc[b + q] >> 2;
     int vv[4];
     pair_verts(S, at[k], ai[k], aj[k], vv);
     for (int c = 0; c < 4; ++c) cb[4 * q + c] = vv[c];
   }
-  g[3 * v] = gx; g[3 * v + 1] = gy; g[3 * v + 2] = gz;
   isort_global(cb, 4 * m);
   int u = 0;
   for (int q = 0; q < 4 * m; ++q)
     if (q == 0 || cb[q] != cb[q - 1]) cb[u++] = cb[q];
-  rowcnt[v] = u;
+  *count = u;
 }
 
-// Pass A, rows with m <= ROW_M, one wave per row: sort the row's incidence
-// entries (so every sum below runs in a fixed order), sum its gradient,
-// and store its distinct columns (the stencil vertices of its pairs) sorted
-// at colbuf[4 * inc_off[v] ...]; rowcnt[v] = their number.
+// Pass A (structure; needs the active list only), rows with m <= ROW_M, one
+// wave per row: sort the row's incidence entries (so every sum of pass B
+// runs in a fixed order) and store its distinct columns (the stencil
+// vertices of its pairs) sorted at colbuf[4 * inc_off[v] ...]; rowcnt[v] =
+// their number.
 __global__ __launch_bounds__(64) void k_row_a(SceneDev S, const int* ai, const int* aj, const unsigned char* at,
-                                              const int* inc_off, int* inc, const double* G, double* g, int* colbuf,
-                                              int* rowcnt) {
+                                              const int* inc_off, int* inc, int* colbuf, int* rowcnt) {
   __shared__ int ent[ROW_M];
   __shared__ int tab[ROW_M_TAB];
   const int lane = threadIdx.x;
@@ -994,16 +1004,12 @@ __global__ __launch_bounds__(64) void k_row_a(SceneDev S, const int* ai, const i
       // (4q + t) & 63, register (4q + t) >> 6
       int e = lane < m ? inc[b + lane] : PAD;
       e = wave_sort64(e);
-      double gx = 0.0, gy = 0.0, gz = 0.0;
       int vv[4] = {PAD, PAD, PAD, PAD};
       if (lane < m) {
         inc[b + lane] = e;
-        const int k = e >> 2, s = e & 3;
-        gx = G[12LL * k + 3 * s]; gy = G[12LL * k + 3 * s + 1]; gz = G[12LL * k + 3 * s + 2];
+        const int k = e >> 2;
         pair_verts(S, at[k], ai[k], aj[k], vv);
       }
-      wave_ordered_sum3(gx, gy, gz);
-      if (lane == 0) { g[3 * v] = gx; g[3 * v + 1] = gy; g[3 * v + 2] = gz; }
       const int t = lane & 3, q0 = lane >> 2, q1 = 16 + (lane >> 2);
       int w0 = __shfl(vv[0], q0, 64), w1 = __shfl(vv[1], q0, 64), w2 = __shfl(vv[2], q0, 64),
           w3 = __shfl(vv[3], q0, 64);
@@ -1030,14 +1036,6 @@ __global__ __launch_bounds__(64) void k_row_a(SceneDev S, const int* ai, const i
     for (int q = lane; q < T; q += 64) tab[q] = EMPTY;
     __syncthreads();
     team_bitonic<64>(ent, Pm);
-    const int per = (m + 63) / 64;  // gradient: contiguous runs, combined in lane order
-    double gx = 0.0, gy = 0.0, gz = 0.0;
-    for (int q = lane * per; q < m && q < (lane + 1) * per; ++q) {
-      int e = ent[q], k = e >> 2, s = e & 3;
-      gx += G[12LL * k + 3 * s]; gy += G[12LL * k + 3 * s + 1]; gz += G[12LL * k + 3 * s + 2];
-    }
-    wave_ordered_sum3(gx, gy, gz);
-    if (lane == 0) { g[3 * v] = gx; g[3 * v + 1] = gy; g[3 * v + 2] = gz; }
     for (int q = lane; q < m; q += 64) {
       int e = ent[q], k = e >> 2;
       inc[b + q] = e;
@@ -1081,13 +1079,11 @@ __device__ __forceinline__ int big_rows(const int* inc_off, int nv, int* list, i
 }
 
 __global__ __launch_bounds__(256) void k_row_a_big(SceneDev S, const int* ai, const int* aj, const unsigned char* at,
-                                                   const int* inc_off, int* inc, const double* G, double* g,
-                                                   int* colbuf, int* rowcnt) {
+                                                   const int* inc_off, int* inc, int* colbuf, int* rowcnt) {
   __shared__ int ent[ROW_H];
   __shared__ int tab[ROW_H_TAB];
   __shared__ int list[256];
-  __shared__ double gs[4][3];
-  const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
+  const int tid = threadIdx.x;
   const int per = (S.nv - (int)blockIdx.x + (int)gridDim.x - 1) / (int)gridDim.x;
   for (int base = 0; base < per; base += 256) {
     const int nbig = big_rows(inc_off, S.nv, list, base);
@@ -1096,7 +1092,7 @@ __global__ __launch_bounds__(256) void k_row_a_big(SceneDev S, const int* ai, co
       const int b = inc_off[v], m = inc_off[v + 1] - b;
       int* cb = colbuf + 4LL * b;
       if (m > ROW_H) {
-        if (tid == 0) row_a_serial(S, ai, aj, at, v, b, m, inc, G, g, cb, rowcnt);
+        if (tid == 0) row_a_serial(S, ai, aj, at, b, m, inc, cb, rowcnt + v);
         __syncthreads();
         continue;
       }
@@ -1106,14 +1102,6 @@ __global__ __launch_bounds__(256) void k_row_a_big(SceneDev S, const int* ai, co
       for (int q = tid; q < T; q += 256) tab[q] = EMPTY;
       __syncthreads();
       team_bitonic<256>(ent, Pm);
-      const int run = (m + 255) / 256;
-      double gx = 0.0, gy = 0.0, gz = 0.0;
-      for (int q = tid * run; q < m && q < (tid + 1) * run; ++q) {
-        int e = ent[q], k = e >> 2, s = e & 3;
-        gx += G[12LL * k + 3 * s]; gy += G[12LL * k + 3 * s + 1]; gz += G[12LL * k + 3 * s + 2];
-      }
-      wave_ordered_sum3(gx, gy, gz);
-      if (lane == 0) { gs[w][0] = gx; gs[w][1] = gy; gs[w][2] = gz; }
       for (int q = tid; q < m; q += 256) {
         int e = ent[q], k = e >> 2;
         inc[b + q] = e;
@@ -1123,8 +1111,6 @@ __global__ __launch_bounds__(256) void k_row_a_big(SceneDev S, const int* ai, co
         for (int c = 0; c < 4; ++c) set_insert(tab, T, vv[c]);
       }
       __syncthreads();
-      if (tid == 0)
-        for (int a = 0; a < 3; ++a) g[3 * v + a] = ((gs[0][a] + gs[1][a]) + gs[2][a]) + gs[3][a];
       int u = 0;
       for (int c = 0; c < T; c += 256) {
         int x = tab[c + tid];
@@ -1145,14 +1131,6 @@ __global__ __launch_bounds__(256) void k_row_a_big(SceneDev S, const int* ai, co
   }
 }
 
-__global__ void k_asm_nnzb(const int* row_ptr, int nv, long long* nnzb, long long cap, unsigned* status) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    long long t = row_ptr[nv];
-    *nnzb = t;
-    if (t > cap) atomicOr(status, (unsigned)BF_S_BSR_OVERFLOW);
-  }
-}
-
 // Slot (0..3) of vertex c in a pair's stencil, -1 if absent.
 __device__ __forceinline__ int slot_of(const int* vv, int c) {
   return vv[0] == c ? 0 : vv[1] == c ? 1 : vv[2] == c ? 2 : vv[3] == c ? 3 : -1;
@@ -1166,10 +1144,13 @@ __device__ __forceinline__ int slot_of(const int* vv, int c) {
 // blocks of its columns from LDS, entries in sorted order.
 template <int NT>
 __device__ __forceinline__ void row_b(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,
-                                      const int* inc, int b, int m, const int* cb, int r0, int u, const double* H,
-                                      int* col, double* val, int* vs, double* band) {
+                                      const int* inc, int b, int m, const int* cb, int r0, int u, const double* G,
+                                      const double* H, double* grow, int* col, double* val, int* vs, double* band,
+                                      double* gw) {
   constexpr int CH = NT / 2;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = lane_id();
+  double gsum[3] = {0.0, 0.0, 0.0};  // the row's gradient (thread 0), chunk by chunk in entry order
+  if (m == 0 && tid == 0) grow[0] = grow[1] = grow[2] = 0.0;
   for (int cbase = 0; cbase < u; cbase += 2 * NT) {
     const int ca = cbase + tid < u ? cb[cbase + tid] : EMPTY;
     const int cz = cbase + NT + tid < u ? cb[cbase + NT + tid] : EMPTY;
@@ -1177,6 +1158,7 @@ __device__ __forceinline__ void row_b(const SceneDev& S, const int* ai, const in
     for (int qc = 0; qc < m; qc += CH) {
       const int nq = min(CH, m - qc);
       const int q = tid >> 1, half = tid & 1;
+      double gx = 0.0, gy = 0.0, gz = 0.0;
       if (q < nq) {
         const int e = inc[b + qc + q], k = e >> 2;
         const double* src = H + 144LL * k + 36 * (e & 3) + 18 * half;
@@ -1188,9 +1170,23 @@ __device__ __forceinline__ void row_b(const SceneDev& S, const int* ai, const in
           pair_verts(S, at[k], ai[k], aj[k], vv);
 #pragma unroll
           for (int c = 0; c < 4; ++c) vs[4 * q + c] = vv[c];
+          if (cbase == 0) {
+            const double* gk = G + 12LL * k + 3 * (e & 3);
+            gx = gk[0]; gy = gk[1]; gz = gk[2];
+          }
+        }
+      }
+      if (cbase == 0) {  // gradient of this chunk: fixed-order sums over the lanes, then the waves
+        wave_ordered_sum3(gx, gy, gz);
+        if (NT == 64) {
+          if (tid == 0) { gsum[0] += gx; gsum[1] += gy; gsum[2] += gz; }
+        } else {
+          if (lane == 0) { gw[3 * (tid >> 6)] = gx; gw[3 * (tid >> 6) + 1] = gy; gw[3 * (tid >> 6) + 2] = gz; }
         }
       }
       __syncthreads();
+      if (NT != 64 && cbase == 0 && tid == 0)
+        for (int a = 0; a < 3; ++a) gsum[a] += ((gw[a] + gw[3 + a]) + gw[6 + a]) + gw[9 + a];
       for (int r = 0; r < nq; ++r) {
         const int w[4] = {vs[4 * r], vs[4 * r + 1], vs[4 * r + 2], vs[4 * r + 3]};
         const double* bq = band + 36 * r;
@@ -1210,6 +1206,7 @@ __device__ __forceinline__ void row_b(const SceneDev& S, const int* ai, const in
       }
       __syncthreads();
     }
+    if (cbase == 0 && tid == 0) { grow[0] = gsum[0]; grow[1] = gsum[1]; grow[2] = gsum[2]; }
     if (ca != EMPTY) {
       col[r0 + cbase + tid] = ca;
 #pragma unroll
@@ -1225,26 +1222,42 @@ __device__ __forceinline__ void row_b(const SceneDev& S, const int* ai, const in
 
 // Pass B, rows with m <= ROW_M, one wave per row.
 __global__ __launch_bounds__(64) void k_row_b(SceneDev S, const int* ai, const int* aj, const unsigned char* at,
-                                              const int* inc_off, const int* inc, const int* colbuf, const double* H,
-                                              const int* row_ptr, int* col, double* val, long long cap) {
+                                              const int* inc_off, const int* inc, const int* colbuf, const double* G,
+                                              const double* H, double* g, const int* row_ptr, int* col, double* val,
+                                              long long cap, long long* nnzb, unsigned* status,
+                                              const unsigned long long* act_count, long long acap,
+                                              const double* epart, double* E_out) {
   __shared__ int vs[4 * 32];
   __shared__ double band[32 * 36];
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) {
+      const long long t = row_ptr[S.nv];
+      *nnzb = t;
+      if (t > cap) atomicOr(status, (unsigned)BF_S_BSR_OVERFLOW);
+    }
+    // energy: the per-tile sums of the evaluation kernel, in tile order
+    long long n = (long long)*act_count;
+    if (n > acap) n = acap;
+    energy_total(epart, (n + 63) / 64, E_out);
+  }
   for (int v = blockIdx.x; v < S.nv; v += gridDim.x) {
     const int b = inc_off[v], m = inc_off[v + 1] - b;
     if (m > ROW_M) continue;  // block path
     const int r0 = row_ptr[v], r1 = row_ptr[v + 1];
-    if (r1 > cap) continue;   // overflow: reported by k_asm_nnzb
-    row_b<64>(S, ai, aj, at, inc, b, m, colbuf + 4LL * b, r0, r1 - r0, H, col, val, vs, band);
+    if (r1 > cap) continue;   // overflow: reported above
+    row_b<64>(S, ai, aj, at, inc, b, m, colbuf + 4LL * b, r0, r1 - r0, G, H, g + 3LL * v, col, val, vs, band,
+              nullptr);
   }
 }
 
 __global__ __launch_bounds__(256) void k_row_b_big(SceneDev S, const int* ai, const int* aj, const unsigned char* at,
                                                    const int* inc_off, const int* inc, const int* colbuf,
-                                                   const double* H, const int* row_ptr, int* col, double* val,
-                                                   long long cap) {
+                                                   const double* G, const double* H, double* g, const int* row_ptr,
+                                                   int* col, double* val, long long cap) {
   __shared__ int vs[4 * 128];
   __shared__ double band[128 * 36];
   __shared__ int list[256];
+  __shared__ double gw[12];
   const int per = (S.nv - (int)blockIdx.x + (int)gridDim.x - 1) / (int)gridDim.x;
   for (int base = 0; base < per; base += 256) {
     const int nbig = big_rows(inc_off, S.nv, list, base);
@@ -1253,7 +1266,8 @@ __global__ __launch_bounds__(256) void k_row_b_big(SceneDev S, const int* ai, co
       const int b = inc_off[v], m = inc_off[v + 1] - b;
       const int r0 = row_ptr[v], r1 = row_ptr[v + 1];
       if (r1 > cap) continue;  // uniform across the block
-      row_b<256>(S, ai, aj, at, inc, b, m, colbuf + 4LL * b, r0, r1 - r0, H, col, val, vs, band);
+      row_b<256>(S, ai, aj, at, inc, b, m, colbuf + 4LL * b, r0, r1 - r0, G, H, g + 3LL * v, col, val, vs, band,
+                 gw);
     }
     __syncthreads();
   }
@@ -1388,9 +1402,8 @@ static void launch_pairs(const SceneDev& S, int nquery, const BroadWs& W, int* o
   int nb = (nquery * PQ + 255) / 256;
   hipLaunchKernelGGL(k_pair_count<PQ>, dim3(nb), dim3(256), 0, st, S, nquery, W.box, W.grid, W.cell_start,
                      W.sorted_id, W.sorted_box, S.h, W.pair_cnt, W.pair_bsum);
-  scan_excl(W.pair_bsum, W.pair_boff, nullptr, nb + 1, W.scan_tmp, st);
   hipLaunchKernelGGL(k_pair_emit<PQ>, dim3(nb), dim3(256), 0, st, S, nquery, W.box, W.grid, W.cell_start,
-                     W.sorted_id, W.sorted_box, S.h, W.pair_cnt, W.pair_boff, oi, oj, ot, cap, count, status);
+                     W.sorted_id, W.sorted_box, S.h, W.pair_cnt, W.pair_bsum, oi, oj, ot, cap, count, status);
 }
 
 void run_broad(const SceneDev& S, const double* x, const BroadWs& W, int* oi, int* oj, unsigned char* ot,
@@ -1431,22 +1444,21 @@ void run_narrow(const SceneDev& S, const double* x, const int* ci, const int* cj
 
 void run_eval(const SceneDev& S, const double* x, const int* ai, const int* aj, const unsigned char* at,
               const unsigned char* acode, const unsigned char* aflags, const long long* act_count, long long acap,
-              double* E, double* G, double* H, hipStream_t st) {
+              double* E, double* G, double* H, double* epart, hipStream_t st) {
   if (S.mixed)
     hipLaunchKernelGGL(k_eval<true>, dim3(nblocks(acap, 64, 65535)), dim3(64), 0, st, S, x, ai, aj, at, acode,
-                       aflags, (const unsigned long long*)act_count, acap, E, G, H);
+                       aflags, (const unsigned long long*)act_count, acap, E, G, H, epart);
   else
     hipLaunchKernelGGL(k_eval<false>, dim3(nblocks(acap, 64, 65535)), dim3(64), 0, st, S, x, ai, aj, at, acode,
-                       aflags, (const unsigned long long*)act_count, acap, E, G, H);
+                       aflags, (const unsigned long long*)act_count, acap, E, G, H, epart);
 }
 
-void run_assemble(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,
-                  const unsigned char* aflags, const long long* act_count, long long acap, const double* E,
-                  const double* G, const double* H, double* E_out, double* g, int* row_ptr, int* col, double* val,
-                  long long bsr_cap, long long* nnzb, const AsmWs& A, unsigned* status, hipStream_t st) {
+static inline int big_grid_of(int nv) { return std::max(1, std::min((nv + 15) / 16, 4096)); }  // ~16 rows a block
+
+void run_asm_structure(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,
+                       const unsigned char* aflags, const long long* act_count, long long acap, const AsmWs& A,
+                       hipStream_t st) {
   const unsigned long long* nact = (const unsigned long long*)act_count;
-  hipLaunchKernelGGL(k_esum, dim3(256), dim3(256), 0, st, E, nact, acap, A.epart);
-  hipLaunchKernelGGL(k_esum_final, dim3(1), dim3(256), 0, st, A.epart, 256, E_out);
   // incidence counts are zero on entry: k_inc_fill returns them to zero
   hipLaunchKernelGGL(k_inc_count, dim3(nblocks(acap)), dim3(256), 0, st, S, ai, aj, at, aflags, nact, acap,
                      A.inc_cnt);
@@ -1454,17 +1466,22 @@ void run_assemble(const SceneDev& S, const int* ai, const int* aj, const unsigne
   hipLaunchKernelGGL(k_inc_fill, dim3(nblocks(acap)), dim3(256), 0, st, S, ai, aj, at, aflags, nact, acap, A.inc_cnt,
                      A.inc_off, A.inc);
   int rows_grid = (int)std::min(S.nv, 1 << 20);
-  int big_grid = (int)std::max(1, std::min((S.nv + 15) / 16, 4096));  // ~16 rows per block
-  hipLaunchKernelGGL(k_row_a, dim3(rows_grid), dim3(64), 0, st, S, ai, aj, at, A.inc_off, A.inc, G, g, A.colbuf,
-                     A.rowcnt);
-  hipLaunchKernelGGL(k_row_a_big, dim3(big_grid), dim3(256), 0, st, S, ai, aj, at, A.inc_off, A.inc, G, g, A.colbuf,
-                     A.rowcnt);
+  hipLaunchKernelGGL(k_row_a, dim3(rows_grid), dim3(64), 0, st, S, ai, aj, at, A.inc_off, A.inc, A.colbuf, A.rowcnt);
+  hipLaunchKernelGGL(k_row_a_big, dim3(big_grid_of(S.nv)), dim3(256), 0, st, S, ai, aj, at, A.inc_off, A.inc,
+                     A.colbuf, A.rowcnt);
+}
+
+void run_asm_values(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,
+                    const long long* act_count, long long acap, const double* G, const double* H, double* E_out,
+                    double* g, int* row_ptr, int* col, double* val, long long bsr_cap, long long* nnzb,
+                    const AsmWs& A, unsigned* status, hipStream_t st) {
+  const unsigned long long* nact = (const unsigned long long*)act_count;
   scan_excl(A.rowcnt, row_ptr, nullptr, S.nv + 1, A.scan_tmp, st);
-  hipLaunchKernelGGL(k_asm_nnzb, dim3(1), dim3(64), 0, st, row_ptr, S.nv, nnzb, bsr_cap, status);
-  hipLaunchKernelGGL(k_row_b, dim3(rows_grid), dim3(64), 0, st, S, ai, aj, at, A.inc_off, A.inc, A.colbuf, H, row_ptr,
-                     col, val, bsr_cap);
-  hipLaunchKernelGGL(k_row_b_big, dim3(big_grid), dim3(256), 0, st, S, ai, aj, at, A.inc_off, A.inc, A.colbuf, H,
-                     row_ptr, col, val, bsr_cap);
+  int rows_grid = (int)std::min(S.nv, 1 << 20);
+  hipLaunchKernelGGL(k_row_b, dim3(rows_grid), dim3(64), 0, st, S, ai, aj, at, A.inc_off, A.inc, A.colbuf, G, H, g,
+                     row_ptr, col, val, bsr_cap, nnzb, status, nact, acap, A.epart, E_out);
+  hipLaunchKernelGGL(k_row_b_big, dim3(big_grid_of(S.nv)), dim3(256), 0, st, S, ai, aj, at, A.inc_off, A.inc,
+                     A.colbuf, G, H, g, row_ptr, col, val, bsr_cap);
 }
 
 int run_components(const SceneDev& S, int* lab, int* flag, int* scan, int* comp, int* scan_tmp, int* d_changed,
