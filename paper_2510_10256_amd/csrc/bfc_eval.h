@@ -154,8 +154,6 @@ template <int N> __device__ __forceinline__ void psd_jacobi(double* A, double* P
     }
 }
 
-// Output helpers: packed upper triangle of the 12 x 12 Hessian.
-__device__ __forceinline__ int hix(int I, int J) { return I <= J ? I * 12 - (I * (I - 1)) / 2 + (J - I) : hix(J, I); }
 
 // Select one of four vertices without indexing a register array at run time
 // (which would place it in scratch memory).
@@ -186,51 +184,48 @@ __device__ __forceinline__ Chain chain_coeffs(double D, double a, double eta, do
   return ch;
 }
 
-// Row k of the per-pair outputs: E, G[12], packed H[78].
-struct OutRow {
-  double* E;
-  double* G;
-  double* H;
+// A pair's results: the energy, and the projected Hessian in the reduced
+// form it is computed in, from which hess_row() produces the rows of the
+// 12 x 12 matrix one at a time (the caller streams them out).  The gradient
+// is stored directly (G, 12 doubles).
+enum { H_ZERO = 0, H_PP = 1, H_PE = 2, H_TRI = 3 };
+struct PairOut {
+  double E;
+  int kind;      // H_*
+  int sl[3];     // PP: slots (s0, s1); PE: slots (point, e0, e1)
+  double A[45];  // TRI: projected 9 x 9 (upper); PE: projected 6 x 6 (upper, 21);
+                 // PP: r (3), eigenvalue along r, across r, 1 / D
 };
-__device__ __forceinline__ void zero_row(OutRow o) {
+__device__ __forceinline__ void zero_grad(double* G) {
 #pragma unroll
-  for (int q = 0; q < 12; ++q) o.G[q] = 0.0;
-#pragma unroll
-  for (int q = 0; q < 78; ++q) o.H[q] = 0.0;
+  for (int q = 0; q < 12; ++q) G[q] = 0.0;
 }
 
 // ---- PP: closed-form projection ------------------------------------------
 // H_y = c1 (2r)(2r)^T + 2 c2 I has eigenvalue kappa b'' along r and kappa b'/d
 // across it; the projection keeps the positive parts.
 __device__ __forceinline__ void eval_pp(const d3* P, int s0, int s1, double a, double eta, double kappa,
-                                        OutRow o) {
+                                        double* G, PairOut& h) {
   d3 r = pick4(P, s0) - pick4(P, s1);
   double D = dot(r, r);
   Chain ch = chain_coeffs(D, a, eta, kappa);
-  *o.E = ch.E;
-  zero_row(o);
+  h.E = ch.E;
+  zero_grad(G);
   if (ch.zero) return;
   double rr[3] = {r.x, r.y, r.z};
-  double lr = fmax(4.0 * ch.c1 * D + 2.0 * ch.c2, 0.0);  // eigenvalue along r
-  double lt = fmax(2.0 * ch.c2, 0.0);                    // eigenvalue across r
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     double g = 2.0 * ch.cg * rr[i];
-    o.G[3 * s0 + i] = g;
-    o.G[3 * s1 + i] = -g;
+    G[3 * s0 + i] = g;
+    G[3 * s1 + i] = -g;
   }
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      double m = (lr - lt) * rr[i] * rr[j] / D + (i == j ? lt : 0.0);
-      int I0 = 3 * s0 + i, I1 = 3 * s1 + i, J0 = 3 * s0 + j, J1 = 3 * s1 + j;
-      if (i <= j) {
-        o.H[hix(I0, J0)] = m;
-        o.H[hix(I1, J1)] = m;
-      }
-      o.H[hix(I0, J1)] = -m;  // s0 < s1 for every PP code, so (I0, J1) is in the upper triangle
-    }
+  h.kind = H_PP;
+  h.sl[0] = s0;
+  h.sl[1] = s1;
+  h.A[0] = r.x; h.A[1] = r.y; h.A[2] = r.z;
+  h.A[3] = fmax(4.0 * ch.c1 * D + 2.0 * ch.c2, 0.0);  // eigenvalue along r
+  h.A[4] = fmax(2.0 * ch.c2, 0.0);                    // eigenvalue across r
+  h.A[5] = 1.0 / D;
 }
 
 // ---- PE: 6 x 6 reduced system ----------------------------------------------
@@ -238,7 +233,7 @@ __device__ __forceinline__ void eval_pp(const d3* P, int s0, int s1, double a, d
 // w1 = (1, -1, 0)/sqrt2, w2 = (1, 1, -2)/sqrt6.  With y = (r, e) = Y x the
 // coupling b = Y W is [[sqrt2, 0], [1/sqrt2, -3/sqrt6]].
 __device__ __forceinline__ void eval_pe(const d3* P, int sp, int se0, int se1, double a, double eta,
-                                        double kappa, double tol2, OutRow o) {
+                                        double kappa, double tol2, double* G, PairOut& h) {
   const double S2 = 1.4142135623730951, IS2 = 0.70710678118654752, IS6 = 0.40824829046386302;
   d3 xp = pick4(P, sp), x0 = pick4(P, se0), x1 = pick4(P, se1);
   d3 r = xp - x0, e = x1 - x0;
@@ -246,9 +241,11 @@ __device__ __forceinline__ void eval_pe(const d3* P, int sp, int se0, int se1, d
   d3 c = cross(r, e);
   double D = dot(c, c) * im;
   Chain ch = chain_coeffs(D, a, eta, kappa);
-  *o.E = ch.E;
-  zero_row(o);
-  if (ch.zero) return;
+  h.E = ch.E;
+  if (ch.zero) {
+    zero_grad(G);
+    return;
+  }
   double rv[3] = {r.x, r.y, r.z}, ev[3] = {e.x, e.y, e.z};
   double gr[3], ge[3];
 #pragma unroll
@@ -285,33 +282,20 @@ __device__ __forceinline__ void eval_pe(const d3* P, int sp, int se0, int se1, d
           A[uix<6>(I, J)] = br[al] * br[bt] * Yrr[i][j] + br[al] * be[bt] * Yre[i][j] +
                             be[al] * br[bt] * Yre[j][i] + be[al] * be[bt] * Yee[i][j];
         }
-  double Ap[21];
-  psd_jacobi<6>(A, Ap, tol2);
+  psd_jacobi<6>(A, h.A, tol2);
+  // slot of the pair missing from the stencil gets a zero gradient
+  zero_grad(G);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {  // Y rows: r = (1, -1, 0), e = (0, -1, 1) on (p, e0, e1)
     double grx = ch.cg * gr[i], gex = ch.cg * ge[i];
-    o.G[3 * sp + i] = grx;
-    o.G[3 * se0 + i] = -grx - gex;
-    o.G[3 * se1 + i] = gex;
+    G[3 * sp + i] = grx;
+    G[3 * se0 + i] = -grx - gex;
+    G[3 * se1 + i] = gex;
   }
-  const double W[3][2] = {{IS2, IS6}, {-IS2, IS6}, {0.0, -2.0 * IS6}};
-  const int sl[3] = {sp, se0, se1};
-#pragma unroll
-  for (int u = 0; u < 3; ++u)
-#pragma unroll
-    for (int w = 0; w < 3; ++w)
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          if (3 * u + i > 3 * w + j) continue;  // each unordered entry once
-          double acc = 0.0;
-#pragma unroll
-          for (int al = 0; al < 2; ++al)
-#pragma unroll
-            for (int bt = 0; bt < 2; ++bt) acc += W[u][al] * W[w][bt] * Ap[uix<6>(3 * al + i, 3 * bt + j)];
-          o.H[hix(3 * sl[u] + i, 3 * sl[w] + j)] = acc;
-        }
+  h.kind = H_PE;
+  h.sl[0] = sp;
+  h.sl[1] = se0;
+  h.sl[2] = se1;
 }
 
 // ---- PT and EE: 9 x 9 reduced system --------------------------------------
@@ -321,7 +305,7 @@ __device__ __forceinline__ void eval_pe(const d3* P, int sp, int se0, int se1, d
 //   PT (r = p-t0, u = t1-t0, v = t2-t0):  r (0,1,1)  u (-1,1,0)  v (-1,0,1)
 //   EE (r = a0-b0, u = a1-a0, v = b1-b0): r (1,0,1)  u (0,-1,-1) v (0,-1,1)
 __device__ __forceinline__ void eval_tri(const d3* P, bool is_pt, double a, double eta, double kappa, double tol2,
-                                         OutRow o) {
+                                         double* G, PairOut& h) {
   d3 r, u, v;
   if (is_pt) {
     r = P[0] - P[1]; u = P[2] - P[1]; v = P[3] - P[1];
@@ -332,9 +316,9 @@ __device__ __forceinline__ void eval_tri(const d3* P, bool is_pt, double a, doub
   double s = dot(r, n), m = dot(n, n), im = 1.0 / m;
   double D = s * s * im;
   Chain ch = chain_coeffs(D, a, eta, kappa);
-  *o.E = ch.E;
+  h.E = ch.E;
   if (ch.zero) {
-    zero_row(o);
+    zero_grad(G);
     return;
   }
   double uu = dot(u, u), vv = dot(v, v), uv = dot(u, v);
@@ -397,42 +381,81 @@ __device__ __forceinline__ void eval_tri(const d3* P, bool is_pt, double a, doub
             }
           A[uix<9>(I, J)] = acc;
         }
-  double Ap[45];
-  psd_jacobi<9>(A, Ap, tol2);
+  psd_jacobi<9>(A, h.A, tol2);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     double gr = ch.cg * g[i], gu = ch.cg * g[3 + i], gv = ch.cg * g[6 + i];
     if (is_pt) {  // r = p - t0, u = t1 - t0, v = t2 - t0
-      o.G[i] = gr;
-      o.G[3 + i] = -gr - gu - gv;
-      o.G[6 + i] = gu;
-      o.G[9 + i] = gv;
+      G[i] = gr;
+      G[3 + i] = -gr - gu - gv;
+      G[6 + i] = gu;
+      G[9 + i] = gv;
     } else {      // r = a0 - b0, u = a1 - a0, v = b1 - b0
-      o.G[i] = gr - gu;
-      o.G[3 + i] = gu;
-      o.G[6 + i] = -gr - gv;
-      o.G[9 + i] = gv;
+      G[i] = gr - gu;
+      G[3 + i] = gu;
+      G[6 + i] = -gr - gv;
+      G[9 + i] = gv;
     }
   }
-  const float W[4][3] = {{0.5f, 0.5f, 0.5f}, {0.5f, -0.5f, -0.5f}, {-0.5f, 0.5f, -0.5f}, {-0.5f, -0.5f, 0.5f}};
+  h.kind = H_TRI;
+}
+
+// Row I (compile-time) of a pair's projected 12 x 12 Hessian, from its
+// reduced form: H = W A W^T with W the orthonormal basis of the translation
+// complement (Hadamard rows for four vertices, (1,-1,0)/sqrt2 and
+// (1,1,-2)/sqrt6 for point-edge), and the point-point closed form.
+template <int I> __device__ __forceinline__ void hess_row(const PairOut& h, double* out) {
+  constexpr int s = I / 3, i = I % 3;
 #pragma unroll
-  for (int st = 0; st < 4; ++st)
+  for (int q = 0; q < 12; ++q) out[q] = 0.0;
+  if (h.kind == H_TRI) {
+    constexpr float W[4][3] = {{0.5f, 0.5f, 0.5f}, {0.5f, -0.5f, -0.5f}, {-0.5f, 0.5f, -0.5f}, {-0.5f, -0.5f, 0.5f}};
+    double C[3][3];  // C[bt][j] = sum_al W[s][al] A[3al+i][3bt+j]
 #pragma unroll
-    for (int tt = st; tt < 4; ++tt)
+    for (int bt = 0; bt < 3; ++bt)
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double c = 0.0;
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          int I = 3 * st + i, J = 3 * tt + j;
-          if (I > J) continue;
-          double acc = 0.0;
+        for (int al = 0; al < 3; ++al) c += (double)W[s][al] * h.A[uix<9>(3 * al + i, 3 * bt + j)];
+        C[bt][j] = c;
+      }
 #pragma unroll
-          for (int al = 0; al < 3; ++al)
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
-            for (int bt = 0; bt < 3; ++bt)
-              acc += (double)(W[st][al] * W[tt][bt]) * Ap[uix<9>(3 * al + i, 3 * bt + j)];
-          o.H[hix(I, J)] = acc;
-        }
+      for (int j = 0; j < 3; ++j)
+        out[3 * t + j] = (double)W[t][0] * C[0][j] + (double)W[t][1] * C[1][j] + (double)W[t][2] * C[2][j];
+  } else if (h.kind == H_PE) {
+    const double IS2 = 0.70710678118654752, IS6 = 0.40824829046386302;
+    // local index (0, 1, 2) of a slot in the stencil (point, e0, e1); basis rows
+    // (1,-1,0)/sqrt2 and (1,1,-2)/sqrt6 over the local indices
+    auto w0 = [&](int slot) { return slot == h.sl[0] ? IS2 : slot == h.sl[1] ? -IS2 : 0.0; };
+    auto w1 = [&](int slot) { return slot == h.sl[0] || slot == h.sl[1] ? IS6 : slot == h.sl[2] ? -2.0 * IS6 : 0.0; };
+    const double ws0 = w0(s), ws1 = w1(s);
+    double C[2][3];
+#pragma unroll
+    for (int bt = 0; bt < 2; ++bt)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        C[bt][j] = ws0 * h.A[uix<6>(i, 3 * bt + j)] + ws1 * h.A[uix<6>(3 + i, 3 * bt + j)];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const double wt0 = w0(t), wt1 = w1(t);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) out[3 * t + j] = wt0 * C[0][j] + wt1 * C[1][j];
+    }
+  } else if (h.kind == H_PP) {
+    // blocks (s0,s0) = (s1,s1) = M, (s0,s1) = (s1,s0) = -M,
+    // M = (l_r - l_t) r r^T / D + l_t I
+    const double sr = s == h.sl[0] ? 1.0 : s == h.sl[1] ? -1.0 : 0.0;
+    const double ri = h.A[i], lr = h.A[3], lt = h.A[4], iD = h.A[5];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const double st = t == h.sl[0] ? sr : t == h.sl[1] ? -sr : 0.0;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) out[3 * t + j] = st * ((lr - lt) * ri * h.A[j] * iD + (i == j ? lt : 0.0));
+    }
+  }
 }
 
 // Evaluate one active pair with the sub-case `code` fixed by the narrow
@@ -441,17 +464,18 @@ __device__ __forceinline__ void eval_tri(const d3* P, bool is_pt, double a, doub
 // stay FP64 on both paths: FP32 derivative terms lose up to 1e-2 relative
 // accuracy for nearly parallel edges (successive turns of a coiled rod).
 template <bool MIXED>
-__device__ __forceinline__ void eval_pair(const d3* P, int code, double a, double eta, double kappa, OutRow o) {
+__device__ __forceinline__ void eval_pair(const d3* P, int code, double a, double eta, double kappa, double* G,
+                                          PairOut& h) {
   const double tol2 = MIXED ? 1e-14 : 1e-32;
   int kind = case_kind(code);
   if (kind == K_PT || kind == K_EE) {
-    eval_tri(P, kind == K_PT, a, eta, kappa, tol2, o);
+    eval_tri(P, kind == K_PT, a, eta, kappa, tol2, G, h);
     return;
   }
   int s0, s1, s2;
   case_slots(code, s0, s1, s2);
-  if (kind == K_PP) eval_pp(P, s0, s1, a, eta, kappa, o);
-  else eval_pe(P, s0, s1, s2, a, eta, kappa, tol2, o);
+  if (kind == K_PP) eval_pp(P, s0, s1, a, eta, kappa, G, h);
+  else eval_pe(P, s0, s1, s2, a, eta, kappa, tol2, G, h);
 }
 
 }  // namespace bfc

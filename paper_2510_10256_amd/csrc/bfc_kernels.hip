@@ -780,51 +780,69 @@ __global__ __launch_bounds__(256) void k_compact(StageWs W, int G, int* ai, int*
 // ---------------------------------------------------------------------------
 // Barrier evaluation (Eq. 2, Eq. 3) and PSD projection
 // ---------------------------------------------------------------------------
-// One wave per work-group; every lane evaluates one pair into its row of an
-// LDS tile (E, G[12], upper triangle of H), and the wave then writes the
-// tile's contiguous rows of E, G and the full 12 x 12 H with coalesced stores.
+// One wave per work-group, one pair per lane.  Each lane keeps its pair's
+// projected Hessian in reduced form (registers); the 12 rows of the 12 x 12
+// matrices of the tile's 64 pairs then go out one row at a time through a
+// small LDS buffer, as contiguous 96-byte segments (a 64 x 144 staging tile
+// would cut occupancy to three waves per CU; stores straight from each
+// lane's registers scatter every instruction over 64 cache lines).  The
+// energies of each 64-pair tile are summed in a fixed order into epart
+// (partials of the total).
+template <int I>
+__device__ __forceinline__ void flush_row(const PairOut& h, double* buf, double* H, long long k0, int rows) {
+  const int lane = threadIdx.x;
+  double r[12];
+  hess_row<I>(h, r);
+#pragma unroll
+  for (int j = 0; j < 12; ++j) buf[13 * lane + j] = r[j];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 12; ++q) {
+    const int v = lane + 64 * q, p = v / 12, j = v - 12 * p;
+    if (p < rows) H[144 * (k0 + p) + 12 * I + j] = buf[13 * p + j];
+  }
+  __syncthreads();
+}
+template <int I>
+__device__ __forceinline__ void flush_rows(const PairOut& h, double* buf, double* H, long long k0, int rows) {
+  flush_row<I>(h, buf, H, k0, rows);
+  if constexpr (I + 1 < 12) flush_rows<I + 1>(h, buf, H, k0, rows);
+}
+
 template <bool MIXED>
 __global__ __launch_bounds__(64) void k_eval(SceneDev S, const double* x, const int* ai, const int* aj,
                                              const unsigned char* at, const unsigned char* acode,
                                              const unsigned char* aflags, const unsigned long long* act_count,
                                              long long acap, double* E, double* G, double* H, double* epart) {
-  __shared__ double tE[64], tG[64 * 12], tH[64 * 78];
+  __shared__ double buf[64 * 13];
   long long n = (long long)*act_count;
   if (n > acap) n = acap;
   const int lane = threadIdx.x;
   for (long long k0 = (long long)blockIdx.x * 64; k0 < n; k0 += (long long)gridDim.x * 64) {
-    long long k = k0 + lane;
-    OutRow o{tE + lane, tG + 12 * lane, tH + 78 * lane};
+    const long long k = k0 + lane;
+    PairOut h;
+    h.E = 0.0;
+    h.kind = H_ZERO;
     if (k < n) {
       int type = at[k], code = acode[k], fl = aflags[k];
       int v[4];
       pair_verts(S, type, ai[k], aj[k], v);
       if (fl & BF_F_INFEASIBLE) {
-        *o.E = INFINITY;
-        zero_row(o);
+        h.E = INFINITY;
+        zero_grad(G + 12 * k);
       } else {
         d3 P[4] = {load3(x, v[0]), load3(x, v[1]), load3(x, v[2]), load3(x, v[3])};
         double a, eta;
         if (fl & BF_F_FILTERED) { a = S.dmin[S.comp[v[0]]]; eta = 0.0; }
         else { a = S.h; eta = S.eta; }
-        eval_pair<MIXED>(P, code, a, eta, S.kappa, o);
+        eval_pair<MIXED>(P, code, a, eta, S.kappa, G + 12 * k, h);
       }
+      E[k] = h.E;
     }
-    __syncthreads();
-    int rows = (int)min((long long)64, n - k0);
-    if (lane < rows) E[k0 + lane] = tE[lane];
-    {  // the tile's energy, summed in a fixed order (partials of the total)
-      double e = lane < rows ? tE[lane] : 0.0, y = 0.0, z = 0.0;
-      wave_ordered_sum3(e, y, z);
-      if (lane == 0 && epart) epart[k0 / 64] = e;
-    }
-    for (int q = lane; q < rows * 12; q += 64) G[12 * k0 + q] = tG[q];
-    for (int q = lane; q < rows * 144; q += 64) {  // full 12 x 12 rows from the packed tile
-      const int r = q / 144, e = q - 144 * r, i = e / 12, j = e - 12 * i;
-      const int lo = min(i, j), hi = max(i, j);
-      H[144 * k0 + q] = tH[78 * r + lo * 12 - (lo * (lo - 1)) / 2 + (hi - lo)];
-    }
-    __syncthreads();
+    double e = h.E, y = 0.0, z = 0.0;
+    wave_ordered_sum3(e, y, z);
+    if (lane == 0 && epart) epart[k0 / 64] = e;
+    flush_rows<0>(h, buf, H, k0, (int)min((long long)64, n - k0));
   }
 }
 
