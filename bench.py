@@ -36,6 +36,23 @@ FLOPS_PER_KIND = {0: 150.0, 1: 2700.0, 2: 8000.0, 3: 8000.0}
 EVAL_BYTES_PER_PAIR = 11 + 96 + 8 + 96 + 1152
 KIND_OF_CODE = np.array([0, 0, 0, 1, 1, 1, 2, 0, 0, 0, 0, 1, 1, 1, 1, 3])
 
+# HBM bytes per launch of the evaluation kernel, counted with rocprofv3 --pmc
+# (FETCH_SIZE x 2 and WRITE_SIZE x 1, the factors a plain 256 MiB copy gives)
+# on the kernel source whose fingerprint is EVAL_TRAFFIC_SOURCE; reported as
+# null once that source changes.
+EVAL_TRAFFIC_SOURCE = "ef1b218641781cf9"
+EVAL_TRAFFIC_BYTES = {"woven_patch": 48.6e6, "folded_cloth": 2120.0e6}
+
+
+def eval_source_fingerprint():
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2510_10256_amd", "csrc")
+    src = open(os.path.join(csrc, "bfc_kernels.hip")).read()
+    a = src.index("// One wave per work-group, one pair per lane.  Each lane keeps its pair")
+    b = src.index("\n}\n", src.index("__global__ __launch_bounds__(64) void k_eval")) + 3
+    text = open(os.path.join(csrc, "bfc_eval.h")).read() + src[a:b]
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -392,6 +409,8 @@ def main():
     eval_ms = e0.elapsed_time(e1) / reps
     roof = eval_roofline(eval_ms, n_act, kinds, "k_eval (eval_barrier)")
     roof["kernel_ms"] = eval_ms
+    if args.prec == "fp64" and sc.name in EVAL_TRAFFIC_BYTES and eval_source_fingerprint() == EVAL_TRAFFIC_SOURCE:
+        roof["traffic"] = EVAL_TRAFFIC_BYTES[sc.name]
 
     out = {
         "metric": "filtered contact pairs evaluated/s (dist+filter+grad+Hessian); p50/p99 latency",

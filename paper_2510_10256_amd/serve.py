@@ -115,8 +115,8 @@ def scene_caps(scene):
     generous enough that overflows, and the retry they cost, are rare)."""
     nprims = scene.n_edges + (scene.n_tris + scene.n_verts if scene.kind == "shell" else 0)
     shell = scene.kind == "shell"
-    cand = max(4096, (56 if shell else 12) * nprims)
-    act = max(4096, (3 * nprims if shell else 3 * nprims // 2))
+    cand = max(4096, (48 if shell else 12) * nprims)
+    act = max(4096, (2 * nprims if shell else 3 * nprims // 2))
     return cand, act, max(4096, 5 * act)
 
 
