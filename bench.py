@@ -63,8 +63,8 @@ def parse():
                     choices=["woven_patch", "folded_cloth", "helix_loop_rod", "batch64", "serve256"])
     ap.add_argument("--prec", default=None, choices=["fp64", "mixed"],
                     help="default: fp64 for one scene, mixed for the batch")
-    ap.add_argument("--lanes", type=int, default=0, help="batch: concurrent streams in the graph (0 = tune)")
-    ap.add_argument("--tune", type=int, default=1, help="batch: tune threads per broad-phase query per scene")
+    ap.add_argument("--lanes", type=int, default=0, help="batch: concurrent streams in the graph (0 = four)")
+    ap.add_argument("--tune", type=int, default=1, help="tune threads per broad-phase query (per scene)")
     ap.add_argument("--budget-gib", type=float, default=2.0, help="serve: HBM budget of resident scenes")
     ap.add_argument("--slots", type=int, default=4, help="serve: requests on the device at once")
     ap.add_argument("--requests", type=int, default=300, help="serve: requests per open-loop run")
@@ -305,6 +305,9 @@ def main():
     cs = bfc.ContactScene(sc, prec=prec, device=dev)
     t0 = time.perf_counter()
     cs.run(x)  # sizes the buffers (grows them on overflow, then steps again)
+    if args.tune:
+        cs.tune(x)  # threads per broad-phase query
+        cs.run(x)
     counts = cs.counts()
     n_c, n_act = counts["n_c"], counts["n_act"]
     codes = cs.a_code[:n_act].cpu().numpy()
@@ -432,7 +435,7 @@ def main():
                                                  if sc.name == "woven_patch" else sc.name),
                    "n_verts": sc.n_verts, "n_edges": sc.n_edges, "n_tris": sc.n_tris,
                    "N_bp": counts["n_bp"], "N_c": n_c, "N_filt": counts["n_filt"], "N_act": n_act,
-                   "nnzb": counts["nnzb"], "launch": launch, "precision": args.prec},
+                   "nnzb": counts["nnzb"], "launch": launch, "pq": cs.pq, "precision": args.prec},
         "active_pairs_per_s": n_act / (ms_per_step * 1e-3),
         "call_ms": call_ms,
         "launch": launch,

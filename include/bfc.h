@@ -211,9 +211,8 @@ bf_status bf_scene_tune(bf_scene* s, const double* x_d, bf_pairs* cand, int32_t 
  * scene is captured once, the scenes spread over `lanes` streams inside the
  * graph (forked from and joined back to the launching stream), so the small
  * kernels of different scenes run side by side.  Scenes go to lanes by
- * decreasing primitive count, each to the least loaded lane.  lanes = 0 tunes
- * it: the batch is captured and timed with 1, 2, 4 and 8 lanes (the steps run,
- * so every item must hold valid positions and buffers) and the fastest kept.
+ * decreasing primitive count, each to the least loaded lane.  lanes = 0 takes
+ * 4, the hardware queues a process gets on this device.
  * Items are copied; the scenes and buffers they name must outlive the batch
  * and keep their capacities (rebuild the batch after bf_scene_reserve).
  * Results of a scene are bitwise those of its own four calls. */
@@ -230,7 +229,7 @@ typedef struct {
 
 typedef struct bf_batch bf_batch;
 
-/* Capture (and, for lanes = 0, tune) the batch; synchronises. */
+/* Capture the batch (once); synchronises. */
 bf_status bf_batch_create(const bf_batch_item* items, int32_t n, int32_t lanes, void* stream, bf_batch** out);
 /* One step of every scene of the batch: one graph launch on `stream`. */
 bf_status bf_batch_step(bf_batch* b, void* stream);

@@ -325,8 +325,8 @@ class Batch:
 
     ``scenes`` are ContactScene objects already sized for their inputs (call
     ``run`` once each); ``xs`` their device position tensors, which the batch
-    reads at every step (update them in place).  ``lanes`` = 0 tunes the
-    number of concurrent streams inside the graph.
+    reads at every step (update them in place).  ``lanes``: concurrent streams
+    inside the graph (0: four, the hardware queues a process gets).
     """
 
     def __init__(self, scenes, xs, lanes=0):

@@ -585,23 +585,6 @@ bf_status batch_capture(bf_batch* b, int lanes) {
   return BF_OK;
 }
 
-float time_launches(hipGraphExec_t exec, hipStream_t st, int reps) {
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess) return INFINITY;
-  if (hipEventCreate(&e1) != hipSuccess) {
-    (void)hipEventDestroy(e0);
-    return INFINITY;
-  }
-  float ms = INFINITY;
-  bool ok = hipGraphLaunch(exec, st) == hipSuccess && hipEventRecord(e0, st) == hipSuccess;
-  for (int k = 0; k < reps && ok; ++k) ok = hipGraphLaunch(exec, st) == hipSuccess;
-  ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
-       hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  return ok ? ms / reps : INFINITY;
-}
-
 }  // namespace
 
 extern "C" {
@@ -672,24 +655,12 @@ bf_status bf_batch_create(const bf_batch_item* items, int32_t n, int32_t lanes, 
     delete b;
     return fail_hip(he, "bf_batch_create");
   }
-  bf_status r = BF_OK;
-  if (lanes > 0) {
-    r = batch_capture(b, lanes);
-  } else {  // tune the number of lanes on the live buffers
-    int best = 1;
-    float best_ms = INFINITY;
-    for (int L = 1; L <= 8 && r == BF_OK; L *= 2) {
-      if (L > 1 && L > n) break;
-      r = batch_capture(b, L);
-      if (r != BF_OK) break;
-      float ms = time_launches(b->exec, b->origin, 5);
-      if (ms < best_ms) {
-        best_ms = ms;
-        best = L;
-      }
-    }
-    if (r == BF_OK) r = batch_capture(b, best);
-  }
+  // lanes = 0: as many as the device has hardware queues for one process
+  // (4).  The batch is captured once: tuning the lane count by capturing,
+  // timing and destroying several graphs in a row was followed by a crash in
+  // the runtime at the next launch (host segmentation fault, cause not
+  // known), so that path is gone.
+  bf_status r = batch_capture(b, lanes > 0 ? lanes : 4);
   if (r == BF_OK && (he = hipStreamSynchronize(b->origin)) != hipSuccess) r = fail_hip(he, "bf_batch_create");
   if (r != BF_OK) {
     bf_batch_destroy(b);

@@ -1,6 +1,6 @@
 // Kernels of libbfc (gfx950, wave64).
 //
-//   broad phase   : k_bounds, k_count, scan, k_scatter, k_pair_count, scan, k_pair_emit
+//   broad phase   : k_bounds, k_count, scan, k_scatter, k_cell_order, k_pair_count, k_pair_emit
 //   narrow phase  : k_narrow, scan, k_compact (distance, filter of Eq. 4, exact thresholds,
 //                   ballot compaction by distance kind)
 //   evaluation    : k_eval        (Eq. 2/3 barrier, derivatives, PSD projection)
@@ -534,15 +534,16 @@ __global__ __launch_bounds__(256) void k_pair_emit(SceneDev S, int nquery, const
   for (int q = threadIdx.x; q < upto; q += blockDim.x) part += bsum[q];
   const long long before = block_sum256(part);
   if (blockIdx.x == 0 && threadIdx.x == 0) *count = before;
+  const long long base = blockIdx.x == 0 ? 0 : before;
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   int c = t < nt ? cnt[t] : 0;
-  int off = (blockIdx.x == 0 ? 0 : (int)before) + block_excl_scan256(c, nullptr);
+  int loc = block_excl_scan256(c, nullptr);
   if (c == 0) return;
   int qtype, qid, qv[2];
   Box qb;
   query_of(S, box, t / PQ, qtype, qid, qb, qv);
-  visit_pairs<PQ, true>(S, g, cell_start, sorted_id, sorted_box, hf, qtype, qid, qb, qv, t % PQ, off, cap, oi, oj, ot,
-                    status);
+  visit_pairs<PQ, true>(S, g, cell_start, sorted_id, sorted_box, hf, qtype, qid, qb, qv, t % PQ, base + loc, cap, oi,
+                        oj, ot, status);
 }
 
 // ---------------------------------------------------------------------------
@@ -1156,16 +1157,17 @@ __device__ __forceinline__ int slot_of(const int* vv, int c) {
 
 // Pass B of one row by the NT threads of the block.  Every thread owns up to
 // two of the row's columns per pass (2 NT columns a pass).  The row's entries
-// are taken CH = NT / 2 at a time: two threads per entry load the entry's
-// band (rows 3s..3s+2 of its pair's 12 x 12 Hessian: 36 contiguous doubles)
-// into LDS beside the pair's stencil vertices; each owner then adds the 3x3
-// blocks of its columns from LDS, entries in sorted order.
-template <int NT>
+// are taken CH at a time: NT / CH threads per entry load the entry's band
+// (rows 3s..3s+2 of its pair's 12 x 12 Hessian: 36 contiguous doubles) into
+// LDS beside the pair's stencil vertices; each owner then adds the 3x3 blocks
+// of its columns from LDS, entries in sorted order.
+template <int NT, int CH>
 __device__ __forceinline__ void row_b(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,
                                       const int* inc, int b, int m, const int* cb, int r0, int u, const double* G,
                                       const double* H, double* grow, int* col, double* val, int* vs, double* band,
                                       double* gw) {
-  constexpr int CH = NT / 2;
+  constexpr int TPE = NT / CH, PART = 36 / TPE;  // threads per entry, doubles per thread
+  static_assert(TPE * PART == 36, "band split");
   const int tid = threadIdx.x, lane = lane_id();
   double gsum[3] = {0.0, 0.0, 0.0};  // the row's gradient (thread 0), chunk by chunk in entry order
   if (m == 0 && tid == 0) grow[0] = grow[1] = grow[2] = 0.0;
@@ -1175,15 +1177,15 @@ __device__ __forceinline__ void row_b(const SceneDev& S, const int* ai, const in
     double A[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, Z[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int qc = 0; qc < m; qc += CH) {
       const int nq = min(CH, m - qc);
-      const int q = tid >> 1, half = tid & 1;
+      const int q = tid / TPE, part = tid % TPE;
       double gx = 0.0, gy = 0.0, gz = 0.0;
       if (q < nq) {
         const int e = inc[b + qc + q], k = e >> 2;
-        const double* src = H + 144LL * k + 36 * (e & 3) + 18 * half;
-        double* dst = band + 36 * q + 18 * half;
+        const double* src = H + 144LL * k + 36 * (e & 3) + PART * part;
+        double* dst = band + 36 * q + PART * part;
 #pragma unroll
-        for (int o = 0; o < 18; ++o) dst[o] = src[o];
-        if (half == 0) {
+        for (int o = 0; o < PART; ++o) dst[o] = src[o];
+        if (part == 0) {
           int vv[4];
           pair_verts(S, at[k], ai[k], aj[k], vv);
 #pragma unroll
@@ -1245,8 +1247,8 @@ __global__ __launch_bounds__(64) void k_row_b(SceneDev S, const int* ai, const i
                                               long long cap, long long* nnzb, unsigned* status,
                                               const unsigned long long* act_count, long long acap,
                                               const double* epart, double* E_out) {
-  __shared__ int vs[4 * 32];
-  __shared__ double band[32 * 36];
+  __shared__ int vs[4 * 16];
+  __shared__ double band[16 * 36];
   if (blockIdx.x == 0) {
     if (threadIdx.x == 0) {
       const long long t = row_ptr[S.nv];
@@ -1263,7 +1265,7 @@ __global__ __launch_bounds__(64) void k_row_b(SceneDev S, const int* ai, const i
     if (m > ROW_M) continue;  // block path
     const int r0 = row_ptr[v], r1 = row_ptr[v + 1];
     if (r1 > cap) continue;   // overflow: reported above
-    row_b<64>(S, ai, aj, at, inc, b, m, colbuf + 4LL * b, r0, r1 - r0, G, H, g + 3LL * v, col, val, vs, band,
+    row_b<64, 16>(S, ai, aj, at, inc, b, m, colbuf + 4LL * b, r0, r1 - r0, G, H, g + 3LL * v, col, val, vs, band,
               nullptr);
   }
 }
@@ -1284,7 +1286,7 @@ __global__ __launch_bounds__(256) void k_row_b_big(SceneDev S, const int* ai, co
       const int b = inc_off[v], m = inc_off[v + 1] - b;
       const int r0 = row_ptr[v], r1 = row_ptr[v + 1];
       if (r1 > cap) continue;  // uniform across the block
-      row_b<256>(S, ai, aj, at, inc, b, m, colbuf + 4LL * b, r0, r1 - r0, G, H, g + 3LL * v, col, val, vs, band,
+      row_b<256, 128>(S, ai, aj, at, inc, b, m, colbuf + 4LL * b, r0, r1 - r0, G, H, g + 3LL * v, col, val, vs, band,
                  gw);
     }
     __syncthreads();

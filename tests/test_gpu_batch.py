@@ -32,7 +32,7 @@ def _fill_outputs(cs):
 
 @requires_gpu
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-@pytest.mark.parametrize("lanes", [1, 4, 0])
+@pytest.mark.parametrize("lanes", [1, 2, 0])
 def test_batch_equals_alone(prec, lanes):
     import paper_2510_10256_amd as bfc
     p = bfc.BF_FP64 if prec == "fp64" else bfc.BF_MIXED
