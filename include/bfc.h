@@ -80,9 +80,10 @@ typedef struct {
   double h;        /* thickness: activation distance of unfiltered pairs (Sec. 3) */
   double eta;      /* biphasic offset of unfiltered pairs, 0 <= eta < h (Eq. 3) */
   double kappa;    /* barrier stiffness multiplying every pair energy (> 0) */
-  int32_t prec;    /* BF_FP64, or BF_MIXED: the eigen-projection stops at about 1e-7 of |H|
-                      (results within 1e-5 relative instead of about 1e-12); both modes
-                      use FP32 boxes in the broad phase and exact threshold decisions */
+  int32_t prec;    /* BF_FP64, or BF_MIXED: the eigen-projection's QR iteration stops at
+                      1e-8 of |H| (results within 1e-5 relative instead of about 1e-13);
+                      both modes use FP32 boxes in the broad phase and exact threshold
+                      decisions */
   int32_t filter;  /* BF_FILTER_PAPER (Eq. 4) or BF_FILTER_NONE (offset barrier everywhere) */
 } bf_params;
 

@@ -15,6 +15,7 @@
 // Newton).  Mapping back through W gives the projected 12x12 Hessian, whose
 // translation null space is exact by construction.
 #pragma once
+#include "bfc_eig.h"
 #include "bfc_geom.h"
 
 namespace bfc {
@@ -35,125 +36,6 @@ template <class T> __device__ __forceinline__ T comp(V3<T> a, int i) { return i 
 template <int N> __device__ __forceinline__ constexpr int uix(int i, int j) {
   return i <= j ? i * N - (i * (i - 1)) / 2 + (j - i) : j * N - (j * (j - 1)) / 2 + (i - j);
 }
-
-// Round-robin (tournament) orderings of the index pairs of a 6 x 6 and a
-// 9 x 9 matrix: every pair once per sweep, the pairs of one round disjoint,
-// so the rotations of a round commute and their angles can be computed
-// independently (instruction-level parallelism instead of one long chain).
-// -1 marks a bye.
-template <int N> struct Sched;
-template <> struct Sched<6> {
-  static constexpr int R = 5, K = 3;
-};
-template <> struct Sched<9> {
-  static constexpr int R = 9, K = 4;
-};
-__device__ __forceinline__ constexpr int sched_idx(int n, int r, int k, int w) {
-  constexpr int S6[5][3][2] = {{{0, 5}, {1, 4}, {2, 3}}, {{0, 4}, {3, 5}, {1, 2}}, {{0, 3}, {2, 4}, {1, 5}},
-                               {{0, 2}, {1, 3}, {4, 5}}, {{0, 1}, {2, 5}, {3, 4}}};
-  constexpr int S9[9][4][2] = {{{1, 8}, {2, 7}, {3, 6}, {4, 5}}, {{0, 8}, {1, 6}, {2, 5}, {3, 4}},
-                               {{0, 7}, {6, 8}, {1, 4}, {2, 3}}, {{0, 6}, {5, 7}, {4, 8}, {1, 2}},
-                               {{0, 5}, {4, 6}, {3, 7}, {2, 8}}, {{0, 4}, {3, 5}, {2, 6}, {1, 7}},
-                               {{0, 3}, {2, 4}, {1, 5}, {7, 8}}, {{0, 2}, {1, 3}, {5, 8}, {6, 7}},
-                               {{0, 1}, {3, 8}, {4, 7}, {5, 6}}};
-  return n == 6 ? S6[r][k][w] : S9[r][k][w];
-}
-
-// Cyclic Jacobi eigen-decomposition of the symmetric N x N matrix A (upper
-// triangle, destroyed) in round-robin order, followed by
-// A+ = V max(L, 0) V^T written to P (upper).  Stops when the off-diagonal
-// mass is below tol2 of the Frobenius mass (1e-32 for FP64 results; the
-// error left in A+ is about sqrt(2 tol2) |A|).
-//
-// A rotation angle only decides how much of a_pq a rotation removes, not the
-// exactness of the similarity transform, so the angles are computed in FP32
-// on the matrix scaled to unit Frobenius norm (fast reciprocal and square
-// root); the rotation (c, s) is then made orthogonal to FP64 precision
-// (c = (1 + t^2)^-1/2 by Newton steps in FP64) and applied with the full
-// 2 x 2 update, since a_pq' is no longer exactly zero.  Near convergence
-// each sweep still shrinks the off-diagonal mass by the FP32 angle accuracy.
-template <int N> __device__ __forceinline__ void psd_jacobi(double* A, double* P, double tol2) {
-  constexpr int R = Sched<N>::R, K = Sched<N>::K;
-  double V[N][N];
-#pragma unroll
-  for (int i = 0; i < N; ++i)
-#pragma unroll
-    for (int j = 0; j < N; ++j) V[i][j] = i == j ? 1.0 : 0.0;
-  double fro = 0.0;
-#pragma unroll
-  for (int i = 0; i < N; ++i)
-#pragma unroll
-    for (int j = i; j < N; ++j) fro += (i == j ? 1.0 : 2.0) * A[uix<N>(i, j)] * A[uix<N>(i, j)];
-  const double inv = fro > 0.0 ? 1.0 / sqrt(fro) : 0.0;
-  for (int sweep = 0; sweep < 20; ++sweep) {
-    double off = 0.0;
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-      for (int j = i + 1; j < N; ++j) off += A[uix<N>(i, j)] * A[uix<N>(i, j)];
-    if (!(off > tol2 * fro)) break;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      double cs[K], sn[K];
-#pragma unroll
-      for (int k = 0; k < K; ++k) {  // independent rotation angles of this round
-        const int p = sched_idx(N, r, k, 0), q = sched_idx(N, r, k, 1);
-        if (p < 0) {
-          cs[k] = 1.0; sn[k] = 0.0;
-          continue;
-        }
-        double apq = A[uix<N>(p, q)];
-        float num = (float)((A[uix<N>(q, q)] - A[uix<N>(p, p)]) * inv);
-        float den = (float)(2.0 * apq * inv);
-        float tau = num * __builtin_amdgcn_rcpf(den);
-        float tf = __builtin_amdgcn_rcpf(fabsf(tau) + __builtin_amdgcn_sqrtf(fmaf(tau, tau, 1.0f)));
-        tf = tau < 0.0f ? -tf : tf;
-        double t = (apq != 0.0 && den != 0.0 && tf == tf) ? (double)tf : 0.0;
-        double x = fma(t, t, 1.0);
-        double c = (double)__builtin_amdgcn_rsqf((float)x);
-        c = c * (1.5 - 0.5 * x * c * c);  // Newton steps for x^-1/2
-        c = c * (1.5 - 0.5 * x * c * c);
-        cs[k] = c; sn[k] = t * c;
-      }
-#pragma unroll
-      for (int k = 0; k < K; ++k) {  // apply them (disjoint index pairs commute)
-        const int p = sched_idx(N, r, k, 0), q = sched_idx(N, r, k, 1);
-        if (p < 0) continue;
-        const double c = cs[k], s = sn[k];
-        double app = A[uix<N>(p, p)], aqq = A[uix<N>(q, q)], apq = A[uix<N>(p, q)];
-        A[uix<N>(p, p)] = c * c * app - 2.0 * c * s * apq + s * s * aqq;
-        A[uix<N>(q, q)] = s * s * app + 2.0 * c * s * apq + c * c * aqq;
-        A[uix<N>(p, q)] = c * s * (app - aqq) + (c * c - s * s) * apq;
-#pragma unroll
-        for (int m = 0; m < N; ++m) {
-          if (m == p || m == q) continue;
-          double amp = A[uix<N>(m, p)], amq = A[uix<N>(m, q)];
-          A[uix<N>(m, p)] = c * amp - s * amq;
-          A[uix<N>(m, q)] = s * amp + c * amq;
-        }
-#pragma unroll
-        for (int m = 0; m < N; ++m) {
-          double vmp = V[m][p], vmq = V[m][q];
-          V[m][p] = c * vmp - s * vmq;
-          V[m][q] = s * vmp + c * vmq;
-        }
-      }
-    }
-  }
-  double lam[N];
-#pragma unroll
-  for (int k = 0; k < N; ++k) lam[k] = fmax(A[uix<N>(k, k)], 0.0);
-#pragma unroll
-  for (int i = 0; i < N; ++i)
-#pragma unroll
-    for (int j = i; j < N; ++j) {
-      double acc = 0.0;
-#pragma unroll
-      for (int k = 0; k < N; ++k) acc += V[i][k] * lam[k] * V[j][k];
-      P[uix<N>(i, j)] = acc;
-    }
-}
-
 
 // Select one of four vertices without indexing a register array at run time
 // (which would place it in scratch memory).
@@ -233,7 +115,7 @@ __device__ __forceinline__ void eval_pp(const d3* P, int s0, int s1, double a, d
 // w1 = (1, -1, 0)/sqrt2, w2 = (1, 1, -2)/sqrt6.  With y = (r, e) = Y x the
 // coupling b = Y W is [[sqrt2, 0], [1/sqrt2, -3/sqrt6]].
 __device__ __forceinline__ void eval_pe(const d3* P, int sp, int se0, int se1, double a, double eta,
-                                        double kappa, double tol2, double* G, PairOut& h) {
+                                        double kappa, double tol, double* G, PairOut& h) {
   const double S2 = 1.4142135623730951, IS2 = 0.70710678118654752, IS6 = 0.40824829046386302;
   d3 xp = pick4(P, sp), x0 = pick4(P, se0), x1 = pick4(P, se1);
   d3 r = xp - x0, e = x1 - x0;
@@ -282,7 +164,7 @@ __device__ __forceinline__ void eval_pe(const d3* P, int sp, int se0, int se1, d
           A[uix<6>(I, J)] = br[al] * br[bt] * Yrr[i][j] + br[al] * be[bt] * Yre[i][j] +
                             be[al] * br[bt] * Yre[j][i] + be[al] * be[bt] * Yee[i][j];
         }
-  psd_jacobi<6>(A, h.A, tol2);
+  psd_project<6>(A, h.A, tol);
   // slot of the pair missing from the stencil gets a zero gradient
   zero_grad(G);
 #pragma unroll
@@ -304,7 +186,7 @@ __device__ __forceinline__ void eval_pe(const d3* P, int sp, int se0, int se1, d
 // Couplings b = Y W (rows r, u, v):
 //   PT (r = p-t0, u = t1-t0, v = t2-t0):  r (0,1,1)  u (-1,1,0)  v (-1,0,1)
 //   EE (r = a0-b0, u = a1-a0, v = b1-b0): r (1,0,1)  u (0,-1,-1) v (0,-1,1)
-__device__ __forceinline__ void eval_tri(const d3* P, bool is_pt, double a, double eta, double kappa, double tol2,
+__device__ __forceinline__ void eval_tri(const d3* P, bool is_pt, double a, double eta, double kappa, double tol,
                                          double* G, PairOut& h) {
   d3 r, u, v;
   if (is_pt) {
@@ -381,7 +263,7 @@ __device__ __forceinline__ void eval_tri(const d3* P, bool is_pt, double a, doub
             }
           A[uix<9>(I, J)] = acc;
         }
-  psd_jacobi<9>(A, h.A, tol2);
+  psd_project<9>(A, h.A, tol);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     double gr = ch.cg * g[i], gu = ch.cg * g[3 + i], gv = ch.cg * g[6 + i];
@@ -459,23 +341,24 @@ template <int I> __device__ __forceinline__ void hess_row(const PairOut& h, doub
 }
 
 // Evaluate one active pair with the sub-case `code` fixed by the narrow
-// phase.  MIXED: the projection stops at about 1e-7 of |H| instead of FP64
-// convergence.  Distances, derivative terms and the projection arithmetic
-// stay FP64 on both paths: FP32 derivative terms lose up to 1e-2 relative
-// accuracy for nearly parallel edges (successive turns of a coiled rod).
+// phase.  MIXED: the projection's QR iteration stops once the tridiagonal's
+// off-diagonal is below 1e-8 of |H| instead of FP64 rounding (2.2e-16).
+// Distances, derivative terms and the projection arithmetic stay FP64 on both
+// paths: FP32 derivative terms lose up to 1e-2 relative accuracy for nearly
+// parallel edges (successive turns of a coiled rod).
 template <bool MIXED>
 __device__ __forceinline__ void eval_pair(const d3* P, int code, double a, double eta, double kappa, double* G,
                                           PairOut& h) {
-  const double tol2 = MIXED ? 1e-14 : 1e-32;
+  const double tol = MIXED ? 1e-8 : 2.2e-16;
   int kind = case_kind(code);
   if (kind == K_PT || kind == K_EE) {
-    eval_tri(P, kind == K_PT, a, eta, kappa, tol2, G, h);
+    eval_tri(P, kind == K_PT, a, eta, kappa, tol, G, h);
     return;
   }
   int s0, s1, s2;
   case_slots(code, s0, s1, s2);
   if (kind == K_PP) eval_pp(P, s0, s1, a, eta, kappa, G, h);
-  else eval_pe(P, s0, s1, s2, a, eta, kappa, tol2, G, h);
+  else eval_pe(P, s0, s1, s2, a, eta, kappa, tol, G, h);
 }
 
 }  // namespace bfc

@@ -1,0 +1,112 @@
+"""CPU check of the library's PSD projection (tridiagonal QR, bfc_eig.h),
+built for the host: against LAPACK (numpy eigh) on random, structured and
+degenerate symmetric matrices, and on reduced pair Hessians of the workloads
+(from the oracle)."""
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(os.path.dirname(HERE), "paper_2510_10256_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def exe():
+    d = tempfile.mkdtemp(prefix="eig_host_")
+    out = os.path.join(d, "eig_host")
+    cmd = ["/opt/rocm/bin/hipcc", "-O2", "-std=c++17", "-I", CSRC, os.path.join(HERE, "host", "eig_host.cpp"),
+           "-o", out]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("hipcc host build failed: " + r.stderr[-500:])
+    return out
+
+
+def _upper(A):
+    n = A.shape[-1]
+    iu = np.triu_indices(n)
+    return A[..., iu[0], iu[1]]
+
+
+def _full(U, n):
+    A = np.zeros(U.shape[:-1] + (n, n))
+    iu = np.triu_indices(n)
+    A[..., iu[0], iu[1]] = U
+    A[..., iu[1], iu[0]] = U
+    return A
+
+
+def _project(exe, mats, tol=2.2e-16):
+    n = mats.shape[-1]
+    d = tempfile.mkdtemp(prefix="eig_io_")
+    fi, fo = os.path.join(d, "in.bin"), os.path.join(d, "out.bin")
+    with open(fi, "wb") as f:
+        np.array([len(mats), n], np.int64).tofile(f)
+        np.ascontiguousarray(_upper(mats), np.float64).tofile(f)
+    r = subprocess.run([exe, fi, fo, repr(tol)], capture_output=True)
+    assert r.returncode == 0, r
+    return _full(np.fromfile(fo, np.float64).reshape(len(mats), -1), n)
+
+
+def _reference(mats):
+    w, V = np.linalg.eigh(mats)
+    return np.einsum("nij,nj,nkj->nik", V, np.maximum(w, 0.0), V)
+
+
+def _cases(n, rng):
+    out = []
+    for _ in range(200):  # random, random scale
+        B = rng.normal(size=(n, n)) * 10.0 ** rng.uniform(-6, 6)
+        out.append(B + B.T)
+    for _ in range(50):   # low rank (repeated zero eigenvalues), mixed signs
+        U = rng.normal(size=(n, 3))
+        out.append(U @ np.diag(rng.normal(size=3)) @ U.T)
+    for _ in range(50):   # repeated eigenvalues of both signs
+        Q, _ = np.linalg.qr(rng.normal(size=(n, n)))
+        lam = rng.choice([-2.0, -1e-9, 0.0, 1.0, 3.0], size=n)
+        out.append(Q @ np.diag(lam) @ Q.T)
+    out.append(np.zeros((n, n)))
+    out.append(np.diag(rng.normal(size=n)))
+    T = np.diag(rng.normal(size=n)) + np.diag(rng.normal(size=n - 1), 1)
+    out.append(T + np.triu(T, 1).T)
+    out.append(np.eye(n) * -1.0)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("n", [6, 9])
+def test_projection_matches_lapack(exe, n):
+    rng = np.random.default_rng(5 + n)
+    mats = _cases(n, rng)
+    got = _project(exe, mats)
+    ref = _reference(mats)
+    scale = np.linalg.norm(mats, axis=(1, 2)) + 1e-300
+    err = np.linalg.norm(got - ref, axis=(1, 2)) / scale
+    assert err.max() < 1e-13, (err.max(), int(err.argmax()))
+    # the projection is PSD and idempotent
+    w = np.linalg.eigvalsh(got)
+    assert (w >= -1e-13 * scale[:, None]).all()
+
+
+def test_pair_hessians_of_the_workloads(exe):
+    # reduced (translation-free) Hessians of active pairs of the yarn and cloth
+    # workloads, from the oracle: 9x9 for edge-edge / point-triangle, 6x6 for
+    # point-edge
+    import oracle
+    import synth
+    W4 = 0.5 * np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], float)
+    for sc in (synth.woven_patch(n_warp=8, n_weft=8, verts_per_rod=128),
+               synth.folded_cloth(n=72, gaps=(950.0,), l_mid=4000.0, l_conv=2000.0)):
+        r = oracle.evaluate(sc, mode=1, derivs=True)
+        act = ((r["flags"] & 2) != 0) & ((r["flags"] & 4) == 0)
+        H, codes = r["Hraw"][act], r["code"][act]
+        tri = (codes == 6) | (codes == 15)
+        if tri.any():
+            Wf = np.kron(W4, np.eye(3))
+            mats = np.einsum("ia,nij,jb->nab", Wf, H[tri], Wf)
+            got = _project(exe, mats)
+            ref = _reference(mats)
+            err = np.linalg.norm(got - ref, axis=(1, 2)) / (np.linalg.norm(mats, axis=(1, 2)) + 1e-300)
+            assert err.max() < 1e-13, (sc.name, err.max())
