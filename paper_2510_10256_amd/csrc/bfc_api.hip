@@ -113,6 +113,7 @@ bf_status alloc_asm(bf_scene* s, long long act_cap) {
   A.inc = dalloc<int>(s->asm_allocs, 4 * act_cap, &e);
   A.colbuf = dalloc<int>(s->asm_allocs, 16 * act_cap, &e);
   A.rowcnt = dalloc<int>(s->asm_allocs, s->nv + 1, &e);
+  A.mid = dalloc<int>(s->asm_allocs, s->nv + 1, &e);
   A.epart = dalloc<double>(s->asm_allocs, (act_cap + 63) / 64 + 1, &e);
   A.scan_tmp = dalloc<int>(s->asm_allocs, scan_parts(s->nv + 1) + 16, &e);
   if (e != hipSuccess) return fail(BF_E_NOMEM, "bf_scene_reserve: device allocation failed");

@@ -11,14 +11,18 @@ struct Box {
   float lo[3], hi[3];
 };
 
-// Uniform grid of the broad phase.  Cell size >= (largest primitive box side
-// + h) so that two primitives whose boxes are closer than h have box centres
-// in the same or adjacent cells; every cell has two sub-lists (edges, then
-// triangles).  Coordinates are clamped to the grid, which keeps the
-// adjacency property.
+// Uniform grid of the broad phase.  Every stored primitive sits in the cell
+// of its box centre (coordinates clamped to the grid); the sorted lists hold
+// all cells' edges, then all cells' triangles, so that a run of cells along
+// x is one contiguous range of either.  A primitive whose box is within h of
+// a query box has its centre within `reach` (h + half the largest box side,
+// plus slack) of the query box, so a query visits the cells of that range
+// only; the cell side is free (half of largest side + h here).
 struct Grid {
   double orgd[3];
   double cell, inv_cell;
+  double reach;
+  float gapf;  // a float box gap above this is above h on every path of the exact test
   int n[3];
   int ncells;
   int nscan;  // 2 * ncells + 1 sub-list boundaries
@@ -48,7 +52,7 @@ struct BroadWs {
   float* part;       // [8 * BOUNDS_BLOCKS] per-block bounds
   unsigned* done;    // [1] block counter of the last-block reduction (zero between launches)
   Grid* grid;        // [1]
-  int* cell_cnt;     // [2*max_cells + 1], zero between steps
+  int* cell_cnt;     // [2*max_cells + 1], zero between steps (edges of every cell, then triangles)
   int* cell_start;   // [2*max_cells + 1]
   int* placed_id;    // [NS] stored primitives grouped by cell (any order inside a cell)
   Box* placed_box;   // [NS]
@@ -80,6 +84,7 @@ struct AsmWs {
   int* inc;       // [4 * act_cap] entries 4k + s grouped by vertex
   int* colbuf;    // [16 * act_cap] stencil vertices of each entry's pair (row columns, sorted per row)
   int* rowcnt;    // [V + 1] distinct columns per row
+  int* mid;       // [V + 1] rows with 16 < m <= 256 entries (pass A's list, any order); mid[V] = their number
   double* epart;  // [act_cap / 64 + 1] energy of each 64-pair tile of the evaluation
   int* scan_tmp;
 };

@@ -247,7 +247,7 @@ __device__ void make_grid(const float* lo_f, const float* hi_f, float ext_f, dou
   }
   double ext = (double)ext_f;
   if (!(ext >= 0.0)) ext = 0.0;
-  double cell = (ext + h) * 1.001 + 1e-6 * (1.0 + amax);
+  double cell = 0.5 * (ext + h) + 1e-6 * (1.0 + amax);
   int coarse = 0;
   long long n[3], tot = 1;
   for (int it = 0; it < 64; ++it) {
@@ -269,6 +269,11 @@ __device__ void make_grid(const float* lo_f, const float* hi_f, float ext_f, dou
   }
   g->cell = cell;
   g->inv_cell = 1.0 / cell;
+  // centre reach: h (and the exact test's slack) + half the largest side
+  g->reach = h + 0.5 * ext + 1e-9 * (1.0 + amax + ext + h);
+  // float prefilter bound: a float gap g > gapf has an exact gap of at least
+  // g (1 - 2^-24) > h + 1e-15 |coordinates|
+  g->gapf = __double2float_ru(h * (1.0 + 1e-6) + 2e-15 * amax);
   for (int a = 0; a < 3; ++a) { g->n[a] = (int)n[a]; g->orgd[a] = lo[a]; }
   g->ncells = (int)tot;
   g->nscan = 2 * (int)tot + 1;
@@ -374,6 +379,16 @@ __device__ __forceinline__ void cell_coords(const Grid& g, const Box& b, int* c)
 __device__ __forceinline__ int cell_lin(const Grid& g, int cx, int cy, int cz) {
   return (cz * g.n[1] + cy) * g.n[0] + cx;
 }
+__device__ __forceinline__ int clamp_cell(double q, int n) { return q >= 0.0 ? (q < (double)n ? (int)q : n - 1) : 0; }
+// Cells of the box centres within reach of box b (the same rounding steps
+// as cell_coords, which keeps the range a superset).
+__device__ __forceinline__ void cell_range(const Grid& g, const Box& b, int* lo, int* hi) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = clamp_cell(floor(((double)b.lo[a] - g.reach - g.orgd[a]) / g.cell), g.n[a]);
+    hi[a] = max(lo[a], clamp_cell(floor(((double)b.hi[a] + g.reach - g.orgd[a]) / g.cell), g.n[a]));
+  }
+}
 
 __global__ __launch_bounds__(256) void k_count(int nstored, int ne, const Box* box, const Grid* gp, int* cell_cnt,
                                                int* cell_of) {
@@ -381,7 +396,7 @@ __global__ __launch_bounds__(256) void k_count(int nstored, int ne, const Box* b
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < nstored; p += grid_stride()) {
     int c[3];
     cell_coords(g, box[p], c);
-    int sub = 2 * cell_lin(g, c[0], c[1], c[2]) + (p >= ne ? 1 : 0);
+    int sub = cell_lin(g, c[0], c[1], c[2]) + (p >= ne ? g.ncells : 0);
     cell_of[p] = sub;
     atomicAdd(&cell_cnt[sub], 1);
   }
@@ -427,30 +442,40 @@ __device__ __forceinline__ bool boxes_near(const Box& a, const Box& b, double h)
   return true;
 }
 
+// Float gap above gapf on some axis: the exact test below fails too.  (NaN
+// gaps compare false and go on to the exact test.)
+__device__ __forceinline__ bool boxes_far_f(const Box& a, const Box& b, float gapf) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (fmaxf(b.lo[k] - a.hi[k], a.lo[k] - b.hi[k]) > gapf) return true;
+  return false;
+}
+
 // Visit the stored primitives of the sub-list for the query (triangles for a
-// point, edges for an edge) in the neighbour cells c = sub, sub + PQ, ...
-// of the 27 cells around the query's cell; count, or emit at `pos`, every
-// non-incident pair whose boxes are within h.
+// point, edges with a larger id for an edge) in the rows (y, z) = sub,
+// sub + PQ, ... of the query's cell range, each row one contiguous run of
+// cells along x; count, or emit at `pos`, every non-incident pair whose
+// boxes are within h.
 template <int PQ, bool EMIT>
 __device__ __forceinline__ int visit_pairs(const SceneDev& S, const Grid& g, const int* cell_start,
                                            const int* sorted_id, const Box* sorted_box, double hf, int qtype,
                                            int qid, const Box& qb, const int* qv, int sub, long long pos,
                                            long long cap, int* oi, int* oj, unsigned char* ot, unsigned* status) {
-  int c[3];
-  cell_coords(g, qb, c);
+  int lo[3], hi[3];
+  cell_range(g, qb, lo, hi);
+  const int ny = hi[1] - lo[1] + 1, nrow = ny * (hi[2] - lo[2] + 1);
+  const int base = qtype == BF_PT ? g.ncells : 0;
   int cnt = 0;
-  int sub_type = qtype == BF_PT ? 1 : 0;
-  for (int nb = sub; nb < 27; nb += PQ) {
-    int cx = c[0] + nb % 3 - 1, cy = c[1] + (nb / 3) % 3 - 1, cz = c[2] + nb / 9 - 1;
-    if (cx < 0 || cy < 0 || cz < 0 || cx >= g.n[0] || cy >= g.n[1] || cz >= g.n[2]) continue;
-    int sl = 2 * cell_lin(g, cx, cy, cz) + sub_type;
-    int b = cell_start[sl], e = cell_start[sl + 1];
+  for (int row = sub; row < nrow; row += PQ) {
+    const int cy = lo[1] + row % ny, cz = lo[2] + row / ny;
+    const int l0 = base + cell_lin(g, lo[0], cy, cz);
+    const int b = cell_start[l0], e = cell_start[l0 + hi[0] - lo[0] + 1];
     for (int k = b; k < e; ++k) {
-      Box rb = sorted_box[k];
-      if (!boxes_near(qb, rb, hf)) continue;
       int r = sorted_id[k];
+      if (qtype == BF_EE && r <= qid) continue;
+      const Box rb = sorted_box[k];
+      if (boxes_far_f(qb, rb, g.gapf) || !boxes_near(qb, rb, hf)) continue;
       if (qtype == BF_EE) {
-        if (r <= qid) continue;
         int r0 = S.edges[2 * r], r1 = S.edges[2 * r + 1];
         if (r0 == qv[0] || r0 == qv[1] || r1 == qv[0] || r1 == qv[1]) continue;
       } else {
@@ -858,7 +883,8 @@ __global__ __launch_bounds__(64) void k_eval(SceneDev S, const double* x, const 
 // Incidence counts of the feasible active pairs' stencil vertices.
 __global__ __launch_bounds__(256) void k_inc_count(SceneDev S, const int* ai, const int* aj, const unsigned char* at,
                                                    const unsigned char* aflags, const unsigned long long* act_count,
-                                                   long long acap, int* inc_cnt) {
+                                                   long long acap, int* inc_cnt, int* mid_count) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *mid_count = 0;  // pass A appends to the list afresh
   long long n = (long long)*act_count;
   if (n > acap) n = acap;
   for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += grid_stride()) {
@@ -900,10 +926,13 @@ __global__ __launch_bounds__(256) void k_inc_fill(SceneDev S, const int* ai, con
 }
 
 // ---- per-row assembly ------------------------------------------------------
-// A row with m incidence entries takes one of three paths: m <= ROW_L in the
+// A row with m incidence entries takes one of four paths: m <= ROW_S in the
+// registers of a 16-lane team (four rows a wave), m <= ROW_L in the
 // registers of one wave, m <= ROW_M in one wave's LDS, m <= ROW_H by a
 // 256-thread block in LDS; beyond ROW_H one lane works in global memory
-// (correct, slow).  Cloth rows reach a few hundred entries, rod rows a few.
+// (correct, slow).  Cloth rows reach a few hundred entries, rod rows a
+// dozen or two.
+constexpr int ROW_S = 16;  // rows with m <= ROW_S: one 16-lane team each, four rows a wave
 constexpr int ROW_L = 32;
 constexpr int ROW_M = 256;
 constexpr int ROW_M_TAB = 4 * ROW_M;  // hash slots: at least the row's 4m candidate columns
@@ -967,6 +996,53 @@ __device__ __forceinline__ void wave_sort128(int& a0, int& a1) {
     }
 }
 
+// Sorts inside the 16-lane teams of a wave (team t = lanes 16t..16t+15):
+// 16 values (one per lane) and 64 values (element i in lane i & 15,
+// register i >> 4).
+__device__ __forceinline__ int team_sort16(int x) {
+  const int tl = lane_id() & 15;
+#pragma unroll
+  for (int k = 2; k <= 16; k <<= 1)
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      int y = __shfl_xor(x, j, 16);
+      bool keep_min = ((tl & j) == 0) == ((tl & k) == 0);
+      x = keep_min ? min(x, y) : max(x, y);
+    }
+  return x;
+}
+__device__ __forceinline__ void team_sort64(int (&a)[4]) {
+  const int tl = lane_id() & 15;
+#pragma unroll
+  for (int k = 2; k <= 64; k <<= 1)
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j >= 16) {  // partner in another register of the same lane
+        const int rj = j >> 4;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (r & rj) continue;
+          const bool up = ((16 * r + tl) & k) == 0;
+          const int lo = min(a[r], a[r | rj]), hi = max(a[r], a[r | rj]);
+          a[r] = up ? lo : hi;
+          a[r | rj] = up ? hi : lo;
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * r + tl;
+          const int y = __shfl_xor(a[r], j, 16);
+          const bool keep_min = ((i & j) == 0) == ((i & k) == 0);
+          a[r] = keep_min ? min(a[r], y) : max(a[r], y);
+        }
+      }
+    }
+}
+// the 16 bits of a wave ballot that belong to this lane's team
+__device__ __forceinline__ unsigned team_bits(unsigned long long m) {
+  return (unsigned)((m >> (lane_id() & 48)) & 0xffffull);
+}
+
 // Insert key into an LDS open-addressing set of T slots (T a power of two
 // larger than or equal to the number of distinct keys ever inserted).
 __device__ __forceinline__ void set_insert(int* tab, int T, int key) {
@@ -1004,81 +1080,153 @@ __device__ void row_a_serial(const SceneDev& S, const int* ai, const int* aj, co
   *count = u;
 }
 
-// Pass A (structure; needs the active list only), rows with m <= ROW_M, one
-// wave per row: sort the row's incidence entries (so every sum of pass B
-// runs in a fixed order) and store its distinct columns (the stencil
-// vertices of its pairs) sorted at colbuf[4 * inc_off[v] ...]; rowcnt[v] =
-// their number.
+// Pass A (structure; needs the active list only): sort the row's incidence
+// entries (so every sum of pass B runs in a fixed order) and store its
+// distinct columns (the stencil vertices of its pairs) sorted at
+// colbuf[4 * inc_off[v] ...]; rowcnt[v] = their number.
+
+// Rows with m <= ROW_S, one per 16-lane team: entry q in lane q, candidate
+// column 4q + c in lane (4q + c) & 15, register (4q + c) >> 4.  `mine` is
+// false on teams without such a row (their lanes take part in the
+// shuffles with padding only).
+__device__ __forceinline__ void row_a_team(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,
+                                           bool mine, int v, int b, int m, int* inc, int* colbuf, int* rowcnt) {
+  const int tl = lane_id() & 15;
+  int e = mine && tl < m ? inc[b + tl] : PAD;
+  e = team_sort16(e);
+  int vv[4] = {PAD, PAD, PAD, PAD};
+  if (mine && tl < m) {
+    inc[b + tl] = e;
+    const int k = e >> 2;
+    pair_verts(S, at[k], ai[k], aj[k], vv);
+  }
+  const int t4 = tl & 3;
+  int c[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int q = 4 * r + (tl >> 2);
+    const int w0 = __shfl(vv[0], q, 16), w1 = __shfl(vv[1], q, 16), w2 = __shfl(vv[2], q, 16),
+              w3 = __shfl(vv[3], q, 16);
+    c[r] = t4 == 0 ? w0 : t4 == 1 ? w1 : t4 == 2 ? w2 : w3;
+  }
+  team_sort64(c);
+  int* cb = colbuf + 4LL * b;
+  int u = 0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    int p = __shfl_up(c[r], 1, 16);
+    const int last = r > 0 ? __shfl(c[r - 1], 15, 16) : PAD;
+    if (tl == 0) p = last;
+    const bool f = c[r] != PAD && ((r == 0 && tl == 0) || c[r] != p);
+    const unsigned msk = team_bits(__ballot(f));
+    if (f && mine) cb[u + __popc(msk & ((1u << tl) - 1u))] = c[r];
+    u += __popc(msk);
+  }
+  if (mine && tl == 0) rowcnt[v] = u;
+}
+
+// One row with ROW_S < m <= ROW_M by the whole wave (a block of one wave).
+__device__ void row_a_wave(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at, int v, int b,
+                           int m, int* inc, int* colbuf, int* rowcnt, int* ent, int* tab) {
+  const int lane = threadIdx.x;
+  int* cb = colbuf + 4LL * b;
+  if (m <= ROW_L) {
+    // registers: entry q in lane q, candidate column 4q + t in lane
+    // (4q + t) & 63, register (4q + t) >> 6
+    int e = lane < m ? inc[b + lane] : PAD;
+    e = wave_sort64(e);
+    int vv[4] = {PAD, PAD, PAD, PAD};
+    if (lane < m) {
+      inc[b + lane] = e;
+      const int k = e >> 2;
+      pair_verts(S, at[k], ai[k], aj[k], vv);
+    }
+    const int t = lane & 3, q0 = lane >> 2, q1 = 16 + (lane >> 2);
+    int w0 = __shfl(vv[0], q0, 64), w1 = __shfl(vv[1], q0, 64), w2 = __shfl(vv[2], q0, 64),
+        w3 = __shfl(vv[3], q0, 64);
+    int c0 = t == 0 ? w0 : t == 1 ? w1 : t == 2 ? w2 : w3;
+    w0 = __shfl(vv[0], q1, 64); w1 = __shfl(vv[1], q1, 64); w2 = __shfl(vv[2], q1, 64); w3 = __shfl(vv[3], q1, 64);
+    int c1 = t == 0 ? w0 : t == 1 ? w1 : t == 2 ? w2 : w3;
+    wave_sort128(c0, c1);
+    const int p0 = __shfl_up(c0, 1, 64), last0 = __shfl(c0, 63, 64);
+    int p1 = __shfl_up(c1, 1, 64);
+    if (lane == 0) p1 = last0;
+    const bool f0 = c0 != PAD && (lane == 0 || c0 != p0);
+    const bool f1 = c1 != PAD && c1 != p1;
+    const unsigned long long m0 = __ballot(f0), m1 = __ballot(f1);
+    const int u0 = __popcll(m0);
+    if (f0) cb[lanes_below(m0)] = c0;
+    if (f1) cb[u0 + lanes_below(m1)] = c1;
+    if (lane == 0) rowcnt[v] = u0 + __popcll(m1);
+    return;
+  }
+  // LDS
+  const int Pm = pow2_at_least(m);
+  for (int q = lane; q < Pm; q += 64) ent[q] = q < m ? inc[b + q] : PAD;
+  const int T = min(ROW_M_TAB, pow2_at_least(8 * m));
+  for (int q = lane; q < T; q += 64) tab[q] = EMPTY;
+  __syncthreads();
+  team_bitonic<64>(ent, Pm);
+  for (int q = lane; q < m; q += 64) {
+    int e = ent[q], k = e >> 2;
+    inc[b + q] = e;
+    int vv[4];
+    pair_verts(S, at[k], ai[k], aj[k], vv);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) set_insert(tab, T, vv[c]);
+  }
+  __syncthreads();
+  int u = 0;  // compact the set in place (a chunk is read before any of it is written)
+  for (int c = 0; c < T; c += 64) {
+    int x = tab[c + lane];
+    bool ok = x != EMPTY;
+    unsigned long long msk = __ballot(ok);
+    if (ok) tab[u + lanes_below(msk)] = x;
+    u += __popcll(msk);
+  }
+  const int P = pow2_at_least(u > 0 ? u : 1);
+  for (int q = u + lane; q < P; q += 64) tab[q] = PAD;
+  __syncthreads();
+  team_bitonic<64>(tab, P);
+  for (int q = lane; q < u; q += 64) cb[q] = tab[q];
+  if (lane == 0) rowcnt[v] = u;
+  __syncthreads();
+}
+
+// Rows 4j .. 4j + 3 per block of one wave: first the rows with m <= ROW_S
+// (a team each), then those with m <= ROW_M one after another.
 __global__ __launch_bounds__(64) void k_row_a(SceneDev S, const int* ai, const int* aj, const unsigned char* at,
-                                              const int* inc_off, int* inc, int* colbuf, int* rowcnt) {
+                                              const int* inc_off, int* inc, int* colbuf, int* rowcnt, int* mid) {
   __shared__ int ent[ROW_M];
   __shared__ int tab[ROW_M_TAB];
-  const int lane = threadIdx.x;
-  for (int v = blockIdx.x; v < S.nv; v += gridDim.x) {
-    const int b = inc_off[v], m = inc_off[v + 1] - b;
-    if (m > ROW_M) continue;  // block path
-    int* cb = colbuf + 4LL * b;
-    if (m <= ROW_L) {
-      // registers: entry q in lane q, candidate column 4q + t in lane
-      // (4q + t) & 63, register (4q + t) >> 6
-      int e = lane < m ? inc[b + lane] : PAD;
-      e = wave_sort64(e);
-      int vv[4] = {PAD, PAD, PAD, PAD};
-      if (lane < m) {
-        inc[b + lane] = e;
-        const int k = e >> 2;
-        pair_verts(S, at[k], ai[k], aj[k], vv);
-      }
-      const int t = lane & 3, q0 = lane >> 2, q1 = 16 + (lane >> 2);
-      int w0 = __shfl(vv[0], q0, 64), w1 = __shfl(vv[1], q0, 64), w2 = __shfl(vv[2], q0, 64),
-          w3 = __shfl(vv[3], q0, 64);
-      int c0 = t == 0 ? w0 : t == 1 ? w1 : t == 2 ? w2 : w3;
-      w0 = __shfl(vv[0], q1, 64); w1 = __shfl(vv[1], q1, 64); w2 = __shfl(vv[2], q1, 64); w3 = __shfl(vv[3], q1, 64);
-      int c1 = t == 0 ? w0 : t == 1 ? w1 : t == 2 ? w2 : w3;
-      wave_sort128(c0, c1);
-      const int p0 = __shfl_up(c0, 1, 64), last0 = __shfl(c0, 63, 64);
-      int p1 = __shfl_up(c1, 1, 64);
-      if (lane == 0) p1 = last0;
-      const bool f0 = c0 != PAD && (lane == 0 || c0 != p0);
-      const bool f1 = c1 != PAD && c1 != p1;
-      const unsigned long long m0 = __ballot(f0), m1 = __ballot(f1);
-      const int u0 = __popcll(m0);
-      if (f0) cb[lanes_below(m0)] = c0;
-      if (f1) cb[u0 + lanes_below(m1)] = c1;
-      if (lane == 0) rowcnt[v] = u0 + __popcll(m1);
-      continue;
+  const int t = lane_id() >> 4;
+  for (long long v0 = 4LL * blockIdx.x; v0 < S.nv; v0 += 4LL * gridDim.x) {
+    const int v = (int)v0 + t;
+    int b = 0, m = 0;
+    if (v < S.nv) {
+      b = inc_off[v];
+      m = inc_off[v + 1] - b;
     }
-    // LDS, one wave
-    const int Pm = pow2_at_least(m);
-    for (int q = lane; q < Pm; q += 64) ent[q] = q < m ? inc[b + q] : PAD;
-    const int T = min(ROW_M_TAB, pow2_at_least(8 * m));
-    for (int q = lane; q < T; q += 64) tab[q] = EMPTY;
-    __syncthreads();
-    team_bitonic<64>(ent, Pm);
-    for (int q = lane; q < m; q += 64) {
-      int e = ent[q], k = e >> 2;
-      inc[b + q] = e;
-      int vv[4];
-      pair_verts(S, at[k], ai[k], aj[k], vv);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) set_insert(tab, T, vv[c]);
+    const bool small = v < S.nv && m <= ROW_S;
+    if (__all(!small || m == 0)) {  // nothing to sort in this group
+      if (small && (lane_id() & 15) == 0) rowcnt[v] = 0;
+    } else {
+      row_a_team(S, ai, aj, at, small, v, b, m, inc, colbuf, rowcnt);
     }
-    __syncthreads();
-    int u = 0;  // compact the set in place (a chunk is read before any of it is written)
-    for (int c = 0; c < T; c += 64) {
-      int x = tab[c + lane];
-      bool ok = x != EMPTY;
-      unsigned long long msk = __ballot(ok);
-      if (ok) tab[u + lanes_below(msk)] = x;
-      u += __popcll(msk);
+    // rows for the one-wave path of pass B: appended to mid[0 .. mid[nv]) (any order)
+    const unsigned long long lead = __ballot((lane_id() & 15) == 0 && v < S.nv && m > ROW_S && m <= ROW_M);
+    if (lead != 0) {
+      int base = 0;
+      if (lane_id() == 0) base = atomicAdd(&mid[S.nv], __popcll(lead));
+      base = __shfl(base, 0, 64);
+      if ((lead >> lane_id()) & 1ull) mid[base + lanes_below(lead)] = v;
     }
-    const int P = pow2_at_least(u > 0 ? u : 1);
-    for (int q = u + lane; q < P; q += 64) tab[q] = PAD;
-    __syncthreads();
-    team_bitonic<64>(tab, P);
-    for (int q = lane; q < u; q += 64) cb[q] = tab[q];
-    if (lane == 0) rowcnt[v] = u;
-    __syncthreads();
+#pragma unroll 1
+    for (int r = 0; r < 4; ++r) {
+      const int vr = __shfl(v, 16 * r, 64), br = __shfl(b, 16 * r, 64), mr = __shfl(m, 16 * r, 64);
+      if (vr >= S.nv || mr <= ROW_S || mr > ROW_M) continue;  // uniform over the wave
+      row_a_wave(S, ai, aj, at, vr, br, mr, inc, colbuf, rowcnt, ent, tab);
+    }
   }
 }
 
@@ -1240,15 +1388,92 @@ __device__ __forceinline__ void row_b(const SceneDev& S, const int* ai, const in
   }
 }
 
-// Pass B, rows with m <= ROW_M, one wave per row.
+// Pass B of rows with m <= ROW_S, one per 16-lane team.  Lane q < m holds
+// entry q: its pair's stencil vertices go to the team's slice of vs, its
+// gradient part into a fixed-order tree over the team's lanes.  Lane tl owns
+// column tl of each group of 16.  The entries are taken
+// four at a time: four lanes per entry copy its band (36 contiguous
+// doubles) into the team's slice of `band`, then each owner adds the 3x3
+// blocks of its columns, entries in sorted order.  Teams with m = 0 and
+// u = 0 only take part in the shuffles and barriers (a block is one wave).
+constexpr int TEAM_CH = 4;  // entries per chunk and team
+__device__ __forceinline__ void row_b_team(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,
+                                           bool mine, const int* inc, int b, int m, const int* cb, int r0, int u,
+                                           const double* G, const double* H, double* grow, int* col, double* val,
+                                           int* vs, double* band) {
+  const int lane = lane_id(), tl = lane & 15;
+  int* vst = vs + 4 * ROW_S * (lane >> 4);
+  double* bt = band + 36 * TEAM_CH * (lane >> 4);
+  int e = 0;
+  int vv[4] = {EMPTY, EMPTY, EMPTY, EMPTY};
+  double gx = 0.0, gy = 0.0, gz = 0.0;
+  if (tl < m) {
+    e = inc[b + tl];
+    const int k = e >> 2;
+    pair_verts(S, at[k], ai[k], aj[k], vv);
+    const double* gk = G + 12LL * k + 3 * (e & 3);
+    gx = gk[0]; gy = gk[1]; gz = gk[2];
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) vst[4 * tl + c] = vv[c];
+#pragma unroll
+  for (int o = 1; o < 16; o <<= 1) {
+    const double tx = __shfl_down(gx, o, 16), ty = __shfl_down(gy, o, 16), tz = __shfl_down(gz, o, 16);
+    if ((tl & (2 * o - 1)) == 0) { gx += tx; gy += ty; gz += tz; }
+  }
+  if (mine && tl == 0) { grow[0] = gx; grow[1] = gy; grow[2] = gz; }
+  const int r = tl >> 2, part = tl & 3;  // chunk entry and quarter of its band copied by this lane
+  for (int cbase = 0; !__all(cbase >= u); cbase += 16) {
+    const int ca = cbase + tl < u ? cb[cbase + tl] : EMPTY;
+    double A[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int qc = 0; !__all(qc >= m); qc += TEAM_CH) {
+      const int eq = __shfl(e, qc + r, 16);
+      __syncthreads();  // the stencils are written, the previous chunk is read
+      if (qc + r < m) {
+        const double* src = H + 144LL * (eq >> 2) + 36 * (eq & 3) + 9 * part;
+        double* dst = bt + 36 * r + 9 * part;
+#pragma unroll
+        for (int o = 0; o < 9; ++o) dst[o] = src[o];
+      }
+      __syncthreads();
+      const int nq = min(TEAM_CH, m - qc);
+#pragma unroll 1
+      for (int q = 0; q < nq; ++q) {
+        const int w[4] = {vst[4 * (qc + q)], vst[4 * (qc + q) + 1], vst[4 * (qc + q) + 2], vst[4 * (qc + q) + 3]};
+        const double* bq = bt + 36 * q;
+        const int sa = slot_of(w, ca);
+        if (sa >= 0) {
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) A[3 * i + j] += bq[12 * i + 3 * sa + j];
+        }
+      }
+    }
+    if (ca != EMPTY) {
+      col[r0 + cbase + tl] = ca;
+#pragma unroll
+      for (int o = 0; o < 9; ++o) val[9LL * (r0 + cbase + tl) + o] = A[o];
+    }
+  }
+}
+
+// Pass B for rows with m <= ROW_M, blocks of one wave.  The first
+// nmid_blocks blocks take the rows that pass A listed (ROW_S < m <= ROW_M)
+// one at a time (strided over the list); every other block takes four
+// consecutive rows and works on those with m <= ROW_S, a team each.  Block
+// 0 also stores the block count and the total energy.
 __global__ __launch_bounds__(64) void k_row_b(SceneDev S, const int* ai, const int* aj, const unsigned char* at,
                                               const int* inc_off, const int* inc, const int* colbuf, const double* G,
                                               const double* H, double* g, const int* row_ptr, int* col, double* val,
                                               long long cap, long long* nnzb, unsigned* status,
                                               const unsigned long long* act_count, long long acap,
-                                              const double* epart, double* E_out) {
-  __shared__ int vs[4 * 16];
+                                              const double* epart, double* E_out, const int* mid, int nmid_blocks) {
+  // shared by both paths: 4 teams x ROW_S stencils / 16 entries' stencils,
+  // 4 teams x TEAM_CH bands / 16 bands
+  __shared__ int vs[4 * 4 * ROW_S];
   __shared__ double band[16 * 36];
+  static_assert(4 * TEAM_CH <= 16, "team bands fit the shared band buffer");
   if (blockIdx.x == 0) {
     if (threadIdx.x == 0) {
       const long long t = row_ptr[S.nv];
@@ -1260,13 +1485,34 @@ __global__ __launch_bounds__(64) void k_row_b(SceneDev S, const int* ai, const i
     if (n > acap) n = acap;
     energy_total(epart, (n + 63) / 64, E_out);
   }
-  for (int v = blockIdx.x; v < S.nv; v += gridDim.x) {
-    const int b = inc_off[v], m = inc_off[v + 1] - b;
-    if (m > ROW_M) continue;  // block path
-    const int r0 = row_ptr[v], r1 = row_ptr[v + 1];
-    if (r1 > cap) continue;   // overflow: reported above
-    row_b<64, 16>(S, ai, aj, at, inc, b, m, colbuf + 4LL * b, r0, r1 - r0, G, H, g + 3LL * v, col, val, vs, band,
-              nullptr);
+  if ((int)blockIdx.x < nmid_blocks) {  // the listed rows, one at a time by the whole wave
+    const int n = mid[S.nv];
+    for (int q = blockIdx.x; q < n; q += nmid_blocks) {
+      const int v = mid[q];
+      const int b = inc_off[v], m = inc_off[v + 1] - b;
+      const int r0 = row_ptr[v], r1 = row_ptr[v + 1];
+      if (r1 > cap) continue;  // overflow: reported by block 0
+      row_b<64, 16>(S, ai, aj, at, inc, b, m, colbuf + 4LL * b, r0, r1 - r0, G, H, g + 3LL * v, col, val, vs, band,
+                    nullptr);
+    }
+    return;
+  }
+  const int t = lane_id() >> 4;
+  const int nteam_blocks = (int)gridDim.x - nmid_blocks;
+  for (long long v0 = 4LL * ((int)blockIdx.x - nmid_blocks); v0 < S.nv; v0 += 4LL * nteam_blocks) {
+    const int v = (int)v0 + t;
+    int b = 0, m = 0, r0 = 0, r1 = 0;
+    if (v < S.nv) {
+      b = inc_off[v];
+      m = inc_off[v + 1] - b;
+      r0 = row_ptr[v];
+      r1 = row_ptr[v + 1];
+    }
+    const bool small = v < S.nv && m <= ROW_S;
+    // columns are stored only when the row fits the output (overflow is reported above)
+    const int u = small && r1 <= cap ? r1 - r0 : 0;
+    row_b_team(S, ai, aj, at, small, inc, b, small ? m : 0, colbuf + 4LL * b, r0, u, G, H, g + 3LL * v, col, val, vs,
+               band);
   }
 }
 
@@ -1481,12 +1727,13 @@ void run_asm_structure(const SceneDev& S, const int* ai, const int* aj, const un
   const unsigned long long* nact = (const unsigned long long*)act_count;
   // incidence counts are zero on entry: k_inc_fill returns them to zero
   hipLaunchKernelGGL(k_inc_count, dim3(nblocks(acap)), dim3(256), 0, st, S, ai, aj, at, aflags, nact, acap,
-                     A.inc_cnt);
+                     A.inc_cnt, A.mid + S.nv);
   scan_excl(A.inc_cnt, A.inc_off, nullptr, S.nv + 1, A.scan_tmp, st);
   hipLaunchKernelGGL(k_inc_fill, dim3(nblocks(acap)), dim3(256), 0, st, S, ai, aj, at, aflags, nact, acap, A.inc_cnt,
                      A.inc_off, A.inc);
-  int rows_grid = (int)std::min(S.nv, 1 << 20);
-  hipLaunchKernelGGL(k_row_a, dim3(rows_grid), dim3(64), 0, st, S, ai, aj, at, A.inc_off, A.inc, A.colbuf, A.rowcnt);
+  const int rows_grid = std::max(1, std::min((S.nv + 3) / 4, 1 << 20));  // four rows a block
+  hipLaunchKernelGGL(k_row_a, dim3(rows_grid), dim3(64), 0, st, S, ai, aj, at, A.inc_off, A.inc, A.colbuf, A.rowcnt,
+                     A.mid);
   hipLaunchKernelGGL(k_row_a_big, dim3(big_grid_of(S.nv)), dim3(256), 0, st, S, ai, aj, at, A.inc_off, A.inc,
                      A.colbuf, A.rowcnt);
 }
@@ -1497,9 +1744,10 @@ void run_asm_values(const SceneDev& S, const int* ai, const int* aj, const unsig
                     const AsmWs& A, unsigned* status, hipStream_t st) {
   const unsigned long long* nact = (const unsigned long long*)act_count;
   scan_excl(A.rowcnt, row_ptr, nullptr, S.nv + 1, A.scan_tmp, st);
-  int rows_grid = (int)std::min(S.nv, 1 << 20);
-  hipLaunchKernelGGL(k_row_b, dim3(rows_grid), dim3(64), 0, st, S, ai, aj, at, A.inc_off, A.inc, A.colbuf, G, H, g,
-                     row_ptr, col, val, bsr_cap, nnzb, status, nact, acap, A.epart, E_out);
+  const int rows_grid = std::max(1, std::min((S.nv + 3) / 4, 1 << 20));  // four rows a block
+  const int mid_grid = std::min(rows_grid, 8192);                          // listed rows, strided
+  hipLaunchKernelGGL(k_row_b, dim3(mid_grid + rows_grid), dim3(64), 0, st, S, ai, aj, at, A.inc_off, A.inc, A.colbuf,
+                     G, H, g, row_ptr, col, val, bsr_cap, nnzb, status, nact, acap, A.epart, E_out, A.mid, mid_grid);
   hipLaunchKernelGGL(k_row_b_big, dim3(big_grid_of(S.nv)), dim3(256), 0, st, S, ai, aj, at, A.inc_off, A.inc,
                      A.colbuf, G, H, g, row_ptr, col, val, bsr_cap);
 }

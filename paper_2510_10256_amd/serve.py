@@ -127,7 +127,7 @@ def scene_bytes(scene, cand, act, bsr):
     nprims = scene.n_edges + (scene.n_tris + nv if scene.kind == "shell" else 0)
     buffers = 9 * cand + act * (4 + 4 + 1 + 1 + 1 + 8 + 8 + 96 + 1152) + bsr * (4 + 72) + nv * 3 * 8 * 2 + 4 * nv
     workspace = (nprims * (24 + 8 + 16 + 16) + 16 * 2 * max(4096, 2 * nprims) + 8 * 4 * (nv + scene.n_edges)
-                 + 20 * cand + 80 * act + 16 * nv)
+                 + 20 * cand + 80 * act + 20 * nv)
     return int(buffers + workspace)
 
 
