@@ -211,6 +211,8 @@ bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int
   W.placed_box = dalloc<Box>(s->allocs, ne + nt, &e);
   W.pair_cnt = dalloc<int>(s->allocs, nq, &e);
   W.pair_bsum = dalloc<int>(s->allocs, nq / 256 + 2, &e);
+  W.pair_bseg = dalloc<long long>(s->allocs, nq / 256 + 2, &e);
+  W.seg_count = dalloc<unsigned long long>(s->allocs, 1, &e);
   W.scan_tmp = dalloc<int>(s->allocs, std::max(std::max(scan_parts(nscan), scan_parts(nv + 1)), scan_parts(nq)) + 16, &e);
   if (e != hipSuccess) {
     free_list(s->allocs);
@@ -274,7 +276,7 @@ bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int
     }
     S = dev_view(s);
     run_lift_ref(S, xref, st);
-    run_broad(S, xref, W, ci, cj, ct, cap, cnt, s->d_status, st);
+    run_broad(S, xref, W, ci, cj, ct, cap, cnt, s->d_status, nullptr, nullptr, 0, st);  // no staging yet
     (void)hipMemcpyAsync(dbest, best.data(), sizeof(unsigned long long) * nc, hipMemcpyHostToDevice, st);
     run_refmin(S, ci, cj, ct, cnt, cap, dbest, st);
     long long hcnt = 0;
@@ -393,8 +395,10 @@ bf_status build_candidates(bf_scene* s, const double* x_d, bf_pairs* cand, void*
     return fail(BF_E_ARG, "build_candidates: null argument or capacity < 1");
   hipStream_t st = (hipStream_t)stream;
   s->last = st;
+  // the narrow phase's staging buffers hold the count pass's segments (they
+  // are free until filter_pairs, which runs after this call on the stream)
   run_broad(dev_view(s), x_d, s->bw, cand->i_d, cand->j_d, cand->type_d, cand->cap, (long long*)cand->count_d,
-            s->d_status, st);
+            s->d_status, s->sw.si, s->sw.sm, s->sw.cap, st);
   hipError_t he = hipGetLastError();
   return he == hipSuccess ? BF_OK : fail_hip(he, "build_candidates");
 }

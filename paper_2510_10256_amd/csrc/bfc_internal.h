@@ -60,6 +60,8 @@ struct BroadWs {
   Box* sorted_box;   // [NS]
   int* pair_cnt;     // [NQ * PQ_MAX] pairs per (query, cell subset)
   int* pair_bsum;    // [work-groups + 1] pairs per work-group of the count pass
+  long long* pair_bseg;            // [work-groups + 1] start of each group's staged pairs, -1: visit again
+  unsigned long long* seg_count;   // [1] staged pairs of this step (segments are taken in any order)
   int* scan_tmp;     // [scan partials]
   int max_cells;
 };

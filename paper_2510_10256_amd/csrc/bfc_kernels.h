@@ -20,7 +20,8 @@ void scan_excl(const int* in, int* out, const int* n_dev, int n_max, int* tmp, h
 
 // Broad phase over the positions x (FP64 [V,3]) at inflation S.h.
 void run_broad(const SceneDev& S, const double* x, const BroadWs& W, int* oi, int* oj, unsigned char* ot,
-               long long cap, long long* count, unsigned* status, hipStream_t st);
+               long long cap, long long* count, unsigned* status, int* seg_r, unsigned* seg_t, long long seg_cap,
+               hipStream_t st);
 
 // Narrow phase, filter and compaction.
 void run_narrow(const SceneDev& S, const double* x, const int* ci, const int* cj, const unsigned char* ct,

@@ -391,8 +391,9 @@ __device__ __forceinline__ void cell_range(const Grid& g, const Box& b, int* lo,
 }
 
 __global__ __launch_bounds__(256) void k_count(int nstored, int ne, const Box* box, const Grid* gp, int* cell_cnt,
-                                               int* cell_of) {
+                                               int* cell_of, unsigned long long* seg_count) {
   Grid g = *gp;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *seg_count = 0;  // segments of this step's count pass
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < nstored; p += grid_stride()) {
     int c[3];
     cell_coords(g, box[p], c);
@@ -454,9 +455,12 @@ __device__ __forceinline__ bool boxes_far_f(const Box& a, const Box& b, float ga
 // Visit the stored primitives of the sub-list for the query (triangles for a
 // point, edges with a larger id for an edge) in the rows (y, z) = sub,
 // sub + PQ, ... of the query's cell range, each row one contiguous run of
-// cells along x; count, or emit at `pos`, every non-incident pair whose
-// boxes are within h.
-template <int PQ, bool EMIT>
+// cells along x; count every non-incident pair whose boxes are within h,
+// and stage it (its stored id at stage[256 * n] while n < STAGE_K) or emit
+// it at `pos`.
+constexpr int VISIT_COUNT = 0, VISIT_STAGE = 1, VISIT_EMIT = 2;
+constexpr int STAGE_K = 16;  // candidates a count-pass thread keeps in LDS
+template <int PQ, int MODE>
 __device__ __forceinline__ int visit_pairs(const SceneDev& S, const Grid& g, const int* cell_start,
                                            const int* sorted_id, const Box* sorted_box, double hf, int qtype,
                                            int qid, const Box& qb, const int* qv, int sub, long long pos,
@@ -484,7 +488,8 @@ __device__ __forceinline__ int visit_pairs(const SceneDev& S, const Grid& g, con
         if (t0 == qid || t1 == qid || t2 == qid) continue;
         r = t;
       }
-      if (EMIT) {
+      if (MODE == VISIT_STAGE && cnt < STAGE_K) oi[256 * cnt] = r;
+      if (MODE == VISIT_EMIT) {
         long long p = pos + cnt;
         if (p < cap) {
           oi[p] = qid;
@@ -516,12 +521,28 @@ __device__ __forceinline__ void query_of(const SceneDev& S, const Box* box, int 
   }
 }
 
-// pass 1: pair count of every (query, neighbour-cell subset) thread, and the
-// total of each work-group in bsum[block] (bsum[nblocks] = 0)
+// (type, id) of query q: points first for shells, then edges
+__device__ __forceinline__ void query_id(const SceneDev& S, int q, int& qtype, int& qid) {
+  if (S.kind == 1 && q < S.nv) { qtype = BF_PT; qid = q; }
+  else { qtype = BF_EE; qid = S.kind == 1 ? q - S.nv : q; }
+}
+
+// Pass 1: pair count of every (query, row subset) thread and the total of
+// each work-group in bsum[block] (bsum[nblocks] = 0).  The pairs are staged
+// in LDS; the group takes a segment of seg_r / seg_t (one atomic per group,
+// in any order) and stores there, coalesced, the pairs of its threads that
+// found at most STAGE_K: stored id, and thread | index << 8.  bseg[block] =
+// the segment's start, or -1 when there was no room (pass 2 then visits
+// the cells of every thread again, as it does for threads over STAGE_K).
 template <int PQ>
 __global__ __launch_bounds__(256) void k_pair_count(SceneDev S, int nquery, const Box* box, const Grid* gp,
                                                     const int* cell_start, const int* sorted_id, const Box* sorted_box,
-                                                    double hf, int* cnt, int* bsum) {
+                                                    double hf, int* cnt, int* bsum, long long* bseg,
+                                                    unsigned long long* seg_count, int* seg_r, unsigned* seg_t,
+                                                    long long seg_cap) {
+  __shared__ int stage[STAGE_K * 256];
+  __shared__ int locs[256];
+  __shared__ long long s_seg;
   Grid g = *gp;
   int nt = nquery * PQ;
   int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -530,26 +551,54 @@ __global__ __launch_bounds__(256) void k_pair_count(SceneDev S, int nquery, cons
     int qtype, qid, qv[2];
     Box qb;
     query_of(S, box, t / PQ, qtype, qid, qb, qv);
-    c = visit_pairs<PQ, false>(S, g, cell_start, sorted_id, sorted_box, hf, qtype, qid, qb, qv, t % PQ, 0, 0, nullptr,
-                           nullptr, nullptr, nullptr);
+    c = visit_pairs<PQ, VISIT_STAGE>(S, g, cell_start, sorted_id, sorted_box, hf, qtype, qid, qb, qv, t % PQ, 0, 0,
+                                     stage + threadIdx.x, nullptr, nullptr, nullptr);
     cnt[t] = c;
   }
-  int tot;
+  int tot, stot;
   block_excl_scan256(c, &tot);
+  const int ks = c <= STAGE_K ? c : 0;  // staged pairs of this thread
+  locs[threadIdx.x] = block_excl_scan256(ks, &stot);
   if (threadIdx.x == 0) {
+    long long sg = -1;
+    if (stot == 0) {
+      sg = 0;
+    } else if (seg_r != nullptr) {
+      const unsigned long long a = atomicAdd(seg_count, (unsigned long long)stot);
+      if ((long long)a + stot <= seg_cap) sg = (long long)a;
+    }
+    s_seg = sg;
     bsum[blockIdx.x] = tot;
+    bseg[blockIdx.x] = sg;
     if (blockIdx.x == 0) bsum[gridDim.x] = 0;
+  }
+  __syncthreads();
+  const long long sg = s_seg;
+  if (sg < 0) return;
+  for (int q = threadIdx.x; q < stot; q += 256) {
+    int lo = 0, hi = 255;  // the thread that staged pair q: the last u with locs[u] <= q
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (locs[mid] <= q) lo = mid; else hi = mid - 1;
+    }
+    const int k = q - locs[lo];
+    seg_r[sg + q] = stage[256 * k + lo];
+    seg_t[sg + q] = (unsigned)lo | ((unsigned)k << 8);
   }
 }
 
-// pass 2: offsets from the scanned work-group totals plus an in-group scan;
-// emit in query-major order (no atomics)
+// Pass 2: the group's offset from the totals of all earlier groups plus, per
+// thread, an in-group scan; output in query-major order (no atomics).  The
+// group copies its segment (coalesced); threads whose pairs are not in it
+// visit their cells again.
 template <int PQ>
 __global__ __launch_bounds__(256) void k_pair_emit(SceneDev S, int nquery, const Box* box, const Grid* gp,
                                                    const int* cell_start, const int* sorted_id, const Box* sorted_box,
-                                                   double hf, const int* cnt, const int* bsum, int* oi, int* oj,
+                                                   double hf, const int* cnt, const int* bsum, const long long* bseg,
+                                                   const int* seg_r, const unsigned* seg_t, int* oi, int* oj,
                                                    unsigned char* ot, long long cap, long long* count,
                                                    unsigned* status) {
+  __shared__ int locs[256];
   Grid g = *gp;
   int nt = nquery * PQ;
   // this block's offset: the pairs of all earlier blocks of the count pass
@@ -560,15 +609,36 @@ __global__ __launch_bounds__(256) void k_pair_emit(SceneDev S, int nquery, const
   const long long before = block_sum256(part);
   if (blockIdx.x == 0 && threadIdx.x == 0) *count = before;
   const long long base = blockIdx.x == 0 ? 0 : before;
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int c = t < nt ? cnt[t] : 0;
-  int loc = block_excl_scan256(c, nullptr);
-  if (c == 0) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = t < nt ? cnt[t] : 0;
+  const int loc = block_excl_scan256(c, nullptr);
+  int stot;
+  block_excl_scan256(c <= STAGE_K ? c : 0, &stot);
+  locs[threadIdx.x] = loc;
+  __syncthreads();
+  const long long sg = bseg[blockIdx.x];
+  if (sg >= 0) {
+    for (int q = threadIdx.x; q < stot; q += 256) {
+      const unsigned w = seg_t[sg + q];
+      const int u = (int)(w & 255u);
+      const long long p = base + locs[u] + (int)(w >> 8);
+      if (p >= cap) {
+        atomicOr(status, (unsigned)BF_S_CAND_OVERFLOW);
+        continue;
+      }
+      int qtype, qid;
+      query_id(S, (int)(((long long)blockIdx.x * 256 + u) / PQ), qtype, qid);
+      oi[p] = qid;
+      oj[p] = seg_r[sg + q];
+      ot[p] = (unsigned char)qtype;
+    }
+  }
+  if (c == 0 || (sg >= 0 && c <= STAGE_K)) return;
   int qtype, qid, qv[2];
   Box qb;
   query_of(S, box, t / PQ, qtype, qid, qb, qv);
-  visit_pairs<PQ, true>(S, g, cell_start, sorted_id, sorted_box, hf, qtype, qid, qb, qv, t % PQ, base + loc, cap, oi,
-                        oj, ot, status);
+  visit_pairs<PQ, VISIT_EMIT>(S, g, cell_start, sorted_id, sorted_box, hf, qtype, qid, qb, qv, t % PQ, base + loc, cap,
+                              oi, oj, ot, status);
 }
 
 // ---------------------------------------------------------------------------
@@ -1664,16 +1734,20 @@ void run_lift_ref(const SceneDev& S, double* xref, hipStream_t st) {
 
 template <int PQ>
 static void launch_pairs(const SceneDev& S, int nquery, const BroadWs& W, int* oi, int* oj, unsigned char* ot,
-                         long long cap, long long* count, unsigned* status, hipStream_t st) {
+                         long long cap, long long* count, unsigned* status, int* seg_r, unsigned* seg_t,
+                         long long seg_cap, hipStream_t st) {
   int nb = (nquery * PQ + 255) / 256;
   hipLaunchKernelGGL(k_pair_count<PQ>, dim3(nb), dim3(256), 0, st, S, nquery, W.box, W.grid, W.cell_start,
-                     W.sorted_id, W.sorted_box, S.h, W.pair_cnt, W.pair_bsum);
+                     W.sorted_id, W.sorted_box, S.h, W.pair_cnt, W.pair_bsum, W.pair_bseg, W.seg_count, seg_r, seg_t,
+                     seg_cap);
   hipLaunchKernelGGL(k_pair_emit<PQ>, dim3(nb), dim3(256), 0, st, S, nquery, W.box, W.grid, W.cell_start,
-                     W.sorted_id, W.sorted_box, S.h, W.pair_cnt, W.pair_bsum, oi, oj, ot, cap, count, status);
+                     W.sorted_id, W.sorted_box, S.h, W.pair_cnt, W.pair_bsum, W.pair_bseg, seg_r, seg_t, oi, oj, ot,
+                     cap, count, status);
 }
 
 void run_broad(const SceneDev& S, const double* x, const BroadWs& W, int* oi, int* oj, unsigned char* ot,
-               long long cap, long long* count, unsigned* status, hipStream_t st) {
+               long long cap, long long* count, unsigned* status, int* seg_r, unsigned* seg_t, long long seg_cap,
+               hipStream_t st) {
   int np = S.ne + S.nt + (S.kind == 1 ? S.nv : 0);
   int nstored = S.ne + S.nt;
   int nquery = S.kind == 1 ? S.nv + S.ne : S.ne;
@@ -1683,17 +1757,17 @@ void run_broad(const SceneDev& S, const double* x, const BroadWs& W, int* oi, in
                      W.done, S.h, W.max_cells, W.grid, count);
   // cell counts are zero on entry: the scatter below returns them to zero
   hipLaunchKernelGGL(k_count, dim3(nblocks(nstored)), dim3(256), 0, st, nstored, S.ne, W.box, W.grid, W.cell_cnt,
-                     W.cell_of);
+                     W.cell_of, W.seg_count);
   scan_excl(W.cell_cnt, W.cell_start, nscan_dev, nscan_max, W.scan_tmp, st);
   hipLaunchKernelGGL(k_scatter, dim3(nblocks(nstored)), dim3(256), 0, st, nstored, W.box, W.cell_of, W.cell_cnt,
                      W.cell_start, W.placed_id, W.placed_box);
   hipLaunchKernelGGL(k_cell_order, dim3(nblocks(nstored)), dim3(256), 0, st, nstored, W.cell_of, W.cell_start,
                      W.placed_id, W.placed_box, W.sorted_id, W.sorted_box);
-  // one thread per (query, cell subset): no grid-stride here
+  // one thread per (query, row subset): no grid-stride here
   switch (S.pq) {
-    case 2: launch_pairs<2>(S, nquery, W, oi, oj, ot, cap, count, status, st); break;
-    case 8: launch_pairs<8>(S, nquery, W, oi, oj, ot, cap, count, status, st); break;
-    default: launch_pairs<4>(S, nquery, W, oi, oj, ot, cap, count, status, st); break;
+    case 2: launch_pairs<2>(S, nquery, W, oi, oj, ot, cap, count, status, seg_r, seg_t, seg_cap, st); break;
+    case 8: launch_pairs<8>(S, nquery, W, oi, oj, ot, cap, count, status, seg_r, seg_t, seg_cap, st); break;
+    default: launch_pairs<4>(S, nquery, W, oi, oj, ot, cap, count, status, seg_r, seg_t, seg_cap, st); break;
   }
 }
 
