@@ -154,6 +154,31 @@ __global__ __launch_bounds__(256) void k_scan_down(const int* in, int* out, cons
   }
 }
 
+// Down-sweep for up to SCAN2_MAX_BLOCKS tiles that sums the earlier tiles'
+// totals itself (no separate partials pass).
+__global__ __launch_bounds__(256) void k_scan_down2(const int* in, int* out, const int* n_dev, int n_const,
+                                                    const int* part) {
+  int n = n_dev ? *n_dev : n_const;
+  int base = blockIdx.x * SCAN_TILE;
+  if (base >= n) return;
+  const long long before = block_sum256(threadIdx.x < blockIdx.x ? part[threadIdx.x] : 0);
+  int v[SCAN_ITEMS];
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    int i = base + threadIdx.x * SCAN_ITEMS + k;
+    v[k] = i < n ? in[i] : 0;
+    s += v[k];
+  }
+  int run = block_excl_scan256(s, nullptr) + (int)before;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    int i = base + threadIdx.x * SCAN_ITEMS + k;
+    if (i < n) out[i] = run;
+    run += v[k];
+  }
+}
+
 // one work-group scan for short arrays (n <= SCAN1_MAX)
 __global__ __launch_bounds__(1024) void k_scan1(const int* in, int* out, const int* n_dev, int n_const) {
   int n = n_dev ? *n_dev : n_const;
@@ -200,6 +225,10 @@ void scan_excl(const int* in, int* out, const int* n_dev, int n_max, int* tmp, h
   int nb = (n_max + SCAN_TILE - 1) / SCAN_TILE;
   if (nb < 1) nb = 1;
   hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(256), 0, st, in, n_dev, n_max, tmp);
+  if (nb <= 256) {  // each tile sums the earlier tiles' totals itself
+    hipLaunchKernelGGL(k_scan_down2, dim3(nb), dim3(256), 0, st, in, out, n_dev, n_max, tmp);
+    return;
+  }
   hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, tmp, n_dev, n_max);
   hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(256), 0, st, in, out, n_dev, n_max, tmp);
 }
