@@ -11,7 +11,8 @@ results (sums over pairs, Sec. 3 and App. A: the global energy, gradient and
 Hessian fed to the Newton solve).
 
 Functions whose parity is not pinned by an independent check: none; see
-``tests/test_oracle_pins.py`` for the pin of each function.
+``tests/test_oracle_pins.py`` and ``tests/test_oracle_accd.py`` for the pin
+of each function.
 """
 from __future__ import annotations
 
@@ -73,6 +74,13 @@ def lib():
                                        P, P, P, P, P, C.c_int32]
         L.orc_barrier_scalar.argtypes = [C.c_double, C.c_double, C.c_double, P, P, P]
         L.orc_psd_project.argtypes = [C.c_int32, P, P, P]
+        L.orc_accd_pair.argtypes = [C.c_int32, P, P, C.c_double, C.c_double, C.c_int32, P, P]
+        L.orc_max_step.argtypes = [C.POINTER(_Scene), P, P, C.c_double, C.c_int32, C.c_int32, C.c_int32]
+        L.orc_max_step.restype = C.c_void_p
+        L.orc_ms_count.argtypes = [P]
+        L.orc_ms_count.restype = C.c_int64
+        L.orc_ms_get.argtypes = [P] * 8
+        L.orc_ms_free.argtypes = [P]
         _lib = L
     return _lib
 
@@ -221,3 +229,50 @@ def assemble(res, n_verts):
     col = np.array([c for (_, c) in keys], np.int32)
     val = np.array([blocks[k] for k in keys]).reshape(-1, 3, 3) if keys else np.zeros((0, 3, 3))
     return dict(E=E, g=g, row_ptr=row_ptr, col=col, val=val)
+
+
+# ---- line search (Sec. 3.3, last paragraph; App. A) --------------------------
+
+def energy(scene, x, filter_mode=0, eta=None, kappa=None, nthreads=0):
+    """Energy-only evaluation at positions x: the sum of the filtered barrier
+    over the active pairs (+inf if any active pair is at or inside its
+    offset), in the order of the sorted pair list."""
+    res = evaluate(scene, x, mode=1, derivs=False, filter_mode=filter_mode, eta=eta, kappa=kappa,
+                   nthreads=nthreads)
+    act = (res["flags"] & F_ACTIVE) != 0
+    return float(np.sum(res["E"][act])) if act.any() else 0.0, res
+
+
+def accd_pair(ptype, X, P, xi, s=0.1, max_iter=65536):
+    """Additive CCD of one pair (4 local vertices X, displacements P, offset
+    xi): (t, iterations)."""
+    X = np.ascontiguousarray(X, np.float64).reshape(12)
+    P = np.ascontiguousarray(P, np.float64).reshape(12)
+    t = np.zeros(1)
+    it = np.zeros(1, np.int32)
+    lib().orc_accd_pair(int(ptype), _p(X), _p(P), float(xi), float(s), int(max_iter), _p(t), _p(it))
+    return float(t[0]), int(it[0])
+
+
+def max_step(scene, x, p, s=0.1, max_iter=65536, mode=1, filter_mode=0, eta=None, nthreads=0):
+    """ACCD over the pairs whose boxes swept from x to x + p are within h,
+    each with its filtered offset (eta, or 0 for filtered stencils).
+
+    Returns dict(t=min step (1 if no pair), ptype, i, j, filtered, iters, xi,
+    tpair) with the pairs sorted by (ptype, i, j)."""
+    x = np.ascontiguousarray(x, np.float64)
+    p = np.ascontiguousarray(p, np.float64)
+    sc, keep = _scene_struct(scene, filter_mode, eta)
+    L = lib()
+    h = L.orc_max_step(C.byref(sc), _p(x), _p(p), float(s), int(max_iter), int(mode), int(nthreads))
+    try:
+        n = L.orc_ms_count(h)
+        out = dict(ptype=np.zeros(n, np.int32), i=np.zeros(n, np.int32), j=np.zeros(n, np.int32),
+                   filtered=np.zeros(n, np.int32), iters=np.zeros(n, np.int32), xi=np.zeros(n),
+                   tpair=np.zeros(n))
+        L.orc_ms_get(h, _p(out["ptype"]), _p(out["i"]), _p(out["j"]), _p(out["filtered"]),
+                     _p(out["iters"]), _p(out["xi"]), _p(out["tpair"]))
+    finally:
+        L.orc_ms_free(h)
+    out["t"] = float(out["tpair"].min()) if n else 1.0
+    return out

@@ -25,7 +25,12 @@
 //     does not spell out the projection, this is the reading used);
 //   * decisions "d < a", "d <= eta" and "dbar < h" made in double precision
 //     and, inside a relative guard band of 1e-9, re-made in binary128
-//     (__float128) from the same formula.
+//     (__float128) from the same formula;
+//   * line search (Sec. 3.3, last paragraph; App. A): additive CCD (ACCD, Li
+//     et al. 2021) per pair with the offset of Eq. 4 (eta for ordinary pairs,
+//     0 for filtered stencils), over the pairs whose boxes swept from x to
+//     x + p come within h.  The energy-only evaluation at a trial point is
+//     orc_evaluate without derivatives.
 //
 // Build: g++ -O2 -std=c++17 -fopenmp -ffp-contract=off -shared -fPIC
 //        oracle.cpp -o liboracle.so -lquadmath
@@ -684,6 +689,71 @@ void prim_box(const Mesh& m, const double* x, int role, int id, double* lo, doub
     }
 }
 
+// ---------------------------------------------------------------------------
+// Line search: additive CCD with the filtered offsets.
+//
+// ACCD (Li, Kaufman and Jiang 2021, "Codimensional Incremental Potential
+// Contact", additive CCD) advances the stencil along its displacement in
+// steps that cannot close more than a fixed fraction of the remaining gap
+// d - xi: the distance between the two primitives shrinks at most at the rate
+// lp (the largest displacement on one side plus the largest on the other,
+// after removing the stencil's mean displacement, which does not change any
+// distance).  The first step closes (1 - s) of the gap, every later one 0.9
+// of the current gap; the search stops before the step after which the gap
+// fell below s times the initial gap, or when the accumulated step passes the
+// full step 1.  The gap is written (D - xi^2) / (sqrt(D) + xi) (no
+// cancellation when xi is close to d).
+// ---------------------------------------------------------------------------
+inline double accd_gap(double D, double xi) { return (D - xi * xi) / (std::sqrt(D) + xi); }
+
+double accd_pair(int ptype, const double* X0, const double* P0, double xi, double s, int max_iter, int* iters) {
+  double X[12], P[12], pm[3] = {0.0, 0.0, 0.0};
+  for (int v = 0; v < 4; ++v)
+    for (int c = 0; c < 3; ++c) pm[c] += P0[3 * v + c];
+  for (int c = 0; c < 3; ++c) pm[c] /= 4.0;
+  for (int k = 0; k < 12; ++k) { X[k] = X0[k]; P[k] = P0[k] - pm[k % 3]; }
+  double nrm[4];
+  for (int v = 0; v < 4; ++v) nrm[v] = std::sqrt(dot3(P + 3 * v, P + 3 * v));
+  // point-triangle: the point against the triangle's vertices; edge-edge: one
+  // edge's endpoints against the other's
+  const double lp = ptype == 0 ? nrm[0] + std::max(nrm[1], std::max(nrm[2], nrm[3]))
+                               : std::max(nrm[0], nrm[1]) + std::max(nrm[2], nrm[3]);
+  *iters = 0;
+  if (lp == 0.0) return 1.0;
+  const double gap0 = accd_gap(classify(ptype, X).D, xi);
+  if (!(gap0 > 0.0)) return 0.0;  // already at or inside the offset: no step is safe
+  const double g = s * gap0;
+  double t = 0.0, tl = (1.0 - s) * gap0 / lp;
+  for (int it = 0; it < max_iter; ++it) {
+    *iters = it + 1;
+    for (int k = 0; k < 12; ++k) X[k] = X[k] + tl * P[k];
+    const double gap = accd_gap(classify(ptype, X).D, xi);
+    if (t > 0.0 && gap < g) break;
+    t += tl;
+    if (t > 1.0) return 1.0;
+    tl = 0.9 * gap / lp;
+  }
+  return t;
+}
+
+// Box of a primitive's vertices at x and at x + p (the straight-line sweep).
+void swept_box(const Mesh& m, const double* x, const double* p, int role, int id, double* lo, double* hi) {
+  int vs[3]; int nvs;
+  if (role == 0) { vs[0] = id; nvs = 1; }
+  else if (role == 1) { vs[0] = m.edges[2 * id]; vs[1] = m.edges[2 * id + 1]; nvs = 2; }
+  else { vs[0] = m.tris[3 * id]; vs[1] = m.tris[3 * id + 1]; vs[2] = m.tris[3 * id + 2]; nvs = 3; }
+  for (int c = 0; c < 3; ++c) { lo[c] = INFINITY; hi[c] = -INFINITY; }
+  for (int k = 0; k < nvs; ++k)
+    for (int c = 0; c < 3; ++c) {
+      const double a = x[3 * vs[k] + c], b = a + p[3 * vs[k] + c];
+      lo[c] = std::min(lo[c], std::min(a, b));
+      hi[c] = std::max(hi[c], std::max(a, b));
+    }
+}
+
+struct StepRec { int ptype, i, j, filtered, iters; double xi, t; };
+struct StepResult { std::vector<StepRec> recs; };
+
 }  // namespace
 
 // ===========================================================================
@@ -887,5 +957,115 @@ int32_t orc_decide(int32_t code, const double* X, double thr, int32_t lt, int32_
 void orc_psd_project(int32_t n, const double* A, double* Ap, double* evals) {
   psd_project(n, A, Ap, evals);
 }
+
+// ACCD of one pair of 4 local vertices X with displacements P and offset xi.
+void orc_accd_pair(int32_t ptype, const double* X, const double* P, double xi, double s, int32_t max_iter,
+                   double* t, int32_t* iters) {
+  int it = 0;
+  *t = accd_pair(ptype, X, P, xi, s, max_iter, &it);
+  *iters = it;
+}
+
+// ACCD over the pairs of the universe whose swept boxes are within h on every
+// axis (gap max(lo_b - hi_a, lo_a - hi_b) < h in double), each with its
+// filtered offset; records sorted by (ptype, i, j).  The step is the minimum
+// of their t.  mode 0: all pairs (the definition); mode 1: the same pairs,
+// pruned first by a sweep along x with a few ulps of slack.
+void* orc_max_step(const orc_scene* s, const double* x, const double* p, double sfac, int32_t max_iter,
+                   int32_t mode, int32_t nthreads) {
+  Mesh m = make_mesh(s);
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+  int T = omp_get_max_threads();
+  std::vector<std::vector<StepRec>> recs(T);
+  struct B { int id; double lo[3], hi[3]; };
+  std::vector<B> pts, egs, trs;
+  if (m.kind == 1)
+    for (int64_t v = 0; v < m.nv; ++v) { B b; b.id = (int)v; swept_box(m, x, p, 0, (int)v, b.lo, b.hi); pts.push_back(b); }
+  for (int64_t e = 0; e < m.ne; ++e) { B b; b.id = (int)e; swept_box(m, x, p, 1, (int)e, b.lo, b.hi); egs.push_back(b); }
+  if (m.kind == 1)
+    for (int64_t t = 0; t < m.nt; ++t) { B b; b.id = (int)t; swept_box(m, x, p, 2, (int)t, b.lo, b.hi); trs.push_back(b); }
+  double amax = 0.0;
+  for (int64_t k = 0; k < 3 * m.nv; ++k) amax = std::max(amax, std::fabs(x[k]) + std::fabs(p[k]));
+  const double lim = m.h * (1.0 + 1e-12) + 1e-14 * amax;  // pruning only
+  auto within_h = [&](const B& a, const B& b) {  // the definition of the pair set
+    for (int c = 0; c < 3; ++c)
+      if (!(std::max(b.lo[c] - a.hi[c], a.lo[c] - b.hi[c]) < m.h)) return false;
+    return true;
+  };
+  auto visit = [&](int ptype, int i, int j, const B& A, const B& Bb) {
+    if (incident(m, ptype, i, j) || !within_h(A, Bb)) return;
+    int verts[4];
+    double X[12], P[12];
+    gather(m, x, ptype, i, j, verts, X);
+    for (int k = 0; k < 4; ++k)
+      for (int c = 0; c < 3; ++c) P[3 * k + c] = p[3 * verts[k] + c];
+    StepRec r;
+    r.ptype = ptype; r.i = i; r.j = j;
+    r.filtered = is_filtered(m, ptype, i, j) ? 1 : 0;
+    r.xi = r.filtered ? 0.0 : m.eta;  // Eq. 4: filtered stencils have no offset
+    r.t = accd_pair(ptype, X, P, r.xi, sfac, max_iter, &r.iters);
+    recs[omp_get_thread_num()].push_back(r);
+  };
+  auto by_lo0 = [](const B& a, const B& b) { return a.lo[0] < b.lo[0] || (a.lo[0] == b.lo[0] && a.id < b.id); };
+  if (mode == 0) {
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t a = 0; a < m.ne; ++a)
+      for (int64_t b = a + 1; b < m.ne; ++b) visit(1, (int)a, (int)b, egs[a], egs[b]);
+    if (m.kind == 1) {
+      #pragma omp parallel for schedule(dynamic, 16)
+      for (int64_t v = 0; v < m.nv; ++v)
+        for (int64_t t = 0; t < m.nt; ++t) visit(0, (int)v, (int)t, pts[v], trs[t]);
+    }
+  } else {
+    std::vector<B> es = egs;
+    std::sort(es.begin(), es.end(), by_lo0);
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t k = 0; k < (int64_t)es.size(); ++k)
+      for (size_t l = k + 1; l < es.size(); ++l) {
+        if (es[l].lo[0] - es[k].hi[0] >= lim) break;
+        const B& A = es[k].id < es[l].id ? es[k] : es[l];
+        const B& Bb = es[k].id < es[l].id ? es[l] : es[k];
+        visit(1, A.id, Bb.id, A, Bb);
+      }
+    if (m.kind == 1) {
+      std::vector<B> ts = trs;
+      std::sort(ts.begin(), ts.end(), by_lo0);
+      double wmax = 0.0;
+      for (const B& t : ts) wmax = std::max(wmax, t.hi[0] - t.lo[0]);
+      #pragma omp parallel for schedule(dynamic, 64)
+      for (int64_t v = 0; v < m.nv; ++v) {
+        const B& A = pts[v];
+        double lo_bound = A.lo[0] - lim - wmax;
+        size_t l = std::lower_bound(ts.begin(), ts.end(), lo_bound,
+                                    [](const B& q, double val) { return q.lo[0] < val; }) - ts.begin();
+        for (; l < ts.size(); ++l) {
+          if (ts[l].lo[0] - A.hi[0] >= lim) break;
+          visit(0, (int)v, ts[l].id, A, ts[l]);
+        }
+      }
+    }
+  }
+  StepResult* res = new StepResult;
+  for (auto& v : recs) res->recs.insert(res->recs.end(), v.begin(), v.end());
+  std::sort(res->recs.begin(), res->recs.end(), [](const StepRec& a, const StepRec& b) {
+    if (a.ptype != b.ptype) return a.ptype < b.ptype;
+    if (a.i != b.i) return a.i < b.i;
+    return a.j < b.j;
+  });
+  return res;
+}
+
+int64_t orc_ms_count(void* h) { return (int64_t)((StepResult*)h)->recs.size(); }
+
+void orc_ms_get(void* h, int32_t* ptype, int32_t* pi, int32_t* pj, int32_t* filtered, int32_t* iters, double* xi,
+                double* t) {
+  const auto& R = ((StepResult*)h)->recs;
+  for (size_t k = 0; k < R.size(); ++k) {
+    ptype[k] = R[k].ptype; pi[k] = R[k].i; pj[k] = R[k].j; filtered[k] = R[k].filtered;
+    iters[k] = R[k].iters; xi[k] = R[k].xi; t[k] = R[k].t;
+  }
+}
+
+void orc_ms_free(void* h) { delete (StepResult*)h; }
 
 }  // extern "C"
