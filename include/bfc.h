@@ -195,9 +195,47 @@ bf_status eval_barrier(bf_scene* s, const double* x_d, const bf_active* act, bf_
 bf_status assemble_grad_hess(bf_scene* s, const bf_active* act, const bf_local* loc, double* E_d,
                              double* g_d, bf_bsr* H, void* stream);
 
+/* ---- line search (Sec. 3.3, last paragraph; App. A) ---------------------
+ * The Newton iteration's line search needs a step that keeps every pair
+ * outside its offset, and the energy alone at trial points.  The offsets
+ * follow Eq. 4: eta for ordinary pairs, 0 for filtered stencil pairs.
+ *
+ * build_candidates_swept: the broad phase of build_candidates on the boxes
+ * swept by each primitive from x to x + p (p_d: [V,3] FP64 displacements,
+ * the search direction times the largest step).  The list holds every pair
+ * whose d(x + tau p) < h for some tau in [0, 1], so it serves the CCD below
+ * and eval_energy at any point of the segment.
+ *
+ * max_step_accd: for every candidate whose exact swept boxes (vertices at x
+ * and x + p, FP64) are closer than h on every axis, additive CCD (Li et al.
+ * 2021) with the pair's offset xi: steps of (1 - accd_s) of the gap d - xi,
+ * then 0.9 of the current gap, over the bound on the relative motion after
+ * removing the stencil's mean displacement; the search stops before the
+ * step after which the gap falls below accd_s of its initial value, at the
+ * full step 1, or after max_iter steps.  t_d[1] (device) = the smallest step
+ * in [0, 1] (0 if a pair starts at or inside its offset, 1 if there is no
+ * pair).  tpair_d (device, [cand->cap], may be NULL) receives each
+ * candidate's step, or -1 for candidates outside the swept set.  accd_s in
+ * (0, 1) (0.1 is usual), max_iter >= 1; BF_E_ARG otherwise.
+ *
+ * eval_energy: E_d[1] (device) = the filtered barrier energy (Eq. 2, Eq. 4)
+ * of the candidates at positions x_d, with the decisions of filter_pairs;
+ * +inf if a pair is at or inside its offset.  The candidates must include
+ * every pair with d < h at x_d (a build_candidates list at x_d, or a swept
+ * list whose segment holds x_d).  The sum runs in a fixed order: repeatable
+ * bit for bit.
+ *
+ * All three enqueue on `stream` and do not synchronise; the workspace of the
+ * last two is per scene (calls on one scene are stream-ordered). */
+bf_status build_candidates_swept(bf_scene* s, const double* x_d, const double* p_d, bf_pairs* cand,
+                                 void* stream);
+bf_status max_step_accd(bf_scene* s, const double* x_d, const double* p_d, const bf_pairs* cand,
+                        double accd_s, int32_t max_iter, double* t_d, double* tpair_d, void* stream);
+bf_status eval_energy(bf_scene* s, const double* x_d, const bf_pairs* cand, double* E_d, void* stream);
+
 /* ---- tuning ---------------------------------------------------------------
  * Threads per broad-phase query (2, 4 or 8; default 4): more threads split a
- * query's 27 neighbour cells finer (small scenes, few queries), fewer cost
+ * query's rows of grid cells finer (small scenes, few queries), fewer cost
  * less bookkeeping (large scenes).  bf_scene_tune times build_candidates with
  * each choice on the positions x_d (reps timed launches each, median) and
  * keeps the fastest; it synchronises and must not be called inside a

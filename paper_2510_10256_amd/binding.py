@@ -27,8 +27,8 @@ BF_F_FILTERED, BF_F_INFEASIBLE = 1, 4
 
 EXPORTED = ["bf_scene_create", "bf_scene_reserve", "bf_scene_destroy", "bf_scene_info", "build_candidates",
             "filter_pairs", "eval_barrier", "assemble_grad_hess", "bf_scene_set_pq", "bf_scene_tune",
-            "bf_batch_create", "bf_batch_step", "bf_batch_info", "bf_batch_destroy", "bf_status_word",
-            "bf_last_error"]
+            "bf_batch_create", "bf_batch_step", "bf_batch_info", "bf_batch_destroy", "build_candidates_swept",
+            "max_step_accd", "eval_energy", "bf_status_word", "bf_last_error"]
 
 
 def build(verbose: bool = False) -> str:
@@ -103,6 +103,9 @@ def lib():
         L.bf_batch_step.argtypes = [P, P]
         L.bf_batch_info.argtypes = [P, C.POINTER(C.c_int32), P]
         L.bf_batch_destroy.argtypes = [P]
+        L.build_candidates_swept.argtypes = [P, P, P, C.POINTER(Pairs), P]
+        L.max_step_accd.argtypes = [P, P, P, C.POINTER(Pairs), C.c_double, C.c_int32, P, P, P]
+        L.eval_energy.argtypes = [P, P, C.POINTER(Pairs), P, P]
         L.bf_status_word.argtypes = [P, C.POINTER(C.c_uint32), C.c_int32]
         L.bf_last_error.restype = C.c_char_p
         for name in EXPORTED[:-1]:
@@ -214,6 +217,30 @@ class ContactScene:
         self.filter_pairs(x)
         self.eval_barrier(x)
         self.assemble_grad_hess()
+
+    # -- line search -----------------------------------------------------------
+    def build_candidates_swept(self, x, p):
+        """Candidates for the whole segment x -> x + p (enqueued, no sync)."""
+        _check(lib().build_candidates_swept(self.handle, _ptr(x), _ptr(p), C.byref(self._cand),
+                                            C.c_void_p(self._stream())), "build_candidates_swept")
+
+    def max_step(self, x, p, accd_s=0.1, max_iter=65536, per_pair=False):
+        """Additive CCD step over the swept candidates (run build_candidates_swept
+        first).  Returns a device tensor t[1] (and per-candidate steps, -1 outside
+        the swept set, when per_pair)."""
+        t = self.torch.zeros(1, dtype=self.torch.float64, device=self.device)
+        tp = self.torch.zeros(self.cand_cap, dtype=self.torch.float64, device=self.device) if per_pair else None
+        _check(lib().max_step_accd(self.handle, _ptr(x), _ptr(p), C.byref(self._cand), float(accd_s),
+                                   int(max_iter), _ptr(t), _ptr(tp) if tp is not None else None,
+                                   C.c_void_p(self._stream())), "max_step_accd")
+        return (t, tp) if per_pair else t
+
+    def eval_energy(self, x, out=None):
+        """Energy alone at x over the current candidates; a device tensor E[1]."""
+        E = out if out is not None else self.torch.zeros(1, dtype=self.torch.float64, device=self.device)
+        _check(lib().eval_energy(self.handle, _ptr(x), C.byref(self._cand), _ptr(E), C.c_void_p(self._stream())),
+               "eval_energy")
+        return E
 
     def set_pq(self, pq):
         """Threads per broad-phase query (2, 4 or 8)."""

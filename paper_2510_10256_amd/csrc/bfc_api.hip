@@ -22,6 +22,7 @@ struct bf_scene {
   double* d_dmin = nullptr;
   double* d_thr2 = nullptr;
   unsigned* d_status = nullptr;
+  double* d_line = nullptr;  // [LINE_BLOCKS] per-block minima / sums of the line-search calls
   std::vector<int> comp_h;
   std::vector<double> dmin2_h, dmin_h;
   BroadWs bw{};
@@ -193,6 +194,7 @@ bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int
   s->d_ref = dalloc<double>(s->allocs, nref, &e);
   s->d_comp = dalloc<int>(s->allocs, nv, &e);
   s->d_status = dalloc<unsigned>(s->allocs, 4, &e);
+  s->d_line = dalloc<double>(s->allocs, LINE_BLOCKS, &e);
   int np = ne + nt + (s->kind == BF_SHELL ? nv : 0);
   BroadWs& W = s->bw;
   W.max_cells = (int)std::min<long long>(std::max<long long>(4096, 2LL * np), 1LL << 26);
@@ -276,7 +278,7 @@ bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int
     }
     S = dev_view(s);
     run_lift_ref(S, xref, st);
-    run_broad(S, xref, W, ci, cj, ct, cap, cnt, s->d_status, nullptr, nullptr, 0, st);  // no staging yet
+    run_broad(S, xref, nullptr, W, ci, cj, ct, cap, cnt, s->d_status, nullptr, nullptr, 0, st);  // no staging yet
     (void)hipMemcpyAsync(dbest, best.data(), sizeof(unsigned long long) * nc, hipMemcpyHostToDevice, st);
     run_refmin(S, ci, cj, ct, cnt, cap, dbest, st);
     long long hcnt = 0;
@@ -397,10 +399,47 @@ bf_status build_candidates(bf_scene* s, const double* x_d, bf_pairs* cand, void*
   s->last = st;
   // the narrow phase's staging buffers hold the count pass's segments (they
   // are free until filter_pairs, which runs after this call on the stream)
-  run_broad(dev_view(s), x_d, s->bw, cand->i_d, cand->j_d, cand->type_d, cand->cap, (long long*)cand->count_d,
-            s->d_status, s->sw.si, s->sw.sm, s->sw.cap, st);
+  run_broad(dev_view(s), x_d, nullptr, s->bw, cand->i_d, cand->j_d, cand->type_d, cand->cap,
+            (long long*)cand->count_d, s->d_status, s->sw.si, s->sw.sm, s->sw.cap, st);
   hipError_t he = hipGetLastError();
   return he == hipSuccess ? BF_OK : fail_hip(he, "build_candidates");
+}
+
+bf_status build_candidates_swept(bf_scene* s, const double* x_d, const double* p_d, bf_pairs* cand, void* stream) {
+  if (!s || !x_d || !p_d || !cand || !cand->i_d || !cand->j_d || !cand->type_d || !cand->count_d || cand->cap < 1)
+    return fail(BF_E_ARG, "build_candidates_swept: null argument or capacity < 1");
+  hipStream_t st = (hipStream_t)stream;
+  s->last = st;
+  run_broad(dev_view(s), x_d, p_d, s->bw, cand->i_d, cand->j_d, cand->type_d, cand->cap, (long long*)cand->count_d,
+            s->d_status, s->sw.si, s->sw.sm, s->sw.cap, st);
+  hipError_t he = hipGetLastError();
+  return he == hipSuccess ? BF_OK : fail_hip(he, "build_candidates_swept");
+}
+
+bf_status max_step_accd(bf_scene* s, const double* x_d, const double* p_d, const bf_pairs* cand, double accd_s,
+                        int32_t max_iter, double* t_d, double* tpair_d, void* stream) {
+  if (!s || !x_d || !p_d || !cand || !cand->i_d || !cand->j_d || !cand->type_d || !cand->count_d || !t_d ||
+      cand->cap < 1)
+    return fail(BF_E_ARG, "max_step_accd: null argument or capacity < 1");
+  if (!(accd_s > 0.0 && accd_s < 1.0) || max_iter < 1)
+    return fail(BF_E_ARG, "max_step_accd: accd_s must lie in (0, 1) and max_iter be at least 1");
+  hipStream_t st = (hipStream_t)stream;
+  s->last = st;
+  run_accd(dev_view(s), x_d, p_d, cand->i_d, cand->j_d, cand->type_d, (const long long*)cand->count_d, cand->cap,
+           accd_s, max_iter, tpair_d, s->d_line, t_d, st);
+  hipError_t he = hipGetLastError();
+  return he == hipSuccess ? BF_OK : fail_hip(he, "max_step_accd");
+}
+
+bf_status eval_energy(bf_scene* s, const double* x_d, const bf_pairs* cand, double* E_d, void* stream) {
+  if (!s || !x_d || !cand || !cand->i_d || !cand->j_d || !cand->type_d || !cand->count_d || !E_d || cand->cap < 1)
+    return fail(BF_E_ARG, "eval_energy: null argument or capacity < 1");
+  hipStream_t st = (hipStream_t)stream;
+  s->last = st;
+  run_energy(dev_view(s), x_d, cand->i_d, cand->j_d, cand->type_d, (const long long*)cand->count_d, cand->cap,
+             s->d_line, E_d, st);
+  hipError_t he = hipGetLastError();
+  return he == hipSuccess ? BF_OK : fail_hip(he, "eval_energy");
 }
 
 bf_status filter_pairs(bf_scene* s, const double* x_d, const bf_pairs* cand, bf_active* act, void* stream) {

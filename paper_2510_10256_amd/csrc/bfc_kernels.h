@@ -10,6 +10,7 @@ constexpr int SCAN_TILE = 256 * SCAN_ITEMS;
 constexpr int SCAN1_MAX = 1 << 14;     // arrays up to this length are scanned by one work-group
 constexpr int PQ_MAX = 8;              // threads per broad-phase query: 2, 4 (default) or 8
 constexpr int NW_ITEMS = 4;            // candidates per thread in the narrow phase
+constexpr int LINE_BLOCKS = 8192;      // work-groups of the line-search kernels (grid-stride)
 constexpr int NW_TILE = 256 * NW_ITEMS;
 constexpr int BOUNDS_BLOCKS = 512;     // cap on k_bounds work-groups (partials of the last-block reduction)
 
@@ -19,9 +20,14 @@ inline long long scan_parts(long long n) { return (n + SCAN_TILE - 1) / SCAN_TIL
 void scan_excl(const int* in, int* out, const int* n_dev, int n_max, int* tmp, hipStream_t st);
 
 // Broad phase over the positions x (FP64 [V,3]) at inflation S.h.
-void run_broad(const SceneDev& S, const double* x, const BroadWs& W, int* oi, int* oj, unsigned char* ot,
-               long long cap, long long* count, unsigned* status, int* seg_r, unsigned* seg_t, long long seg_cap,
-               hipStream_t st);
+void run_broad(const SceneDev& S, const double* x, const double* pdisp, const BroadWs& W, int* oi, int* oj,
+               unsigned char* ot, long long cap, long long* count, unsigned* status, int* seg_r, unsigned* seg_t,
+               long long seg_cap, hipStream_t st);
+void run_accd(const SceneDev& S, const double* x, const double* pdisp, const int* ci, const int* cj,
+              const unsigned char* ct, const long long* ccount, long long ccap, double s, int max_iter, double* tpair,
+              double* bred, double* t_out, hipStream_t st);
+void run_energy(const SceneDev& S, const double* x, const int* ci, const int* cj, const unsigned char* ct,
+                const long long* ccount, long long ccap, double* bred, double* E_out, hipStream_t st);
 
 // Narrow phase, filter and compaction.
 void run_narrow(const SceneDev& S, const double* x, const int* ci, const int* cj, const unsigned char* ct,

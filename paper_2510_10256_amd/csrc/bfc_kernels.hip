@@ -309,11 +309,12 @@ __device__ void make_grid(const float* lo_f, const float* hi_f, float ext_f, dou
   g->coarsened = coarse;
 }
 
-// Boxes of all primitives (FP32, rounded outward) and, in the last block to
-// finish, the reduction of the per-block bounds and the grid parameters.
+// Boxes of all primitives (FP32, rounded outward; with pdisp, the boxes of
+// the straight sweep from x to x + pdisp) and, in the last block to finish,
+// the reduction of the per-block bounds and the grid parameters.
 // The last block also clears the candidate counter of this step.
-__global__ __launch_bounds__(256) void k_bounds(SceneDev S, const double* x, int np, Box* box, float* part,
-                                                unsigned* done, double h, int max_cells, Grid* grid,
+__global__ __launch_bounds__(256) void k_bounds(SceneDev S, const double* x, const double* pdisp, int np, Box* box,
+                                                float* part, unsigned* done, double h, int max_cells, Grid* grid,
                                                 long long* cand_count) {
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, ext = 0.0f;
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += grid_stride()) {
@@ -325,6 +326,11 @@ __global__ __launch_bounds__(256) void k_bounds(SceneDev S, const double* x, int
         double c = x[3 * v[k] + a];
         l[a] = fmin(l[a], c);
         hh[a] = fmax(hh[a], c);
+        if (pdisp) {  // swept box: the vertex at x and at x + p
+          const double ce = c + pdisp[3 * v[k] + a];
+          l[a] = fmin(l[a], ce);
+          hh[a] = fmax(hh[a], ce);
+        }
       }
     Box b;
     for (int a = 0; a < 3; ++a) {
@@ -1639,6 +1645,176 @@ __global__ __launch_bounds__(256) void k_row_b_big(SceneDev S, const int* ai, co
 }
 
 // ---------------------------------------------------------------------------
+// Line search (Sec. 3.3, last paragraph; App. A): additive CCD with the
+// filtered offsets, and the energy alone at a trial point.
+// ---------------------------------------------------------------------------
+
+// Additive CCD (Li, Kaufman and Jiang 2021, C-IPC) of one stencil with offset
+// xi along the displacements P: the distance between the primitives closes
+// at most at rate lp (largest displacement on one side plus the largest on
+// the other, after the stencil's mean displacement is removed), so steps of
+// (1 - s) of the gap, then 0.9 of the current gap, never reach the offset.
+// The search stops before the step after which the gap is below s of the
+// initial gap, or at the full step 1, or after max_iter steps.  Positions
+// advance by additions of products (no fused multiply-add).
+__device__ double accd_stencil(int type, const d3* X0, const d3* P0, double xi, double s, int max_iter) {
+  d3 pm;
+  pm.x = (((P0[0].x + P0[1].x) + P0[2].x) + P0[3].x) / 4.0;
+  pm.y = (((P0[0].y + P0[1].y) + P0[2].y) + P0[3].y) / 4.0;
+  pm.z = (((P0[0].z + P0[1].z) + P0[2].z) + P0[3].z) / 4.0;
+  d3 X[4], P[4];
+  double nr[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    X[k] = X0[k];
+    P[k] = P0[k] - pm;
+    nr[k] = sqrt(dot(P[k], P[k]));
+  }
+  const double lp = type == BF_PT ? nr[0] + fmax(nr[1], fmax(nr[2], nr[3])) : fmax(nr[0], nr[1]) + fmax(nr[2], nr[3]);
+  if (lp == 0.0) return 1.0;
+  const double xi2 = xi * xi;
+  double D = type == BF_PT ? classify_pt(X).D : classify_ee(X).D;
+  const double gap0 = (D - xi2) / (sqrt(D) + xi);
+  if (!(gap0 > 0.0)) return 0.0;  // at or inside the offset already
+  const double g = s * gap0;
+  double t = 0.0, tl = (1.0 - s) * gap0 / lp;
+  for (int it = 0; it < max_iter; ++it) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      X[k].x = __dadd_rn(X[k].x, __dmul_rn(tl, P[k].x));
+      X[k].y = __dadd_rn(X[k].y, __dmul_rn(tl, P[k].y));
+      X[k].z = __dadd_rn(X[k].z, __dmul_rn(tl, P[k].z));
+    }
+    D = type == BF_PT ? classify_pt(X).D : classify_ee(X).D;
+    const double gap = (D - xi2) / (sqrt(D) + xi);
+    if (t > 0.0 && gap < g) break;
+    t += tl;
+    if (t > 1.0) return 1.0;
+    tl = 0.9 * gap / lp;
+  }
+  return t;
+}
+
+// Exact swept-box test of a candidate (the definition of the CCD pair set):
+// the boxes of each primitive's vertices at x and x + p, gap below h on
+// every axis, in double.
+__device__ __forceinline__ bool swept_within(int type, const d3* X, const d3* P, double h) {
+  const int na = type == BF_PT ? 1 : 2;
+  double lo[2][3], hi[2][3];
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { lo[q][c] = INFINITY; hi[q][c] = -INFINITY; }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int q = k < na ? 0 : 1;
+    const double a[3] = {X[k].x, X[k].y, X[k].z}, b[3] = {X[k].x + P[k].x, X[k].y + P[k].y, X[k].z + P[k].z};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      lo[q][c] = fmin(lo[q][c], fmin(a[c], b[c]));
+      hi[q][c] = fmax(hi[q][c], fmax(a[c], b[c]));
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    if (!(fmax(lo[1][c] - hi[0][c], lo[0][c] - hi[1][c]) < h)) return false;
+  return true;
+}
+
+// Per candidate: ACCD if its swept boxes are within h (offset 0 for filtered
+// stencils, eta otherwise; Eq. 4), t = -1 otherwise; the minimum per block.
+__global__ __launch_bounds__(256) void k_accd(SceneDev S, const double* x, const double* pdisp, const int* ci,
+                                              const int* cj, const unsigned char* ct, const long long* cand_count,
+                                              long long ccap, double s, int max_iter, double* tpair, double* bmin) {
+  long long n = *cand_count;
+  if (n > ccap) n = ccap;
+  double tmin = 1.0;
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += grid_stride()) {
+    const int type = ct[k];
+    int v[4];
+    pair_verts(S, type, ci[k], cj[k], v);
+    d3 X[4], P[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) { X[q] = load3(x, v[q]); P[q] = load3(pdisp, v[q]); }
+    double t = -1.0;
+    if (swept_within(type, X, P, S.h)) {
+      const double xi = is_filtered(S, type, v) ? 0.0 : S.eta;
+      t = accd_stencil(type, X, P, xi, s, max_iter);
+      tmin = fmin(tmin, t);
+    }
+    if (tpair) tpair[k] = t;
+  }
+  for (int o = 32; o > 0; o >>= 1) tmin = fmin(tmin, __shfl_xor(tmin, o, 64));
+  __shared__ double wm[4];
+  if (lane_id() == 0) wm[threadIdx.x >> 6] = tmin;
+  __syncthreads();
+  if (threadIdx.x == 0) bmin[blockIdx.x] = fmin(fmin(wm[0], wm[1]), fmin(wm[2], wm[3]));
+}
+
+__global__ __launch_bounds__(256) void k_min_final(const double* bmin, int nb, double* out) {
+  double m = 1.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) m = fmin(m, bmin[b]);
+  for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o, 64));
+  __shared__ double wm[4];
+  if (lane_id() == 0) wm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = fmin(fmin(wm[0], wm[1]), fmin(wm[2], wm[3]));
+}
+
+// Energy alone (Eq. 2 with the parameters of Eq. 4) of every candidate at x:
+// the same decisions as the narrow phase (d < h, the filter, d < a, d <= eta
+// gives +inf); per block a fixed-order sum (each thread's candidates in
+// order, then the lanes, then the four waves).
+__global__ __launch_bounds__(256) void k_energy(SceneDev S, const double* x, const int* ci, const int* cj,
+                                                const unsigned char* ct, const long long* cand_count, long long ccap,
+                                                double* bsum) {
+  long long n = *cand_count;
+  if (n > ccap) n = ccap;
+  const dd h2 = dd_sq(S.h), e2 = dd_sq(S.eta);
+  double e = 0.0;
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += grid_stride()) {
+    const int type = ct[k];
+    int v[4];
+    pair_verts(S, type, ci[k], cj[k], v);
+    d3 P[4] = {load3(x, v[0]), load3(x, v[1]), load3(x, v[2]), load3(x, v[3])};
+    const Near nr = type == BF_PT ? classify_pt(P) : classify_ee(P);
+    if (!decide_sq(nr.code, P, nr.D, h2, true)) continue;  // d >= h
+    dd T;
+    double a, eta;
+    if (is_filtered(S, type, v)) {
+      const int c = S.comp[v[0]];
+      T = dd{S.thr2[2 * c], S.thr2[2 * c + 1]};
+      a = S.dmin[c];
+      eta = 0.0;
+    } else {
+      T = h2;
+      a = S.h;
+      eta = S.eta;
+    }
+    if (!decide_sq(nr.code, P, nr.D, T, true)) continue;  // inactive: d >= a
+    const bool infeas = eta > 0.0 ? decide_sq(nr.code, P, nr.D, e2, false) : !(nr.D > 0.0);
+    if (infeas) {
+      e += INFINITY;
+      continue;
+    }
+    double b, b1, b2;
+    barrier3<double>(sqrt(nr.D), a, eta, b, b1, b2);
+    e += S.kappa * b;
+  }
+  double y = 0.0, z = 0.0;
+  wave_ordered_sum3(e, y, z);
+  __shared__ double ws[4];
+  if (lane_id() == 0) ws[threadIdx.x >> 6] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) bsum[blockIdx.x] = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+}
+
+// Fixed-order total of the per-block sums (one wave).
+__global__ __launch_bounds__(64) void k_sum_final(const double* bsum, int nb, double* out) {
+  energy_total(bsum, nb, out);
+}
+
+// ---------------------------------------------------------------------------
 // Precompute (Sec. 3.2): connected components and d_min
 // ---------------------------------------------------------------------------
 __global__ void k_cc_init(int* lab, int nv) {
@@ -1774,16 +1950,16 @@ static void launch_pairs(const SceneDev& S, int nquery, const BroadWs& W, int* o
                      cap, count, status);
 }
 
-void run_broad(const SceneDev& S, const double* x, const BroadWs& W, int* oi, int* oj, unsigned char* ot,
-               long long cap, long long* count, unsigned* status, int* seg_r, unsigned* seg_t, long long seg_cap,
-               hipStream_t st) {
+void run_broad(const SceneDev& S, const double* x, const double* pdisp, const BroadWs& W, int* oi, int* oj,
+               unsigned char* ot, long long cap, long long* count, unsigned* status, int* seg_r, unsigned* seg_t,
+               long long seg_cap, hipStream_t st) {
   int np = S.ne + S.nt + (S.kind == 1 ? S.nv : 0);
   int nstored = S.ne + S.nt;
   int nquery = S.kind == 1 ? S.nv + S.ne : S.ne;
   int nscan_max = 2 * W.max_cells + 1;
   const int* nscan_dev = &W.grid->nscan;
-  hipLaunchKernelGGL(k_bounds, dim3(nblocks(np, 256, BOUNDS_BLOCKS)), dim3(256), 0, st, S, x, np, W.box, W.part,
-                     W.done, S.h, W.max_cells, W.grid, count);
+  hipLaunchKernelGGL(k_bounds, dim3(nblocks(np, 256, BOUNDS_BLOCKS)), dim3(256), 0, st, S, x, pdisp, np, W.box,
+                     W.part, W.done, S.h, W.max_cells, W.grid, count);
   // cell counts are zero on entry: the scatter below returns them to zero
   hipLaunchKernelGGL(k_count, dim3(nblocks(nstored)), dim3(256), 0, st, nstored, S.ne, W.box, W.grid, W.cell_cnt,
                      W.cell_of, W.seg_count);
@@ -1798,6 +1974,22 @@ void run_broad(const SceneDev& S, const double* x, const BroadWs& W, int* oi, in
     case 8: launch_pairs<8>(S, nquery, W, oi, oj, ot, cap, count, status, seg_r, seg_t, seg_cap, st); break;
     default: launch_pairs<4>(S, nquery, W, oi, oj, ot, cap, count, status, seg_r, seg_t, seg_cap, st); break;
   }
+}
+
+void run_accd(const SceneDev& S, const double* x, const double* pdisp, const int* ci, const int* cj,
+              const unsigned char* ct, const long long* ccount, long long ccap, double s, int max_iter, double* tpair,
+              double* bred, double* t_out, hipStream_t st) {
+  const int nb = nblocks(ccap, 256, LINE_BLOCKS);
+  hipLaunchKernelGGL(k_accd, dim3(nb), dim3(256), 0, st, S, x, pdisp, ci, cj, ct, ccount, ccap, s, max_iter, tpair,
+                     bred);
+  hipLaunchKernelGGL(k_min_final, dim3(1), dim3(256), 0, st, bred, nb, t_out);
+}
+
+void run_energy(const SceneDev& S, const double* x, const int* ci, const int* cj, const unsigned char* ct,
+                const long long* ccount, long long ccap, double* bred, double* E_out, hipStream_t st) {
+  const int nb = nblocks(ccap, 256, LINE_BLOCKS);
+  hipLaunchKernelGGL(k_energy, dim3(nb), dim3(256), 0, st, S, x, ci, cj, ct, ccount, ccap, bred);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(64), 0, st, bred, nb, E_out);
 }
 
 void run_narrow(const SceneDev& S, const double* x, const int* ci, const int* cj, const unsigned char* ct,

@@ -1,0 +1,145 @@
+"""GPU parity of the line-search calls against the CPU oracle.
+
+build_candidates_swept -> max_step_accd -> eval_energy at trial points, on
+the small rod, yarn and cloth scenes and the full yarn patch, with seeded
+displacements large enough that many pairs stop the step.
+
+Bar: the CCD pair set (exact FP64 swept-box decisions on both sides) equal;
+each pair's ACCD step and the minimum within 1e-9 relative (the iteration is
+the same on both sides; the distances differ by rounding only); energies
+within 1e-10 of the sum of |E_k| + b_ref,k over the active pairs (the bound
+of the path's parity tests); +inf exactly where the oracle has it; every
+result bit-for-bit repeatable.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+requires_gpu = pytest.mark.skipif(not torch.cuda.is_available(), reason="no GPU")
+
+S_ACCD = 0.1
+MAX_ITER = 65536
+
+SCENES = {
+    "rod": lambda: synth.helix_loop_rod(),
+    "yarn": lambda: synth.woven_patch(n_warp=4, n_weft=4, verts_per_rod=80),
+    "cloth": lambda: synth.folded_cloth(n=72, gaps=(950.0,), l_mid=4000.0, l_conv=2000.0),
+    "yarn_full": lambda: synth.workload("woven_patch"),
+}
+
+
+def _direction(sc, seed):
+    """Seeded search direction: a squeeze toward the scene's mid-plane (z) plus
+    per-vertex noise, scaled to a few activation bands, so that many pairs
+    close their gaps within the step."""
+    rng = np.random.default_rng(seed)
+    x = sc.x
+    band = sc.h - sc.eta
+    zc = 0.5 * (x[:, 2].max() + x[:, 2].min())
+    p = np.zeros_like(x)
+    p[:, 2] = -(x[:, 2] - zc) / max(1.0, np.abs(x[:, 2] - zc).max()) * 3.0 * band
+    p += rng.normal(scale=1.5 * band, size=x.shape)
+    return p
+
+
+def _gpu_line(sc, p, alphas):
+    import paper_2510_10256_amd as bfc
+    dev = torch.device("cuda:0")
+    cs = bfc.ContactScene(sc, device=dev)
+    x = torch.tensor(sc.x, dtype=torch.float64, device=dev)
+    pt = torch.tensor(p, dtype=torch.float64, device=dev)
+    cs.run(x)  # sizes the buffers on the static candidates
+    # grow the candidate capacity until the swept list fits
+    for _ in range(4):
+        cs.build_candidates_swept(x, pt)
+        torch.cuda.synchronize()
+        n = int(cs.c_n.item())
+        if n <= cs.cand_cap:
+            break
+        cs.cand_cap = n + n // 4 + 1024
+        bfc.lib().bf_scene_reserve(cs.handle, cs.cand_cap, cs.act_cap)
+        cs._alloc()
+    t, tp = cs.max_step(x, pt, accd_s=S_ACCD, max_iter=MAX_ITER, per_pair=True)
+    torch.cuda.synchronize()
+    n = int(cs.c_n.item())
+    out = dict(t=float(t.item()), n=n, tp=tp[:n].cpu().numpy(),
+               ct=cs.c_t[:n].cpu().numpy().astype(np.int32), ci=cs.c_i[:n].cpu().numpy(),
+               cj=cs.c_j[:n].cpu().numpy())
+    # repeatability of the step
+    t2, tp2 = cs.max_step(x, pt, accd_s=S_ACCD, max_iter=MAX_ITER, per_pair=True)
+    torch.cuda.synchronize()
+    out["repeat_ok"] = float(t2.item()) == out["t"] and np.array_equal(tp2[:n].cpu().numpy(), out["tp"])
+    energies = []
+    for a in alphas:
+        xa = x + float(a) * pt
+        E1 = float(cs.eval_energy(xa).item())
+        E2 = float(cs.eval_energy(xa).item())
+        energies.append((E1, E2))
+    out["E"] = energies
+    cs.close()
+    return out
+
+
+def _energy_bound(o, tau=1e-10):
+    act = (o["flags"] & oracle.F_ACTIVE) != 0
+    if not act.any():
+        return 1e-300
+    a, eta, E = o["a"][act], o["eta"][act], o["E"][act]
+    w = a - eta
+    bref = (w / 2) ** 2 * math.log(2)
+    return tau * float(np.sum(np.abs(E[np.isfinite(E)])) + np.sum(bref)) + 1e-300
+
+
+@requires_gpu
+@pytest.mark.parametrize("name", list(SCENES))
+def test_max_step_and_energy_match_the_oracle(name):
+    sc = SCENES[name]()
+    p = _direction(sc, seed=20251010 + len(name))
+    print(f"[linesearch] {name} V={sc.n_verts}", flush=True)
+    orc = oracle.max_step(sc, sc.x, p, s=S_ACCD, max_iter=MAX_ITER)
+    t_o = orc["t"]
+    alphas = [0.0, 0.5 * t_o, t_o]
+    g = _gpu_line(sc, p, alphas)
+    assert g["repeat_ok"]
+    # the CCD pair set
+    inset = g["tp"] >= 0.0
+    gk = {(int(a), int(b), int(c)): float(t) for a, b, c, t in
+          zip(g["ct"][inset], g["ci"][inset], g["cj"][inset], g["tp"][inset])}
+    ok = {(int(a), int(b), int(c)): float(t) for a, b, c, t in zip(orc["ptype"], orc["i"], orc["j"], orc["tpair"])}
+    assert set(gk) == set(ok), (len(gk), len(ok), len(set(gk) ^ set(ok)))
+    # every pair's step, and the minimum
+    tg = np.array([gk[k] for k in ok])
+    to = np.array([ok[k] for k in ok])
+    rel = np.abs(tg - to) / np.maximum(np.abs(to), 1e-300)
+    short = int(np.sum(to < 1.0))
+    print(name, "pairs", len(ok), "stopping the step", short, "t", g["t"], t_o, "worst rel", rel.max(initial=0.0),
+          flush=True)
+    assert short > 0
+    assert np.all((rel <= 1e-9) | ((to == 0.0) & (tg == 0.0)))
+    assert abs(g["t"] - t_o) <= 1e-9 * max(t_o, 1e-300)
+    # energy at the start, half way and at the step
+    for a, (E1, E2) in zip(alphas, g["E"]):
+        assert E1 == E2 or (math.isnan(E1) and math.isnan(E2))
+        Eo, o = oracle.energy(sc, sc.x + a * p)
+        if math.isinf(Eo):
+            assert math.isinf(E1), (a, E1)
+            continue
+        assert abs(E1 - Eo) <= _energy_bound(o), (a, E1, Eo)
+
+
+@requires_gpu
+def test_zero_direction_gives_the_full_step():
+    sc = SCENES["yarn"]()
+    p = np.zeros_like(sc.x)
+    g = _gpu_line(sc, p, [0.0])
+    assert g["t"] == 1.0
+    assert np.all(g["tp"][g["tp"] >= 0] == 1.0)
+    Eo, o = oracle.energy(sc, sc.x)
+    assert abs(g["E"][0][0] - Eo) <= _energy_bound(o)
