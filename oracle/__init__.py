@@ -26,7 +26,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "oracle.cpp")
 
-F_FILTERED, F_ACTIVE, F_INFEASIBLE, F_EXTENDED = 1, 2, 4, 8
+F_FILTERED, F_ACTIVE, F_INFEASIBLE, F_EXTENDED, F_CORE = 1, 2, 4, 8, 16
 PT, EE = 0, 1
 
 # distance sub-case codes (see oracle.cpp): kind of formula per code
@@ -47,7 +47,8 @@ class _Scene(C.Structure):
     _fields_ = [("kind", C.c_int32), ("nv", C.c_int64), ("ne", C.c_int64), ("nt", C.c_int64),
                 ("edges", C.c_void_p), ("tris", C.c_void_p), ("ref", C.c_void_p),
                 ("h", C.c_double), ("eta", C.c_double), ("kappa", C.c_double),
-                ("filter_mode", C.c_int32)]
+                ("filter_mode", C.c_int32), ("n_core", C.c_int64), ("core_ptype", C.c_void_p),
+                ("core_i", C.c_void_p), ("core_j", C.c_void_p)]
 
 
 _lib = None
@@ -81,6 +82,7 @@ def lib():
         L.orc_ms_count.restype = C.c_int64
         L.orc_ms_get.argtypes = [P] * 8
         L.orc_ms_free.argtypes = [P]
+        L.orc_core_release.argtypes = [C.POINTER(_Scene), P, C.c_int64, P, P, P, P]
         _lib = L
     return _lib
 
@@ -89,17 +91,24 @@ def _p(a):
     return a.ctypes.data_as(C.c_void_p) if a is not None else None
 
 
-def _scene_struct(scene, filter_mode=0, eta=None, kappa=None):
+def _scene_struct(scene, filter_mode=0, eta=None, kappa=None, core=None):
     keep = []
     edges = np.ascontiguousarray(scene.edges, np.int32)
     tris = np.ascontiguousarray(scene.tris, np.int32)
     ref = np.ascontiguousarray(scene.ref, np.float64)
     keep += [edges, tris, ref]
+    cp = ci = cj = None
+    n_core = 0
+    if core is not None and len(core[0]):
+        cp, ci, cj = (np.ascontiguousarray(a, np.int32) for a in core)
+        keep += [cp, ci, cj]
+        n_core = len(cp)
     s = _Scene(0 if scene.kind == "rod" else 1, scene.n_verts, scene.n_edges,
                scene.n_tris if scene.kind == "shell" else 0,
                _p(edges), _p(tris) if tris.size else None, _p(ref),
                float(scene.h), float(scene.eta if eta is None else eta),
-               float(scene.kappa if kappa is None else kappa), int(filter_mode))
+               float(scene.kappa if kappa is None else kappa), int(filter_mode), n_core,
+               _p(cp), _p(ci), _p(cj))
     return s, keep
 
 
@@ -115,15 +124,17 @@ def precompute(scene, filter_mode=0):
 
 
 def evaluate(scene, x=None, mode=1, derivs=True, filter_mode=0, eta=None, kappa=None,
-             nthreads=0):
+             nthreads=0, core=None):
     """Every pair of the universe with d < h, sorted by (ptype, i, j).
 
     Returns a dict of numpy arrays: ptype, i, j, verts[n,4], code, flags, d, a,
     eta, E, G[n,12], Hraw[n,12,12], Hpsd[n,12,12] (derivative arrays are zero
-    for inactive pairs; E is +inf for infeasible active pairs).
+    for inactive pairs; E is +inf for infeasible active pairs).  core: the
+    (ptype, i, j) arrays of pairs under the temporary zero offset (Sec. 3.4;
+    pass the ones not released at x, see core_release).
     """
     x = np.ascontiguousarray(scene.x if x is None else x, np.float64)
-    s, keep = _scene_struct(scene, filter_mode, eta, kappa)
+    s, keep = _scene_struct(scene, filter_mode, eta, kappa, core)
     L = lib()
     h = L.orc_evaluate(C.byref(s), _p(x), int(mode), int(bool(derivs)), int(nthreads))
     try:
@@ -276,3 +287,23 @@ def max_step(scene, x, p, s=0.1, max_iter=65536, mode=1, filter_mode=0, eta=None
         L.orc_ms_free(h)
     out["t"] = float(out["tpair"].min()) if n else 1.0
     return out
+
+
+# ---- temporary zero offset (Sec. 3.4) -----------------------------------------
+
+def core_mark(scene, x, filter_mode=0, nthreads=0):
+    """Non-stencil pairs inside the core at x (d < h and d <= eta, not
+    filtered), as sorted (ptype, i, j) arrays."""
+    res = evaluate(scene, x, mode=1, derivs=False, filter_mode=filter_mode, nthreads=nthreads)
+    sel = ((res["flags"] & F_INFEASIBLE) != 0) & ((res["flags"] & F_FILTERED) == 0)
+    return res["ptype"][sel].copy(), res["i"][sel].copy(), res["j"][sel].copy()
+
+
+def core_release(scene, x, core, filter_mode=0):
+    """Boolean mask over the core pairs: True where the pair is at d > eta at x."""
+    x = np.ascontiguousarray(x, np.float64)
+    cp, ci, cj = (np.ascontiguousarray(a, np.int32) for a in core)
+    s, keep = _scene_struct(scene, filter_mode)
+    out = np.zeros(len(cp), np.int32)
+    lib().orc_core_release(C.byref(s), _p(x), len(cp), _p(cp), _p(ci), _p(cj), _p(out))
+    return out.astype(bool)

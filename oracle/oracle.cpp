@@ -30,7 +30,10 @@
 //     et al. 2021) per pair with the offset of Eq. 4 (eta for ordinary pairs,
 //     0 for filtered stencils), over the pairs whose boxes swept from x to
 //     x + p come within h.  The energy-only evaluation at a trial point is
-//     orc_evaluate without derivatives.
+//     orc_evaluate without derivatives;
+//   * temporary zero offset (Sec. 3.4): non-stencil pairs found inside the
+//     core (d <= eta) at a configuration get eta = 0 (activation h) until
+//     they are seen with d > eta, then the ordinary (h, eta) again.
 //
 // Build: g++ -O2 -std=c++17 -fopenmp -ffp-contract=off -shared -fPIC
 //        oracle.cpp -o liboracle.so -lquadmath
@@ -41,6 +44,7 @@
 #include <cstdint>
 #include <cstring>
 #include <limits>
+#include <unordered_set>
 #include <vector>
 #include <omp.h>
 #include <quadmath.h>
@@ -413,7 +417,13 @@ struct Mesh {
   // exact squared activation threshold of filtered pairs per component: the
   // canonical d_min^2 (shells) or the exact square of the minimum gap (rods)
   std::vector<f128> thr2;
+  // pairs under the temporary zero offset of Sec. 3.4 (not yet released)
+  std::unordered_set<uint64_t> core;
 };
+
+inline uint64_t pair_key(int ptype, int i, int j) {
+  return ((uint64_t)ptype << 62) | ((uint64_t)(uint32_t)i << 31) | (uint64_t)(uint32_t)j;
+}
 
 // Reference (parametric-space) distance of a pair, as the value that the
 // filter compares with h.  Rods: 1D gap between the two edges' arc-length
@@ -591,7 +601,7 @@ void compute_dmin(Mesh& m, int nc) {
 // ---------------------------------------------------------------------------
 // Per-pair record.
 // ---------------------------------------------------------------------------
-enum { F_FILTERED = 1, F_ACTIVE = 2, F_INFEASIBLE = 4, F_EXTENDED = 8 };
+enum { F_FILTERED = 1, F_ACTIVE = 2, F_INFEASIBLE = 4, F_EXTENDED = 8, F_CORE = 16 };
 
 struct Deriv {
   double G[12];
@@ -633,13 +643,17 @@ bool eval_pair(const Mesh& m, const double* x, int ptype, int i, int j, bool der
   r.d = std::sqrt(ds.D);
   r.flags = 0;
   bool filt = is_filtered(m, ptype, i, j);
+  // Sec. 3.4: a non-stencil pair initialised inside the core keeps a zero
+  // offset (activation h) until it is released
+  bool core = !filt && !m.core.empty() && m.core.count(pair_key(ptype, i, j)) != 0;
   int c = ptype == 0 ? m.comp[i] : m.comp[m.edges[2 * i]];
   double Td; f128 Tq;
   if (filt) {  // Eq. 4, second case: activation d_min, no offset
     r.a = m.dmin[c]; r.eta = 0.0; r.flags |= F_FILTERED;
     Tq = m.thr2[c]; Td = (double)Tq;
-  } else {     // Eq. 4, first case: activation h, offset eta
-    r.a = m.h; r.eta = m.eta;
+  } else {     // Eq. 4, first case: activation h, offset eta (0 while in the core set)
+    r.a = m.h; r.eta = core ? 0.0 : m.eta;
+    if (core) r.flags |= F_CORE;
     Tq = sq(m.h); Td = m.h * m.h;
   }
   // Eq. 2: active iff d < a; Eq. 3: the barrier diverges at d = eta
@@ -769,6 +783,10 @@ typedef struct {
   const double* ref;
   double h, eta, kappa;
   int32_t filter_mode;
+  int64_t n_core;  // pairs under the temporary zero offset (Sec. 3.4), may be 0
+  const int32_t* core_ptype;
+  const int32_t* core_i;
+  const int32_t* core_j;
 } orc_scene;
 
 static Mesh make_mesh(const orc_scene* s) {
@@ -779,6 +797,7 @@ static Mesh make_mesh(const orc_scene* s) {
   m.comp.resize(m.nv);
   int nc = components(m.nv, m.ne, m.edges, m.tris, m.nt, m.comp.data());
   compute_dmin(m, nc);
+  for (int64_t k = 0; k < s->n_core; ++k) m.core.insert(pair_key(s->core_ptype[k], s->core_i[k], s->core_j[k]));
   return m;
 }
 
@@ -1067,5 +1086,20 @@ void orc_ms_get(void* h, int32_t* ptype, int32_t* pi, int32_t* pj, int32_t* filt
 }
 
 void orc_ms_free(void* h) { delete (StepResult*)h; }
+
+// Release test of the temporary zero offset (Sec. 3.4): released[k] = 1 when
+// pair k is at d > eta at x (decided as the filter decides d <= eta).
+void orc_core_release(const orc_scene* s, const double* x, int64_t n, const int32_t* ptype, const int32_t* pi,
+                      const int32_t* pj, int32_t* released) {
+  Mesh m = make_mesh(s);
+  for (int64_t k = 0; k < n; ++k) {
+    int verts[4];
+    double X[12];
+    gather(m, x, ptype[k], pi[k], pj[k], verts, X);
+    Dist ds = classify(ptype[k], X);
+    bool ext = false;
+    released[k] = decide(ds.code, X, ds.D, m.eta * m.eta, sq(m.eta), false, &ext) ? 0 : 1;
+  }
+}
 
 }  // extern "C"
