@@ -71,6 +71,9 @@ def parse():
     ap.add_argument("--graph", type=int, default=-1,
                     help="1: replay the step as a captured HIP graph; 0: eager launches (the assembly's structure "
                          "then overlaps the evaluation on a second stream); -1: time both, report the faster")
+    ap.add_argument("--path", default="step", choices=["step", "linesearch"],
+                    help="step: the four calls of a Newton step (default); linesearch: swept broad phase, additive "
+                         "CCD with the filtered offsets and the energy at the step found (one pass per step)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (calibrates HBM byte counters)")
@@ -112,6 +115,113 @@ def eval_roofline(ms, n_act, kinds, label):
     roof["units"] = {"active_pairs": int(n_act), "bytes": bytes_, "fp64_flops": flops,
                      "pairs_by_kind": {k: int(np.sum(kinds == q)) for q, k in enumerate(["PP", "PE", "PT", "EE"])}}
     return roof
+
+
+# FP64 operations of additive CCD (model): per pair in the swept set (loads,
+# mean displacement, motion bound, exact swept-box test, first distance,
+# filter) and per step (position update, classification, gap)
+ACCD_FLOPS_SETUP = 180.0
+ACCD_FLOPS_PER_ITER = 110.0
+
+
+def bench_linesearch(args):
+    """One line-search pass of a Newton iteration (Sec. 3.3, last paragraph;
+    App. A) per step: the broad phase over the boxes swept from x to x + p,
+    additive CCD of every pair in the swept set with its filtered offset, and
+    the energy alone at the step found (read on the device).  p is the seeded
+    search direction of the workload (a squeeze toward the mid-plane plus
+    noise, a few activation bands)."""
+    import torch
+    import synth
+    import paper_2510_10256_amd as bfc
+
+    sc = synth.workload(args.workload)
+    p = synth.search_direction(sc)
+    dev = torch.device("cuda:0")
+    x = torch.tensor(sc.x, dtype=torch.float64, device=dev)
+    pt = torch.tensor(p, dtype=torch.float64, device=dev)
+    cs = bfc.ContactScene(sc, device=dev)
+    cs.run(x)
+    n_bp = cs.fit_swept(x, pt)
+    tstep = torch.zeros(1, dtype=torch.float64, device=dev)
+    E = torch.zeros(1, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def one_pass():
+        cs.build_candidates_swept(x, pt)
+        cs.max_step(x, pt, out=tstep)
+        cs.eval_energy(x, pt, tstep, out=E)
+
+    for _ in range(args.warmup):
+        one_pass()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    t_start = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(args.steps):
+        one_pass()
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms = wall * 1e3 / args.steps
+    step_ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
+    # the swept set and the step counts (one more max_step with per-pair output)
+    t_dev, tp, it = cs.max_step(x, pt, per_pair=True)
+    torch.cuda.synchronize()
+    tp, it = tp[:n_bp].cpu().numpy(), it[:n_bp].cpu().numpy()
+    n_ccd = int(np.sum(tp >= 0.0))
+    iters = int(np.sum(it))
+    # k_accd (with its final minimum) timed alone on the launching stream
+    reps = max(20, args.steps // 2)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    cs.max_step(x, pt, out=tstep)
+    e0.record(stream)
+    for _ in range(reps):
+        cs.max_step(x, pt, out=tstep)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    accd_ms = e0.elapsed_time(e1) / reps
+    flops = n_ccd * ACCD_FLOPS_SETUP + iters * ACCD_FLOPS_PER_ITER
+    roof = {"kernel": "k_accd (max_step_accd)", "bound": "alu", "achieved": flops / (accd_ms * 1e-3) / 1e12,
+            "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "traffic": None, "kernel_ms": accd_ms,
+            "units": {"ccd_pairs": n_ccd, "accd_steps": iters, "fp64_flops": flops}}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    out = {
+        "metric": "line search: CCD pairs/s (swept broad phase + additive CCD with filtered offsets + energy at the "
+                  "step); p50/p99 latency",
+        "value": n_ccd / (ms * 1e-3),
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "p50_ms": float(np.percentile(step_ms, 50)),
+        "p99_ms": float(np.percentile(step_ms, 99)),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded generator and search direction)",
+        "config": {"workload": f"{sc.name} line search", "n_verts": sc.n_verts, "N_bp_swept": n_bp,
+                   "N_ccd": n_ccd, "accd_steps": iters, "step": float(t_dev.item()),
+                   "energy_at_step": float(E.item())},
+        "roofline": roof,
+    }
+    if args.cpu_baseline:
+        import oracle
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        reps_c, t_total = 0, 0.0
+        while t_total < 10.0 and reps_c < 20:
+            t0 = time.perf_counter()
+            r = oracle.max_step(sc, sc.x, p, nthreads=threads)
+            oracle.energy(sc, sc.x + r["t"] * p, nthreads=threads)
+            t_total += time.perf_counter() - t0
+            reps_c += 1
+        assert len(r["tpair"]) == n_ccd, (len(r["tpair"]), n_ccd)
+        out["cpu_baseline"] = {"value": n_ccd * reps_c / t_total, "unit": "pairs/s", "cores": threads,
+                               "kind": "oracle", "sample": f"whole workload, {reps_c} pass(es) of ACCD over the "
+                                                           f"swept pair set and the energy at the step"}
+    print(json.dumps(out))
 
 
 def bench_batch(args):
@@ -289,6 +399,12 @@ def main():
     if args.gpus != 1:
         print("bench.py: this path runs on one GPU; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
+    if args.path == "linesearch":
+        if args.workload in ("batch64", "serve256"):
+            print("bench.py: the line-search pass runs on one scene (woven_patch, folded_cloth, helix_loop_rod)",
+                  file=sys.stderr)
+            sys.exit(2)
+        return bench_linesearch(args)
     if args.workload == "batch64":
         return bench_batch(args)
     if args.workload == "serve256":

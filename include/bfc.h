@@ -215,23 +215,29 @@ bf_status assemble_grad_hess(bf_scene* s, const bf_active* act, const bf_local* 
  * full step 1, or after max_iter steps.  t_d[1] (device) = the smallest step
  * in [0, 1] (0 if a pair starts at or inside its offset, 1 if there is no
  * pair).  tpair_d (device, [cand->cap], may be NULL) receives each
- * candidate's step, or -1 for candidates outside the swept set.  accd_s in
- * (0, 1) (0.1 is usual), max_iter >= 1; BF_E_ARG otherwise.
+ * candidate's step, or -1 for candidates outside the swept set; iters_d
+ * (device int32 [cand->cap], may be NULL) its number of steps (0 outside the
+ * set; max_iter where the cap ended the search).  accd_s in (0, 1) (0.1 is
+ * usual), max_iter >= 1; BF_E_ARG otherwise.
  *
  * eval_energy: E_d[1] (device) = the filtered barrier energy (Eq. 2, Eq. 4)
- * of the candidates at positions x_d, with the decisions of filter_pairs;
- * +inf if a pair is at or inside its offset.  The candidates must include
- * every pair with d < h at x_d (a build_candidates list at x_d, or a swept
- * list whose segment holds x_d).  The sum runs in a fixed order: repeatable
- * bit for bit.
+ * of the candidates at positions x_d, or at x_d + alpha p_d when p_d and
+ * alpha_d (device, one double, e.g. the t_d of max_step_accd) are given
+ * (each coordinate x + alpha * p, product then sum); with the decisions of
+ * filter_pairs; +inf if a pair is at or inside its offset.  The candidates
+ * must include every pair with d < h at the evaluated point (a
+ * build_candidates list there, or a swept list whose segment holds it).
+ * The sum runs in a fixed order: repeatable bit for bit.
  *
  * All three enqueue on `stream` and do not synchronise; the workspace of the
  * last two is per scene (calls on one scene are stream-ordered). */
 bf_status build_candidates_swept(bf_scene* s, const double* x_d, const double* p_d, bf_pairs* cand,
                                  void* stream);
 bf_status max_step_accd(bf_scene* s, const double* x_d, const double* p_d, const bf_pairs* cand,
-                        double accd_s, int32_t max_iter, double* t_d, double* tpair_d, void* stream);
-bf_status eval_energy(bf_scene* s, const double* x_d, const bf_pairs* cand, double* E_d, void* stream);
+                        double accd_s, int32_t max_iter, double* t_d, double* tpair_d, int32_t* iters_d,
+                        void* stream);
+bf_status eval_energy(bf_scene* s, const double* x_d, const double* p_d, const double* alpha_d,
+                      const bf_pairs* cand, double* E_d, void* stream);
 
 /* ---- tuning ---------------------------------------------------------------
  * Threads per broad-phase query (2, 4 or 8; default 4): more threads split a

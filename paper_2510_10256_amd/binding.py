@@ -104,8 +104,8 @@ def lib():
         L.bf_batch_info.argtypes = [P, C.POINTER(C.c_int32), P]
         L.bf_batch_destroy.argtypes = [P]
         L.build_candidates_swept.argtypes = [P, P, P, C.POINTER(Pairs), P]
-        L.max_step_accd.argtypes = [P, P, P, C.POINTER(Pairs), C.c_double, C.c_int32, P, P, P]
-        L.eval_energy.argtypes = [P, P, C.POINTER(Pairs), P, P]
+        L.max_step_accd.argtypes = [P, P, P, C.POINTER(Pairs), C.c_double, C.c_int32, P, P, P, P]
+        L.eval_energy.argtypes = [P, P, P, P, C.POINTER(Pairs), P, P]
         L.bf_status_word.argtypes = [P, C.POINTER(C.c_uint32), C.c_int32]
         L.bf_last_error.restype = C.c_char_p
         for name in EXPORTED[:-1]:
@@ -224,22 +224,41 @@ class ContactScene:
         _check(lib().build_candidates_swept(self.handle, _ptr(x), _ptr(p), C.byref(self._cand),
                                             C.c_void_p(self._stream())), "build_candidates_swept")
 
-    def max_step(self, x, p, accd_s=0.1, max_iter=65536, per_pair=False):
-        """Additive CCD step over the swept candidates (run build_candidates_swept
-        first).  Returns a device tensor t[1] (and per-candidate steps, -1 outside
-        the swept set, when per_pair)."""
-        t = self.torch.zeros(1, dtype=self.torch.float64, device=self.device)
-        tp = self.torch.zeros(self.cand_cap, dtype=self.torch.float64, device=self.device) if per_pair else None
-        _check(lib().max_step_accd(self.handle, _ptr(x), _ptr(p), C.byref(self._cand), float(accd_s),
-                                   int(max_iter), _ptr(t), _ptr(tp) if tp is not None else None,
-                                   C.c_void_p(self._stream())), "max_step_accd")
-        return (t, tp) if per_pair else t
+    def fit_swept(self, x, p, max_tries=4):
+        """Grow the candidate capacity until the swept list of (x, p) fits
+        (synchronises); returns its length."""
+        for _ in range(max_tries):
+            self.build_candidates_swept(x, p)
+            self.torch.cuda.synchronize(self.device)
+            n = int(self.c_n.item())
+            if n <= self.cand_cap:
+                return n
+            self.cand_cap = n + n // 4 + 1024
+            _check(lib().bf_scene_reserve(self.handle, self.cand_cap, self.act_cap), "bf_scene_reserve")
+            self._alloc()
+        raise RuntimeError("swept candidate list kept overflowing")
 
-    def eval_energy(self, x, out=None):
-        """Energy alone at x over the current candidates; a device tensor E[1]."""
+    def max_step(self, x, p, accd_s=0.1, max_iter=65536, per_pair=False, out=None):
+        """Additive CCD step over the swept candidates (run build_candidates_swept
+        first).  Returns a device tensor t[1]; with per_pair also the steps of
+        the candidates (-1 outside the swept set) and their step counts."""
+        t = out if out is not None else self.torch.zeros(1, dtype=self.torch.float64, device=self.device)
+        tp = it = None
+        if per_pair:
+            tp = self.torch.zeros(self.cand_cap, dtype=self.torch.float64, device=self.device)
+            it = self.torch.zeros(self.cand_cap, dtype=self.torch.int32, device=self.device)
+        _check(lib().max_step_accd(self.handle, _ptr(x), _ptr(p), C.byref(self._cand), float(accd_s),
+                                   int(max_iter), _ptr(t), _ptr(tp) if per_pair else None,
+                                   _ptr(it) if per_pair else None, C.c_void_p(self._stream())), "max_step_accd")
+        return (t, tp, it) if per_pair else t
+
+    def eval_energy(self, x, p=None, alpha=None, out=None):
+        """Energy alone at x (or at x + alpha p, alpha a device tensor [1]) over
+        the current candidates; a device tensor E[1]."""
         E = out if out is not None else self.torch.zeros(1, dtype=self.torch.float64, device=self.device)
-        _check(lib().eval_energy(self.handle, _ptr(x), C.byref(self._cand), _ptr(E), C.c_void_p(self._stream())),
-               "eval_energy")
+        _check(lib().eval_energy(self.handle, _ptr(x), _ptr(p) if p is not None else None,
+                                 _ptr(alpha) if alpha is not None else None, C.byref(self._cand), _ptr(E),
+                                 C.c_void_p(self._stream())), "eval_energy")
         return E
 
     def set_pq(self, pq):

@@ -417,7 +417,7 @@ bf_status build_candidates_swept(bf_scene* s, const double* x_d, const double* p
 }
 
 bf_status max_step_accd(bf_scene* s, const double* x_d, const double* p_d, const bf_pairs* cand, double accd_s,
-                        int32_t max_iter, double* t_d, double* tpair_d, void* stream) {
+                        int32_t max_iter, double* t_d, double* tpair_d, int32_t* iters_d, void* stream) {
   if (!s || !x_d || !p_d || !cand || !cand->i_d || !cand->j_d || !cand->type_d || !cand->count_d || !t_d ||
       cand->cap < 1)
     return fail(BF_E_ARG, "max_step_accd: null argument or capacity < 1");
@@ -426,18 +426,21 @@ bf_status max_step_accd(bf_scene* s, const double* x_d, const double* p_d, const
   hipStream_t st = (hipStream_t)stream;
   s->last = st;
   run_accd(dev_view(s), x_d, p_d, cand->i_d, cand->j_d, cand->type_d, (const long long*)cand->count_d, cand->cap,
-           accd_s, max_iter, tpair_d, s->d_line, t_d, st);
+           accd_s, max_iter, tpair_d, iters_d, s->d_line, t_d, st);
   hipError_t he = hipGetLastError();
   return he == hipSuccess ? BF_OK : fail_hip(he, "max_step_accd");
 }
 
-bf_status eval_energy(bf_scene* s, const double* x_d, const bf_pairs* cand, double* E_d, void* stream) {
+bf_status eval_energy(bf_scene* s, const double* x_d, const double* p_d, const double* alpha_d, const bf_pairs* cand,
+                      double* E_d, void* stream) {
   if (!s || !x_d || !cand || !cand->i_d || !cand->j_d || !cand->type_d || !cand->count_d || !E_d || cand->cap < 1)
     return fail(BF_E_ARG, "eval_energy: null argument or capacity < 1");
+  if ((p_d == nullptr) != (alpha_d == nullptr))
+    return fail(BF_E_ARG, "eval_energy: p_d and alpha_d are given together or not at all");
   hipStream_t st = (hipStream_t)stream;
   s->last = st;
-  run_energy(dev_view(s), x_d, cand->i_d, cand->j_d, cand->type_d, (const long long*)cand->count_d, cand->cap,
-             s->d_line, E_d, st);
+  run_energy(dev_view(s), x_d, p_d, alpha_d, cand->i_d, cand->j_d, cand->type_d, (const long long*)cand->count_d,
+             cand->cap, s->d_line, E_d, st);
   hipError_t he = hipGetLastError();
   return he == hipSuccess ? BF_OK : fail_hip(he, "eval_energy");
 }

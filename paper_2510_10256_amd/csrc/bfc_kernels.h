@@ -25,9 +25,10 @@ void run_broad(const SceneDev& S, const double* x, const double* pdisp, const Br
                long long seg_cap, hipStream_t st);
 void run_accd(const SceneDev& S, const double* x, const double* pdisp, const int* ci, const int* cj,
               const unsigned char* ct, const long long* ccount, long long ccap, double s, int max_iter, double* tpair,
-              double* bred, double* t_out, hipStream_t st);
-void run_energy(const SceneDev& S, const double* x, const int* ci, const int* cj, const unsigned char* ct,
-                const long long* ccount, long long ccap, double* bred, double* E_out, hipStream_t st);
+              int* iters, double* bred, double* t_out, hipStream_t st);
+void run_energy(const SceneDev& S, const double* x, const double* pdisp, const double* alpha, const int* ci,
+                const int* cj, const unsigned char* ct, const long long* ccount, long long ccap, double* bred,
+                double* E_out, hipStream_t st);
 
 // Narrow phase, filter and compaction.
 void run_narrow(const SceneDev& S, const double* x, const int* ci, const int* cj, const unsigned char* ct,

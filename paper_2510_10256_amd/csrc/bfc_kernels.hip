@@ -1657,7 +1657,8 @@ __global__ __launch_bounds__(256) void k_row_b_big(SceneDev S, const int* ai, co
 // The search stops before the step after which the gap is below s of the
 // initial gap, or at the full step 1, or after max_iter steps.  Positions
 // advance by additions of products (no fused multiply-add).
-__device__ double accd_stencil(int type, const d3* X0, const d3* P0, double xi, double s, int max_iter) {
+__device__ double accd_stencil(int type, const d3* X0, const d3* P0, double xi, double s, int max_iter, int& iters) {
+  iters = 0;
   d3 pm;
   pm.x = (((P0[0].x + P0[1].x) + P0[2].x) + P0[3].x) / 4.0;
   pm.y = (((P0[0].y + P0[1].y) + P0[2].y) + P0[3].y) / 4.0;
@@ -1679,6 +1680,7 @@ __device__ double accd_stencil(int type, const d3* X0, const d3* P0, double xi, 
   const double g = s * gap0;
   double t = 0.0, tl = (1.0 - s) * gap0 / lp;
   for (int it = 0; it < max_iter; ++it) {
+    iters = it + 1;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       X[k].x = __dadd_rn(X[k].x, __dmul_rn(tl, P[k].x));
@@ -1722,10 +1724,12 @@ __device__ __forceinline__ bool swept_within(int type, const d3* X, const d3* P,
 }
 
 // Per candidate: ACCD if its swept boxes are within h (offset 0 for filtered
-// stencils, eta otherwise; Eq. 4), t = -1 otherwise; the minimum per block.
+// stencils, eta otherwise; Eq. 4), t = -1 otherwise (and its step count);
+// the minimum per block.
 __global__ __launch_bounds__(256) void k_accd(SceneDev S, const double* x, const double* pdisp, const int* ci,
                                               const int* cj, const unsigned char* ct, const long long* cand_count,
-                                              long long ccap, double s, int max_iter, double* tpair, double* bmin) {
+                                              long long ccap, double s, int max_iter, double* tpair, int* iters,
+                                              double* bmin) {
   long long n = *cand_count;
   if (n > ccap) n = ccap;
   double tmin = 1.0;
@@ -1737,12 +1741,14 @@ __global__ __launch_bounds__(256) void k_accd(SceneDev S, const double* x, const
 #pragma unroll
     for (int q = 0; q < 4; ++q) { X[q] = load3(x, v[q]); P[q] = load3(pdisp, v[q]); }
     double t = -1.0;
+    int it = 0;
     if (swept_within(type, X, P, S.h)) {
       const double xi = is_filtered(S, type, v) ? 0.0 : S.eta;
-      t = accd_stencil(type, X, P, xi, s, max_iter);
+      t = accd_stencil(type, X, P, xi, s, max_iter, it);
       tmin = fmin(tmin, t);
     }
     if (tpair) tpair[k] = t;
+    if (iters) iters[k] = it;
   }
   for (int o = 32; o > 0; o >>= 1) tmin = fmin(tmin, __shfl_xor(tmin, o, 64));
   __shared__ double wm[4];
@@ -1761,22 +1767,33 @@ __global__ __launch_bounds__(256) void k_min_final(const double* bmin, int nb, d
   if (threadIdx.x == 0) *out = fmin(fmin(wm[0], wm[1]), fmin(wm[2], wm[3]));
 }
 
-// Energy alone (Eq. 2 with the parameters of Eq. 4) of every candidate at x:
+// Energy alone (Eq. 2 with the parameters of Eq. 4) of every candidate at x
+// (or at x + alpha p when pdisp is given, alpha read from device memory):
 // the same decisions as the narrow phase (d < h, the filter, d < a, d <= eta
 // gives +inf); per block a fixed-order sum (each thread's candidates in
 // order, then the lanes, then the four waves).
-__global__ __launch_bounds__(256) void k_energy(SceneDev S, const double* x, const int* ci, const int* cj,
-                                                const unsigned char* ct, const long long* cand_count, long long ccap,
-                                                double* bsum) {
+__global__ __launch_bounds__(256) void k_energy(SceneDev S, const double* x, const double* pdisp, const double* alpha,
+                                                const int* ci, const int* cj, const unsigned char* ct,
+                                                const long long* cand_count, long long ccap, double* bsum) {
   long long n = *cand_count;
   if (n > ccap) n = ccap;
   const dd h2 = dd_sq(S.h), e2 = dd_sq(S.eta);
+  const double al = pdisp ? *alpha : 0.0;
   double e = 0.0;
   for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += grid_stride()) {
     const int type = ct[k];
     int v[4];
     pair_verts(S, type, ci[k], cj[k], v);
     d3 P[4] = {load3(x, v[0]), load3(x, v[1]), load3(x, v[2]), load3(x, v[3])};
+    if (pdisp) {  // trial point x + alpha p (a product, then a sum: no fused multiply-add)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const d3 d = load3(pdisp, v[q]);
+        P[q].x = __dadd_rn(P[q].x, __dmul_rn(al, d.x));
+        P[q].y = __dadd_rn(P[q].y, __dmul_rn(al, d.y));
+        P[q].z = __dadd_rn(P[q].z, __dmul_rn(al, d.z));
+      }
+    }
     const Near nr = type == BF_PT ? classify_pt(P) : classify_ee(P);
     if (!decide_sq(nr.code, P, nr.D, h2, true)) continue;  // d >= h
     dd T;
@@ -1978,17 +1995,18 @@ void run_broad(const SceneDev& S, const double* x, const double* pdisp, const Br
 
 void run_accd(const SceneDev& S, const double* x, const double* pdisp, const int* ci, const int* cj,
               const unsigned char* ct, const long long* ccount, long long ccap, double s, int max_iter, double* tpair,
-              double* bred, double* t_out, hipStream_t st) {
+              int* iters, double* bred, double* t_out, hipStream_t st) {
   const int nb = nblocks(ccap, 256, LINE_BLOCKS);
   hipLaunchKernelGGL(k_accd, dim3(nb), dim3(256), 0, st, S, x, pdisp, ci, cj, ct, ccount, ccap, s, max_iter, tpair,
-                     bred);
+                     iters, bred);
   hipLaunchKernelGGL(k_min_final, dim3(1), dim3(256), 0, st, bred, nb, t_out);
 }
 
-void run_energy(const SceneDev& S, const double* x, const int* ci, const int* cj, const unsigned char* ct,
-                const long long* ccount, long long ccap, double* bred, double* E_out, hipStream_t st) {
+void run_energy(const SceneDev& S, const double* x, const double* pdisp, const double* alpha, const int* ci,
+                const int* cj, const unsigned char* ct, const long long* ccount, long long ccap, double* bred,
+                double* E_out, hipStream_t st) {
   const int nb = nblocks(ccap, 256, LINE_BLOCKS);
-  hipLaunchKernelGGL(k_energy, dim3(nb), dim3(256), 0, st, S, x, ci, cj, ct, ccount, ccap, bred);
+  hipLaunchKernelGGL(k_energy, dim3(nb), dim3(256), 0, st, S, x, pdisp, alpha, ci, cj, ct, ccount, ccap, bred);
   hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(64), 0, st, bred, nb, E_out);
 }
 

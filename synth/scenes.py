@@ -441,6 +441,21 @@ def serving_scenes(seed: int = BASE_SEED + 4000, n_scenes: int = 256, median: fl
     return out
 
 
+def search_direction(scene: Scene, seed: int = BASE_SEED + 5000) -> np.ndarray:
+    """Seeded displacement field for line-search workloads: a squeeze of the
+    scene toward its mid-plane in z (3 activation bands at the extremes) plus
+    per-vertex Gaussian noise of 1.5 bands, so that many pairs close their
+    gaps within the step."""
+    rng = np.random.default_rng(seed)
+    x = scene.x
+    band = scene.h - scene.eta
+    zc = 0.5 * (x[:, 2].max() + x[:, 2].min())
+    p = np.zeros_like(x)
+    p[:, 2] = -(x[:, 2] - zc) / max(1.0, np.abs(x[:, 2] - zc).max()) * 3.0 * band
+    p += rng.normal(scale=1.5 * band, size=x.shape)
+    return p
+
+
 WORKLOADS = {
     "helix_loop_rod": lambda: helix_loop_rod(),
     "woven_patch": lambda: woven_patch(),

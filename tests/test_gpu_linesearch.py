@@ -5,11 +5,11 @@ the small rod, yarn and cloth scenes and the full yarn patch, with seeded
 displacements large enough that many pairs stop the step.
 
 Bar: the CCD pair set (exact FP64 swept-box decisions on both sides) equal;
-each pair's ACCD step and the minimum within 1e-9 relative (the iteration is
-the same on both sides; the distances differ by rounding only); energies
-within 1e-10 of the sum of |E_k| + b_ref,k over the active pairs (the bound
-of the path's parity tests); +inf exactly where the oracle has it; every
-result bit-for-bit repeatable.
+each pair's step count equal, its ACCD step and the minimum within 1e-9
+relative (the same iteration on both sides; the distances differ by rounding
+only); energies within 1e-10 of the sum of |E_k| + b_ref,k over the active
+pairs (the bound of the path's parity tests); +inf exactly where the oracle
+has it; every result bit-for-bit repeatable.
 """
 import math
 
@@ -35,20 +35,6 @@ SCENES = {
 }
 
 
-def _direction(sc, seed):
-    """Seeded search direction: a squeeze toward the scene's mid-plane (z) plus
-    per-vertex noise, scaled to a few activation bands, so that many pairs
-    close their gaps within the step."""
-    rng = np.random.default_rng(seed)
-    x = sc.x
-    band = sc.h - sc.eta
-    zc = 0.5 * (x[:, 2].max() + x[:, 2].min())
-    p = np.zeros_like(x)
-    p[:, 2] = -(x[:, 2] - zc) / max(1.0, np.abs(x[:, 2] - zc).max()) * 3.0 * band
-    p += rng.normal(scale=1.5 * band, size=x.shape)
-    return p
-
-
 def _gpu_line(sc, p, alphas):
     import paper_2510_10256_amd as bfc
     dev = torch.device("cuda:0")
@@ -56,32 +42,27 @@ def _gpu_line(sc, p, alphas):
     x = torch.tensor(sc.x, dtype=torch.float64, device=dev)
     pt = torch.tensor(p, dtype=torch.float64, device=dev)
     cs.run(x)  # sizes the buffers on the static candidates
-    # grow the candidate capacity until the swept list fits
-    for _ in range(4):
-        cs.build_candidates_swept(x, pt)
-        torch.cuda.synchronize()
-        n = int(cs.c_n.item())
-        if n <= cs.cand_cap:
-            break
-        cs.cand_cap = n + n // 4 + 1024
-        bfc.lib().bf_scene_reserve(cs.handle, cs.cand_cap, cs.act_cap)
-        cs._alloc()
-    t, tp = cs.max_step(x, pt, accd_s=S_ACCD, max_iter=MAX_ITER, per_pair=True)
+    cs.fit_swept(x, pt)
+    t, tp, it = cs.max_step(x, pt, accd_s=S_ACCD, max_iter=MAX_ITER, per_pair=True)
     torch.cuda.synchronize()
     n = int(cs.c_n.item())
-    out = dict(t=float(t.item()), n=n, tp=tp[:n].cpu().numpy(),
+    out = dict(t=float(t.item()), n=n, tp=tp[:n].cpu().numpy(), it=it[:n].cpu().numpy(),
                ct=cs.c_t[:n].cpu().numpy().astype(np.int32), ci=cs.c_i[:n].cpu().numpy(),
                cj=cs.c_j[:n].cpu().numpy())
     # repeatability of the step
-    t2, tp2 = cs.max_step(x, pt, accd_s=S_ACCD, max_iter=MAX_ITER, per_pair=True)
+    t2, tp2, _ = cs.max_step(x, pt, accd_s=S_ACCD, max_iter=MAX_ITER, per_pair=True)
     torch.cuda.synchronize()
     out["repeat_ok"] = float(t2.item()) == out["t"] and np.array_equal(tp2[:n].cpu().numpy(), out["tp"])
+    # energy at x + alpha p, alpha on the device (computed in the kernel)
     energies = []
     for a in alphas:
-        xa = x + float(a) * pt
-        E1 = float(cs.eval_energy(xa).item())
-        E2 = float(cs.eval_energy(xa).item())
+        al = torch.tensor([float(a)], dtype=torch.float64, device=dev)
+        E1 = float(cs.eval_energy(x, pt, al).item())
+        E2 = float(cs.eval_energy(x, pt, al).item())
         energies.append((E1, E2))
+    # and at the step itself, straight from max_step's device result
+    Et = float(cs.eval_energy(x, pt, t).item())
+    out["E_at_t"] = Et
     out["E"] = energies
     cs.close()
     return out
@@ -101,7 +82,7 @@ def _energy_bound(o, tau=1e-10):
 @pytest.mark.parametrize("name", list(SCENES))
 def test_max_step_and_energy_match_the_oracle(name):
     sc = SCENES[name]()
-    p = _direction(sc, seed=20251010 + len(name))
+    p = synth.search_direction(sc)
     print(f"[linesearch] {name} V={sc.n_verts}", flush=True)
     orc = oracle.max_step(sc, sc.x, p, s=S_ACCD, max_iter=MAX_ITER)
     t_o = orc["t"]
@@ -114,6 +95,12 @@ def test_max_step_and_energy_match_the_oracle(name):
           zip(g["ct"][inset], g["ci"][inset], g["cj"][inset], g["tp"][inset])}
     ok = {(int(a), int(b), int(c)): float(t) for a, b, c, t in zip(orc["ptype"], orc["i"], orc["j"], orc["tpair"])}
     assert set(gk) == set(ok), (len(gk), len(ok), len(set(gk) ^ set(ok)))
+    assert np.all(g["it"][~inset] == 0)
+    # step counts: the same iteration on both sides
+    gi = {(int(a), int(b), int(c)): int(i) for a, b, c, i in
+          zip(g["ct"][inset], g["ci"][inset], g["cj"][inset], g["it"][inset])}
+    oi = {(int(a), int(b), int(c)): int(i) for a, b, c, i in zip(orc["ptype"], orc["i"], orc["j"], orc["iters"])}
+    assert gi == oi
     # every pair's step, and the minimum
     tg = np.array([gk[k] for k in ok])
     to = np.array([ok[k] for k in ok])
@@ -127,11 +114,13 @@ def test_max_step_and_energy_match_the_oracle(name):
     # energy at the start, half way and at the step
     for a, (E1, E2) in zip(alphas, g["E"]):
         assert E1 == E2 or (math.isnan(E1) and math.isnan(E2))
-        Eo, o = oracle.energy(sc, sc.x + a * p)
+        Eo, o = oracle.energy(sc, sc.x + a * p)  # numpy: product, then sum
         if math.isinf(Eo):
             assert math.isinf(E1), (a, E1)
             continue
         assert abs(E1 - Eo) <= _energy_bound(o), (a, E1, Eo)
+        if a == t_o:  # the energy at the GPU's own step, read on the device
+            assert abs(g["E_at_t"] - Eo) <= _energy_bound(o) + 1e-7 * abs(Eo) * abs(g["t"] - t_o) / max(t_o, 1e-300)
 
 
 @requires_gpu
