@@ -67,14 +67,16 @@ enum {
   BF_S_CAND_OVERFLOW = 1u << 0,   /* candidate list capacity exceeded */
   BF_S_ACT_OVERFLOW = 1u << 1,    /* active list capacity exceeded */
   BF_S_INFEASIBLE = 1u << 2,      /* some active pair has d <= eta (energy +inf) */
-  BF_S_BSR_OVERFLOW = 1u << 3    /* BSR block capacity exceeded */
+  BF_S_BSR_OVERFLOW = 1u << 3,   /* BSR block capacity exceeded */
+  BF_S_CORE_OVERFLOW = 1u << 4   /* more core pairs than bf_core_mark's capacity */
 };
 
 /* Pair types. */
 enum { BF_PT = 0, BF_EE = 1 };
 
-/* Per-active-pair flag bits. */
-enum { BF_F_FILTERED = 1, BF_F_INFEASIBLE = 4 };
+/* Per-active-pair flag bits (BF_F_CORE: under the temporary zero offset of
+ * Sec. 3.4, see bf_core_mark). */
+enum { BF_F_FILTERED = 1, BF_F_INFEASIBLE = 4, BF_F_CORE = 8 };
 
 typedef struct {
   double h;        /* thickness: activation distance of unfiltered pairs (Sec. 3) */
@@ -238,6 +240,31 @@ bf_status max_step_accd(bf_scene* s, const double* x_d, const double* p_d, const
                         void* stream);
 bf_status eval_energy(bf_scene* s, const double* x_d, const double* p_d, const double* alpha_d,
                       const bf_pairs* cand, double* E_d, void* stream);
+
+/* ---- temporary zero offset (Sec. 3.4) -----------------------------------
+ * Pairs that are not stencils but start closer than eta (inside the core:
+ * an input intersecting within the offset) make the biphasic barrier
+ * infinite.  The paper proposes a temporary filter: such pairs get offset 0
+ * (activation h, the single-phase barrier) until relaxation pushes them
+ * beyond eta.
+ *
+ * bf_core_mark: (re)builds the scene's set from the candidates at x_d: every
+ * candidate with d < h and d <= eta that is not a filtered stencil (the
+ * decisions of filter_pairs).  cap = the most pairs expected (the table
+ * holds at least 2 cap slots; a larger set raises BF_S_CORE_OVERFLOW and
+ * keeps the pairs that fit); count_d (device int64) = pairs marked.
+ * Synchronises when the table has to grow.
+ *
+ * While a set exists, filter_pairs first releases every pair of the set that
+ * is now at d > eta (for good), then gives the remaining ones (h, 0) and the
+ * flag BF_F_CORE; eval_barrier, eval_energy and max_step_accd use offset 0
+ * for them too.  bf_core_live: count_d = pairs not yet released.
+ * bf_core_clear: drop the set.  A batch captures the set as it is when the
+ * batch is created (mark before bf_batch_create). */
+bf_status bf_core_mark(bf_scene* s, const double* x_d, const bf_pairs* cand, int64_t cap, int64_t* count_d,
+                       void* stream);
+bf_status bf_core_live(bf_scene* s, int64_t* count_d, void* stream);
+bf_status bf_core_clear(bf_scene* s);
 
 /* ---- tuning ---------------------------------------------------------------
  * Threads per broad-phase query (2, 4 or 8; default 4): more threads split a

@@ -265,15 +265,16 @@ def accd_pair(ptype, X, P, xi, s=0.1, max_iter=65536):
     return float(t[0]), int(it[0])
 
 
-def max_step(scene, x, p, s=0.1, max_iter=65536, mode=1, filter_mode=0, eta=None, nthreads=0):
+def max_step(scene, x, p, s=0.1, max_iter=65536, mode=1, filter_mode=0, eta=None, nthreads=0, core=None):
     """ACCD over the pairs whose boxes swept from x to x + p are within h,
-    each with its filtered offset (eta, or 0 for filtered stencils).
+    each with its filtered offset (eta, or 0 for filtered stencils and for
+    the pairs of the core set, Sec. 3.4).
 
     Returns dict(t=min step (1 if no pair), ptype, i, j, filtered, iters, xi,
     tpair) with the pairs sorted by (ptype, i, j)."""
     x = np.ascontiguousarray(x, np.float64)
     p = np.ascontiguousarray(p, np.float64)
-    sc, keep = _scene_struct(scene, filter_mode, eta)
+    sc, keep = _scene_struct(scene, filter_mode, eta, core=core)
     L = lib()
     h = L.orc_max_step(C.byref(sc), _p(x), _p(p), float(s), int(max_iter), int(mode), int(nthreads))
     try:

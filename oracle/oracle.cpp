@@ -1021,7 +1021,9 @@ void* orc_max_step(const orc_scene* s, const double* x, const double* p, double 
     StepRec r;
     r.ptype = ptype; r.i = i; r.j = j;
     r.filtered = is_filtered(m, ptype, i, j) ? 1 : 0;
-    r.xi = r.filtered ? 0.0 : m.eta;  // Eq. 4: filtered stencils have no offset
+    // Eq. 4: filtered stencils have no offset; nor do pairs in the core set (Sec. 3.4)
+    const bool core = !r.filtered && !m.core.empty() && m.core.count(pair_key(ptype, i, j)) != 0;
+    r.xi = r.filtered || core ? 0.0 : m.eta;
     r.t = accd_pair(ptype, X, P, r.xi, sfac, max_iter, &r.iters);
     recs[omp_get_thread_num()].push_back(r);
   };

@@ -22,13 +22,14 @@ BF_ROD, BF_SHELL = 0, 1
 BF_FP64, BF_MIXED = 0, 1
 BF_FILTER_PAPER, BF_FILTER_NONE = 0, 1
 BF_S_CAND_OVERFLOW, BF_S_ACT_OVERFLOW, BF_S_INFEASIBLE = 1, 2, 4
-BF_S_BSR_OVERFLOW = 8
-BF_F_FILTERED, BF_F_INFEASIBLE = 1, 4
+BF_S_BSR_OVERFLOW, BF_S_CORE_OVERFLOW = 8, 16
+BF_F_FILTERED, BF_F_INFEASIBLE, BF_F_CORE = 1, 4, 8
 
 EXPORTED = ["bf_scene_create", "bf_scene_reserve", "bf_scene_destroy", "bf_scene_info", "build_candidates",
             "filter_pairs", "eval_barrier", "assemble_grad_hess", "bf_scene_set_pq", "bf_scene_tune",
             "bf_batch_create", "bf_batch_step", "bf_batch_info", "bf_batch_destroy", "build_candidates_swept",
-            "max_step_accd", "eval_energy", "bf_status_word", "bf_last_error"]
+            "max_step_accd", "eval_energy", "bf_core_mark", "bf_core_live", "bf_core_clear", "bf_status_word",
+            "bf_last_error"]
 
 
 def build(verbose: bool = False) -> str:
@@ -106,6 +107,9 @@ def lib():
         L.build_candidates_swept.argtypes = [P, P, P, C.POINTER(Pairs), P]
         L.max_step_accd.argtypes = [P, P, P, C.POINTER(Pairs), C.c_double, C.c_int32, P, P, P, P]
         L.eval_energy.argtypes = [P, P, P, P, C.POINTER(Pairs), P, P]
+        L.bf_core_mark.argtypes = [P, P, C.POINTER(Pairs), C.c_int64, P, P]
+        L.bf_core_live.argtypes = [P, P, P]
+        L.bf_core_clear.argtypes = [P]
         L.bf_status_word.argtypes = [P, C.POINTER(C.c_uint32), C.c_int32]
         L.bf_last_error.restype = C.c_char_p
         for name in EXPORTED[:-1]:
@@ -260,6 +264,24 @@ class ContactScene:
                                  _ptr(alpha) if alpha is not None else None, C.byref(self._cand), _ptr(E),
                                  C.c_void_p(self._stream())), "eval_energy")
         return E
+
+    # -- temporary zero offset (Sec. 3.4) ------------------------------------
+    def core_mark(self, x, cap=None):
+        """Mark the non-stencil pairs inside the core at x (uses the current
+        candidates: call build_candidates(x) first).  Returns a device int64[1]
+        count."""
+        cnt = self.torch.zeros(1, dtype=self.torch.int64, device=self.device)
+        _check(lib().bf_core_mark(self.handle, _ptr(x), C.byref(self._cand), int(cap or max(64, self.act_cap)),
+                                  _ptr(cnt), C.c_void_p(self._stream())), "bf_core_mark")
+        return cnt
+
+    def core_live(self):
+        cnt = self.torch.zeros(1, dtype=self.torch.int64, device=self.device)
+        _check(lib().bf_core_live(self.handle, _ptr(cnt), C.c_void_p(self._stream())), "bf_core_live")
+        return cnt
+
+    def core_clear(self):
+        _check(lib().bf_core_clear(self.handle), "bf_core_clear")
 
     def set_pq(self, pq):
         """Threads per broad-phase query (2, 4 or 8)."""

@@ -23,6 +23,11 @@ struct bf_scene {
   double* d_thr2 = nullptr;
   unsigned* d_status = nullptr;
   double* d_line = nullptr;  // [LINE_BLOCKS] per-block minima / sums of the line-search calls
+  // temporary zero offset (Sec. 3.4): pair keys and live flags, core_slots a power of two (0: no set)
+  unsigned long long* core_key = nullptr;
+  unsigned char* core_live = nullptr;
+  unsigned core_slots = 0;
+  std::vector<void*> core_allocs;
   std::vector<int> comp_h;
   std::vector<double> dmin2_h, dmin_h;
   BroadWs bw{};
@@ -95,6 +100,9 @@ SceneDev dev_view(const bf_scene* s) {
   S.eta = s->prm.eta;
   S.kappa = s->prm.kappa;
   S.filter = s->prm.filter;
+  S.core_key = s->core_slots ? s->core_key : nullptr;
+  S.core_live = s->core_live;
+  S.core_mask = s->core_slots ? s->core_slots - 1 : 0;
   S.mixed = s->prm.prec == BF_MIXED;
   S.pq = s->pq;
   return S;
@@ -372,6 +380,7 @@ bf_status bf_scene_destroy(bf_scene* s) {
   // on the side stream always joins back into that stream)
   free_list(s->asm_allocs, s->last);
   free_list(s->stage_allocs, s->last);
+  free_list(s->core_allocs, s->last);
   free_list(s->allocs, s->last);
   if (s->ev_join) (void)hipEventDestroy(s->ev_join);
   if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
@@ -431,6 +440,62 @@ bf_status max_step_accd(bf_scene* s, const double* x_d, const double* p_d, const
   return he == hipSuccess ? BF_OK : fail_hip(he, "max_step_accd");
 }
 
+bf_status bf_core_mark(bf_scene* s, const double* x_d, const bf_pairs* cand, int64_t cap, int64_t* count_d,
+                       void* stream) {
+  if (!s || !x_d || !cand || !cand->i_d || !cand->j_d || !cand->type_d || !cand->count_d || !count_d || cap < 1 ||
+      cand->cap < 1)
+    return fail(BF_E_ARG, "bf_core_mark: null argument or capacity < 1");
+  if (cap > (1LL << 29)) return fail(BF_E_ARG, "bf_core_mark: capacity above 2^29 pairs");
+  hipStream_t st = (hipStream_t)stream;
+  s->last = st;
+  unsigned slots = 64;
+  while ((long long)slots < 2 * cap) slots <<= 1;
+  if (slots > s->core_slots) {  // grow: as bf_scene_reserve, between device synchronisations
+    hipError_t he = hipDeviceSynchronize();
+    if (he != hipSuccess) return fail_hip(he, "bf_core_mark");
+    g_alloc_stream = nullptr;
+    free_list(s->core_allocs, nullptr);
+    s->core_slots = 0;
+    hipError_t e = hipSuccess;
+    s->core_key = dalloc<unsigned long long>(s->core_allocs, slots, &e);
+    s->core_live = dalloc<unsigned char>(s->core_allocs, slots, &e);
+    if (e != hipSuccess) {
+      free_list(s->core_allocs, nullptr);
+      return fail(BF_E_NOMEM, "bf_core_mark: device allocation failed");
+    }
+    if ((he = hipDeviceSynchronize()) != hipSuccess) return fail_hip(he, "bf_core_mark");
+    s->core_slots = slots;
+  }
+  SceneDev S = dev_view(s);
+  S.core_key = nullptr;  // marking uses the plain offsets
+  run_core_mark(S, x_d, cand->i_d, cand->j_d, cand->type_d, (const long long*)cand->count_d, cand->cap, s->core_key,
+                s->core_live, s->core_slots, cap, (long long*)count_d, s->d_status, st);
+  hipError_t he = hipGetLastError();
+  return he == hipSuccess ? BF_OK : fail_hip(he, "bf_core_mark");
+}
+
+bf_status bf_core_live(bf_scene* s, int64_t* count_d, void* stream) {
+  if (!s || !count_d) return fail(BF_E_ARG, "bf_core_live: null argument");
+  hipStream_t st = (hipStream_t)stream;
+  if (!s->core_slots) {
+    hipError_t he = hipMemsetAsync(count_d, 0, sizeof(int64_t), st);
+    return he == hipSuccess ? BF_OK : fail_hip(he, "bf_core_live");
+  }
+  s->last = st;
+  run_core_count(dev_view(s), (long long*)count_d, st);
+  hipError_t he = hipGetLastError();
+  return he == hipSuccess ? BF_OK : fail_hip(he, "bf_core_live");
+}
+
+bf_status bf_core_clear(bf_scene* s) {
+  if (!s) return fail(BF_E_ARG, "bf_core_clear: null scene");
+  free_list(s->core_allocs, s->last);
+  s->core_key = nullptr;
+  s->core_live = nullptr;
+  s->core_slots = 0;
+  return BF_OK;
+}
+
 bf_status eval_energy(bf_scene* s, const double* x_d, const double* p_d, const double* alpha_d, const bf_pairs* cand,
                       double* E_d, void* stream) {
   if (!s || !x_d || !cand || !cand->i_d || !cand->j_d || !cand->type_d || !cand->count_d || !E_d || cand->cap < 1)
@@ -454,6 +519,7 @@ bf_status filter_pairs(bf_scene* s, const double* x_d, const bf_pairs* cand, bf_
   hipStream_t st = (hipStream_t)stream;
   s->last = st;
   s->prepared = false;
+  if (s->core_slots) run_core_release(dev_view(s), x_d, st);  // Sec. 3.4: pairs now beyond eta leave the set
   run_narrow(dev_view(s), x_d, cand->i_d, cand->j_d, cand->type_d, (const long long*)cand->count_d, cand->cap, s->sw,
              act->p.i_d, act->p.j_d, act->p.type_d, act->code_d, act->flags_d, act->dist_d, act->p.cap,
              (long long*)act->p.count_d, (long long*)act->counters_d, s->d_status, st);

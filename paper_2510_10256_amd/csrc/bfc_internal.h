@@ -40,6 +40,11 @@ struct SceneDev {
   const double* dmin;  // [C] activation of filtered pairs
   const double* thr2;  // [C,2] exact squared activation of filtered pairs (hi, lo)
   double h, eta, kappa;
+  // pairs under the temporary zero offset (Sec. 3.4): open-addressing table
+  // of packed pair keys and their live flags (core_key null: no such pairs)
+  const unsigned long long* core_key;
+  const unsigned char* core_live;
+  unsigned core_mask;  // slots - 1
   int filter;  // 0 paper, 1 none
   int mixed;   // 1: projection converged to the mixed-precision tolerance
   int pq;      // threads per broad-phase query (2, 4 or 8)

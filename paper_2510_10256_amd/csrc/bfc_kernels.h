@@ -26,6 +26,11 @@ void run_broad(const SceneDev& S, const double* x, const double* pdisp, const Br
 void run_accd(const SceneDev& S, const double* x, const double* pdisp, const int* ci, const int* cj,
               const unsigned char* ct, const long long* ccount, long long ccap, double s, int max_iter, double* tpair,
               int* iters, double* bred, double* t_out, hipStream_t st);
+void run_core_mark(const SceneDev& S, const double* x, const int* ci, const int* cj, const unsigned char* ct,
+                   const long long* ccount, long long ccap, unsigned long long* keys, unsigned char* live,
+                   unsigned slots, long long cap, long long* count, unsigned* status, hipStream_t st);
+void run_core_release(const SceneDev& S, const double* x, hipStream_t st);
+void run_core_count(const SceneDev& S, long long* out, hipStream_t st);
 void run_energy(const SceneDev& S, const double* x, const double* pdisp, const double* alpha, const int* ci,
                 const int* cj, const unsigned char* ct, const long long* ccount, long long ccap, double* bred,
                 double* E_out, hipStream_t st);

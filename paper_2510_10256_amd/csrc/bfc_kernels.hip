@@ -736,6 +736,32 @@ __device__ dd ref_sqdist_q(const SceneDev& S, int type, const int* v) {
   return dd_min(dd_min(seg2q(P[0], P[2], P[3]), seg2q(P[1], P[2], P[3])), dd_min(seg2q(P[2], P[0], P[1]), seg2q(P[3], P[0], P[1])));
 }
 
+// Pairs under the temporary zero offset (Sec. 3.4): key = type << 62 |
+// i << 31 | j, open addressing with linear probing over a power-of-two
+// table that is at most half full.
+constexpr unsigned long long CORE_EMPTY = ~0ull;
+__device__ __forceinline__ unsigned long long core_key_of(int type, int i, int j) {
+  return ((unsigned long long)type << 62) | ((unsigned long long)(unsigned)i << 31) | (unsigned long long)(unsigned)j;
+}
+__device__ __forceinline__ unsigned core_hash(unsigned long long k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  return (unsigned)k;
+}
+__device__ __forceinline__ bool in_core(const SceneDev& S, int type, int i, int j) {
+  if (!S.core_key) return false;
+  const unsigned long long key = core_key_of(type, i, j);
+  unsigned h = core_hash(key) & S.core_mask;
+  for (unsigned p = 0; p <= S.core_mask; ++p) {
+    const unsigned long long kk = S.core_key[h];
+    if (kk == key) return S.core_live[h] != 0;
+    if (kk == CORE_EMPTY) return false;
+    h = (h + 1) & S.core_mask;
+  }
+  return false;
+}
+
 // Stencil pair with 0 < dbar < h in the same component (Sec. 3.2)?
 __device__ __forceinline__ bool is_filtered(const SceneDev& S, int type, const int* v) {
   if (S.filter != 0) return false;
@@ -784,7 +810,7 @@ __global__ __launch_bounds__(256) void k_narrow(SceneDev S, const double* x, con
 #pragma unroll
   for (int it = 0; it < NW_ITEMS; ++it) {
     long long k = base + it * 256 + threadIdx.x;
-    bool nc = false, filt = false, active = false, infeas = false;
+    bool nc = false, filt = false, core = false, active = false, infeas = false;
     int type = 0, i = 0, j = 0, code = 0;
     double D = 0.0;
     if (k < n) {
@@ -798,15 +824,16 @@ __global__ __launch_bounds__(256) void k_narrow(SceneDev S, const double* x, con
       nc = decide_sq(code, P, D, h2, true);  // d < h
       if (nc) {
         filt = is_filtered(S, type, v);
+        core = !filt && in_core(S, type, i, j);
         dd T;
         double eta;
         if (filt) {  // Eq. 4 second case: (d_min, 0)
           int c = S.comp[v[0]];
           T = dd{S.thr2[2 * c], S.thr2[2 * c + 1]};
           eta = 0.0;
-        } else {     // Eq. 4 first case: (h, eta)
+        } else {     // Eq. 4 first case: (h, eta); (h, 0) while in the core set (Sec. 3.4)
           T = h2;
-          eta = S.eta;
+          eta = core ? 0.0 : S.eta;
         }
         active = decide_sq(code, P, D, T, true);  // Eq. 2: d < a
         if (active) infeas = eta > 0.0 ? decide_sq(code, P, D, e2, false) : !(D > 0.0);
@@ -817,7 +844,7 @@ __global__ __launch_bounds__(256) void k_narrow(SceneDev S, const double* x, con
     rk[it] = active ? kind_rank(code) : 3;
     ri[it] = i; rj[it] = j;
     rm[it] = (unsigned)type | ((unsigned)code << 8) |
-             ((unsigned)((filt ? BF_F_FILTERED : 0) | (infeas ? BF_F_INFEASIBLE : 0)) << 16);
+             ((unsigned)((filt ? BF_F_FILTERED : 0) | (infeas ? BF_F_INFEASIBLE : 0) | (core ? BF_F_CORE : 0)) << 16);
     rd[it] = sqrt(D);
 #pragma unroll
     for (int K = 0; K < 3; ++K) {
@@ -965,7 +992,7 @@ __global__ __launch_bounds__(64) void k_eval(SceneDev S, const double* x, const 
         d3 P[4] = {load3(x, v[0]), load3(x, v[1]), load3(x, v[2]), load3(x, v[3])};
         double a, eta;
         if (fl & BF_F_FILTERED) { a = S.dmin[S.comp[v[0]]]; eta = 0.0; }
-        else { a = S.h; eta = S.eta; }
+        else { a = S.h; eta = (fl & BF_F_CORE) ? 0.0 : S.eta; }
         eval_pair<MIXED>(P, code, a, eta, S.kappa, G + 12 * k, h);
       }
       E[k] = h.E;
@@ -1743,7 +1770,7 @@ __global__ __launch_bounds__(256) void k_accd(SceneDev S, const double* x, const
     double t = -1.0;
     int it = 0;
     if (swept_within(type, X, P, S.h)) {
-      const double xi = is_filtered(S, type, v) ? 0.0 : S.eta;
+      const double xi = is_filtered(S, type, v) || in_core(S, type, ci[k], cj[k]) ? 0.0 : S.eta;
       t = accd_stencil(type, X, P, xi, s, max_iter, it);
       tmin = fmin(tmin, t);
     }
@@ -1806,7 +1833,7 @@ __global__ __launch_bounds__(256) void k_energy(SceneDev S, const double* x, con
     } else {
       T = h2;
       a = S.h;
-      eta = S.eta;
+      eta = in_core(S, type, ci[k], cj[k]) ? 0.0 : S.eta;
     }
     if (!decide_sq(nr.code, P, nr.D, T, true)) continue;  // inactive: d >= a
     const bool infeas = eta > 0.0 ? decide_sq(nr.code, P, nr.D, e2, false) : !(nr.D > 0.0);
@@ -1829,6 +1856,73 @@ __global__ __launch_bounds__(256) void k_energy(SceneDev S, const double* x, con
 // Fixed-order total of the per-block sums (one wave).
 __global__ __launch_bounds__(64) void k_sum_final(const double* bsum, int nb, double* out) {
   energy_total(bsum, nb, out);
+}
+
+// ---------------------------------------------------------------------------
+// Temporary zero offset (Sec. 3.4): marking, release, count
+// ---------------------------------------------------------------------------
+
+// Insert every candidate with d < h and d <= eta that is not a filtered
+// stencil (exact decisions, as in the narrow phase).
+__global__ __launch_bounds__(256) void k_core_mark(SceneDev S, const double* x, const int* ci, const int* cj,
+                                                   const unsigned char* ct, const long long* cand_count,
+                                                   long long ccap, unsigned long long* keys, unsigned char* live,
+                                                   unsigned mask, long long cap, unsigned long long* count,
+                                                   unsigned* status) {
+  long long n = *cand_count;
+  if (n > ccap) n = ccap;
+  const dd h2 = dd_sq(S.h), e2 = dd_sq(S.eta);
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += grid_stride()) {
+    const int type = ct[k], i = ci[k], j = cj[k];
+    int v[4];
+    pair_verts(S, type, i, j, v);
+    d3 P[4] = {load3(x, v[0]), load3(x, v[1]), load3(x, v[2]), load3(x, v[3])};
+    const Near nr = type == BF_PT ? classify_pt(P) : classify_ee(P);
+    if (!decide_sq(nr.code, P, nr.D, h2, true)) continue;    // d >= h
+    if (is_filtered(S, type, v)) continue;                  // stencils have no offset anyway
+    if (!decide_sq(nr.code, P, nr.D, e2, false)) continue;  // d > eta
+    const unsigned long long key = core_key_of(type, i, j);
+    unsigned h = core_hash(key) & mask;
+    bool placed = false;
+    for (unsigned p = 0; p <= mask; ++p) {
+      const unsigned long long old = atomicCAS(&keys[h], CORE_EMPTY, key);
+      if (old == CORE_EMPTY || old == key) {
+        live[h] = 1;
+        placed = old == CORE_EMPTY;
+        break;
+      }
+      h = (h + 1) & mask;
+    }
+    if (!placed || (long long)atomicAdd(count, 1ull) >= cap) atomicOr(status, (unsigned)BF_S_CORE_OVERFLOW);
+  }
+}
+
+// Release, for good, every live pair now at d > eta.
+__global__ __launch_bounds__(256) void k_core_release(SceneDev S, const double* x, const unsigned long long* keys,
+                                                      unsigned char* live, unsigned slots) {
+  const dd e2 = dd_sq(S.eta);
+  for (unsigned q = blockIdx.x * blockDim.x + threadIdx.x; q < slots; q += grid_stride()) {
+    if (!live[q]) continue;
+    const unsigned long long key = keys[q];
+    const int type = (int)(key >> 62), i = (int)((key >> 31) & 0x7fffffffull), j = (int)(key & 0x7fffffffull);
+    int v[4];
+    pair_verts(S, type, i, j, v);
+    d3 P[4] = {load3(x, v[0]), load3(x, v[1]), load3(x, v[2]), load3(x, v[3])};
+    const Near nr = type == BF_PT ? classify_pt(P) : classify_ee(P);
+    if (!decide_sq(nr.code, P, nr.D, e2, false)) live[q] = 0;
+  }
+}
+
+// Number of live pairs (one block).
+__global__ __launch_bounds__(256) void k_core_count(const unsigned char* live, unsigned slots, long long* out) {
+  long long c = 0;
+  for (unsigned q = threadIdx.x; q < slots; q += blockDim.x) c += live[q];
+  c = block_sum256(c);
+  if (threadIdx.x == 0) *out = c;
+}
+
+__global__ void k_fill_u8(unsigned char* a, long long n, unsigned char v) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += grid_stride()) a[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -2000,6 +2094,26 @@ void run_accd(const SceneDev& S, const double* x, const double* pdisp, const int
   hipLaunchKernelGGL(k_accd, dim3(nb), dim3(256), 0, st, S, x, pdisp, ci, cj, ct, ccount, ccap, s, max_iter, tpair,
                      iters, bred);
   hipLaunchKernelGGL(k_min_final, dim3(1), dim3(256), 0, st, bred, nb, t_out);
+}
+
+void run_core_mark(const SceneDev& S, const double* x, const int* ci, const int* cj, const unsigned char* ct,
+                   const long long* ccount, long long ccap, unsigned long long* keys, unsigned char* live,
+                   unsigned slots, long long cap, long long* count, unsigned* status, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(slots)), dim3(256), 0, st, keys, (long long)slots, CORE_EMPTY);
+  hipLaunchKernelGGL(k_fill_u8, dim3(nblocks(slots)), dim3(256), 0, st, live, (long long)slots, (unsigned char)0);
+  hipLaunchKernelGGL(k_zero_ll, dim3(1), dim3(64), 0, st, count, 1, nullptr, 0);
+  hipLaunchKernelGGL(k_core_mark, dim3(nblocks(ccap)), dim3(256), 0, st, S, x, ci, cj, ct, ccount, ccap, keys, live,
+                     slots - 1, cap, (unsigned long long*)count, status);
+}
+
+void run_core_release(const SceneDev& S, const double* x, hipStream_t st) {
+  const unsigned slots = S.core_mask + 1;
+  hipLaunchKernelGGL(k_core_release, dim3(nblocks(slots)), dim3(256), 0, st, S, x, S.core_key,
+                     const_cast<unsigned char*>(S.core_live), slots);
+}
+
+void run_core_count(const SceneDev& S, long long* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_core_count, dim3(1), dim3(256), 0, st, S.core_live, S.core_mask + 1, out);
 }
 
 void run_energy(const SceneDev& S, const double* x, const double* pdisp, const double* alpha, const int* ci,

@@ -441,6 +441,20 @@ def serving_scenes(seed: int = BASE_SEED + 4000, n_scenes: int = 256, median: fl
     return out
 
 
+def crossing_rods(z: float = 250.0, n: int = 14, ell: float = 100.0, h: float = 300.0,
+                  eta: float = 270.0) -> Scene:
+    """Two straight rods crossing at right angles, centrelines z apart
+    (z < eta: the crossing starts inside the core).  n vertices per rod,
+    segments of length ell centred on the crossing."""
+    xs = (np.arange(n) - (n - 1) / 2.0) * ell
+    a = np.stack([xs, np.zeros(n), np.zeros(n)], 1)
+    b = np.stack([np.zeros(n), xs, np.full(n, float(z))], 1)
+    e = np.stack([np.arange(n - 1), np.arange(1, n)], 1)
+    s = xs - xs[0]
+    return Scene("crossing_rods", "rod", np.concatenate([a, b]), np.concatenate([e, e + n]).astype(np.int32),
+                 np.zeros((0, 3), np.int32), np.concatenate([s, s]), h=float(h), eta=float(eta), seed=0)
+
+
 def search_direction(scene: Scene, seed: int = BASE_SEED + 5000) -> np.ndarray:
     """Seeded displacement field for line-search workloads: a squeeze of the
     scene toward its mid-plane in z (3 activation bands at the extremes) plus

@@ -21,26 +21,13 @@ import math
 import numpy as np
 
 import oracle
+import synth
 
 H, ETA = 300.0, 270.0
 
 
-class _Cross:
-    kind = "rod"
-    h, eta, kappa = H, ETA, 1.0
-
-    def __init__(self, z):
-        xs = np.arange(-650.0, 651.0, 100.0)   # 14 vertices, segments centred on 0
-        n = len(xs)
-        a = np.stack([xs, np.zeros(n), np.zeros(n)], 1)
-        b = np.stack([np.zeros(n), xs, np.full(n, z)], 1)
-        self.x = np.concatenate([a, b])
-        self.n_verts, self.n_edges, self.n_tris = 2 * n, 2 * (n - 1), 0
-        e = np.stack([np.arange(n - 1), np.arange(1, n)], 1)
-        self.edges = np.concatenate([e, e + n]).astype(np.int32)
-        self.tris = np.zeros((0, 3), np.int32)
-        s = xs - xs[0]
-        self.ref = np.concatenate([s, s])
+def _Cross(z):
+    return synth.crossing_rods(z, n=14, ell=100.0, h=H, eta=ETA)
 
 
 def _mid_edges(sc):
@@ -116,7 +103,6 @@ def test_filtered_stencils_are_never_core():
     # the helix rod squeezed along its axis: successive turns come closer
     # than eta (core pairs), while the rod's own neighbours, much closer
     # still, are filtered stencils and must stay out of the core set
-    import synth
     sc = synth.helix_loop_rod()
     x = sc.x * np.array([1.0, 1.0, 0.9])
     res = oracle.evaluate(sc, x, derivs=False)
