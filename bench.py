@@ -74,13 +74,16 @@ def parse():
     ap.add_argument("--path", default="step", choices=["step", "linesearch"],
                     help="step: the four calls of a Newton step (default); linesearch: swept broad phase, additive "
                          "CCD with the filtered offsets and the energy at the step found (one pass per step)")
+    ap.add_argument("--core-squeeze", type=float, default=0.0,
+                    help="step path: scale z by this factor (e.g. 0.88 puts the woven crossings inside the core) and "
+                         "mark the pairs inside the core for the temporary zero offset before timing (Sec. 3.4)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
-def cpu_baseline(sc, n_c_gpu):
+def cpu_baseline(sc, n_c_gpu, x=None, core=None):
     """The oracle, as it stands, on the same workload (swept enumeration,
     derivatives of every active pair); repeated until ~10 s of CPU work."""
     import oracle
@@ -88,7 +91,7 @@ def cpu_baseline(sc, n_c_gpu):
     reps, t_total, n_c = 0, 0.0, 0
     while t_total < 10.0 and reps < 20:
         t0 = time.perf_counter()
-        res = oracle.evaluate(sc, mode=1, derivs=True, nthreads=threads)
+        res = oracle.evaluate(sc, x, mode=1, derivs=True, nthreads=threads, core=core)
         t_total += time.perf_counter() - t0
         n_c = oracle.counts(res)["n_c"]
         reps += 1
@@ -417,10 +420,16 @@ def main():
     sc = synth.workload(args.workload)
     prec = bfc.BF_FP64 if args.prec == "fp64" else bfc.BF_MIXED
     dev = torch.device("cuda:0")
-    x = torch.tensor(sc.x, dtype=torch.float64, device=dev)
+    x_np = sc.x * np.array([1.0, 1.0, args.core_squeeze]) if args.core_squeeze > 0 else sc.x
+    x = torch.tensor(x_np, dtype=torch.float64, device=dev)
     cs = bfc.ContactScene(sc, prec=prec, device=dev)
     t0 = time.perf_counter()
     cs.run(x)  # sizes the buffers (grows them on overflow, then steps again)
+    n_core = 0
+    if args.core_squeeze > 0:  # the temporary zero offset of the pairs inside the core (Sec. 3.4)
+        cs.build_candidates(x)
+        n_core = int(cs.core_mark(x).item())
+        cs.run(x)
     if args.tune:
         cs.tune(x)  # threads per broad-phase query
         cs.run(x)
@@ -528,7 +537,8 @@ def main():
     eval_ms = e0.elapsed_time(e1) / reps
     roof = eval_roofline(eval_ms, n_act, kinds, "k_eval (eval_barrier)")
     roof["kernel_ms"] = eval_ms
-    if args.prec == "fp64" and sc.name in EVAL_TRAFFIC_BYTES and eval_source_fingerprint() == EVAL_TRAFFIC_SOURCE:
+    if (args.prec == "fp64" and args.core_squeeze == 0 and sc.name in EVAL_TRAFFIC_BYTES
+            and eval_source_fingerprint() == EVAL_TRAFFIC_SOURCE):
         roof["traffic"] = EVAL_TRAFFIC_BYTES[sc.name]
 
     out = {
@@ -548,10 +558,14 @@ def main():
         "data": "synthetic (seeded generator)",
         "config": {"workload": f"{sc.name}: " + ("32 warp x 32 weft rods, 512 vertices per rod, segments "
                                                  "20-300 um, h = 300 um, dhat = 30 um"
-                                                 if sc.name == "woven_patch" else sc.name),
+                                                 if sc.name == "woven_patch" else sc.name)
+                               + (f"; z scaled by {args.core_squeeze}, pairs inside the core under the temporary "
+                                  f"zero offset" if args.core_squeeze > 0 else ""),
                    "n_verts": sc.n_verts, "n_edges": sc.n_edges, "n_tris": sc.n_tris,
                    "N_bp": counts["n_bp"], "N_c": n_c, "N_filt": counts["n_filt"], "N_act": n_act,
-                   "nnzb": counts["nnzb"], "launch": launch, "pq": cs.pq, "precision": args.prec},
+                   "nnzb": counts["nnzb"], "launch": launch, "pq": cs.pq, "precision": args.prec,
+                   **({"core_squeeze_z": args.core_squeeze, "core_pairs_marked": n_core,
+                       "core_pairs_live": int(cs.core_live().item())} if args.core_squeeze > 0 else {})},
         "active_pairs_per_s": n_act / (ms_per_step * 1e-3),
         "call_ms": call_ms,
         "launch": launch,
@@ -560,7 +574,11 @@ def main():
         "roofline": roof,
     }
     if args.cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sc, n_c)
+        core = None
+        if args.core_squeeze > 0:
+            import oracle
+            core = oracle.core_mark(sc, x_np)
+        out["cpu_baseline"] = cpu_baseline(sc, n_c, x_np if args.core_squeeze > 0 else None, core)
     print(json.dumps(out))
 
 
