@@ -48,7 +48,7 @@ class _Scene(C.Structure):
                 ("edges", C.c_void_p), ("tris", C.c_void_p), ("ref", C.c_void_p),
                 ("h", C.c_double), ("eta", C.c_double), ("kappa", C.c_double),
                 ("filter_mode", C.c_int32), ("n_core", C.c_int64), ("core_ptype", C.c_void_p),
-                ("core_i", C.c_void_p), ("core_j", C.c_void_p)]
+                ("core_i", C.c_void_p), ("core_j", C.c_void_p), ("cull_radius", C.c_int32)]
 
 
 _lib = None
@@ -91,7 +91,7 @@ def _p(a):
     return a.ctypes.data_as(C.c_void_p) if a is not None else None
 
 
-def _scene_struct(scene, filter_mode=0, eta=None, kappa=None, core=None):
+def _scene_struct(scene, filter_mode=0, eta=None, kappa=None, core=None, cull_radius=11):
     keep = []
     edges = np.ascontiguousarray(scene.edges, np.int32)
     tris = np.ascontiguousarray(scene.tris, np.int32)
@@ -108,7 +108,7 @@ def _scene_struct(scene, filter_mode=0, eta=None, kappa=None, core=None):
                _p(edges), _p(tris) if tris.size else None, _p(ref),
                float(scene.h), float(scene.eta if eta is None else eta),
                float(scene.kappa if kappa is None else kappa), int(filter_mode), n_core,
-               _p(cp), _p(ci), _p(cj))
+               _p(cp), _p(ci), _p(cj), int(cull_radius))
     return s, keep
 
 
@@ -124,17 +124,19 @@ def precompute(scene, filter_mode=0):
 
 
 def evaluate(scene, x=None, mode=1, derivs=True, filter_mode=0, eta=None, kappa=None,
-             nthreads=0, core=None):
+             nthreads=0, core=None, cull_radius=11):
     """Every pair of the universe with d < h, sorted by (ptype, i, j).
 
     Returns a dict of numpy arrays: ptype, i, j, verts[n,4], code, flags, d, a,
     eta, E, G[n,12], Hraw[n,12,12], Hpsd[n,12,12] (derivative arrays are zero
     for inactive pairs; E is +inf for infeasible active pairs).  core: the
     (ptype, i, j) arrays of pairs under the temporary zero offset (Sec. 3.4;
-    pass the ones not released at x, see core_release).
+    pass the ones not released at x, see core_release).  filter_mode: 0 the
+    paper's filter (Eq. 4), 1 none, 2 culling of edges of one polyline at most
+    cull_radius elements apart (rods).
     """
     x = np.ascontiguousarray(scene.x if x is None else x, np.float64)
-    s, keep = _scene_struct(scene, filter_mode, eta, kappa, core)
+    s, keep = _scene_struct(scene, filter_mode, eta, kappa, core, cull_radius)
     L = lib()
     h = L.orc_evaluate(C.byref(s), _p(x), int(mode), int(bool(derivs)), int(nthreads))
     try:

@@ -411,7 +411,10 @@ struct Mesh {
   const int32_t* tris;
   const double* ref;
   double h, eta, kappa;
-  int filter_mode;  // 0 paper (Eq. 4), 1 none (plain offset barrier everywhere)
+  int filter_mode;  // 0 paper (Eq. 4), 1 none (plain offset barrier everywhere), 2 cull (rods)
+  int cull_radius;  // mode 2: edges of one polyline at most this many elements apart are ignored
+  std::vector<int> edge_pos;   // mode 2: index of each edge along its polyline
+  std::vector<int> loop_len;   // mode 2: edge count of the edge's polyline if it is closed, else 0
   std::vector<int32_t> comp;
   std::vector<double> dmin2, dmin;  // per component; +inf when nothing is filtered
   // exact squared activation threshold of filtered pairs per component: the
@@ -495,6 +498,51 @@ bool is_filtered(const Mesh& m, int ptype, int i, int j) {
   ref_dist<f128>(m, ptype, i, j, &q, &g);
   f128 hq = (f128)m.h * (f128)m.h;
   return q > hq * (f128)kTie && q < hq * (1 - (f128)kTie);
+}
+
+// Culling comparison mode (Kaldor et al.): two edges of the same polyline
+// whose positions along it differ by at most the radius (the shorter way
+// round a closed loop) are not contact pairs.
+bool is_culled(const Mesh& m, int ptype, int i, int j) {
+  if (m.filter_mode != 2 || ptype != 1) return false;
+  if (m.comp[m.edges[2 * i]] != m.comp[m.edges[2 * j]]) return false;
+  int d = std::abs(m.edge_pos[i] - m.edge_pos[j]);
+  if (m.loop_len[i] > 0) d = std::min(d, m.loop_len[i] - d);
+  return d <= m.cull_radius;
+}
+
+// Positions of the edges along each polyline: walk every open polyline from
+// its lower-numbered end, then every closed loop from its smallest vertex.
+void order_polylines(Mesh& m) {
+  std::vector<std::vector<int>> inc(m.nv);
+  for (int64_t e = 0; e < m.ne; ++e) {
+    inc[m.edges[2 * e]].push_back((int)e);
+    inc[m.edges[2 * e + 1]].push_back((int)e);
+  }
+  m.edge_pos.assign(m.ne, -1);
+  m.loop_len.assign(m.ne, 0);
+  auto walk = [&](int v) {
+    std::vector<int> seq;
+    int prev = -1;
+    for (;;) {
+      int next = -1;
+      for (int e : inc[v])
+        if (e != prev && m.edge_pos[e] < 0) { next = e; break; }
+      if (next < 0) break;
+      m.edge_pos[next] = (int)seq.size();
+      seq.push_back(next);
+      v = m.edges[2 * next] == v ? m.edges[2 * next + 1] : m.edges[2 * next];
+      prev = next;
+    }
+    return seq;
+  };
+  for (int64_t v = 0; v < m.nv; ++v)
+    if (inc[v].size() == 1 && m.edge_pos[inc[v][0]] < 0) walk((int)v);
+  for (int64_t v = 0; v < m.nv; ++v)
+    if (inc[v].size() == 2 && m.edge_pos[inc[v][0]] < 0) {
+      std::vector<int> seq = walk((int)v);
+      for (int e : seq) m.loop_len[e] = (int)seq.size();
+    }
 }
 
 // Incident pairs share a vertex and are not in the pair universe.
@@ -633,6 +681,7 @@ void gather(const Mesh& m, const double* x, int ptype, int i, int j, int* verts,
 // Evaluate one pair of the universe; returns false if d >= h (not a contact
 // candidate at the full activation distance).
 bool eval_pair(const Mesh& m, const double* x, int ptype, int i, int j, bool derivs, Rec& r) {
+  if (is_culled(m, ptype, i, j)) return false;  // culling mode: not a contact pair
   double X[12];
   gather(m, x, ptype, i, j, r.verts, X);
   Dist ds = classify(ptype, X);
@@ -787,6 +836,7 @@ typedef struct {
   const int32_t* core_ptype;
   const int32_t* core_i;
   const int32_t* core_j;
+  int32_t cull_radius;  // filter_mode 2 (rods): radius in elements
 } orc_scene;
 
 static Mesh make_mesh(const orc_scene* s) {
@@ -798,6 +848,8 @@ static Mesh make_mesh(const orc_scene* s) {
   int nc = components(m.nv, m.ne, m.edges, m.tris, m.nt, m.comp.data());
   compute_dmin(m, nc);
   for (int64_t k = 0; k < s->n_core; ++k) m.core.insert(pair_key(s->core_ptype[k], s->core_i[k], s->core_j[k]));
+  m.cull_radius = s->cull_radius;
+  if (m.filter_mode == 2) order_polylines(m);
   return m;
 }
 
@@ -1012,7 +1064,7 @@ void* orc_max_step(const orc_scene* s, const double* x, const double* p, double 
     return true;
   };
   auto visit = [&](int ptype, int i, int j, const B& A, const B& Bb) {
-    if (incident(m, ptype, i, j) || !within_h(A, Bb)) return;
+    if (incident(m, ptype, i, j) || is_culled(m, ptype, i, j) || !within_h(A, Bb)) return;
     int verts[4];
     double X[12], P[12];
     gather(m, x, ptype, i, j, verts, X);

@@ -17,7 +17,9 @@ segments, 0.18-0.5 mm thick; its cloth table: 10k-100k triangles,
 0.1-5 mm thick).
 """
 from .scenes import (Scene, helix_loop_rod, woven_patch, folded_cloth,
-                     batch_scenes, serving_scenes, crossing_rods, search_direction, workload, WORKLOADS)
+                     batch_scenes, serving_scenes, crossing_rods, straight_rod, flat_sheet, search_direction,
+                     workload, WORKLOADS)
 
 __all__ = ["Scene", "helix_loop_rod", "woven_patch", "folded_cloth",
-           "batch_scenes", "serving_scenes", "crossing_rods", "search_direction", "workload", "WORKLOADS"]
+           "batch_scenes", "serving_scenes", "crossing_rods", "straight_rod", "flat_sheet", "search_direction",
+           "workload", "WORKLOADS"]

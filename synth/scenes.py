@@ -455,6 +455,45 @@ def crossing_rods(z: float = 250.0, n: int = 14, ell: float = 100.0, h: float = 
                  np.zeros((0, 3), np.int32), np.concatenate([s, s]), h=float(h), eta=float(eta), seed=0)
 
 
+def straight_rod(ell: float, length: float = 50000.0, h: float = 300.0) -> Scene:
+    """A straight rod at rest (the contact-locking toy of the paper: a 5 cm
+    yarn) with uniform segments of length ell.  The offset follows the
+    paper's comparison setting eta = 0.9 min(h, dbar_min), with
+    dbar_min = ell (the rest gap of edges two apart) when ell < h."""
+    n = int(round(length / ell)) + 1
+    xs = np.arange(n) * float(ell)
+    x = np.stack([xs, np.zeros(n), np.zeros(n)], 1)
+    e = np.stack([np.arange(n - 1), np.arange(1, n)], 1).astype(np.int32)
+    eta = 0.9 * min(h, float(ell))
+    return Scene(f"straight_rod_l{ell:g}", "rod", x, e, np.zeros((0, 3), np.int32), xs.copy(), h=float(h),
+                 eta=eta, seed=0)
+
+
+def flat_sheet(ell: float, side: float = 20000.0, h: float = 1000.0) -> Scene:
+    """A flat square sheet at rest, regular grid of spacing ell with one
+    diagonal per cell (rest coordinates = positions).  eta = 0.9 min(h,
+    dbar_min) with dbar_min = ell / sqrt(2) (a vertex to the diagonal of the
+    next cell)."""
+    n = int(round(side / ell)) + 1
+    ii, jj = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    u = np.stack([ii.ravel() * float(ell), jj.ravel() * float(ell)], 1)
+    x = np.concatenate([u, np.zeros((n * n, 1))], 1)
+    vid = lambda i, j: i * n + j
+    tris = []
+    for i in range(n - 1):
+        for j in range(n - 1):
+            tris.append((vid(i, j), vid(i + 1, j), vid(i + 1, j + 1)))
+            tris.append((vid(i, j), vid(i + 1, j + 1), vid(i, j + 1)))
+    tris = np.array(tris, np.int32)
+    ed = set()
+    for t in tris:
+        for a, b in ((t[0], t[1]), (t[1], t[2]), (t[2], t[0])):
+            ed.add((min(a, b), max(a, b)))
+    edges = np.array(sorted(ed), np.int32)
+    eta = 0.9 * min(h, float(ell) / np.sqrt(2.0))
+    return Scene(f"flat_sheet_l{ell:g}", "shell", x, edges, tris, u, h=float(h), eta=eta, seed=0)
+
+
 def search_direction(scene: Scene, seed: int = BASE_SEED + 5000) -> np.ndarray:
     """Seeded displacement field for line-search workloads: a squeeze of the
     scene toward its mid-plane in z (3 activation bands at the extremes) plus
