@@ -71,9 +71,11 @@ def parse():
     ap.add_argument("--graph", type=int, default=-1,
                     help="1: replay the step as a captured HIP graph; 0: eager launches (the assembly's structure "
                          "then overlaps the evaluation on a second stream); -1: time both, report the faster")
-    ap.add_argument("--path", default="step", choices=["step", "linesearch"],
+    ap.add_argument("--path", default="step", choices=["step", "linesearch", "locking"],
                     help="step: the four calls of a Newton step (default); linesearch: swept broad phase, additive "
-                         "CCD with the filtered offsets and the energy at the step found (one pass per step)")
+                         "CCD with the filtered offsets and the energy at the step found (one pass per step); "
+                         "locking: contact state at rest of a straight rod and a flat sheet over resolutions, with "
+                         "the paper's filter, no filter and culling (the comparison of Fig. self_pushing_toy_example)")
     ap.add_argument("--core-squeeze", type=float, default=0.0,
                     help="step path: scale z by this factor (e.g. 0.88 puts the woven crossings inside the core) and "
                          "mark the pairs inside the core for the temporary zero offset before timing (Sec. 3.4)")
@@ -225,6 +227,49 @@ def bench_linesearch(args):
                                "kind": "oracle", "sample": f"whole workload, {reps_c} pass(es) of ACCD over the "
                                                            f"swept pair set and the energy at the step"}
     print(json.dumps(out))
+
+
+def bench_locking(args):
+    """Contact locking at rest (Fig. self_pushing_toy_example; App. A): a 5 cm
+    straight rod (h = 300 um) and a 2 cm flat sheet (h = 1000 um) at rest, for
+    several segment lengths, with the paper's filter, no filter and culling
+    at 11 and 5 elements (rods).  Per case: pairs within h, active pairs,
+    barrier energy and the largest vertex force at rest (all zero without
+    locking), and the time of one step on the GPU."""
+    import torch
+    import synth
+    import paper_2510_10256_amd as bfc
+
+    dev = torch.device("cuda:0")
+    modes = {"filter": (bfc.BF_FILTER_PAPER, 11), "none": (bfc.BF_FILTER_NONE, 11),
+             "cull11": (bfc.BF_FILTER_CULL, 11), "cull5": (bfc.BF_FILTER_CULL, 5)}
+    rows = []
+    cases = [("rod", ell, synth.straight_rod(ell)) for ell in (1000.0, 600.0, 300.0, 200.0, 150.0, 100.0, 50.0, 25.0)]
+    cases += [("sheet", ell, synth.flat_sheet(ell)) for ell in (2000.0, 1000.0, 700.0, 500.0, 350.0, 250.0)]
+    for kind, ell, sc in cases:
+        x = torch.tensor(sc.x, dtype=torch.float64, device=dev)
+        for name, (mode, r) in modes.items():
+            if kind == "sheet" and mode == bfc.BF_FILTER_CULL:
+                continue
+            cs = bfc.ContactScene(sc, filter_mode=mode, cull_radius=r, device=dev)
+            cs.run(x)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                cs.step(x)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / 5
+            c = cs.counts()
+            gmax = float(cs.g.abs().max().item())
+            rows.append({"kind": kind, "ell_um": ell, "h_um": sc.h, "eta_um": sc.eta, "mode": name,
+                         "n_verts": sc.n_verts, "N_c": c["n_c"], "N_act": c["n_act"], "E_rest": float(cs.E.item()),
+                         "max_vertex_force": gmax, "ms_per_step": ms})
+            cs.close()
+    locked = {m: [r["ell_um"] for r in rows if r["mode"] == m and r["N_act"] > 0] for m in modes}
+    print(json.dumps({"metric": "contact locking at rest: active pairs, energy and largest vertex force per "
+                                "resolution and mode (zero without locking)", "value": None, "unit": None,
+                      "n_gpus": 1, "higher_is_better": None, "data": "synthetic (straight rod 5 cm, flat sheet 2 cm)",
+                      "locked_resolutions_um": locked, "rows": rows}))
 
 
 def bench_batch(args):
@@ -402,6 +447,8 @@ def main():
     if args.gpus != 1:
         print("bench.py: this path runs on one GPU; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
+    if args.path == "locking":
+        return bench_locking(args)
     if args.path == "linesearch":
         if args.workload in ("batch64", "serve256"):
             print("bench.py: the line-search pass runs on one scene (woven_patch, folded_cloth, helix_loop_rod)",

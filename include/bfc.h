@@ -60,7 +60,7 @@ typedef enum {
 
 enum { BF_ROD = 0, BF_SHELL = 1 };
 enum { BF_FP64 = 0, BF_MIXED = 1 };
-enum { BF_FILTER_PAPER = 0, BF_FILTER_NONE = 1 };
+enum { BF_FILTER_PAPER = 0, BF_FILTER_NONE = 1, BF_FILTER_CULL = 2 };
 
 /* device status word bits */
 enum {
@@ -86,7 +86,12 @@ typedef struct {
                       1e-8 of |H| (results within 1e-5 relative instead of about 1e-13);
                       both modes use FP32 boxes in the broad phase and exact threshold
                       decisions */
-  int32_t filter;  /* BF_FILTER_PAPER (Eq. 4) or BF_FILTER_NONE (offset barrier everywhere) */
+  int32_t filter;  /* BF_FILTER_PAPER (Eq. 4), BF_FILTER_NONE (offset barrier everywhere), or
+                      BF_FILTER_CULL (rods only: the comparison mode of Kaldor et al. that the
+                      paper discusses in Sec. 2 and App. A: pairs of edges of one polyline at
+                      most cull_radius elements apart are left out of contact, every other pair
+                      takes (h, eta)) */
+  int32_t cull_radius; /* BF_FILTER_CULL: radius in elements (the paper uses 11, and 5); >= 1 */
 } bf_params;
 
 typedef struct {

@@ -20,7 +20,7 @@ SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("bfc_kernels.hip", "bfc_api.
 BF_OK = 0
 BF_ROD, BF_SHELL = 0, 1
 BF_FP64, BF_MIXED = 0, 1
-BF_FILTER_PAPER, BF_FILTER_NONE = 0, 1
+BF_FILTER_PAPER, BF_FILTER_NONE, BF_FILTER_CULL = 0, 1, 2
 BF_S_CAND_OVERFLOW, BF_S_ACT_OVERFLOW, BF_S_INFEASIBLE = 1, 2, 4
 BF_S_BSR_OVERFLOW, BF_S_CORE_OVERFLOW = 8, 16
 BF_F_FILTERED, BF_F_INFEASIBLE, BF_F_CORE = 1, 4, 8
@@ -46,7 +46,7 @@ def build(verbose: bool = False) -> str:
 
 class Params(C.Structure):
     _fields_ = [("h", C.c_double), ("eta", C.c_double), ("kappa", C.c_double),
-                ("prec", C.c_int32), ("filter", C.c_int32)]
+                ("prec", C.c_int32), ("filter", C.c_int32), ("cull_radius", C.c_int32)]
 
 
 class MeshDesc(C.Structure):
@@ -136,7 +136,7 @@ class ContactScene:
     retries the step; ``step`` never synchronises).
     """
 
-    def __init__(self, scene, prec=BF_FP64, filter_mode=BF_FILTER_PAPER, kappa=None, eta=None,
+    def __init__(self, scene, prec=BF_FP64, filter_mode=BF_FILTER_PAPER, kappa=None, eta=None, cull_radius=11,
                  cand_cap=None, act_cap=None, bsr_cap=None, device="cuda"):
         import torch
         self.torch = torch
@@ -156,7 +156,7 @@ class ContactScene:
         self._ref = np.ascontiguousarray(scene.ref, np.float64)
         desc = MeshDesc(self.kind, self.nv, self.ne, self.nt, self._edges.ctypes.data,
                         self._tris.ctypes.data if self.nt else None, self._ref.ctypes.data)
-        prm = Params(self.h, self.eta, self.kappa, int(prec), int(filter_mode))
+        prm = Params(self.h, self.eta, self.kappa, int(prec), int(filter_mode), int(cull_radius))
         self.prec, self.filter_mode = int(prec), int(filter_mode)
         h = C.c_void_p()
         _check(lib().bf_scene_create(C.byref(desc), C.byref(prm), self.cand_cap, self.act_cap,

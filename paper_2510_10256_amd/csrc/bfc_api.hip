@@ -23,6 +23,8 @@ struct bf_scene {
   double* d_thr2 = nullptr;
   unsigned* d_status = nullptr;
   double* d_line = nullptr;  // [LINE_BLOCKS] per-block minima / sums of the line-search calls
+  int* d_eidx = nullptr;     // culling mode: [E] element index along the polyline
+  int* d_eloop = nullptr;    // culling mode: [E] edge count of the edge's polyline if closed, else 0
   // temporary zero offset (Sec. 3.4): pair keys and live flags, core_slots a power of two (0: no set)
   unsigned long long* core_key = nullptr;
   unsigned char* core_live = nullptr;
@@ -100,6 +102,9 @@ SceneDev dev_view(const bf_scene* s) {
   S.eta = s->prm.eta;
   S.kappa = s->prm.kappa;
   S.filter = s->prm.filter;
+  S.eidx = s->d_eidx;
+  S.eloop = s->d_eloop;
+  S.cull_r = s->prm.cull_radius;
   S.core_key = s->core_slots ? s->core_key : nullptr;
   S.core_live = s->core_live;
   S.core_mask = s->core_slots ? s->core_slots - 1 : 0;
@@ -133,6 +138,45 @@ bf_status alloc_asm(bf_scene* s, long long act_cap) {
   s->aw = A;
   s->act_cap = act_cap;
   return BF_OK;
+}
+
+// Culling mode: order every polyline of a rod mesh.  eidx[e] = position of
+// edge e along its polyline (walked from an end, or from its smallest vertex
+// when closed); eloop[e] = the polyline's edge count when it is closed, 0
+// when open.  False if a vertex lies on more than two edges.
+bool polyline_order(int nv, int ne, const int32_t* edges, std::vector<int>& eidx, std::vector<int>& eloop) {
+  std::vector<int> deg(nv, 0), adj(2LL * nv, -1);  // incident edges per vertex
+  for (int e = 0; e < ne; ++e)
+    for (int k = 0; k < 2; ++k) {
+      const int v = edges[2 * e + k];
+      if (deg[v] == 2) return false;
+      adj[2 * v + deg[v]++] = e;
+    }
+  eidx.assign(ne, -1);
+  eloop.assign(ne, 0);
+  auto walk = [&](int v0) {  // from v0 along unvisited edges; returns the edges in order
+    std::vector<int> order;
+    int v = v0, prev = -1;
+    while (true) {
+      int next = -1;
+      for (int k = 0; k < deg[v]; ++k)
+        if (adj[2 * v + k] != prev && eidx[adj[2 * v + k]] < 0) { next = adj[2 * v + k]; break; }
+      if (next < 0) break;
+      eidx[next] = (int)order.size();
+      order.push_back(next);
+      v = edges[2 * next] == v ? edges[2 * next + 1] : edges[2 * next];
+      prev = next;
+    }
+    return order;
+  };
+  for (int v = 0; v < nv; ++v)
+    if (deg[v] == 1 && eidx[adj[2 * v]] < 0) walk(v);           // open polylines, from an end
+  for (int v = 0; v < nv; ++v)
+    if (deg[v] == 2 && eidx[adj[2 * v]] < 0) {                  // closed loops
+      const std::vector<int> order = walk(v);
+      for (int e : order) eloop[e] = (int)order.size();
+    }
+  return true;
 }
 
 bf_status alloc_stage(bf_scene* s, long long cand_cap) {
@@ -175,8 +219,10 @@ bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int
       !std::isfinite(params->h))
     return fail(BF_E_ARG, "bf_scene_create: need h > 0, 0 <= eta < h, kappa > 0");
   if (params->prec != BF_FP64 && params->prec != BF_MIXED) return fail(BF_E_ARG, "bf_scene_create: bad prec");
-  if (params->filter != BF_FILTER_PAPER && params->filter != BF_FILTER_NONE)
+  if (params->filter != BF_FILTER_PAPER && params->filter != BF_FILTER_NONE && params->filter != BF_FILTER_CULL)
     return fail(BF_E_ARG, "bf_scene_create: bad filter mode");
+  if (params->filter == BF_FILTER_CULL && (mesh->kind != BF_ROD || params->cull_radius < 1))
+    return fail(BF_E_ARG, "bf_scene_create: culling is defined for rods, with a radius of at least one element");
   if (cand_cap < 1 || act_cap < 1) return fail(BF_E_ARG, "bf_scene_create: capacities must be >= 1");
   int nv = (int)mesh->n_verts, ne = (int)mesh->n_edges, nt = mesh->kind == BF_SHELL ? (int)mesh->n_tris : 0;
   for (long long k = 0; k < 2LL * ne; ++k)
@@ -263,6 +309,23 @@ bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int
   }
   s->nc = nc;
   s->comp_h.resize(nv);
+  if (params->filter == BF_FILTER_CULL) {
+    std::vector<int> eidx, eloop;
+    if (!polyline_order(nv, ne, mesh->edges_h, eidx, eloop)) {
+      free_list(s->allocs);
+      delete s;
+      return fail(BF_E_ARG, "bf_scene_create: culling needs polylines (no vertex on more than two edges)");
+    }
+    s->d_eidx = dalloc<int>(s->allocs, ne, &e);
+    s->d_eloop = dalloc<int>(s->allocs, ne, &e);
+    if (e != hipSuccess || hipMemcpyAsync(s->d_eidx, eidx.data(), sizeof(int) * ne, hipMemcpyHostToDevice, st) ||
+        hipMemcpyAsync(s->d_eloop, eloop.data(), sizeof(int) * ne, hipMemcpyHostToDevice, st) ||
+        hipStreamSynchronize(st)) {
+      free_list(s->allocs);
+      delete s;
+      return fail(BF_E_NOMEM, "bf_scene_create: culling tables");
+    }
+  }
   s->d_dmin = dalloc<double>(s->allocs, nc, &e);
   s->d_thr2 = dalloc<double>(s->allocs, 2LL * nc, &e);
 

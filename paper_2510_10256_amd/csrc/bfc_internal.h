@@ -45,7 +45,12 @@ struct SceneDev {
   const unsigned long long* core_key;
   const unsigned char* core_live;
   unsigned core_mask;  // slots - 1
-  int filter;  // 0 paper, 1 none
+  // culling mode (rods): element index of each edge along its polyline and
+  // the polyline's edge count when it is closed (0 when open)
+  const int* eidx;
+  const int* eloop;
+  int cull_r;
+  int filter;  // 0 paper, 1 none, 2 cull
   int mixed;   // 1: projection converged to the mixed-precision tolerance
   int pq;      // threads per broad-phase query (2, 4 or 8)
 };

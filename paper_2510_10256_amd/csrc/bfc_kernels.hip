@@ -762,6 +762,17 @@ __device__ __forceinline__ bool in_core(const SceneDev& S, int type, int i, int 
   return false;
 }
 
+// Culling comparison mode (rods): edges of one polyline at most cull_r
+// elements apart are left out of contact.
+__device__ __forceinline__ bool is_culled(const SceneDev& S, int type, int i, int j) {
+  if (S.filter != BF_FILTER_CULL || type != BF_EE) return false;
+  if (S.comp[S.edges[2 * i]] != S.comp[S.edges[2 * j]]) return false;
+  int d = abs(S.eidx[i] - S.eidx[j]);
+  const int L = S.eloop[i];
+  if (L > 0) d = min(d, L - d);
+  return d <= S.cull_r;
+}
+
 // Stencil pair with 0 < dbar < h in the same component (Sec. 3.2)?
 __device__ __forceinline__ bool is_filtered(const SceneDev& S, int type, const int* v) {
   if (S.filter != 0) return false;
@@ -821,7 +832,7 @@ __global__ __launch_bounds__(256) void k_narrow(SceneDev S, const double* x, con
       Near nr = type == BF_PT ? classify_pt(P) : classify_ee(P);
       code = nr.code;
       D = nr.D;
-      nc = decide_sq(code, P, D, h2, true);  // d < h
+      nc = !is_culled(S, type, i, j) && decide_sq(code, P, D, h2, true);  // d < h (culled pairs: not in contact)
       if (nc) {
         filt = is_filtered(S, type, v);
         core = !filt && in_core(S, type, i, j);
@@ -1769,7 +1780,7 @@ __global__ __launch_bounds__(256) void k_accd(SceneDev S, const double* x, const
     for (int q = 0; q < 4; ++q) { X[q] = load3(x, v[q]); P[q] = load3(pdisp, v[q]); }
     double t = -1.0;
     int it = 0;
-    if (swept_within(type, X, P, S.h)) {
+    if (!is_culled(S, type, ci[k], cj[k]) && swept_within(type, X, P, S.h)) {
       const double xi = is_filtered(S, type, v) || in_core(S, type, ci[k], cj[k]) ? 0.0 : S.eta;
       t = accd_stencil(type, X, P, xi, s, max_iter, it);
       tmin = fmin(tmin, t);
@@ -1821,6 +1832,7 @@ __global__ __launch_bounds__(256) void k_energy(SceneDev S, const double* x, con
         P[q].z = __dadd_rn(P[q].z, __dmul_rn(al, d.z));
       }
     }
+    if (is_culled(S, type, ci[k], cj[k])) continue;
     const Near nr = type == BF_PT ? classify_pt(P) : classify_ee(P);
     if (!decide_sq(nr.code, P, nr.D, h2, true)) continue;  // d >= h
     dd T;
@@ -1877,6 +1889,7 @@ __global__ __launch_bounds__(256) void k_core_mark(SceneDev S, const double* x, 
     int v[4];
     pair_verts(S, type, i, j, v);
     d3 P[4] = {load3(x, v[0]), load3(x, v[1]), load3(x, v[2]), load3(x, v[3])};
+    if (is_culled(S, type, i, j)) continue;
     const Near nr = type == BF_PT ? classify_pt(P) : classify_ee(P);
     if (!decide_sq(nr.code, P, nr.D, h2, true)) continue;    // d >= h
     if (is_filtered(S, type, v)) continue;                  // stencils have no offset anyway
