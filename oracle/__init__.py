@@ -83,6 +83,10 @@ def lib():
         L.orc_ms_get.argtypes = [P] * 8
         L.orc_ms_free.argtypes = [P]
         L.orc_core_release.argtypes = [C.POINTER(_Scene), P, C.c_int64, P, P, P, P]
+        L.orc_friction_lag.argtypes = [C.c_int32, P, C.c_double, C.c_double, C.c_double, C.c_double, P, P, P]
+        L.orc_friction_pair.argtypes = [P, P, P, P, C.c_double, C.c_double, C.c_double, P, P, P, P]
+        L.orc_friction_energy.argtypes = [P, P, P, P, C.c_double, C.c_double, C.c_double]
+        L.orc_friction_energy.restype = C.c_double
         _lib = L
     return _lib
 
@@ -310,3 +314,57 @@ def core_release(scene, x, core, filter_mode=0):
     out = np.zeros(len(cp), np.int32)
     lib().orc_core_release(C.byref(s), _p(x), len(cp), _p(cp), _p(ci), _p(cj), _p(out))
     return out.astype(bool)
+
+
+# ---- lagged friction (App. A: IPC contact and friction energies) -----------------
+
+def _local(x, verts):
+    return np.ascontiguousarray(np.asarray(x, np.float64)[np.asarray(verts)].reshape(12))
+
+
+def friction_lag(scene, xlag, filter_mode=0, core=None, kappa=None):
+    """Lagged friction data of the active pairs at xlag (sorted by (ptype, i,
+    j)): lam (kappa |b'(d)|, 0 for infeasible pairs), closest-point weights
+    w[n,4] and contact normals n[n,3]; plus the pairs' ptype, i, j, verts."""
+    res = evaluate(scene, xlag, mode=1, derivs=False, filter_mode=filter_mode, core=core, kappa=kappa)
+    act = (res["flags"] & F_ACTIVE) != 0
+    idx = np.nonzero(act)[0]
+    kap = float(scene.kappa if kappa is None else kappa)
+    lam = np.zeros(len(idx))
+    w = np.zeros((len(idx), 4))
+    nrm = np.zeros((len(idx), 3))
+    L = lib()
+    for q, k in enumerate(idx):
+        X = _local(xlag, res["verts"][k])
+        lo, wo, no = np.zeros(1), np.zeros(4), np.zeros(3)
+        L.orc_friction_lag(int(res["code"][k]), _p(X), float(res["d"][k]), float(res["a"][k]),
+                           float(res["eta"][k]), kap, _p(lo), _p(wo), _p(no))
+        lam[q], w[q], nrm[q] = lo[0], wo, no
+    return dict(ptype=res["ptype"][idx], i=res["i"][idx], j=res["j"][idx], verts=res["verts"][idx],
+                code=res["code"][idx], lam=lam, w=w, n=nrm)
+
+
+def friction_eval(lag, x, xlag, mu, eh, derivs=True):
+    """Friction energy (and gradient, Hessian) of every lagged pair at x."""
+    n = len(lag["lam"])
+    E = np.zeros(n)
+    G = np.zeros((n, 12))
+    H = np.zeros((n, 12, 12))
+    Hp = np.zeros((n, 12, 12))
+    L = lib()
+    for q in range(n):
+        X = _local(x, lag["verts"][q])
+        Xl = _local(xlag, lag["verts"][q])
+        w = np.ascontiguousarray(lag["w"][q])
+        nn = np.ascontiguousarray(lag["n"][q])
+        if derivs:
+            e = np.zeros(1)
+            g = np.zeros(12)
+            h = np.zeros((12, 12))
+            hp = np.zeros((12, 12))
+            L.orc_friction_pair(_p(X), _p(Xl), _p(w), _p(nn), float(lag["lam"][q]), float(mu), float(eh),
+                                _p(e), _p(g), _p(h), _p(hp))
+            E[q], G[q], H[q], Hp[q] = e[0], g, h, hp
+        else:
+            E[q] = L.orc_friction_energy(_p(X), _p(Xl), _p(w), _p(nn), float(lag["lam"][q]), float(mu), float(eh))
+    return dict(E=E, G=G, H=H, Hpsd=Hp)

@@ -33,7 +33,13 @@
 //     orc_evaluate without derivatives;
 //   * temporary zero offset (Sec. 3.4): non-stencil pairs found inside the
 //     core (d <= eta) at a configuration get eta = 0 (activation h) until
-//     they are seen with d > eta, then the ordinary (h, eta) again.
+//     they are seen with d > eta, then the ordinary (h, eta) again;
+//   * lagged friction (App. A: IPC energies for contact and friction; the
+//     lagged model of IPC, Li et al. 2020): per active pair, from the lagged
+//     positions, the normal force kappa |b'(d)|, the closest-point weights and
+//     the contact normal; the friction energy mu lambda f0(|tangential
+//     relative displacement|) with IPC's smoothed Coulomb f0, differentiated
+//     by hyper-dual sweeps.
 //
 // Build: g++ -O2 -std=c++17 -fopenmp -ffp-contract=off -shared -fPIC
 //        oracle.cpp -o liboracle.so -lquadmath
@@ -814,6 +820,66 @@ void swept_box(const Mesh& m, const double* x, const double* p, int role, int id
     }
 }
 
+// ---------------------------------------------------------------------------
+// Lagged friction.  The relative displacement of the two closest points of a
+// pair is sum_s w[s] dX_s (first primitive minus second), with the weights of
+// the distance sub-case at the lagged positions: PP (1, -1); PE the point
+// against the edge point at parameter beta; PT the point against its
+// projection's barycentric combination; EE the two line points at (alpha,
+// beta).  Its tangential part (orthogonal to the lagged contact normal n)
+// has length y, and the pair's friction energy is mu lambda f0(y) with
+// f0(y) = y for y >= eh and -y^3/(3 eh^2) + y^2/eh + eh/3 below (eh: the
+// sliding threshold eps_v times the time step).
+// ---------------------------------------------------------------------------
+void closest_weights(int code, const double* X, double* w) {
+  for (int s = 0; s < 4; ++s) w[s] = 0.0;
+  const Case& c = kCases[code];
+  if (c.kind == 0) {
+    w[c.s0] = 1.0; w[c.s1] = -1.0;
+  } else if (c.kind == 1) {
+    double e[3], r[3];
+    sub3(X + 3 * c.s2, X + 3 * c.s1, e); sub3(X + 3 * c.s0, X + 3 * c.s1, r);
+    const double beta = dot3(r, e) / dot3(e, e);
+    w[c.s0] = 1.0; w[c.s1] = -(1.0 - beta); w[c.s2] = -beta;
+  } else if (c.kind == 2) {
+    double u[3], v[3], r[3];
+    sub3(X + 6, X + 3, u); sub3(X + 9, X + 3, v); sub3(X, X + 3, r);
+    const double uu = dot3(u, u), uv = dot3(u, v), vv = dot3(v, v), ru = dot3(r, u), rv = dot3(r, v);
+    const double det = uu * vv - uv * uv;
+    const double b1 = (vv * ru - uv * rv) / det, b2 = (uu * rv - uv * ru) / det;
+    w[0] = 1.0; w[1] = -(1.0 - b1 - b2); w[2] = -b1; w[3] = -b2;
+  } else {
+    double ea[3], eb[3], r[3];
+    sub3(X + 3, X, ea); sub3(X + 9, X + 6, eb); sub3(X, X + 6, r);
+    const double A = dot3(ea, ea), B = dot3(ea, eb), C = dot3(eb, eb), D = dot3(ea, r), E = dot3(eb, r);
+    const double den = A * C - B * B;
+    const double al = (B * E - C * D) / den, be = (A * E - B * D) / den;
+    w[0] = 1.0 - al; w[1] = al; w[2] = -(1.0 - be); w[3] = -be;
+  }
+}
+
+template <class T> HD<T> f0_hd(HD<T> y, T eh) {
+  if (y.a >= eh) return y;
+  return -(y * y * y) * HD<T>(T(1) / (T(3) * eh * eh)) + y * y * HD<T>(T(1) / eh) + HD<T>(eh / T(3));
+}
+
+// mu lambda f0(|tangential part of sum_s w_s (X_s - Xlag_s)|) in scalar type T
+template <class T> HD<T> friction_hd(const HD<T>* Xh, const double* Xlag, const double* w, const double* n,
+                                     double lam, double mu, double eh) {
+  HD<T> dl[3];
+  for (int c = 0; c < 3; ++c) {
+    dl[c] = HD<T>(T(0));
+    for (int s = 0; s < 4; ++s) dl[c] = dl[c] + HD<T>((T)w[s]) * (Xh[3 * s + c] - HD<T>((T)Xlag[3 * s + c]));
+  }
+  HD<T> dn = dl[0] * HD<T>((T)n[0]) + dl[1] * HD<T>((T)n[1]) + dl[2] * HD<T>((T)n[2]);
+  HD<T> y2(T(0));
+  for (int c = 0; c < 3; ++c) {
+    HD<T> t = dl[c] - HD<T>((T)n[c]) * dn;
+    y2 = y2 + t * t;
+  }
+  return f0_hd(hsqrt(y2), (T)eh) * HD<T>((T)(mu * lam));
+}
+
 struct StepRec { int ptype, i, j, filtered, iters; double xi, t; };
 struct StepResult { std::vector<StepRec> recs; };
 
@@ -1126,6 +1192,60 @@ void* orc_max_step(const orc_scene* s, const double* x, const double* p, double 
     return a.j < b.j;
   });
   return res;
+}
+
+// Lagged friction data of one active pair of sub-case `code` at the lagged
+// local positions X (distance d, barrier parameters a, eta): the normal force
+// lambda = kappa |b'(d)| (0 when d >= a or d <= eta), the closest-point
+// weights w[4] and the contact normal n[3].
+void orc_friction_lag(int32_t code, const double* X, double d, double a, double eta, double kappa, double* lam,
+                      double* w, double* n) {
+  closest_weights(code, X, w);
+  double c[3] = {0.0, 0.0, 0.0};
+  for (int s = 0; s < 4; ++s)
+    for (int k = 0; k < 3; ++k) c[k] += w[s] * X[3 * s + k];
+  const double nc = std::sqrt(dot3(c, c));
+  for (int k = 0; k < 3; ++k) n[k] = c[k] / nc;
+  *lam = 0.0;
+  if (d < a && d > eta) {
+    HD<double> x(d, 1.0, 1.0, 0.0);
+    *lam = kappa * std::fabs(barrier_hd(x, a, eta).b);
+  }
+}
+
+// Friction energy, gradient and Hessian (then its PSD projection, which the
+// exact Hessian does not need) of one pair at local positions X.
+void orc_friction_pair(const double* X, const double* Xlag, const double* w, const double* n, double lam, double mu,
+                       double eh, double* E, double* G, double* H, double* Hpsd) {
+  for (int i = 0; i < 12; ++i)
+    for (int j = i; j < 12; ++j) {
+      HD<double> Xh[12];
+      for (int k = 0; k < 12; ++k) Xh[k] = HD<double>(X[k]);
+      Xh[i].b = 1.0;
+      Xh[j].c = 1.0;
+      HD<double> e = friction_hd<double>(Xh, Xlag, w, n, lam, mu, eh);
+      if (i == 0 && j == 0) *E = e.a;
+      if (j == i) G[i] = e.b;
+      H[i * 12 + j] = e.d;
+      H[j * 12 + i] = e.d;
+    }
+  psd_project(12, H, Hpsd, nullptr);
+}
+
+// Friction energy alone (no derivatives; defined at zero sliding too).
+double orc_friction_energy(const double* X, const double* Xlag, const double* w, const double* n, double lam,
+                           double mu, double eh) {
+  HD<double> Xh[12];
+  for (int k = 0; k < 12; ++k) Xh[k] = HD<double>(X[k]);
+  double dl[3] = {0.0, 0.0, 0.0};
+  for (int c = 0; c < 3; ++c)
+    for (int s = 0; s < 4; ++s) dl[c] += w[s] * (X[3 * s + c] - Xlag[3 * s + c]);
+  const double dn = dot3(dl, n);
+  double y2 = 0.0;
+  for (int c = 0; c < 3; ++c) y2 += (dl[c] - n[c] * dn) * (dl[c] - n[c] * dn);
+  const double y = std::sqrt(y2);
+  const double f0 = y >= eh ? y : -y * y * y / (3.0 * eh * eh) + y * y / eh + eh / 3.0;
+  return mu * lam * f0;
 }
 
 int64_t orc_ms_count(void* h) { return (int64_t)((StepResult*)h)->recs.size(); }
