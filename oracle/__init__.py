@@ -87,6 +87,7 @@ def lib():
         L.orc_friction_pair.argtypes = [P, P, P, P, C.c_double, C.c_double, C.c_double, P, P, P, P]
         L.orc_friction_energy.argtypes = [P, P, P, P, C.c_double, C.c_double, C.c_double]
         L.orc_friction_energy.restype = C.c_double
+        L.orc_friction_batch.argtypes = [C.c_int64, P, P, P, P, P, C.c_double, C.c_double, P, P, P, P, C.c_int32]
         _lib = L
     return _lib
 
@@ -344,7 +345,7 @@ def friction_lag(scene, xlag, filter_mode=0, core=None, kappa=None):
                 code=res["code"][idx], lam=lam, w=w, n=nrm)
 
 
-def friction_eval(lag, x, xlag, mu, eh, derivs=True):
+def friction_eval(lag, x, xlag, mu, eh, derivs=True, nthreads=0):
     """Friction energy (and gradient, Hessian) of every lagged pair at x."""
     n = len(lag["lam"])
     E = np.zeros(n)
@@ -352,6 +353,16 @@ def friction_eval(lag, x, xlag, mu, eh, derivs=True):
     H = np.zeros((n, 12, 12))
     Hp = np.zeros((n, 12, 12))
     L = lib()
+    if derivs:
+        vt = np.asarray(lag["verts"])
+        X = np.ascontiguousarray(np.asarray(x, np.float64)[vt].reshape(n, 12))
+        Xl = np.ascontiguousarray(np.asarray(xlag, np.float64)[vt].reshape(n, 12))
+        w = np.ascontiguousarray(lag["w"], np.float64)
+        nn = np.ascontiguousarray(lag["n"], np.float64)
+        lam = np.ascontiguousarray(lag["lam"], np.float64)
+        L.orc_friction_batch(n, _p(X), _p(Xl), _p(w), _p(nn), _p(lam), float(mu), float(eh), _p(E), _p(G), _p(H),
+                             _p(Hp), int(nthreads))
+        return dict(E=E, G=G, H=H, Hpsd=Hp)
     for q in range(n):
         X = _local(x, lag["verts"][q])
         Xl = _local(xlag, lag["verts"][q])

@@ -849,12 +849,15 @@ void closest_weights(int code, const double* X, double* w) {
     const double b1 = (vv * ru - uv * rv) / det, b2 = (uu * rv - uv * ru) / det;
     w[0] = 1.0; w[1] = -(1.0 - b1 - b2); w[2] = -b1; w[3] = -b2;
   } else {
-    double ea[3], eb[3], r[3];
-    sub3(X + 3, X, ea); sub3(X + 9, X + 6, eb); sub3(X, X + 6, r);
-    const double A = dot3(ea, ea), B = dot3(ea, eb), C = dot3(eb, eb), D = dot3(ea, r), E = dot3(eb, r);
-    const double den = A * C - B * B;
-    const double al = (B * E - C * D) / den, be = (A * E - B * D) / den;
-    w[0] = 1.0 - al; w[1] = al; w[2] = -(1.0 - be); w[3] = -be;
+    // in binary128: for nearly parallel edges the 2 x 2 system loses about
+    // log10(1 / sin^2) digits, more than double precision can spare
+    f128 Q[12], ea[3], eb[3], r[3];
+    for (int k = 0; k < 12; ++k) Q[k] = (f128)X[k];
+    sub3(Q + 3, Q, ea); sub3(Q + 9, Q + 6, eb); sub3(Q, Q + 6, r);
+    const f128 A = dot3(ea, ea), B = dot3(ea, eb), C = dot3(eb, eb), D = dot3(ea, r), E = dot3(eb, r);
+    const f128 den = A * C - B * B;
+    const f128 al = (B * E - C * D) / den, be = (A * E - B * D) / den;
+    w[0] = (double)(1 - al); w[1] = (double)al; w[2] = (double)(-(1 - be)); w[3] = (double)(-be);
   }
 }
 
@@ -1230,6 +1233,18 @@ void orc_friction_pair(const double* X, const double* Xlag, const double* w, con
       H[j * 12 + i] = e.d;
     }
   psd_project(12, H, Hpsd, nullptr);
+}
+
+// The same for n pairs at once (local positions and lagged data stacked),
+// over OpenMP threads.
+void orc_friction_batch(int64_t n, const double* X, const double* Xlag, const double* w, const double* nrm,
+                        const double* lam, double mu, double eh, double* E, double* G, double* H, double* Hpsd,
+                        int32_t nthreads) {
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+  #pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t k = 0; k < n; ++k)
+    orc_friction_pair(X + 12 * k, Xlag + 12 * k, w + 4 * k, nrm + 3 * k, lam[k], mu, eh, E + k, G + 12 * k,
+                      H + 144 * k, Hpsd + 144 * k);
 }
 
 // Friction energy alone (no derivatives; defined at zero sliding too).

@@ -134,3 +134,28 @@ def test_gradient_against_differences_and_psd_hessian():
         ev = np.linalg.eigvalsh(Hm)
         assert ev.min() >= -1e-9 * max(1.0, np.abs(ev).max()), (trial, ev.min())
         assert np.allclose(r["Hpsd"][0], Hm, atol=1e-9 * max(1.0, np.abs(ev).max()))
+
+
+@pytest.mark.parametrize("theta", [1e-3, 3e-5, 1.2e-5])
+def test_nearly_parallel_edges_weights_exact(theta):
+    # edge b at height 280 over edge a, turned by theta in the plane: the
+    # closest points are the lines' crossing in projection.  The weights
+    # solve a 2 x 2 system whose determinant is |ea|^2 |eb|^2 sin^2 theta;
+    # compare with the exact rational solution for the stored coordinates.
+    # (Edges with sin^2 theta below 1e-10 are classified as parallel and
+    # take a point-edge sub-case instead.)
+    from fractions import Fraction as Fr
+    c, s = math.cos(theta), math.sin(theta)
+    Xl = np.array([-100, 0, 0, 100, 0, 0, 37 - 100 * c, -100 * s, 280, 37 + 100 * c, 100 * s, 280], float)
+    lag, code = _lag_pair(1, Xl)
+    assert code == 15
+    Q = [Fr(float(v)) for v in Xl]
+    sub = lambda a, b: [Q[a + k] - Q[b + k] for k in range(3)]
+    dot = lambda u, v: sum(p * q for p, q in zip(u, v))
+    ea, eb, r = sub(3, 0), sub(9, 6), sub(0, 6)
+    A, B, C, D, E = dot(ea, ea), dot(ea, eb), dot(eb, eb), dot(ea, r), dot(eb, r)
+    den = A * C - B * B
+    al, be = (B * E - C * D) / den, (A * E - B * D) / den
+    exact = [float(1 - al), float(al), float(-(1 - be)), float(-be)]
+    assert abs(float(al) - 0.685) < 1e-6 and abs(float(be) - 0.5) < 1e-6
+    assert np.allclose(lag["w"][0], exact, rtol=0, atol=4e-16), (lag["w"][0], exact)
