@@ -271,6 +271,34 @@ bf_status bf_core_mark(bf_scene* s, const double* x_d, const bf_pairs* cand, int
 bf_status bf_core_live(bf_scene* s, int64_t* count_d, void* stream);
 bf_status bf_core_clear(bf_scene* s);
 
+/* ---- lagged friction (App. A: IPC's contact and friction energies) --------
+ * IPC's lagged friction on the active pairs.  friction_lag, at the lagged
+ * positions xlag_d (the start of the time step; act from filter_pairs there):
+ * per active pair k, the normal force lam[k] = kappa |b'(d)| of its barrier
+ * (Eq. 2-4 with the pair's (a, eta); 0 when infeasible), the weights w[k,4]
+ * of the closest points (their relative displacement is sum_q w_q dx_q for
+ * the pair's stencil vertices) and the contact normal n[k,3].
+ *
+ * friction_eval at x_d: with dt the part of sum_q w_q (x_q - xlag_q)
+ * orthogonal to n and y = |dt|, the energy mu lam f0(y) (f0(y) = y for
+ * y >= eps_vh, -y^3/(3 eps_vh^2) + y^2/eps_vh + eps_vh/3 below; eps_vh = the
+ * sliding threshold times the time step, > 0), its gradient [12] and its
+ * Hessian [12x12] (positive semidefinite as it stands) in the layout of
+ * eval_barrier.  accumulate = 0 overwrites out, 1 adds to it (after
+ * eval_barrier: contact + friction); either way the energy tile sums are
+ * refreshed, so assemble_grad_hess then assembles what out holds.
+ * mu >= 0, eps_vh > 0; fr capacity >= act capacity. */
+typedef struct {
+  double* lam_d;  /* [cap] */
+  double* w_d;    /* [cap,4] */
+  double* n_d;    /* [cap,3] */
+  int64_t cap;
+} bf_friction;
+bf_status friction_lag(bf_scene* s, const double* xlag_d, const bf_active* act, bf_friction* fr, void* stream);
+bf_status friction_eval(bf_scene* s, const double* x_d, const double* xlag_d, const bf_active* act,
+                        const bf_friction* fr, double mu, double eps_vh, int32_t accumulate, bf_local* out,
+                        void* stream);
+
 /* ---- tuning ---------------------------------------------------------------
  * Threads per broad-phase query (2, 4 or 8; default 4): more threads split a
  * query's rows of grid cells finer (small scenes, few queries), fewer cost

@@ -28,8 +28,8 @@ BF_F_FILTERED, BF_F_INFEASIBLE, BF_F_CORE = 1, 4, 8
 EXPORTED = ["bf_scene_create", "bf_scene_reserve", "bf_scene_destroy", "bf_scene_info", "build_candidates",
             "filter_pairs", "eval_barrier", "assemble_grad_hess", "bf_scene_set_pq", "bf_scene_tune",
             "bf_batch_create", "bf_batch_step", "bf_batch_info", "bf_batch_destroy", "build_candidates_swept",
-            "max_step_accd", "eval_energy", "bf_core_mark", "bf_core_live", "bf_core_clear", "bf_status_word",
-            "bf_last_error"]
+            "max_step_accd", "eval_energy", "bf_core_mark", "bf_core_live", "bf_core_clear", "friction_lag",
+            "friction_eval", "bf_status_word", "bf_last_error"]
 
 
 def build(verbose: bool = False) -> str:
@@ -73,6 +73,10 @@ class Bsr(C.Structure):
                 ("nnzb_d", C.c_void_p)]
 
 
+class Friction(C.Structure):
+    _fields_ = [("lam_d", C.c_void_p), ("w_d", C.c_void_p), ("n_d", C.c_void_p), ("cap", C.c_int64)]
+
+
 class BatchItem(C.Structure):
     _fields_ = [("scene", C.c_void_p), ("x_d", C.c_void_p), ("cand", Pairs), ("act", Active), ("loc", Local),
                 ("E_d", C.c_void_p), ("g_d", C.c_void_p), ("H", Bsr)]
@@ -110,6 +114,9 @@ def lib():
         L.bf_core_mark.argtypes = [P, P, C.POINTER(Pairs), C.c_int64, P, P]
         L.bf_core_live.argtypes = [P, P, P]
         L.bf_core_clear.argtypes = [P]
+        L.friction_lag.argtypes = [P, P, C.POINTER(Active), C.POINTER(Friction), P]
+        L.friction_eval.argtypes = [P, P, P, C.POINTER(Active), C.POINTER(Friction), C.c_double, C.c_double,
+                                    C.c_int32, C.POINTER(Local), P]
         L.bf_status_word.argtypes = [P, C.POINTER(C.c_uint32), C.c_int32]
         L.bf_last_error.restype = C.c_char_p
         for name in EXPORTED[:-1]:
@@ -163,6 +170,8 @@ class ContactScene:
                                      C.c_void_p(self._stream()), C.byref(h)), "bf_scene_create")
         self.handle = h
         self.pq = 4
+        self._gen = 0       # filter_pairs calls so far (the lagged friction list is tied to one)
+        self._fgen = -1
         self._alloc()
 
     # -- buffers -------------------------------------------------------------
@@ -203,6 +212,7 @@ class ContactScene:
                "build_candidates")
 
     def filter_pairs(self, x):
+        self._gen += 1
         _check(lib().filter_pairs(self.handle, _ptr(x), C.byref(self._cand), C.byref(self._act),
                                   C.c_void_p(self._stream())), "filter_pairs")
 
@@ -264,6 +274,68 @@ class ContactScene:
                                  _ptr(alpha) if alpha is not None else None, C.byref(self._cand), _ptr(E),
                                  C.c_void_p(self._stream())), "eval_energy")
         return E
+
+    # -- lagged friction (App. A: IPC contact and friction energies) ----------
+    def friction_lag(self, xlag):
+        """Lagged friction data at xlag for the active list of the last
+        filter_pairs (run the step at xlag first).  The lagged list is copied
+        into buffers of its own: later steps replace the contact list, the
+        friction keeps its pairs until the next friction_lag."""
+        t = self.torch
+        cap = self.act_cap
+        z = lambda shape, dt=t.float64: t.zeros(shape, dtype=dt, device=self.device)
+        self.f_i, self.f_j, self.f_t = self.a_i.clone(), self.a_j.clone(), self.a_t.clone()
+        self.f_cnt, self.f_code, self.f_flags = self.a_n.clone(), self.a_code.clone(), self.a_flags.clone()
+        self.f_dist, self.f_counters = self.a_dist.clone(), self.counters.clone()
+        self._fact = Active(Pairs(self.f_i.data_ptr(), self.f_j.data_ptr(), self.f_t.data_ptr(), cap,
+                                  self.f_cnt.data_ptr()),
+                            self.f_code.data_ptr(), self.f_flags.data_ptr(), self.f_dist.data_ptr(),
+                            self.f_counters.data_ptr())
+        self.f_lam, self.f_w, self.f_n = z(cap), z((cap, 4)), z((cap, 3))
+        self._fr = Friction(self.f_lam.data_ptr(), self.f_w.data_ptr(), self.f_n.data_ptr(), cap)
+        self.fl_E, self.fl_G, self.fl_H = z(cap), z((cap, 12)), z((cap, 144))
+        self._floc = Local(self.fl_E.data_ptr(), self.fl_G.data_ptr(), self.fl_H.data_ptr(), cap)
+        self.f_E, self.f_g = z(1), z((self.nv, 3))
+        self.f_row_ptr, self.f_col = z(self.nv + 1, t.int32), z(self.bsr_cap, t.int32)
+        self.f_val, self.f_nnzb = z((self.bsr_cap, 9)), z(1, t.int64)
+        self._fbsr = Bsr(self.f_row_ptr.data_ptr(), self.f_col.data_ptr(), self.f_val.data_ptr(), self.bsr_cap,
+                         self.f_nnzb.data_ptr())
+        self._xlag = xlag
+        self._fgen = self._gen
+        _check(lib().friction_lag(self.handle, _ptr(xlag), C.byref(self._fact), C.byref(self._fr),
+                                  C.c_void_p(self._stream())), "friction_lag")
+
+    def friction_eval(self, x, mu, eps_vh, accumulate=False):
+        """Friction of the lagged pairs at x into their own local buffers
+        (fl_E, fl_G, fl_H).  accumulate=True adds it onto the contact terms
+        instead (l_E, l_G, l_H), which is only meaningful while the contact
+        list is still the lagged one (no filter_pairs since friction_lag)."""
+        if accumulate and self._gen != self._fgen:
+            raise RuntimeError("friction_eval(accumulate=True): the contact list changed since friction_lag")
+        loc = self._loc if accumulate else self._floc
+        _check(lib().friction_eval(self.handle, _ptr(x), _ptr(self._xlag), C.byref(self._fact), C.byref(self._fr),
+                                   float(mu), float(eps_vh), int(bool(accumulate)), C.byref(loc),
+                                   C.c_void_p(self._stream())), "friction_eval")
+
+    def friction_assemble(self):
+        """Assemble the friction terms of the last friction_eval over the lagged
+        list into f_E, f_g and the block matrix (f_row_ptr, f_col, f_val)."""
+        _check(lib().assemble_grad_hess(self.handle, C.byref(self._fact), C.byref(self._floc), _ptr(self.f_E),
+                                        _ptr(self.f_g), C.byref(self._fbsr), C.c_void_p(self._stream())),
+               "assemble_grad_hess (friction)")
+
+    def friction_results(self):
+        """Host copies of the lagged list, its friction data and the last
+        friction evaluation and assembly (synchronises)."""
+        self.torch.cuda.synchronize(self.device)
+        n = min(int(self.f_cnt.item()), self.act_cap)
+        nb = min(int(self.f_nnzb.item()), self.bsr_cap)
+        c = lambda a: a[:n].cpu().numpy()
+        return dict(ptype=c(self.f_t).astype(np.int32), i=c(self.f_i), j=c(self.f_j), lam=c(self.f_lam),
+                    w=c(self.f_w), n=c(self.f_n), E=c(self.fl_E), G=c(self.fl_G),
+                    Hpsd=c(self.fl_H).reshape(-1, 12, 12), E_total=float(self.f_E.item()), g=self.f_g.cpu().numpy(),
+                    row_ptr=self.f_row_ptr.cpu().numpy().astype(np.int64), col=self.f_col[:nb].cpu().numpy(),
+                    val=self.f_val[:nb].cpu().numpy().reshape(-1, 3, 3), nnzb=int(self.f_nnzb.item()))
 
     # -- temporary zero offset (Sec. 3.4) ------------------------------------
     def core_mark(self, x, cap=None):

@@ -537,6 +537,38 @@ bf_status bf_core_mark(bf_scene* s, const double* x_d, const bf_pairs* cand, int
   return he == hipSuccess ? BF_OK : fail_hip(he, "bf_core_mark");
 }
 
+bf_status friction_lag(bf_scene* s, const double* xlag_d, const bf_active* act, bf_friction* fr, void* stream) {
+  if (!s || !xlag_d || !act || !fr || !fr->lam_d || !fr->w_d || !fr->n_d || !act->p.count_d || !act->p.i_d ||
+      !act->p.j_d || !act->p.type_d || !act->code_d || !act->flags_d)
+    return fail(BF_E_ARG, "friction_lag: null argument");
+  if (fr->cap < act->p.cap) return fail(BF_E_CAPACITY, "friction_lag: friction capacity below active capacity");
+  hipStream_t st = (hipStream_t)stream;
+  s->last = st;
+  run_friction_lag(dev_view(s), xlag_d, act->p.i_d, act->p.j_d, act->p.type_d, act->code_d, act->flags_d,
+                   (const long long*)act->p.count_d, act->p.cap, fr->lam_d, fr->w_d, fr->n_d, st);
+  hipError_t he = hipGetLastError();
+  return he == hipSuccess ? BF_OK : fail_hip(he, "friction_lag");
+}
+
+bf_status friction_eval(bf_scene* s, const double* x_d, const double* xlag_d, const bf_active* act,
+                        const bf_friction* fr, double mu, double eps_vh, int32_t accumulate, bf_local* out,
+                        void* stream) {
+  if (!s || !x_d || !xlag_d || !act || !fr || !fr->lam_d || !fr->w_d || !fr->n_d || !out || !out->E_d ||
+      !out->G_d || !out->H_d || !act->p.count_d || !act->p.i_d || !act->p.j_d || !act->p.type_d)
+    return fail(BF_E_ARG, "friction_eval: null argument");
+  if (!(mu >= 0.0) || !(eps_vh > 0.0)) return fail(BF_E_ARG, "friction_eval: need mu >= 0 and eps_vh > 0");
+  if (fr->cap < act->p.cap || out->cap < act->p.cap)
+    return fail(BF_E_CAPACITY, "friction_eval: friction or local capacity below active capacity");
+  hipStream_t st = (hipStream_t)stream;
+  s->last = st;
+  const bool fits = act->p.cap <= s->act_cap;
+  run_friction_eval(dev_view(s), x_d, xlag_d, act->p.i_d, act->p.j_d, act->p.type_d,
+                    (const long long*)act->p.count_d, act->p.cap, fr->lam_d, fr->w_d, fr->n_d, mu, eps_vh,
+                    accumulate ? 1 : 0, out->E_d, out->G_d, out->H_d, fits ? s->aw.epart : nullptr, st);
+  hipError_t he = hipGetLastError();
+  return he == hipSuccess ? BF_OK : fail_hip(he, "friction_eval");
+}
+
 bf_status bf_core_live(bf_scene* s, int64_t* count_d, void* stream) {
   if (!s || !count_d) return fail(BF_E_ARG, "bf_core_live: null argument");
   hipStream_t st = (hipStream_t)stream;

@@ -31,6 +31,13 @@ void run_core_mark(const SceneDev& S, const double* x, const int* ci, const int*
                    unsigned slots, long long cap, long long* count, unsigned* status, hipStream_t st);
 void run_core_release(const SceneDev& S, const double* x, hipStream_t st);
 void run_core_count(const SceneDev& S, long long* out, hipStream_t st);
+void run_friction_lag(const SceneDev& S, const double* xl, const int* ai, const int* aj, const unsigned char* at,
+                      const unsigned char* acode, const unsigned char* aflags, const long long* act_count,
+                      long long acap, double* lam, double* w, double* n, hipStream_t st);
+void run_friction_eval(const SceneDev& S, const double* x, const double* xl, const int* ai, const int* aj,
+                       const unsigned char* at, const long long* act_count, long long acap, const double* lam,
+                       const double* w, const double* n, double mu, double eh, int accumulate, double* E, double* G,
+                       double* H, double* epart, hipStream_t st);
 void run_energy(const SceneDev& S, const double* x, const double* pdisp, const double* alpha, const int* ci,
                 const int* cj, const unsigned char* ct, const long long* ccount, long long ccap, double* bred,
                 double* E_out, hipStream_t st);

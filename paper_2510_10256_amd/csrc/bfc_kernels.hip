@@ -1871,6 +1871,165 @@ __global__ __launch_bounds__(64) void k_sum_final(const double* bsum, int nb, do
 }
 
 // ---------------------------------------------------------------------------
+// Lagged friction (App. A: IPC's contact and friction energies; the lagged
+// model of Li et al. 2020)
+// ---------------------------------------------------------------------------
+
+// Closest-point weights of sub-case `code` at X: the relative displacement of
+// the pair's two closest points is sum_q w[q] dX_q.
+__device__ __forceinline__ void friction_weights(int code, const d3* X, double* w) {
+  const int kind = case_kind(code);
+  if (kind == K_PT) {  // point 0 against the projection onto triangle (1, 2, 3)
+    const d3 u = X[2] - X[1], v = X[3] - X[1], r = X[0] - X[1];
+    const double uu = dot(u, u), uv = dot(u, v), vv = dot(v, v), ru = dot(r, u), rv = dot(r, v);
+    const double det = uu * vv - uv * uv;
+    const double b1 = (vv * ru - uv * rv) / det, b2 = (uu * rv - uv * ru) / det;
+    w[0] = 1.0; w[1] = -(1.0 - b1 - b2); w[2] = -b1; w[3] = -b2;
+    return;
+  }
+  if (kind == K_EE) {  // the two line points at parameters (alpha, beta)
+    // in double-double: for nearly parallel edges the 2 x 2 system loses
+    // about log10(1 / sin^2) digits, which FP64 cannot spare
+    const q3 Q[4] = {q3_of(X[0]), q3_of(X[1]), q3_of(X[2]), q3_of(X[3])};
+    const q3 ea = Q[1] - Q[0], eb = Q[3] - Q[2], r = Q[0] - Q[2];
+    const dd A = dot(ea, ea), B = dot(ea, eb), C = dot(eb, eb), D = dot(ea, r), E = dot(eb, r);
+    const dd den = A * C - B * B;
+    const dd al = (B * E - C * D) / den, be = (A * E - B * D) / den;
+    const dd one = dd_of(1.0);
+    w[0] = (one - al).hi; w[1] = al.hi; w[2] = -(one - be).hi; w[3] = -be.hi;
+    return;
+  }
+  int s0, s1, s2;
+  case_slots(code, s0, s1, s2);
+  double w0 = 1.0, w1 = -1.0, w2 = 0.0;  // point-point
+  if (kind == K_PE) {                    // point s0 against edge (s1, s2) at parameter beta
+    const d3 p = pick4(X, s0), e0 = pick4(X, s1), e1 = pick4(X, s2);
+    const d3 e = e1 - e0;
+    const double beta = dot(p - e0, e) / dot(e, e);
+    w1 = -(1.0 - beta);
+    w2 = -beta;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) w[q] = (q == s0 ? w0 : 0.0) + (q == s1 ? w1 : 0.0) + (q == s2 ? w2 : 0.0);
+}
+
+// Per active pair at the lagged positions: lambda = kappa |b'(d)| (0 when the
+// pair is infeasible or not inside (eta, a)), weights w[4], contact normal n.
+__global__ __launch_bounds__(256) void k_friction_lag(SceneDev S, const double* xl, const int* ai, const int* aj,
+                                                      const unsigned char* at, const unsigned char* acode,
+                                                      const unsigned char* aflags,
+                                                      const unsigned long long* act_count, long long acap,
+                                                      double* lam, double* wout, double* nout) {
+  long long n = (long long)*act_count;
+  if (n > acap) n = acap;
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += grid_stride()) {
+    const int type = at[k], code = acode[k], fl = aflags[k];
+    int v[4];
+    pair_verts(S, type, ai[k], aj[k], v);
+    const d3 X[4] = {load3(xl, v[0]), load3(xl, v[1]), load3(xl, v[2]), load3(xl, v[3])};
+    double w[4];
+    friction_weights(code, X, w);
+    d3 c = w[0] * X[0];
+#pragma unroll
+    for (int q = 1; q < 4; ++q) c = c + w[q] * X[q];
+    const double cn = sqrt(dot(c, c));
+    double l = 0.0;
+    if (!(fl & BF_F_INFEASIBLE)) {
+      double a, eta;
+      if (fl & BF_F_FILTERED) { a = S.dmin[S.comp[v[0]]]; eta = 0.0; }
+      else { a = S.h; eta = (fl & BF_F_CORE) ? 0.0 : S.eta; }
+      const double d = sqrt(sqd_case<double>(code, X));
+      if (d < a && d > eta) {
+        double b, b1, b2;
+        barrier3<double>(d, a, eta, b, b1, b2);
+        l = S.kappa * fabs(b1);
+      }
+    }
+    lam[k] = l;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wout[4 * k + q] = w[q];
+    nout[3 * k] = c.x / cn;
+    nout[3 * k + 1] = c.y / cn;
+    nout[3 * k + 2] = c.z / cn;
+  }
+}
+
+// Friction of every active pair at x against the lagged xl: with dt the part
+// of sum_q w_q (x_q - xl_q) orthogonal to n and y = |dt|, energy
+// mu lambda f0(y) (f0 = y at y >= eh, the smoothing cubic below), gradient
+// w_q mu lambda f1(y)/y dt and Hessian blocks w_q w_r M with
+// M = mu lambda ((f1' y - f1)/y^3 dt dt^T + f1/y (I - n n^T)), positive
+// semidefinite as it stands.  Written into, or added to, the pair's E, G and
+// H; one wave per 64 pairs also stores the tile's energy sum.
+__global__ __launch_bounds__(64) void k_friction_eval(SceneDev S, const double* x, const double* xl, const int* ai,
+                                                      const int* aj, const unsigned char* at,
+                                                      const unsigned long long* act_count, long long acap,
+                                                      const double* lam, const double* win, const double* nin,
+                                                      double mu, double eh, int accumulate, double* E, double* G,
+                                                      double* H, double* epart) {
+  long long n = (long long)*act_count;
+  if (n > acap) n = acap;
+  const long long k = (long long)blockIdx.x * 64 + threadIdx.x;
+  double e = 0.0;
+  if (k < n) {
+    int v[4];
+    pair_verts(S, at[k], ai[k], aj[k], v);
+    double w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) w[q] = win[4 * k + q];
+    const d3 nn = {nin[3 * k], nin[3 * k + 1], nin[3 * k + 2]};
+    d3 dl = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dl = dl + w[q] * (load3(x, v[q]) - load3(xl, v[q]));
+    const double dn = dot(dl, nn);
+    const d3 dt = dl - dn * nn;
+    const double y = sqrt(dot(dt, dt));
+    double f0, g1, c1;  // f0, f1/y, (f1' y - f1)/y^3
+    if (y >= eh) {
+      f0 = y;
+      g1 = 1.0 / y;
+      c1 = -1.0 / (y * y * y);
+    } else {
+      f0 = -y * y * y / (3.0 * eh * eh) + y * y / eh + eh / 3.0;
+      g1 = -y / (eh * eh) + 2.0 / eh;
+      c1 = y > 0.0 ? -1.0 / (eh * eh * y) : 0.0;
+    }
+    const double ml = mu * lam[k];
+    const double Ek = ml * f0;
+    const d3 gv = (ml * g1) * dt;
+    const double t[3] = {dt.x, dt.y, dt.z}, nv[3] = {nn.x, nn.y, nn.z};
+    double M[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) M[3 * i + j] = ml * (c1 * t[i] * t[j] + g1 * ((i == j ? 1.0 : 0.0) - nv[i] * nv[j]));
+    const double gq[3] = {gv.x, gv.y, gv.z};
+    double* Hk = H + 144 * k;
+    double* Gk = G + 12 * k;
+    // accumulate: one rounded addition onto what is there (no contraction
+    // with the product), so the sum equals contact + friction exactly
+    auto put = [accumulate](double* p, double v) { *p = accumulate ? __dadd_rn(*p, v) : v; };
+    put(E + k, Ek);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) put(Gk + 3 * q + i, __dmul_rn(w[q], gq[i]));
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) put(Hk + 12 * (3 * q + i) + 3 * r + j, __dmul_rn(w[q] * w[r], M[3 * i + j]));
+    e = E[k];
+  }
+  double y2 = 0.0, z2 = 0.0;
+  wave_ordered_sum3(e, y2, z2);
+  if (threadIdx.x == 0 && epart && (long long)blockIdx.x * 64 < acap) epart[blockIdx.x] = e;
+}
+
+// ---------------------------------------------------------------------------
 // Temporary zero offset (Sec. 3.4): marking, release, count
 // ---------------------------------------------------------------------------
 
@@ -2127,6 +2286,21 @@ void run_core_release(const SceneDev& S, const double* x, hipStream_t st) {
 
 void run_core_count(const SceneDev& S, long long* out, hipStream_t st) {
   hipLaunchKernelGGL(k_core_count, dim3(1), dim3(256), 0, st, S.core_live, S.core_mask + 1, out);
+}
+
+void run_friction_lag(const SceneDev& S, const double* xl, const int* ai, const int* aj, const unsigned char* at,
+                      const unsigned char* acode, const unsigned char* aflags, const long long* act_count,
+                      long long acap, double* lam, double* w, double* n, hipStream_t st) {
+  hipLaunchKernelGGL(k_friction_lag, dim3(nblocks(acap)), dim3(256), 0, st, S, xl, ai, aj, at, acode, aflags,
+                     (const unsigned long long*)act_count, acap, lam, w, n);
+}
+
+void run_friction_eval(const SceneDev& S, const double* x, const double* xl, const int* ai, const int* aj,
+                       const unsigned char* at, const long long* act_count, long long acap, const double* lam,
+                       const double* w, const double* n, double mu, double eh, int accumulate, double* E, double* G,
+                       double* H, double* epart, hipStream_t st) {
+  hipLaunchKernelGGL(k_friction_eval, dim3(nblocks(acap, 64, 1 << 30)), dim3(64), 0, st, S, x, xl, ai, aj, at,
+                     (const unsigned long long*)act_count, acap, lam, w, n, mu, eh, accumulate, E, G, H, epart);
 }
 
 void run_energy(const SceneDev& S, const double* x, const double* pdisp, const double* alpha, const int* ci,
