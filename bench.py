@@ -34,6 +34,10 @@ FLOPS_PER_KIND = {0: 150.0, 1: 2700.0, 2: 8000.0, 3: 8000.0}
 # Algorithmic bytes of one active pair in eval_barrier: pair ids, type, code,
 # flags (11 B), four FP64 vertices (96 B), and E, G[12], H[12 x 12] (1256 B).
 EVAL_BYTES_PER_PAIR = 11 + 96 + 8 + 96 + 1152
+# Algorithmic bytes of one lagged pair in friction_eval: pair ids and type
+# (9 B), lambda, weights[4], normal[3] (64 B), four vertices at x and at the
+# lagged positions (192 B), and E, G[12], H[12 x 12] (1256 B).
+FRICTION_BYTES_PER_PAIR = 9 + 64 + 192 + 8 + 96 + 1152
 KIND_OF_CODE = np.array([0, 0, 0, 1, 1, 1, 2, 0, 0, 0, 0, 1, 1, 1, 1, 3])
 
 # HBM bytes per launch of the evaluation kernel, counted with rocprofv3 --pmc
@@ -79,28 +83,38 @@ def parse():
     ap.add_argument("--core-squeeze", type=float, default=0.0,
                     help="step path: scale z by this factor (e.g. 0.88 puts the woven crossings inside the core) and "
                          "mark the pairs inside the core for the temporary zero offset before timing (Sec. 3.4)")
+    ap.add_argument("--friction-mu", type=float, default=0.0,
+                    help="step path: with mu > 0 the step also evaluates and assembles IPC's lagged friction of the "
+                         "active pairs (App. A), lagged at x - 0.02 p (the previous positions; slips of about eps_vh)")
+    ap.add_argument("--eps-vh", type=float, default=1.0, help="friction smoothing width in um (sliding speed x dt)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
-def cpu_baseline(sc, n_c_gpu, x=None, core=None):
+def cpu_baseline(sc, n_c_gpu, x=None, core=None, friction=None):
     """The oracle, as it stands, on the same workload (swept enumeration,
-    derivatives of every active pair); repeated until ~10 s of CPU work."""
+    derivatives of every active pair, and the lagged friction if given);
+    repeated until ~10 s of CPU work."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     reps, t_total, n_c = 0, 0.0, 0
+    if friction is not None:
+        lag, xlag, mu, eh = friction
     while t_total < 10.0 and reps < 20:
         t0 = time.perf_counter()
         res = oracle.evaluate(sc, x, mode=1, derivs=True, nthreads=threads, core=core)
+        if friction is not None:
+            oracle.friction_eval(lag, sc.x if x is None else x, xlag, mu, eh, nthreads=threads)
         t_total += time.perf_counter() - t0
         n_c = oracle.counts(res)["n_c"]
         reps += 1
     assert n_c == n_c_gpu, (n_c, n_c_gpu)
     return {"value": n_c * reps / t_total, "unit": "pairs/s", "cores": threads, "kind": "oracle",
             "sample": f"whole workload, {reps} evaluation(s) of all pairs with d < h "
-                      f"(swept enumeration, FP64, derivatives and projection of every active pair)"}
+                      f"(swept enumeration, FP64, derivatives and projection of every active pair"
+                      + (", lagged friction of every lagged pair" if friction is not None else "") + ")"}
 
 
 def eval_roofline(ms, n_act, kinds, label):
@@ -337,7 +351,8 @@ def bench_batch(args):
         assert not (st & (bfc.BF_S_CAND_OVERFLOW | bfc.BF_S_ACT_OVERFLOW | bfc.BF_S_BSR_OVERFLOW)), st
         assert cs.counts() == c
     out = {
-        "metric": "filtered contact pairs evaluated/s (dist+filter+grad+Hessian); p50/p99 latency",
+        "metric": "filtered contact pairs evaluated/s (dist+filter+grad+Hessian"
+                  + (" + lagged friction" if fric else "") + "); p50/p99 latency",
         "value": n_c / (ms_per_step * 1e-3),
         "unit": "pairs/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -408,7 +423,8 @@ def bench_serve(args):
                            "scenes_evicted": server.evicted - e0, "retries": int(sum(r.retries for r in d))}
     head = runs["0.75"]
     out = {
-        "metric": "filtered contact pairs evaluated/s (dist+filter+grad+Hessian); p50/p99 latency",
+        "metric": "filtered contact pairs evaluated/s (dist+filter+grad+Hessian"
+                  + (" + lagged friction" if fric else "") + "); p50/p99 latency",
         "value": head["pairs_per_s"], "unit": "pairs/s",
         "n_gpus": 1, "steps": head["requests"], "warmup": 32, "ms_per_step": head["mean_ms"],
         "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
@@ -480,12 +496,27 @@ def main():
     if args.tune:
         cs.tune(x)  # threads per broad-phase query
         cs.run(x)
+    fric = args.friction_mu > 0
+    if fric:  # lagged friction (App. A): the active list and its data at the previous positions
+        xlag_np = x_np - 0.02 * synth.search_direction(sc)
+        xlag = torch.tensor(xlag_np, dtype=torch.float64, device=dev)
+        cs.run(xlag)
+        cs.friction_lag(xlag)
+        cs.run(x)
+        n_fric = int(cs.f_cnt.item())
     counts = cs.counts()
     n_c, n_act = counts["n_c"], counts["n_act"]
     codes = cs.a_code[:n_act].cpu().numpy()
     kinds = KIND_OF_CODE[codes]
 
     stream = torch.cuda.current_stream(dev)
+
+    def step():
+        cs.step(x)
+        if fric:
+            cs.friction_eval(x, args.friction_mu, args.eps_vh)
+            cs.friction_assemble()
+
     graph = None
     if args.graph != 0:
         # one step captured as a graph (every launch is on the current stream,
@@ -493,12 +524,12 @@ def main():
         side = torch.cuda.Stream(device=dev)
         side.wait_stream(stream)
         with torch.cuda.stream(side):
-            cs.step(x)
+            step()
         stream.wait_stream(side)
         torch.cuda.synchronize()
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
-            cs.step(x)
+            step()
         torch.cuda.synchronize()
 
     if args.copy_mib > 0:
@@ -517,7 +548,7 @@ def main():
             if use_graph:
                 graph.replay()
             else:
-                cs.step(x)
+                step()
         for _ in range(args.warmup):
             one_step()
         torch.cuda.synchronize()
@@ -549,9 +580,12 @@ def main():
     calls = ["build_candidates", "filter_pairs", "eval_barrier", "assemble_grad_hess"]
     fns = [lambda: cs.build_candidates(x), lambda: cs.filter_pairs(x), lambda: cs.eval_barrier(x),
            lambda: cs.assemble_grad_hess()]
+    if fric:
+        calls += ["friction_eval", "assemble_grad_hess (friction)"]
+        fns += [lambda: cs.friction_eval(x, args.friction_mu, args.eps_vh), lambda: cs.friction_assemble()]
     per = {c: [] for c in calls}
     for _ in range(max(10, args.steps // 5)):
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(len(calls) + 1)]
         e[0].record(stream)
         for q, f in enumerate(fns):
             f()
@@ -584,12 +618,32 @@ def main():
     eval_ms = e0.elapsed_time(e1) / reps
     roof = eval_roofline(eval_ms, n_act, kinds, "k_eval (eval_barrier)")
     roof["kernel_ms"] = eval_ms
+    fric_roof = None
+    if fric:
+        # friction_eval alone (one kernel), replays timed the same way
+        fg = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(fg):
+            cs.friction_eval(x, args.friction_mu, args.eps_vh)
+        torch.cuda.synchronize()
+        fg.replay()
+        e0.record(stream)
+        for _ in range(reps):
+            fg.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        f_ms = e0.elapsed_time(e1) / reps
+        fb = float(FRICTION_BYTES_PER_PAIR * n_fric)
+        fric_roof = {"kernel": "k_friction_eval (friction_eval)", "bound": "hbm",
+                     "achieved": fb / (f_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None,
+                     "kernel_ms": f_ms, "units": {"lagged_pairs": n_fric, "bytes": fb}}
+        fric_roof["frac"] = fric_roof["achieved"] / HBM_PEAK_GBS
     if (args.prec == "fp64" and args.core_squeeze == 0 and sc.name in EVAL_TRAFFIC_BYTES
             and eval_source_fingerprint() == EVAL_TRAFFIC_SOURCE):
         roof["traffic"] = EVAL_TRAFFIC_BYTES[sc.name]
 
     out = {
-        "metric": "filtered contact pairs evaluated/s (dist+filter+grad+Hessian); p50/p99 latency",
+        "metric": "filtered contact pairs evaluated/s (dist+filter+grad+Hessian"
+                  + (" + lagged friction" if fric else "") + "); p50/p99 latency",
         "value": n_c / (ms_per_step * 1e-3),
         "unit": "pairs/s",
         "n_gpus": 1,
@@ -607,10 +661,13 @@ def main():
                                                  "20-300 um, h = 300 um, dhat = 30 um"
                                                  if sc.name == "woven_patch" else sc.name)
                                + (f"; z scaled by {args.core_squeeze}, pairs inside the core under the temporary "
-                                  f"zero offset" if args.core_squeeze > 0 else ""),
+                                  f"zero offset" if args.core_squeeze > 0 else "")
+                               + (f"; lagged friction mu = {args.friction_mu}, eps_vh = {args.eps_vh} um"
+                                  if fric else ""),
                    "n_verts": sc.n_verts, "n_edges": sc.n_edges, "n_tris": sc.n_tris,
                    "N_bp": counts["n_bp"], "N_c": n_c, "N_filt": counts["n_filt"], "N_act": n_act,
                    "nnzb": counts["nnzb"], "launch": launch, "pq": cs.pq, "precision": args.prec,
+                   **({"N_friction": n_fric} if fric else {}),
                    **({"core_squeeze_z": args.core_squeeze, "core_pairs_marked": n_core,
                        "core_pairs_live": int(cs.core_live().item())} if args.core_squeeze > 0 else {})},
         "active_pairs_per_s": n_act / (ms_per_step * 1e-3),
@@ -619,13 +676,18 @@ def main():
         "ms_per_step_by_launch": {m: v[0] for m, v in modes.items()},
         "setup_s": time.perf_counter() - t0 - sum(v[2] for v in modes.values()),
         "roofline": roof,
+        **({"friction_roofline": fric_roof} if fric else {}),
     }
     if args.cpu_baseline:
         core = None
         if args.core_squeeze > 0:
             import oracle
             core = oracle.core_mark(sc, x_np)
-        out["cpu_baseline"] = cpu_baseline(sc, n_c, x_np if args.core_squeeze > 0 else None, core)
+        fr = None
+        if fric:
+            import oracle
+            fr = (oracle.friction_lag(sc, xlag_np), xlag_np, args.friction_mu, args.eps_vh)
+        out["cpu_baseline"] = cpu_baseline(sc, n_c, x_np if (args.core_squeeze > 0 or fric) else None, core, fr)
     print(json.dumps(out))
 
 

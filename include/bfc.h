@@ -298,6 +298,17 @@ bf_status friction_lag(bf_scene* s, const double* xlag_d, const bf_active* act, 
 bf_status friction_eval(bf_scene* s, const double* x_d, const double* xlag_d, const bf_active* act,
                         const bf_friction* fr, double mu, double eps_vh, int32_t accumulate, bf_local* out,
                         void* stream);
+/* The friction's sums over the lagged list (same outputs and fixed order as
+ * assemble_grad_hess): friction_lag also builds the assembly structure of
+ * its list (incidence lists, sorted row columns) in a workspace of the
+ * scene's own, so friction_assemble only adds the values that the last
+ * friction_eval (accumulate = 0) wrote into loc.  act must be the list given
+ * to the last friction_lag, unchanged (BF_E_STATE for any other list) and
+ * within the scene's active capacity.  friction_lag synchronises the device
+ * when it (re)allocates that workspace: on the first call, and when the
+ * list's capacity grows; otherwise neither call synchronises. */
+bf_status friction_assemble(bf_scene* s, const bf_active* act, const bf_local* loc, double* E_d, double* g_d,
+                            bf_bsr* H, void* stream);
 
 /* ---- tuning ---------------------------------------------------------------
  * Threads per broad-phase query (2, 4 or 8; default 4): more threads split a

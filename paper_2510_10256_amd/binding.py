@@ -29,7 +29,7 @@ EXPORTED = ["bf_scene_create", "bf_scene_reserve", "bf_scene_destroy", "bf_scene
             "filter_pairs", "eval_barrier", "assemble_grad_hess", "bf_scene_set_pq", "bf_scene_tune",
             "bf_batch_create", "bf_batch_step", "bf_batch_info", "bf_batch_destroy", "build_candidates_swept",
             "max_step_accd", "eval_energy", "bf_core_mark", "bf_core_live", "bf_core_clear", "friction_lag",
-            "friction_eval", "bf_status_word", "bf_last_error"]
+            "friction_eval", "friction_assemble", "bf_status_word", "bf_last_error"]
 
 
 def build(verbose: bool = False) -> str:
@@ -117,6 +117,7 @@ def lib():
         L.friction_lag.argtypes = [P, P, C.POINTER(Active), C.POINTER(Friction), P]
         L.friction_eval.argtypes = [P, P, P, C.POINTER(Active), C.POINTER(Friction), C.c_double, C.c_double,
                                     C.c_int32, C.POINTER(Local), P]
+        L.friction_assemble.argtypes = [P, C.POINTER(Active), C.POINTER(Local), P, P, C.POINTER(Bsr), P]
         L.bf_status_word.argtypes = [P, C.POINTER(C.c_uint32), C.c_int32]
         L.bf_last_error.restype = C.c_char_p
         for name in EXPORTED[:-1]:
@@ -320,9 +321,9 @@ class ContactScene:
     def friction_assemble(self):
         """Assemble the friction terms of the last friction_eval over the lagged
         list into f_E, f_g and the block matrix (f_row_ptr, f_col, f_val)."""
-        _check(lib().assemble_grad_hess(self.handle, C.byref(self._fact), C.byref(self._floc), _ptr(self.f_E),
-                                        _ptr(self.f_g), C.byref(self._fbsr), C.c_void_p(self._stream())),
-               "assemble_grad_hess (friction)")
+        _check(lib().friction_assemble(self.handle, C.byref(self._fact), C.byref(self._floc), _ptr(self.f_E),
+                                       _ptr(self.f_g), C.byref(self._fbsr), C.c_void_p(self._stream())),
+               "friction_assemble")
 
     def friction_results(self):
         """Host copies of the lagged list, its friction data and the last

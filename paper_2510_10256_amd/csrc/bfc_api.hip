@@ -36,6 +36,12 @@ struct bf_scene {
   StageWs sw{};
   AsmWs aw{};
   long long act_cap = 0;
+  // lagged friction: the assembly structure of the lagged list, built once by
+  // friction_lag and read by every friction_assemble until the next one
+  AsmWs faw{};
+  long long fasm_cap = 0;
+  std::vector<void*> fasm_allocs;
+  const void* fric_list = nullptr;  // the lagged list (its pair ids) the structure belongs to
   std::vector<void*> allocs;        // scene-lifetime allocations
   std::vector<void*> asm_allocs;    // assembly scratch (regrown by reserve)
   std::vector<void*> stage_allocs;  // narrow-phase staging (regrown by reserve)
@@ -118,26 +124,34 @@ void free_list(std::vector<void*>& l, hipStream_t st = g_alloc_stream) {
   l.clear();
 }
 
-bf_status alloc_asm(bf_scene* s, long long act_cap) {
-  free_list(s->asm_allocs);
+// One assembly workspace for lists of up to act_cap pairs (incidence counts
+// cleared, as the structure pass expects them).
+bf_status alloc_asm_ws(const bf_scene* s, long long act_cap, std::vector<void*>& allocs, AsmWs* out,
+                       const char* who) {
+  free_list(allocs);
   hipError_t e = hipSuccess;
   AsmWs A{};
-  A.inc_cnt = dalloc<int>(s->asm_allocs, s->nv + 1, &e);
-  A.inc_off = dalloc<int>(s->asm_allocs, s->nv + 1, &e);
-  A.inc = dalloc<int>(s->asm_allocs, 4 * act_cap, &e);
-  A.colbuf = dalloc<int>(s->asm_allocs, 16 * act_cap, &e);
-  A.rowcnt = dalloc<int>(s->asm_allocs, s->nv + 1, &e);
-  A.mid = dalloc<int>(s->asm_allocs, s->nv + 1, &e);
-  A.epart = dalloc<double>(s->asm_allocs, (act_cap + 63) / 64 + 1, &e);
-  A.scan_tmp = dalloc<int>(s->asm_allocs, scan_parts(s->nv + 1) + 16, &e);
-  if (e != hipSuccess) return fail(BF_E_NOMEM, "bf_scene_reserve: device allocation failed");
+  A.inc_cnt = dalloc<int>(allocs, s->nv + 1, &e);
+  A.inc_off = dalloc<int>(allocs, s->nv + 1, &e);
+  A.inc = dalloc<int>(allocs, 4 * act_cap, &e);
+  A.colbuf = dalloc<int>(allocs, 16 * act_cap, &e);
+  A.rowcnt = dalloc<int>(allocs, s->nv + 1, &e);
+  A.mid = dalloc<int>(allocs, s->nv + 1, &e);
+  A.epart = dalloc<double>(allocs, (act_cap + 63) / 64 + 1, &e);
+  A.scan_tmp = dalloc<int>(allocs, scan_parts(s->nv + 1) + 16, &e);
+  if (e != hipSuccess) return fail(BF_E_NOMEM, who);
   if (hipMemsetAsync(A.inc_cnt, 0, sizeof(int) * (s->nv + 1), g_alloc_stream) != hipSuccess ||
       hipMemsetAsync(A.rowcnt, 0, sizeof(int) * (s->nv + 1), g_alloc_stream) != hipSuccess ||
       hipStreamSynchronize(g_alloc_stream) != hipSuccess)
-    return fail(BF_E_DEVICE, "bf_scene_reserve: clearing the incidence counts failed");
-  s->aw = A;
-  s->act_cap = act_cap;
+    return fail(BF_E_DEVICE, who);
+  *out = A;
   return BF_OK;
+}
+
+bf_status alloc_asm(bf_scene* s, long long act_cap) {
+  bf_status r = alloc_asm_ws(s, act_cap, s->asm_allocs, &s->aw, "bf_scene_reserve: assembly workspace");
+  if (r == BF_OK) s->act_cap = act_cap;
+  return r;
 }
 
 // Culling mode: order every polyline of a rod mesh.  eidx[e] = position of
@@ -444,6 +458,7 @@ bf_status bf_scene_destroy(bf_scene* s) {
   free_list(s->asm_allocs, s->last);
   free_list(s->stage_allocs, s->last);
   free_list(s->core_allocs, s->last);
+  free_list(s->fasm_allocs, s->last);
   free_list(s->allocs, s->last);
   if (s->ev_join) (void)hipEventDestroy(s->ev_join);
   if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
@@ -544,10 +559,44 @@ bf_status friction_lag(bf_scene* s, const double* xlag_d, const bf_active* act, 
   if (fr->cap < act->p.cap) return fail(BF_E_CAPACITY, "friction_lag: friction capacity below active capacity");
   hipStream_t st = (hipStream_t)stream;
   s->last = st;
-  run_friction_lag(dev_view(s), xlag_d, act->p.i_d, act->p.j_d, act->p.type_d, act->code_d, act->flags_d,
+  if (act->p.cap > s->fasm_cap) {  // (re)size the friction assembly's workspace
+    hipError_t he = hipDeviceSynchronize();
+    if (he != hipSuccess) return fail_hip(he, "friction_lag");
+    g_alloc_stream = nullptr;
+    s->fasm_cap = 0;
+    s->fric_list = nullptr;
+    bf_status r = alloc_asm_ws(s, act->p.cap, s->fasm_allocs, &s->faw, "friction_lag: assembly workspace");
+    if (r != BF_OK) return r;
+    s->fasm_cap = act->p.cap;
+  }
+  const SceneDev S = dev_view(s);
+  run_friction_lag(S, xlag_d, act->p.i_d, act->p.j_d, act->p.type_d, act->code_d, act->flags_d,
                    (const long long*)act->p.count_d, act->p.cap, fr->lam_d, fr->w_d, fr->n_d, st);
+  run_asm_structure(S, act->p.i_d, act->p.j_d, act->p.type_d, act->flags_d, (const long long*)act->p.count_d,
+                    act->p.cap, s->faw, st);
+  s->fric_list = act->p.i_d;
   hipError_t he = hipGetLastError();
   return he == hipSuccess ? BF_OK : fail_hip(he, "friction_lag");
+}
+
+bf_status friction_assemble(bf_scene* s, const bf_active* act, const bf_local* loc, double* E_d, double* g_d,
+                            bf_bsr* H, void* stream) {
+  if (!s || !act || !loc || !E_d || !g_d || !H || !H->row_ptr_d || !H->col_d || !H->val_d || !H->nnzb_d ||
+      H->cap < 1 || !act->p.count_d || !loc->G_d || !loc->H_d)
+    return fail(BF_E_ARG, "friction_assemble: null argument or capacity < 1");
+  if (!s->fric_list || act->p.i_d != s->fric_list)
+    return fail(BF_E_STATE, "friction_assemble: not the list of the last friction_lag");
+  if (act->p.cap > s->act_cap || act->p.cap > s->fasm_cap)
+    return fail(BF_E_CAPACITY, "friction_assemble: lagged capacity exceeds the scene reserve (bf_scene_reserve)");
+  hipStream_t st = (hipStream_t)stream;
+  s->last = st;
+  AsmWs F = s->faw;
+  F.epart = s->aw.epart;  // friction_eval's per-tile energy sums
+  run_asm_values(dev_view(s), act->p.i_d, act->p.j_d, act->p.type_d, (const long long*)act->p.count_d, act->p.cap,
+                 loc->G_d, loc->H_d, E_d, g_d, H->row_ptr_d, H->col_d, H->val_d, H->cap, (long long*)H->nnzb_d, F,
+                 s->d_status, st);
+  hipError_t he = hipGetLastError();
+  return he == hipSuccess ? BF_OK : fail_hip(he, "friction_assemble");
 }
 
 bf_status friction_eval(bf_scene* s, const double* x_d, const double* xlag_d, const bf_active* act,

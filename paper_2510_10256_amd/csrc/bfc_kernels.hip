@@ -1961,72 +1961,99 @@ __global__ __launch_bounds__(256) void k_friction_lag(SceneDev S, const double* 
 // M = mu lambda ((f1' y - f1)/y^3 dt dt^T + f1/y (I - n n^T)), positive
 // semidefinite as it stands.  Written into, or added to, the pair's E, G and
 // H; one wave per 64 pairs also stores the tile's energy sum.
-__global__ __launch_bounds__(64) void k_friction_eval(SceneDev S, const double* x, const double* xl, const int* ai,
+//
+// Four waves per 64 pairs.  Each lane of the first wave computes its pair's
+// w[4], force f[3] and M[9] and leaves them in LDS; the four waves then
+// write the tile's 64 x 12 gradient and 64 x 144 Hessian entries as one
+// contiguous run each (thread t takes entries t, t + 256, ...), rebuilding
+// every entry from LDS as w_q f_i or w_q w_r M_ij.  Stores straight from each
+// lane's registers would scatter every instruction over 64 rows 1152 bytes
+// apart; the extra waves shorten the store loop of a tile.
+constexpr int FR_ST = 17;  // LDS doubles per pair: w[4], f[3], M[9], pad (odd stride)
+__global__ __launch_bounds__(256) void k_friction_eval(SceneDev S, const double* x, const double* xl, const int* ai,
                                                       const int* aj, const unsigned char* at,
                                                       const unsigned long long* act_count, long long acap,
                                                       const double* lam, const double* win, const double* nin,
                                                       double mu, double eh, int accumulate, double* E, double* G,
                                                       double* H, double* epart) {
+  __shared__ double sm[64 * FR_ST];
   long long n = (long long)*act_count;
   if (n > acap) n = acap;
-  const long long k = (long long)blockIdx.x * 64 + threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const long long k0 = (long long)blockIdx.x * 64, k = k0 + lane;
   double e = 0.0;
-  if (k < n) {
-    int v[4];
-    pair_verts(S, at[k], ai[k], aj[k], v);
-    double w[4];
+  if (k0 < n) {
+    double* my = sm + FR_ST * lane;
+    if (tid < 64 && k < n) {
+      int v[4];
+      pair_verts(S, at[k], ai[k], aj[k], v);
+      double w[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) w[q] = win[4 * k + q];
-    const d3 nn = {nin[3 * k], nin[3 * k + 1], nin[3 * k + 2]};
-    d3 dl = {0.0, 0.0, 0.0};
+      for (int q = 0; q < 4; ++q) w[q] = win[4 * k + q];
+      const d3 nn = {nin[3 * k], nin[3 * k + 1], nin[3 * k + 2]};
+      d3 dl = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int q = 0; q < 4; ++q) dl = dl + w[q] * (load3(x, v[q]) - load3(xl, v[q]));
-    const double dn = dot(dl, nn);
-    const d3 dt = dl - dn * nn;
-    const double y = sqrt(dot(dt, dt));
-    double f0, g1, c1;  // f0, f1/y, (f1' y - f1)/y^3
-    if (y >= eh) {
-      f0 = y;
-      g1 = 1.0 / y;
-      c1 = -1.0 / (y * y * y);
-    } else {
-      f0 = -y * y * y / (3.0 * eh * eh) + y * y / eh + eh / 3.0;
-      g1 = -y / (eh * eh) + 2.0 / eh;
-      c1 = y > 0.0 ? -1.0 / (eh * eh * y) : 0.0;
-    }
-    const double ml = mu * lam[k];
-    const double Ek = ml * f0;
-    const d3 gv = (ml * g1) * dt;
-    const double t[3] = {dt.x, dt.y, dt.z}, nv[3] = {nn.x, nn.y, nn.z};
-    double M[9];
+      for (int q = 0; q < 4; ++q) dl = dl + w[q] * (load3(x, v[q]) - load3(xl, v[q]));
+      const double dn = dot(dl, nn);
+      const d3 dt = dl - dn * nn;
+      const double y = sqrt(dot(dt, dt));
+      double f0, g1, c1;  // f0, f1/y, (f1' y - f1)/y^3
+      if (y >= eh) {
+        f0 = y;
+        g1 = 1.0 / y;
+        c1 = -1.0 / (y * y * y);
+      } else {
+        f0 = -y * y * y / (3.0 * eh * eh) + y * y / eh + eh / 3.0;
+        g1 = -y / (eh * eh) + 2.0 / eh;
+        c1 = y > 0.0 ? -1.0 / (eh * eh * y) : 0.0;
+      }
+      const double ml = mu * lam[k];
+      const double Ek = ml * f0;
+      const d3 gv = (ml * g1) * dt;
+      const double t[3] = {dt.x, dt.y, dt.z}, nv[3] = {nn.x, nn.y, nn.z};
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) M[3 * i + j] = ml * (c1 * t[i] * t[j] + g1 * ((i == j ? 1.0 : 0.0) - nv[i] * nv[j]));
-    const double gq[3] = {gv.x, gv.y, gv.z};
-    double* Hk = H + 144 * k;
-    double* Gk = G + 12 * k;
-    // accumulate: one rounded addition onto what is there (no contraction
-    // with the product), so the sum equals contact + friction exactly
-    auto put = [accumulate](double* p, double v) { *p = accumulate ? __dadd_rn(*p, v) : v; };
-    put(E + k, Ek);
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int i = 0; i < 3; ++i) put(Gk + 3 * q + i, __dmul_rn(w[q], gq[i]));
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
+      for (int q = 0; q < 4; ++q) my[q] = w[q];
+      my[4] = gv.x;
+      my[5] = gv.y;
+      my[6] = gv.z;
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int j = 0; j < 3; ++j)
+          my[7 + 3 * i + j] = ml * (c1 * t[i] * t[j] + g1 * ((i == j ? 1.0 : 0.0) - nv[i] * nv[j]));
+      // accumulate: one rounded addition onto what is there (no contraction
+      // with the product), so the sum equals contact + friction exactly
+      E[k] = accumulate ? __dadd_rn(E[k], Ek) : Ek;
+      e = E[k];
+    }
+    __syncthreads();
+    const int rows = (int)(n - k0 < 64 ? n - k0 : 64);
+    double* Gt = G + 12 * k0;
 #pragma unroll
-          for (int j = 0; j < 3; ++j) put(Hk + 12 * (3 * q + i) + 3 * r + j, __dmul_rn(w[q] * w[r], M[3 * i + j]));
-    e = E[k];
+    for (int it = 0; it < 3; ++it) {
+      const int idx = it * 256 + tid, pp = idx / 12, c = idx - 12 * pp;
+      if (pp < rows) {
+        const double* ps = sm + FR_ST * pp;
+        const double val = __dmul_rn(ps[c / 3], ps[4 + c % 3]);
+        Gt[idx] = accumulate ? __dadd_rn(Gt[idx], val) : val;
+      }
+    }
+    double* Ht = H + 144 * k0;
+    for (int it = 0; it < 36; ++it) {
+      const int idx = it * 256 + tid, pp = idx / 144, rem = idx - 144 * pp;
+      if (pp < rows) {
+        const int rw = rem / 12, cl = rem - 12 * rw;
+        const double* ps = sm + FR_ST * pp;
+        const double val = __dmul_rn(ps[rw / 3] * ps[cl / 3], ps[7 + 3 * (rw % 3) + cl % 3]);
+        Ht[idx] = accumulate ? __dadd_rn(Ht[idx], val) : val;
+      }
+    }
   }
-  double y2 = 0.0, z2 = 0.0;
-  wave_ordered_sum3(e, y2, z2);
-  if (threadIdx.x == 0 && epart && (long long)blockIdx.x * 64 < acap) epart[blockIdx.x] = e;
+  if (tid < 64) {  // the first wave holds the tile's energies
+    double y2 = 0.0, z2 = 0.0;
+    wave_ordered_sum3(e, y2, z2);
+    if (tid == 0 && epart && k0 < acap) epart[blockIdx.x] = e;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -2299,7 +2326,7 @@ void run_friction_eval(const SceneDev& S, const double* x, const double* xl, con
                        const unsigned char* at, const long long* act_count, long long acap, const double* lam,
                        const double* w, const double* n, double mu, double eh, int accumulate, double* E, double* G,
                        double* H, double* epart, hipStream_t st) {
-  hipLaunchKernelGGL(k_friction_eval, dim3(nblocks(acap, 64, 1 << 30)), dim3(64), 0, st, S, x, xl, ai, aj, at,
+  hipLaunchKernelGGL(k_friction_eval, dim3(nblocks(acap, 64, 1 << 30)), dim3(256), 0, st, S, x, xl, ai, aj, at,
                      (const unsigned long long*)act_count, acap, lam, w, n, mu, eh, accumulate, E, G, H, epart);
 }
 

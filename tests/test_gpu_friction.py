@@ -69,6 +69,12 @@ def test_lagged_friction_matches_the_oracle(name):
     cs.friction_eval(X, MU, EH)
     cs.friction_assemble()
     g = cs.friction_results()
+    # the assembly structure belongs to the lagged list: another list is refused
+    import ctypes as C
+    from paper_2510_10256_amd import binding as B
+    rc = B.lib().friction_assemble(cs.handle, C.byref(cs._act), C.byref(cs._floc), B._ptr(cs.f_E), B._ptr(cs.f_g),
+                                   C.byref(cs._fbsr), C.c_void_p(cs._stream()))
+    assert rc == 5   # BF_E_STATE
     assert cs.status(clear=True) & bfc.BF_S_BSR_OVERFLOW == 0
     lag = oracle.friction_lag(sc, xl)
     o = oracle.friction_eval(lag, x, xl, MU, EH)
