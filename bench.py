@@ -44,18 +44,31 @@ KIND_OF_CODE = np.array([0, 0, 0, 1, 1, 1, 2, 0, 0, 0, 0, 1, 1, 1, 1, 3])
 # (FETCH_SIZE x 2 and WRITE_SIZE x 1, the factors a plain 256 MiB copy gives)
 # on the kernel source whose fingerprint is EVAL_TRAFFIC_SOURCE; reported as
 # null once that source changes.
-EVAL_TRAFFIC_SOURCE = "1316a7d711850f36"
-EVAL_TRAFFIC_BYTES = {"woven_patch": 49.6e6, "folded_cloth": 2177.8e6}
+EVAL_TRAFFIC_SOURCE = "173737cb16c1e993"
+EVAL_TRAFFIC_BYTES = {"woven_patch": 51.7e6, "folded_cloth": 2305.7e6}
+# the same for the friction kernel (lag at x - 0.02 p; the bytes do not depend on mu)
+FRICTION_TRAFFIC_SOURCE = "423c9b78a4f89de4"
+FRICTION_TRAFFIC_BYTES = {"woven_patch": 39.7e6, "folded_cloth": 2833.5e6}
 
 
-def eval_source_fingerprint():
+def _source_fingerprint(first_line, kernel, headers):
     import hashlib
     csrc = os.path.join(ROOT, "paper_2510_10256_amd", "csrc")
     src = open(os.path.join(csrc, "bfc_kernels.hip")).read()
-    a = src.index("// One wave per work-group, one pair per lane.  Each lane keeps its pair")
-    b = src.index("\n}\n", src.index("__global__ __launch_bounds__(64) void k_eval")) + 3
-    text = "".join(open(os.path.join(csrc, f)).read() for f in ("bfc_eval.h", "bfc_eig.h", "bfc_geom.h")) + src[a:b]
+    a = src.index(first_line)
+    b = src.index("\n}\n", src.index(kernel, a)) + 3
+    text = "".join(open(os.path.join(csrc, f)).read() for f in headers) + src[a:b]
     return hashlib.sha256(text.encode()).hexdigest()[:16]
+
+
+def eval_source_fingerprint():
+    return _source_fingerprint("// One wave per work-group, one pair per lane.  Each lane keeps its pair",
+                               "__global__ __launch_bounds__(64) void k_eval", ("bfc_eval.h", "bfc_eig.h", "bfc_geom.h"))
+
+
+def friction_source_fingerprint():
+    return _source_fingerprint("// Friction of every active pair at x against the lagged xl",
+                               "void k_friction_eval(", ("bfc_geom.h",))
 
 
 def parse():
@@ -140,6 +153,9 @@ def eval_roofline(ms, n_act, kinds, label):
 # mean displacement, motion bound, exact swept-box test, first distance,
 # filter) and per step (position update, classification, gap)
 ACCD_FLOPS_SETUP = 180.0
+# per-kernel timing: launches captured back to back in one graph (replayed;
+# a lone short kernel per replay would time the replay's launch instead)
+KERNEL_LAUNCHES = 10
 ACCD_FLOPS_PER_ITER = 110.0
 
 
@@ -596,47 +612,45 @@ def main():
     call_ms = {c: float(np.mean(v)) for c, v in per.items()}
 
     # roofline of the per-pair evaluation kernel: eval_barrier captured alone
-    # (under capture it launches only k_eval), replays timed with events
-    eval_graph = torch.cuda.CUDAGraph()
-    side = torch.cuda.Stream(device=dev)
-    side.wait_stream(stream)
-    with torch.cuda.stream(side):
-        cs.eval_barrier(x)
-    stream.wait_stream(side)
-    torch.cuda.synchronize()
-    with torch.cuda.graph(eval_graph):
-        cs.eval_barrier(x)
-    torch.cuda.synchronize()
-    reps = max(20, args.steps // 2)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    eval_graph.replay()
-    e0.record(stream)
-    for _ in range(reps):
-        eval_graph.replay()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    eval_ms = e0.elapsed_time(e1) / reps
+    # (under capture it launches only k_eval), KERNEL_LAUNCHES launches back to
+    # back in one graph; replays timed with events on the launching stream
+    def per_launch_ms(fn):
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream(device=dev)
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            fn()
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            for _ in range(KERNEL_LAUNCHES):
+                fn()
+        torch.cuda.synchronize()
+        reps = max(4, args.steps // 10)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        g.replay()
+        e0.record(stream)
+        for _ in range(reps):
+            g.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / (reps * KERNEL_LAUNCHES)
+
+    eval_ms = per_launch_ms(lambda: cs.eval_barrier(x))
     roof = eval_roofline(eval_ms, n_act, kinds, "k_eval (eval_barrier)")
     roof["kernel_ms"] = eval_ms
     fric_roof = None
     if fric:
-        # friction_eval alone (one kernel), replays timed the same way
-        fg = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(fg):
-            cs.friction_eval(x, args.friction_mu, args.eps_vh)
-        torch.cuda.synchronize()
-        fg.replay()
-        e0.record(stream)
-        for _ in range(reps):
-            fg.replay()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        f_ms = e0.elapsed_time(e1) / reps
+        # friction_eval alone (one kernel), timed the same way
+        f_ms = per_launch_ms(lambda: cs.friction_eval(x, args.friction_mu, args.eps_vh))
         fb = float(FRICTION_BYTES_PER_PAIR * n_fric)
         fric_roof = {"kernel": "k_friction_eval (friction_eval)", "bound": "hbm",
                      "achieved": fb / (f_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None,
                      "kernel_ms": f_ms, "units": {"lagged_pairs": n_fric, "bytes": fb}}
         fric_roof["frac"] = fric_roof["achieved"] / HBM_PEAK_GBS
+        if (args.core_squeeze == 0 and sc.name in FRICTION_TRAFFIC_BYTES
+                and friction_source_fingerprint() == FRICTION_TRAFFIC_SOURCE):
+            fric_roof["traffic"] = FRICTION_TRAFFIC_BYTES[sc.name]
     if (args.prec == "fp64" and args.core_squeeze == 0 and sc.name in EVAL_TRAFFIC_BYTES
             and eval_source_fingerprint() == EVAL_TRAFFIC_SOURCE):
         roof["traffic"] = EVAL_TRAFFIC_BYTES[sc.name]
