@@ -5,7 +5,8 @@
 // The eigensystem comes from a Householder reduction to tridiagonal form
 // followed by implicit symmetric QR steps with Wilkinson shifts, deflating
 // from the bottom (Golub and Van Loan, Matrix Computations, Alg. 8.3.1 and
-// 8.3.2).  For n = 9 this costs about a quarter of the FP64 operations of
+// 8.3.2; the orthogonal factor formed from the reflectors by backward
+// accumulation, Sec. 5.1.6).  For n = 9 this costs about a quarter of the FP64 operations of
 // cyclic Jacobi (which needs about seven sweeps of 36 rotations here).  All
 // array indices are compile-time constants (registers, no scratch); the only
 // data-dependent control is the number of QR steps per deflation stage, a loop
@@ -36,9 +37,32 @@ BFC_HD bool eig_all(bool p) {
 #endif
 }
 
+// Plane rotation that maps (x, z) to (r, 0): c = x / r, s = z / r,
+// r = |(x, z)|, from one reciprocal square root (a square root and a
+// division per rotation lengthen the dependent chain of a QR step).
+BFC_HD void eig_givens(double x, double z, double& c, double& s, double& r) {
+  const double q = x * x + z * z;
+  if (q > 0.0) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const double ir = rsqrt(q);
+#else
+    const double ir = 1.0 / sqrt(q);
+#endif
+    c = x * ir;
+    s = z * ir;
+    r = q * ir;
+  } else {
+    c = 1.0;
+    s = 0.0;
+    r = 0.0;
+  }
+}
+
 // One implicit symmetric QR step with Wilkinson shift on the leading block
-// 0..L of the tridiagonal (d, e); the rotations are applied to the columns of
-// Z (N x N, row-major).
+// 0..L of the tridiagonal (d, e); the rotations are then applied to the
+// columns of Z (N x N, row-major) one row at a time (each element sees the
+// same operations in the same order as rotation by rotation; a row in flight
+// at a time keeps the live set small).
 template <int N, int L> BFC_HD void eig_qr_step(double* d, double* e, double (*Z)[N]) {
   const double dl = 0.5 * (d[L - 1] - d[L]);
   const double b2 = e[L - 1] * e[L - 1];
@@ -46,15 +70,13 @@ template <int N, int L> BFC_HD void eig_qr_step(double* d, double* e, double (*Z
   const double den = dl >= 0.0 ? dl + rt : dl - rt;
   const double mu = den != 0.0 ? d[L] - b2 / den : d[L];
   double x = d[0] - mu, z = e[0];
+  double cr[L], sr[L];
 #pragma unroll
   for (int k = 0; k < L; ++k) {
-    const double r = sqrt(x * x + z * z);
-    double c = 1.0, s = 0.0;
-    if (r > 0.0) {
-      const double ir = 1.0 / r;
-      c = x * ir;
-      s = z * ir;
-    }
+    double c, s, r;
+    eig_givens(x, z, c, s, r);
+    cr[k] = c;
+    sr[k] = s;
     if (k > 0) e[k - 1] = r;
     const double a = d[k], b = e[k], cc = d[k + 1];
     const double c2 = c * c, s2 = s * s, cs = c * s;
@@ -66,12 +88,17 @@ template <int N, int L> BFC_HD void eig_qr_step(double* d, double* e, double (*Z
       e[k + 1] = c * e[k + 1];
       x = e[k];
     }
+  }
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-      const double zk = Z[i][k], zk1 = Z[i][k + 1];
-      Z[i][k] = c * zk + s * zk1;
-      Z[i][k + 1] = c * zk1 - s * zk;
+  for (int i = 0; i < N; ++i) {
+    double zk = Z[i][0];
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+      const double zk1 = Z[i][k + 1];
+      Z[i][k] = cr[k] * zk + sr[k] * zk1;
+      zk = cr[k] * zk1 - sr[k] * zk;
     }
+    Z[i][L] = zk;
   }
 }
 
@@ -91,13 +118,15 @@ template <int N, int L> BFC_HD void eig_stages(double* d, double* e, double (*Z)
 // A: upper triangle of the symmetric N x N input (destroyed); P: upper
 // triangle of A+.  tol: relative size (to |A|) below which an off-diagonal
 // element of the tridiagonal counts as zero.
+//
+// Live data is kept small so that the whole projection stays in registers:
+// the reduction stores its reflectors in the entries of A it zeroes (Z is not
+// carried through it), Z is formed from them afterwards, and A+ is built row
+// by row while the rows of Z that are no longer needed die.
 template <int N> BFC_HD void psd_project(double* A, double* P, double tol) {
-  double Z[N][N];
-#pragma unroll
-  for (int i = 0; i < N; ++i)
-#pragma unroll
-    for (int j = 0; j < N; ++j) Z[i][j] = i == j ? 1.0 : 0.0;
-  // Householder reduction: step k zeroes entries k+2.. of column k
+  // Householder reduction: step k zeroes entries k+2.. of row k and keeps
+  // v[k+2..] there, v[k+1] in vh[k] and 2 / (v^T v) in bh[k] (0: identity)
+  double vh[N > 2 ? N - 2 : 1], bh[N > 2 ? N - 2 : 1];
 #pragma unroll
   for (int k = 0; k < N - 2; ++k) {
     double v[N];
@@ -105,7 +134,9 @@ template <int N> BFC_HD void psd_project(double* A, double* P, double tol) {
 #pragma unroll
     for (int j = k + 2; j < N; ++j) sig += A[eig_uix<N>(k, j)] * A[eig_uix<N>(k, j)];
     const double x0 = A[eig_uix<N>(k, k + 1)];
-    if (!(sig > 0.0)) continue;  // already tridiagonal in this column (the same on every lane of typical input)
+    vh[k] = 0.0;
+    bh[k] = 0.0;
+    if (!(sig > 0.0)) continue;  // already tridiagonal in this row (the same on every lane of typical input)
     const double nrm = sqrt(x0 * x0 + sig);
     const double alpha = x0 >= 0.0 ? -nrm : nrm;
     const double beta = 1.0 / (alpha * (alpha - x0));  // 2 / (v^T v)
@@ -133,18 +164,8 @@ template <int N> BFC_HD void psd_project(double* A, double* P, double tol) {
 #pragma unroll
       for (int j = i; j < N; ++j) A[eig_uix<N>(i, j)] -= v[i] * p[j] + p[i] * v[j];
     A[eig_uix<N>(k, k + 1)] = alpha;
-#pragma unroll
-    for (int j = k + 2; j < N; ++j) A[eig_uix<N>(k, j)] = 0.0;
-    // Z <- Z H
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      double s = 0.0;
-#pragma unroll
-      for (int j = k + 1; j < N; ++j) s += Z[i][j] * v[j];
-      s *= beta;
-#pragma unroll
-      for (int j = k + 1; j < N; ++j) Z[i][j] -= s * v[j];
-    }
+    vh[k] = v[k + 1];
+    bh[k] = beta;  // v[k+2..] stay in row k of A
   }
   double d[N], e[N];
   double anorm = 0.0;
@@ -152,21 +173,49 @@ template <int N> BFC_HD void psd_project(double* A, double* P, double tol) {
   for (int i = 0; i < N; ++i) {
     d[i] = A[eig_uix<N>(i, i)];
     e[i] = i + 1 < N ? A[eig_uix<N>(i, i + 1)] : 0.0;
-    anorm = fmax(anorm, fabs(d[i]) + fabs(e[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0));
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) anorm = fmax(anorm, fabs(d[i]) + fabs(e[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0));
+  // Z = H_0 H_1 ... H_{N-3}, accumulated from the last reflector (H_k acts on
+  // indices k+1..N-1, where the product so far is still the identity outside)
+  double Z[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) Z[i][j] = i == j ? 1.0 : 0.0;
+#pragma unroll
+  for (int k = N - 3; k >= 0; --k) {
+    double v[N];
+    v[k + 1] = vh[k];
+#pragma unroll
+    for (int j = k + 2; j < N; ++j) v[j] = A[eig_uix<N>(k, j)];
+#pragma unroll
+    for (int j = k + 1; j < N; ++j) {
+      double w = 0.0;
+#pragma unroll
+      for (int i = k + 1; i < N; ++i) w += v[i] * Z[i][j];
+      w *= bh[k];
+#pragma unroll
+      for (int i = k + 1; i < N; ++i) Z[i][j] -= w * v[i];
+    }
   }
   eig_stages<N, N - 1>(d, e, Z, tol * anorm);
   double lam[N];
 #pragma unroll
   for (int k = 0; k < N; ++k) lam[k] = fmax(d[k], 0.0);
 #pragma unroll
-  for (int i = 0; i < N; ++i)
+  for (int i = 0; i < N; ++i) {
+    double zl[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) zl[k] = Z[i][k] * lam[k];
 #pragma unroll
     for (int j = i; j < N; ++j) {
       double acc = 0.0;
 #pragma unroll
-      for (int k = 0; k < N; ++k) acc += Z[i][k] * lam[k] * Z[j][k];
+      for (int k = 0; k < N; ++k) acc += zl[k] * Z[j][k];
       P[eig_uix<N>(i, j)] = acc;
     }
+  }
 }
 
 }  // namespace bfc

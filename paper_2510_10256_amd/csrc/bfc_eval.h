@@ -164,8 +164,8 @@ __device__ __forceinline__ void eval_pe(const d3* P, int sp, int se0, int se1, d
           A[uix<6>(I, J)] = br[al] * br[bt] * Yrr[i][j] + br[al] * be[bt] * Yre[i][j] +
                             be[al] * br[bt] * Yre[j][i] + be[al] * be[bt] * Yee[i][j];
         }
-  psd_project<6>(A, h.A, tol);
-  // slot of the pair missing from the stencil gets a zero gradient
+  // the gradient goes out first: nothing but A stays live through the projection
+  // (slot of the pair missing from the stencil gets a zero gradient)
   zero_grad(G);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {  // Y rows: r = (1, -1, 0), e = (0, -1, 1) on (p, e0, e1)
@@ -174,6 +174,7 @@ __device__ __forceinline__ void eval_pe(const d3* P, int sp, int se0, int se1, d
     G[3 * se0 + i] = -grx - gex;
     G[3 * se1 + i] = gex;
   }
+  psd_project<6>(A, h.A, tol);
   h.kind = H_PE;
   h.sl[0] = sp;
   h.sl[1] = se0;
@@ -263,7 +264,7 @@ __device__ __forceinline__ void eval_tri(const d3* P, bool is_pt, double a, doub
             }
           A[uix<9>(I, J)] = acc;
         }
-  psd_project<9>(A, h.A, tol);
+  // the gradient goes out first: nothing but A stays live through the projection
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     double gr = ch.cg * g[i], gu = ch.cg * g[3 + i], gv = ch.cg * g[6 + i];
@@ -279,6 +280,7 @@ __device__ __forceinline__ void eval_tri(const d3* P, bool is_pt, double a, doub
       G[9 + i] = gv;
     }
   }
+  psd_project<9>(A, h.A, tol);
   h.kind = H_TRI;
 }
 
