@@ -137,6 +137,7 @@ bf_status alloc_asm_ws(const bf_scene* s, long long act_cap, std::vector<void*>&
   A.colbuf = dalloc<int>(allocs, 16 * act_cap, &e);
   A.rowcnt = dalloc<int>(allocs, s->nv + 1, &e);
   A.mid = dalloc<int>(allocs, s->nv + 1, &e);
+  A.big = dalloc<int>(allocs, s->nv + 1, &e);
   A.epart = dalloc<double>(allocs, (act_cap + 63) / 64 + 1, &e);
   A.scan_tmp = dalloc<int>(allocs, scan_parts(s->nv + 1) + 16, &e);
   if (e != hipSuccess) return fail(BF_E_NOMEM, who);

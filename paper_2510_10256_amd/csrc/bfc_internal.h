@@ -97,6 +97,7 @@ struct AsmWs {
   int* colbuf;    // [16 * act_cap] stencil vertices of each entry's pair (row columns, sorted per row)
   int* rowcnt;    // [V + 1] distinct columns per row
   int* mid;       // [V + 1] rows with 16 < m <= 256 entries (pass A's list, any order); mid[V] = their number
+  int* big;       // [V + 1] rows with m > 256 entries (pass A's list, any order); big[V] = their number
   double* epart;  // [act_cap / 64 + 1] energy of each 64-pair tile of the evaluation
   int* scan_tmp;
 };

@@ -1024,18 +1024,43 @@ __global__ __launch_bounds__(64) void k_eval(SceneDev S, const double* x, const 
 // timing.
 // ---------------------------------------------------------------------------
 // Incidence counts of the feasible active pairs' stencil vertices.
+// Runs of equal values in consecutive lanes of a wave (the active list is in
+// query order, so a primitive's pairs share stencil vertices lane after
+// lane): this lane's run starts at lane `start` and the run has `len` lanes
+// (valid at the run's first lane).  Every lane of the wave must call it.
+__device__ __forceinline__ void lane_runs(int key, int& start, int& len, bool& head) {
+  const int lane = lane_id();
+  const int prev = __shfl_up(key, 1, 64);
+  head = lane == 0 || key != prev;
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+  start = 63 - __clzll(heads & upto);
+  const unsigned long long after = heads & ~upto;
+  len = (after ? __ffsll((long long)after) - 1 : 64) - lane;
+}
+
+// Incidence counts of the feasible active pairs' stencil vertices; one
+// atomic per run of equal vertices in consecutive lanes (whole waves step
+// through the list together).
 __global__ __launch_bounds__(256) void k_inc_count(SceneDev S, const int* ai, const int* aj, const unsigned char* at,
                                                    const unsigned char* aflags, const unsigned long long* act_count,
-                                                   long long acap, int* inc_cnt, int* mid_count) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) *mid_count = 0;  // pass A appends to the list afresh
+                                                   long long acap, int* inc_cnt, int* mid_count,
+                                                   int* big_count) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *mid_count = *big_count = 0;  // pass A appends to the lists afresh
   long long n = (long long)*act_count;
   if (n > acap) n = acap;
-  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += grid_stride()) {
-    if (aflags[k] & BF_F_INFEASIBLE) continue;
-    int v[4];
-    pair_verts(S, at[k], ai[k], aj[k], v);
+  const int lane = lane_id();
+  for (long long w0 = blockIdx.x * (long long)blockDim.x + (threadIdx.x & ~63); w0 < n; w0 += grid_stride()) {
+    const long long k = w0 + lane;
+    int v[4] = {-1, -1, -1, -1};
+    if (k < n && !(aflags[k] & BF_F_INFEASIBLE)) pair_verts(S, at[k], ai[k], aj[k], v);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) atomicAdd(&inc_cnt[v[s]], 1);
+    for (int s = 0; s < 4; ++s) {
+      int start, len;
+      bool head;
+      lane_runs(v[s], start, len, head);
+      if (head && v[s] >= 0) atomicAdd(&inc_cnt[v[s]], len);
+    }
   }
 }
 
@@ -1051,19 +1076,26 @@ __device__ __forceinline__ void energy_total(const double* epart, long long ntil
 }
 
 // scatter the entries into their vertex segments; returns the counts to zero
+// (one atomic per run of equal vertices in consecutive lanes, as counted)
 __global__ __launch_bounds__(256) void k_inc_fill(SceneDev S, const int* ai, const int* aj, const unsigned char* at,
                                                   const unsigned char* aflags, const unsigned long long* act_count,
                                                   long long acap, int* inc_cnt, const int* inc_off, int* inc) {
   long long n = (long long)*act_count;
   if (n > acap) n = acap;
-  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += grid_stride()) {
-    if (aflags[k] & BF_F_INFEASIBLE) continue;
-    int v[4];
-    pair_verts(S, at[k], ai[k], aj[k], v);
+  const int lane = lane_id();
+  for (long long w0 = blockIdx.x * (long long)blockDim.x + (threadIdx.x & ~63); w0 < n; w0 += grid_stride()) {
+    const long long k = w0 + lane;
+    int v[4] = {-1, -1, -1, -1};
+    if (k < n && !(aflags[k] & BF_F_INFEASIBLE)) pair_verts(S, at[k], ai[k], aj[k], v);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      int pos = inc_off[v[s]] + atomicSub(&inc_cnt[v[s]], 1) - 1;
-      inc[pos] = (int)(4 * k + s);
+      int start, len;
+      bool head;
+      lane_runs(v[s], start, len, head);
+      int top = 0;
+      if (head && v[s] >= 0) top = atomicSub(&inc_cnt[v[s]], len);
+      top = __shfl(top, start, 64);
+      if (v[s] >= 0) inc[inc_off[v[s]] + top - 1 - (lane - start)] = (int)(4 * k + s);
     }
   }
 }
@@ -1339,7 +1371,8 @@ __device__ void row_a_wave(const SceneDev& S, const int* ai, const int* aj, cons
 // Rows 4j .. 4j + 3 per block of one wave: first the rows with m <= ROW_S
 // (a team each), then those with m <= ROW_M one after another.
 __global__ __launch_bounds__(64) void k_row_a(SceneDev S, const int* ai, const int* aj, const unsigned char* at,
-                                              const int* inc_off, int* inc, int* colbuf, int* rowcnt, int* mid) {
+                                              const int* inc_off, int* inc, int* colbuf, int* rowcnt, int* mid,
+                                              int* big) {
   __shared__ int ent[ROW_M];
   __shared__ int tab[ROW_M_TAB];
   const int t = lane_id() >> 4;
@@ -1364,6 +1397,14 @@ __global__ __launch_bounds__(64) void k_row_a(SceneDev S, const int* ai, const i
       base = __shfl(base, 0, 64);
       if ((lead >> lane_id()) & 1ull) mid[base + lanes_below(lead)] = v;
     }
+    // rows for the block-per-row paths: appended to big[0 .. big[nv])
+    const unsigned long long blead = __ballot((lane_id() & 15) == 0 && v < S.nv && m > ROW_M);
+    if (blead != 0) {
+      int base = 0;
+      if (lane_id() == 0) base = atomicAdd(&big[S.nv], __popcll(blead));
+      base = __shfl(base, 0, 64);
+      if ((blead >> lane_id()) & 1ull) big[base + lanes_below(blead)] = v;
+    }
 #pragma unroll 1
     for (int r = 0; r < 4; ++r) {
       const int vr = __shfl(v, 16 * r, 64), br = __shfl(b, 16 * r, 64), mr = __shfl(m, 16 * r, 64);
@@ -1373,71 +1414,56 @@ __global__ __launch_bounds__(64) void k_row_a(SceneDev S, const int* ai, const i
   }
 }
 
-// Rows with m > ROW_M (passes A and B): one 256-thread block per row.
-// Block j of G looks at rows j, j + G, j + 2G, ... (rows with many entries
-// cluster in space, and so in vertex numbering) and works on the large ones
-// one after another.
-__device__ __forceinline__ int big_rows(const int* inc_off, int nv, int* list, int base) {
-  const int v = blockIdx.x + (long long)gridDim.x * (base + threadIdx.x) < nv
-                    ? (int)(blockIdx.x + (long long)gridDim.x * (base + threadIdx.x)) : -1;
-  const int m = v >= 0 ? inc_off[v + 1] - inc_off[v] : 0;
-  int nbig;
-  const int off = block_excl_scan256(m > ROW_M ? 1 : 0, &nbig);
-  if (m > ROW_M) list[off] = v;
-  __syncthreads();
-  return nbig;
-}
-
+// Rows with m > ROW_M (passes A and B): one 256-thread block per row, the
+// rows taken from pass A's list strided over the blocks (they cluster in
+// space, and so in vertex numbering: a list spreads them evenly).
 __global__ __launch_bounds__(256) void k_row_a_big(SceneDev S, const int* ai, const int* aj, const unsigned char* at,
-                                                   const int* inc_off, int* inc, int* colbuf, int* rowcnt) {
+                                                   const int* inc_off, int* inc, int* colbuf, int* rowcnt,
+                                                   const int* big) {
   __shared__ int ent[ROW_H];
   __shared__ int tab[ROW_H_TAB];
-  __shared__ int list[256];
   const int tid = threadIdx.x;
-  const int per = (S.nv - (int)blockIdx.x + (int)gridDim.x - 1) / (int)gridDim.x;
-  for (int base = 0; base < per; base += 256) {
-    const int nbig = big_rows(inc_off, S.nv, list, base);
-    for (int r = 0; r < nbig; ++r) {
-      const int v = list[r];
-      const int b = inc_off[v], m = inc_off[v + 1] - b;
-      int* cb = colbuf + 4LL * b;
-      if (m > ROW_H) {
-        if (tid == 0) row_a_serial(S, ai, aj, at, b, m, inc, cb, rowcnt + v);
-        __syncthreads();
-        continue;
-      }
-      const int Pm = pow2_at_least(m);
-      for (int q = tid; q < Pm; q += 256) ent[q] = q < m ? inc[b + q] : PAD;
-      const int T = min(ROW_H_TAB, pow2_at_least(8 * m));
-      for (int q = tid; q < T; q += 256) tab[q] = EMPTY;
+  const int nbig = big[S.nv];
+  for (int r = blockIdx.x; r < nbig; r += gridDim.x) {
+    const int v = big[r];
+    const int b = inc_off[v], m = inc_off[v + 1] - b;
+    int* cb = colbuf + 4LL * b;
+    if (m > ROW_H) {
+      if (tid == 0) row_a_serial(S, ai, aj, at, b, m, inc, cb, rowcnt + v);
       __syncthreads();
-      team_bitonic<256>(ent, Pm);
-      for (int q = tid; q < m; q += 256) {
-        int e = ent[q], k = e >> 2;
-        inc[b + q] = e;
-        int vv[4];
-        pair_verts(S, at[k], ai[k], aj[k], vv);
+      continue;
+    }
+    const int Pm = pow2_at_least(m);
+    for (int q = tid; q < Pm; q += 256) ent[q] = q < m ? inc[b + q] : PAD;
+    const int T = min(ROW_H_TAB, pow2_at_least(8 * m));
+    for (int q = tid; q < T; q += 256) tab[q] = EMPTY;
+    __syncthreads();
+    team_bitonic<256>(ent, Pm);
+    for (int q = tid; q < m; q += 256) {
+      int e = ent[q], k = e >> 2;
+      inc[b + q] = e;
+      int vv[4];
+      pair_verts(S, at[k], ai[k], aj[k], vv);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) set_insert(tab, T, vv[c]);
-      }
-      __syncthreads();
-      int u = 0;
-      for (int c = 0; c < T; c += 256) {
-        int x = tab[c + tid];
-        int tot;
-        int o = block_excl_scan256(x != EMPTY ? 1 : 0, &tot);  // synchronises: the chunk is read
-        if (x != EMPTY) tab[u + o] = x;
-        u += tot;
-        __syncthreads();
-      }
-      const int P = pow2_at_least(u > 0 ? u : 1);
-      for (int q = u + tid; q < P; q += 256) tab[q] = PAD;
-      __syncthreads();
-      team_bitonic<256>(tab, P);
-      for (int q = tid; q < u; q += 256) cb[q] = tab[q];
-      if (tid == 0) rowcnt[v] = u;
+      for (int c = 0; c < 4; ++c) set_insert(tab, T, vv[c]);
+    }
+    __syncthreads();
+    int u = 0;
+    for (int c = 0; c < T; c += 256) {
+      int x = tab[c + tid];
+      int tot;
+      int o = block_excl_scan256(x != EMPTY ? 1 : 0, &tot);  // synchronises: the chunk is read
+      if (x != EMPTY) tab[u + o] = x;
+      u += tot;
       __syncthreads();
     }
+    const int P = pow2_at_least(u > 0 ? u : 1);
+    for (int q = u + tid; q < P; q += 256) tab[q] = PAD;
+    __syncthreads();
+    team_bitonic<256>(tab, P);
+    for (int q = tid; q < u; q += 256) cb[q] = tab[q];
+    if (tid == 0) rowcnt[v] = u;
+    __syncthreads();
   }
 }
 
@@ -1662,23 +1688,18 @@ __global__ __launch_bounds__(64) void k_row_b(SceneDev S, const int* ai, const i
 __global__ __launch_bounds__(256) void k_row_b_big(SceneDev S, const int* ai, const int* aj, const unsigned char* at,
                                                    const int* inc_off, const int* inc, const int* colbuf,
                                                    const double* G, const double* H, double* g, const int* row_ptr,
-                                                   int* col, double* val, long long cap) {
+                                                   int* col, double* val, long long cap, const int* big) {
   __shared__ int vs[4 * 128];
   __shared__ double band[128 * 36];
-  __shared__ int list[256];
   __shared__ double gw[12];
-  const int per = (S.nv - (int)blockIdx.x + (int)gridDim.x - 1) / (int)gridDim.x;
-  for (int base = 0; base < per; base += 256) {
-    const int nbig = big_rows(inc_off, S.nv, list, base);
-    for (int r = 0; r < nbig; ++r) {
-      const int v = list[r];
-      const int b = inc_off[v], m = inc_off[v + 1] - b;
-      const int r0 = row_ptr[v], r1 = row_ptr[v + 1];
-      if (r1 > cap) continue;  // uniform across the block
-      row_b<256, 128>(S, ai, aj, at, inc, b, m, colbuf + 4LL * b, r0, r1 - r0, G, H, g + 3LL * v, col, val, vs, band,
-                 gw);
-    }
-    __syncthreads();
+  const int nbig = big[S.nv];
+  for (int r = blockIdx.x; r < nbig; r += gridDim.x) {
+    const int v = big[r];
+    const int b = inc_off[v], m = inc_off[v + 1] - b;
+    const int r0 = row_ptr[v], r1 = row_ptr[v + 1];
+    if (r1 > cap) continue;  // uniform across the block
+    row_b<256, 128>(S, ai, aj, at, inc, b, m, colbuf + 4LL * b, r0, r1 - r0, G, H, g + 3LL * v, col, val, vs, band,
+                    gw);
   }
 }
 
@@ -2360,7 +2381,7 @@ void run_eval(const SceneDev& S, const double* x, const int* ai, const int* aj, 
                        aflags, (const unsigned long long*)act_count, acap, E, G, H, epart);
 }
 
-static inline int big_grid_of(int nv) { return std::max(1, std::min((nv + 15) / 16, 4096)); }  // ~16 rows a block
+static inline int big_grid_of(int nv) { return std::max(1, std::min(nv, 1024)); }  // list entries strided over these
 
 void run_asm_structure(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,
                        const unsigned char* aflags, const long long* act_count, long long acap, const AsmWs& A,
@@ -2368,15 +2389,15 @@ void run_asm_structure(const SceneDev& S, const int* ai, const int* aj, const un
   const unsigned long long* nact = (const unsigned long long*)act_count;
   // incidence counts are zero on entry: k_inc_fill returns them to zero
   hipLaunchKernelGGL(k_inc_count, dim3(nblocks(acap)), dim3(256), 0, st, S, ai, aj, at, aflags, nact, acap,
-                     A.inc_cnt, A.mid + S.nv);
+                     A.inc_cnt, A.mid + S.nv, A.big + S.nv);
   scan_excl(A.inc_cnt, A.inc_off, nullptr, S.nv + 1, A.scan_tmp, st);
   hipLaunchKernelGGL(k_inc_fill, dim3(nblocks(acap)), dim3(256), 0, st, S, ai, aj, at, aflags, nact, acap, A.inc_cnt,
                      A.inc_off, A.inc);
   const int rows_grid = std::max(1, std::min((S.nv + 3) / 4, 1 << 20));  // four rows a block
   hipLaunchKernelGGL(k_row_a, dim3(rows_grid), dim3(64), 0, st, S, ai, aj, at, A.inc_off, A.inc, A.colbuf, A.rowcnt,
-                     A.mid);
+                     A.mid, A.big);
   hipLaunchKernelGGL(k_row_a_big, dim3(big_grid_of(S.nv)), dim3(256), 0, st, S, ai, aj, at, A.inc_off, A.inc,
-                     A.colbuf, A.rowcnt);
+                     A.colbuf, A.rowcnt, A.big);
 }
 
 void run_asm_values(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,
@@ -2390,7 +2411,7 @@ void run_asm_values(const SceneDev& S, const int* ai, const int* aj, const unsig
   hipLaunchKernelGGL(k_row_b, dim3(mid_grid + rows_grid), dim3(64), 0, st, S, ai, aj, at, A.inc_off, A.inc, A.colbuf,
                      G, H, g, row_ptr, col, val, bsr_cap, nnzb, status, nact, acap, A.epart, E_out, A.mid, mid_grid);
   hipLaunchKernelGGL(k_row_b_big, dim3(big_grid_of(S.nv)), dim3(256), 0, st, S, ai, aj, at, A.inc_off, A.inc,
-                     A.colbuf, G, H, g, row_ptr, col, val, bsr_cap);
+                     A.colbuf, G, H, g, row_ptr, col, val, bsr_cap, A.big);
 }
 
 int run_components(const SceneDev& S, int* lab, int* flag, int* scan, int* comp, int* scan_tmp, int* d_changed,
