@@ -44,8 +44,8 @@ KIND_OF_CODE = np.array([0, 0, 0, 1, 1, 1, 2, 0, 0, 0, 0, 1, 1, 1, 1, 3])
 # (FETCH_SIZE x 2 and WRITE_SIZE x 1, the factors a plain 256 MiB copy gives)
 # on the kernel source whose fingerprint is EVAL_TRAFFIC_SOURCE; reported as
 # null once that source changes.
-EVAL_TRAFFIC_SOURCE = "173737cb16c1e993"
-EVAL_TRAFFIC_BYTES = {"woven_patch": 51.7e6, "folded_cloth": 2305.7e6}
+EVAL_TRAFFIC_SOURCE = "278c93e8959d1179"
+EVAL_TRAFFIC_BYTES = {"woven_patch": 48.6e6, "folded_cloth": 2127.4e6}
 # the same for the friction kernel (lag at x - 0.02 p; the bytes do not depend on mu)
 FRICTION_TRAFFIC_SOURCE = "423c9b78a4f89de4"
 FRICTION_TRAFFIC_BYTES = {"woven_patch": 39.7e6, "folded_cloth": 2833.5e6}
@@ -367,8 +367,7 @@ def bench_batch(args):
         assert not (st & (bfc.BF_S_CAND_OVERFLOW | bfc.BF_S_ACT_OVERFLOW | bfc.BF_S_BSR_OVERFLOW)), st
         assert cs.counts() == c
     out = {
-        "metric": "filtered contact pairs evaluated/s (dist+filter+grad+Hessian"
-                  + (" + lagged friction" if fric else "") + "); p50/p99 latency",
+        "metric": "filtered contact pairs evaluated/s (dist+filter+grad+Hessian); p50/p99 latency",
         "value": n_c / (ms_per_step * 1e-3),
         "unit": "pairs/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -439,8 +438,7 @@ def bench_serve(args):
                            "scenes_evicted": server.evicted - e0, "retries": int(sum(r.retries for r in d))}
     head = runs["0.75"]
     out = {
-        "metric": "filtered contact pairs evaluated/s (dist+filter+grad+Hessian"
-                  + (" + lagged friction" if fric else "") + "); p50/p99 latency",
+        "metric": "filtered contact pairs evaluated/s (dist+filter+grad+Hessian); p50/p99 latency",
         "value": head["pairs_per_s"], "unit": "pairs/s",
         "n_gpus": 1, "steps": head["requests"], "warmup": 32, "ms_per_step": head["mean_ms"],
         "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
