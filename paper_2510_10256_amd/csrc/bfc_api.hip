@@ -135,6 +135,7 @@ bf_status alloc_asm_ws(const bf_scene* s, long long act_cap, std::vector<void*>&
   A.inc_off = dalloc<int>(allocs, s->nv + 1, &e);
   A.inc = dalloc<int>(allocs, 4 * act_cap, &e);
   A.colbuf = dalloc<int>(allocs, 16 * act_cap, &e);
+  A.stn = dalloc<int4>(allocs, 4 * act_cap, &e);
   A.rowcnt = dalloc<int>(allocs, s->nv + 1, &e);
   A.mid = dalloc<int>(allocs, s->nv + 1, &e);
   A.big = dalloc<int>(allocs, s->nv + 1, &e);

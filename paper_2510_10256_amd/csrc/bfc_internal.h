@@ -95,6 +95,7 @@ struct AsmWs {
   int* inc_off;   // [V + 1] their exclusive scan
   int* inc;       // [4 * act_cap] entries 4k + s grouped by vertex
   int* colbuf;    // [16 * act_cap] stencil vertices of each entry's pair (row columns, sorted per row)
+  int4* stn;      // [4 * act_cap] stencil of each incidence entry's pair, in the row's sorted entry order
   int* rowcnt;    // [V + 1] distinct columns per row
   int* mid;       // [V + 1] rows with 16 < m <= 256 entries (pass A's list, any order); mid[V] = their number
   int* big;       // [V + 1] rows with m > 256 entries (pass A's list, any order); big[V] = their number

@@ -1240,12 +1240,13 @@ __device__ void isort_global(int* a, int m) {
 // One lane, global memory: sort the entries and store the distinct sorted
 // columns; *count = their number.
 __device__ void row_a_serial(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at, int b, int m,
-                             int* inc, int* cb, int* count) {
+                             int* inc, int* cb, int* count, int4* stn) {
   isort_global(inc + b, m);
   for (int q = 0; q < m; ++q) {
     int k = inc[b + q] >> 2;
     int vv[4];
     pair_verts(S, at[k], ai[k], aj[k], vv);
+    stn[b + q] = make_int4(vv[0], vv[1], vv[2], vv[3]);
     for (int c = 0; c < 4; ++c) cb[4 * q + c] = vv[c];
   }
   isort_global(cb, 4 * m);
@@ -1265,7 +1266,8 @@ __device__ void row_a_serial(const SceneDev& S, const int* ai, const int* aj, co
 // false on teams without such a row (their lanes take part in the
 // shuffles with padding only).
 __device__ __forceinline__ void row_a_team(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,
-                                           bool mine, int v, int b, int m, int* inc, int* colbuf, int* rowcnt) {
+                                           bool mine, int v, int b, int m, int* inc, int* colbuf, int* rowcnt,
+                                           int4* stn) {
   const int tl = lane_id() & 15;
   int e = mine && tl < m ? inc[b + tl] : PAD;
   e = team_sort16(e);
@@ -1274,6 +1276,7 @@ __device__ __forceinline__ void row_a_team(const SceneDev& S, const int* ai, con
     inc[b + tl] = e;
     const int k = e >> 2;
     pair_verts(S, at[k], ai[k], aj[k], vv);
+    stn[b + tl] = make_int4(vv[0], vv[1], vv[2], vv[3]);
   }
   const int t4 = tl & 3;
   int c[4];
@@ -1302,7 +1305,7 @@ __device__ __forceinline__ void row_a_team(const SceneDev& S, const int* ai, con
 
 // One row with ROW_S < m <= ROW_M by the whole wave (a block of one wave).
 __device__ void row_a_wave(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at, int v, int b,
-                           int m, int* inc, int* colbuf, int* rowcnt, int* ent, int* tab) {
+                           int m, int* inc, int* colbuf, int* rowcnt, int* ent, int* tab, int4* stn) {
   const int lane = threadIdx.x;
   int* cb = colbuf + 4LL * b;
   if (m <= ROW_L) {
@@ -1315,6 +1318,7 @@ __device__ void row_a_wave(const SceneDev& S, const int* ai, const int* aj, cons
       inc[b + lane] = e;
       const int k = e >> 2;
       pair_verts(S, at[k], ai[k], aj[k], vv);
+      stn[b + lane] = make_int4(vv[0], vv[1], vv[2], vv[3]);
     }
     const int t = lane & 3, q0 = lane >> 2, q1 = 16 + (lane >> 2);
     int w0 = __shfl(vv[0], q0, 64), w1 = __shfl(vv[1], q0, 64), w2 = __shfl(vv[2], q0, 64),
@@ -1347,6 +1351,7 @@ __device__ void row_a_wave(const SceneDev& S, const int* ai, const int* aj, cons
     inc[b + q] = e;
     int vv[4];
     pair_verts(S, at[k], ai[k], aj[k], vv);
+    stn[b + q] = make_int4(vv[0], vv[1], vv[2], vv[3]);
 #pragma unroll
     for (int c = 0; c < 4; ++c) set_insert(tab, T, vv[c]);
   }
@@ -1372,7 +1377,7 @@ __device__ void row_a_wave(const SceneDev& S, const int* ai, const int* aj, cons
 // (a team each), then those with m <= ROW_M one after another.
 __global__ __launch_bounds__(64) void k_row_a(SceneDev S, const int* ai, const int* aj, const unsigned char* at,
                                               const int* inc_off, int* inc, int* colbuf, int* rowcnt, int* mid,
-                                              int* big) {
+                                              int* big, int4* stn) {
   __shared__ int ent[ROW_M];
   __shared__ int tab[ROW_M_TAB];
   const int t = lane_id() >> 4;
@@ -1387,7 +1392,7 @@ __global__ __launch_bounds__(64) void k_row_a(SceneDev S, const int* ai, const i
     if (__all(!small || m == 0)) {  // nothing to sort in this group
       if (small && (lane_id() & 15) == 0) rowcnt[v] = 0;
     } else {
-      row_a_team(S, ai, aj, at, small, v, b, m, inc, colbuf, rowcnt);
+      row_a_team(S, ai, aj, at, small, v, b, m, inc, colbuf, rowcnt, stn);
     }
     // rows for the one-wave path of pass B: appended to mid[0 .. mid[nv]) (any order)
     const unsigned long long lead = __ballot((lane_id() & 15) == 0 && v < S.nv && m > ROW_S && m <= ROW_M);
@@ -1409,7 +1414,7 @@ __global__ __launch_bounds__(64) void k_row_a(SceneDev S, const int* ai, const i
     for (int r = 0; r < 4; ++r) {
       const int vr = __shfl(v, 16 * r, 64), br = __shfl(b, 16 * r, 64), mr = __shfl(m, 16 * r, 64);
       if (vr >= S.nv || mr <= ROW_S || mr > ROW_M) continue;  // uniform over the wave
-      row_a_wave(S, ai, aj, at, vr, br, mr, inc, colbuf, rowcnt, ent, tab);
+      row_a_wave(S, ai, aj, at, vr, br, mr, inc, colbuf, rowcnt, ent, tab, stn);
     }
   }
 }
@@ -1419,7 +1424,7 @@ __global__ __launch_bounds__(64) void k_row_a(SceneDev S, const int* ai, const i
 // space, and so in vertex numbering: a list spreads them evenly).
 __global__ __launch_bounds__(256) void k_row_a_big(SceneDev S, const int* ai, const int* aj, const unsigned char* at,
                                                    const int* inc_off, int* inc, int* colbuf, int* rowcnt,
-                                                   const int* big) {
+                                                   const int* big, int4* stn) {
   __shared__ int ent[ROW_H];
   __shared__ int tab[ROW_H_TAB];
   const int tid = threadIdx.x;
@@ -1429,7 +1434,7 @@ __global__ __launch_bounds__(256) void k_row_a_big(SceneDev S, const int* ai, co
     const int b = inc_off[v], m = inc_off[v + 1] - b;
     int* cb = colbuf + 4LL * b;
     if (m > ROW_H) {
-      if (tid == 0) row_a_serial(S, ai, aj, at, b, m, inc, cb, rowcnt + v);
+      if (tid == 0) row_a_serial(S, ai, aj, at, b, m, inc, cb, rowcnt + v, stn);
       __syncthreads();
       continue;
     }
@@ -1444,6 +1449,7 @@ __global__ __launch_bounds__(256) void k_row_a_big(SceneDev S, const int* ai, co
       inc[b + q] = e;
       int vv[4];
       pair_verts(S, at[k], ai[k], aj[k], vv);
+      stn[b + q] = make_int4(vv[0], vv[1], vv[2], vv[3]);
 #pragma unroll
       for (int c = 0; c < 4; ++c) set_insert(tab, T, vv[c]);
     }
@@ -1482,7 +1488,7 @@ template <int NT, int CH>
 __device__ __forceinline__ void row_b(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,
                                       const int* inc, int b, int m, const int* cb, int r0, int u, const double* G,
                                       const double* H, double* grow, int* col, double* val, int* vs, double* band,
-                                      double* gw) {
+                                      double* gw, const int4* stn) {
   constexpr int TPE = NT / CH, PART = 36 / TPE;  // threads per entry, doubles per thread
   static_assert(TPE * PART == 36, "band split");
   const int tid = threadIdx.x, lane = lane_id();
@@ -1503,10 +1509,11 @@ __device__ __forceinline__ void row_b(const SceneDev& S, const int* ai, const in
 #pragma unroll
         for (int o = 0; o < PART; ++o) dst[o] = src[o];
         if (part == 0) {
-          int vv[4];
-          pair_verts(S, at[k], ai[k], aj[k], vv);
-#pragma unroll
-          for (int c = 0; c < 4; ++c) vs[4 * q + c] = vv[c];
+          const int4 w4 = stn[b + qc + q];
+          vs[4 * q] = w4.x;
+          vs[4 * q + 1] = w4.y;
+          vs[4 * q + 2] = w4.z;
+          vs[4 * q + 3] = w4.w;
           if (cbase == 0) {
             const double* gk = G + 12LL * k + 3 * (e & 3);
             gx = gk[0]; gy = gk[1]; gz = gk[2];
@@ -1569,7 +1576,7 @@ constexpr int TEAM_CH = 4;  // entries per chunk and team
 __device__ __forceinline__ void row_b_team(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,
                                            bool mine, const int* inc, int b, int m, const int* cb, int r0, int u,
                                            const double* G, const double* H, double* grow, int* col, double* val,
-                                           int* vs, double* band) {
+                                           int* vs, double* band, const int4* stn) {
   const int lane = lane_id(), tl = lane & 15;
   int* vst = vs + 4 * ROW_S * (lane >> 4);
   double* bt = band + 36 * TEAM_CH * (lane >> 4);
@@ -1579,7 +1586,8 @@ __device__ __forceinline__ void row_b_team(const SceneDev& S, const int* ai, con
   if (tl < m) {
     e = inc[b + tl];
     const int k = e >> 2;
-    pair_verts(S, at[k], ai[k], aj[k], vv);
+    const int4 w4 = stn[b + tl];
+    vv[0] = w4.x; vv[1] = w4.y; vv[2] = w4.z; vv[3] = w4.w;
     const double* gk = G + 12LL * k + 3 * (e & 3);
     gx = gk[0]; gy = gk[1]; gz = gk[2];
   }
@@ -1637,7 +1645,8 @@ __global__ __launch_bounds__(64) void k_row_b(SceneDev S, const int* ai, const i
                                               const double* H, double* g, const int* row_ptr, int* col, double* val,
                                               long long cap, long long* nnzb, unsigned* status,
                                               const unsigned long long* act_count, long long acap,
-                                              const double* epart, double* E_out, const int* mid, int nmid_blocks) {
+                                              const double* epart, double* E_out, const int* mid, int nmid_blocks,
+                                              const int4* stn) {
   // shared by both paths: 4 teams x ROW_S stencils / 16 entries' stencils,
   // 4 teams x TEAM_CH bands / 16 bands
   __shared__ int vs[4 * 4 * ROW_S];
@@ -1662,7 +1671,7 @@ __global__ __launch_bounds__(64) void k_row_b(SceneDev S, const int* ai, const i
       const int r0 = row_ptr[v], r1 = row_ptr[v + 1];
       if (r1 > cap) continue;  // overflow: reported by block 0
       row_b<64, 16>(S, ai, aj, at, inc, b, m, colbuf + 4LL * b, r0, r1 - r0, G, H, g + 3LL * v, col, val, vs, band,
-                    nullptr);
+                    nullptr, stn);
     }
     return;
   }
@@ -1681,14 +1690,15 @@ __global__ __launch_bounds__(64) void k_row_b(SceneDev S, const int* ai, const i
     // columns are stored only when the row fits the output (overflow is reported above)
     const int u = small && r1 <= cap ? r1 - r0 : 0;
     row_b_team(S, ai, aj, at, small, inc, b, small ? m : 0, colbuf + 4LL * b, r0, u, G, H, g + 3LL * v, col, val, vs,
-               band);
+               band, stn);
   }
 }
 
 __global__ __launch_bounds__(256) void k_row_b_big(SceneDev S, const int* ai, const int* aj, const unsigned char* at,
                                                    const int* inc_off, const int* inc, const int* colbuf,
                                                    const double* G, const double* H, double* g, const int* row_ptr,
-                                                   int* col, double* val, long long cap, const int* big) {
+                                                   int* col, double* val, long long cap, const int* big,
+                                                   const int4* stn) {
   __shared__ int vs[4 * 128];
   __shared__ double band[128 * 36];
   __shared__ double gw[12];
@@ -1699,7 +1709,7 @@ __global__ __launch_bounds__(256) void k_row_b_big(SceneDev S, const int* ai, co
     const int r0 = row_ptr[v], r1 = row_ptr[v + 1];
     if (r1 > cap) continue;  // uniform across the block
     row_b<256, 128>(S, ai, aj, at, inc, b, m, colbuf + 4LL * b, r0, r1 - r0, G, H, g + 3LL * v, col, val, vs, band,
-                    gw);
+                    gw, stn);
   }
 }
 
@@ -2395,9 +2405,9 @@ void run_asm_structure(const SceneDev& S, const int* ai, const int* aj, const un
                      A.inc_off, A.inc);
   const int rows_grid = std::max(1, std::min((S.nv + 3) / 4, 1 << 20));  // four rows a block
   hipLaunchKernelGGL(k_row_a, dim3(rows_grid), dim3(64), 0, st, S, ai, aj, at, A.inc_off, A.inc, A.colbuf, A.rowcnt,
-                     A.mid, A.big);
+                     A.mid, A.big, A.stn);
   hipLaunchKernelGGL(k_row_a_big, dim3(big_grid_of(S.nv)), dim3(256), 0, st, S, ai, aj, at, A.inc_off, A.inc,
-                     A.colbuf, A.rowcnt, A.big);
+                     A.colbuf, A.rowcnt, A.big, A.stn);
 }
 
 void run_asm_values(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,
@@ -2409,9 +2419,10 @@ void run_asm_values(const SceneDev& S, const int* ai, const int* aj, const unsig
   const int rows_grid = std::max(1, std::min((S.nv + 3) / 4, 1 << 20));  // four rows a block
   const int mid_grid = std::min(rows_grid, 8192);                          // listed rows, strided
   hipLaunchKernelGGL(k_row_b, dim3(mid_grid + rows_grid), dim3(64), 0, st, S, ai, aj, at, A.inc_off, A.inc, A.colbuf,
-                     G, H, g, row_ptr, col, val, bsr_cap, nnzb, status, nact, acap, A.epart, E_out, A.mid, mid_grid);
+                     G, H, g, row_ptr, col, val, bsr_cap, nnzb, status, nact, acap, A.epart, E_out, A.mid, mid_grid,
+                     A.stn);
   hipLaunchKernelGGL(k_row_b_big, dim3(big_grid_of(S.nv)), dim3(256), 0, st, S, ai, aj, at, A.inc_off, A.inc,
-                     A.colbuf, G, H, g, row_ptr, col, val, bsr_cap, A.big);
+                     A.colbuf, G, H, g, row_ptr, col, val, bsr_cap, A.big, A.stn);
 }
 
 int run_components(const SceneDev& S, int* lab, int* flag, int* scan, int* comp, int* scan_tmp, int* d_changed,
