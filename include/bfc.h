@@ -131,7 +131,8 @@ typedef struct {
 typedef struct {
   double* E_d;  /* [cap] kappa * b (+inf for infeasible pairs) */
   double* G_d;  /* [cap,12] gradient */
-  double* H_d;  /* [cap,144] projected 12 x 12 Hessian, row-major */
+  double* H_d;  /* [cap,144] projected 12 x 12 Hessian, row-major; 16-byte aligned for eval_barrier
+                   (device allocations are) */
   int64_t cap;
 } bf_local;
 
@@ -191,7 +192,7 @@ bf_status filter_pairs(bf_scene* s, const double* x_d, const bf_pairs* cand, bf_
  * is being captured into a graph there is no fork: assemble_grad_hess then
  * builds the structure itself. */
 bf_status eval_barrier(bf_scene* s, const double* x_d, const bf_active* act, bf_local* out,
-                       void* stream);
+                       void* stream);  /* BF_E_ARG if out->H_d is not 16-byte aligned */
 
 /* Assembly: E_d[1] = sum of pair energies (+inf if any pair is infeasible),
  * g_d[V,3] = sum of pair gradients, H = sum of pair Hessian blocks over the

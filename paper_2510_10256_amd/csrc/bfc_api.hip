@@ -677,6 +677,7 @@ bf_status eval_barrier(bf_scene* s, const double* x_d, const bf_active* act, bf_
   if (!s || !x_d || !act || !out || !out->E_d || !out->G_d || !out->H_d || !act->p.count_d)
     return fail(BF_E_ARG, "eval_barrier: null argument");
   if (out->cap < act->p.cap) return fail(BF_E_CAPACITY, "eval_barrier: local capacity below active capacity");
+  if ((reinterpret_cast<uintptr_t>(out->H_d) & 15u) != 0) return fail(BF_E_ARG, "eval_barrier: H_d not 16-byte aligned");
   hipStream_t st = (hipStream_t)stream;
   s->last = st;
   const SceneDev S = dev_view(s);

@@ -952,9 +952,11 @@ __global__ __launch_bounds__(256) void k_compact(StageWs W, int G, int* ai, int*
 // One wave per work-group, one pair per lane.  Each lane keeps its pair's
 // projected Hessian in reduced form (registers); the 12 rows of the 12 x 12
 // matrices of the tile's 64 pairs then go out one row at a time through a
-// small LDS buffer, as contiguous 96-byte segments (a 64 x 144 staging tile
-// would cut occupancy to three waves per CU; stores straight from each
-// lane's registers scatter every instruction over 64 cache lines).  The
+// small LDS buffer, as contiguous 96-byte segments written 16 bytes a lane
+// (a 64 x 144 staging tile would cut occupancy to three waves per CU; stores
+// straight from each lane's registers scatter every instruction over 64
+// cache lines; two rows a pass, or a fallback for unaligned H, raise the
+// register pressure of the whole kernel).  The
 // energies of each 64-pair tile are summed in a fixed order into epart
 // (partials of the total).
 template <int I>
@@ -966,9 +968,9 @@ __device__ __forceinline__ void flush_row(const PairOut& h, double* buf, double*
   for (int j = 0; j < 12; ++j) buf[13 * lane + j] = r[j];
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < 12; ++q) {
-    const int v = lane + 64 * q, p = v / 12, j = v - 12 * p;
-    if (p < rows) H[144 * (k0 + p) + 12 * I + j] = buf[13 * p + j];
+  for (int q = 0; q < 6; ++q) {  // two doubles a store (H is 16-byte aligned, rows are 96 bytes)
+    const int v = lane + 64 * q, p = v / 6, c = v - 6 * p;
+    if (p < rows) *(double2*)(H + 144 * (k0 + p) + 12 * I + 2 * c) = make_double2(buf[13 * p + 2 * c], buf[13 * p + 2 * c + 1]);
   }
   __syncthreads();
 }

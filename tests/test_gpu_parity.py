@@ -150,3 +150,22 @@ def test_full_cloth_parity(prec):
     for (r, c), b in list(key.items())[:20000]:
         assert np.allclose(key[(c, r)].T, b, rtol=0, atol=1e-9 * np.abs(b).max() + 1e-300)
     print(g["counts"], "H worst ratio", worst, flush=True)
+
+
+@requires_gpu
+def test_unaligned_hessian_buffer_is_refused():
+    # eval_barrier writes H two doubles at a time: a buffer off 16-byte
+    # alignment is refused on the host (no kernel runs)
+    import ctypes as C
+    import paper_2510_10256_amd as bfc
+    from paper_2510_10256_amd import binding as B
+    sc = SMALL["yarn"]()
+    cs = bfc.ContactScene(sc, device=torch.device("cuda:0"))
+    x = torch.tensor(sc.x, dtype=torch.float64, device="cuda:0")
+    cs.run(x)
+    Hx = torch.zeros(cs.act_cap * 144 + 1, dtype=torch.float64, device="cuda:0")
+    loc = B.Local(cs.l_E.data_ptr(), cs.l_G.data_ptr(), Hx.data_ptr() + 8, cs.act_cap)
+    rc = B.lib().eval_barrier(cs.handle, B._ptr(x), C.byref(cs._act), C.byref(loc), C.c_void_p(cs._stream()))
+    assert rc == 1  # BF_E_ARG
+    torch.cuda.synchronize()
+    cs.close()
