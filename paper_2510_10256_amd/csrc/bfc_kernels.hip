@@ -1176,13 +1176,26 @@ __device__ __forceinline__ void wave_sort128(int& a0, int& a1) {
 // Sorts inside the 16-lane teams of a wave (team t = lanes 16t..16t+15):
 // 16 values (one per lane) and 64 values (element i in lane i & 15,
 // register i >> 4).
+// Value of lane (this lane xor j) within the lane's row of 16, j = 1, 2, 4
+// or 8, by DPP moves instead of an LDS permute: quad permutations give xor 1,
+// 2 and 3, the row's half mirror xor 7 and its mirror xor 15, so xor 4 =
+// 7 ^ 3 and xor 8 = 15 ^ 7 take two moves.  j must fold to a constant.
+__device__ __forceinline__ int team_xor(int x, int j) {
+  if (j == 1) return __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  if (j == 2) return __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+  if (j == 4)  // row_half_mirror, then quad_perm [3,2,1,0]
+    return __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, false), 0x1B, 0xF, 0xF, false);
+  // row_mirror, then row_half_mirror
+  return __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(x, 0x140, 0xF, 0xF, false), 0x141, 0xF, 0xF, false);
+}
+
 __device__ __forceinline__ int team_sort16(int x) {
   const int tl = lane_id() & 15;
 #pragma unroll
   for (int k = 2; k <= 16; k <<= 1)
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
-      int y = __shfl_xor(x, j, 16);
+      int y = team_xor(x, j);
       bool keep_min = ((tl & j) == 0) == ((tl & k) == 0);
       x = keep_min ? min(x, y) : max(x, y);
     }
@@ -1208,7 +1221,7 @@ __device__ __forceinline__ void team_sort64(int (&a)[4]) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = 16 * r + tl;
-          const int y = __shfl_xor(a[r], j, 16);
+          const int y = team_xor(a[r], j);
           const bool keep_min = ((i & j) == 0) == ((i & k) == 0);
           a[r] = keep_min ? min(a[r], y) : max(a[r], y);
         }
