@@ -1662,11 +1662,12 @@ __global__ __launch_bounds__(64) void k_row_b(SceneDev S, const int* ai, const i
                                               const unsigned long long* act_count, long long acap,
                                               const double* epart, double* E_out, const int* mid, int nmid_blocks,
                                               const int4* stn) {
-  // shared by both paths: 4 teams x ROW_S stencils / 16 entries' stencils,
-  // 4 teams x TEAM_CH bands / 16 bands
+  // shared by both paths: 4 teams x ROW_S stencils / 32 entries' stencils,
+  // 4 teams x TEAM_CH bands / 32 bands (a listed row's entries 32 at a time:
+  // fewer dependent rounds of band loads than 16, and 64 take too much LDS)
   __shared__ int vs[4 * 4 * ROW_S];
-  __shared__ double band[16 * 36];
-  static_assert(4 * TEAM_CH <= 16, "team bands fit the shared band buffer");
+  __shared__ double band[32 * 36];
+  static_assert(4 * TEAM_CH <= 32, "team bands fit the shared band buffer");
   if (blockIdx.x == 0) {
     if (threadIdx.x == 0) {
       const long long t = row_ptr[S.nv];
@@ -1685,7 +1686,7 @@ __global__ __launch_bounds__(64) void k_row_b(SceneDev S, const int* ai, const i
       const int b = inc_off[v], m = inc_off[v + 1] - b;
       const int r0 = row_ptr[v], r1 = row_ptr[v + 1];
       if (r1 > cap) continue;  // overflow: reported by block 0
-      row_b<64, 16>(S, ai, aj, at, inc, b, m, colbuf + 4LL * b, r0, r1 - r0, G, H, g + 3LL * v, col, val, vs, band,
+      row_b<64, 32>(S, ai, aj, at, inc, b, m, colbuf + 4LL * b, r0, r1 - r0, G, H, g + 3LL * v, col, val, vs, band,
                     nullptr, stn);
     }
     return;
