@@ -1742,44 +1742,61 @@ __global__ __launch_bounds__(256) void k_row_b_big(SceneDev S, const int* ai, co
 // The search stops before the step after which the gap is below s of the
 // initial gap, or at the full step 1, or after max_iter steps.  Positions
 // advance by additions of products (no fused multiply-add).
-__device__ double accd_stencil(int type, const d3* X0, const d3* P0, double xi, double s, int max_iter, int& iters) {
-  iters = 0;
+// The search as a state that advances one step at a time (a lane whose pair
+// finishes can take the next pair while the others keep stepping).
+struct Accd {
+  d3 X[4], P[4];
+  double lp, xi, xi2, g, t, tl;
+  int type, it;
+};
+
+// Set-up of one stencil: returns true when steps are needed, else the step
+// in t (1 without relative motion, 0 at or inside the offset).
+__device__ __forceinline__ bool accd_setup(Accd& A, int type, const d3* X0, const d3* P0, double xi, double s,
+                                           double& t) {
   d3 pm;
   pm.x = (((P0[0].x + P0[1].x) + P0[2].x) + P0[3].x) / 4.0;
   pm.y = (((P0[0].y + P0[1].y) + P0[2].y) + P0[3].y) / 4.0;
   pm.z = (((P0[0].z + P0[1].z) + P0[2].z) + P0[3].z) / 4.0;
-  d3 X[4], P[4];
   double nr[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    X[k] = X0[k];
-    P[k] = P0[k] - pm;
-    nr[k] = sqrt(dot(P[k], P[k]));
+    A.X[k] = X0[k];
+    A.P[k] = P0[k] - pm;
+    nr[k] = sqrt(dot(A.P[k], A.P[k]));
   }
-  const double lp = type == BF_PT ? nr[0] + fmax(nr[1], fmax(nr[2], nr[3])) : fmax(nr[0], nr[1]) + fmax(nr[2], nr[3]);
-  if (lp == 0.0) return 1.0;
-  const double xi2 = xi * xi;
-  double D = type == BF_PT ? classify_pt(X).D : classify_ee(X).D;
-  const double gap0 = (D - xi2) / (sqrt(D) + xi);
-  if (!(gap0 > 0.0)) return 0.0;  // at or inside the offset already
-  const double g = s * gap0;
-  double t = 0.0, tl = (1.0 - s) * gap0 / lp;
-  for (int it = 0; it < max_iter; ++it) {
-    iters = it + 1;
+  A.type = type;
+  A.it = 0;
+  A.lp = type == BF_PT ? nr[0] + fmax(nr[1], fmax(nr[2], nr[3])) : fmax(nr[0], nr[1]) + fmax(nr[2], nr[3]);
+  if (A.lp == 0.0) { t = 1.0; return false; }
+  A.xi = xi;
+  A.xi2 = xi * xi;
+  const double D = type == BF_PT ? classify_pt(A.X).D : classify_ee(A.X).D;
+  const double gap0 = (D - A.xi2) / (sqrt(D) + xi);
+  if (!(gap0 > 0.0)) { t = 0.0; return false; }  // at or inside the offset already
+  A.g = s * gap0;
+  A.t = 0.0;
+  A.tl = (1.0 - s) * gap0 / A.lp;
+  return true;
+}
+
+// One step: returns false once the search has ended, with the step in t.
+__device__ __forceinline__ bool accd_step(Accd& A, int max_iter, double& t) {
+  A.it += 1;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      X[k].x = __dadd_rn(X[k].x, __dmul_rn(tl, P[k].x));
-      X[k].y = __dadd_rn(X[k].y, __dmul_rn(tl, P[k].y));
-      X[k].z = __dadd_rn(X[k].z, __dmul_rn(tl, P[k].z));
-    }
-    D = type == BF_PT ? classify_pt(X).D : classify_ee(X).D;
-    const double gap = (D - xi2) / (sqrt(D) + xi);
-    if (t > 0.0 && gap < g) break;
-    t += tl;
-    if (t > 1.0) return 1.0;
-    tl = 0.9 * gap / lp;
+  for (int k = 0; k < 4; ++k) {
+    A.X[k].x = __dadd_rn(A.X[k].x, __dmul_rn(A.tl, A.P[k].x));
+    A.X[k].y = __dadd_rn(A.X[k].y, __dmul_rn(A.tl, A.P[k].y));
+    A.X[k].z = __dadd_rn(A.X[k].z, __dmul_rn(A.tl, A.P[k].z));
   }
-  return t;
+  const double D = A.type == BF_PT ? classify_pt(A.X).D : classify_ee(A.X).D;
+  const double gap = (D - A.xi2) / (sqrt(D) + A.xi);
+  if (A.t > 0.0 && gap < A.g) { t = A.t; return false; }
+  A.t += A.tl;
+  if (A.t > 1.0) { t = 1.0; return false; }
+  A.tl = 0.9 * gap / A.lp;
+  if (A.it >= max_iter) { t = A.t; return false; }
+  return true;
 }
 
 // Exact swept-box test of a candidate (the definition of the CCD pair set):
@@ -1811,33 +1828,106 @@ __device__ __forceinline__ bool swept_within(int type, const d3* X, const d3* P,
 // Per candidate: ACCD if its swept boxes are within h (offset 0 for filtered
 // stencils, eta otherwise; Eq. 4), t = -1 otherwise (and its step count);
 // the minimum per block.
+// Lists of capacity up to ACCD_REFILL_MAX (a few candidates per lane of the
+// chip) are launched on at most ACCD_REFILL_BLOCKS blocks, which split the
+// list into contiguous shares, one per wave.  Once half a wave's lanes have no search in progress, those
+// lanes set up the next candidates of the share, and every round each lane
+// with a search in progress takes one step, so lanes whose searches end early
+// are refilled instead of idling until the longest search of their wave ends
+// (a refill waits on the candidates' loads, so it is done for many lanes at
+// once).  Longer lists: one candidate per lane at a time over the whole grid,
+// where other waves hide each wave's loads.  The step of each pair does not
+// depend on which lane computes it.
+constexpr long long ACCD_REFILL_MAX = 1 << 21;
+constexpr int ACCD_REFILL_BLOCKS = 512;
 __global__ __launch_bounds__(256) void k_accd(SceneDev S, const double* x, const double* pdisp, const int* ci,
                                               const int* cj, const unsigned char* ct, const long long* cand_count,
                                               long long ccap, double s, int max_iter, double* tpair, int* iters,
                                               double* bmin) {
   long long n = *cand_count;
   if (n > ccap) n = ccap;
+  const int lane = lane_id();
   double tmin = 1.0;
-  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += grid_stride()) {
-    const int type = ct[k];
-    int v[4];
-    pair_verts(S, type, ci[k], cj[k], v);
-    d3 X[4], P[4];
+  if ((int)gridDim.x <= ACCD_REFILL_BLOCKS) {  // the launch's choice (by capacity)
+    const int blocks = (int)gridDim.x;
+    {
+      const long long nwaves = (long long)blocks * (blockDim.x >> 6);
+      const long long wv = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+      const long long share = (n + nwaves - 1) / nwaves;
+      long long next = wv * share;  // next candidate of the share (same on every lane)
+      const long long end = next + share < n ? next + share : n;
+      Accd A;
+      long long k = -1;             // this lane's candidate in progress
+      while (true) {
+        if (__popcll(__ballot(k < 0)) >= 32) while (true) {
+          const bool need = k < 0;
+          const unsigned long long needy = __ballot(need);
+          if (needy == 0 || next >= end) break;
+          if (need) {
+            const long long kk = next + lanes_below(needy);
+            if (kk < end) {
+              const int type = ct[kk];
+              int v[4];
+              pair_verts(S, type, ci[kk], cj[kk], v);
+              d3 X[4], P[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) { X[q] = load3(x, v[q]); P[q] = load3(pdisp, v[q]); }
-    double t = -1.0;
-    int it = 0;
-    if (!is_culled(S, type, ci[k], cj[k]) && swept_within(type, X, P, S.h)) {
-      const double xi = is_filtered(S, type, v) || in_core(S, type, ci[k], cj[k]) ? 0.0 : S.eta;
-      t = accd_stencil(type, X, P, xi, s, max_iter, it);
-      tmin = fmin(tmin, t);
+              for (int q = 0; q < 4; ++q) { X[q] = load3(x, v[q]); P[q] = load3(pdisp, v[q]); }
+              double t = -1.0;
+              bool go = false;
+              if (!is_culled(S, type, ci[kk], cj[kk]) && swept_within(type, X, P, S.h)) {
+                const double xi = is_filtered(S, type, v) || in_core(S, type, ci[kk], cj[kk]) ? 0.0 : S.eta;
+                go = accd_setup(A, type, X, P, xi, s, t);
+              }
+              if (go) {
+                k = kk;
+              } else {  // decided at set-up
+                if (t >= 0.0) tmin = fmin(tmin, t);
+                if (tpair) tpair[kk] = t;
+                if (iters) iters[kk] = 0;
+              }
+            }
+          }
+          next += __popcll(needy);
+        }
+        if (__ballot(k >= 0) == 0) break;  // the share is done
+        if (k >= 0) {
+          double t;
+          if (!accd_step(A, max_iter, t)) {
+            tmin = fmin(tmin, t);
+            if (tpair) tpair[k] = t;
+            if (iters) iters[k] = A.it;
+            k = -1;
+          }
+        }
+      }
     }
-    if (tpair) tpair[k] = t;
-    if (iters) iters[k] = it;
+  } else {
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += grid_stride()) {
+      const int type = ct[k];
+      int v[4];
+      pair_verts(S, type, ci[k], cj[k], v);
+      d3 X[4], P[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) { X[q] = load3(x, v[q]); P[q] = load3(pdisp, v[q]); }
+      double t = -1.0;
+      int it = 0;
+      if (!is_culled(S, type, ci[k], cj[k]) && swept_within(type, X, P, S.h)) {
+        const double xi = is_filtered(S, type, v) || in_core(S, type, ci[k], cj[k]) ? 0.0 : S.eta;
+        Accd A;
+        if (accd_setup(A, type, X, P, xi, s, t)) {
+          while (accd_step(A, max_iter, t)) {
+          }
+          it = A.it;
+        }
+        tmin = fmin(tmin, t);
+      }
+      if (tpair) tpair[k] = t;
+      if (iters) iters[k] = it;
+    }
   }
   for (int o = 32; o > 0; o >>= 1) tmin = fmin(tmin, __shfl_xor(tmin, o, 64));
   __shared__ double wm[4];
-  if (lane_id() == 0) wm[threadIdx.x >> 6] = tmin;
+  if (lane == 0) wm[threadIdx.x >> 6] = tmin;
   __syncthreads();
   if (threadIdx.x == 0) bmin[blockIdx.x] = fmin(fmin(wm[0], wm[1]), fmin(wm[2], wm[3]));
 }
@@ -2336,7 +2426,8 @@ void run_broad(const SceneDev& S, const double* x, const double* pdisp, const Br
 void run_accd(const SceneDev& S, const double* x, const double* pdisp, const int* ci, const int* cj,
               const unsigned char* ct, const long long* ccount, long long ccap, double s, int max_iter, double* tpair,
               int* iters, double* bred, double* t_out, hipStream_t st) {
-  const int nb = nblocks(ccap, 256, LINE_BLOCKS);
+  const int nb = ccap <= ACCD_REFILL_MAX ? nblocks(ccap, 256, ACCD_REFILL_BLOCKS)
+                                        : std::max(ACCD_REFILL_BLOCKS + 1, nblocks(ccap, 256, LINE_BLOCKS));
   hipLaunchKernelGGL(k_accd, dim3(nb), dim3(256), 0, st, S, x, pdisp, ci, cj, ct, ccount, ccap, s, max_iter, tpair,
                      iters, bred);
   hipLaunchKernelGGL(k_min_final, dim3(1), dim3(256), 0, st, bred, nb, t_out);

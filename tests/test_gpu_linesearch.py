@@ -35,10 +35,10 @@ SCENES = {
 }
 
 
-def _gpu_line(sc, p, alphas):
+def _gpu_line(sc, p, alphas, cand_cap=None):
     import paper_2510_10256_amd as bfc
     dev = torch.device("cuda:0")
-    cs = bfc.ContactScene(sc, device=dev)
+    cs = bfc.ContactScene(sc, device=dev, cand_cap=cand_cap)
     x = torch.tensor(sc.x, dtype=torch.float64, device=dev)
     pt = torch.tensor(p, dtype=torch.float64, device=dev)
     cs.run(x)  # sizes the buffers on the static candidates
@@ -78,16 +78,21 @@ def _energy_bound(o, tau=1e-10):
     return tau * float(np.sum(np.abs(E[np.isfinite(E)])) + np.sum(bref)) + 1e-300
 
 
+# a candidate capacity above 2^21 launches the CCD kernel's long-list form
+# (one candidate per lane at a time) instead of the refilled shares
+BIG_CAP = (1 << 21) + 4096
+
+
 @requires_gpu
-@pytest.mark.parametrize("name", list(SCENES))
-def test_max_step_and_energy_match_the_oracle(name):
+@pytest.mark.parametrize("name,cap", [(n, None) for n in SCENES] + [("yarn", BIG_CAP), ("cloth", BIG_CAP)])
+def test_max_step_and_energy_match_the_oracle(name, cap):
     sc = SCENES[name]()
     p = synth.search_direction(sc)
-    print(f"[linesearch] {name} V={sc.n_verts}", flush=True)
+    print(f"[linesearch] {name} V={sc.n_verts} cand_cap={cap}", flush=True)
     orc = oracle.max_step(sc, sc.x, p, s=S_ACCD, max_iter=MAX_ITER)
     t_o = orc["t"]
     alphas = [0.0, 0.5 * t_o, t_o]
-    g = _gpu_line(sc, p, alphas)
+    g = _gpu_line(sc, p, alphas, cand_cap=cap)
     assert g["repeat_ok"]
     # the CCD pair set
     inset = g["tp"] >= 0.0
