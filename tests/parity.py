@@ -60,11 +60,11 @@ def compare(gpu, orc, nv, kappa=1.0, tau=1e-10, check_assembly=True, derivs=True
     if derivs:
         dG = np.linalg.norm(gpu["G"][gi][feas] - orc["G"][oi][feas], axis=1)
         tolG = tau * (np.linalg.norm(orc["G"][oi][feas], axis=1) + bref[feas] / w[feas])
-        report["G_worst"] = float(np.max(dG / tolG))
+        report["G_worst"] = float(np.max(dG / tolG, initial=0.0))
         assert np.all(dG <= tolG), f"per-pair gradient: worst ratio {report['G_worst']:.3g}"
         dH = np.linalg.norm((gpu["Hpsd"][gi][feas] - orc["Hpsd"][oi][feas]).reshape(-1, 144), axis=1)
         tolH = tau * (np.linalg.norm(orc["Hpsd"][oi][feas].reshape(-1, 144), axis=1) + bref[feas] / w[feas] ** 2)
-        report["H_worst"] = float(np.max(dH / tolH))
+        report["H_worst"] = float(np.max(dH / tolH, initial=0.0))
         assert np.all(dH <= tolH), f"per-pair Hessian: worst ratio {report['H_worst']:.3g}, " \
                                    f"{int(np.sum(dH > tolH))} pairs"
     if check_assembly and derivs:
