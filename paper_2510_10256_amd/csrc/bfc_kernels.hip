@@ -1112,7 +1112,8 @@ __global__ __launch_bounds__(256) void k_inc_fill(SceneDev S, const int* ai, con
 constexpr int ROW_S = 16;  // rows with m <= ROW_S: one 16-lane team each, four rows a wave
 constexpr int ROW_L = 32;
 constexpr int ROW_M = 256;
-constexpr int ROW_M_TAB = 4 * ROW_M;  // hash slots: at least the row's 4m candidate columns
+constexpr int ROW_M_TAB = 4 * ROW_M;  // hash slots: at least the row's 4m candidate columns (tables
+                                      // take pow2(4m + 1) slots up to this: always room for every key)
 constexpr int ROW_H = 2048;
 constexpr int ROW_H_TAB = 4 * ROW_H;
 constexpr int EMPTY = -1;
@@ -1357,7 +1358,7 @@ __device__ void row_a_wave(const SceneDev& S, const int* ai, const int* aj, cons
   // LDS
   const int Pm = pow2_at_least(m);
   for (int q = lane; q < Pm; q += 64) ent[q] = q < m ? inc[b + q] : PAD;
-  const int T = min(ROW_M_TAB, pow2_at_least(8 * m));
+  const int T = min(ROW_M_TAB, pow2_at_least(4 * m + 1));
   for (int q = lane; q < T; q += 64) tab[q] = EMPTY;
   __syncthreads();
   team_bitonic<64>(ent, Pm);
@@ -1455,7 +1456,7 @@ __global__ __launch_bounds__(256) void k_row_a_big(SceneDev S, const int* ai, co
     }
     const int Pm = pow2_at_least(m);
     for (int q = tid; q < Pm; q += 256) ent[q] = q < m ? inc[b + q] : PAD;
-    const int T = min(ROW_H_TAB, pow2_at_least(8 * m));
+    const int T = min(ROW_H_TAB, pow2_at_least(4 * m + 1));
     for (int q = tid; q < T; q += 256) tab[q] = EMPTY;
     __syncthreads();
     team_bitonic<256>(ent, Pm);
