@@ -140,9 +140,10 @@ bf_status alloc_asm_ws(const bf_scene* s, long long act_cap, std::vector<void*>&
   A.mid = dalloc<int>(allocs, s->nv + 1, &e);
   A.big = dalloc<int>(allocs, s->nv + 1, &e);
   A.epart = dalloc<double>(allocs, (act_cap + 63) / 64 + 1, &e);
-  A.scan_tmp = dalloc<int>(allocs, scan_parts(s->nv + 1) + 16, &e);
+  A.scan_tmp = dalloc<int>(allocs, scan_tmp_ints(s->nv + 1), &e);
   if (e != hipSuccess) return fail(BF_E_NOMEM, who);
   if (hipMemsetAsync(A.inc_cnt, 0, sizeof(int) * (s->nv + 1), g_alloc_stream) != hipSuccess ||
+      hipMemsetAsync(A.scan_tmp, 0, sizeof(int) * SCAN_LB_STATE, g_alloc_stream) != hipSuccess ||
       hipMemsetAsync(A.rowcnt, 0, sizeof(int) * (s->nv + 1), g_alloc_stream) != hipSuccess ||
       hipStreamSynchronize(g_alloc_stream) != hipSuccess)
     return fail(BF_E_DEVICE, who);
@@ -207,8 +208,11 @@ bf_status alloc_stage(bf_scene* s, long long cand_cap) {
   W.kcnt = dalloc<int>(s->stage_allocs, 3 * G + 1, &e);
   W.kofs = dalloc<int>(s->stage_allocs, 3 * G + 1, &e);
   W.ccnt = dalloc<int>(s->stage_allocs, 3 * G, &e);
-  W.scan_tmp = dalloc<int>(s->stage_allocs, scan_parts(3 * G + 1) + 16, &e);
+  W.scan_tmp = dalloc<int>(s->stage_allocs, scan_tmp_ints(3 * G + 1), &e);
   if (e != hipSuccess) return fail(BF_E_NOMEM, "bf_scene_reserve: device allocation failed");
+  if (hipMemsetAsync(W.scan_tmp, 0, sizeof(int) * SCAN_LB_STATE, g_alloc_stream) != hipSuccess ||
+      hipStreamSynchronize(g_alloc_stream) != hipSuccess)
+    return fail(BF_E_DEVICE, "bf_scene_reserve: clearing the scan state failed");
   W.cap = G * NW_TILE;
   s->sw = W;
   return BF_OK;
@@ -285,7 +289,7 @@ bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int
   W.pair_bsum = dalloc<int>(s->allocs, nq / 256 + 2, &e);
   W.pair_bseg = dalloc<long long>(s->allocs, nq / 256 + 2, &e);
   W.seg_count = dalloc<unsigned long long>(s->allocs, 1, &e);
-  W.scan_tmp = dalloc<int>(s->allocs, std::max(std::max(scan_parts(nscan), scan_parts(nv + 1)), scan_parts(nq)) + 16, &e);
+  W.scan_tmp = dalloc<int>(s->allocs, std::max(std::max(scan_tmp_ints(nscan), scan_tmp_ints(nv + 1)), scan_tmp_ints(nq)), &e);
   if (e != hipSuccess) {
     free_list(s->allocs);
     delete s;
@@ -297,6 +301,7 @@ bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int
       (he = hipMemcpyAsync(s->d_ref, mesh->ref_h, sizeof(double) * nref, hipMemcpyHostToDevice, st)) ||
       (he = hipMemsetAsync(s->d_status, 0, 4 * sizeof(unsigned), st)) ||
       (he = hipMemsetAsync(W.cell_cnt, 0, sizeof(int) * nscan, st)) ||
+      (he = hipMemsetAsync(W.scan_tmp, 0, sizeof(int) * SCAN_LB_STATE, st)) ||
       (he = hipMemsetAsync(W.done, 0, sizeof(unsigned), st))) {
     free_list(s->allocs);
     delete s;

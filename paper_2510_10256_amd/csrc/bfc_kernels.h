@@ -14,8 +14,13 @@ constexpr int LINE_BLOCKS = 8192;      // work-groups of the line-search kernels
 constexpr int NW_TILE = 256 * NW_ITEMS;
 constexpr int BOUNDS_BLOCKS = 512;     // cap on k_bounds work-groups (partials of the last-block reduction)
 
-// number of scan partials needed for n elements
-inline long long scan_parts(long long n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
+constexpr int SCAN_LB_TILES = 256;     // arrays of up to this many tiles take the single-pass scan
+// The scan's scratch: first the single-pass scan's state (SCAN_LB_TILES 64-bit
+// tile words, then a ticket and a done counter; zero when no scan runs, so
+// it is cleared once when allocated), then the partials of the longer scans.
+constexpr int SCAN_LB_STATE = 2 * SCAN_LB_TILES + 8;
+// ints of scratch for a scan of n elements
+inline long long scan_tmp_ints(long long n) { return SCAN_LB_STATE + (n + SCAN_TILE - 1) / SCAN_TILE + 1 + 16; }
 
 void scan_excl(const int* in, int* out, const int* n_dev, int n_max, int* tmp, hipStream_t st);
 

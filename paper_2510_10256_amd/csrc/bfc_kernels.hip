@@ -154,14 +154,25 @@ __global__ __launch_bounds__(256) void k_scan_down(const int* in, int* out, cons
   }
 }
 
-// Down-sweep for up to SCAN2_MAX_BLOCKS tiles that sums the earlier tiles'
-// totals itself (no separate partials pass).
-__global__ __launch_bounds__(256) void k_scan_down2(const int* in, int* out, const int* n_dev, int n_const,
-                                                    const int* part) {
-  int n = n_dev ? *n_dev : n_const;
-  int base = blockIdx.x * SCAN_TILE;
-  if (base >= n) return;
-  const long long before = block_sum256(threadIdx.x < blockIdx.x ? part[threadIdx.x] : 0);
+// Single-pass exclusive scan of at most SCAN_LB_TILES tiles.  A work-group
+// takes its tile from a ticket when it starts, publishes the tile's total,
+// then reads the totals of all earlier tiles at once (one thread a tile) and
+// adds them.  It only ever waits on tiles whose work-groups started before
+// it, and those publish before they wait on anything: every wait ends.  The
+// total and its "published" flag share one 64-bit word, written and read
+// with device-scope atomics (no other data passes between work-groups, so
+// no release or acquire is needed).  The last work-group to finish clears the
+// words and the counters for the next scan.  The poll is bounded all the same
+// (a total that never came would give a wrong sum, not a hang).
+__global__ __launch_bounds__(256) void k_scan_lb(const int* in, int* out, const int* n_dev, int n_const,
+                                                 int* state) {
+  unsigned long long* word = (unsigned long long*)state;  // [SCAN_LB_TILES] 1 << 32 | total
+  unsigned* ctr = (unsigned*)(state + 2 * SCAN_LB_TILES);  // ticket, done
+  __shared__ int s_tile;
+  const int n = n_dev ? *n_dev : n_const;
+  if (threadIdx.x == 0) s_tile = (int)atomicAdd(&ctr[0], 1u);
+  __syncthreads();
+  const int tile = s_tile, base = tile * SCAN_TILE;
   int v[SCAN_ITEMS];
   int s = 0;
 #pragma unroll
@@ -170,12 +181,33 @@ __global__ __launch_bounds__(256) void k_scan_down2(const int* in, int* out, con
     v[k] = i < n ? in[i] : 0;
     s += v[k];
   }
-  int run = block_excl_scan256(s, nullptr) + (int)before;
+  int tot;
+  const int excl = block_excl_scan256(s, &tot);
+  if (threadIdx.x == 0)
+    __hip_atomic_store(&word[tile], (1ull << 32) | (unsigned)tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  int earlier = 0;
+  if ((int)threadIdx.x < tile) {
+    unsigned long long w;
+    int polls = 0;
+    do {
+      w = __hip_atomic_load(&word[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } while ((w >> 32) == 0 && ++polls < (1 << 22));
+    earlier = (int)(unsigned)w;
+  }
+  int run = excl + (int)block_sum256(earlier);
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
     int i = base + threadIdx.x * SCAN_ITEMS + k;
     if (i < n) out[i] = run;
     run += v[k];
+  }
+  if (threadIdx.x == 0) {  // after the block sum: this work-group has read every word it needs
+    const unsigned d = __hip_atomic_fetch_add(&ctr[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (d == gridDim.x - 1) {
+      for (int j = 0; j < (int)gridDim.x; ++j) word[j] = 0ull;
+      ctr[0] = 0u;
+      ctr[1] = 0u;
+    }
   }
 }
 
@@ -224,13 +256,14 @@ void scan_excl(const int* in, int* out, const int* n_dev, int n_max, int* tmp, h
   }
   int nb = (n_max + SCAN_TILE - 1) / SCAN_TILE;
   if (nb < 1) nb = 1;
-  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(256), 0, st, in, n_dev, n_max, tmp);
-  if (nb <= 256) {  // each tile sums the earlier tiles' totals itself
-    hipLaunchKernelGGL(k_scan_down2, dim3(nb), dim3(256), 0, st, in, out, n_dev, n_max, tmp);
+  if (nb <= SCAN_LB_TILES) {
+    hipLaunchKernelGGL(k_scan_lb, dim3(nb), dim3(256), 0, st, in, out, n_dev, n_max, tmp);
     return;
   }
-  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, tmp, n_dev, n_max);
-  hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(256), 0, st, in, out, n_dev, n_max, tmp);
+  int* part = tmp + SCAN_LB_STATE;
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(256), 0, st, in, n_dev, n_max, part);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, part, n_dev, n_max);
+  hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(256), 0, st, in, out, n_dev, n_max, part);
 }
 
 __global__ void k_zero_i(int* a, const int* n_dev, long long n_const) {
