@@ -61,6 +61,39 @@ def test_small_parity_fp64(name):
 
 @requires_gpu
 @pytest.mark.parametrize("name", list(SMALL))
+def test_small_parity_no_offset(name):
+    # eta = 0: the filter of Eq. 4 reduces to that of Eq. 1 (the rest distance
+    # as activation, no offset) and the other pairs take the plain barrier
+    # with activation h
+    from tests.parity import compare
+    sc = SMALL[name]()
+    print(f"[parity eta=0] {name} V={sc.n_verts}", flush=True)
+    g = run_gpu(sc, eta=0.0)
+    o = oracle.evaluate(sc, mode=1, eta=0.0)
+    assert np.all(o["eta"] == 0.0)
+    rep = compare(g, o, sc.n_verts, kappa=sc.kappa, tau=1e-10)
+    print(name, g["counts"], rep, flush=True)
+
+
+@requires_gpu
+@pytest.mark.parametrize("name", list(SMALL))
+def test_small_parity_unfiltered(name):
+    # no filter (plain offset barrier on every pair, the comparison setting):
+    # stencil neighbours closer than h at rest are active too, most of them
+    # infeasible
+    import paper_2510_10256_amd as bfc
+    from tests.parity import compare
+    sc = SMALL[name]()
+    print(f"[parity unfiltered] {name} V={sc.n_verts}", flush=True)
+    g = run_gpu(sc, filter_mode=bfc.BF_FILTER_NONE)
+    o = oracle.evaluate(sc, mode=1, filter_mode=1)
+    assert g["counts"]["n_filt"] == 0 and g["counts"]["n_infeasible"] > 0
+    rep = compare(g, o, sc.n_verts, kappa=sc.kappa, tau=1e-10)
+    print(name, g["counts"], rep, flush=True)
+
+
+@requires_gpu
+@pytest.mark.parametrize("name", list(SMALL))
 def test_small_parity_mixed(name):
     # FP32 screen in the narrow phase, FP32 derivative terms: the active set
     # stays exact, values within tau = 1e-5
