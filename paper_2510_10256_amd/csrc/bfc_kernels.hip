@@ -89,7 +89,9 @@ __device__ __forceinline__ long long block_sum256(long long v) {
 }
 
 // ---------------------------------------------------------------------------
-// device-wide exclusive scan of int32 (3 kernels); n = n_dev ? *n_dev : n_const
+// device-wide exclusive scan of int32; n = n_dev ? *n_dev : n_const: one
+// work-group (k_scan1), one pass (k_scan_lb) or, for more than SCAN_LB_TILES
+// tiles, three kernels (tile totals, their scan, down-sweep)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_scan_reduce(const int* in, const int* n_dev, int n_const, int* part) {
   int n = n_dev ? *n_dev : n_const;
