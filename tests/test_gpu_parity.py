@@ -108,6 +108,29 @@ def test_small_parity_mixed(name):
 
 
 @requires_gpu
+@pytest.mark.parametrize("seed", [11, 12, 13])
+def test_seeded_moved_parity(seed):
+    # other seeds of the generators, at positions moved along a seeded
+    # displacement: pairs close in, and on the cloth some cross the offset
+    # (infeasible, E = +inf)
+    import paper_2510_10256_amd as bfc
+    from tests.parity import compare
+    for name, sc in (("yarn", synth.woven_patch(seed=seed, n_warp=4, n_weft=4, verts_per_rod=80)),
+                     ("cloth", synth.folded_cloth(seed=seed, n=48, gaps=(950.0,), l_mid=4000.0, l_conv=2000.0))):
+        x = sc.x + 0.05 * synth.search_direction(sc, seed=seed + 100)
+        print(f"[parity seed] {name} seed={seed} V={sc.n_verts}", flush=True)
+        cs = bfc.ContactScene(sc)
+        cs.run(x)
+        g = cs.results()
+        cs.close()
+        o = oracle.evaluate(sc, x, mode=1)
+        rep = compare(g, o, sc.n_verts, kappa=sc.kappa, tau=1e-10)
+        print(name, seed, g["counts"], rep, flush=True)
+        if name == "cloth":
+            assert g["counts"]["n_infeasible"] > 0
+
+
+@requires_gpu
 def test_full_yarn_patch_parity_mixed():
     import paper_2510_10256_amd as bfc
     from tests.parity import compare
