@@ -108,8 +108,9 @@ def test_small_parity_mixed(name):
 
 
 @requires_gpu
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("seed", [11, 12, 13])
-def test_seeded_moved_parity(seed):
+def test_seeded_moved_parity(seed, prec):
     # other seeds of the generators, at positions moved along a seeded
     # displacement: pairs close in, and on the cloth some cross the offset
     # (infeasible, E = +inf)
@@ -118,14 +119,14 @@ def test_seeded_moved_parity(seed):
     for name, sc in (("yarn", synth.woven_patch(seed=seed, n_warp=4, n_weft=4, verts_per_rod=80)),
                      ("cloth", synth.folded_cloth(seed=seed, n=48, gaps=(950.0,), l_mid=4000.0, l_conv=2000.0))):
         x = sc.x + 0.05 * synth.search_direction(sc, seed=seed + 100)
-        print(f"[parity seed] {name} seed={seed} V={sc.n_verts}", flush=True)
-        cs = bfc.ContactScene(sc)
+        print(f"[parity seed] {name} seed={seed} {prec} V={sc.n_verts}", flush=True)
+        cs = bfc.ContactScene(sc, prec=bfc.BF_FP64 if prec == "fp64" else bfc.BF_MIXED)
         cs.run(x)
         g = cs.results()
         cs.close()
         o = oracle.evaluate(sc, x, mode=1)
-        rep = compare(g, o, sc.n_verts, kappa=sc.kappa, tau=1e-10)
-        print(name, seed, g["counts"], rep, flush=True)
+        rep = compare(g, o, sc.n_verts, kappa=sc.kappa, tau=1e-10 if prec == "fp64" else 1e-5)
+        print(name, seed, prec, g["counts"], rep, flush=True)
         if name == "cloth":
             assert g["counts"]["n_infeasible"] > 0
 
