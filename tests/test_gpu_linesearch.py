@@ -89,6 +89,21 @@ def test_max_step_and_energy_match_the_oracle(name, cap):
     sc = SCENES[name]()
     p = synth.search_direction(sc)
     print(f"[linesearch] {name} V={sc.n_verts} cand_cap={cap}", flush=True)
+    _check_line(sc, p, cap, name)
+
+
+@requires_gpu
+@pytest.mark.parametrize("seed", [11, 12])
+def test_line_search_other_seeds(seed):
+    # other seeds of the yarn and cloth generators and of the direction
+    for name, sc in (("yarn", synth.woven_patch(seed=seed, n_warp=4, n_weft=4, verts_per_rod=80)),
+                     ("cloth", synth.folded_cloth(seed=seed, n=48, gaps=(950.0,), l_mid=4000.0, l_conv=2000.0))):
+        p = synth.search_direction(sc, seed=seed + 100)
+        print(f"[linesearch] {name} seed={seed} V={sc.n_verts}", flush=True)
+        _check_line(sc, p, None, name)
+
+
+def _check_line(sc, p, cap, name):
     orc = oracle.max_step(sc, sc.x, p, s=S_ACCD, max_iter=MAX_ITER)
     t_o = orc["t"]
     alphas = [0.0, 0.5 * t_o, t_o]
