@@ -39,11 +39,25 @@ def _keyed(ptype, i, j):
 @requires_gpu
 @pytest.mark.parametrize("name", list(SCENES))
 def test_lagged_friction_matches_the_oracle(name):
-    import paper_2510_10256_amd as bfc
     sc = SCENES[name]()
-    xl = sc.x
-    x = xl + 0.02 * synth.search_direction(sc)   # slips of about one eh
     print(f"[friction] {name} V={sc.n_verts}", flush=True)
+    _check_friction(sc, synth.search_direction(sc), name)
+
+
+@requires_gpu
+@pytest.mark.parametrize("seed", [11, 12])
+def test_friction_other_seeds(seed):
+    # other seeds of the yarn and cloth generators and of the slip direction
+    for name, sc in (("yarn", synth.woven_patch(seed=seed, n_warp=4, n_weft=4, verts_per_rod=80)),
+                     ("cloth", synth.folded_cloth(seed=seed, n=48, gaps=(950.0,), l_mid=4000.0, l_conv=2000.0))):
+        print(f"[friction] {name} seed={seed} V={sc.n_verts}", flush=True)
+        _check_friction(sc, synth.search_direction(sc, seed=seed + 100), name)
+
+
+def _check_friction(sc, p, name):
+    import paper_2510_10256_amd as bfc
+    xl = sc.x
+    x = xl + 0.02 * p   # slips of about one eh
     dev = torch.device("cuda:0")
     cs = bfc.ContactScene(sc, device=dev)
     XL = torch.tensor(xl, dtype=torch.float64, device=dev)
@@ -90,7 +104,8 @@ def test_lagged_friction_matches_the_oracle(name):
     res0 = oracle.evaluate(sc, xl, mode=1, derivs=False)
     act0 = (res0["flags"] & oracle.F_ACTIVE) != 0
     k0 = _keyed(res0["ptype"][act0], res0["i"][act0], res0["j"][act0])
-    wband = np.array([res0["a"][act0][k0[k]] - res0["eta"][act0][k0[k]] for k in ok])
+    band0 = res0["a"][act0] - res0["eta"][act0]
+    wband = band0[np.array([k0[k] for k in ok], dtype=np.int64)]
     fref = sc.kappa * wband * np.log(2) / 4
     dl = np.abs(g["lam"][gi] - lo) / (lo + fref)
     dw = np.abs(g["w"][gi] - lag["w"][oi]).max(axis=1)
@@ -121,12 +136,15 @@ def test_lagged_friction_matches_the_oracle(name):
         np.add.at(gb, lag["verts"][:, q], TAU * (np.linalg.norm(o["G"], axis=1) + sl))
     assert np.all(np.linalg.norm(g["g"] - asm["g"], axis=1) <= gb + 1e-300)
     assert np.array_equal(g["row_ptr"], asm["row_ptr"]) and np.array_equal(g["col"], asm["col"])
+    # each pair's bound on the 16 blocks (a, b) of its stencil, found by the
+    # key a * V + b among the CSR's (row-major, columns sorted) keys
+    nv = sc.n_verts
+    keys = np.repeat(np.arange(nv, dtype=np.int64), np.diff(asm["row_ptr"])) * nv + asm["col"]
+    V4 = lag["verts"].astype(np.int64)
+    idx = np.searchsorted(keys, np.repeat(V4, 4, axis=1) * nv + np.tile(V4, (1, 4)))
+    assert np.array_equal(keys[idx], np.repeat(V4, 4, axis=1) * nv + np.tile(V4, (1, 4)))
+    sck = TAU * (np.linalg.norm(o["Hpsd"].reshape(len(oi), -1), axis=1) + sl / EH)
     hb = np.zeros(len(g["col"]))
-    for k in range(len(oi)):
-        sc_k = TAU * (np.linalg.norm(o["Hpsd"][k]) + sl[k] / EH)
-        for a in lag["verts"][k]:
-            for b in lag["verts"][k]:
-                r0, r1 = asm["row_ptr"][a], asm["row_ptr"][a + 1]
-                hb[r0 + np.searchsorted(asm["col"][r0:r1], b)] += sc_k
+    np.add.at(hb, idx.ravel(), np.repeat(sck, 16))
     assert np.all(np.abs(g["val"] - asm["val"]).reshape(len(hb), -1).max(axis=1) <= hb + 1e-300)
     cs.close()
