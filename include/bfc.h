@@ -33,8 +33,9 @@
  *
  * Errors.  Argument and state errors return synchronously with a status code
  * and a thread-local message (bf_last_error).  Conditions found on the device
- * (capacity overflow, infeasible pair, spin limit) set bits in the scene's
- * device status word, read by bf_status_word (which synchronises).  On
+ * (capacity overflow, infeasible pair, an eigen-iteration at its step limit,
+ * a scan that stopped waiting) set bits in the scene's device status word,
+ * read by bf_status_word (which synchronises); they never abort a kernel.  On
  * overflow the device counters still hold the required size so the caller
  * can grow its buffers and call again.
  */
@@ -55,7 +56,9 @@ typedef enum {
   BF_E_NOMEM = 2,    /* device allocation failed in create/reserve */
   BF_E_DEVICE = 3,   /* a HIP runtime call failed */
   BF_E_CAPACITY = 4, /* a caller buffer is too small (synchronous checks) */
-  BF_E_STATE = 5     /* call order violated */
+  BF_E_STATE = 5,    /* call order violated */
+  BF_E_DEGENERATE = 6 /* a degenerate rest primitive: an edge whose two vertices have the same
+                         rest parameters, or a triangle of zero rest area (bf_scene_create) */
 } bf_status;
 
 enum { BF_ROD = 0, BF_SHELL = 1 };
@@ -68,7 +71,12 @@ enum {
   BF_S_ACT_OVERFLOW = 1u << 1,    /* active list capacity exceeded */
   BF_S_INFEASIBLE = 1u << 2,      /* some active pair has d <= eta (energy +inf) */
   BF_S_BSR_OVERFLOW = 1u << 3,   /* BSR block capacity exceeded */
-  BF_S_CORE_OVERFLOW = 1u << 4   /* more core pairs than bf_core_mark's capacity */
+  BF_S_CORE_OVERFLOW = 1u << 4,  /* more core pairs than bf_core_mark's capacity */
+  BF_S_EIG_NOCONV = 1u << 5,     /* a pair Hessian's eigen-iteration hit its step limit
+                                    (that pair's projection is not exact) */
+  BF_S_SCAN_SLOW = 1u << 6       /* a single-pass scan stopped waiting for an earlier
+                                    tile's total and summed that tile itself (results
+                                    exact; reported for diagnosis) */
 };
 
 /* Pair types. */
@@ -358,6 +366,12 @@ bf_status bf_batch_destroy(bf_batch* b);
 /* Device status word (BF_S_* bits) accumulated since the last clear;
  * synchronises the stream the scene last used.  clear != 0 resets it. */
 bf_status bf_status_word(bf_scene* s, uint32_t* bits_h, int32_t clear);
+
+/* Diagnostics: the number of loads a single-pass scan spends waiting for
+ * each earlier tile's published total before it sums that tile itself
+ * (BF_S_SCAN_SLOW).  Default 2^22; >= 0.  Process-wide; affects launches
+ * enqueued after the call. */
+bf_status bf_set_scan_poll_limit(int32_t polls);
 
 /* Message of the last non-OK return on this thread. */
 const char* bf_last_error(void);

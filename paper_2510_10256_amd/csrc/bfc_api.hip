@@ -116,6 +116,7 @@ SceneDev dev_view(const bf_scene* s) {
   S.core_mask = s->core_slots ? s->core_slots - 1 : 0;
   S.mixed = s->prm.prec == BF_MIXED;
   S.pq = s->pq;
+  S.status = s->d_status;
   return S;
 }
 
@@ -218,11 +219,39 @@ bf_status alloc_stage(bf_scene* s, long long cand_cap) {
   return BF_OK;
 }
 
+// Stencil primitives must not be degenerate in rest space (the reference
+// distances of Sec. 3.2 divide by rest edge lengths): an edge whose two rest
+// parameters are equal, or a triangle whose rest edge vectors have a zero
+// cross product (evaluated in double; exactly zero for coincident or
+// collinear rest vertices on a lattice).  Returns the message, or null.
+const char* degenerate_rest(const bf_mesh_desc& m, int nv, int ne, int nt) {
+  const double* u = m.ref_h;
+  for (int e = 0; e < ne; ++e) {
+    const int a = m.edges_h[2 * e], b = m.edges_h[2 * e + 1];
+    const bool same = m.kind == BF_ROD ? u[a] == u[b] : (u[2 * a] == u[2 * b] && u[2 * a + 1] == u[2 * b + 1]);
+    if (same) return "bf_scene_create: an edge has zero rest length";
+  }
+  for (int t = 0; t < nt; ++t) {
+    const int a = m.tris_h[3 * t], b = m.tris_h[3 * t + 1], c = m.tris_h[3 * t + 2];
+    const double ux = u[2 * b] - u[2 * a], uy = u[2 * b + 1] - u[2 * a + 1];
+    const double vx = u[2 * c] - u[2 * a], vy = u[2 * c + 1] - u[2 * a + 1];
+    if (ux * vy - uy * vx == 0.0) return "bf_scene_create: a triangle has zero rest area";
+  }
+  (void)nv;
+  return nullptr;
+}
+
 }  // namespace
 
 extern "C" {
 
 const char* bf_last_error(void) { return g_err.c_str(); }
+
+bf_status bf_set_scan_poll_limit(int32_t polls) {
+  if (polls < 0) return fail(BF_E_ARG, "bf_set_scan_poll_limit: polls must be >= 0");
+  g_scan_polls = polls;
+  return BF_OK;
+}
 
 bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int64_t cand_cap, int64_t act_cap,
                           void* stream, bf_scene** out) {
@@ -251,6 +280,7 @@ bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int
     if (mesh->tris_h[k] < 0 || mesh->tris_h[k] >= nv) return fail(BF_E_ARG, "bf_scene_create: triangle vertex out of range");
   for (int e = 0; e < ne; ++e)
     if (mesh->edges_h[2 * e] == mesh->edges_h[2 * e + 1]) return fail(BF_E_ARG, "bf_scene_create: degenerate edge");
+  if (const char* why = degenerate_rest(*mesh, nv, ne, nt)) return fail(BF_E_DEGENERATE, why);
 
   hipStream_t st = (hipStream_t)stream;
   g_alloc_stream = st;
@@ -628,12 +658,9 @@ bf_status friction_eval(bf_scene* s, const double* x_d, const double* xlag_d, co
 bf_status bf_core_live(bf_scene* s, int64_t* count_d, void* stream) {
   if (!s || !count_d) return fail(BF_E_ARG, "bf_core_live: null argument");
   hipStream_t st = (hipStream_t)stream;
-  if (!s->core_slots) {
-    hipError_t he = hipMemsetAsync(count_d, 0, sizeof(int64_t), st);
-    return he == hipSuccess ? BF_OK : fail_hip(he, "bf_core_live");
-  }
   s->last = st;
-  run_core_count(dev_view(s), (long long*)count_d, st);
+  if (!s->core_slots) run_zero_i64((long long*)count_d, 1, st);  // a kernel, not a memset: capturable
+  else run_core_count(dev_view(s), (long long*)count_d, st);
   hipError_t he = hipGetLastError();
   return he == hipSuccess ? BF_OK : fail_hip(he, "bf_core_live");
 }
@@ -823,6 +850,18 @@ bf_status batch_capture(bf_batch* b, int lanes) {
     if ((he = hipEventCreateWithFlags(&e, hipEventDisableTiming)) != hipSuccess) return fail_hip(he, "bf_batch");
     b->events.push_back(e);
   }
+  // the four calls record their stream in the scene (the stream bf_scene_destroy
+  // and bf_status_word order against); under capture that would be a lane stream
+  // of this batch, destroyed with it, so each scene's stream is put back after
+  std::vector<hipStream_t> last(n);
+  for (int i = 0; i < n; ++i) last[i] = b->items[i].scene->last;
+  struct Restore {
+    bf_batch* b;
+    std::vector<hipStream_t>& last;
+    ~Restore() {
+      for (size_t i = 0; i < last.size(); ++i) b->items[i].scene->last = last[i];
+    }
+  } restore{b, last};
   if ((he = hipStreamBeginCapture(b->origin, hipStreamCaptureModeThreadLocal)) != hipSuccess)
     return fail_hip(he, "bf_batch: begin capture");
   bf_status r = BF_OK;

@@ -3,14 +3,16 @@
 //   A+ = Z max(L, 0) Z^T,  A = Z L Z^T.
 //
 // The eigensystem comes from a Householder reduction to tridiagonal form
-// followed by implicit symmetric QR steps with Wilkinson shifts, deflating
-// from the bottom (Golub and Van Loan, Matrix Computations, Alg. 8.3.1 and
-// 8.3.2; the orthogonal factor formed from the reflectors by backward
-// accumulation, Sec. 5.1.6).  For n = 9 this costs about a quarter of the FP64 operations of
+// followed by implicit symmetric QR steps with Wilkinson shifts on the
+// unreduced block that ends at the bottom, deflating from the bottom and
+// splitting wherever an off-diagonal entry is negligible (Golub and Van Loan,
+// Matrix Computations, Alg. 8.3.1, 8.3.2 and 8.3.3; the orthogonal factor
+// formed from the reflectors by backward accumulation, Sec. 5.1.6).  For n = 9 this costs about a quarter of the FP64 operations of
 // cyclic Jacobi (which needs about seven sweeps of 36 rotations here).  All
 // array indices are compile-time constants (registers, no scratch); the only
 // data-dependent control is the number of QR steps per deflation stage, a loop
-// that the lanes of a wave leave together once every lane has converged.
+// that the lanes of a wave leave together once every lane has converged, and
+// the start of the unreduced block, which selects identity rotations.
 //
 // Written for host and device so that it can be checked on the CPU.
 #pragma once
@@ -58,26 +60,38 @@ BFC_HD void eig_givens(double x, double z, double& c, double& s, double& r) {
   }
 }
 
-// One implicit symmetric QR step with Wilkinson shift on the leading block
-// 0..L of the tridiagonal (d, e); the rotations are then applied to the
+// One implicit symmetric QR step with Wilkinson shift on the unreduced block
+// p..L of the tridiagonal (d, e), p known at run time only (e[p-1] = 0, or
+// p = 0): the loop runs over 0..L with compile-time indices and the
+// rotations below p are the identity (c = 1, s = 0 leave every entry exactly
+// as it was), so a block split inside the matrix gets its own QR steps
+// (Golub and Van Loan, Alg. 8.3.3).  The rotations are then applied to the
 // columns of Z (N x N, row-major) one row at a time (each element sees the
 // same operations in the same order as rotation by rotation; a row in flight
 // at a time keeps the live set small).
-template <int N, int L> BFC_HD void eig_qr_step(double* d, double* e, double (*Z)[N]) {
+template <int N, int L> BFC_HD void eig_qr_step(double* d, double* e, double (*Z)[N], int p) {
   const double dl = 0.5 * (d[L - 1] - d[L]);
   const double b2 = e[L - 1] * e[L - 1];
   const double rt = sqrt(dl * dl + b2);
   const double den = dl >= 0.0 ? dl + rt : dl - rt;
   const double mu = den != 0.0 ? d[L] - b2 / den : d[L];
-  double x = d[0] - mu, z = e[0];
+  double x = 0.0, z = 0.0;
   double cr[L], sr[L];
 #pragma unroll
   for (int k = 0; k < L; ++k) {
+    if (k == p) {
+      x = d[k] - mu;
+      z = e[k];
+    }
     double c, s, r;
     eig_givens(x, z, c, s, r);
+    if (k < p) {
+      c = 1.0;
+      s = 0.0;
+    }
     cr[k] = c;
     sr[k] = s;
-    if (k > 0) e[k - 1] = r;
+    if (k > p) e[k - 1] = r;
     const double a = d[k], b = e[k], cc = d[k + 1];
     const double c2 = c * c, s2 = s * s, cs = c * s;
     d[k] = c2 * a + 2.0 * cs * b + s2 * cc;
@@ -102,28 +116,46 @@ template <int N, int L> BFC_HD void eig_qr_step(double* d, double* e, double (*Z
   }
 }
 
-// Deflation stages L = N-1 down to 1: QR steps on the block 0..L until
-// |e[L-1]| <= tol * anorm on every lane (at most 48 steps).
-template <int N, int L> BFC_HD void eig_stages(double* d, double* e, double (*Z)[N], double lim) {
+// Deflation stages L = N-1 down to 1: QR steps on the unreduced block that
+// ends at L until |e[L-1]| <= lim on every lane (at most 48 steps a stage).
+// Before each step, off-diagonal entries at or below lim inside the block are
+// set to zero and the block starts after the last of them.  Returns false on
+// a lane whose stage hit the step limit (its projection is then not exact).
+template <int N, int L> BFC_HD bool eig_stages(double* d, double* e, double (*Z)[N], double lim) {
   if constexpr (L >= 1) {
-    for (int it = 0; it < 48; ++it) {
+    bool ok = true;
+    int it = 0;
+    for (; it < 48; ++it) {
       const bool conv = !(fabs(e[L - 1]) > lim);
       if (eig_all(conv)) break;
-      if (!conv) eig_qr_step<N, L>(d, e, Z);
+      if (!conv) {
+        int p = 0;
+#pragma unroll
+        for (int k = 0; k + 1 < L; ++k)
+          if (!(fabs(e[k]) > lim)) {
+            e[k] = 0.0;
+            p = k + 1;
+          }
+        eig_qr_step<N, L>(d, e, Z, p);
+      }
     }
-    eig_stages<N, L - 1>(d, e, Z, lim);
+    if (it == 48 && fabs(e[L - 1]) > lim) ok = false;
+    e[L - 1] = 0.0;
+    return eig_stages<N, L - 1>(d, e, Z, lim) && ok;
   }
+  return true;
 }
 
 // A: upper triangle of the symmetric N x N input (destroyed); P: upper
 // triangle of A+.  tol: relative size (to |A|) below which an off-diagonal
-// element of the tridiagonal counts as zero.
+// element of the tridiagonal counts as zero.  Returns false when a deflation
+// stage did not converge within its step limit.
 //
 // Live data is kept small so that the whole projection stays in registers:
 // the reduction stores its reflectors in the entries of A it zeroes (Z is not
 // carried through it), Z is formed from them afterwards, and A+ is built row
 // by row while the rows of Z that are no longer needed die.
-template <int N> BFC_HD void psd_project(double* A, double* P, double tol) {
+template <int N> BFC_HD bool psd_project(double* A, double* P, double tol) {
   // Householder reduction: step k zeroes entries k+2.. of row k and keeps
   // v[k+2..] there, v[k+1] in vh[k] and 2 / (v^T v) in bh[k] (0: identity)
   double vh[N > 2 ? N - 2 : 1], bh[N > 2 ? N - 2 : 1];
@@ -199,7 +231,7 @@ template <int N> BFC_HD void psd_project(double* A, double* P, double tol) {
       for (int i = k + 1; i < N; ++i) Z[i][j] -= w * v[i];
     }
   }
-  eig_stages<N, N - 1>(d, e, Z, tol * anorm);
+  const bool ok = eig_stages<N, N - 1>(d, e, Z, tol * anorm);
   double lam[N];
 #pragma unroll
   for (int k = 0; k < N; ++k) lam[k] = fmax(d[k], 0.0);
@@ -216,6 +248,7 @@ template <int N> BFC_HD void psd_project(double* A, double* P, double tol) {
       P[eig_uix<N>(i, j)] = acc;
     }
   }
+  return ok;
 }
 
 }  // namespace bfc

@@ -74,6 +74,7 @@ enum { H_ZERO = 0, H_PP = 1, H_PE = 2, H_TRI = 3 };
 struct PairOut {
   double E;
   int kind;      // H_*
+  int eig_ok;    // 0: the projection's QR iteration hit its step limit
   int sl[3];     // PP: slots (s0, s1); PE: slots (point, e0, e1)
   double A[45];  // TRI: projected 9 x 9 (upper); PE: projected 6 x 6 (upper, 21);
                  // PP: r (3), eigenvalue along r, across r, 1 / D
@@ -174,7 +175,7 @@ __device__ __forceinline__ void eval_pe(const d3* P, int sp, int se0, int se1, d
     G[3 * se0 + i] = -grx - gex;
     G[3 * se1 + i] = gex;
   }
-  psd_project<6>(A, h.A, tol);
+  h.eig_ok = psd_project<6>(A, h.A, tol);
   h.kind = H_PE;
   h.sl[0] = sp;
   h.sl[1] = se0;
@@ -280,7 +281,7 @@ __device__ __forceinline__ void eval_tri(const d3* P, bool is_pt, double a, doub
       G[9 + i] = gv;
     }
   }
-  psd_project<9>(A, h.A, tol);
+  h.eig_ok = psd_project<9>(A, h.A, tol);
   h.kind = H_TRI;
 }
 

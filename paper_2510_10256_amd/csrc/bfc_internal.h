@@ -53,6 +53,7 @@ struct SceneDev {
   int filter;  // 0 paper, 1 none, 2 cull
   int mixed;   // 1: projection converged to the mixed-precision tolerance
   int pq;      // threads per broad-phase query (2, 4 or 8)
+  unsigned* status;  // the scene's device status word (BF_S_* bits)
 };
 
 // Broad-phase scratch (device pointers inside the scene workspace).

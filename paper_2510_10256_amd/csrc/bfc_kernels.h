@@ -22,7 +22,11 @@ constexpr int SCAN_LB_STATE = 2 * SCAN_LB_TILES + 8;
 // ints of scratch for a scan of n elements
 inline long long scan_tmp_ints(long long n) { return SCAN_LB_STATE + (n + SCAN_TILE - 1) / SCAN_TILE + 1 + 16; }
 
-void scan_excl(const int* in, int* out, const int* n_dev, int n_max, int* tmp, hipStream_t st);
+// Exclusive scan; a single-pass scan that summed a missing tile total
+// itself sets BF_S_SCAN_SLOW in *status (may be null).  g_scan_polls bounds
+// that scan's wait for each earlier tile (loads of its published total).
+extern int g_scan_polls;
+void scan_excl(const int* in, int* out, const int* n_dev, int n_max, int* tmp, unsigned* status, hipStream_t st);
 
 // Broad phase over the positions x (FP64 [V,3]) at inflation S.h.
 void run_broad(const SceneDev& S, const double* x, const double* pdisp, const BroadWs& W, int* oi, int* oj,
@@ -72,6 +76,9 @@ void run_asm_values(const SceneDev& S, const int* ai, const int* aj, const unsig
 
 int run_components(const SceneDev& S, int* lab, int* flag, int* scan, int* comp, int* scan_tmp, int* d_changed,
                    hipStream_t st);
+
+// a[0..n) = 0 for n <= 64 (a kernel: unlike a memset it may be captured)
+void run_zero_i64(long long* a, int n, hipStream_t st);
 
 // Lift rest parameters to 3D points (rods (s,0,0); shells (u1,u2,0)).
 void run_lift_ref(const SceneDev& S, double* xref, hipStream_t st);

@@ -164,10 +164,12 @@ __global__ __launch_bounds__(256) void k_scan_down(const int* in, int* out, cons
 // total and its "published" flag share one 64-bit word, written and read
 // with device-scope atomics (no other data passes between work-groups, so
 // no release or acquire is needed).  The last work-group to finish clears the
-// words and the counters for the next scan.  The poll is bounded all the same
-// (a total that never came would give a wrong sum, not a hang).
+// words and the counters for the next scan.  The poll is bounded all the
+// same (max_polls loads): a total still missing then is summed from the
+// input tile by the waiting thread itself, so the scan stays exact, and
+// BF_S_SCAN_SLOW is raised in the status word.
 __global__ __launch_bounds__(256) void k_scan_lb(const int* in, int* out, const int* n_dev, int n_const,
-                                                 int* state) {
+                                                 int* state, int max_polls, unsigned* status) {
   unsigned long long* word = (unsigned long long*)state;  // [SCAN_LB_TILES] 1 << 32 | total
   unsigned* ctr = (unsigned*)(state + 2 * SCAN_LB_TILES);  // ticket, done
   __shared__ int s_tile;
@@ -189,12 +191,18 @@ __global__ __launch_bounds__(256) void k_scan_lb(const int* in, int* out, const 
     __hip_atomic_store(&word[tile], (1ull << 32) | (unsigned)tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   int earlier = 0;
   if ((int)threadIdx.x < tile) {
-    unsigned long long w;
-    int polls = 0;
-    do {
+    unsigned long long w = 0;
+    for (int polls = 0; polls < max_polls; ++polls) {
       w = __hip_atomic_load(&word[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } while ((w >> 32) == 0 && ++polls < (1 << 22));
-    earlier = (int)(unsigned)w;
+      if ((w >> 32) != 0) break;
+    }
+    if ((w >> 32) != 0) {
+      earlier = (int)(unsigned)w;
+    } else {  // not published within the bound: sum that tile of the input here
+      const int b0 = threadIdx.x * SCAN_TILE, b1 = min(n, b0 + SCAN_TILE);
+      for (int i = b0; i < b1; ++i) earlier += in[i];
+      if (status) atomicOr(status, (unsigned)BF_S_SCAN_SLOW);
+    }
   }
   int run = excl + (int)block_sum256(earlier);
 #pragma unroll
@@ -251,7 +259,9 @@ __global__ __launch_bounds__(1024) void k_scan1(const int* in, int* out, const i
   }
 }
 
-void scan_excl(const int* in, int* out, const int* n_dev, int n_max, int* tmp, hipStream_t st) {
+int g_scan_polls = 1 << 22;
+
+void scan_excl(const int* in, int* out, const int* n_dev, int n_max, int* tmp, unsigned* status, hipStream_t st) {
   if (n_max <= SCAN1_MAX) {
     hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, st, in, out, n_dev, n_max);
     return;
@@ -259,7 +269,7 @@ void scan_excl(const int* in, int* out, const int* n_dev, int n_max, int* tmp, h
   int nb = (n_max + SCAN_TILE - 1) / SCAN_TILE;
   if (nb < 1) nb = 1;
   if (nb <= SCAN_LB_TILES) {
-    hipLaunchKernelGGL(k_scan_lb, dim3(nb), dim3(256), 0, st, in, out, n_dev, n_max, tmp);
+    hipLaunchKernelGGL(k_scan_lb, dim3(nb), dim3(256), 0, st, in, out, n_dev, n_max, tmp, g_scan_polls, status);
     return;
   }
   int* part = tmp + SCAN_LB_STATE;
@@ -1029,6 +1039,7 @@ __global__ __launch_bounds__(64) void k_eval(SceneDev S, const double* x, const 
     PairOut h;
     h.E = 0.0;
     h.kind = H_ZERO;
+    h.eig_ok = 1;
     if (k < n) {
       int type = at[k], code = acode[k], fl = aflags[k];
       int v[4];
@@ -1045,6 +1056,7 @@ __global__ __launch_bounds__(64) void k_eval(SceneDev S, const double* x, const 
       }
       E[k] = h.E;
     }
+    if (__ballot(!h.eig_ok) != 0ull && lane == 0 && S.status) atomicOr(S.status, (unsigned)BF_S_EIG_NOCONV);
     double e = h.E, y = 0.0, z = 0.0;
     wave_ordered_sum3(e, y, z);
     if (lane == 0 && epart) epart[k0 / 64] = e;
@@ -2416,6 +2428,10 @@ __global__ void k_zero_ll(long long* a, int n, long long* b, int m) {
   if (b && threadIdx.x < m) b[threadIdx.x] = 0;
 }
 
+void run_zero_i64(long long* a, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_ll, dim3(1), dim3(64), 0, st, a, n, nullptr, 0);
+}
+
 void run_lift_ref(const SceneDev& S, double* xref, hipStream_t st) {
   hipLaunchKernelGGL(k_lift_ref, dim3(nblocks(S.nv)), dim3(256), 0, st, S, xref);
 }
@@ -2446,7 +2462,7 @@ void run_broad(const SceneDev& S, const double* x, const double* pdisp, const Br
   // cell counts are zero on entry: the scatter below returns them to zero
   hipLaunchKernelGGL(k_count, dim3(nblocks(nstored)), dim3(256), 0, st, nstored, S.ne, W.box, W.grid, W.cell_cnt,
                      W.cell_of, W.seg_count);
-  scan_excl(W.cell_cnt, W.cell_start, nscan_dev, nscan_max, W.scan_tmp, st);
+  scan_excl(W.cell_cnt, W.cell_start, nscan_dev, nscan_max, W.scan_tmp, status, st);
   hipLaunchKernelGGL(k_scatter, dim3(nblocks(nstored)), dim3(256), 0, st, nstored, W.box, W.cell_of, W.cell_cnt,
                      W.cell_start, W.placed_id, W.placed_box);
   hipLaunchKernelGGL(k_cell_order, dim3(nblocks(nstored)), dim3(256), 0, st, nstored, W.cell_of, W.cell_start,
@@ -2518,7 +2534,7 @@ void run_narrow(const SceneDev& S, const double* x, const int* ci, const int* cj
                 long long* counters, unsigned* status, hipStream_t st) {
   int G = (int)((ccap + NW_TILE - 1) / NW_TILE);
   hipLaunchKernelGGL(k_narrow, dim3(G), dim3(256), 0, st, S, x, ci, cj, ct, ccount, ccap, W);
-  scan_excl(W.kcnt, W.kofs, nullptr, 3 * G + 1, W.scan_tmp, st);
+  scan_excl(W.kcnt, W.kofs, nullptr, 3 * G + 1, W.scan_tmp, status, st);
   hipLaunchKernelGGL(k_compact, dim3(G), dim3(256), 0, st, W, G, ai, aj, at, acode, aflags, adist, acap, act_count,
                      counters, status);
 }
@@ -2543,7 +2559,7 @@ void run_asm_structure(const SceneDev& S, const int* ai, const int* aj, const un
   // incidence counts are zero on entry: k_inc_fill returns them to zero
   hipLaunchKernelGGL(k_inc_count, dim3(nblocks(acap)), dim3(256), 0, st, S, ai, aj, at, aflags, nact, acap,
                      A.inc_cnt, A.mid + S.nv, A.big + S.nv);
-  scan_excl(A.inc_cnt, A.inc_off, nullptr, S.nv + 1, A.scan_tmp, st);
+  scan_excl(A.inc_cnt, A.inc_off, nullptr, S.nv + 1, A.scan_tmp, S.status, st);
   hipLaunchKernelGGL(k_inc_fill, dim3(nblocks(acap)), dim3(256), 0, st, S, ai, aj, at, aflags, nact, acap, A.inc_cnt,
                      A.inc_off, A.inc);
   const int rows_grid = std::max(1, std::min((S.nv + 3) / 4, 1 << 20));  // four rows a block
@@ -2558,7 +2574,7 @@ void run_asm_values(const SceneDev& S, const int* ai, const int* aj, const unsig
                     double* g, int* row_ptr, int* col, double* val, long long bsr_cap, long long* nnzb,
                     const AsmWs& A, unsigned* status, hipStream_t st) {
   const unsigned long long* nact = (const unsigned long long*)act_count;
-  scan_excl(A.rowcnt, row_ptr, nullptr, S.nv + 1, A.scan_tmp, st);
+  scan_excl(A.rowcnt, row_ptr, nullptr, S.nv + 1, A.scan_tmp, status, st);
   const int rows_grid = std::max(1, std::min((S.nv + 3) / 4, 1 << 20));  // four rows a block
   const int mid_grid = std::min(rows_grid, 8192);                          // listed rows, strided
   hipLaunchKernelGGL(k_row_b, dim3(mid_grid + rows_grid), dim3(64), 0, st, S, ai, aj, at, A.inc_off, A.inc, A.colbuf,
@@ -2582,7 +2598,7 @@ int run_components(const SceneDev& S, int* lab, int* flag, int* scan, int* comp,
     if (!h_changed) break;
   }
   hipLaunchKernelGGL(k_cc_isroot, dim3(nblocks(S.nv)), dim3(256), 0, st, lab, S.nv, flag);
-  scan_excl(flag, scan, nullptr, S.nv, scan_tmp, st);
+  scan_excl(flag, scan, nullptr, S.nv, scan_tmp, S.status, st);
   hipLaunchKernelGGL(k_cc_label, dim3(nblocks(S.nv)), dim3(256), 0, st, lab, scan, S.nv, comp);
   int last_scan = 0, last_flag = 0;
   if (hipMemcpyAsync(&last_scan, scan + S.nv - 1, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) return -1;

@@ -76,6 +76,54 @@ def _cases(n, rng):
     return np.array(out)
 
 
+def _split_cases(n, rng):
+    """Matrices whose tridiagonal form splits inside (an exact zero off the
+    diagonal above the last entry): a null row and column, block-diagonal
+    matrices, split tridiagonals, and a dense block beside a null block."""
+    out = []
+    for k in range(n):  # symmetric with row/column k zero
+        B = rng.normal(size=(n, n))
+        A = B + B.T
+        A[k, :] = 0.0
+        A[:, k] = 0.0
+        out.append(A)
+    for p in range(1, n):  # two dense diagonal blocks, sizes p and n - p
+        A = np.zeros((n, n))
+        B1 = rng.normal(size=(p, p))
+        B2 = rng.normal(size=(n - p, n - p))
+        A[:p, :p] = B1 + B1.T
+        A[p:, p:] = B2 + B2.T
+        out.append(A)
+    for p in range(1, n - 1):  # tridiagonal with e[p-1] = 0 (a split above the bottom pair)
+        d = rng.normal(size=n)
+        e = rng.normal(size=n - 1)
+        e[p - 1] = 0.0
+        out.append(np.diag(d) + np.diag(e, 1) + np.diag(e, -1))
+    for _ in range(20):  # block-diagonal with random orthogonal blocks and mixed signs, permuted
+        p = int(rng.integers(1, n))
+        Q1, _ = np.linalg.qr(rng.normal(size=(p, p)))
+        Q2, _ = np.linalg.qr(rng.normal(size=(n - p, n - p)))
+        A = np.zeros((n, n))
+        A[:p, :p] = Q1 @ np.diag(rng.normal(size=p)) @ Q1.T
+        A[p:, p:] = Q2 @ np.diag(rng.normal(size=n - p)) @ Q2.T
+        P = np.eye(n)[rng.permutation(n)]
+        out.append(P @ A @ P.T)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("n", [6, 9])
+def test_projection_split_tridiagonal(exe, n):
+    # a zero inside the tridiagonal decouples the blocks: each block needs its
+    # own QR steps (a chase started at the top stops at the zero)
+    rng = np.random.default_rng(11 + n)
+    mats = _split_cases(n, rng)
+    got = _project(exe, mats)
+    ref = _reference(mats)
+    scale = np.linalg.norm(mats, axis=(1, 2)) + 1e-300
+    err = np.linalg.norm(got - ref, axis=(1, 2)) / scale
+    assert err.max() < 1e-13, (err.max(), int(err.argmax()))
+
+
 @pytest.mark.parametrize("n", [6, 9])
 def test_projection_matches_lapack(exe, n):
     rng = np.random.default_rng(5 + n)
