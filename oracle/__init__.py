@@ -10,9 +10,14 @@ This module is argument marshalling plus the plain assembly of the per-pair
 results (sums over pairs, Sec. 3 and App. A: the global energy, gradient and
 Hessian fed to the Newton solve).
 
-Functions whose parity is not pinned by an independent check: none; see
-``tests/test_oracle_pins.py`` and ``tests/test_oracle_accd.py`` for the pin
-of each function.
+Functions whose parity is not pinned by an independent check: none.  The
+pins of each function are in ``tests/test_oracle_pins.py`` (distances,
+barrier, derivatives, projection, decisions, precompute, rest states),
+``tests/test_oracle_assembly.py`` (assembly against finite differences of
+the assembled energy and gradient; the binary128 derivative branch against
+50-digit arithmetic; exact ties against rational arithmetic),
+``tests/test_oracle_accd.py``, ``tests/test_oracle_core.py``,
+``tests/test_oracle_cull.py`` and ``tests/test_oracle_friction.py``.
 """
 from __future__ import annotations
 
@@ -73,6 +78,7 @@ def lib():
         L.orc_case_distance.argtypes = [C.c_int32, P, P, P, P]
         L.orc_pair_barrier.argtypes = [C.c_int32, P, C.c_double, C.c_double, C.c_double,
                                        P, P, P, P, P, C.c_int32]
+        L.orc_pair_barrier_code.argtypes = [C.c_int32, P, C.c_double, C.c_double, C.c_double, P, P, P, P, C.c_int32]
         L.orc_barrier_scalar.argtypes = [C.c_double, C.c_double, C.c_double, P, P, P]
         L.orc_psd_project.argtypes = [C.c_int32, P, P, P]
         L.orc_accd_pair.argtypes = [C.c_int32, P, P, C.c_double, C.c_double, C.c_int32, P, P]
@@ -197,6 +203,19 @@ def pair_barrier(ptype, X, a, eta, kappa=1.0, quad=False):
     return dict(E=float(E[0]), G=G, Hraw=Hraw, Hpsd=Hpsd, code=int(code[0]))
 
 
+def pair_barrier_code(code, X, a, eta, kappa=1.0, quad=False):
+    """pair_barrier with the distance sub-case `code` given instead of
+    classified (for pairs at a boundary between sub-cases of equal distance)."""
+    X = np.ascontiguousarray(X, np.float64).reshape(12)
+    E = np.zeros(1)
+    G = np.zeros(12)
+    Hraw = np.zeros((12, 12))
+    Hpsd = np.zeros((12, 12))
+    lib().orc_pair_barrier_code(int(code), _p(X), float(a), float(eta), float(kappa),
+                                _p(E), _p(G), _p(Hraw), _p(Hpsd), int(bool(quad)))
+    return dict(E=float(E[0]), G=G, Hraw=Hraw, Hpsd=Hpsd, code=int(code))
+
+
 def barrier_scalar(d, a, eta):
     o = np.zeros(3)
     lib().orc_barrier_scalar(float(d), float(a), float(eta), _p(o[0:1]), _p(o[1:2]), _p(o[2:3]))
@@ -212,13 +231,25 @@ def psd_project(A):
     return Ap, ev
 
 
-def assemble(res, n_verts):
+def _stencil(res, k):
+    """Global vertex ids of active pair k's four local slots."""
+    return res["verts"][k]
+
+
+def _block(H, r, c):
+    """The 3x3 block (local slot r, local slot c) of a 12x12 pair matrix."""
+    return H[3 * r:3 * r + 3, 3 * c:3 * c + 3]
+
+
+def assemble(res, n_verts, hess="Hpsd"):
     """Plain sums of the active pairs' results (row-major BSR with 3x3 blocks).
 
     Every active pair contributes its 12-vector to the gradient of its four
     stencil vertices, and all 16 3x3 blocks of its projected Hessian to the
     block pattern of its four stencil vertices.  Returns E, g[V,3] and the BSR
     arrays row_ptr[V+1], col[nnzb], val[nnzb,3,3] with columns sorted per row.
+    hess names the per-pair matrices summed ("Hpsd"; "Hraw", the Hessians
+    before projection, for the finite-difference pins of this function).
     """
     act = (res["flags"] & F_ACTIVE) != 0
     feas = act & ((res["flags"] & F_INFEASIBLE) == 0)
@@ -227,14 +258,14 @@ def assemble(res, n_verts):
     blocks = {}
     idx = np.nonzero(feas)[0]
     for k in idx:
-        vs = res["verts"][k]
+        vs = _stencil(res, k)
         G = res["G"][k].reshape(4, 3)
-        H = res["Hpsd"][k]
+        H = res[hess][k]
         for r in range(4):
             g[vs[r]] += G[r]
             for c in range(4):
                 key = (int(vs[r]), int(vs[c]))
-                blk = H[3 * r:3 * r + 3, 3 * c:3 * c + 3]
+                blk = _block(H, r, c)
                 if key in blocks:
                     blocks[key] = blocks[key] + blk
                 else:

@@ -25,7 +25,9 @@
 //     does not spell out the projection, this is the reading used);
 //   * decisions "d < a", "d <= eta" and "dbar < h" made in double precision
 //     and, inside a relative guard band of 1e-9, re-made in binary128
-//     (__float128) from the same formula;
+//     (__float128) from the same formula, and within 1e-20 of the threshold
+//     in exact integer arithmetic: every decision is that of the exact
+//     distance of the double inputs;
 //   * line search (Sec. 3.3, last paragraph; App. A): additive CCD (ACCD, Li
 //     et al. 2021) per pair with the offset of Eq. 4 (eta for ordinary pairs,
 //     0 for filtered stencils), over the pairs whose boxes swept from x to
@@ -57,8 +59,6 @@
 
 typedef __float128 f128;
 
-// relative width of an exact tie in the extended-precision decisions
-static const double kTie = 1e-24;
 
 namespace {
 
@@ -159,6 +159,154 @@ const Case kCases[16] = {
   {1, 0, 2, 3, -1}, {1, 1, 2, 3, -1}, {1, 2, 0, 1, -1}, {1, 3, 0, 1, -1}, {3, 0, 1, 2, 3},
 };
 
+// ---------------------------------------------------------------------------
+// Exact rationals (numerator and denominator as sign-magnitude integers with
+// 32-bit limbs, schoolbook arithmetic, no reduction): the last resort of the
+// threshold decisions.  Every double is an exact rational, so the same
+// formulas evaluated on Rat give the exact value of the double inputs.
+// ---------------------------------------------------------------------------
+struct Big {
+  bool neg = false;
+  std::vector<uint32_t> m;  // magnitude, least significant limb first, no leading zero limbs
+};
+inline void trim(std::vector<uint32_t>& a) { while (!a.empty() && a.back() == 0) a.pop_back(); }
+inline int cmp_mag(const std::vector<uint32_t>& a, const std::vector<uint32_t>& b) {
+  if (a.size() != b.size()) return a.size() < b.size() ? -1 : 1;
+  for (size_t k = a.size(); k-- > 0;)
+    if (a[k] != b[k]) return a[k] < b[k] ? -1 : 1;
+  return 0;
+}
+inline std::vector<uint32_t> add_mag(const std::vector<uint32_t>& a, const std::vector<uint32_t>& b) {
+  std::vector<uint32_t> r(std::max(a.size(), b.size()) + 1, 0);
+  uint64_t carry = 0;
+  for (size_t k = 0; k < r.size(); ++k) {
+    uint64_t t = carry + (k < a.size() ? a[k] : 0) + (k < b.size() ? b[k] : 0);
+    r[k] = (uint32_t)t;
+    carry = t >> 32;
+  }
+  trim(r);
+  return r;
+}
+inline std::vector<uint32_t> sub_mag(const std::vector<uint32_t>& a, const std::vector<uint32_t>& b) {  // a >= b
+  std::vector<uint32_t> r(a.size(), 0);
+  int64_t borrow = 0;
+  for (size_t k = 0; k < a.size(); ++k) {
+    int64_t t = (int64_t)a[k] - (k < b.size() ? b[k] : 0) - borrow;
+    borrow = t < 0;
+    r[k] = (uint32_t)(t + (borrow ? (int64_t)1 << 32 : 0));
+  }
+  trim(r);
+  return r;
+}
+inline Big big_add(const Big& a, const Big& b) {
+  Big r;
+  if (a.neg == b.neg) {
+    r.m = add_mag(a.m, b.m);
+    r.neg = a.neg;
+  } else if (cmp_mag(a.m, b.m) >= 0) {
+    r.m = sub_mag(a.m, b.m);
+    r.neg = a.neg;
+  } else {
+    r.m = sub_mag(b.m, a.m);
+    r.neg = b.neg;
+  }
+  if (r.m.empty()) r.neg = false;
+  return r;
+}
+inline Big big_neg(Big a) {
+  if (!a.m.empty()) a.neg = !a.neg;
+  return a;
+}
+inline Big big_mul(const Big& a, const Big& b) {
+  Big r;
+  if (a.m.empty() || b.m.empty()) return r;
+  r.m.assign(a.m.size() + b.m.size(), 0);
+  for (size_t i = 0; i < a.m.size(); ++i) {
+    uint64_t carry = 0;
+    for (size_t j = 0; j < b.m.size(); ++j) {
+      uint64_t t = (uint64_t)a.m[i] * b.m[j] + r.m[i + j] + carry;
+      r.m[i + j] = (uint32_t)t;
+      carry = t >> 32;
+    }
+    r.m[i + b.m.size()] = (uint32_t)carry;
+  }
+  trim(r.m);
+  r.neg = a.neg != b.neg;
+  return r;
+}
+inline Big big_pow2(int k) {  // 2^k, k >= 0
+  Big r;
+  r.m.assign(k / 32 + 1, 0);
+  r.m[k / 32] = 1u << (k % 32);
+  return r;
+}
+inline Big big_u64(uint64_t v) {
+  Big r;
+  r.m = {(uint32_t)v, (uint32_t)(v >> 32)};
+  trim(r.m);
+  return r;
+}
+inline int big_sign(const Big& a) { return a.m.empty() ? 0 : (a.neg ? -1 : 1); }
+
+struct Rat {
+  Big n, d;  // value n / d, d > 0
+  Rat() { d = big_u64(1); }
+  Rat(int v) {  // small integers (the constants of the formulas)
+    n = big_u64((uint64_t)(v < 0 ? -(int64_t)v : v));
+    n.neg = v < 0 && !n.m.empty();
+    d = big_u64(1);
+  }
+  explicit Rat(double v) {  // exact value of a finite double: M 2^e
+    d = big_u64(1);
+    if (v == 0.0) return;
+    int E;
+    const double f = std::frexp(std::fabs(v), &E);   // |v| = f 2^E, f in [0.5, 1)
+    n = big_u64((uint64_t)std::ldexp(f, 53));         // |v| = n 2^(E - 53)
+    const int e = E - 53;
+    if (e >= 0) n = big_mul(n, big_pow2(e));
+    else d = big_pow2(-e);
+    n.neg = v < 0.0;
+  }
+};
+inline Rat operator+(const Rat& a, const Rat& b) {
+  Rat r;
+  r.n = big_add(big_mul(a.n, b.d), big_mul(b.n, a.d));
+  r.d = big_mul(a.d, b.d);
+  return r;
+}
+inline Rat operator-(const Rat& a) {
+  Rat r = a;
+  r.n = big_neg(a.n);
+  return r;
+}
+inline Rat operator-(const Rat& a, const Rat& b) { return a + (-b); }
+inline Rat operator*(const Rat& a, const Rat& b) {
+  Rat r;
+  r.n = big_mul(a.n, b.n);
+  r.d = big_mul(a.d, b.d);
+  return r;
+}
+inline Rat operator/(const Rat& a, const Rat& b) {  // b != 0
+  Rat r;
+  r.n = big_mul(a.n, b.d);
+  r.d = big_mul(a.d, b.n);
+  if (r.d.neg) {
+    r.d.neg = false;
+    r.n = big_neg(r.n);
+  }
+  return r;
+}
+inline int rat_cmp(const Rat& a, const Rat& b) { return big_sign(big_add(big_mul(a.n, b.d), big_neg(big_mul(b.n, a.d)))); }
+inline bool operator<(const Rat& a, const Rat& b) { return rat_cmp(a, b) < 0; }
+inline bool operator>(const Rat& a, const Rat& b) { return rat_cmp(a, b) > 0; }
+inline bool operator<=(const Rat& a, const Rat& b) { return rat_cmp(a, b) <= 0; }
+inline bool operator>=(const Rat& a, const Rat& b) { return rat_cmp(a, b) >= 0; }
+inline bool operator==(const Rat& a, const Rat& b) { return rat_cmp(a, b) == 0; }
+inline bool operator<(const Rat& a, int b) { return a < Rat(b); }
+inline bool operator>(const Rat& a, int b) { return a > Rat(b); }
+inline bool operator<=(const Rat& a, int b) { return a <= Rat(b); }
+inline bool operator>=(const Rat& a, int b) { return a >= Rat(b); }
+
 // Squared distance of sub-case `code` evaluated on 4 local vertices X[12].
 template <class S> S D_case(int code, const S* X) {
   const Case& c = kCases[code];
@@ -247,17 +395,25 @@ inline Dist classify(int ptype, const double* X) { return ptype == 0 ? classify_
 // of sub-case `code` at the double inputs X, where T is an exact squared
 // threshold (Tq, with Td its double approximation).  Outside a 1e-9 relative
 // band the double value D decides; inside it, the formula is re-evaluated in
-// binary128.  A value within 1e-24 (relative) of T is a tie -- exact ties of
-// the geometry (lattice-aligned primitives) reach the formulas' divisions as
-// rounding noise of that size -- and a tie counts as d = thr: not below it,
-// but at most it.
+// binary128 (relative error far below 1e-28 for the formulas at the edge
+// angles they are used for); within 1e-20 of T, where that rounding could
+// still flip the answer (exact ties of lattice geometry land there), the
+// decision is taken in exact integer arithmetic.
 bool decide(int code, const double* X, double D, double Td, f128 Tq, bool lt, bool* used_ext) {
   if (std::fabs(D - Td) > 1e-9 * Td) return lt ? (D < Td) : (D <= Td);
   if (used_ext) *used_ext = true;
   f128 Xq[12];
   for (int k = 0; k < 12; ++k) Xq[k] = (f128)X[k];
   f128 Dq = D_case<f128>(code, Xq);
-  return lt ? (Dq < Tq * (1 - (f128)kTie)) : (Dq <= Tq * (1 + (f128)kTie));
+  f128 gap = Dq - Tq;
+  if (gap < 0) gap = -gap;
+  if (gap > Tq * (f128)1e-20) return lt ? (Dq < Tq) : (Dq <= Tq);
+  // exact: T is the square of a double, or a double (at most 106 bits: two doubles)
+  const double Th = (double)Tq, Tl = (double)(Tq - (f128)Th);
+  Rat Xr[12];
+  for (int k = 0; k < 12; ++k) Xr[k] = Rat(X[k]);
+  const int sg = rat_cmp(D_case<Rat>(code, Xr), Rat(Th) + Rat(Tl));
+  return lt ? sg < 0 : sg <= 0;
 }
 inline f128 sq(double v) { return (f128)v * (f128)v; }  // exact square of a double
 
@@ -487,7 +643,7 @@ bool ref_dist(const Mesh& m, int ptype, int i, int j, S* q, double* dbar_rod) {
 
 // Is the pair in the stencil set with reference distance below h (filtered)?
 // Shells: decided on dbar^2 in double outside a 1e-9 relative band around
-// h^2 (and away from 0), in binary128 inside it.
+// h^2 (and away from 0), in binary128 inside it, exactly within 1e-20 of h^2.
 bool is_filtered(const Mesh& m, int ptype, int i, int j) {
   if (m.filter_mode != 0) return false;
   double g;
@@ -503,7 +659,15 @@ bool is_filtered(const Mesh& m, int ptype, int i, int j) {
   f128 q;
   ref_dist<f128>(m, ptype, i, j, &q, &g);
   f128 hq = (f128)m.h * (f128)m.h;
-  return q > hq * (f128)kTie && q < hq * (1 - (f128)kTie);
+  // binary128 is exact for every branch test and for zero (differences and
+  // 2D cross products of doubles fit its mantissa); only the division c^2/ee
+  // rounds, which matters within 1e-20 of h^2: decide that band exactly
+  f128 gap = q - hq;
+  if (gap < 0) gap = -gap;
+  if (gap > hq * (f128)1e-20) return q > 0 && q < hq;
+  Rat qr;
+  ref_dist<Rat>(m, ptype, i, j, &qr, &g);
+  return qr > 0 && qr < Rat(m.h) * Rat(m.h);
 }
 
 // Culling comparison mode (Kaldor et al.): two edges of the same polyline
@@ -1073,6 +1237,16 @@ void orc_pair_barrier(int32_t ptype, const double* X, double a, double eta, doub
   *code = d.code;
   if (quad) energy_derivs<f128>(d.code, X, a, eta, kappa, E, G, Hraw);
   else energy_derivs<double>(d.code, X, a, eta, kappa, E, G, Hraw);
+  psd_project(12, Hraw, Hpsd, nullptr);
+}
+
+// The same with the distance sub-case given: at a region boundary, where
+// several sub-cases give the same distance, each one's formula is a valid
+// one-sided derivative (the tests accept the one the GPU took there).
+void orc_pair_barrier_code(int32_t code, const double* X, double a, double eta, double kappa,
+                           double* E, double* G, double* Hraw, double* Hpsd, int32_t quad) {
+  if (quad) energy_derivs<f128>(code, X, a, eta, kappa, E, G, Hraw);
+  else energy_derivs<double>(code, X, a, eta, kappa, E, G, Hraw);
   psd_project(12, Hraw, Hpsd, nullptr);
 }
 

@@ -3,6 +3,8 @@ import os
 import re
 import ctypes
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -35,3 +37,31 @@ def test_argument_errors_are_reported_without_gpu():
     assert rc == 1 and b"null" in L.bf_last_error()
     rc = L.build_candidates(None, None, None, None)
     assert rc == 1
+
+
+def _create(kind, nv, edges, tris, ref):
+    import paper_2510_10256_amd as bfc
+    L = bfc.lib()
+    edges = np.ascontiguousarray(edges, np.int32)
+    tris = np.ascontiguousarray(tris, np.int32) if tris is not None else None
+    ref = np.ascontiguousarray(ref, np.float64)
+    desc = bfc.binding.MeshDesc(kind, nv, len(edges), 0 if tris is None else len(tris), edges.ctypes.data,
+                                None if tris is None else tris.ctypes.data, ref.ctypes.data)
+    prm = bfc.binding.Params(1000.0, 900.0, 1.0, 0, 0, 11)
+    out = ctypes.c_void_p()
+    rc = L.bf_scene_create(ctypes.byref(desc), ctypes.byref(prm), 16, 16, None, ctypes.byref(out))
+    return rc, L.bf_last_error()
+
+
+def test_degenerate_rest_primitives_are_refused_without_gpu():
+    # Sec. 3.2's reference distances divide by rest edge lengths: a rod edge
+    # whose two rest parameters coincide, a shell edge of zero rest length and
+    # a triangle of zero rest area are refused before any device work
+    rc, msg = _create(0, 3, [[0, 1], [1, 2]], None, [0.0, 50.0, 50.0])
+    assert rc == 6 and b"zero rest length" in msg
+    u = [[0, 0], [500, 0], [1000, 0], [0, 500]]
+    rc, msg = _create(1, 4, [[0, 1], [1, 2], [0, 2], [0, 3], [1, 3]], [[0, 1, 2], [0, 1, 3]], u)
+    assert rc == 6 and b"zero rest area" in msg
+    u2 = [[0, 0], [500, 0], [500, 0], [0, 500]]
+    rc, msg = _create(1, 4, [[0, 1], [1, 2], [0, 2], [0, 3], [1, 3]], [[0, 1, 2], [0, 1, 3]], u2)
+    assert rc == 6 and b"zero rest length" in msg
