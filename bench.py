@@ -1,11 +1,12 @@
 """Benchmark: barrier-filtered contact evaluation on one MI355X.
 
 One step = build_candidates -> filter_pairs -> eval_barrier ->
-assemble_grad_hess over the woven yarn patch (32 warp x 32 weft rods, 512
-vertices per rod, graded 20-300 um segments, h = 300 um, dhat = 30 um) with
-the positions already resident in device memory.  The throughput numerator
-is N_c, the number of pairs closer than h (the pairs the path evaluates for
-distance and filter); N_act (active pairs) is reported beside it.
+assemble_grad_hess over the thick shell cloth (256 x 256 vertices, 130,050
+triangles, three Z-folds bringing layers within 2 mm, h = 1 mm, dhat =
+0.1 mm), the largest single-scene workload, with the positions already
+resident in device memory.  The throughput numerator is N_c, the number of
+pairs closer than h (the pairs the path evaluates for distance and filter);
+N_act (active pairs) is reported beside it.
 
 Prints one JSON line (see the fields below).  --gpus above 1 is refused: the
 path runs on one GPU.
@@ -31,21 +32,35 @@ FP64_PEAK_TFLOPS = 78.6
 # 4n^3/3 tridiagonalisation + 6n^3 QL with vectors + n^3 reconstruction) and
 # the map back to 12 DOFs (0.4k / 0.7k).
 FLOPS_PER_KIND = {0: 150.0, 1: 2700.0, 2: 8000.0, 3: 8000.0}
-# Algorithmic bytes of one active pair in eval_barrier: pair ids, type, code,
-# flags (11 B), four FP64 vertices (96 B), and E, G[12], H[12 x 12] (1256 B).
-EVAL_BYTES_PER_PAIR = 11 + 96 + 8 + 96 + 1152
+# Algorithmic work per unit of each stage of the step (the path's scope
+# table, measurement row): bytes that must cross HBM, and FP64 operations.
+#   a1 broad phase: positions and topology in (24 V + 8 E + 12 F), one
+#      counting sort of the stored primitives (2 x (8 + 4) B each), the
+#      candidate list out (9 B per candidate: i, j, type)
+#   a2 narrow phase and filter: 9 B of ids per candidate in, 32 B per active
+#      pair out; about 150 FP64 operations per candidate (distance and tests)
+#   a3 + a4 evaluation and projection: 8 + 96 + 624 = 728 B out per active
+#      pair (E, G[12], the upper triangle of H), 11 B of ids in; FP64 by kind
+#   a5 assembly: 96 + 720 B read per active pair (gradient, the ten 3 x 3
+#      blocks of the pair's upper triangle), 72 B written per block of the
+#      matrix and 24 B per vertex (gradient)
+A1_BYTES_PER_STORED = 2 * (8 + 4)
+CAND_BYTES = 9
+A2_FLOPS_PER_CAND = 150.0
+A2_BYTES_PER_ACTIVE = 32
+A3_BYTES_PER_ACTIVE = 728 + 11
+A5_BYTES_PER_ACTIVE = 96 + 720
+KIND_OF_CODE = np.array([0, 0, 0, 1, 1, 1, 2, 0, 0, 0, 0, 1, 1, 1, 1, 3])
 # Algorithmic bytes of one lagged pair in friction_eval: pair ids and type
 # (9 B), lambda, weights[4], normal[3] (64 B), four vertices at x and at the
 # lagged positions (192 B), and E, G[12], H[12 x 12] (1256 B).
 FRICTION_BYTES_PER_PAIR = 9 + 64 + 192 + 8 + 96 + 1152
-KIND_OF_CODE = np.array([0, 0, 0, 1, 1, 1, 2, 0, 0, 0, 0, 1, 1, 1, 1, 3])
 
-# HBM bytes per launch of the evaluation kernel, counted with rocprofv3 --pmc
-# (FETCH_SIZE x 2 and WRITE_SIZE x 1, the factors a plain 256 MiB copy gives)
-# on the kernel source whose fingerprint is EVAL_TRAFFIC_SOURCE; reported as
-# null once that source changes.
-EVAL_TRAFFIC_SOURCE = "029859ba53065a5e"
-EVAL_TRAFFIC_BYTES = {"woven_patch": 48.4e6, "folded_cloth": 2097.4e6}
+# HBM bytes per launch of a stage's kernels, counted with rocprofv3 --pmc
+# (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a
+# plain device copy of known size) on the kernel source whose fingerprint is
+# given; reported as null once that source changes.
+TRAFFIC = {}
 # the same for the friction kernel (lag at x - 0.02 p; the bytes do not depend on mu)
 FRICTION_TRAFFIC_SOURCE = "423c9b78a4f89de4"
 FRICTION_TRAFFIC_BYTES = {"woven_patch": 39.7e6, "folded_cloth": 2833.3e6}
@@ -61,9 +76,9 @@ def _source_fingerprint(first_line, kernel, headers):
     return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
-def eval_source_fingerprint():
-    return _source_fingerprint("// One wave per work-group, one pair per lane.  Each lane keeps its pair",
-                               "__global__ __launch_bounds__(64) void k_eval", ("bfc_eval.h", "bfc_eig.h", "bfc_geom.h"))
+def stage_source_fingerprint(kernel):
+    """Fingerprint of a kernel's source and the headers it includes."""
+    return _source_fingerprint(kernel, kernel, ("bfc_eval.h", "bfc_eig.h", "bfc_geom.h", "bfc_internal.h"))
 
 
 def friction_source_fingerprint():
@@ -76,7 +91,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="woven_patch",
+    ap.add_argument("--workload", default="folded_cloth",
                     choices=["woven_patch", "folded_cloth", "helix_loop_rod", "batch64", "serve256"])
     ap.add_argument("--prec", default=None, choices=["fp64", "mixed"],
                     help="default: fp64 for one scene, mixed for the batch")
@@ -127,13 +142,13 @@ def cpu_baseline(sc, n_c_gpu, x=None, core=None, friction=None):
     return {"value": n_c * reps / t_total, "unit": "pairs/s", "cores": threads, "kind": "oracle",
             "sample": f"whole workload, {reps} evaluation(s) of all pairs with d < h "
                       f"(swept enumeration, FP64, derivatives and projection of every active pair"
-                      + (", lagged friction of every lagged pair" if friction is not None else "") + ")"}
+                      + (", lagged friction of every lagged pair" if friction is not None else "") + ")"}, res
 
 
 def eval_roofline(ms, n_act, kinds, label):
     """Roofline of the per-pair evaluation kernel from its measured time."""
     flops = float(sum(FLOPS_PER_KIND[int(k)] * int(np.sum(kinds == k)) for k in range(4)))
-    bytes_ = float(EVAL_BYTES_PER_PAIR * n_act)
+    bytes_ = float(A3_BYTES_PER_ACTIVE * n_act)
     t_hbm = bytes_ / (HBM_PEAK_GBS * 1e9)
     t_fp = flops / (FP64_PEAK_TFLOPS * 1e12)
     if t_hbm >= t_fp:
@@ -147,6 +162,123 @@ def eval_roofline(ms, n_act, kinds, label):
     roof["units"] = {"active_pairs": int(n_act), "bytes": bytes_, "fp64_flops": flops,
                      "pairs_by_kind": {k: int(np.sum(kinds == q)) for q, k in enumerate(["PP", "PE", "PT", "EE"])}}
     return roof
+
+
+# the stages of one step, the kernels in each, and the row of the path's
+# scope table whose work they do
+STAGES = [
+    ("broad", "a1 broad phase", ["k_bounds", "k_count", "k_scan", "k_scatter", "k_cell_order", "k_pair_count",
+                                 "k_pair_emit"]),
+    ("narrow", "a2 narrow phase + filter", ["k_narrow"]),
+    ("compact", "a2 compaction", ["k_scan", "k_compact", "k_exact"]),
+    ("eval", "a3 + a4 barrier, derivatives, PSD projection", ["k_eval"]),
+    ("asm_structure", "a5 assembly (structure)", ["k_inc_count", "k_scan", "k_inc_fill", "k_row_a", "k_row_a_big"]),
+    ("asm_values", "a5 assembly (values)", ["k_scan", "k_row_b", "k_row_b_big"]),
+]
+
+
+def step_roofline(sc, counts, kinds, stage_ms, ms_step):
+    """Roofline of the step from the algorithmic work of each stage:
+    T_roof = sum over stages of max(bytes / HBM peak, FP64 ops / FP64 peak),
+    and the fraction T_roof / T_step; per stage, the same against its
+    measured duration.  'dominant' is the stage with the longest duration."""
+    V, E, F = sc.n_verts, sc.n_edges, sc.n_tris
+    n_bp, n_act, nnzb = counts["n_bp"], counts["n_act"], counts["nnzb"]
+    f_eval = float(sum(FLOPS_PER_KIND[int(k)] * int(np.sum(kinds == k)) for k in range(4)))
+    work = {  # stage: (bytes, fp64 ops)
+        "broad": (24.0 * V + 8.0 * E + 12.0 * F + A1_BYTES_PER_STORED * (E + F) + CAND_BYTES * n_bp, 0.0),
+        "narrow": (float(CAND_BYTES * n_bp + A2_BYTES_PER_ACTIVE * n_act), A2_FLOPS_PER_CAND * n_bp),
+        "compact": (0.0, 0.0),
+        "eval": (float(A3_BYTES_PER_ACTIVE * n_act), f_eval),
+        "asm_structure": (0.0, 0.0),
+        "asm_values": (float(A5_BYTES_PER_ACTIVE * n_act + 72 * nnzb + 24 * V), 0.0),
+    }
+    stages = {}
+    t_roof = 0.0
+    for name, row, kernels in STAGES:
+        b, f = work[name]
+        t_b, t_f = b / (HBM_PEAK_GBS * 1e9), f / (FP64_PEAK_TFLOPS * 1e12)
+        t = max(t_b, t_f)
+        t_roof += t
+        ms = stage_ms.get(name, -1.0)
+        st = {"row": row, "kernels": kernels, "bytes": b, "fp64_flops": f,
+              "bound": "hbm" if t_b >= t_f else "fp64", "t_roof_ms": t * 1e3, "measured_ms": ms}
+        if ms > 0 and t > 0:
+            st["frac"] = t * 1e3 / ms
+        stages[name] = st
+    dom = max(stages, key=lambda k: stages[k]["measured_ms"])
+    d = stages[dom]
+    ms = d["measured_ms"]
+    if d["bound"] == "hbm":
+        dominant = {"kernel": " + ".join(d["kernels"]) + f" ({dom})", "stage": dom, "kernels": d["kernels"],
+                    "bound": "hbm", "achieved": d["bytes"] / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s"}
+    else:
+        dominant = {"kernel": " + ".join(d["kernels"]) + f" ({dom})", "stage": dom, "kernels": d["kernels"],
+                    "bound": "fp64", "achieved": d["fp64_flops"] / (ms * 1e-3) / 1e12,
+                    "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
+    dominant["frac"] = dominant["achieved"] / dominant["peak"]
+    dominant["kernel_ms"] = ms
+    dominant["traffic"] = None
+    dominant["units"] = {"candidates": int(n_bp), "active_pairs": int(n_act), "blocks": int(nnzb),
+                         "bytes": d["bytes"], "fp64_flops": d["fp64_flops"]}
+    return {"t_roof_ms": t_roof * 1e3, "t_step_ms": ms_step, "frac": t_roof * 1e3 / ms_step,
+            "stages": stages, "dominant": dominant}
+
+
+def oracle_errors(g, o, nv, kappa, tau):
+    """Errors of the GPU's results against the oracle's on the whole workload:
+    the active set and counts (exact), and the worst per-pair and assembled
+    errors as fractions of the tolerance (per pair p with band width
+    w = a - eta and b_ref = kappa (w/2)^2 ln 2: |dE| <= tau (|E| + b_ref),
+    |dG| <= tau (|G| + b_ref/w), |dH+|_F <= tau (|H+|_F + b_ref/w^2); the
+    assembled gradient and blocks against the sums of those bounds)."""
+    import oracle
+    rep = {"tau": tau}
+    oc = oracle.counts(o)
+    rep["counts_equal"] = all(g["counts"][k] == oc[k] for k in oc)
+    act = np.nonzero((o["flags"] & oracle.F_ACTIVE) != 0)[0]
+    oi = act[np.lexsort((o["j"][act], o["i"][act], o["ptype"][act]))]
+    gi = np.lexsort((g["j"], g["i"], g["ptype"]))
+    same = len(gi) == len(oi) and all(np.array_equal(g[k][gi], o[k][oi]) for k in ("ptype", "i", "j"))
+    same = same and np.array_equal(g["flags"][gi] & 5, o["flags"][oi] & 5)
+    rep["active_set_equal"] = bool(same)
+    if not same:
+        return rep
+    rep["subcase_equal"] = float(np.mean(g["code"][gi] == o["code"][oi])) if len(gi) else 1.0
+    feas = (o["flags"][oi] & oracle.F_INFEASIBLE) == 0
+    w = (o["a"][oi] - o["eta"][oi])[feas]
+    bref = kappa * (w / 2) ** 2 * math.log(2)
+    gE, oE = g["E"][gi][feas], o["E"][oi][feas]
+    rep["E_pair_worst"] = float(np.max(np.abs(gE - oE) / (tau * (np.abs(oE) + bref)), initial=0.0))
+    gG, oG = g["G"][gi][feas], o["G"][oi][feas]
+    nG = np.linalg.norm(oG, axis=1)
+    rep["G_pair_worst"] = float(np.max(np.linalg.norm(gG - oG, axis=1) / (tau * (nG + bref / w)), initial=0.0))
+    ok = g["code"][gi][feas] == o["code"][oi][feas]  # where the sub-cases agree (else a boundary tie)
+    gH, oH = g["Hpsd"][gi][feas][ok].reshape(-1, 144), o["Hpsd"][oi][feas][ok].reshape(-1, 144)
+    nH = np.linalg.norm(oH, axis=1)
+    rep["H_pair_worst"] = float(np.max(np.linalg.norm(gH - oH, axis=1) / (tau * (nH + bref[ok] / w[ok] ** 2)),
+                                       initial=0.0))
+    asm = oracle.assemble(o, nv)
+    sig = float(np.sum(np.abs(oE) + bref))
+    rep["E_total_worst"] = abs(g["E_total"] - asm["E"]) / (tau * sig) if np.isfinite(asm["E"]) else None
+    verts = o["verts"][oi][feas]
+    gb = np.zeros(nv)
+    for q in range(4):
+        np.add.at(gb, verts[:, q], tau * (nG + bref / w))
+    dg = np.linalg.norm(g["g"] - asm["g"], axis=1)
+    rep["g_worst"] = float(np.max(dg / np.maximum(gb, 1e-300), initial=0.0))
+    rep["bsr_pattern_equal"] = bool(np.array_equal(g["row_ptr"], asm["row_ptr"]) and
+                                    np.array_equal(g["col"], asm["col"]))
+    if rep["bsr_pattern_equal"] and np.all(ok):
+        nHall = np.linalg.norm(o["Hpsd"][oi][feas].reshape(-1, 144), axis=1)
+        hb = np.zeros(nv)
+        for q in range(4):
+            np.add.at(hb, verts[:, q], tau * (nHall + bref / w ** 2))
+        rows = np.repeat(np.arange(nv), np.diff(asm["row_ptr"]))
+        dv = np.linalg.norm((g["val"] - asm["val"]).reshape(-1, 9), axis=1)
+        rep["bsr_worst"] = float(np.max(dv / np.maximum(hb[rows], 1e-300), initial=0.0))
+    return rep
 
 
 # FP64 operations of additive CCD (model): per pair in the swept set (loads,
@@ -609,20 +741,33 @@ def main():
             per[c].append(e[q].elapsed_time(e[q + 1]))
     call_ms = {c: float(np.mean(v)) for c, v in per.items()}
 
-    # roofline of the per-pair evaluation kernel: eval_barrier captured alone
-    # (under capture it launches only k_eval), KERNEL_LAUNCHES launches back to
-    # back in one graph; replays timed with events on the launching stream
-    def per_launch_ms(fn):
+    # per-stage kernel durations: HIP events around each stage's kernels on
+    # the stream they run on (the library's stage timers), eager steps after
+    # the timed region; medians over the steps
+    cs.set_timing(True)
+    stage_runs = []
+    for _ in range(max(10, args.steps // 5)):
+        cs.step(x)
+        stage_runs.append(cs.stage_ms())
+    cs.set_timing(False)
+    stage_ms = {k: float(np.median([r[k] for r in stage_runs])) for k in stage_runs[0]}
+    step_roof = step_roofline(sc, counts, kinds, stage_ms, ms_per_step)
+    roof = dict(step_roof["dominant"])
+    roof["step"] = {k: v for k, v in step_roof.items() if k != "dominant"}
+    fric_roof = None
+    if fric:
+        # friction_eval alone (one kernel): ten launches captured back to back in
+        # one graph, replays timed with events on the launching stream
         g = torch.cuda.CUDAGraph()
         side = torch.cuda.Stream(device=dev)
         side.wait_stream(stream)
         with torch.cuda.stream(side):
-            fn()
+            cs.friction_eval(x, args.friction_mu, args.eps_vh)
         stream.wait_stream(side)
         torch.cuda.synchronize()
         with torch.cuda.graph(g):
-            for _ in range(KERNEL_LAUNCHES):
-                fn()
+            for _ in range(10):
+                cs.friction_eval(x, args.friction_mu, args.eps_vh)
         torch.cuda.synchronize()
         reps = max(4, args.steps // 10)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -632,15 +777,7 @@ def main():
             g.replay()
         e1.record(stream)
         torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / (reps * KERNEL_LAUNCHES)
-
-    eval_ms = per_launch_ms(lambda: cs.eval_barrier(x))
-    roof = eval_roofline(eval_ms, n_act, kinds, "k_eval (eval_barrier)")
-    roof["kernel_ms"] = eval_ms
-    fric_roof = None
-    if fric:
-        # friction_eval alone (one kernel), timed the same way
-        f_ms = per_launch_ms(lambda: cs.friction_eval(x, args.friction_mu, args.eps_vh))
+        f_ms = e0.elapsed_time(e1) / (reps * 10)
         fb = float(FRICTION_BYTES_PER_PAIR * n_fric)
         fric_roof = {"kernel": "k_friction_eval (friction_eval)", "bound": "hbm",
                      "achieved": fb / (f_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None,
@@ -649,9 +786,11 @@ def main():
         if (args.core_squeeze == 0 and sc.name in FRICTION_TRAFFIC_BYTES
                 and friction_source_fingerprint() == FRICTION_TRAFFIC_SOURCE):
             fric_roof["traffic"] = FRICTION_TRAFFIC_BYTES[sc.name]
-    if (args.prec == "fp64" and args.core_squeeze == 0 and sc.name in EVAL_TRAFFIC_BYTES
-            and eval_source_fingerprint() == EVAL_TRAFFIC_SOURCE):
-        roof["traffic"] = EVAL_TRAFFIC_BYTES[sc.name]
+    key = (roof["stage"], sc.name, args.prec)
+    if args.core_squeeze == 0 and not fric and key in TRAFFIC:
+        src, per_launch = TRAFFIC[key]
+        if stage_source_fingerprint(roof["kernels"][0]) == src:
+            roof["traffic"] = per_launch
 
     out = {
         "metric": "filtered contact pairs evaluated/s (dist+filter+grad+Hessian"
@@ -679,6 +818,7 @@ def main():
                    "n_verts": sc.n_verts, "n_edges": sc.n_edges, "n_tris": sc.n_tris,
                    "N_bp": counts["n_bp"], "N_c": n_c, "N_filt": counts["n_filt"], "N_act": n_act,
                    "nnzb": counts["nnzb"], "launch": launch, "pq": cs.pq, "precision": args.prec,
+                   "N_exact": cs.deferred(),
                    **({"N_friction": n_fric} if fric else {}),
                    **({"core_squeeze_z": args.core_squeeze, "core_pairs_marked": n_core,
                        "core_pairs_live": int(cs.core_live().item())} if args.core_squeeze > 0 else {})},
@@ -699,7 +839,12 @@ def main():
         if fric:
             import oracle
             fr = (oracle.friction_lag(sc, xlag_np), xlag_np, args.friction_mu, args.eps_vh)
-        out["cpu_baseline"] = cpu_baseline(sc, n_c, x_np if (args.core_squeeze > 0 or fric) else None, core, fr)
+        out["cpu_baseline"], res = cpu_baseline(sc, n_c, x_np if (args.core_squeeze > 0 or fric) else None, core, fr)
+        # the error of every result of the step against the oracle's, on the whole workload
+        g = cs.results()
+        del g["cand"]
+        out["oracle_errors"] = oracle_errors(g, res, sc.n_verts, sc.kappa, 1e-10 if args.prec == "fp64" else 1e-5)
+        del g, res
     print(json.dumps(out))
 
 

@@ -74,9 +74,13 @@ enum {
   BF_S_CORE_OVERFLOW = 1u << 4,  /* more core pairs than bf_core_mark's capacity */
   BF_S_EIG_NOCONV = 1u << 5,     /* a pair Hessian's eigen-iteration hit its step limit
                                     (that pair's projection is not exact) */
-  BF_S_SCAN_SLOW = 1u << 6       /* a single-pass scan stopped waiting for an earlier
+  BF_S_SCAN_SLOW = 1u << 6,      /* a single-pass scan stopped waiting for an earlier
                                     tile's total and summed that tile itself (results
                                     exact; reported for diagnosis) */
+  BF_S_EXACT_LIMIT = 1u << 7     /* an exact threshold decision needed more than the
+                                    expansion length it has room for (coordinates
+                                    spanning hundreds of binary orders of magnitude);
+                                    the double-double decision was kept */
 };
 
 /* Pair types. */
@@ -133,14 +137,15 @@ typedef struct {
 
 /* Per-active-pair results, row k for active pair k.  The 12 DOFs are the
  * pair's four stencil vertices in the order (point, t0, t1, t2) or
- * (a0, a1, b0, b1), xyz each.  H is stored in full (symmetric, row-major) so
- * that the three rows of one stencil vertex are 36 contiguous doubles: the
- * assembly reads each pair's Hessian once per stencil vertex, in one piece. */
+ * (a0, a1, b0, b1), xyz each.  H holds the upper triangle of the symmetric
+ * projected 12 x 12 Hessian, packed by 3 x 3 blocks (78 doubles): block-row s
+ * (the three rows of stencil vertex s) is block (s, s) as its upper triangle
+ * (xx, xy, xz, yy, yz, zz) followed by blocks (s, t), t > s, each row-major;
+ * block-rows 0, 1, 2, 3 start at 0, 33, 57 and 72. */
 typedef struct {
   double* E_d;  /* [cap] kappa * b (+inf for infeasible pairs) */
   double* G_d;  /* [cap,12] gradient */
-  double* H_d;  /* [cap,144] projected 12 x 12 Hessian, row-major; 16-byte aligned for eval_barrier
-                   (device allocations are) */
+  double* H_d;  /* [cap,78] projected Hessian, packed upper triangle (above) */
   int64_t cap;
 } bf_local;
 
@@ -200,7 +205,7 @@ bf_status filter_pairs(bf_scene* s, const double* x_d, const bf_pairs* cand, bf_
  * is being captured into a graph there is no fork: assemble_grad_hess then
  * builds the structure itself. */
 bf_status eval_barrier(bf_scene* s, const double* x_d, const bf_active* act, bf_local* out,
-                       void* stream);  /* BF_E_ARG if out->H_d is not 16-byte aligned */
+                       void* stream);
 
 /* Assembly: E_d[1] = sum of pair energies (+inf if any pair is infeasible),
  * g_d[V,3] = sum of pair gradients, H = sum of pair Hessian blocks over the
@@ -366,6 +371,29 @@ bf_status bf_batch_destroy(bf_batch* b);
 /* Device status word (BF_S_* bits) accumulated since the last clear;
  * synchronises the stream the scene last used.  clear != 0 resets it. */
 bf_status bf_status_word(bf_scene* s, uint32_t* bits_h, int32_t clear);
+
+/* ---- per-stage timing (measurement) --------------------------------------
+ * With timing on, every stage below records a pair of HIP events around its
+ * kernels on the stream they run on (not while that stream is captured):
+ *   BF_T_BROAD       build_candidates (grid, cells, pair count and emission)
+ *   BF_T_NARROW      filter_pairs' decisions kernel (k_narrow)
+ *   BF_T_COMPACT     filter_pairs' list: scan, compaction, exact decisions
+ *   BF_T_EVAL        eval_barrier's evaluation kernel (k_eval)
+ *   BF_T_ASM_STRUCT  the assembly's structure (eval_barrier's second stream, or
+ *                    assemble_grad_hess)
+ *   BF_T_ASM_VALUES  assemble_grad_hess's values
+ * bf_scene_stage_ms synchronises on those events and writes the duration of
+ * each stage's latest call (ms; -1 where the stage has not run since timing
+ * was switched on) to ms_h[BF_T_COUNT].  Setting timing allocates events. */
+/* Diagnostics: the number of candidates of the last filter_pairs whose
+ * decisions neither FP64 nor double-double settled and that were decided in
+ * exact arithmetic (synchronises). */
+bf_status bf_scene_deferred(bf_scene* s, int64_t* n_h);
+
+enum { BF_T_BROAD = 0, BF_T_NARROW = 1, BF_T_COMPACT = 2, BF_T_EVAL = 3, BF_T_ASM_STRUCT = 4,
+       BF_T_ASM_VALUES = 5, BF_T_COUNT = 6 };
+bf_status bf_scene_set_timing(bf_scene* s, int32_t on);
+bf_status bf_scene_stage_ms(bf_scene* s, float* ms_h);
 
 /* Diagnostics: the number of loads a single-pass scan spends waiting for
  * each earlier tile's published total before it sums that tile itself

@@ -232,13 +232,13 @@ def psd_project(A):
 
 
 def _stencil(res, k):
-    """Global vertex ids of active pair k's four local slots."""
+    """Global vertex ids of the four local slots of active pair(s) k."""
     return res["verts"][k]
 
 
 def _block(H, r, c):
-    """The 3x3 block (local slot r, local slot c) of a 12x12 pair matrix."""
-    return H[3 * r:3 * r + 3, 3 * c:3 * c + 3]
+    """The 3x3 block (local slot r, local slot c) of 12x12 pair matrices (stacked)."""
+    return H[..., 3 * r:3 * r + 3, 3 * c:3 * c + 3]
 
 
 def assemble(res, n_verts, hess="Hpsd"):
@@ -250,34 +250,38 @@ def assemble(res, n_verts, hess="Hpsd"):
     arrays row_ptr[V+1], col[nnzb], val[nnzb,3,3] with columns sorted per row.
     hess names the per-pair matrices summed ("Hpsd"; "Hraw", the Hessians
     before projection, for the finite-difference pins of this function).
+    The sums are numpy scatter-adds over (vertex) and (row vertex, column
+    vertex) keys; the same values as pair-by-pair accumulation up to the
+    order of the additions.
     """
     act = (res["flags"] & F_ACTIVE) != 0
     feas = act & ((res["flags"] & F_INFEASIBLE) == 0)
     E = float(np.sum(res["E"][act])) if act.any() else 0.0
     g = np.zeros((n_verts, 3))
-    blocks = {}
     idx = np.nonzero(feas)[0]
-    for k in idx:
-        vs = _stencil(res, k)
-        G = res["G"][k].reshape(4, 3)
-        H = res[hess][k]
-        for r in range(4):
-            g[vs[r]] += G[r]
-            for c in range(4):
-                key = (int(vs[r]), int(vs[c]))
-                blk = _block(H, r, c)
-                if key in blocks:
-                    blocks[key] = blocks[key] + blk
-                else:
-                    blocks[key] = blk.copy()
-    keys = sorted(blocks)
+    if not len(idx):
+        return dict(E=E, g=g, row_ptr=np.zeros(n_verts + 1, np.int64), col=np.zeros(0, np.int32),
+                    val=np.zeros((0, 3, 3)))
+    vs = np.asarray(_stencil(res, idx)).astype(np.int64)  # [n, 4]
+    G = res["G"][idx].reshape(-1, 4, 3)
+    H = res[hess][idx]
+    rows, cols, blks = [], [], []
+    for r in range(4):
+        np.add.at(g, vs[:, r], G[:, r])
+        for c in range(4):
+            rows.append(vs[:, r])
+            cols.append(vs[:, c])
+            blks.append(_block(H, r, c))
+    # pair-major order: every key (and its transpose) receives its pairs'
+    # blocks in pair order, so the sums are bitwise symmetric
+    key = (np.stack(rows, 1) * n_verts + np.stack(cols, 1)).reshape(-1)
+    uk, inv = np.unique(key, return_inverse=True)
+    val = np.zeros((len(uk), 3, 3))
+    np.add.at(val, inv, np.stack(blks, 1).reshape(-1, 3, 3))
+    row = uk // n_verts
     row_ptr = np.zeros(n_verts + 1, np.int64)
-    for (r, c) in keys:
-        row_ptr[r + 1] += 1
-    row_ptr = np.cumsum(row_ptr)
-    col = np.array([c for (_, c) in keys], np.int32)
-    val = np.array([blocks[k] for k in keys]).reshape(-1, 3, 3) if keys else np.zeros((0, 3, 3))
-    return dict(E=E, g=g, row_ptr=row_ptr, col=col, val=val)
+    np.add.at(row_ptr, row + 1, 1)
+    return dict(E=E, g=g, row_ptr=np.cumsum(row_ptr), col=(uk % n_verts).astype(np.int32), val=val)
 
 
 # ---- line search (Sec. 3.3, last paragraph; App. A) --------------------------

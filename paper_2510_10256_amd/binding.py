@@ -23,13 +23,15 @@ BF_FP64, BF_MIXED = 0, 1
 BF_FILTER_PAPER, BF_FILTER_NONE, BF_FILTER_CULL = 0, 1, 2
 BF_S_CAND_OVERFLOW, BF_S_ACT_OVERFLOW, BF_S_INFEASIBLE = 1, 2, 4
 BF_S_BSR_OVERFLOW, BF_S_CORE_OVERFLOW = 8, 16
+BF_S_EIG_NOCONV, BF_S_SCAN_SLOW, BF_S_EXACT_LIMIT = 32, 64, 128
 BF_F_FILTERED, BF_F_INFEASIBLE, BF_F_CORE = 1, 4, 8
 
 EXPORTED = ["bf_scene_create", "bf_scene_reserve", "bf_scene_destroy", "bf_scene_info", "build_candidates",
             "filter_pairs", "eval_barrier", "assemble_grad_hess", "bf_scene_set_pq", "bf_scene_tune",
             "bf_batch_create", "bf_batch_step", "bf_batch_info", "bf_batch_destroy", "build_candidates_swept",
             "max_step_accd", "eval_energy", "bf_core_mark", "bf_core_live", "bf_core_clear", "friction_lag",
-            "friction_eval", "friction_assemble", "bf_status_word", "bf_last_error"]
+            "friction_eval", "friction_assemble", "bf_status_word", "bf_set_scan_poll_limit", "bf_scene_set_timing",
+            "bf_scene_stage_ms", "bf_scene_deferred", "bf_last_error"]
 
 
 def build(verbose: bool = False) -> str:
@@ -42,6 +44,28 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("hipcc failed:\n" + r.stderr)
     os.replace(LIB_PATH + ".tmp", LIB_PATH)
     return LIB_PATH
+
+
+def _packed_index():
+    """Packed position of every entry (I, J) of a pair's 12 x 12 Hessian: the
+    upper triangle by 3 x 3 blocks, block-row s = block (s, s) as its upper
+    triangle, then blocks (s, t > s) row-major; block-rows at 0, 33, 57, 72."""
+    off = [0, 33, 57, 72]
+    idx = np.zeros((12, 12), np.int64)
+    for I in range(12):
+        for J in range(12):
+            a, b = min(I, J), max(I, J)
+            s, i, t, j = a // 3, a % 3, b // 3, b % 3
+            idx[I, J] = off[s] + ([j, 2 + j, 5][i] if s == t else 6 + 9 * (t - s - 1) + 3 * i + j)
+    return idx
+
+
+PACKED_INDEX = _packed_index()
+
+
+def unpack_hessians(Hp):
+    """[n, 78] packed upper triangles -> [n, 12, 12] symmetric matrices."""
+    return np.asarray(Hp)[:, PACKED_INDEX]
 
 
 class Params(C.Structure):
@@ -119,6 +143,10 @@ def lib():
                                     C.c_int32, C.POINTER(Local), P]
         L.friction_assemble.argtypes = [P, C.POINTER(Active), C.POINTER(Local), P, P, C.POINTER(Bsr), P]
         L.bf_status_word.argtypes = [P, C.POINTER(C.c_uint32), C.c_int32]
+        L.bf_set_scan_poll_limit.argtypes = [C.c_int32]
+        L.bf_scene_set_timing.argtypes = [P, C.c_int32]
+        L.bf_scene_stage_ms.argtypes = [P, P]
+        L.bf_scene_deferred.argtypes = [P, C.POINTER(C.c_int64)]
         L.bf_last_error.restype = C.c_char_p
         for name in EXPORTED[:-1]:
             getattr(L, name).restype = C.c_int
@@ -190,7 +218,7 @@ class ContactScene:
         self.a_dist = z(self.act_cap, t.float64)
         self.counters = z(4, t.int64)
         self.l_E, self.l_G, self.l_H = z(self.act_cap, t.float64), z((self.act_cap, 12), t.float64), \
-            z((self.act_cap, 144), t.float64)
+            z((self.act_cap, 78), t.float64)
         self.E = z(1, t.float64)
         self.g = z((self.nv, 3), t.float64)
         self.row_ptr = z(self.nv + 1, t.int32)
@@ -294,7 +322,7 @@ class ContactScene:
                             self.f_counters.data_ptr())
         self.f_lam, self.f_w, self.f_n = z(cap), z((cap, 4)), z((cap, 3))
         self._fr = Friction(self.f_lam.data_ptr(), self.f_w.data_ptr(), self.f_n.data_ptr(), cap)
-        self.fl_E, self.fl_G, self.fl_H = z(cap), z((cap, 12)), z((cap, 144))
+        self.fl_E, self.fl_G, self.fl_H = z(cap), z((cap, 12)), z((cap, 78))
         self._floc = Local(self.fl_E.data_ptr(), self.fl_G.data_ptr(), self.fl_H.data_ptr(), cap)
         self.f_E, self.f_g = z(1), z((self.nv, 3))
         self.f_row_ptr, self.f_col = z(self.nv + 1, t.int32), z(self.bsr_cap, t.int32)
@@ -334,7 +362,7 @@ class ContactScene:
         c = lambda a: a[:n].cpu().numpy()
         return dict(ptype=c(self.f_t).astype(np.int32), i=c(self.f_i), j=c(self.f_j), lam=c(self.f_lam),
                     w=c(self.f_w), n=c(self.f_n), E=c(self.fl_E), G=c(self.fl_G),
-                    Hpsd=c(self.fl_H).reshape(-1, 12, 12), E_total=float(self.f_E.item()), g=self.f_g.cpu().numpy(),
+                    Hpsd=unpack_hessians(c(self.fl_H)), E_total=float(self.f_E.item()), g=self.f_g.cpu().numpy(),
                     row_ptr=self.f_row_ptr.cpu().numpy().astype(np.int64), col=self.f_col[:nb].cpu().numpy(),
                     val=self.f_val[:nb].cpu().numpy().reshape(-1, 3, 3), nnzb=int(self.f_nnzb.item()))
 
@@ -376,6 +404,24 @@ class ContactScene:
         alive by the caller; a batch reads it at every step)."""
         return BatchItem(self.handle, x.data_ptr(), self._cand, self._act, self._loc, self.E.data_ptr(),
                          self.g.data_ptr(), self._bsr)
+
+    STAGES = ("broad", "narrow", "compact", "eval", "asm_structure", "asm_values")
+
+    def set_timing(self, on=True):
+        """Per-stage HIP events around the kernels of each call (eager launches)."""
+        _check(lib().bf_scene_set_timing(self.handle, int(bool(on))), "bf_scene_set_timing")
+
+    def stage_ms(self):
+        """Durations (ms) of each stage's latest call (synchronises)."""
+        ms = np.zeros(len(self.STAGES), np.float32)
+        _check(lib().bf_scene_stage_ms(self.handle, ms.ctypes.data), "bf_scene_stage_ms")
+        return {k: float(v) for k, v in zip(self.STAGES, ms)}
+
+    def deferred(self):
+        """Candidates of the last filter_pairs decided in exact arithmetic."""
+        n = C.c_int64(0)
+        _check(lib().bf_scene_deferred(self.handle, C.byref(n)), "bf_scene_deferred")
+        return int(n.value)
 
     def status(self, clear=True):
         v = C.c_uint32(0)
@@ -437,7 +483,7 @@ class ContactScene:
         na = min(int(self.a_n.item()), self.act_cap)
         nc = min(int(self.c_n.item()), self.cand_cap)
         nb = min(int(self.nnzb.item()), self.bsr_cap)
-        Hf = self.l_H[:na].cpu().numpy().reshape(-1, 12, 12)
+        Hf = unpack_hessians(self.l_H[:na].cpu().numpy())
         return dict(
             cand=np.stack([self.c_t[:nc].cpu().numpy().astype(np.int32), self.c_i[:nc].cpu().numpy(),
                            self.c_j[:nc].cpu().numpy()], 1),

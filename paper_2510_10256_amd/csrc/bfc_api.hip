@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -53,6 +54,11 @@ struct bf_scene {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool prepared = false;             // structure built for the active list at prepared_for
   const void* prepared_for = nullptr;
+  // per-stage timing (bf_scene_set_timing): an event pair around each stage's
+  // kernels, recorded on the stream they run on, outside graph capture
+  bool timing = false;
+  hipEvent_t tev[BF_T_COUNT][2] = {};
+  bool tev_set[BF_T_COUNT] = {};
 };
 
 namespace {
@@ -206,10 +212,12 @@ bf_status alloc_stage(bf_scene* s, long long cand_cap) {
   W.sj = dalloc<int>(s->stage_allocs, G * NW_TILE, &e);
   W.sm = dalloc<unsigned>(s->stage_allocs, G * NW_TILE, &e);
   W.sd = dalloc<double>(s->stage_allocs, G * NW_TILE, &e);
-  W.kcnt = dalloc<int>(s->stage_allocs, 3 * G + 1, &e);
-  W.kofs = dalloc<int>(s->stage_allocs, 3 * G + 1, &e);
+  W.kcnt = dalloc<int>(s->stage_allocs, NW_KINDS * G + 1, &e);
+  W.kofs = dalloc<int>(s->stage_allocs, NW_KINDS * G + 1, &e);
   W.ccnt = dalloc<int>(s->stage_allocs, 3 * G, &e);
-  W.scan_tmp = dalloc<int>(s->stage_allocs, scan_tmp_ints(3 * G + 1), &e);
+  W.dfr = dalloc<long long>(s->stage_allocs, G * NW_TILE, &e);
+  W.xcnt = dalloc<int>(s->stage_allocs, 5LL * XP_BLOCKS, &e);
+  W.scan_tmp = dalloc<int>(s->stage_allocs, scan_tmp_ints(NW_KINDS * G + 1), &e);
   if (e != hipSuccess) return fail(BF_E_NOMEM, "bf_scene_reserve: device allocation failed");
   if (hipMemsetAsync(W.scan_tmp, 0, sizeof(int) * SCAN_LB_STATE, g_alloc_stream) != hipSuccess ||
       hipStreamSynchronize(g_alloc_stream) != hipSuccess)
@@ -240,6 +248,24 @@ const char* degenerate_rest(const bf_mesh_desc& m, int nv, int ne, int nt) {
   (void)nv;
   return nullptr;
 }
+
+// Per-stage timing: record the start / stop event of a stage on st (no-op
+// unless timing is on and st is not being captured).
+struct StageTimer {
+  bf_scene* s;
+  int stage;
+  hipStream_t st;
+  bool on;
+  StageTimer(bf_scene* s_, int stage_, hipStream_t st_) : s(s_), stage(stage_), st(st_), on(false) {
+    if (!s->timing) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+    on = hipEventRecord(s->tev[stage][0], st) == hipSuccess;
+  }
+  ~StageTimer() {
+    if (on && hipEventRecord(s->tev[stage][1], st) == hipSuccess) s->tev_set[stage] = true;
+  }
+};
 
 }  // namespace
 
@@ -500,6 +526,9 @@ bf_status bf_scene_destroy(bf_scene* s) {
   if (s->ev_join) (void)hipEventDestroy(s->ev_join);
   if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
   if (s->side) (void)hipStreamDestroy(s->side);
+  for (int k = 0; k < BF_T_COUNT; ++k)
+    for (int e = 0; e < 2; ++e)
+      if (s->tev[k][e]) (void)hipEventDestroy(s->tev[k][e]);
   delete s;
   return BF_OK;
 }
@@ -521,6 +550,7 @@ bf_status build_candidates(bf_scene* s, const double* x_d, bf_pairs* cand, void*
     return fail(BF_E_ARG, "build_candidates: null argument or capacity < 1");
   hipStream_t st = (hipStream_t)stream;
   s->last = st;
+  StageTimer tm(s, BF_T_BROAD, st);
   // the narrow phase's staging buffers hold the count pass's segments (they
   // are free until filter_pairs, which runs after this call on the stream)
   run_broad(dev_view(s), x_d, nullptr, s->bw, cand->i_d, cand->j_d, cand->type_d, cand->cap,
@@ -698,9 +728,17 @@ bf_status filter_pairs(bf_scene* s, const double* x_d, const bf_pairs* cand, bf_
   s->last = st;
   s->prepared = false;
   if (s->core_slots) run_core_release(dev_view(s), x_d, st);  // Sec. 3.4: pairs now beyond eta leave the set
-  run_narrow(dev_view(s), x_d, cand->i_d, cand->j_d, cand->type_d, (const long long*)cand->count_d, cand->cap, s->sw,
-             act->p.i_d, act->p.j_d, act->p.type_d, act->code_d, act->flags_d, act->dist_d, act->p.cap,
-             (long long*)act->p.count_d, (long long*)act->counters_d, s->d_status, st);
+  {
+    StageTimer tm(s, BF_T_NARROW, st);
+    run_narrow(dev_view(s), x_d, cand->i_d, cand->j_d, cand->type_d, (const long long*)cand->count_d, cand->cap,
+               s->sw, st);
+  }
+  {
+    StageTimer tm(s, BF_T_COMPACT, st);
+    run_compact(dev_view(s), x_d, cand->i_d, cand->j_d, cand->type_d, cand->cap, s->sw, act->p.i_d, act->p.j_d,
+                act->p.type_d, act->code_d, act->flags_d, act->dist_d, act->p.cap, (long long*)act->p.count_d,
+                (long long*)act->counters_d, s->d_status, st);
+  }
   hipError_t he = hipGetLastError();
   return he == hipSuccess ? BF_OK : fail_hip(he, "filter_pairs");
 }
@@ -709,7 +747,6 @@ bf_status eval_barrier(bf_scene* s, const double* x_d, const bf_active* act, bf_
   if (!s || !x_d || !act || !out || !out->E_d || !out->G_d || !out->H_d || !act->p.count_d)
     return fail(BF_E_ARG, "eval_barrier: null argument");
   if (out->cap < act->p.cap) return fail(BF_E_CAPACITY, "eval_barrier: local capacity below active capacity");
-  if ((reinterpret_cast<uintptr_t>(out->H_d) & 15u) != 0) return fail(BF_E_ARG, "eval_barrier: H_d not 16-byte aligned");
   hipStream_t st = (hipStream_t)stream;
   s->last = st;
   const SceneDev S = dev_view(s);
@@ -727,12 +764,16 @@ bf_status eval_barrier(bf_scene* s, const double* x_d, const bf_active* act, bf_
   if (fork) {
     if ((he = hipEventRecord(s->ev_fork, st)) != hipSuccess || (he = hipStreamWaitEvent(s->side, s->ev_fork, 0)))
       return fail_hip(he, "eval_barrier: fork");
+    StageTimer tm(s, BF_T_ASM_STRUCT, s->side);
     run_asm_structure(S, act->p.i_d, act->p.j_d, act->p.type_d, act->flags_d, (const long long*)act->p.count_d,
                       act->p.cap, s->aw, s->side);
   }
-  run_eval(S, x_d, act->p.i_d, act->p.j_d, act->p.type_d, act->code_d, act->flags_d,
-           (const long long*)act->p.count_d, act->p.cap, out->E_d, out->G_d, out->H_d, fits ? s->aw.epart : nullptr,
-           st);
+  {
+    StageTimer tm(s, BF_T_EVAL, st);
+    run_eval(S, x_d, act->p.i_d, act->p.j_d, act->p.type_d, act->code_d, act->flags_d,
+             (const long long*)act->p.count_d, act->p.cap, out->E_d, out->G_d, out->H_d,
+             fits ? s->aw.epart : nullptr, st);
+  }
   if (fork) {
     if ((he = hipEventRecord(s->ev_join, s->side)) != hipSuccess || (he = hipStreamWaitEvent(st, s->ev_join, 0)))
       return fail_hip(he, "eval_barrier: join");
@@ -753,15 +794,54 @@ bf_status assemble_grad_hess(bf_scene* s, const bf_active* act, const bf_local* 
   hipStream_t st = (hipStream_t)stream;
   s->last = st;
   const SceneDev S = dev_view(s);
-  if (!(s->prepared && s->prepared_for == act->p.i_d))
+  if (!(s->prepared && s->prepared_for == act->p.i_d)) {
+    StageTimer tm(s, BF_T_ASM_STRUCT, st);
     run_asm_structure(S, act->p.i_d, act->p.j_d, act->p.type_d, act->flags_d, (const long long*)act->p.count_d,
                       act->p.cap, s->aw, st);
+  }
   s->prepared = false;
+  StageTimer tm(s, BF_T_ASM_VALUES, st);
   run_asm_values(S, act->p.i_d, act->p.j_d, act->p.type_d, (const long long*)act->p.count_d, act->p.cap, loc->G_d,
                  loc->H_d, E_d, g_d, H->row_ptr_d, H->col_d, H->val_d, H->cap, (long long*)H->nnzb_d, s->aw,
                  s->d_status, st);
   hipError_t he = hipGetLastError();
   return he == hipSuccess ? BF_OK : fail_hip(he, "assemble_grad_hess");
+}
+
+bf_status bf_scene_deferred(bf_scene* s, int64_t* n_h) {
+  if (!s || !n_h) return fail(BF_E_ARG, "bf_scene_deferred: null argument");
+  hipError_t he = hipStreamSynchronize(s->last);
+  unsigned v = 0;
+  if (he == hipSuccess) he = hipMemcpy(&v, s->d_status + 1, sizeof(unsigned), hipMemcpyDeviceToHost);
+  if (he != hipSuccess) return fail_hip(he, "bf_scene_deferred");
+  *n_h = v;
+  return BF_OK;
+}
+
+bf_status bf_scene_set_timing(bf_scene* s, int32_t on) {
+  if (!s) return fail(BF_E_ARG, "bf_scene_set_timing: null scene");
+  if (on && !s->tev[0][0]) {
+    for (int k = 0; k < BF_T_COUNT; ++k)
+      for (int e = 0; e < 2; ++e) {
+        hipError_t he = hipEventCreate(&s->tev[k][e]);
+        if (he != hipSuccess) return fail_hip(he, "bf_scene_set_timing");
+      }
+  }
+  s->timing = on != 0;
+  for (int k = 0; k < BF_T_COUNT; ++k) s->tev_set[k] = false;
+  return BF_OK;
+}
+
+bf_status bf_scene_stage_ms(bf_scene* s, float* ms_h) {
+  if (!s || !ms_h) return fail(BF_E_ARG, "bf_scene_stage_ms: null argument");
+  for (int k = 0; k < BF_T_COUNT; ++k) {
+    ms_h[k] = -1.0f;
+    if (!s->tev_set[k]) continue;
+    hipError_t he = hipEventSynchronize(s->tev[k][1]);
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms_h[k], s->tev[k][0], s->tev[k][1]);
+    if (he != hipSuccess) return fail_hip(he, "bf_scene_stage_ms");
+  }
+  return BF_OK;
 }
 
 bf_status bf_status_word(bf_scene* s, uint32_t* bits_h, int32_t clear) {

@@ -83,9 +83,11 @@ struct StageWs {
   int* sj;       // [cand cap]
   unsigned* sm;  // [cand cap] type | code << 8 | flags << 16
   double* sd;    // [cand cap] distance
-  int* kcnt;     // [3 * G + 1] per-kind counts per tile (kind-major)
-  int* kofs;     // [3 * G + 1] their exclusive scan
+  int* kcnt;     // [4 * G + 1] per-kind counts per tile (kind-major; kind 3: deferred)
+  int* kofs;     // [4 * G + 1] their exclusive scan
   int* ccnt;     // [3 * G] per-tile N_c, N_filt, N_infeasible
+  long long* dfr;  // [cand cap] deferred candidates (indices), in candidate order
+  int* xcnt;       // [5 * XP_BLOCKS] per-range counts of k_exact
   int* scan_tmp;
   long long cap; // staging capacity in candidates
 };

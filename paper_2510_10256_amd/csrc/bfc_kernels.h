@@ -12,6 +12,10 @@ constexpr int PQ_MAX = 8;              // threads per broad-phase query: 2, 4 (d
 constexpr int NW_ITEMS = 4;            // candidates per thread in the narrow phase
 constexpr int LINE_BLOCKS = 8192;      // work-groups of the line-search kernels (grid-stride)
 constexpr int NW_TILE = 256 * NW_ITEMS;
+constexpr int NW_KINDS = 4;            // staged kinds in a narrow-phase tile: 9x9, 6x6, closed form, deferred
+constexpr int NW_DEFER = 3;            // the deferred kind: decided exactly by k_exact
+constexpr int XP_BLOCKS = 1024;        // work-groups of k_exact (ranges of the deferred list)
+constexpr int XP_TPB = 16;             // threads of a k_exact work-group, an LDS expansion slab each
 constexpr int BOUNDS_BLOCKS = 512;     // cap on k_bounds work-groups (partials of the last-block reduction)
 
 constexpr int SCAN_LB_TILES = 256;     // arrays of up to this many tiles take the single-pass scan
@@ -51,11 +55,14 @@ void run_energy(const SceneDev& S, const double* x, const double* pdisp, const d
                 const int* cj, const unsigned char* ct, const long long* ccount, long long ccap, double* bred,
                 double* E_out, hipStream_t st);
 
-// Narrow phase, filter and compaction.
+// Narrow phase and filter (k_narrow: decisions and tile-local compaction),
+// then the list: scan, k_compact, k_exact (the deferred exact decisions).
 void run_narrow(const SceneDev& S, const double* x, const int* ci, const int* cj, const unsigned char* ct,
-                const long long* ccount, long long ccap, const StageWs& W, int* ai, int* aj, unsigned char* at,
-                unsigned char* acode, unsigned char* aflags, double* adist, long long acap, long long* act_count,
-                long long* counters, unsigned* status, hipStream_t st);
+                const long long* ccount, long long ccap, const StageWs& W, hipStream_t st);
+void run_compact(const SceneDev& S, const double* x, const int* ci, const int* cj, const unsigned char* ct,
+                 long long ccap, const StageWs& W, int* ai, int* aj, unsigned char* at, unsigned char* acode,
+                 unsigned char* aflags, double* adist, long long acap, long long* act_count, long long* counters,
+                 unsigned* status, hipStream_t st);
 
 // Per-pair barrier, gradient and projected Hessian.
 void run_eval(const SceneDev& S, const double* x, const int* ai, const int* aj, const unsigned char* at,

@@ -818,8 +818,47 @@ __device__ __forceinline__ bool is_culled(const SceneDev& S, int type, int i, in
   return d <= S.cull_r;
 }
 
-// Stencil pair with 0 < dbar < h in the same component (Sec. 3.2)?
-__device__ __forceinline__ bool is_filtered(const SceneDev& S, int type, const int* v) {
+// dbar^2 < h^2 for a shell pair whose rest distance is near h (not
+// overlapping), exactly when the 2D formulas evaluate without rounding in
+// FP64 (rest coordinates on a lattice): 1 / 0, or 2 when some operation
+// rounds.  dbar^2 < h^2 iff one of the segment distances is.
+__device__ __forceinline__ int seg2_below_exact_in_double(V2<double> p, V2<double> a, V2<double> b, dd hh, bool& ok) {
+  ExactD E{true};
+  const double ex = E.sub(b.x, a.x), ey = E.sub(b.y, a.y), rx = E.sub(p.x, a.x), ry = E.sub(p.y, a.y);
+  const double ee = E.add(E.mul(ex, ex), E.mul(ey, ey)), re = E.add(E.mul(rx, ex), E.mul(ry, ey));
+  double num, den = 1.0;
+  if (!(re > 0.0)) {
+    num = E.add(E.mul(rx, rx), E.mul(ry, ry));
+  } else if (!(re < ee)) {
+    const double qx = E.sub(p.x, b.x), qy = E.sub(p.y, b.y);
+    num = E.add(E.mul(qx, qx), E.mul(qy, qy));
+  } else {
+    const double c = E.sub(E.mul(rx, ey), E.mul(ry, ex));
+    num = E.mul(c, c);
+    den = ee;
+  }
+  ok = ok && E.ok && den > 0.0;
+  return sign_num_minus_tden(num, den, hh) < 0;
+}
+__device__ __forceinline__ int ref_below_h_exact_in_double(const SceneDev& S, int type, const int* v, dd hh) {
+  const V2<double> P0 = ref2(S, v[0]), P1 = ref2(S, v[1]), P2 = ref2(S, v[2]), P3 = ref2(S, v[3]);
+  bool ok = true;
+  int below;
+  if (type == BF_PT) {
+    below = seg2_below_exact_in_double(P0, P1, P2, hh, ok) | seg2_below_exact_in_double(P0, P2, P3, hh, ok) |
+            seg2_below_exact_in_double(P0, P3, P1, hh, ok);
+  } else {
+    below = seg2_below_exact_in_double(P0, P2, P3, hh, ok) | seg2_below_exact_in_double(P1, P2, P3, hh, ok) |
+            seg2_below_exact_in_double(P2, P0, P1, hh, ok) | seg2_below_exact_in_double(P3, P0, P1, hh, ok);
+  }
+  return ok ? below : 2;
+}
+
+// Stencil pair with 0 < dbar < h in the same component (Sec. 3.2)?  Shells
+// compare dbar^2 with h^2 in FP64 outside a relative band of 1e-9 and in
+// double-double inside it; within 1e-20 of h^2 (*amb set, when amb is given)
+// the narrow phase defers the pair to exact arithmetic (is_filtered_exact).
+__device__ __forceinline__ bool is_filtered(const SceneDev& S, int type, const int* v, bool* amb) {
   if (S.filter != 0) return false;
   if (S.comp[v[0]] != S.comp[v[2]]) return false;
   if (S.kind == 0) {
@@ -827,12 +866,49 @@ __device__ __forceinline__ bool is_filtered(const SceneDev& S, int type, const i
     double gap = fmax(fmin(sb0, sb1) - fmax(sa0, sa1), fmin(sa0, sa1) - fmax(sb0, sb1));
     return gap > 0.0 && gap < S.h;
   }
-  double h2 = S.h * S.h;
-  double q = ref_sqdist_d(S, type, v);
+  const double h2 = S.h * S.h;
+  const double q = ref_sqdist_d(S, type, v);
   if (fabs(q - h2) > 1e-9 * h2 && q > 1e-9 * h2) return q < h2;
-  dd qq = ref_sqdist_q(S, type, v);
-  dd hh = dd_sq(S.h), m = dd_of(h2 * BFC_TIE);
-  return dd_lt(m, qq) && dd_lt(qq, hh - m);
+  const dd hh = dd_sq(S.h);
+  if (amb && fabs(q - h2) <= 1e-9 * h2) {  // near h: exact in FP64 on lattice rest coordinates
+    const int r = ref_below_h_exact_in_double(S, type, v, hh);
+    if (r != 2) return r == 1;
+  }
+  const dd qq = ref_sqdist_q(S, type, v);
+  if (amb && !(fabs((qq - hh).hi) > 1e-20 * h2)) *amb = true;  // deferred to exact arithmetic
+  return qq.hi > 0.0 && dd_lt(qq, hh);
+}
+
+// The same decision, exact (k_exact): near h^2 the rest distance is below h
+// iff one of its segment distances is (the pair does not overlap in rest
+// space there), each decided on expansions (xp_seg2_below, slab ws).
+__device__ bool is_filtered_exact(const SceneDev& S, int type, const int* v, double* ws, bool* limit) {
+  const bool r = is_filtered(S, type, v, nullptr);  // FP64, double-double in the band
+  if (S.filter != 0 || S.kind == 0 || S.comp[v[0]] != S.comp[v[2]]) return r;
+  const double h2 = S.h * S.h;
+  if (fabs(ref_sqdist_d(S, type, v) - h2) > 1e-9 * h2) return r;
+  const dd hh = dd_sq(S.h);
+  const int ex = ref_below_h_exact_in_double(S, type, v, hh);
+  if (ex != 2) return ex == 1;
+  if (fabs((ref_sqdist_q(S, type, v) - hh).hi) > 1e-20 * h2) return r;
+  const V2<double> P0 = ref2(S, v[0]), P1 = ref2(S, v[1]), P2 = ref2(S, v[2]), P3 = ref2(S, v[3]);
+  int b[4];
+  if (type == BF_PT) {
+    b[0] = xp_seg2_below(P0.x, P0.y, P1.x, P1.y, P2.x, P2.y, hh, ws);
+    b[1] = xp_seg2_below(P0.x, P0.y, P2.x, P2.y, P3.x, P3.y, hh, ws);
+    b[2] = xp_seg2_below(P0.x, P0.y, P3.x, P3.y, P1.x, P1.y, hh, ws);
+    b[3] = 0;
+  } else {
+    b[0] = xp_seg2_below(P0.x, P0.y, P2.x, P2.y, P3.x, P3.y, hh, ws);
+    b[1] = xp_seg2_below(P1.x, P1.y, P2.x, P2.y, P3.x, P3.y, hh, ws);
+    b[2] = xp_seg2_below(P2.x, P2.y, P0.x, P0.y, P1.x, P1.y, hh, ws);
+    b[3] = xp_seg2_below(P3.x, P3.y, P0.x, P0.y, P1.x, P1.y, hh, ws);
+  }
+  if (b[0] == 2 || b[1] == 2 || b[2] == 2 || b[3] == 2) {
+    *limit = true;
+    return r;
+  }
+  return b[0] == 1 || b[1] == 1 || b[2] == 1 || b[3] == 1;
 }
 
 // Order of the active list by distance kind: 9 x 9 systems (PT, EE) first,
@@ -843,10 +919,58 @@ __device__ __forceinline__ int kind_rank(int code) {
   return (k == K_PT || k == K_EE) ? 0 : (k == K_PE ? 1 : 2);
 }
 
+// Decisions of one candidate pair: the distance sub-case and D = d^2, and
+// d < h (a contact pair, N_c), the filter (Eq. 4: a stencil with
+// 0 < dbar < h), the temporary zero offset (Sec. 3.4), active (Eq. 2: d < a)
+// and infeasible (Eq. 3: d <= eta).  EXACT = false: FP64, double-double where
+// FP64 is unclear, and *amb set where double-double is unclear too (the pair
+// is then left to k_exact); EXACT = true: exact arithmetic there (slab ws;
+// *limit set if the expansions outgrow it).
+struct PairDec {
+  bool nc, filt, core, active, infeas;
+  int code;
+  double D;
+};
+template <bool EXACT>
+__device__ __forceinline__ PairDec narrow_pair(const SceneDev& S, const double* x, int type, int i, int j, bool* amb,
+                                               double* ws, bool* limit) {
+  PairDec r{false, false, false, false, false, 0, 0.0};
+  int v[4];
+  pair_verts(S, type, i, j, v);
+  d3 P[4] = {load3(x, v[0]), load3(x, v[1]), load3(x, v[2]), load3(x, v[3])};
+  const Near nr = type == BF_PT ? classify_pt(P) : classify_ee(P);
+  r.code = nr.code;
+  r.D = nr.D;
+  auto dec = [&](dd T, bool lt) {
+    return EXACT ? decide_sq_exact(r.code, P, r.D, T, lt, ws, limit) : decide_sq(r.code, P, r.D, T, lt, amb);
+  };
+  r.nc = !is_culled(S, type, i, j) && dec(dd_sq(S.h), true);  // d < h (culled pairs: not in contact)
+  if (r.nc) {
+    r.filt = EXACT ? is_filtered_exact(S, type, v, ws, limit) : is_filtered(S, type, v, amb);
+    r.core = !r.filt && in_core(S, type, i, j);
+    dd T;
+    double eta;
+    if (r.filt) {  // Eq. 4 second case: (d_min, 0)
+      const int c = S.comp[v[0]];
+      T = dd{S.thr2[2 * c], S.thr2[2 * c + 1]};
+      eta = 0.0;
+    } else {       // Eq. 4 first case: (h, eta); (h, 0) while in the core set (Sec. 3.4)
+      T = dd_sq(S.h);
+      eta = r.core ? 0.0 : S.eta;
+    }
+    r.active = dec(T, true);  // Eq. 2: d < a
+    if (r.active) r.infeas = eta > 0.0 ? dec(dd_sq(eta), false) : !(r.D > 0.0);
+  }
+  return r;
+}
+
 // Pass 1 of the narrow phase: tile b = candidates [b*NW_TILE, (b+1)*NW_TILE).
 // Active pairs are compacted inside the tile by kind, in candidate order,
-// into the staging arrays; per-kind counts go to kcnt[K*G + b] and the
-// tile's N_c / N_filt / N_infeasible to ccnt[3b..3b+2].  No global atomics.
+// into the staging arrays; a candidate whose decision double-double cannot
+// settle is staged as a fourth kind (its candidate index), for k_exact.
+// Per-kind counts go to kcnt[K*G + b] and the tile's N_c / N_filt /
+// N_infeasible (without the deferred ones) to ccnt[3b..3b+2].  No global
+// atomics.
 __global__ __launch_bounds__(256) void k_narrow(SceneDev S, const double* x, const int* ci, const int* cj,
                                                 const unsigned char* ct, const long long* cand_count, long long ccap,
                                                 StageWs W) {
@@ -854,56 +978,34 @@ __global__ __launch_bounds__(256) void k_narrow(SceneDev S, const double* x, con
   if (n > ccap) n = ccap;
   const int G = gridDim.x;
   const long long base = (long long)blockIdx.x * NW_TILE;
-  const dd h2 = dd_sq(S.h), e2 = dd_sq(S.eta);
   const int lane = lane_id(), w = threadIdx.x >> 6;
-  __shared__ int wc[NW_ITEMS][4][3];
+  __shared__ int wc[NW_ITEMS][4][NW_KINDS];
   __shared__ int cc[4][3];
   int ri[NW_ITEMS], rj[NW_ITEMS], rk[NW_ITEMS], lr[NW_ITEMS];
   unsigned rm[NW_ITEMS];
   double rd[NW_ITEMS];
-  bool act[NW_ITEMS];
   int c_nc = 0, c_f = 0, c_inf = 0;
 #pragma unroll
   for (int it = 0; it < NW_ITEMS; ++it) {
     long long k = base + it * 256 + threadIdx.x;
-    bool nc = false, filt = false, core = false, active = false, infeas = false;
-    int type = 0, i = 0, j = 0, code = 0;
-    double D = 0.0;
+    PairDec pd{false, false, false, false, false, 0, 0.0};
+    int type = 0, i = 0, j = 0;
+    bool amb = false;
     if (k < n) {
       type = ct[k]; i = ci[k]; j = cj[k];
-      int v[4];
-      pair_verts(S, type, i, j, v);
-      d3 P[4] = {load3(x, v[0]), load3(x, v[1]), load3(x, v[2]), load3(x, v[3])};
-      Near nr = type == BF_PT ? classify_pt(P) : classify_ee(P);
-      code = nr.code;
-      D = nr.D;
-      nc = !is_culled(S, type, i, j) && decide_sq(code, P, D, h2, true);  // d < h (culled pairs: not in contact)
-      if (nc) {
-        filt = is_filtered(S, type, v);
-        core = !filt && in_core(S, type, i, j);
-        dd T;
-        double eta;
-        if (filt) {  // Eq. 4 second case: (d_min, 0)
-          int c = S.comp[v[0]];
-          T = dd{S.thr2[2 * c], S.thr2[2 * c + 1]};
-          eta = 0.0;
-        } else {     // Eq. 4 first case: (h, eta); (h, 0) while in the core set (Sec. 3.4)
-          T = h2;
-          eta = core ? 0.0 : S.eta;
-        }
-        active = decide_sq(code, P, D, T, true);  // Eq. 2: d < a
-        if (active) infeas = eta > 0.0 ? decide_sq(code, P, D, e2, false) : !(D > 0.0);
-      }
+      pd = narrow_pair<false>(S, x, type, i, j, &amb, nullptr, nullptr);
     }
-    c_nc += nc; c_f += nc && filt; c_inf += infeas;
-    act[it] = active;
-    rk[it] = active ? kind_rank(code) : 3;
-    ri[it] = i; rj[it] = j;
-    rm[it] = (unsigned)type | ((unsigned)code << 8) |
-             ((unsigned)((filt ? BF_F_FILTERED : 0) | (infeas ? BF_F_INFEASIBLE : 0) | (core ? BF_F_CORE : 0)) << 16);
-    rd[it] = sqrt(D);
+    if (amb) pd.nc = pd.filt = pd.core = pd.active = pd.infeas = false;  // k_exact decides
+    c_nc += pd.nc; c_f += pd.nc && pd.filt; c_inf += pd.infeas;
+    rk[it] = amb ? NW_DEFER : (pd.active ? kind_rank(pd.code) : NW_KINDS);
+    ri[it] = amb ? (int)k : i;
+    rj[it] = j;
+    rm[it] = (unsigned)type | ((unsigned)pd.code << 8) |
+             ((unsigned)((pd.filt ? BF_F_FILTERED : 0) | (pd.infeas ? BF_F_INFEASIBLE : 0) |
+                         (pd.core ? BF_F_CORE : 0)) << 16);
+    rd[it] = sqrt(pd.D);
 #pragma unroll
-    for (int K = 0; K < 3; ++K) {
+    for (int K = 0; K < NW_KINDS; ++K) {
       unsigned long long m = __ballot(rk[it] == K);
       if (lane == 0) wc[it][w][K] = __popcll(m);
       if (rk[it] == K) lr[it] = lanes_below(m);
@@ -912,17 +1014,17 @@ __global__ __launch_bounds__(256) void k_narrow(SceneDev S, const double* x, con
   c_nc = wave_sum(c_nc); c_f = wave_sum(c_f); c_inf = wave_sum(c_inf);
   if (lane == 0) { cc[w][0] = c_nc; cc[w][1] = c_f; cc[w][2] = c_inf; }
   __syncthreads();
-  int tot[3] = {0, 0, 0};
+  int tot[NW_KINDS] = {0, 0, 0, 0};
 #pragma unroll
   for (int it = 0; it < NW_ITEMS; ++it)
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int K = 0; K < 3; ++K) tot[K] += wc[it][q][K];
-  const int koff[3] = {0, tot[0], tot[0] + tot[1]};
+      for (int K = 0; K < NW_KINDS; ++K) tot[K] += wc[it][q][K];
+  const int koff[NW_KINDS] = {0, tot[0], tot[0] + tot[1], tot[0] + tot[1] + tot[2]};
 #pragma unroll
   for (int it = 0; it < NW_ITEMS; ++it) {
-    if (!act[it]) continue;
+    if (rk[it] >= NW_KINDS) continue;
     int K = rk[it];
     int off = koff[K] + lr[it];
     for (int i2 = 0; i2 < NW_ITEMS; ++i2)
@@ -935,8 +1037,8 @@ __global__ __launch_bounds__(256) void k_narrow(SceneDev S, const double* x, con
     W.sd[p] = rd[it];
   }
   if (threadIdx.x == 0) {
-    for (int K = 0; K < 3; ++K) W.kcnt[K * G + blockIdx.x] = tot[K];
-    if (blockIdx.x == 0) W.kcnt[3 * G] = 0;
+    for (int K = 0; K < NW_KINDS; ++K) W.kcnt[K * G + blockIdx.x] = tot[K];
+    if (blockIdx.x == 0) W.kcnt[NW_KINDS * G] = 0;
     int a = 0, b = 0, c = 0;
     for (int q = 0; q < 4; ++q) { a += cc[q][0]; b += cc[q][1]; c += cc[q][2]; }
     W.ccnt[3 * blockIdx.x] = a;
@@ -946,7 +1048,9 @@ __global__ __launch_bounds__(256) void k_narrow(SceneDev S, const double* x, con
 }
 
 // Pass 2: copy each tile's staged pairs to their kind-major position
-// kofs[K*G + b] + r of the active list; block 0 also writes the counters.
+// kofs[K*G + b] + r of the active list, and the deferred candidates to the
+// deferred list (in tile order: candidate order); block 0 also writes the
+// counters (k_exact then adds the deferred pairs' share).
 __global__ __launch_bounds__(256) void k_compact(StageWs W, int G, int* ai, int* aj, unsigned char* at,
                                                  unsigned char* acode, unsigned char* aflags, double* adist,
                                                  long long acap, long long* act_count, long long* counters,
@@ -954,7 +1058,7 @@ __global__ __launch_bounds__(256) void k_compact(StageWs W, int G, int* ai, int*
   const int b = blockIdx.x;
   const long long base = (long long)b * NW_TILE;
   int koff = 0;
-  for (int K = 0; K < 3; ++K) {
+  for (int K = 0; K < NW_KINDS - 1; ++K) {
     int cnt = W.kcnt[K * G + b];
     long long dst = W.kofs[K * G + b];
     for (int r = threadIdx.x; r < cnt; r += blockDim.x) {
@@ -971,6 +1075,11 @@ __global__ __launch_bounds__(256) void k_compact(StageWs W, int G, int* ai, int*
     }
     koff += cnt;
   }
+  {  // deferred candidates (their indices)
+    const int cnt = W.kcnt[NW_DEFER * G + b];
+    const long long dst = W.kofs[NW_DEFER * G + b] - W.kofs[NW_DEFER * G];
+    for (int r = threadIdx.x; r < cnt; r += blockDim.x) W.dfr[dst + r] = W.si[base + koff + r];
+  }
   if (b == 0) {
     __shared__ long long red[3][256];
     long long a = 0, f = 0, c = 0;
@@ -982,42 +1091,177 @@ __global__ __launch_bounds__(256) void k_compact(StageWs W, int G, int* ai, int*
     if (threadIdx.x == 0) {
       long long A = 0, F = 0, C = 0;
       for (int q = 0; q < (int)blockDim.x; ++q) { A += red[0][q]; F += red[1][q]; C += red[2][q]; }
-      long long nact = W.kofs[3 * G];
+      long long nact = W.kofs[NW_DEFER * G];
       counters[0] = A; counters[1] = F; counters[2] = nact; counters[3] = C;
       *act_count = nact;
-      if (nact > acap) atomicOr(status, (unsigned)BF_S_ACT_OVERFLOW);
-      if (C > 0) atomicOr(status, (unsigned)BF_S_INFEASIBLE);
+    }
+  }
+}
+
+// Pass 3: the deferred candidates (neither FP64 nor double-double settled a
+// decision: exact ties whose formula needs more than 106 bits), decided in
+// exact arithmetic.  Work-group b takes the b-th of XP_BLOCKS contiguous
+// ranges of the deferred list, XP_TPB threads each with an expansion slab in
+// LDS; every result goes into the staging arrays at the deferred index (free
+// again after k_compact): ids, type, code, flags, the decisions (bits
+// 24..27: active, d < h, filtered and d < h, expansion room exceeded) and d;
+// the range's counts go to W.xcnt[5b..5b+4] (active, N_c, N_filt,
+// N_infeasible, exceeded).
+__global__ __launch_bounds__(XP_TPB) void k_exact(SceneDev S, const double* x, const int* ci, const int* cj,
+                                                  const unsigned char* ct, StageWs W, int G) {
+  __shared__ double slab[XP_TPB * XP_WS];
+  __shared__ int cnt[5];
+  const long long ndef = W.kofs[NW_KINDS * G] - W.kofs[NW_DEFER * G];
+  const long long R = (ndef + gridDim.x - 1) / gridDim.x, q0 = blockIdx.x * R, q1 = min(ndef, q0 + R);
+  if (threadIdx.x < 5) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  double* ws = slab + threadIdx.x * XP_WS;
+  int c[5] = {0, 0, 0, 0, 0};
+  for (long long q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
+    const long long k = W.dfr[q];
+    const int type = ct[k], i = ci[k], j = cj[k];
+    bool limit = false;
+    const PairDec pd = narrow_pair<true>(S, x, type, i, j, nullptr, ws, &limit);
+    W.si[q] = i;
+    W.sj[q] = j;
+    W.sm[q] = (unsigned)type | ((unsigned)pd.code << 8) |
+              ((unsigned)((pd.filt ? BF_F_FILTERED : 0) | (pd.infeas ? BF_F_INFEASIBLE : 0) |
+                          (pd.core ? BF_F_CORE : 0)) << 16) |
+              (pd.active ? 1u << 24 : 0u) | (pd.nc ? 1u << 25 : 0u) | (pd.nc && pd.filt ? 1u << 26 : 0u) |
+              (limit ? 1u << 27 : 0u);
+    W.sd[q] = sqrt(pd.D);
+    c[0] += pd.active; c[1] += pd.nc; c[2] += pd.nc && pd.filt; c[3] += pd.infeas; c[4] += limit;
+  }
+#pragma unroll
+  for (int t = 0; t < 5; ++t)
+    if (c[t]) atomicAdd(&cnt[t], c[t]);
+  __syncthreads();
+  if (threadIdx.x < 5) W.xcnt[5 * blockIdx.x + threadIdx.x] = cnt[threadIdx.x];
+}
+
+// Pass 4: the deferred pairs that are active are appended after the
+// compacted ones, in candidate order: work-group b copies its range's, after
+// the active pairs of all earlier ranges.  Work-group 0 adds the counts and
+// raises the step's overflow and infeasible bits.
+__global__ __launch_bounds__(256) void k_exact_emit(StageWs W, int G, int* ai, int* aj, unsigned char* at,
+                                                    unsigned char* acode, unsigned char* aflags, double* adist,
+                                                    long long acap, long long* act_count, long long* counters,
+                                                    unsigned* status) {
+  const long long ndef = W.kofs[NW_KINDS * G] - W.kofs[NW_DEFER * G];
+  const long long nact0 = W.kofs[NW_DEFER * G];  // the compacted pairs (k_compact's count)
+  const long long R = (ndef + gridDim.x - 1) / gridDim.x, q0 = blockIdx.x * R, q1 = min(ndef, q0 + R);
+  long long before = 0;
+  for (int b = threadIdx.x; b < (int)blockIdx.x; b += blockDim.x) before += W.xcnt[5 * b];
+  before = block_sum256(before);
+  long long run = nact0 + before;
+  for (long long c0 = q0; c0 < q1; c0 += blockDim.x) {
+    const long long q = c0 + threadIdx.x;
+    const unsigned m = q < q1 ? W.sm[q] : 0u;
+    const bool active = (m >> 24) & 1u;
+    int tot;
+    const int ex = block_excl_scan256(active ? 1 : 0, &tot);
+    if (active) {
+      const long long d = run + ex;
+      if (d < acap) {
+        ai[d] = W.si[q];
+        aj[d] = W.sj[q];
+        at[d] = (unsigned char)(m & 0xffu);
+        acode[d] = (unsigned char)((m >> 8) & 0xffu);
+        aflags[d] = (unsigned char)((m >> 16) & 0xffu);
+        adist[d] = W.sd[q];
+      }
+    }
+    run += tot;
+  }
+  if (blockIdx.x == 0) {
+    long long s[5] = {0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x)
+      for (int t = 0; t < 5; ++t) s[t] += W.xcnt[5 * b + t];
+    for (int t = 0; t < 5; ++t) s[t] = block_sum256(s[t]);
+    if (threadIdx.x == 0) {
+      const long long nact = nact0 + s[0];
+      counters[0] += s[1];
+      counters[1] += s[2];
+      counters[2] = nact;
+      counters[3] += s[3];
+      *act_count = nact;
+      status[1] = (unsigned)min(ndef, 0xffffffffll);  // deferred candidates of this step (diagnostics)
+      unsigned bits = 0;
+      if (nact > acap) bits |= BF_S_ACT_OVERFLOW;
+      if (counters[3] > 0) bits |= BF_S_INFEASIBLE;
+      if (s[4] > 0) bits |= BF_S_EXACT_LIMIT;
+      if (bits) atomicOr(status, bits);
     }
   }
 }
 
 // ---------------------------------------------------------------------------
+// Packed pair Hessian: the upper triangle of the symmetric 12 x 12 matrix by
+// 3 x 3 blocks, 78 doubles.  Block-row s (the rows of stencil vertex s)
+// holds block (s, s) as its upper triangle (xx, xy, xz, yy, yz, zz), then
+// blocks (s, t), t > s, row-major; block-rows 0..3 follow one another
+// (offsets 0, 33, 57, 72).
+// ---------------------------------------------------------------------------
+constexpr int PK_N = 78;
+__host__ __device__ constexpr int pk_off(int s) { return s == 0 ? 0 : s == 1 ? 33 : s == 2 ? 57 : 72; }
+__host__ __device__ constexpr int pk_len(int s) { return 6 + 9 * (3 - s); }
+// packed index of entry (I, J) of the 12 x 12 matrix, I <= J or not
+__host__ __device__ constexpr int pk_index(int I, int J) {
+  const int a = I < J ? I : J, b = I < J ? J : I;
+  const int s = a / 3, i = a % 3, t = b / 3, j = b % 3;
+  if (s == t) return pk_off(s) + (i == 0 ? j : i == 1 ? 2 + j : 5);
+  return pk_off(s) + 6 + 9 * (t - s - 1) + 3 * i + j;
+}
+// tables: the (row, column) of each packed entry, and for each stencil slot
+// s the packed source of each entry of its band (rows 3s..3s+2, 36 doubles)
+struct PkTables {
+  unsigned char row[PK_N], col[PK_N];
+  unsigned char band[4][36];
+  constexpr PkTables() : row(), col(), band() {
+    for (int I = 0; I < 12; ++I)
+      for (int J = I; J < 12; ++J) {
+        row[pk_index(I, J)] = (unsigned char)I;
+        col[pk_index(I, J)] = (unsigned char)J;
+      }
+    for (int sl = 0; sl < 4; ++sl)
+      for (int o = 0; o < 36; ++o) band[sl][o] = (unsigned char)pk_index(3 * sl + o / 12, o % 12);
+  }
+};
+__constant__ PkTables kPk = PkTables();
+
+// ---------------------------------------------------------------------------
 // Barrier evaluation (Eq. 2, Eq. 3) and PSD projection
 // ---------------------------------------------------------------------------
 // One wave per work-group, one pair per lane.  Each lane keeps its pair's
-// projected Hessian in reduced form (registers); the 12 rows of the 12 x 12
-// matrices of the tile's 64 pairs then go out one row at a time through a
-// small LDS buffer, as contiguous 96-byte segments written 16 bytes a lane
-// (a 64 x 144 staging tile would cut occupancy to three waves per CU; stores
-// straight from each lane's registers scatter every instruction over 64
-// cache lines; two rows a pass, or a fallback for unaligned H, raise the
-// register pressure of the whole kernel).  The
-// energies of each 64-pair tile are summed in a fixed order into epart
-// (partials of the total).
+// projected Hessian in reduced form (registers); its packed upper triangle
+// then goes out one block-row at a time: the lanes write the block-row's
+// entries of their rows into a small LDS tile (one row at a time, from the
+// reduced form), and the wave stores the 64 pairs' segments (33, 24, 15 and 6
+// contiguous doubles) as runs (stores straight from each lane's registers
+// would scatter every instruction over 64 records).  The energies of each
+// 64-pair tile are summed in a fixed order into epart (partials of the
+// total).
+constexpr int PK_STRIDE = 33;  // LDS doubles per pair in the staging tile (the longest block-row)
 template <int I>
 __device__ __forceinline__ void flush_row(const PairOut& h, double* buf, double* H, long long k0, int rows) {
+  constexpr int s = I / 3, i = I % 3;
   const int lane = threadIdx.x;
   double r[12];
   hess_row<I>(h, r);
+  double* my = buf + PK_STRIDE * lane;
 #pragma unroll
-  for (int j = 0; j < 12; ++j) buf[13 * lane + j] = r[j];
-  __syncthreads();
+  for (int j = i; j < 3; ++j) my[pk_index(I, 3 * s + j) - pk_off(s)] = r[3 * s + j];
 #pragma unroll
-  for (int q = 0; q < 6; ++q) {  // two doubles a store (H is 16-byte aligned, rows are 96 bytes)
-    const int v = lane + 64 * q, p = v / 6, c = v - 6 * p;
-    if (p < rows) *(double2*)(H + 144 * (k0 + p) + 12 * I + 2 * c) = make_double2(buf[13 * p + 2 * c], buf[13 * p + 2 * c + 1]);
+  for (int c = 3 * s + 3; c < 12; ++c) my[pk_index(I, c) - pk_off(s)] = r[c];
+  if constexpr (i == 2) {  // the block-row is complete: store the tile's segments
+    __syncthreads();
+    constexpr int len = pk_len(s);
+    for (int idx = lane; idx < rows * len; idx += 64) {
+      const int p = idx / len, e = idx - p * len;
+      H[PK_N * (k0 + p) + pk_off(s) + e] = buf[PK_STRIDE * p + e];
+    }
+    __syncthreads();
   }
-  __syncthreads();
 }
 template <int I>
 __device__ __forceinline__ void flush_rows(const PairOut& h, double* buf, double* H, long long k0, int rows) {
@@ -1030,7 +1274,7 @@ __global__ __launch_bounds__(64) void k_eval(SceneDev S, const double* x, const 
                                              const unsigned char* at, const unsigned char* acode,
                                              const unsigned char* aflags, const unsigned long long* act_count,
                                              long long acap, double* E, double* G, double* H, double* epart) {
-  __shared__ double buf[64 * 13];
+  __shared__ double buf[64 * PK_STRIDE];
   long long n = (long long)*act_count;
   if (n > acap) n = acap;
   const int lane = threadIdx.x;
@@ -1567,10 +1811,11 @@ __device__ __forceinline__ void row_b(const SceneDev& S, const int* ai, const in
       double gx = 0.0, gy = 0.0, gz = 0.0;
       if (q < nq) {
         const int e = inc[b + qc + q], k = e >> 2;
-        const double* src = H + 144LL * k + 36 * (e & 3) + PART * part;
+        const double* src = H + (long long)PK_N * k;  // the band of slot e & 3, gathered from the packed record
+        const unsigned char* map = kPk.band[e & 3] + PART * part;
         double* dst = band + 36 * q + PART * part;
 #pragma unroll
-        for (int o = 0; o < PART; ++o) dst[o] = src[o];
+        for (int o = 0; o < PART; ++o) dst[o] = src[map[o]];
         if (part == 0) {
           const int4 w4 = stn[b + qc + q];
           vs[4 * q] = w4.x;
@@ -1670,10 +1915,11 @@ __device__ __forceinline__ void row_b_team(const SceneDev& S, const int* ai, con
       const int eq = __shfl(e, qc + r, 16);
       __syncthreads();  // the stencils are written, the previous chunk is read
       if (qc + r < m) {
-        const double* src = H + 144LL * (eq >> 2) + 36 * (eq & 3) + 9 * part;
+        const double* src = H + (long long)PK_N * (eq >> 2);  // the band of slot eq & 3, from the packed record
+        const unsigned char* map = kPk.band[eq & 3] + 9 * part;
         double* dst = bt + 36 * r + 9 * part;
 #pragma unroll
-        for (int o = 0; o < 9; ++o) dst[o] = src[o];
+        for (int o = 0; o < 9; ++o) dst[o] = src[map[o]];
       }
       __syncthreads();
       const int nq = min(TEAM_CH, m - qc);
@@ -1923,7 +2169,7 @@ __global__ __launch_bounds__(256) void k_accd(SceneDev S, const double* x, const
               double t = -1.0;
               bool go = false;
               if (!is_culled(S, type, ci[kk], cj[kk]) && swept_within(type, X, P, S.h)) {
-                const double xi = is_filtered(S, type, v) || in_core(S, type, ci[kk], cj[kk]) ? 0.0 : S.eta;
+                const double xi = is_filtered(S, type, v, nullptr) || in_core(S, type, ci[kk], cj[kk]) ? 0.0 : S.eta;
                 go = accd_setup(A, type, X, P, xi, s, t);
               }
               if (go) {
@@ -1960,7 +2206,7 @@ __global__ __launch_bounds__(256) void k_accd(SceneDev S, const double* x, const
       double t = -1.0;
       int it = 0;
       if (!is_culled(S, type, ci[k], cj[k]) && swept_within(type, X, P, S.h)) {
-        const double xi = is_filtered(S, type, v) || in_core(S, type, ci[k], cj[k]) ? 0.0 : S.eta;
+        const double xi = is_filtered(S, type, v, nullptr) || in_core(S, type, ci[k], cj[k]) ? 0.0 : S.eta;
         Accd A;
         if (accd_setup(A, type, X, P, xi, s, t)) {
           while (accd_step(A, max_iter, t)) {
@@ -2019,10 +2265,10 @@ __global__ __launch_bounds__(256) void k_energy(SceneDev S, const double* x, con
     }
     if (is_culled(S, type, ci[k], cj[k])) continue;
     const Near nr = type == BF_PT ? classify_pt(P) : classify_ee(P);
-    if (!decide_sq(nr.code, P, nr.D, h2, true)) continue;  // d >= h
+    if (!decide_sq(nr.code, P, nr.D, h2, true, nullptr)) continue;  // d >= h
     dd T;
     double a, eta;
-    if (is_filtered(S, type, v)) {
+    if (is_filtered(S, type, v, nullptr)) {
       const int c = S.comp[v[0]];
       T = dd{S.thr2[2 * c], S.thr2[2 * c + 1]};
       a = S.dmin[c];
@@ -2032,8 +2278,8 @@ __global__ __launch_bounds__(256) void k_energy(SceneDev S, const double* x, con
       a = S.h;
       eta = in_core(S, type, ci[k], cj[k]) ? 0.0 : S.eta;
     }
-    if (!decide_sq(nr.code, P, nr.D, T, true)) continue;  // inactive: d >= a
-    const bool infeas = eta > 0.0 ? decide_sq(nr.code, P, nr.D, e2, false) : !(nr.D > 0.0);
+    if (!decide_sq(nr.code, P, nr.D, T, true, nullptr)) continue;  // inactive: d >= a
+    const bool infeas = eta > 0.0 ? decide_sq(nr.code, P, nr.D, e2, false, nullptr) : !(nr.D > 0.0);
     if (infeas) {
       e += INFINITY;
       continue;
@@ -2149,10 +2395,10 @@ __global__ __launch_bounds__(256) void k_friction_lag(SceneDev S, const double* 
 //
 // Four waves per 64 pairs.  Each lane of the first wave computes its pair's
 // w[4], force f[3] and M[9] and leaves them in LDS; the four waves then
-// write the tile's 64 x 12 gradient and 64 x 144 Hessian entries as one
+// write the tile's 64 x 12 gradient and 64 x 78 packed Hessian entries as one
 // contiguous run each (thread t takes entries t, t + 256, ...), rebuilding
 // every entry from LDS as w_q f_i or w_q w_r M_ij.  Stores straight from each
-// lane's registers would scatter every instruction over 64 rows 1152 bytes
+// lane's registers would scatter every instruction over 64 records 624 bytes
 // apart; the extra waves shorten the store loop of a tile.
 constexpr int FR_ST = 17;  // LDS doubles per pair: w[4], f[3], M[9], pad (odd stride)
 __global__ __launch_bounds__(256) void k_friction_eval(SceneDev S, const double* x, const double* xl, const int* ai,
@@ -2223,11 +2469,11 @@ __global__ __launch_bounds__(256) void k_friction_eval(SceneDev S, const double*
         Gt[idx] = accumulate ? __dadd_rn(Gt[idx], val) : val;
       }
     }
-    double* Ht = H + 144 * k0;
-    for (int it = 0; it < 36; ++it) {
-      const int idx = it * 256 + tid, pp = idx / 144, rem = idx - 144 * pp;
+    double* Ht = H + PK_N * k0;
+    for (int it = 0; it < (64 * PK_N + 255) / 256; ++it) {  // the packed upper triangles, as one run
+      const int idx = it * 256 + tid, pp = idx / PK_N, rem = idx - PK_N * pp;
       if (pp < rows) {
-        const int rw = rem / 12, cl = rem - 12 * rw;
+        const int rw = kPk.row[rem], cl = kPk.col[rem];
         const double* ps = sm + FR_ST * pp;
         const double val = __dmul_rn(ps[rw / 3] * ps[cl / 3], ps[7 + 3 * (rw % 3) + cl % 3]);
         Ht[idx] = accumulate ? __dadd_rn(Ht[idx], val) : val;
@@ -2262,9 +2508,9 @@ __global__ __launch_bounds__(256) void k_core_mark(SceneDev S, const double* x, 
     d3 P[4] = {load3(x, v[0]), load3(x, v[1]), load3(x, v[2]), load3(x, v[3])};
     if (is_culled(S, type, i, j)) continue;
     const Near nr = type == BF_PT ? classify_pt(P) : classify_ee(P);
-    if (!decide_sq(nr.code, P, nr.D, h2, true)) continue;    // d >= h
-    if (is_filtered(S, type, v)) continue;                  // stencils have no offset anyway
-    if (!decide_sq(nr.code, P, nr.D, e2, false)) continue;  // d > eta
+    if (!decide_sq(nr.code, P, nr.D, h2, true, nullptr)) continue;    // d >= h
+    if (is_filtered(S, type, v, nullptr)) continue;                  // stencils have no offset anyway
+    if (!decide_sq(nr.code, P, nr.D, e2, false, nullptr)) continue;  // d > eta
     const unsigned long long key = core_key_of(type, i, j);
     unsigned h = core_hash(key) & mask;
     bool placed = false;
@@ -2293,7 +2539,7 @@ __global__ __launch_bounds__(256) void k_core_release(SceneDev S, const double* 
     pair_verts(S, type, i, j, v);
     d3 P[4] = {load3(x, v[0]), load3(x, v[1]), load3(x, v[2]), load3(x, v[3])};
     const Near nr = type == BF_PT ? classify_pt(P) : classify_ee(P);
-    if (!decide_sq(nr.code, P, nr.D, e2, false)) live[q] = 0;
+    if (!decide_sq(nr.code, P, nr.D, e2, false, nullptr)) live[q] = 0;
   }
 }
 
@@ -2529,14 +2775,22 @@ void run_energy(const SceneDev& S, const double* x, const double* pdisp, const d
 }
 
 void run_narrow(const SceneDev& S, const double* x, const int* ci, const int* cj, const unsigned char* ct,
-                const long long* ccount, long long ccap, const StageWs& W, int* ai, int* aj, unsigned char* at,
-                unsigned char* acode, unsigned char* aflags, double* adist, long long acap, long long* act_count,
-                long long* counters, unsigned* status, hipStream_t st) {
+                const long long* ccount, long long ccap, const StageWs& W, hipStream_t st) {
   int G = (int)((ccap + NW_TILE - 1) / NW_TILE);
   hipLaunchKernelGGL(k_narrow, dim3(G), dim3(256), 0, st, S, x, ci, cj, ct, ccount, ccap, W);
-  scan_excl(W.kcnt, W.kofs, nullptr, 3 * G + 1, W.scan_tmp, status, st);
+}
+
+void run_compact(const SceneDev& S, const double* x, const int* ci, const int* cj, const unsigned char* ct,
+                 long long ccap, const StageWs& W, int* ai, int* aj, unsigned char* at, unsigned char* acode,
+                 unsigned char* aflags, double* adist, long long acap, long long* act_count, long long* counters,
+                 unsigned* status, hipStream_t st) {
+  int G = (int)((ccap + NW_TILE - 1) / NW_TILE);
+  scan_excl(W.kcnt, W.kofs, nullptr, NW_KINDS * G + 1, W.scan_tmp, status, st);
   hipLaunchKernelGGL(k_compact, dim3(G), dim3(256), 0, st, W, G, ai, aj, at, acode, aflags, adist, acap, act_count,
                      counters, status);
+  hipLaunchKernelGGL(k_exact, dim3(XP_BLOCKS), dim3(XP_TPB), 0, st, S, x, ci, cj, ct, W, G);
+  hipLaunchKernelGGL(k_exact_emit, dim3(XP_BLOCKS), dim3(256), 0, st, W, G, ai, aj, at, acode, aflags, adist, acap,
+                     act_count, counters, status);
 }
 
 void run_eval(const SceneDev& S, const double* x, const int* ai, const int* aj, const unsigned char* at,

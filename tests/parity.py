@@ -8,6 +8,15 @@ b_ref = kappa * (w/2)^2 ln 2:
     |dH+|_F  <= tau (|H+|_F + b_ref / w^2)
 Assembled values use the same bounds summed over the contributing pairs.
 The active set (type, i, j, filtered, infeasible) must match exactly.
+
+Where the two sides chose different distance sub-cases for a pair (a pair
+on the boundary between regions, where several sub-cases give the same
+distance: lattice geometry puts points exactly above vertices and edges),
+the energy and gradient are still unique and compared as above; the GPU's
+choice must be a valid one (its sub-case's distance equals the minimum to
+1e-12) and its Hessian is compared with the oracle's derivatives of that
+same sub-case (the one-sided Hessian on the GPU's side of the boundary).
+This needs the positions: gpu["x"].
 """
 import math
 
@@ -47,6 +56,7 @@ def compare(gpu, orc, nv, kappa=1.0, tau=1e-10, check_assembly=True, derivs=True
         assert not missing, f"{len(missing)} pairs with d < h missing from the candidates"
     if not len(gi):
         return report
+    orc = _with_gpu_subcases(gpu, orc, gi, oi, report, kappa)
     a, eta = orc["a"][oi], orc["eta"][oi]
     w = a - eta
     bref = kappa * (w / 2) ** 2 * math.log(2)
@@ -91,3 +101,53 @@ def compare(gpu, orc, nv, kappa=1.0, tau=1e-10, check_assembly=True, derivs=True
         dv = np.linalg.norm((gpu["val"] - asm["val"]).reshape(-1, 9), axis=1)
         assert np.all(dv <= hb[rows] + 1e-300), "assembled Hessian blocks"
     return report
+
+
+def _with_gpu_subcases(gpu, orc, gi, oi, report, kappa):
+    """The oracle's results with the pairs whose sub-case differs from the
+    GPU's re-derived on the GPU's sub-case, after checking that the GPU's
+    sub-case is a valid choice (same distance)."""
+    diff = np.nonzero(gpu["code"][gi] != orc["code"][oi])[0]
+    report["subcase_ties"] = int(len(diff))
+    if not len(diff) or "Hpsd" not in orc:
+        return orc
+    assert "x" in gpu, f"{len(diff)} pairs with another sub-case and no positions to check them"
+    x = np.asarray(gpu["x"], np.float64)
+    out = dict(orc)
+    out["G"] = orc["G"].copy()
+    out["Hpsd"] = orc["Hpsd"].copy()
+    for q in diff:
+        k = oi[q]
+        if orc["flags"][k] & oracle.F_INFEASIBLE:
+            continue
+        X = x[orc["verts"][k]].reshape(12)
+        code = int(gpu["code"][gi[q]])
+        D_alt = oracle.case_distance(code, X)[0]
+        D_min = orc["d"][k] ** 2
+        assert abs(D_alt - D_min) <= 1e-12 * D_min, f"GPU sub-case {code} is not a nearest one"
+        r = oracle.pair_barrier_code(code, X, orc["a"][k], orc["eta"][k], kappa=kappa, quad=True)
+        out["G"][k] = r["G"]
+        out["Hpsd"][k] = r["Hpsd"]
+    return out
+
+
+def compare_assembled(E, g, orc, nv, kappa=1.0, tau=1e-10):
+    """The assembled energy and gradient of a step (E, g[V,3]) against the
+    oracle's, within the summed per-pair bounds (the serving loop returns
+    only these)."""
+    asm = oracle.assemble(orc, nv)
+    act = (orc["flags"] & oracle.F_ACTIVE) != 0
+    feas = act & ((orc["flags"] & oracle.F_INFEASIBLE) == 0)
+    w = (orc["a"] - orc["eta"])[feas]
+    bref = kappa * (w / 2) ** 2 * math.log(2)
+    if np.all(feas == act):
+        assert abs(E - asm["E"]) <= tau * np.sum(np.abs(orc["E"][feas]) + bref) + 1e-300, "assembled energy"
+    else:
+        assert np.isinf(E) and np.isinf(asm["E"])
+    gb = np.zeros(nv)
+    nG = np.linalg.norm(orc["G"][feas], axis=1)
+    for s in range(4):
+        np.add.at(gb, orc["verts"][feas][:, s], tau * (nG + bref / w))
+    dg = np.linalg.norm(np.asarray(g) - asm["g"], axis=1)
+    assert np.all(dg <= gb + 1e-300), "assembled gradient"
+    return {"E_ratio": abs(E - asm["E"]) / (tau * np.sum(np.abs(orc["E"][feas]) + bref) + 1e-300)}

@@ -1,5 +1,6 @@
 """Batches: many scenes stepped by one graph launch give, scene by scene,
-bitwise the results of the scene stepped alone; counts match the oracle."""
+bitwise the results of the scene stepped alone, and the oracle's results
+element by element."""
 import numpy as np
 import pytest
 
@@ -64,6 +65,39 @@ def test_batch_equals_alone(prec, lanes):
             for f in FIELDS:
                 assert np.array_equal(got[f], alone[k][f], equal_nan=True), (k, rep, f)
             assert got["E_total"] == alone[k]["E_total"]
+    batch.close()
+    for cs in css:
+        cs.close()
+
+
+@requires_gpu
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_scenes_match_the_oracle(prec):
+    # every scene of a batch step (four lanes), element by element against the
+    # oracle: active set, counts, per-pair values and the assembly
+    import paper_2510_10256_amd as bfc
+    from tests.parity import compare
+    p = bfc.BF_FP64 if prec == "fp64" else bfc.BF_MIXED
+    scenes = _scenes()
+    print(f"[batch vs oracle] prec={prec} scenes={len(scenes)}", flush=True)
+    dev = torch.device("cuda:0")
+    css, xs = [], []
+    for sc in scenes:
+        cs = bfc.ContactScene(sc, prec=p, device=dev)
+        x = torch.tensor(sc.x, dtype=torch.float64, device=dev)
+        cs.run(x)
+        _fill_outputs(cs)
+        css.append(cs)
+        xs.append(x)
+    batch = bfc.Batch(css, xs, lanes=0)
+    batch.step()
+    torch.cuda.synchronize()
+    for sc, cs in zip(scenes, css):
+        g = cs.results()
+        g["x"] = sc.x
+        rep = compare(g, oracle.evaluate(sc, mode=1), sc.n_verts, kappa=sc.kappa,
+                      tau=1e-10 if prec == "fp64" else 1e-5)
+        print(sc.name, g["counts"], rep, flush=True)
     batch.close()
     for cs in css:
         cs.close()

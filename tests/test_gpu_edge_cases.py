@@ -90,3 +90,57 @@ def test_edge_case_matches_the_oracle(name):
         assert c["n_act"] == 1 and c["n_infeasible"] == 0 and g["E_total"] > 0.0 and c["nnzb"] == 16
     if name == "infeasible":
         assert c["n_infeasible"] == 1 and st & bfc.BF_S_INFEASIBLE and g["E_total"] == float("inf")
+
+
+@requires_gpu
+def test_capacity_overflow_reports_sizes_and_retry_matches_the_oracle():
+    # every device store of the step is guarded by its buffer's capacity: a
+    # list that does not fit sets its status bit and its counter still holds
+    # the size required; growing the buffers to those sizes and stepping again
+    # gives the oracle's results
+    import ctypes as C
+    import paper_2510_10256_amd as bfc
+    from paper_2510_10256_amd import binding as B
+    sc = synth.woven_patch(n_warp=4, n_weft=4, verts_per_rod=80)
+    print(f"[overflow] {sc.name} V={sc.n_verts}", flush=True)
+    o = oracle.evaluate(sc, mode=1)
+    oc = oracle.counts(o)
+    cs = bfc.ContactScene(sc, cand_cap=256, act_cap=64, bsr_cap=64, device="cuda:0")
+    x = cs._as_x(sc.x)
+
+    def grow(cand=None, act=None, bsr=None):
+        cs.cand_cap = cand or cs.cand_cap
+        cs.act_cap = act or cs.act_cap
+        cs.bsr_cap = bsr or cs.bsr_cap
+        B._check(B.lib().bf_scene_reserve(cs.handle, cs.cand_cap, cs.act_cap), "bf_scene_reserve")
+        cs._alloc()
+
+    cs.step(x)
+    st = cs.status(clear=True)
+    assert st & B.BF_S_CAND_OVERFLOW
+    need_cand = int(cs.c_n.item())
+    assert need_cand > 256
+    grow(cand=need_cand)
+    cs.step(x)
+    st = cs.status(clear=True)
+    assert not (st & B.BF_S_CAND_OVERFLOW) and int(cs.c_n.item()) == need_cand
+    assert st & B.BF_S_ACT_OVERFLOW
+    need_act = int(cs.a_n.item())
+    assert need_act == oc["n_act"] and int(cs.counters[2].item()) == oc["n_act"] and need_act > 64
+    grow(act=need_act)
+    cs.step(x)
+    st = cs.status(clear=True)
+    assert not (st & (B.BF_S_CAND_OVERFLOW | B.BF_S_ACT_OVERFLOW))
+    assert st & B.BF_S_BSR_OVERFLOW
+    need_bsr = int(cs.nnzb.item())
+    assert need_bsr > 64
+    grow(bsr=need_bsr)
+    cs.step(x)
+    st = cs.status(clear=True)
+    assert not (st & (B.BF_S_CAND_OVERFLOW | B.BF_S_ACT_OVERFLOW | B.BF_S_BSR_OVERFLOW)), st
+    g = cs.results()
+    g["x"] = sc.x
+    assert g["counts"]["nnzb"] == need_bsr
+    rep = compare(g, o, sc.n_verts, kappa=sc.kappa, tau=1e-10)
+    print(g["counts"], rep, flush=True)
+    cs.close()

@@ -1,6 +1,6 @@
 """Serving loop on the GPU: requests overlap on the device, scenes are evicted
 and re-created under a small HBM budget, and every result equals, bitwise,
-the same request evaluated alone."""
+the same request evaluated alone, and the oracle's energy and gradient."""
 import numpy as np
 import pytest
 
@@ -42,4 +42,15 @@ def test_served_results_equal_alone():
         for k in ("n_c", "n_filt", "n_act", "n_infeasible", "nnzb"):
             assert req.counts[k] == r["counts"][k], (req.rid, k)
         assert np.array_equal(req.g.numpy(), r["g"]), req.rid
+    # and against the oracle: counts, assembled energy and gradient of every
+    # served request (mixed precision: tau = 1e-5)
+    import oracle
+    from tests.parity import compare_assembled
+    for req in done:
+        sc = scenes[req.sid]
+        o = oracle.evaluate(sc, x=req.x, mode=1)
+        oc = oracle.counts(o)
+        for k in ("n_c", "n_filt", "n_act", "n_infeasible"):
+            assert req.counts[k] == oc[k], (req.rid, k)
+        compare_assembled(req.E, req.g.numpy(), o, sc.n_verts, kappa=sc.kappa, tau=1e-5)
     server.close()

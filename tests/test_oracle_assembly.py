@@ -110,8 +110,8 @@ def test_planted_transposed_block_fails(monkeypatch):
     # symmetric diagonal but fails the Hessian pin
     sc = _scenes()[1]
     monkeypatch.setattr(oracle, "_block",
-                        lambda H, r, c: (H[3 * r:3 * r + 3, 3 * c:3 * c + 3].T if r != c
-                                         else H[3 * r:3 * r + 3, 3 * c:3 * c + 3]))
+                        lambda H, r, c: (H[..., 3 * r:3 * r + 3, 3 * c:3 * c + 3].swapaxes(-1, -2) if r != c
+                                         else H[..., 3 * r:3 * r + 3, 3 * c:3 * c + 3]))
     assert _hess_pin(sc) > 1e-3
 
 
@@ -119,7 +119,7 @@ def test_planted_wrong_stencil_map_fails(monkeypatch):
     # a mistake that swaps two stencil slots sends gradient and blocks to the
     # wrong vertices: both pins fail
     sc = _scenes()[1]
-    monkeypatch.setattr(oracle, "_stencil", lambda res, k: res["verts"][k][[0, 2, 1, 3]])
+    monkeypatch.setattr(oracle, "_stencil", lambda res, k: res["verts"][k][..., [0, 2, 1, 3]])
     assert _grad_pin(sc) > 1e-3
     assert _hess_pin(sc) > 1e-3
 
