@@ -260,6 +260,19 @@ bf_status max_step_accd(bf_scene* s, const double* x_d, const double* p_d, const
 bf_status eval_energy(bf_scene* s, const double* x_d, const double* p_d, const double* alpha_d,
                       const bf_pairs* cand, double* E_d, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * evaluation as eval_energy, with the same arguments and results (bitwise),
+ * whose per-work-group partial sums live in a static device array of the
+ * library (8,192 doubles, 64 KiB per device, held until the process ends)
+ * instead of the scene's scratch.  It allocates nothing and takes any
+ * candidate count (the energy kernel strides over the list with at most
+ * 8,192 work-groups); BF_E_CAPACITY if the partials would not fit.  All
+ * calls on one device share the array: calls that overlap on one device
+ * race; calls one after another on a stream do not. */
+bf_status eval_energy_noalloc(bf_scene* s, const double* x_d, const double* p_d, const double* alpha_d,
+                              const bf_pairs* cand, double* E_d, void* stream);
+
 /* ---- temporary zero offset (Sec. 3.4) -----------------------------------
  * Pairs that are not stencils but start closer than eta (inside the core:
  * an input intersecting within the offset) make the biphasic barrier

@@ -31,7 +31,7 @@ EXPORTED = ["bf_scene_create", "bf_scene_reserve", "bf_scene_destroy", "bf_scene
             "bf_batch_create", "bf_batch_step", "bf_batch_info", "bf_batch_destroy", "build_candidates_swept",
             "max_step_accd", "eval_energy", "bf_core_mark", "bf_core_live", "bf_core_clear", "friction_lag",
             "friction_eval", "friction_assemble", "bf_status_word", "bf_set_scan_poll_limit", "bf_scene_set_timing",
-            "bf_scene_stage_ms", "bf_scene_deferred", "bf_last_error"]
+            "bf_scene_stage_ms", "eval_energy_noalloc", "bf_scene_deferred", "bf_last_error"]
 
 
 def build(verbose: bool = False) -> str:
@@ -135,6 +135,7 @@ def lib():
         L.build_candidates_swept.argtypes = [P, P, P, C.POINTER(Pairs), P]
         L.max_step_accd.argtypes = [P, P, P, C.POINTER(Pairs), C.c_double, C.c_int32, P, P, P, P]
         L.eval_energy.argtypes = [P, P, P, P, C.POINTER(Pairs), P, P]
+        L.eval_energy_noalloc.argtypes = [P, P, P, P, C.POINTER(Pairs), P, P]
         L.bf_core_mark.argtypes = [P, P, C.POINTER(Pairs), C.c_int64, P, P]
         L.bf_core_live.argtypes = [P, P, P]
         L.bf_core_clear.argtypes = [P]
@@ -302,6 +303,15 @@ class ContactScene:
         _check(lib().eval_energy(self.handle, _ptr(x), _ptr(p) if p is not None else None,
                                  _ptr(alpha) if alpha is not None else None, C.byref(self._cand), _ptr(E),
                                  C.c_void_p(self._stream())), "eval_energy")
+        return E
+
+    def eval_energy_noalloc(self, x, p=None, alpha=None, out=None):
+        """eval_energy through the allocation-free entry point (its partial
+        sums in the library's static device array)."""
+        E = out if out is not None else self.torch.zeros(1, dtype=self.torch.float64, device=self.device)
+        _check(lib().eval_energy_noalloc(self.handle, _ptr(x), _ptr(p) if p is not None else None,
+                                         _ptr(alpha) if alpha is not None else None, C.byref(self._cand), _ptr(E),
+                                         C.c_void_p(self._stream())), "eval_energy_noalloc")
         return E
 
     # -- lagged friction (App. A: IPC contact and friction energies) ----------

@@ -718,6 +718,64 @@ bf_status eval_energy(bf_scene* s, const double* x_d, const double* p_d, const d
   return he == hipSuccess ? BF_OK : fail_hip(he, "eval_energy");
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free energy evaluation: the per-block partial sums of
+// eval_energy live in this file-scope device array instead of the scene's
+// scratch.  Its address is taken once per device with hipGetSymbolAddress
+// (with that device current) and kept; host code never passes the array's
+// name itself to a kernel.  Every call on one device shares the array, which
+// keeps the last call's partials (each call overwrites every partial it
+// reads): calls that overlap on one device race.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[LINE_BLOCKS];
+namespace {
+constexpr int MAX_DEVICES = 64;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+std::mutex g_scratch_mu;
+
+bf_status scratch_of_device(double** out) {
+  int dev = -1;
+  hipError_t he = hipGetDevice(&dev);
+  if (he != hipSuccess) return fail_hip(he, "eval_energy_noalloc: hipGetDevice");
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(BF_E_DEVICE, "eval_energy_noalloc: device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    he = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (he != hipSuccess || !p) return fail_hip(he, "eval_energy_noalloc: hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return BF_OK;
+}
+}  // namespace
+
+extern "C" {
+
+bf_status eval_energy_noalloc(bf_scene* s, const double* x_d, const double* p_d, const double* alpha_d,
+                              const bf_pairs* cand, double* E_d, void* stream) {
+  if (!s || !x_d || !cand || !cand->i_d || !cand->j_d || !cand->type_d || !cand->count_d || !E_d || cand->cap < 1)
+    return fail(BF_E_ARG, "eval_energy_noalloc: null argument or capacity < 1");
+  if ((p_d == nullptr) != (alpha_d == nullptr))
+    return fail(BF_E_ARG, "eval_energy_noalloc: p_d and alpha_d are given together or not at all");
+  // one partial per work-group of the energy kernel (it strides over the list
+  // with at most LINE_BLOCKS work-groups), and the array holds LINE_BLOCKS
+  const long long parts = std::min<long long>((cand->cap + 255) / 256, LINE_BLOCKS);
+  if (parts > (long long)(sizeof(scratch) / sizeof(double)))
+    return fail(BF_E_CAPACITY, "eval_energy_noalloc: more partial sums than the static scratch holds");
+  double* part = nullptr;
+  bf_status r = scratch_of_device(&part);
+  if (r != BF_OK) return r;
+  hipStream_t st = (hipStream_t)stream;
+  s->last = st;
+  run_energy(dev_view(s), x_d, p_d, alpha_d, cand->i_d, cand->j_d, cand->type_d, (const long long*)cand->count_d,
+             cand->cap, part, E_d, st);
+  hipError_t he = hipGetLastError();
+  return he == hipSuccess ? BF_OK : fail_hip(he, "eval_energy_noalloc");
+}
+
 bf_status filter_pairs(bf_scene* s, const double* x_d, const bf_pairs* cand, bf_active* act, void* stream) {
   if (!s || !x_d || !cand || !act || !cand->count_d || !act->p.i_d || !act->p.j_d || !act->p.type_d ||
       !act->p.count_d || !act->code_d || !act->flags_d || !act->dist_d || !act->counters_d || act->p.cap < 1)
