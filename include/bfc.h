@@ -58,12 +58,25 @@ typedef enum {
   BF_E_CAPACITY = 4, /* a caller buffer is too small (synchronous checks) */
   BF_E_STATE = 5,    /* call order violated */
   BF_E_DEGENERATE = 6 /* a degenerate rest primitive: an edge whose two vertices have the same
-                         rest parameters, or a triangle of zero rest area (bf_scene_create) */
+                         rest parameters, or a triangle of zero rest area; under
+                         BF_REFDIST_EUCLID_REST also a rest pose where two primitives of one
+                         component that share no vertex touch (dbar^2 <= 1e-12 h^2)
+                         (bf_scene_create) */
 } bf_status;
 
 enum { BF_ROD = 0, BF_SHELL = 1 };
 enum { BF_FP64 = 0, BF_MIXED = 1 };
 enum { BF_FILTER_PAPER = 0, BF_FILTER_NONE = 1, BF_FILTER_CULL = 2 };
+/* What the reference distance dbar of Eq. 1 and Eq. 4 measures (Sec. 3.2):
+ * BF_REFDIST_PARAM (default): distance in rest-space parameters, arc length
+ * for rods and 2D rest coordinates for shells (Sec. 1 and Sec. 3.4: the
+ * filter analyses distances along polylines and triangulations);
+ * BF_REFDIST_EUCLID_REST: the literal alternative, the Euclidean distance
+ * between the two primitives at a rest pose (bf_mesh_desc.ref_pos_h).  The
+ * two differ where a polyline or sheet comes back near itself at rest: a
+ * rod loop's successive turns are far apart along the rod but close in
+ * space, and only the Euclidean reading filters them. */
+enum { BF_REFDIST_PARAM = 0, BF_REFDIST_EUCLID_REST = 1 };
 
 /* device status word bits */
 enum {
@@ -104,6 +117,7 @@ typedef struct {
                       most cull_radius elements apart are left out of contact, every other pair
                       takes (h, eta)) */
   int32_t cull_radius; /* BF_FILTER_CULL: radius in elements (the paper uses 11, and 5); >= 1 */
+  int32_t refdist;     /* BF_REFDIST_PARAM or BF_REFDIST_EUCLID_REST (above) */
 } bf_params;
 
 typedef struct {
@@ -114,6 +128,8 @@ typedef struct {
   const int32_t* edges_h; /* [E,2] vertex ids */
   const int32_t* tris_h;  /* [F,3] vertex ids (NULL for rods) */
   const double* ref_h;    /* rest parameters: rods [V] arc length; shells [V,2] rest 2D coords */
+  const double* ref_pos_h; /* [V,3] rest pose, read under BF_REFDIST_EUCLID_REST only (else may be
+                              NULL); copied at bf_scene_create */
 } bf_mesh_desc;
 
 /* Candidate or active pair list (structure of arrays, device memory).
@@ -162,10 +178,29 @@ typedef struct {
  * labels connected components and computes d_min per component (Sec. 3.2).
  * cand_cap / act_cap size the scene scratch used by the per-step calls
  * (narrow-phase staging, assembly incidence lists); they bound the candidate
- * and active capacities the scene accepts without bf_scene_reserve.
- * Synchronises the stream. */
+ * and active capacities the scene accepts without bf_scene_reserve
+ * (act_cap at most 2^28 pairs, BF_E_ARG beyond).  Synchronises the stream. */
 bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int64_t cand_cap,
                           int64_t act_cap, void* stream, bf_scene** out);
+
+/* Caller-owned scene memory.  bf_workspace_bytes writes to *bytes_h the
+ * size of the device workspace that holds everything a scene created with
+ * these arguments keeps (topology, rest data, broad-phase, narrow-phase and
+ * assembly workspaces for cand_cap candidates and act_cap active pairs); it
+ * touches no device.  bf_scene_create_ws creates the scene as
+ * bf_scene_create does, but carves all of that from ws_d (device memory of
+ * ws_bytes bytes, any alignment, owned by the caller, which must keep it
+ * until bf_scene_destroy and must not touch it meanwhile); the library never
+ * frees it.  Short-lived temporaries of the creation itself (component
+ * labelling, the rest-space candidate list) are still allocated and freed
+ * before it returns, and the optional core set (bf_core_mark) and lagged
+ * friction structure (friction_lag) allocate on first use.  BF_E_CAPACITY
+ * if ws_bytes is below the size bf_workspace_bytes gives.  Such a scene
+ * cannot grow: bf_scene_reserve beyond its capacities returns BF_E_STATE. */
+bf_status bf_workspace_bytes(const bf_mesh_desc* mesh, const bf_params* params, int64_t cand_cap,
+                             int64_t act_cap, int64_t* bytes_h);
+bf_status bf_scene_create_ws(const bf_mesh_desc* mesh, const bf_params* params, int64_t cand_cap,
+                             int64_t act_cap, void* ws_d, int64_t ws_bytes, void* stream, bf_scene** out);
 
 /* Grow the scene scratch to hold at least cand_cap candidates / act_cap
  * active pairs (allocates and synchronises the device; not for use inside
@@ -338,7 +373,7 @@ bf_status friction_assemble(bf_scene* s, const bf_active* act, const bf_local* l
                             bf_bsr* H, void* stream);
 
 /* ---- tuning ---------------------------------------------------------------
- * Threads per broad-phase query (2, 4 or 8; default 4): more threads split a
+ * Threads per broad-phase query (2, 4, 8 or 16; default 4): more threads split a
  * query's rows of grid cells finer (small scenes, few queries), fewer cost
  * less bookkeeping (large scenes).  bf_scene_tune times build_candidates with
  * each choice on the positions x_d (reps timed launches each, median) and
@@ -381,6 +416,61 @@ bf_status bf_batch_info(const bf_batch* b, int32_t* lanes, int32_t* lane_of_h);
 /* Waits for the batch's last launch, then frees it (the scenes stay). */
 bf_status bf_batch_destroy(bf_batch* b);
 
+/* ---- serving: requests for many registered scenes ---------------------
+ * A server keeps the registered scenes' host data (copied at start) and runs
+ * requests (a scene and its positions) with a worker thread of its own.
+ * Admission takes requests in arrival order; one whose scene is busy or
+ * does not fit the budget yet may be passed by later ones, at most
+ * max_bypass times, after which it blocks those behind it.  A scene that is
+ * not resident is created in one device block of its own (bf_workspace_bytes
+ * plus the buffers of its step, as bf_serve_info reports), after idle
+ * resident scenes are destroyed, least recently used first, to keep the
+ * resident total within budget_bytes.  At most one request per scene is on
+ * the device at a time; up to `slots` requests run at once, each on a
+ * stream of its own.  A request runs the whole path (build_candidates,
+ * filter_pairs, eval_barrier, assemble_grad_hess) and completes when its
+ * results are in host memory: energy, counters, the step's status word
+ * (read and cleared) and, if g_h was given, the gradient written to g_h.  No
+ * capacity is grown: an overflow shows in the status bits, with the counts
+ * holding the sizes required. */
+typedef struct bf_server bf_server;
+typedef struct {
+  int32_t n_scenes;
+  const bf_mesh_desc* meshes;  /* [n_scenes] */
+  const bf_params* params;     /* [n_scenes] */
+  const int64_t* cand_cap;     /* [n_scenes] capacities of each scene's step */
+  const int64_t* act_cap;      /* [n_scenes] */
+  const int64_t* bsr_cap;      /* [n_scenes] BSR blocks */
+  int64_t budget_bytes;        /* device memory for resident scenes (each alone must fit) */
+  int32_t slots;               /* requests on the device at once, 1..64 */
+  int32_t max_bypass;          /* >= 0 */
+  int32_t device;              /* HIP device of the server */
+} bf_serve_config;
+typedef struct {
+  int32_t done;      /* 1 once the request has completed (the other fields are then set) */
+  int32_t scene;
+  bf_status error;   /* BF_OK, or why the request could not run (bf_last_error is per thread) */
+  uint32_t status;   /* the step's status word (BF_S_* bits) */
+  double E;          /* total energy (+inf if a pair is infeasible) */
+  int64_t counts[5]; /* N_c, N_filt, N_act, N_infeasible, BSR blocks */
+  int64_t n_bp;      /* candidates of the broad phase */
+  double ms;         /* submit to completion, host clock */
+} bf_serve_result;
+/* Start a server (device memory is allocated as scenes become resident). */
+bf_status bf_serve_start(const bf_serve_config* cfg, bf_server** out);
+/* Queue a request: x_h [V,3] positions of the scene's vertices (copied
+ * before return); g_h [V,3] (host, may be NULL) receives the gradient and
+ * must stay valid until the request completes.  *ticket_h identifies it. */
+bf_status bf_serve_submit(bf_server* sv, int32_t scene, const double* x_h, double* g_h, int64_t* ticket_h);
+/* State of a request (wait != 0: block until it completes).  A completed
+ * request's ticket is released by the poll that reports it. */
+bf_status bf_serve_poll(bf_server* sv, int64_t ticket, int32_t wait, bf_serve_result* out);
+/* Resident scenes, device bytes they hold, and (footprint_h[n_scenes], may
+ * be NULL) each scene's device footprint when resident. */
+bf_status bf_serve_info(bf_server* sv, int32_t* resident_h, int64_t* used_bytes_h, int64_t* footprint_h);
+/* Finish every queued request, destroy the resident scenes, free all. */
+bf_status bf_serve_stop(bf_server* sv);
+
 /* Device status word (BF_S_* bits) accumulated since the last clear;
  * synchronises the stream the scene last used.  clear != 0 resets it. */
 bf_status bf_status_word(bf_scene* s, uint32_t* bits_h, int32_t clear);
@@ -398,10 +488,12 @@ bf_status bf_status_word(bf_scene* s, uint32_t* bits_h, int32_t clear);
  * bf_scene_stage_ms synchronises on those events and writes the duration of
  * each stage's latest call (ms; -1 where the stage has not run since timing
  * was switched on) to ms_h[BF_T_COUNT].  Setting timing allocates events. */
-/* Diagnostics: the number of candidates of the last filter_pairs whose
- * decisions neither FP64 nor double-double settled and that were decided in
- * exact arithmetic (synchronises). */
-bf_status bf_scene_deferred(bf_scene* s, int64_t* n_h);
+/* Diagnostics of the last filter_pairs (synchronises): n_band_h, the
+ * candidates with a value in FP64's relative band of 1e-9 around a threshold
+ * (decided again by the exact-in-FP64 check and double-double); n_exact_h,
+ * those of them that double-double left within 1e-20 of the threshold and
+ * that were decided in exact arithmetic.  Either pointer may be NULL. */
+bf_status bf_scene_deferred(bf_scene* s, int64_t* n_band_h, int64_t* n_exact_h);
 
 enum { BF_T_BROAD = 0, BF_T_NARROW = 1, BF_T_COMPACT = 2, BF_T_EVAL = 3, BF_T_ASM_STRUCT = 4,
        BF_T_ASM_VALUES = 5, BF_T_COUNT = 6 };

@@ -53,7 +53,8 @@ class _Scene(C.Structure):
                 ("edges", C.c_void_p), ("tris", C.c_void_p), ("ref", C.c_void_p),
                 ("h", C.c_double), ("eta", C.c_double), ("kappa", C.c_double),
                 ("filter_mode", C.c_int32), ("n_core", C.c_int64), ("core_ptype", C.c_void_p),
-                ("core_i", C.c_void_p), ("core_j", C.c_void_p), ("cull_radius", C.c_int32)]
+                ("core_i", C.c_void_p), ("core_j", C.c_void_p), ("cull_radius", C.c_int32),
+                ("refdist", C.c_int32), ("xrest", C.c_void_p)]
 
 
 _lib = None
@@ -114,12 +115,18 @@ def _scene_struct(scene, filter_mode=0, eta=None, kappa=None, core=None, cull_ra
         cp, ci, cj = (np.ascontiguousarray(a, np.int32) for a in core)
         keep += [cp, ci, cj]
         n_core = len(cp)
+    refdist = int(getattr(scene, "refdist", 0))
+    xrest = None
+    if refdist == 1:
+        xrest = np.ascontiguousarray(scene.xrest, np.float64)
+        assert xrest.shape == (scene.n_verts, 3), "the Euclidean reading needs the rest pose [V,3]"
+        keep.append(xrest)
     s = _Scene(0 if scene.kind == "rod" else 1, scene.n_verts, scene.n_edges,
                scene.n_tris if scene.kind == "shell" else 0,
                _p(edges), _p(tris) if tris.size else None, _p(ref),
                float(scene.h), float(scene.eta if eta is None else eta),
                float(scene.kappa if kappa is None else kappa), int(filter_mode), n_core,
-               _p(cp), _p(ci), _p(cj), int(cull_radius))
+               _p(cp), _p(ci), _p(cj), int(cull_radius), refdist, _p(xrest))
     return s, keep
 
 

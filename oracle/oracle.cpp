@@ -574,6 +574,10 @@ struct Mesh {
   const double* ref;
   double h, eta, kappa;
   int filter_mode;  // 0 paper (Eq. 4), 1 none (plain offset barrier everywhere), 2 cull (rods)
+  // reference distance: 0 parametric (rest-space parameters), 1 Euclidean
+  // distance between the primitives at the rest pose xrest [V,3]
+  int refdist;
+  const double* xrest;
   int cull_radius;  // mode 2: edges of one polyline at most this many elements apart are ignored
   std::vector<int> edge_pos;   // mode 2: index of each edge along its polyline
   std::vector<int> loop_len;   // mode 2: edge count of the edge's polyline if it is closed, else 0
@@ -644,8 +648,10 @@ bool ref_dist(const Mesh& m, int ptype, int i, int j, S* q, double* dbar_rod) {
 // Is the pair in the stencil set with reference distance below h (filtered)?
 // Shells: decided on dbar^2 in double outside a 1e-9 relative band around
 // h^2 (and away from 0), in binary128 inside it, exactly within 1e-20 of h^2.
+bool is_filtered_euclid(const Mesh& m, int ptype, int i, int j);
 bool is_filtered(const Mesh& m, int ptype, int i, int j) {
   if (m.filter_mode != 0) return false;
+  if (m.refdist == 1) return is_filtered_euclid(m, ptype, i, j);
   double g;
   if (m.kind == 0) {
     double q;
@@ -846,6 +852,109 @@ void gather(const Mesh& m, const double* x, int ptype, int i, int j, int* verts,
   }
   for (int k = 0; k < 4; ++k)
     for (int c = 0; c < 3; ++c) X[3 * k + c] = x[3 * verts[k] + c];
+}
+
+// The literal reading of the reference distance (Eq. 1 with dbar measured on
+// the rest pose): dbar = the Euclidean distance between the two primitives at
+// the rest positions xrest, the same distance function as d(x).  A stencil
+// pair (same component, not incident) is filtered iff 0 < dbar < h; the
+// comparison with h is the exact decision used for d(x) < h, and dbar > 0 is
+// read on the double value (rest poses whose non-incident primitives touch
+// are outside the model).
+bool is_filtered_euclid(const Mesh& m, int ptype, int i, int j) {
+  const int ca = ptype == 0 ? m.comp[i] : m.comp[m.edges[2 * i]];
+  const int cb = ptype == 0 ? m.comp[m.tris[3 * j]] : m.comp[m.edges[2 * j]];
+  if (ca != cb) return false;
+  int verts[4];
+  double X[12];
+  gather(m, m.xrest, ptype, i, j, verts, X);
+  const Dist ds = classify(ptype, X);
+  if (!(ds.D > 0.0)) return false;
+  return decide(ds.code, X, ds.D, m.h * m.h, sq(m.h), true, nullptr);
+}
+
+// d_min per component under the Euclidean reading: the binary128 minimum of
+// dbar^2 over the filtered stencil pairs (0 < dbar < h), rounded once to
+// double, found by a sweep over the rest-pose bounding boxes (boxes h or more
+// apart on some axis hold no pair with dbar < h).
+void compute_dmin_euclid(Mesh& m, int nc) {
+  m.dmin2.assign(nc, std::numeric_limits<double>::infinity());
+  m.dmin.assign(nc, std::numeric_limits<double>::infinity());
+  m.thr2.assign(nc, (f128)INFINITY);
+  struct Box { double lo[3], hi[3]; int id; };
+  double rmax = 0.0;
+  for (int64_t k = 0; k < 3 * m.nv; ++k) rmax = std::max(rmax, std::fabs(m.xrest[k]));
+  const double lim = m.h * (1.0 + 1e-12) + 1e-14 * rmax;
+  auto make_box = [&](const int32_t* vs, int n, int id) {
+    Box b;
+    for (int a = 0; a < 3; ++a) { b.lo[a] = INFINITY; b.hi[a] = -INFINITY; }
+    b.id = id;
+    for (int k = 0; k < n; ++k)
+      for (int a = 0; a < 3; ++a) {
+        b.lo[a] = std::min(b.lo[a], m.xrest[3 * vs[k] + a]);
+        b.hi[a] = std::max(b.hi[a], m.xrest[3 * vs[k] + a]);
+      }
+    return b;
+  };
+  auto near = [&](const Box& a, const Box& b) {
+    for (int k = 0; k < 3; ++k)
+      if (!(std::max(b.lo[k] - a.hi[k], a.lo[k] - b.hi[k]) < lim)) return false;
+    return true;
+  };
+  auto by_lo = [](const Box& a, const Box& b) { return a.lo[0] < b.lo[0] || (a.lo[0] == b.lo[0] && a.id < b.id); };
+  int T = omp_get_max_threads();
+  std::vector<std::vector<f128>> best(T, std::vector<f128>(nc, (f128)INFINITY));
+  auto consider = [&](int ptype, int i, int j) {
+    if (incident(m, ptype, i, j) || !is_filtered_euclid(m, ptype, i, j)) return;
+    int verts[4];
+    double X[12];
+    gather(m, m.xrest, ptype, i, j, verts, X);
+    const Dist ds = classify(ptype, X);
+    f128 Xq[12];
+    for (int k = 0; k < 12; ++k) Xq[k] = (f128)X[k];
+    const f128 q = D_case<f128>(ds.code, Xq);
+    const int c = ptype == 0 ? m.comp[i] : m.comp[m.edges[2 * i]];
+    const int t = omp_get_thread_num();
+    if (q < best[t][c]) best[t][c] = q;
+  };
+  std::vector<Box> eb(m.ne);
+  for (int64_t e = 0; e < m.ne; ++e) eb[e] = make_box(m.edges + 2 * e, 2, (int)e);
+  std::sort(eb.begin(), eb.end(), by_lo);
+  #pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t a = 0; a < (int64_t)eb.size(); ++a)
+    for (size_t b = a + 1; b < eb.size(); ++b) {
+      if (eb[b].lo[0] - eb[a].hi[0] >= lim) break;
+      if (!near(eb[a], eb[b])) continue;
+      consider(1, std::min(eb[a].id, eb[b].id), std::max(eb[a].id, eb[b].id));
+    }
+  if (m.kind == 1) {
+    std::vector<Box> tb(m.nt);
+    for (int64_t t = 0; t < m.nt; ++t) tb[t] = make_box(m.tris + 3 * t, 3, (int)t);
+    std::sort(tb.begin(), tb.end(), by_lo);
+    double wmax = 0.0;
+    for (const Box& b : tb) wmax = std::max(wmax, b.hi[0] - b.lo[0]);
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t v = 0; v < m.nv; ++v) {
+      int32_t vv = (int32_t)v;
+      Box P = make_box(&vv, 1, (int)v);
+      size_t l = std::lower_bound(tb.begin(), tb.end(), P.lo[0] - lim - wmax,
+                                  [](const Box& b, double val) { return b.lo[0] < val; }) - tb.begin();
+      for (; l < tb.size(); ++l) {
+        if (tb[l].lo[0] - P.hi[0] >= lim) break;
+        if (!near(P, tb[l])) continue;
+        consider(0, (int)v, tb[l].id);
+      }
+    }
+  }
+  for (int c = 0; c < nc; ++c) {
+    f128 q = (f128)INFINITY;
+    for (int t = 0; t < T; ++t) q = std::min(q, best[t][c]);
+    if (q < (f128)INFINITY) {
+      m.dmin2[c] = (double)q;
+      m.dmin[c] = std::sqrt(m.dmin2[c]);
+      m.thr2[c] = (f128)m.dmin2[c];
+    }
+  }
 }
 
 // Evaluate one pair of the universe; returns false if d >= h (not a contact
@@ -1070,6 +1179,8 @@ typedef struct {
   const int32_t* core_i;
   const int32_t* core_j;
   int32_t cull_radius;  // filter_mode 2 (rods): radius in elements
+  int32_t refdist;      // 0 parametric reference distance, 1 Euclidean at the rest pose
+  const double* xrest;  // [V,3] rest pose (refdist 1)
 } orc_scene;
 
 static Mesh make_mesh(const orc_scene* s) {
@@ -1077,9 +1188,12 @@ static Mesh make_mesh(const orc_scene* s) {
   m.kind = s->kind; m.nv = s->nv; m.ne = s->ne; m.nt = s->kind == 1 ? s->nt : 0;
   m.edges = s->edges; m.tris = s->tris; m.ref = s->ref;
   m.h = s->h; m.eta = s->eta; m.kappa = s->kappa; m.filter_mode = s->filter_mode;
+  m.refdist = s->refdist;
+  m.xrest = s->xrest;
   m.comp.resize(m.nv);
   int nc = components(m.nv, m.ne, m.edges, m.tris, m.nt, m.comp.data());
-  compute_dmin(m, nc);
+  if (m.refdist == 1) compute_dmin_euclid(m, nc);
+  else compute_dmin(m, nc);
   for (int64_t k = 0; k < s->n_core; ++k) m.core.insert(pair_key(s->core_ptype[k], s->core_i[k], s->core_j[k]));
   m.cull_radius = s->cull_radius;
   if (m.filter_mode == 2) order_polylines(m);

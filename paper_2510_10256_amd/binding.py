@@ -15,23 +15,26 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libbfc.so")
-SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("bfc_kernels.hip", "bfc_api.hip")]
+SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("bfc_kernels.hip", "bfc_api.hip", "bfc_serve.hip")]
 
 BF_OK = 0
 BF_ROD, BF_SHELL = 0, 1
 BF_FP64, BF_MIXED = 0, 1
 BF_FILTER_PAPER, BF_FILTER_NONE, BF_FILTER_CULL = 0, 1, 2
+BF_REFDIST_PARAM, BF_REFDIST_EUCLID_REST = 0, 1
 BF_S_CAND_OVERFLOW, BF_S_ACT_OVERFLOW, BF_S_INFEASIBLE = 1, 2, 4
 BF_S_BSR_OVERFLOW, BF_S_CORE_OVERFLOW = 8, 16
 BF_S_EIG_NOCONV, BF_S_SCAN_SLOW, BF_S_EXACT_LIMIT = 32, 64, 128
 BF_F_FILTERED, BF_F_INFEASIBLE, BF_F_CORE = 1, 4, 8
 
-EXPORTED = ["bf_scene_create", "bf_scene_reserve", "bf_scene_destroy", "bf_scene_info", "build_candidates",
-            "filter_pairs", "eval_barrier", "assemble_grad_hess", "bf_scene_set_pq", "bf_scene_tune",
-            "bf_batch_create", "bf_batch_step", "bf_batch_info", "bf_batch_destroy", "build_candidates_swept",
-            "max_step_accd", "eval_energy", "bf_core_mark", "bf_core_live", "bf_core_clear", "friction_lag",
-            "friction_eval", "friction_assemble", "bf_status_word", "bf_set_scan_poll_limit", "bf_scene_set_timing",
-            "bf_scene_stage_ms", "eval_energy_noalloc", "bf_scene_deferred", "bf_last_error"]
+EXPORTED = ["bf_scene_create", "bf_workspace_bytes", "bf_scene_create_ws", "bf_scene_reserve", "bf_scene_destroy",
+            "bf_scene_info", "build_candidates", "filter_pairs", "eval_barrier", "assemble_grad_hess",
+            "bf_scene_set_pq", "bf_scene_tune", "bf_batch_create", "bf_batch_step", "bf_batch_info",
+            "bf_batch_destroy", "build_candidates_swept", "max_step_accd", "eval_energy", "bf_core_mark",
+            "bf_core_live", "bf_core_clear", "friction_lag", "friction_eval", "friction_assemble", "bf_status_word",
+            "bf_set_scan_poll_limit", "bf_scene_set_timing", "bf_scene_stage_ms", "eval_energy_noalloc",
+            "bf_scene_deferred", "bf_serve_start", "bf_serve_submit", "bf_serve_poll", "bf_serve_info",
+            "bf_serve_stop", "bf_last_error"]
 
 
 def build(verbose: bool = False) -> str:
@@ -70,12 +73,23 @@ def unpack_hessians(Hp):
 
 class Params(C.Structure):
     _fields_ = [("h", C.c_double), ("eta", C.c_double), ("kappa", C.c_double),
-                ("prec", C.c_int32), ("filter", C.c_int32), ("cull_radius", C.c_int32)]
+                ("prec", C.c_int32), ("filter", C.c_int32), ("cull_radius", C.c_int32), ("refdist", C.c_int32)]
 
 
 class MeshDesc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n_verts", C.c_int64), ("n_edges", C.c_int64), ("n_tris", C.c_int64),
-                ("edges_h", C.c_void_p), ("tris_h", C.c_void_p), ("ref_h", C.c_void_p)]
+                ("edges_h", C.c_void_p), ("tris_h", C.c_void_p), ("ref_h", C.c_void_p), ("ref_pos_h", C.c_void_p)]
+
+
+class ServeConfig(C.Structure):
+    _fields_ = [("n_scenes", C.c_int32), ("meshes", C.c_void_p), ("params", C.c_void_p), ("cand_cap", C.c_void_p),
+                ("act_cap", C.c_void_p), ("bsr_cap", C.c_void_p), ("budget_bytes", C.c_int64), ("slots", C.c_int32),
+                ("max_bypass", C.c_int32), ("device", C.c_int32)]
+
+
+class ServeResult(C.Structure):
+    _fields_ = [("done", C.c_int32), ("scene", C.c_int32), ("error", C.c_int32), ("status", C.c_uint32),
+                ("E", C.c_double), ("counts", C.c_int64 * 5), ("n_bp", C.c_int64), ("ms", C.c_double)]
 
 
 class Pairs(C.Structure):
@@ -119,6 +133,15 @@ def lib():
         P = C.c_void_p
         L.bf_scene_create.argtypes = [C.POINTER(MeshDesc), C.POINTER(Params), C.c_int64, C.c_int64, P,
                                       C.POINTER(P)]
+        L.bf_workspace_bytes.argtypes = [C.POINTER(MeshDesc), C.POINTER(Params), C.c_int64, C.c_int64,
+                                         C.POINTER(C.c_int64)]
+        L.bf_scene_create_ws.argtypes = [C.POINTER(MeshDesc), C.POINTER(Params), C.c_int64, C.c_int64, P,
+                                         C.c_int64, P, C.POINTER(P)]
+        L.bf_serve_start.argtypes = [C.POINTER(ServeConfig), C.POINTER(P)]
+        L.bf_serve_submit.argtypes = [P, C.c_int32, P, P, C.POINTER(C.c_int64)]
+        L.bf_serve_poll.argtypes = [P, C.c_int64, C.c_int32, C.POINTER(ServeResult)]
+        L.bf_serve_info.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_int64), P]
+        L.bf_serve_stop.argtypes = [P]
         L.bf_scene_reserve.argtypes = [P, C.c_int64, C.c_int64]
         L.bf_scene_destroy.argtypes = [P]
         L.bf_scene_info.argtypes = [P, P, P, P, P, C.c_int32]
@@ -147,7 +170,7 @@ def lib():
         L.bf_set_scan_poll_limit.argtypes = [C.c_int32]
         L.bf_scene_set_timing.argtypes = [P, C.c_int32]
         L.bf_scene_stage_ms.argtypes = [P, P]
-        L.bf_scene_deferred.argtypes = [P, C.POINTER(C.c_int64)]
+        L.bf_scene_deferred.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.bf_last_error.restype = C.c_char_p
         for name in EXPORTED[:-1]:
             getattr(L, name).restype = C.c_int
@@ -174,7 +197,7 @@ class ContactScene:
     """
 
     def __init__(self, scene, prec=BF_FP64, filter_mode=BF_FILTER_PAPER, kappa=None, eta=None, cull_radius=11,
-                 cand_cap=None, act_cap=None, bsr_cap=None, device="cuda"):
+                 cand_cap=None, act_cap=None, bsr_cap=None, device="cuda", own_workspace=False):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -191,13 +214,30 @@ class ContactScene:
         self._edges = np.ascontiguousarray(scene.edges, np.int32)
         self._tris = np.ascontiguousarray(scene.tris, np.int32) if self.nt else None
         self._ref = np.ascontiguousarray(scene.ref, np.float64)
+        # reference distance: the scene's reading (rest parameters, or the
+        # Euclidean distance at its rest pose xrest)
+        self.refdist = int(getattr(scene, "refdist", BF_REFDIST_PARAM))
+        self._xrest = (np.ascontiguousarray(scene.xrest, np.float64) if self.refdist == BF_REFDIST_EUCLID_REST
+                       else None)
         desc = MeshDesc(self.kind, self.nv, self.ne, self.nt, self._edges.ctypes.data,
-                        self._tris.ctypes.data if self.nt else None, self._ref.ctypes.data)
-        prm = Params(self.h, self.eta, self.kappa, int(prec), int(filter_mode), int(cull_radius))
+                        self._tris.ctypes.data if self.nt else None, self._ref.ctypes.data,
+                        self._xrest.ctypes.data if self._xrest is not None else None)
+        prm = Params(self.h, self.eta, self.kappa, int(prec), int(filter_mode), int(cull_radius), self.refdist)
         self.prec, self.filter_mode = int(prec), int(filter_mode)
         h = C.c_void_p()
-        _check(lib().bf_scene_create(C.byref(desc), C.byref(prm), self.cand_cap, self.act_cap,
-                                     C.c_void_p(self._stream()), C.byref(h)), "bf_scene_create")
+        self.workspace = None
+        if own_workspace:
+            # the scene's memory in a tensor of ours (bf_workspace_bytes / bf_scene_create_ws)
+            nb = C.c_int64(0)
+            _check(lib().bf_workspace_bytes(C.byref(desc), C.byref(prm), self.cand_cap, self.act_cap,
+                                            C.byref(nb)), "bf_workspace_bytes")
+            self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+            _check(lib().bf_scene_create_ws(C.byref(desc), C.byref(prm), self.cand_cap, self.act_cap,
+                                            self.workspace.data_ptr(), int(nb.value), C.c_void_p(self._stream()),
+                                            C.byref(h)), "bf_scene_create_ws")
+        else:
+            _check(lib().bf_scene_create(C.byref(desc), C.byref(prm), self.cand_cap, self.act_cap,
+                                         C.c_void_p(self._stream()), C.byref(h)), "bf_scene_create")
         self.handle = h
         self.pq = 4
         self._gen = 0       # filter_pairs calls so far (the lagged friction list is tied to one)
@@ -395,12 +435,12 @@ class ContactScene:
         _check(lib().bf_core_clear(self.handle), "bf_core_clear")
 
     def set_pq(self, pq):
-        """Threads per broad-phase query (2, 4 or 8)."""
+        """Threads per broad-phase query (2, 4, 8 or 16)."""
         _check(lib().bf_scene_set_pq(self.handle, int(pq)), "bf_scene_set_pq")
         self.pq = int(pq)
 
     def tune(self, x, reps=5):
-        """Time build_candidates with 2, 4 and 8 threads per query on x and
+        """Time build_candidates with 2, 4, 8 and 16 threads per query on x and
         keep the fastest (synchronises)."""
         x = self._as_x(x)
         pq = C.c_int32(0)
@@ -428,10 +468,11 @@ class ContactScene:
         return {k: float(v) for k, v in zip(self.STAGES, ms)}
 
     def deferred(self):
-        """Candidates of the last filter_pairs decided in exact arithmetic."""
-        n = C.c_int64(0)
-        _check(lib().bf_scene_deferred(self.handle, C.byref(n)), "bf_scene_deferred")
-        return int(n.value)
+        """(candidates of the last filter_pairs with a value in FP64's band
+        around a threshold, those of them decided in exact arithmetic)."""
+        nb, ne = C.c_int64(0), C.c_int64(0)
+        _check(lib().bf_scene_deferred(self.handle, C.byref(nb), C.byref(ne)), "bf_scene_deferred")
+        return int(nb.value), int(ne.value)
 
     def status(self, clear=True):
         v = C.c_uint32(0)
@@ -551,6 +592,84 @@ class Batch:
     def close(self):
         if getattr(self, "handle", None):
             lib().bf_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class NativeServer:
+    """The library's serving loop (bf_serve_*): scenes registered at start,
+    requests submitted with host positions, results polled by ticket."""
+
+    def __init__(self, scenes, caps, budget_bytes, slots=4, max_bypass=8, prec=BF_FP64, device=0):
+        n = len(scenes)
+        self._keep = []
+        descs = (MeshDesc * n)()
+        prms = (Params * n)()
+        for k, sc in enumerate(scenes):
+            kind = BF_ROD if sc.kind == "rod" else BF_SHELL
+            edges = np.ascontiguousarray(sc.edges, np.int32)
+            tris = np.ascontiguousarray(sc.tris, np.int32) if kind == BF_SHELL else None
+            ref = np.ascontiguousarray(sc.ref, np.float64)
+            refdist = int(getattr(sc, "refdist", BF_REFDIST_PARAM))
+            xr = np.ascontiguousarray(sc.xrest, np.float64) if refdist == BF_REFDIST_EUCLID_REST else None
+            self._keep += [edges, tris, ref, xr]
+            descs[k] = MeshDesc(kind, sc.n_verts, sc.n_edges, sc.n_tris if kind == BF_SHELL else 0,
+                                edges.ctypes.data, tris.ctypes.data if tris is not None else None, ref.ctypes.data,
+                                xr.ctypes.data if xr is not None else None)
+            prms[k] = Params(float(sc.h), float(sc.eta), float(sc.kappa), int(prec), BF_FILTER_PAPER, 11, refdist)
+        cc = np.ascontiguousarray([c[0] for c in caps], np.int64)
+        ac = np.ascontiguousarray([c[1] for c in caps], np.int64)
+        bc = np.ascontiguousarray([c[2] for c in caps], np.int64)
+        self._keep += [descs, prms, cc, ac, bc]
+        cfg = ServeConfig(n, C.addressof(descs), C.addressof(prms), cc.ctypes.data, ac.ctypes.data, bc.ctypes.data,
+                          int(budget_bytes), int(slots), int(max_bypass), int(device))
+        h = C.c_void_p()
+        _check(lib().bf_serve_start(C.byref(cfg), C.byref(h)), "bf_serve_start")
+        self.handle = h
+        self.nv = [sc.n_verts for sc in scenes]
+        self._grads = {}
+
+    def submit(self, sid, x, grad=False):
+        """Queue a request; returns its ticket.  With grad, poll returns the
+        gradient as well."""
+        x = np.ascontiguousarray(x, np.float64)
+        assert x.shape == (self.nv[sid], 3)
+        g = np.zeros((self.nv[sid], 3)) if grad else None
+        t = C.c_int64(0)
+        _check(lib().bf_serve_submit(self.handle, int(sid), x.ctypes.data, g.ctypes.data if grad else None,
+                                     C.byref(t)), "bf_serve_submit")
+        if grad:
+            self._grads[t.value] = g
+        return int(t.value)
+
+    def poll(self, ticket, wait=True):
+        """None while pending; else a dict of the request's results."""
+        r = ServeResult()
+        _check(lib().bf_serve_poll(self.handle, int(ticket), int(bool(wait)), C.byref(r)), "bf_serve_poll")
+        if not r.done:
+            return None
+        out = dict(scene=r.scene, error=r.error, status=r.status, E=r.E, n_bp=r.n_bp, ms=r.ms,
+                   counts=dict(n_c=r.counts[0], n_filt=r.counts[1], n_act=r.counts[2], n_infeasible=r.counts[3],
+                               nnzb=r.counts[4]))
+        g = self._grads.pop(ticket, None)
+        if g is not None:
+            out["g"] = g
+        return out
+
+    def info(self):
+        n, used = C.c_int32(0), C.c_int64(0)
+        fp = np.zeros(len(self.nv), np.int64)
+        _check(lib().bf_serve_info(self.handle, C.byref(n), C.byref(used), fp.ctypes.data), "bf_serve_info")
+        return dict(resident=int(n.value), used=int(used.value), footprint=fp)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().bf_serve_stop(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -19,6 +19,7 @@ struct bf_scene {
   int* d_edges = nullptr;
   int* d_tris = nullptr;
   double* d_ref = nullptr;
+  double* d_xrest = nullptr;  // [V,3] rest pose under BF_REFDIST_EUCLID_REST
   int* d_comp = nullptr;
   double* d_dmin = nullptr;
   double* d_thr2 = nullptr;
@@ -47,6 +48,7 @@ struct bf_scene {
   std::vector<void*> asm_allocs;    // assembly scratch (regrown by reserve)
   std::vector<void*> stage_allocs;  // narrow-phase staging (regrown by reserve)
   int pq = 4;                       // threads per broad-phase query (tunable)
+  bool in_ws = false;                // scene memory carved from the caller's workspace (bf_scene_create_ws)
   hipStream_t last = nullptr;
   // eval_barrier runs the structural part of the assembly on `side`, beside
   // the evaluation kernel; assemble_grad_hess then only adds the values
@@ -79,10 +81,31 @@ bf_status fail_hip(hipError_t e, const char* where) {
 // scene never waits for work of other scenes on other streams.
 thread_local hipStream_t g_alloc_stream = nullptr;
 
+// A caller's workspace (bf_scene_create_ws): while g_arena is set, dalloc
+// carves 256-byte aligned pieces from it instead of allocating, and records
+// nothing to free; with a null base it only adds up the bytes
+// (bf_workspace_bytes).
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, off = 0;
+};
+thread_local Arena* g_arena = nullptr;
+inline bool sizing_only() { return g_arena && !g_arena->base; }
+
 template <class T> T* dalloc(std::vector<void*>& list, size_t n, hipError_t* err) {
   void* p = nullptr;
   size_t bytes = n * sizeof(T);
   if (bytes == 0) bytes = sizeof(T);
+  if (g_arena) {
+    const size_t o = (g_arena->off + 255) & ~(size_t)255;
+    g_arena->off = o + bytes;
+    if (!g_arena->base || *err != hipSuccess) return nullptr;
+    if (g_arena->off > g_arena->cap) {
+      *err = hipErrorOutOfMemory;
+      return nullptr;
+    }
+    return (T*)(g_arena->base + o);
+  }
   hipError_t e = hipMallocAsync(&p, bytes, g_alloc_stream);
   if (e != hipSuccess) {
     *err = e;
@@ -107,6 +130,8 @@ SceneDev dev_view(const bf_scene* s) {
   S.edges = s->d_edges;
   S.tris = s->d_tris;
   S.ref = s->d_ref;
+  S.xrest = s->d_xrest;
+  S.refdist = s->prm.refdist;
   S.comp = s->d_comp;
   S.dmin = s->d_dmin;
   S.thr2 = s->d_thr2;
@@ -135,6 +160,7 @@ void free_list(std::vector<void*>& l, hipStream_t st = g_alloc_stream) {
 // cleared, as the structure pass expects them).
 bf_status alloc_asm_ws(const bf_scene* s, long long act_cap, std::vector<void*>& allocs, AsmWs* out,
                        const char* who) {
+  if (act_cap > (1LL << 28)) return fail(BF_E_ARG, "active capacity above 2^28 pairs");  // assembly item field
   free_list(allocs);
   hipError_t e = hipSuccess;
   AsmWs A{};
@@ -148,7 +174,10 @@ bf_status alloc_asm_ws(const bf_scene* s, long long act_cap, std::vector<void*>&
   A.big = dalloc<int>(allocs, s->nv + 1, &e);
   A.epart = dalloc<double>(allocs, (act_cap + 63) / 64 + 1, &e);
   A.scan_tmp = dalloc<int>(allocs, scan_tmp_ints(s->nv + 1), &e);
-  if (e != hipSuccess) return fail(BF_E_NOMEM, who);
+  if (e != hipSuccess)
+    return g_arena ? fail(BF_E_CAPACITY, "bf_scene_create_ws: workspace smaller than bf_workspace_bytes")
+                   : fail(BF_E_NOMEM, who);
+  if (sizing_only()) return BF_OK;
   if (hipMemsetAsync(A.inc_cnt, 0, sizeof(int) * (s->nv + 1), g_alloc_stream) != hipSuccess ||
       hipMemsetAsync(A.scan_tmp, 0, sizeof(int) * SCAN_LB_STATE, g_alloc_stream) != hipSuccess ||
       hipMemsetAsync(A.rowcnt, 0, sizeof(int) * (s->nv + 1), g_alloc_stream) != hipSuccess ||
@@ -216,9 +245,15 @@ bf_status alloc_stage(bf_scene* s, long long cand_cap) {
   W.kofs = dalloc<int>(s->stage_allocs, NW_KINDS * G + 1, &e);
   W.ccnt = dalloc<int>(s->stage_allocs, 3 * G, &e);
   W.dfr = dalloc<long long>(s->stage_allocs, G * NW_TILE, &e);
+  W.dfr2 = dalloc<int>(s->stage_allocs, G * NW_TILE, &e);
+  W.n2 = dalloc<int>(s->stage_allocs, 1, &e);
   W.xcnt = dalloc<int>(s->stage_allocs, 5LL * XP_BLOCKS, &e);
   W.scan_tmp = dalloc<int>(s->stage_allocs, scan_tmp_ints(NW_KINDS * G + 1), &e);
-  if (e != hipSuccess) return fail(BF_E_NOMEM, "bf_scene_reserve: device allocation failed");
+  if (e != hipSuccess)
+    return g_arena ? fail(BF_E_CAPACITY, "bf_scene_create_ws: workspace smaller than bf_workspace_bytes")
+                   : fail(BF_E_NOMEM, "bf_scene_reserve: device allocation failed");
+  W.cap = G * NW_TILE;
+  if (sizing_only()) return BF_OK;
   if (hipMemsetAsync(W.scan_tmp, 0, sizeof(int) * SCAN_LB_STATE, g_alloc_stream) != hipSuccess ||
       hipStreamSynchronize(g_alloc_stream) != hipSuccess)
     return fail(BF_E_DEVICE, "bf_scene_reserve: clearing the scan state failed");
@@ -269,6 +304,69 @@ struct StageTimer {
 
 }  // namespace
 
+// A scene that failed during creation: its memory back, in stream order.
+void discard_scene(bf_scene* s) {
+  free_list(s->asm_allocs);
+  free_list(s->stage_allocs);
+  free_list(s->allocs);
+  delete s;
+}
+
+// Every buffer the scene keeps: topology, rest data, broad-phase and
+// narrow-phase workspaces, assembly workspace, per-component thresholds
+// (sized by the vertex count, a bound on the components) and the culling
+// tables.  With g_arena set, carved from the caller's workspace (or only
+// counted, bf_workspace_bytes).
+bf_status alloc_persistent(bf_scene* s, long long cand_cap, long long act_cap) {
+  const int nv = s->nv, ne = s->ne, nt = s->nt;
+  hipError_t e = hipSuccess;
+  const int nref = s->kind == BF_ROD ? nv : 2 * nv;
+  s->d_edges = dalloc<int>(s->allocs, 2LL * ne, &e);
+  s->d_tris = dalloc<int>(s->allocs, std::max(3LL * nt, 3LL), &e);
+  s->d_ref = dalloc<double>(s->allocs, nref, &e);
+  if (s->prm.refdist == BF_REFDIST_EUCLID_REST) s->d_xrest = dalloc<double>(s->allocs, 3LL * nv, &e);
+  s->d_comp = dalloc<int>(s->allocs, nv, &e);
+  s->d_status = dalloc<unsigned>(s->allocs, 4, &e);
+  s->d_line = dalloc<double>(s->allocs, LINE_BLOCKS, &e);
+  s->d_dmin = dalloc<double>(s->allocs, nv, &e);
+  s->d_thr2 = dalloc<double>(s->allocs, 2LL * nv, &e);
+  if (s->prm.filter == BF_FILTER_CULL) {
+    s->d_eidx = dalloc<int>(s->allocs, ne, &e);
+    s->d_eloop = dalloc<int>(s->allocs, ne, &e);
+  }
+  const int np = ne + nt + (s->kind == BF_SHELL ? nv : 0);
+  BroadWs& W = s->bw;
+  W.max_cells = (int)std::min<long long>(std::max<long long>(4096, 2LL * np), 1LL << 26);
+  const long long nscan = 2LL * W.max_cells + 1;
+  const long long nq = (long long)(s->kind == BF_SHELL ? nv + ne : ne) * PQ_MAX + 1;
+  W.box = dalloc<Box>(s->allocs, np, &e);
+  W.cell_of = dalloc<int>(s->allocs, ne + nt, &e);
+  W.part = dalloc<float>(s->allocs, 8LL * BOUNDS_BLOCKS, &e);
+  W.done = dalloc<unsigned>(s->allocs, 1, &e);
+  W.grid = dalloc<Grid>(s->allocs, 1, &e);
+  W.cell_cnt = dalloc<int>(s->allocs, nscan, &e);
+  W.cell_start = dalloc<int>(s->allocs, nscan, &e);
+  W.sorted_id = dalloc<int>(s->allocs, ne + nt, &e);
+  W.sorted_box = dalloc<Box>(s->allocs, ne + nt, &e);
+  W.sorted_vid = dalloc<int4>(s->allocs, ne + nt, &e);
+  W.placed_id = dalloc<int>(s->allocs, ne + nt, &e);
+  W.placed_box = dalloc<Box>(s->allocs, ne + nt, &e);
+  W.pair_cnt = dalloc<int>(s->allocs, nq, &e);
+  W.pair_bsum = dalloc<int>(s->allocs, nq / 256 + 2, &e);
+  W.pair_bofs = dalloc<int>(s->allocs, nq / 256 + 2, &e);
+  W.pair_bseg = dalloc<long long>(s->allocs, nq / 256 + 2, &e);
+  W.seg_count = dalloc<unsigned long long>(s->allocs, 1, &e);
+  W.scan_tmp = dalloc<int>(s->allocs, std::max(std::max(scan_tmp_ints(nscan), scan_tmp_ints(nv + 1)), scan_tmp_ints(nq)),
+                           &e);
+  if (e != hipSuccess)
+    return fail(g_arena ? BF_E_CAPACITY : BF_E_NOMEM,
+                g_arena ? "bf_scene_create_ws: workspace smaller than bf_workspace_bytes"
+                        : "bf_scene_create: device allocation failed");
+  bf_status r = alloc_asm(s, act_cap);
+  if (r == BF_OK) r = alloc_stage(s, cand_cap);
+  return r;
+}
+
 extern "C" {
 
 const char* bf_last_error(void) { return g_err.c_str(); }
@@ -279,10 +377,9 @@ bf_status bf_set_scan_poll_limit(int32_t polls) {
   return BF_OK;
 }
 
-bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int64_t cand_cap, int64_t act_cap,
-                          void* stream, bf_scene** out) {
-  if (!mesh || !params || !out) return fail(BF_E_ARG, "bf_scene_create: null argument");
-  *out = nullptr;
+static bf_status check_scene_args(const bf_mesh_desc* mesh, const bf_params* params, int64_t cand_cap,
+                                  int64_t act_cap) {
+  if (!mesh || !params) return fail(BF_E_ARG, "bf_scene_create: null argument");
   if (mesh->kind != BF_ROD && mesh->kind != BF_SHELL) return fail(BF_E_ARG, "bf_scene_create: bad kind");
   if (mesh->n_verts < 2 || mesh->n_edges < 1 || !mesh->edges_h || !mesh->ref_h)
     return fail(BF_E_ARG, "bf_scene_create: need >= 2 vertices, >= 1 edge, edges and rest parameters");
@@ -298,6 +395,13 @@ bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int
     return fail(BF_E_ARG, "bf_scene_create: bad filter mode");
   if (params->filter == BF_FILTER_CULL && (mesh->kind != BF_ROD || params->cull_radius < 1))
     return fail(BF_E_ARG, "bf_scene_create: culling is defined for rods, with a radius of at least one element");
+  if (params->refdist != BF_REFDIST_PARAM && params->refdist != BF_REFDIST_EUCLID_REST)
+    return fail(BF_E_ARG, "bf_scene_create: bad reference-distance mode");
+  if (params->refdist == BF_REFDIST_EUCLID_REST) {
+    if (!mesh->ref_pos_h) return fail(BF_E_ARG, "bf_scene_create: BF_REFDIST_EUCLID_REST needs the rest pose");
+    for (long long k = 0; k < 3LL * mesh->n_verts; ++k)
+      if (!std::isfinite(mesh->ref_pos_h[k])) return fail(BF_E_ARG, "bf_scene_create: rest pose not finite");
+  }
   if (cand_cap < 1 || act_cap < 1) return fail(BF_E_ARG, "bf_scene_create: capacities must be >= 1");
   int nv = (int)mesh->n_verts, ne = (int)mesh->n_edges, nt = mesh->kind == BF_SHELL ? (int)mesh->n_tris : 0;
   for (long long k = 0; k < 2LL * ne; ++k)
@@ -307,6 +411,15 @@ bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int
   for (int e = 0; e < ne; ++e)
     if (mesh->edges_h[2 * e] == mesh->edges_h[2 * e + 1]) return fail(BF_E_ARG, "bf_scene_create: degenerate edge");
   if (const char* why = degenerate_rest(*mesh, nv, ne, nt)) return fail(BF_E_DEGENERATE, why);
+  return BF_OK;
+}
+
+static bf_status create_scene(const bf_mesh_desc* mesh, const bf_params* params, int64_t cand_cap,
+                              int64_t act_cap, void* stream, Arena* arena, bf_scene** out) {
+  if (!out) return fail(BF_E_ARG, "bf_scene_create: null argument");
+  *out = nullptr;
+  if (bf_status r = check_scene_args(mesh, params, cand_cap, act_cap); r != BF_OK) return r;
+  const int nv = (int)mesh->n_verts, ne = (int)mesh->n_edges, nt = mesh->kind == BF_SHELL ? (int)mesh->n_tris : 0;
 
   hipStream_t st = (hipStream_t)stream;
   g_alloc_stream = st;
@@ -317,50 +430,30 @@ bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int
   s->ne = ne;
   s->nt = nt;
   s->last = st;
-  hipError_t e = hipSuccess;
-  int nref = s->kind == BF_ROD ? nv : 2 * nv;
-  s->d_edges = dalloc<int>(s->allocs, 2LL * ne, &e);
-  s->d_tris = dalloc<int>(s->allocs, std::max(3LL * nt, 3LL), &e);
-  s->d_ref = dalloc<double>(s->allocs, nref, &e);
-  s->d_comp = dalloc<int>(s->allocs, nv, &e);
-  s->d_status = dalloc<unsigned>(s->allocs, 4, &e);
-  s->d_line = dalloc<double>(s->allocs, LINE_BLOCKS, &e);
-  int np = ne + nt + (s->kind == BF_SHELL ? nv : 0);
-  BroadWs& W = s->bw;
-  W.max_cells = (int)std::min<long long>(std::max<long long>(4096, 2LL * np), 1LL << 26);
-  long long nscan = 2LL * W.max_cells + 1;
-  long long nq = (long long)(s->kind == BF_SHELL ? nv + ne : ne) * PQ_MAX + 1;
-  W.box = dalloc<Box>(s->allocs, np, &e);
-  W.cell_of = dalloc<int>(s->allocs, ne + nt, &e);
-  W.part = dalloc<float>(s->allocs, 8LL * BOUNDS_BLOCKS, &e);
-  W.done = dalloc<unsigned>(s->allocs, 1, &e);
-  W.grid = dalloc<Grid>(s->allocs, 1, &e);
-  W.cell_cnt = dalloc<int>(s->allocs, nscan, &e);
-  W.cell_start = dalloc<int>(s->allocs, nscan, &e);
-  W.sorted_id = dalloc<int>(s->allocs, ne + nt, &e);
-  W.sorted_box = dalloc<Box>(s->allocs, ne + nt, &e);
-  W.placed_id = dalloc<int>(s->allocs, ne + nt, &e);
-  W.placed_box = dalloc<Box>(s->allocs, ne + nt, &e);
-  W.pair_cnt = dalloc<int>(s->allocs, nq, &e);
-  W.pair_bsum = dalloc<int>(s->allocs, nq / 256 + 2, &e);
-  W.pair_bseg = dalloc<long long>(s->allocs, nq / 256 + 2, &e);
-  W.seg_count = dalloc<unsigned long long>(s->allocs, 1, &e);
-  W.scan_tmp = dalloc<int>(s->allocs, std::max(std::max(scan_tmp_ints(nscan), scan_tmp_ints(nv + 1)), scan_tmp_ints(nq)), &e);
-  if (e != hipSuccess) {
-    free_list(s->allocs);
-    delete s;
-    return fail(BF_E_NOMEM, "bf_scene_create: device allocation failed");
+  const bool euclid = params->refdist == BF_REFDIST_EUCLID_REST;
+  const int nref = s->kind == BF_ROD ? nv : 2 * nv;
+  s->in_ws = arena != nullptr;
+  g_arena = arena;
+  const bf_status ra = alloc_persistent(s, cand_cap, act_cap);
+  g_arena = nullptr;
+  if (bf_status r = ra; r != BF_OK) {
+    discard_scene(s);
+    return r;
   }
+  BroadWs& W = s->bw;
+  const long long nscan = 2LL * W.max_cells + 1;
+  hipError_t e = hipSuccess;
   hipError_t he;
   if ((he = hipMemcpyAsync(s->d_edges, mesh->edges_h, sizeof(int) * 2LL * ne, hipMemcpyHostToDevice, st)) ||
       (nt && (he = hipMemcpyAsync(s->d_tris, mesh->tris_h, sizeof(int) * 3LL * nt, hipMemcpyHostToDevice, st))) ||
       (he = hipMemcpyAsync(s->d_ref, mesh->ref_h, sizeof(double) * nref, hipMemcpyHostToDevice, st)) ||
+      (euclid &&
+       (he = hipMemcpyAsync(s->d_xrest, mesh->ref_pos_h, sizeof(double) * 3LL * nv, hipMemcpyHostToDevice, st))) ||
       (he = hipMemsetAsync(s->d_status, 0, 4 * sizeof(unsigned), st)) ||
       (he = hipMemsetAsync(W.cell_cnt, 0, sizeof(int) * nscan, st)) ||
       (he = hipMemsetAsync(W.scan_tmp, 0, sizeof(int) * SCAN_LB_STATE, st)) ||
       (he = hipMemsetAsync(W.done, 0, sizeof(unsigned), st))) {
-    free_list(s->allocs);
-    delete s;
+    discard_scene(s);
     return fail_hip(he, "bf_scene_create: upload");
   }
 
@@ -372,16 +465,14 @@ bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int
   int* changed = dalloc<int>(tmp, 1, &e);
   if (e != hipSuccess) {
     free_list(tmp);
-    free_list(s->allocs);
-    delete s;
+    discard_scene(s);
     return fail(BF_E_NOMEM, "bf_scene_create: device allocation failed");
   }
   SceneDev S = dev_view(s);
   int nc = run_components(S, lab, flag, scan, s->d_comp, W.scan_tmp, changed, st);
   free_list(tmp);
   if (nc <= 0) {
-    free_list(s->allocs);
-    delete s;
+    discard_scene(s);
     return fail(BF_E_DEVICE, "bf_scene_create: component labelling failed");
   }
   s->nc = nc;
@@ -389,67 +480,75 @@ bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int
   if (params->filter == BF_FILTER_CULL) {
     std::vector<int> eidx, eloop;
     if (!polyline_order(nv, ne, mesh->edges_h, eidx, eloop)) {
-      free_list(s->allocs);
-      delete s;
+      discard_scene(s);
       return fail(BF_E_ARG, "bf_scene_create: culling needs polylines (no vertex on more than two edges)");
     }
-    s->d_eidx = dalloc<int>(s->allocs, ne, &e);
-    s->d_eloop = dalloc<int>(s->allocs, ne, &e);
-    if (e != hipSuccess || hipMemcpyAsync(s->d_eidx, eidx.data(), sizeof(int) * ne, hipMemcpyHostToDevice, st) ||
+    if (hipMemcpyAsync(s->d_eidx, eidx.data(), sizeof(int) * ne, hipMemcpyHostToDevice, st) ||
         hipMemcpyAsync(s->d_eloop, eloop.data(), sizeof(int) * ne, hipMemcpyHostToDevice, st) ||
         hipStreamSynchronize(st)) {
-      free_list(s->allocs);
-      delete s;
+      discard_scene(s);
       return fail(BF_E_NOMEM, "bf_scene_create: culling tables");
     }
   }
-  s->d_dmin = dalloc<double>(s->allocs, nc, &e);
-  s->d_thr2 = dalloc<double>(s->allocs, 2LL * nc, &e);
 
   // --- precompute: d_min per component over stencil pairs with 0 < dbar < h,
   // found by the same broad phase run on the rest parameters lifted to 3D
+  // (or on the rest pose, under the Euclidean reading)
   std::vector<unsigned long long> best(nc, 0x7ff0000000000000ull);  // +inf
   long long cap = std::max<long long>(cand_cap, 1024);
+  const long long tie_cap = std::max<long long>(4096, cap / 16);
   for (int attempt = 0; attempt < 4; ++attempt) {
     std::vector<void*> t2;
-    double* xref = dalloc<double>(t2, 3LL * nv, &e);
+    double* xref = euclid ? nullptr : dalloc<double>(t2, 3LL * nv, &e);
     int* ci = dalloc<int>(t2, cap, &e);
     int* cj = dalloc<int>(t2, cap, &e);
     unsigned char* ct = dalloc<unsigned char>(t2, cap, &e);
     long long* cnt = dalloc<long long>(t2, 1, &e);
     unsigned long long* dbest = dalloc<unsigned long long>(t2, nc, &e);
+    long long* ties = dalloc<long long>(t2, tie_cap, &e);
+    unsigned long long* flags = dalloc<unsigned long long>(t2, 2, &e);  // tie count, degenerate / limit bits
     if (e != hipSuccess) {
       free_list(t2);
-      free_list(s->allocs);
-      delete s;
+      discard_scene(s);
       return fail(BF_E_NOMEM, "bf_scene_create: device allocation failed");
     }
     S = dev_view(s);
-    run_lift_ref(S, xref, st);
-    run_broad(S, xref, nullptr, W, ci, cj, ct, cap, cnt, s->d_status, nullptr, nullptr, 0, st);  // no staging yet
+    if (!euclid) run_lift_ref(S, xref, st);
+    run_broad(S, euclid ? s->d_xrest : xref, nullptr, W, ci, cj, ct, cap, cnt, s->d_status, nullptr, nullptr, 0,
+              st);  // no staging yet
     (void)hipMemcpyAsync(dbest, best.data(), sizeof(unsigned long long) * nc, hipMemcpyHostToDevice, st);
-    run_refmin(S, ci, cj, ct, cnt, cap, dbest, st);
+    run_refmin(S, ci, cj, ct, cnt, cap, dbest, ties, tie_cap, flags, st);
     long long hcnt = 0;
+    unsigned long long hflags[2] = {0, 0};
     (void)hipMemcpyAsync(&hcnt, cnt, sizeof(long long), hipMemcpyDeviceToHost, st);
+    (void)hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, st);
     std::vector<unsigned long long> got(nc);
     (void)hipMemcpyAsync(got.data(), dbest, sizeof(unsigned long long) * nc, hipMemcpyDeviceToHost, st);
     (void)hipMemcpyAsync(s->comp_h.data(), s->d_comp, sizeof(int) * nv, hipMemcpyDeviceToHost, st);
     he = hipStreamSynchronize(st);
     free_list(t2);
     if (he != hipSuccess) {
-      free_list(s->allocs);
-      delete s;
+      discard_scene(s);
       return fail_hip(he, "bf_scene_create: precompute");
     }
-    if (hcnt <= cap) {
+    if (hcnt <= cap && (long long)hflags[0] <= tie_cap) {
+      const char* why = (hflags[1] & 1ull) ? "bf_scene_create: two primitives of the rest pose touch"
+                        : (hflags[1] & 2ull) ? "bf_scene_create: a rest-pose distance needs more exact "
+                                               "arithmetic than the expansions hold"
+                                             : nullptr;
+      if (why) {
+        discard_scene(s);
+        return fail(BF_E_DEGENERATE, why);
+      }
       best = got;
       break;
     }
-    cap = hcnt + hcnt / 8 + 1024;
-    if (attempt == 3) {
-      free_list(s->allocs);
-      delete s;
-      return fail(BF_E_CAPACITY, "bf_scene_create: rest-space candidate list kept overflowing");
+    cap = std::max(cap, hcnt + hcnt / 8 + 1024);
+    if (attempt == 3 || (long long)hflags[0] > tie_cap) {
+      discard_scene(s);
+      return fail(BF_E_CAPACITY, (long long)hflags[0] > tie_cap
+                                     ? "bf_scene_create: too many rest-pose distances tie with h"
+                                     : "bf_scene_create: rest-space candidate list kept overflowing");
     }
   }
   s->dmin2_h.assign(nc, INFINITY);
@@ -462,7 +561,7 @@ bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int
       thr2[2 * c + 1] = 0.0;
       continue;
     }
-    if (s->kind == BF_ROD) {  // the minimum gap; threshold its exact square
+    if (s->kind == BF_ROD && !euclid) {  // the minimum gap; threshold its exact square
       s->dmin_h[c] = v;
       s->dmin2_h[c] = v * v;
       thr2[2 * c] = v * v;
@@ -477,13 +576,11 @@ bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int
   if ((he = hipMemcpyAsync(s->d_dmin, s->dmin_h.data(), sizeof(double) * nc, hipMemcpyHostToDevice, st)) ||
       (he = hipMemcpyAsync(s->d_thr2, thr2.data(), sizeof(double) * 2 * nc, hipMemcpyHostToDevice, st)) ||
       (he = hipMemsetAsync(s->d_status, 0, 4 * sizeof(unsigned), st)) || (he = hipStreamSynchronize(st))) {
-    free_list(s->allocs);
-    delete s;
+    discard_scene(s);
     return fail_hip(he, "bf_scene_create: upload d_min");
   }
-  bf_status r = alloc_asm(s, act_cap);
-  if (r == BF_OK) r = alloc_stage(s, cand_cap);
-  if (r == BF_OK && ((he = hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking)) != hipSuccess ||
+  bf_status r = BF_OK;
+  if (((he = hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking)) != hipSuccess ||
                      (he = hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming)) != hipSuccess ||
                      (he = hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming)) != hipSuccess))
     r = fail_hip(he, "bf_scene_create: side stream");
@@ -491,18 +588,52 @@ bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int
     if (s->ev_join) (void)hipEventDestroy(s->ev_join);
     if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
     if (s->side) (void)hipStreamDestroy(s->side);
-    free_list(s->asm_allocs);
-    free_list(s->stage_allocs);
-    free_list(s->allocs);
-    delete s;
+    discard_scene(s);
     return r;
   }
   *out = s;
   return BF_OK;
 }
 
+bf_status bf_scene_create(const bf_mesh_desc* mesh, const bf_params* params, int64_t cand_cap, int64_t act_cap,
+                          void* stream, bf_scene** out) {
+  return create_scene(mesh, params, cand_cap, act_cap, stream, nullptr, out);
+}
+
+bf_status bf_workspace_bytes(const bf_mesh_desc* mesh, const bf_params* params, int64_t cand_cap, int64_t act_cap,
+                             int64_t* bytes_h) {
+  if (!bytes_h) return fail(BF_E_ARG, "bf_workspace_bytes: null argument");
+  if (bf_status r = check_scene_args(mesh, params, cand_cap, act_cap); r != BF_OK) return r;
+  bf_scene probe;  // host fields only: the allocation sequence is counted, nothing is allocated
+  probe.prm = *params;
+  probe.kind = mesh->kind;
+  probe.nv = (int)mesh->n_verts;
+  probe.ne = (int)mesh->n_edges;
+  probe.nt = mesh->kind == BF_SHELL ? (int)mesh->n_tris : 0;
+  Arena a;
+  g_arena = &a;
+  const bf_status r = alloc_persistent(&probe, cand_cap, act_cap);
+  g_arena = nullptr;
+  if (r != BF_OK) return r;
+  *bytes_h = (int64_t)a.off + 255;  // room to align an unaligned base
+  return BF_OK;
+}
+
+bf_status bf_scene_create_ws(const bf_mesh_desc* mesh, const bf_params* params, int64_t cand_cap, int64_t act_cap,
+                             void* ws_d, int64_t ws_bytes, void* stream, bf_scene** out) {
+  if (!ws_d || ws_bytes < 1) return fail(BF_E_ARG, "bf_scene_create_ws: null or empty workspace");
+  const uintptr_t b0 = (uintptr_t)ws_d, b1 = (b0 + 255) & ~(uintptr_t)255;
+  if ((int64_t)(b1 - b0) >= ws_bytes) return fail(BF_E_CAPACITY, "bf_scene_create_ws: workspace too small");
+  Arena a;
+  a.base = (char*)b1;
+  a.cap = (size_t)(ws_bytes - (int64_t)(b1 - b0));
+  return create_scene(mesh, params, cand_cap, act_cap, stream, &a, out);
+}
+
 bf_status bf_scene_reserve(bf_scene* s, int64_t cand_cap, int64_t act_cap) {
   if (!s || act_cap < 1 || cand_cap < 1) return fail(BF_E_ARG, "bf_scene_reserve: bad argument");
+  if (s->in_ws && (act_cap > s->act_cap || cand_cap > s->sw.cap))
+    return fail(BF_E_STATE, "bf_scene_reserve: a scene in a caller's workspace cannot grow");
   if (act_cap <= s->act_cap && cand_cap <= s->sw.cap) return BF_OK;
   hipError_t he = hipDeviceSynchronize();
   if (he != hipSuccess) return fail_hip(he, "bf_scene_reserve");
@@ -866,13 +997,14 @@ bf_status assemble_grad_hess(bf_scene* s, const bf_active* act, const bf_local* 
   return he == hipSuccess ? BF_OK : fail_hip(he, "assemble_grad_hess");
 }
 
-bf_status bf_scene_deferred(bf_scene* s, int64_t* n_h) {
-  if (!s || !n_h) return fail(BF_E_ARG, "bf_scene_deferred: null argument");
+bf_status bf_scene_deferred(bf_scene* s, int64_t* n_band_h, int64_t* n_exact_h) {
+  if (!s) return fail(BF_E_ARG, "bf_scene_deferred: null scene");
   hipError_t he = hipStreamSynchronize(s->last);
-  unsigned v = 0;
-  if (he == hipSuccess) he = hipMemcpy(&v, s->d_status + 1, sizeof(unsigned), hipMemcpyDeviceToHost);
+  unsigned v[2] = {0, 0};
+  if (he == hipSuccess) he = hipMemcpy(v, s->d_status + 1, sizeof(v), hipMemcpyDeviceToHost);
   if (he != hipSuccess) return fail_hip(he, "bf_scene_deferred");
-  *n_h = v;
+  if (n_band_h) *n_band_h = v[0];
+  if (n_exact_h) *n_exact_h = v[1];
   return BF_OK;
 }
 
@@ -901,6 +1033,22 @@ bf_status bf_scene_stage_ms(bf_scene* s, float* ms_h) {
   }
   return BF_OK;
 }
+
+}  // extern "C"
+
+// For the serving loop (bfc_serve.hip): the status word into device memory
+// and cleared, in stream order; and the library's error message.
+bf_status bfc_status_take(bf_scene* s, uint32_t* dst_d, void* stream) {
+  if (!s || !dst_d) return fail(BF_E_ARG, "bf_serve: null argument");
+  hipStream_t st = (hipStream_t)stream;
+  s->last = st;
+  run_status_take(s->d_status, dst_d, st);
+  const hipError_t he = hipGetLastError();
+  return he == hipSuccess ? BF_OK : fail_hip(he, "bf_serve: status");
+}
+bf_status bfc_fail(bf_status code, const char* msg) { return fail(code, msg); }
+
+extern "C" {
 
 bf_status bf_status_word(bf_scene* s, uint32_t* bits_h, int32_t clear) {
   if (!s || !bits_h) return fail(BF_E_ARG, "bf_status_word: null argument");
@@ -1032,7 +1180,9 @@ bf_status batch_capture(bf_batch* b, int lanes) {
 extern "C" {
 
 bf_status bf_scene_set_pq(bf_scene* s, int32_t pq) {
-  if (!s || (pq != 2 && pq != 4 && pq != 8)) return fail(BF_E_ARG, "bf_scene_set_pq: pq must be 2, 4 or 8");
+  static_assert(PQ_MAX >= 16, "the per-thread broad-phase buffers are sized for PQ_MAX threads per query");
+  if (!s || (pq != 2 && pq != 4 && pq != 8 && pq != 16))
+    return fail(BF_E_ARG, "bf_scene_set_pq: pq must be 2, 4, 8 or 16");
   s->pq = pq;
   return BF_OK;
 }
@@ -1048,11 +1198,11 @@ bf_status bf_scene_tune(bf_scene* s, const double* x_d, bf_pairs* cand, int32_t 
     (void)hipEventDestroy(e0);
     return fail_hip(he, "bf_scene_tune");
   }
-  const int choices[3] = {2, 4, 8};
+  const int choices[4] = {2, 4, 8, 16};
   int best = s->pq;
   float best_ms = INFINITY;
   bf_status r = BF_OK;
-  for (int c = 0; c < 3 && r == BF_OK; ++c) {
+  for (int c = 0; c < 4 && r == BF_OK; ++c) {
     s->pq = choices[c];
     r = build_candidates(s, x_d, cand, stream);  // warm
     std::vector<float> t;

@@ -36,6 +36,8 @@ struct SceneDev {
   const int* edges;  // [E,2]
   const int* tris;   // [F,3]
   const double* ref; // rods [V]; shells [V,2]
+  const double* xrest;  // [V,3] rest pose (BF_REFDIST_EUCLID_REST), else null
+  int refdist;          // BF_REFDIST_PARAM or BF_REFDIST_EUCLID_REST
   const int* comp;   // [V]
   const double* dmin;  // [C] activation of filtered pairs
   const double* thr2;  // [C,2] exact squared activation of filtered pairs (hi, lo)
@@ -52,7 +54,7 @@ struct SceneDev {
   int cull_r;
   int filter;  // 0 paper, 1 none, 2 cull
   int mixed;   // 1: projection converged to the mixed-precision tolerance
-  int pq;      // threads per broad-phase query (2, 4 or 8)
+  int pq;      // threads per broad-phase query (2, 4, 8 or 16)
   unsigned* status;  // the scene's device status word (BF_S_* bits)
 };
 
@@ -69,8 +71,10 @@ struct BroadWs {
   Box* placed_box;   // [NS]
   int* sorted_id;    // [NS] stored primitives in cell order, by id inside a cell
   Box* sorted_box;   // [NS]
+  int4* sorted_vid;  // [NS] their vertex ids (edges: v0, v1, -1; triangles: t0, t1, t2)
   int* pair_cnt;     // [NQ * PQ_MAX] pairs per (query, cell subset)
   int* pair_bsum;    // [work-groups + 1] pairs per work-group of the count pass
+  int* pair_bofs;    // [work-groups + 1] their exclusive scan (the emit pass's offsets)
   long long* pair_bseg;            // [work-groups + 1] start of each group's staged pairs, -1: visit again
   unsigned long long* seg_count;   // [1] staged pairs of this step (segments are taken in any order)
   int* scan_tmp;     // [scan partials]
@@ -87,7 +91,9 @@ struct StageWs {
   int* kofs;     // [4 * G + 1] their exclusive scan
   int* ccnt;     // [3 * G] per-tile N_c, N_filt, N_infeasible
   long long* dfr;  // [cand cap] deferred candidates (indices), in candidate order
-  int* xcnt;       // [5 * XP_BLOCKS] per-range counts of k_exact
+  int* dfr2;       // [cand cap] deferred indices that double-double left open (k_band, any order)
+  int* n2;         // [1] their number
+  int* xcnt;       // [5 * XP_BLOCKS] per-range counts of the deferred results
   int* scan_tmp;
   long long cap; // staging capacity in candidates
 };

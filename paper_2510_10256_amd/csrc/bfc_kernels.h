@@ -8,13 +8,14 @@ namespace bfc {
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = 256 * SCAN_ITEMS;
 constexpr int SCAN1_MAX = 1 << 14;     // arrays up to this length are scanned by one work-group
-constexpr int PQ_MAX = 8;              // threads per broad-phase query: 2, 4 (default) or 8
+constexpr int PQ_MAX = 16;             // threads per broad-phase query: 2, 4 (default), 8 or 16
 constexpr int NW_ITEMS = 4;            // candidates per thread in the narrow phase
 constexpr int LINE_BLOCKS = 8192;      // work-groups of the line-search kernels (grid-stride)
 constexpr int NW_TILE = 256 * NW_ITEMS;
 constexpr int NW_KINDS = 4;            // staged kinds in a narrow-phase tile: 9x9, 6x6, closed form, deferred
 constexpr int NW_DEFER = 3;            // the deferred kind: decided exactly by k_exact
-constexpr int XP_BLOCKS = 1024;        // work-groups of k_exact (ranges of the deferred list)
+constexpr int XP_BLOCKS = 1024;        // work-groups of k_exact (ranges of its list) and of the deferred counts
+constexpr int BAND_BLOCKS = 2048;      // work-groups of k_band (grid-stride over the deferred list)
 constexpr int XP_TPB = 16;             // threads of a k_exact work-group, an LDS expansion slab each
 constexpr int BOUNDS_BLOCKS = 512;     // cap on k_bounds work-groups (partials of the last-block reduction)
 
@@ -85,14 +86,20 @@ int run_components(const SceneDev& S, int* lab, int* flag, int* scan, int* comp,
                    hipStream_t st);
 
 // a[0..n) = 0 for n <= 64 (a kernel: unlike a memset it may be captured)
+// dst[0] = the status word, then the word is cleared (stream order).
+void run_status_take(unsigned* status, unsigned* dst, hipStream_t st);
 void run_zero_i64(long long* a, int n, hipStream_t st);
 
 // Lift rest parameters to 3D points (rods (s,0,0); shells (u1,u2,0)).
 void run_lift_ref(const SceneDev& S, double* xref, hipStream_t st);
 
 // Per-component minimum of the reference distance over stencil pairs with
-// 0 < dbar < h among the candidates (rods: gap; shells: dbar^2 rounded).
+// 0 < dbar < h among the candidates (rods: gap; shells and the Euclidean
+// reading: dbar^2 rounded).  ties [tie_cap]: the Euclidean reading's pairs
+// decided exactly; flags[0] their count, flags[1] bit 0 touching primitives
+// at rest, bit 1 an exact decision out of room.
 void run_refmin(const SceneDev& S, const int* ci, const int* cj, const unsigned char* ct, const long long* count,
-                long long cap, unsigned long long* best, hipStream_t st);
+                long long cap, unsigned long long* best, long long* ties, long long tie_cap,
+                unsigned long long* flags, hipStream_t st);
 
 }  // namespace bfc

@@ -496,9 +496,13 @@ __global__ __launch_bounds__(256) void k_scatter(int nstored, const Box* box, co
 // The scatter's atomics leave the entries of a cell in arbitrary order; each
 // entry's rank among the cell's ids puts them in id order, so candidate
 // lists, and every result downstream, are the same from run to run.
-__global__ __launch_bounds__(256) void k_cell_order(int nstored, const int* cell_of, const int* cell_start,
-                                                    const int* placed_id, const Box* placed_box, int* sorted_id,
-                                                    Box* sorted_box) {
+// Beside each entry go its vertex ids (edges: v0, v1, -1; triangles: t0, t1,
+// t2), which the pair search's incidence test reads with the box instead of
+// gathering them from the topology.
+__global__ __launch_bounds__(256) void k_cell_order(SceneDev S, int nstored, const int* cell_of,
+                                                    const int* cell_start, const int* placed_id,
+                                                    const Box* placed_box, int* sorted_id, Box* sorted_box,
+                                                    int4* sorted_vid) {
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nstored; k += grid_stride()) {
     const int p = placed_id[k], sub = cell_of[p];
     const int b = cell_start[sub], e = cell_start[sub + 1];
@@ -506,6 +510,12 @@ __global__ __launch_bounds__(256) void k_cell_order(int nstored, const int* cell
     for (int q = b; q < e; ++q) r += placed_id[q] < p;
     sorted_id[b + r] = p;
     sorted_box[b + r] = placed_box[k];
+    if (p < S.ne) {
+      sorted_vid[b + r] = make_int4(S.edges[2 * p], S.edges[2 * p + 1], -1, 0);
+    } else {
+      const int t = p - S.ne;
+      sorted_vid[b + r] = make_int4(S.tris[3 * t], S.tris[3 * t + 1], S.tris[3 * t + 2], 0);
+    }
   }
 }
 
@@ -539,10 +549,11 @@ __device__ __forceinline__ bool boxes_far_f(const Box& a, const Box& b, float ga
 // and stage it (its stored id at stage[256 * n] while n < STAGE_K) or emit
 // it at `pos`.
 constexpr int VISIT_COUNT = 0, VISIT_STAGE = 1, VISIT_EMIT = 2;
-constexpr int STAGE_K = 16;  // candidates a count-pass thread keeps in LDS
+constexpr int STAGE_K = 32;  // candidates a count-pass thread keeps in LDS (32 KiB a work-group)
 template <int PQ, int MODE>
 __device__ __forceinline__ int visit_pairs(const SceneDev& S, const Grid& g, const int* cell_start,
-                                           const int* sorted_id, const Box* sorted_box, double hf, int qtype,
+                                           const int* sorted_id, const Box* sorted_box, const int4* sorted_vid,
+                                           double hf, int qtype,
                                            int qid, const Box& qb, const int* qv, int sub, long long pos,
                                            long long cap, int* oi, int* oj, unsigned char* ot, unsigned* status) {
   int lo[3], hi[3];
@@ -559,14 +570,12 @@ __device__ __forceinline__ int visit_pairs(const SceneDev& S, const Grid& g, con
       if (qtype == BF_EE && r <= qid) continue;
       const Box rb = sorted_box[k];
       if (boxes_far_f(qb, rb, g.gapf) || !boxes_near(qb, rb, hf)) continue;
+      const int4 rv = sorted_vid[k];
       if (qtype == BF_EE) {
-        int r0 = S.edges[2 * r], r1 = S.edges[2 * r + 1];
-        if (r0 == qv[0] || r0 == qv[1] || r1 == qv[0] || r1 == qv[1]) continue;
+        if (rv.x == qv[0] || rv.x == qv[1] || rv.y == qv[0] || rv.y == qv[1]) continue;
       } else {
-        int t = r - S.ne;
-        int t0 = S.tris[3 * t], t1 = S.tris[3 * t + 1], t2 = S.tris[3 * t + 2];
-        if (t0 == qid || t1 == qid || t2 == qid) continue;
-        r = t;
+        if (rv.x == qid || rv.y == qid || rv.z == qid) continue;
+        r -= S.ne;
       }
       if (MODE == VISIT_STAGE && cnt < STAGE_K) oi[256 * cnt] = r;
       if (MODE == VISIT_EMIT) {
@@ -617,6 +626,7 @@ __device__ __forceinline__ void query_id(const SceneDev& S, int q, int& qtype, i
 template <int PQ>
 __global__ __launch_bounds__(256) void k_pair_count(SceneDev S, int nquery, const Box* box, const Grid* gp,
                                                     const int* cell_start, const int* sorted_id, const Box* sorted_box,
+                                                    const int4* sorted_vid,
                                                     double hf, int* cnt, int* bsum, long long* bseg,
                                                     unsigned long long* seg_count, int* seg_r, unsigned* seg_t,
                                                     long long seg_cap) {
@@ -631,7 +641,8 @@ __global__ __launch_bounds__(256) void k_pair_count(SceneDev S, int nquery, cons
     int qtype, qid, qv[2];
     Box qb;
     query_of(S, box, t / PQ, qtype, qid, qb, qv);
-    c = visit_pairs<PQ, VISIT_STAGE>(S, g, cell_start, sorted_id, sorted_box, hf, qtype, qid, qb, qv, t % PQ, 0, 0,
+    c = visit_pairs<PQ, VISIT_STAGE>(S, g, cell_start, sorted_id, sorted_box, sorted_vid, hf, qtype, qid, qb, qv,
+                                     t % PQ, 0, 0,
                                      stage + threadIdx.x, nullptr, nullptr, nullptr);
     cnt[t] = c;
   }
@@ -667,28 +678,26 @@ __global__ __launch_bounds__(256) void k_pair_count(SceneDev S, int nquery, cons
   }
 }
 
-// Pass 2: the group's offset from the totals of all earlier groups plus, per
-// thread, an in-group scan; output in query-major order (no atomics).  The
+// Pass 2: the group's offset (the scan of the count pass's group totals)
+// plus, per thread, an in-group scan; output in query-major order (no
+// atomics).  The
 // group copies its segment (coalesced); threads whose pairs are not in it
 // visit their cells again.
 template <int PQ>
 __global__ __launch_bounds__(256) void k_pair_emit(SceneDev S, int nquery, const Box* box, const Grid* gp,
                                                    const int* cell_start, const int* sorted_id, const Box* sorted_box,
-                                                   double hf, const int* cnt, const int* bsum, const long long* bseg,
+                                                   const int4* sorted_vid,
+                                                   double hf, const int* cnt, const int* bofs, const long long* bseg,
                                                    const int* seg_r, const unsigned* seg_t, int* oi, int* oj,
                                                    unsigned char* ot, long long cap, long long* count,
                                                    unsigned* status) {
   __shared__ int locs[256];
   Grid g = *gp;
   int nt = nquery * PQ;
-  // this block's offset: the pairs of all earlier blocks of the count pass
-  // (block 0 also sums them all: the candidate count)
-  const int upto = blockIdx.x == 0 ? (int)gridDim.x : (int)blockIdx.x;
-  long long part = 0;
-  for (int q = threadIdx.x; q < upto; q += blockDim.x) part += bsum[q];
-  const long long before = block_sum256(part);
-  if (blockIdx.x == 0 && threadIdx.x == 0) *count = before;
-  const long long base = blockIdx.x == 0 ? 0 : before;
+  // this block's offset: the exclusive scan of the count pass's block totals
+  // (its last entry, the candidate count, is written by block 0)
+  if (blockIdx.x == 0 && threadIdx.x == 0) *count = bofs[gridDim.x];
+  const long long base = bofs[blockIdx.x];
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int c = t < nt ? cnt[t] : 0;
   const int loc = block_excl_scan256(c, nullptr);
@@ -717,7 +726,8 @@ __global__ __launch_bounds__(256) void k_pair_emit(SceneDev S, int nquery, const
   int qtype, qid, qv[2];
   Box qb;
   query_of(S, box, t / PQ, qtype, qid, qb, qv);
-  visit_pairs<PQ, VISIT_EMIT>(S, g, cell_start, sorted_id, sorted_box, hf, qtype, qid, qb, qv, t % PQ, base + loc, cap,
+  visit_pairs<PQ, VISIT_EMIT>(S, g, cell_start, sorted_id, sorted_box, sorted_vid, hf, qtype, qid, qb, qv, t % PQ,
+                              base + loc, cap,
                               oi, oj, ot, status);
 }
 
@@ -854,6 +864,23 @@ __device__ __forceinline__ int ref_below_h_exact_in_double(const SceneDev& S, in
   return ok ? below : 2;
 }
 
+// Under the Euclidean reading (BF_REFDIST_EUCLID_REST) dbar is the distance
+// between the pair's primitives at the rest pose, the same distance function
+// as d(x); 0 < dbar holds for every pair of the scene (a rest pose with
+// touching primitives is refused at creation), so the filter is dbar < h,
+// decided like d < h: FP64, then (where amb is given) the exact-in-FP64
+// check, then double-double, *amb set within 1e-20 of h^2.
+__device__ __forceinline__ Near rest_near(const SceneDev& S, int type, const int* v, d3* P) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) P[k] = load3(S.xrest, v[k]);
+  return type == BF_PT ? classify_pt(P) : classify_ee(P);
+}
+__device__ __forceinline__ bool euclid_below_h(const SceneDev& S, int type, const int* v, bool* amb) {
+  d3 P[4];
+  const Near nr = rest_near(S, type, v, P);
+  return decide_sq(nr.code, P, nr.D, dd_sq(S.h), true, amb);
+}
+
 // Stencil pair with 0 < dbar < h in the same component (Sec. 3.2)?  Shells
 // compare dbar^2 with h^2 in FP64 outside a relative band of 1e-9 and in
 // double-double inside it; within 1e-20 of h^2 (*amb set, when amb is given)
@@ -861,6 +888,7 @@ __device__ __forceinline__ int ref_below_h_exact_in_double(const SceneDev& S, in
 __device__ __forceinline__ bool is_filtered(const SceneDev& S, int type, const int* v, bool* amb) {
   if (S.filter != 0) return false;
   if (S.comp[v[0]] != S.comp[v[2]]) return false;
+  if (S.refdist == BF_REFDIST_EUCLID_REST) return euclid_below_h(S, type, v, amb);
   if (S.kind == 0) {
     double sa0 = S.ref[v[0]], sa1 = S.ref[v[1]], sb0 = S.ref[v[2]], sb1 = S.ref[v[3]];
     double gap = fmax(fmin(sb0, sb1) - fmax(sa0, sa1), fmin(sa0, sa1) - fmax(sb0, sb1));
@@ -879,10 +907,44 @@ __device__ __forceinline__ bool is_filtered(const SceneDev& S, int type, const i
   return qq.hi > 0.0 && dd_lt(qq, hh);
 }
 
+// The narrow phase's first pass decides in FP64 alone: outside the relative
+// band of 1e-9 around h^2 the FP64 value settles it; inside it *amb is set
+// and the pair goes to k_exact, which takes the whole ladder (FP64, the
+// exact-in-FP64 check, double-double, expansions).  Keeping the ladder out of
+// this pass keeps its register footprint small.
+__device__ __forceinline__ bool decide_fp64(double D, double Th, bool lt, bool* amb) {
+  if (fabs(D - Th) > 1e-9 * Th) return lt ? (D < Th) : (D <= Th);
+  *amb = true;
+  return false;
+}
+__device__ __forceinline__ bool is_filtered_fp64(const SceneDev& S, int type, const int* v, bool* amb) {
+  if (S.filter != 0) return false;
+  if (S.comp[v[0]] != S.comp[v[2]]) return false;
+  if (S.refdist == BF_REFDIST_EUCLID_REST) {
+    d3 P[4];
+    return decide_fp64(rest_near(S, type, v, P).D, S.h * S.h, true, amb);
+  }
+  if (S.kind == 0) {
+    double sa0 = S.ref[v[0]], sa1 = S.ref[v[1]], sb0 = S.ref[v[2]], sb1 = S.ref[v[3]];
+    double gap = fmax(fmin(sb0, sb1) - fmax(sa0, sa1), fmin(sa0, sa1) - fmax(sb0, sb1));
+    return gap > 0.0 && gap < S.h;
+  }
+  const double h2 = S.h * S.h;
+  const double q = ref_sqdist_d(S, type, v);
+  if (fabs(q - h2) > 1e-9 * h2 && q > 1e-9 * h2) return q < h2;
+  *amb = true;
+  return false;
+}
+
 // The same decision, exact (k_exact): near h^2 the rest distance is below h
 // iff one of its segment distances is (the pair does not overlap in rest
 // space there), each decided on expansions (xp_seg2_below, slab ws).
 __device__ bool is_filtered_exact(const SceneDev& S, int type, const int* v, double* ws, bool* limit) {
+  if (S.filter == 0 && S.refdist == BF_REFDIST_EUCLID_REST && S.comp[v[0]] == S.comp[v[2]]) {
+    d3 P[4];
+    const Near nr = rest_near(S, type, v, P);
+    return decide_sq_exact(nr.code, P, nr.D, dd_sq(S.h), true, ws, limit);
+  }
   const bool r = is_filtered(S, type, v, nullptr);  // FP64, double-double in the band
   if (S.filter != 0 || S.kind == 0 || S.comp[v[0]] != S.comp[v[2]]) return r;
   const double h2 = S.h * S.h;
@@ -931,9 +993,16 @@ struct PairDec {
   int code;
   double D;
 };
-template <bool EXACT>
+// NW_FP64: FP64 alone, *amb set where a value lies in the relative band of
+// 1e-9 around its threshold (the narrow phase's first pass, k_narrow);
+// NW_DD: FP64, then the exact-in-FP64 check and double-double in the band,
+// *amb set within 1e-20 of the threshold (k_band); NW_EXACT: the whole
+// ladder, exact arithmetic last (k_exact).
+constexpr int NW_FP64 = 0, NW_DD = 1, NW_EXACT = 2;
+template <int MODE>
 __device__ __forceinline__ PairDec narrow_pair(const SceneDev& S, const double* x, int type, int i, int j, bool* amb,
                                                double* ws, bool* limit) {
+  constexpr bool EXACT = MODE == NW_EXACT;
   PairDec r{false, false, false, false, false, 0, 0.0};
   int v[4];
   pair_verts(S, type, i, j, v);
@@ -942,11 +1011,15 @@ __device__ __forceinline__ PairDec narrow_pair(const SceneDev& S, const double* 
   r.code = nr.code;
   r.D = nr.D;
   auto dec = [&](dd T, bool lt) {
-    return EXACT ? decide_sq_exact(r.code, P, r.D, T, lt, ws, limit) : decide_sq(r.code, P, r.D, T, lt, amb);
+    if constexpr (EXACT) return decide_sq_exact(r.code, P, r.D, T, lt, ws, limit);
+    else if constexpr (MODE == NW_DD) return decide_sq(r.code, P, r.D, T, lt, amb);
+    else return decide_fp64(r.D, T.hi, lt, amb);
   };
   r.nc = !is_culled(S, type, i, j) && dec(dd_sq(S.h), true);  // d < h (culled pairs: not in contact)
   if (r.nc) {
-    r.filt = EXACT ? is_filtered_exact(S, type, v, ws, limit) : is_filtered(S, type, v, amb);
+    if constexpr (EXACT) r.filt = is_filtered_exact(S, type, v, ws, limit);
+    else if constexpr (MODE == NW_DD) r.filt = is_filtered(S, type, v, amb);
+    else r.filt = is_filtered_fp64(S, type, v, amb);
     r.core = !r.filt && in_core(S, type, i, j);
     dd T;
     double eta;
@@ -993,7 +1066,7 @@ __global__ __launch_bounds__(256) void k_narrow(SceneDev S, const double* x, con
     bool amb = false;
     if (k < n) {
       type = ct[k]; i = ci[k]; j = cj[k];
-      pd = narrow_pair<false>(S, x, type, i, j, &amb, nullptr, nullptr);
+      pd = narrow_pair<NW_FP64>(S, x, type, i, j, &amb, nullptr, nullptr);
     }
     if (amb) pd.nc = pd.filt = pd.core = pd.active = pd.infeas = false;  // k_exact decides
     c_nc += pd.nc; c_f += pd.nc && pd.filt; c_inf += pd.infeas;
@@ -1081,6 +1154,7 @@ __global__ __launch_bounds__(256) void k_compact(StageWs W, int G, int* ai, int*
     for (int r = threadIdx.x; r < cnt; r += blockDim.x) W.dfr[dst + r] = W.si[base + koff + r];
   }
   if (b == 0) {
+    if (threadIdx.x == 0) *W.n2 = 0;  // k_band appends to the second list afresh
     __shared__ long long red[3][256];
     long long a = 0, f = 0, c = 0;
     for (int q = threadIdx.x; q < G; q += blockDim.x) {
@@ -1098,48 +1172,78 @@ __global__ __launch_bounds__(256) void k_compact(StageWs W, int G, int* ai, int*
   }
 }
 
-// Pass 3: the deferred candidates (neither FP64 nor double-double settled a
-// decision: exact ties whose formula needs more than 106 bits), decided in
-// exact arithmetic.  Work-group b takes the b-th of XP_BLOCKS contiguous
-// ranges of the deferred list, XP_TPB threads each with an expansion slab in
-// LDS; every result goes into the staging arrays at the deferred index (free
-// again after k_compact): ids, type, code, flags, the decisions (bits
-// 24..27: active, d < h, filtered and d < h, expansion room exceeded) and d;
-// the range's counts go to W.xcnt[5b..5b+4] (active, N_c, N_filt,
-// N_infeasible, exceeded).
-__global__ __launch_bounds__(XP_TPB) void k_exact(SceneDev S, const double* x, const int* ci, const int* cj,
-                                                  const unsigned char* ct, StageWs W, int G) {
-  __shared__ double slab[XP_TPB * XP_WS];
-  __shared__ int cnt[5];
-  const long long ndef = W.kofs[NW_KINDS * G] - W.kofs[NW_DEFER * G];
-  const long long R = (ndef + gridDim.x - 1) / gridDim.x, q0 = blockIdx.x * R, q1 = min(ndef, q0 + R);
-  if (threadIdx.x < 5) cnt[threadIdx.x] = 0;
-  __syncthreads();
-  double* ws = slab + threadIdx.x * XP_WS;
-  int c[5] = {0, 0, 0, 0, 0};
-  for (long long q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
-    const long long k = W.dfr[q];
-    const int type = ct[k], i = ci[k], j = cj[k];
-    bool limit = false;
-    const PairDec pd = narrow_pair<true>(S, x, type, i, j, nullptr, ws, &limit);
-    W.si[q] = i;
-    W.sj[q] = j;
-    W.sm[q] = (unsigned)type | ((unsigned)pd.code << 8) |
-              ((unsigned)((pd.filt ? BF_F_FILTERED : 0) | (pd.infeas ? BF_F_INFEASIBLE : 0) |
-                          (pd.core ? BF_F_CORE : 0)) << 16) |
-              (pd.active ? 1u << 24 : 0u) | (pd.nc ? 1u << 25 : 0u) | (pd.nc && pd.filt ? 1u << 26 : 0u) |
-              (limit ? 1u << 27 : 0u);
-    W.sd[q] = sqrt(pd.D);
-    c[0] += pd.active; c[1] += pd.nc; c[2] += pd.nc && pd.filt; c[3] += pd.infeas; c[4] += limit;
-  }
-#pragma unroll
-  for (int t = 0; t < 5; ++t)
-    if (c[t]) atomicAdd(&cnt[t], c[t]);
-  __syncthreads();
-  if (threadIdx.x < 5) W.xcnt[5 * blockIdx.x + threadIdx.x] = cnt[threadIdx.x];
+// The result record of a decided deferred candidate, at its deferred index
+// q in the staging arrays (free again after k_compact): ids, type, code,
+// flags, the decisions (bits 24..27: active, d < h, filtered and d < h,
+// expansion room exceeded) and d.
+__device__ __forceinline__ void put_deferred(const StageWs& W, long long q, int type, int i, int j, const PairDec& pd,
+                                             bool limit) {
+  W.si[q] = i;
+  W.sj[q] = j;
+  W.sm[q] = (unsigned)type | ((unsigned)pd.code << 8) |
+            ((unsigned)((pd.filt ? BF_F_FILTERED : 0) | (pd.infeas ? BF_F_INFEASIBLE : 0) |
+                        (pd.core ? BF_F_CORE : 0)) << 16) |
+            (pd.active ? 1u << 24 : 0u) | (pd.nc ? 1u << 25 : 0u) | (pd.nc && pd.filt ? 1u << 26 : 0u) |
+            (limit ? 1u << 27 : 0u);
+  W.sd[q] = sqrt(pd.D);
 }
 
-// Pass 4: the deferred pairs that are active are appended after the
+// Pass 3: the deferred candidates (a value in FP64's band around its
+// threshold), one per thread: the exact-in-FP64 check and double-double
+// settle most (lattice geometry); the rest, within 1e-20 of a threshold,
+// go to the second list (any order: each result goes to its own index).
+__global__ __launch_bounds__(256) void k_band(SceneDev S, const double* x, const int* ci, const int* cj,
+                                              const unsigned char* ct, StageWs W, int G) {
+  const long long ndef = W.kofs[NW_KINDS * G] - W.kofs[NW_DEFER * G];
+  for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < ndef; q += grid_stride()) {
+    const long long k = W.dfr[q];
+    const int type = ct[k], i = ci[k], j = cj[k];
+    bool amb = false;
+    const PairDec pd = narrow_pair<NW_DD>(S, x, type, i, j, &amb, nullptr, nullptr);
+    if (amb) W.dfr2[atomicAdd(W.n2, 1)] = (int)q;
+    else put_deferred(W, q, type, i, j, pd, false);
+  }
+}
+
+// Pass 4: the second list in exact arithmetic.  XP_TPB threads per
+// work-group, each with an expansion slab in LDS, over contiguous ranges of
+// the list.
+__global__ __launch_bounds__(XP_TPB) void k_exact(SceneDev S, const double* x, const int* ci, const int* cj,
+                                                  const unsigned char* ct, StageWs W) {
+  __shared__ double slab[XP_TPB * XP_WS];
+  const long long n2 = *W.n2;
+  const long long R = (n2 + gridDim.x - 1) / gridDim.x, r0 = blockIdx.x * R, r1 = min(n2, r0 + R);
+  double* ws = slab + threadIdx.x * XP_WS;
+  for (long long r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+    const long long q = W.dfr2[r], k = W.dfr[q];
+    const int type = ct[k], i = ci[k], j = cj[k];
+    bool limit = false;
+    const PairDec pd = narrow_pair<NW_EXACT>(S, x, type, i, j, nullptr, ws, &limit);
+    put_deferred(W, q, type, i, j, pd, limit);
+  }
+}
+
+// Pass 5: counts of the deferred results per contiguous range of the
+// deferred list (range b of XP_BLOCKS into W.xcnt[5b..5b+4]: active, N_c,
+// N_filt, N_infeasible, exceeded).
+__global__ __launch_bounds__(256) void k_dfr_count(StageWs W, int G) {
+  const long long ndef = W.kofs[NW_KINDS * G] - W.kofs[NW_DEFER * G];
+  const long long R = (ndef + gridDim.x - 1) / gridDim.x, q0 = blockIdx.x * R, q1 = min(ndef, q0 + R);
+  int c[5] = {0, 0, 0, 0, 0};
+  for (long long q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
+    const unsigned m = W.sm[q];
+    c[0] += (m >> 24) & 1u;
+    c[1] += (m >> 25) & 1u;
+    c[2] += (m >> 26) & 1u;
+    c[3] += ((m >> 24) & 1u) && (((m >> 16) & 0xffu) & BF_F_INFEASIBLE);
+    c[4] += (m >> 27) & 1u;
+  }
+#pragma unroll
+  for (int t = 0; t < 5; ++t) c[t] = block_sum256(c[t]);
+  if (threadIdx.x < 5) W.xcnt[5 * blockIdx.x + threadIdx.x] = c[threadIdx.x];
+}
+
+// Pass 6: the deferred pairs that are active are appended after the
 // compacted ones, in candidate order: work-group b copies its range's, after
 // the active pairs of all earlier ranges.  Work-group 0 adds the counts and
 // raises the step's overflow and infeasible bits.
@@ -1186,6 +1290,7 @@ __global__ __launch_bounds__(256) void k_exact_emit(StageWs W, int G, int* ai, i
       counters[3] += s[3];
       *act_count = nact;
       status[1] = (unsigned)min(ndef, 0xffffffffll);  // deferred candidates of this step (diagnostics)
+      status[2] = (unsigned)*W.n2;                      // of which decided in exact arithmetic
       unsigned bits = 0;
       if (nact > acap) bits |= BF_S_ACT_OVERFLOW;
       if (counters[3] > 0) bits |= BF_S_INFEASIBLE;
@@ -2602,8 +2707,36 @@ __global__ void k_cc_label(const int* lab, const int* scan, int nv, int* comp) {
 // Minimum reference distance per component over stencil pairs with 0 < dbar < h.
 // Rods: the gap (one double subtraction); shells: dbar^2 in double-double,
 // rounded to double.  Non-negative doubles order like their bit patterns.
+// Under the Euclidean reading (candidates found on the rest pose): dbar^2 of
+// the rest-pose distance in double-double, rounded; a pair whose decision
+// dbar < h double-double leaves open goes to the tie list (k_refmin_tie
+// decides it exactly), and a pair of one component whose primitives touch
+// at rest (dbar^2 <= 1e-12 h^2) sets bit 0 of flags[1].
+__device__ __forceinline__ void refmin_put(unsigned long long* best, int c, unsigned long long key) {
+  // one atomic per wave when every contributing lane has the same component
+  const int first = __ffsll((long long)__ballot(c >= 0)) - 1;
+  const int c0 = __shfl(c, first < 0 ? 0 : first, 64);
+  const bool uniform = __ballot(c >= 0 && c != c0) == 0ull;
+  if (uniform) {
+    unsigned long long mk = key;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      unsigned long long y = __shfl_xor(mk, o, 64);
+      mk = y < mk ? y : mk;
+    }
+    if (lane_id() == 0 && c0 >= 0) atomicMin(&best[c0], mk);
+  } else if (c >= 0) {
+    atomicMin(&best[c], key);
+  }
+}
+__device__ __forceinline__ double rest_sq_dd(const d3* P, int code) {
+  q3 Q[4] = {q3_of(P[0]), q3_of(P[1]), q3_of(P[2]), q3_of(P[3])};
+  const dd q = sqd_case<dd>(code, Q);
+  return q.hi + q.lo;  // round to nearest double
+}
 __global__ __launch_bounds__(256) void k_refmin(SceneDev S, const int* ci, const int* cj, const unsigned char* ct,
-                                                const long long* count, long long cap, unsigned long long* best) {
+                                                const long long* count, long long cap, unsigned long long* best,
+                                                long long* ties, long long tie_cap, unsigned long long* flags) {
   long long n = *count;
   if (n > cap) n = cap;
   const long long n_up = (n + 63) / 64 * 64;  // whole waves iterate together
@@ -2615,7 +2748,22 @@ __global__ __launch_bounds__(256) void k_refmin(SceneDev S, const int* ci, const
       pair_verts(S, ct[k], ci[k], cj[k], v);
       if (S.comp[v[0]] == S.comp[v[2]]) {
         double val = -1.0;
-        if (S.kind == 0) {
+        if (S.refdist == BF_REFDIST_EUCLID_REST) {
+          d3 P[4];
+          const Near nr = rest_near(S, ct[k], v, P);
+          if (!(nr.D > 1e-12 * S.h * S.h)) {
+            atomicOr(&flags[1], 1ull);
+          } else {
+            bool amb = false;
+            const bool below = decide_sq(nr.code, P, nr.D, dd_sq(S.h), true, &amb);
+            if (amb) {
+              const unsigned long long t = atomicAdd(&flags[0], 1ull);
+              if ((long long)t < tie_cap) ties[t] = k;
+            } else if (below) {
+              val = rest_sq_dd(P, nr.code);
+            }
+          }
+        } else if (S.kind == 0) {
           double sa0 = S.ref[v[0]], sa1 = S.ref[v[1]], sb0 = S.ref[v[2]], sb1 = S.ref[v[3]];
           double gap = fmax(fmin(sb0, sb1) - fmax(sa0, sa1), fmin(sa0, sa1) - fmax(sb0, sb1));
           if (gap > 0.0 && gap < S.h) val = gap;
@@ -2629,21 +2777,33 @@ __global__ __launch_bounds__(256) void k_refmin(SceneDev S, const int* ci, const
         }
       }
     }
-    // one atomic per wave when every contributing lane has the same component
-    const int first = __ffsll((long long)__ballot(c >= 0)) - 1;
-    const int c0 = __shfl(c, first < 0 ? 0 : first, 64);
-    const bool uniform = __ballot(c >= 0 && c != c0) == 0ull;
-    if (uniform) {
-      unsigned long long mk = key;
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        unsigned long long y = __shfl_xor(mk, o, 64);
-        mk = y < mk ? y : mk;
-      }
-      if (lane_id() == 0 && c0 >= 0) atomicMin(&best[c0], mk);
-    } else if (c >= 0) {
-      atomicMin(&best[c], key);
-    }
+    refmin_put(best, c, key);
+  }
+}
+
+// The tie list of k_refmin (rest-pose distances within 1e-20 of h): dbar < h
+// decided in exact arithmetic (expansions in an LDS slab per thread, as in
+// k_exact); the pairs below h join the minimum.  Bit 1 of flags[1]: an
+// expansion outgrew its slab.
+__global__ __launch_bounds__(XP_TPB) void k_refmin_tie(SceneDev S, const int* ci, const int* cj,
+                                                       const unsigned char* ct, const long long* ties,
+                                                       long long tie_cap, unsigned long long* flags,
+                                                       unsigned long long* best) {
+  __shared__ double slab[XP_TPB * XP_WS];
+  double* ws = slab + threadIdx.x * XP_WS;
+  long long nt = (long long)flags[0];
+  if (nt > tie_cap) nt = tie_cap;
+  for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < nt; q += (long long)gridDim.x * blockDim.x) {
+    const long long k = ties[q];
+    int v[4];
+    pair_verts(S, ct[k], ci[k], cj[k], v);
+    d3 P[4];
+    const Near nr = rest_near(S, ct[k], v, P);
+    bool limit = false;
+    const bool below = decide_sq_exact(nr.code, P, nr.D, dd_sq(S.h), true, ws, &limit);
+    if (limit) atomicOr(&flags[1], 2ull);
+    else if (below)
+      atomicMin(&best[S.comp[v[0]]], (unsigned long long)__double_as_longlong(rest_sq_dd(P, nr.code)));
   }
 }
 
@@ -2674,6 +2834,16 @@ __global__ void k_zero_ll(long long* a, int n, long long* b, int m) {
   if (b && threadIdx.x < m) b[threadIdx.x] = 0;
 }
 
+__global__ void k_status_take(unsigned* status, unsigned* dst) {
+  if (threadIdx.x == 0) {
+    dst[0] = status[0];
+    status[0] = 0u;
+  }
+}
+void run_status_take(unsigned* status, unsigned* dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_status_take, dim3(1), dim3(64), 0, st, status, dst);
+}
+
 void run_zero_i64(long long* a, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_ll, dim3(1), dim3(64), 0, st, a, n, nullptr, 0);
 }
@@ -2686,12 +2856,16 @@ template <int PQ>
 static void launch_pairs(const SceneDev& S, int nquery, const BroadWs& W, int* oi, int* oj, unsigned char* ot,
                          long long cap, long long* count, unsigned* status, int* seg_r, unsigned* seg_t,
                          long long seg_cap, hipStream_t st) {
+  static_assert(PQ <= PQ_MAX, "pair_cnt, pair_bsum and pair_bseg hold PQ_MAX threads per query");
   int nb = (nquery * PQ + 255) / 256;
   hipLaunchKernelGGL(k_pair_count<PQ>, dim3(nb), dim3(256), 0, st, S, nquery, W.box, W.grid, W.cell_start,
-                     W.sorted_id, W.sorted_box, S.h, W.pair_cnt, W.pair_bsum, W.pair_bseg, W.seg_count, seg_r, seg_t,
+                     W.sorted_id, W.sorted_box, W.sorted_vid, S.h, W.pair_cnt, W.pair_bsum, W.pair_bseg, W.seg_count,
+                     seg_r, seg_t,
                      seg_cap);
+  scan_excl(W.pair_bsum, W.pair_bofs, nullptr, nb + 1, W.scan_tmp, status, st);
   hipLaunchKernelGGL(k_pair_emit<PQ>, dim3(nb), dim3(256), 0, st, S, nquery, W.box, W.grid, W.cell_start,
-                     W.sorted_id, W.sorted_box, S.h, W.pair_cnt, W.pair_bsum, W.pair_bseg, seg_r, seg_t, oi, oj, ot,
+                     W.sorted_id, W.sorted_box, W.sorted_vid, S.h, W.pair_cnt, W.pair_bofs, W.pair_bseg, seg_r, seg_t,
+                     oi, oj, ot,
                      cap, count, status);
 }
 
@@ -2711,12 +2885,13 @@ void run_broad(const SceneDev& S, const double* x, const double* pdisp, const Br
   scan_excl(W.cell_cnt, W.cell_start, nscan_dev, nscan_max, W.scan_tmp, status, st);
   hipLaunchKernelGGL(k_scatter, dim3(nblocks(nstored)), dim3(256), 0, st, nstored, W.box, W.cell_of, W.cell_cnt,
                      W.cell_start, W.placed_id, W.placed_box);
-  hipLaunchKernelGGL(k_cell_order, dim3(nblocks(nstored)), dim3(256), 0, st, nstored, W.cell_of, W.cell_start,
-                     W.placed_id, W.placed_box, W.sorted_id, W.sorted_box);
+  hipLaunchKernelGGL(k_cell_order, dim3(nblocks(nstored)), dim3(256), 0, st, S, nstored, W.cell_of, W.cell_start,
+                     W.placed_id, W.placed_box, W.sorted_id, W.sorted_box, W.sorted_vid);
   // one thread per (query, row subset): no grid-stride here
   switch (S.pq) {
     case 2: launch_pairs<2>(S, nquery, W, oi, oj, ot, cap, count, status, seg_r, seg_t, seg_cap, st); break;
     case 8: launch_pairs<8>(S, nquery, W, oi, oj, ot, cap, count, status, seg_r, seg_t, seg_cap, st); break;
+    case 16: launch_pairs<16>(S, nquery, W, oi, oj, ot, cap, count, status, seg_r, seg_t, seg_cap, st); break;
     default: launch_pairs<4>(S, nquery, W, oi, oj, ot, cap, count, status, seg_r, seg_t, seg_cap, st); break;
   }
 }
@@ -2788,7 +2963,9 @@ void run_compact(const SceneDev& S, const double* x, const int* ci, const int* c
   scan_excl(W.kcnt, W.kofs, nullptr, NW_KINDS * G + 1, W.scan_tmp, status, st);
   hipLaunchKernelGGL(k_compact, dim3(G), dim3(256), 0, st, W, G, ai, aj, at, acode, aflags, adist, acap, act_count,
                      counters, status);
-  hipLaunchKernelGGL(k_exact, dim3(XP_BLOCKS), dim3(XP_TPB), 0, st, S, x, ci, cj, ct, W, G);
+  hipLaunchKernelGGL(k_band, dim3(BAND_BLOCKS), dim3(256), 0, st, S, x, ci, cj, ct, W, G);
+  hipLaunchKernelGGL(k_exact, dim3(XP_BLOCKS), dim3(XP_TPB), 0, st, S, x, ci, cj, ct, W);
+  hipLaunchKernelGGL(k_dfr_count, dim3(XP_BLOCKS), dim3(256), 0, st, W, G);
   hipLaunchKernelGGL(k_exact_emit, dim3(XP_BLOCKS), dim3(256), 0, st, W, G, ai, aj, at, acode, aflags, adist, acap,
                      act_count, counters, status);
 }
@@ -2830,7 +3007,7 @@ void run_asm_values(const SceneDev& S, const int* ai, const int* aj, const unsig
   const unsigned long long* nact = (const unsigned long long*)act_count;
   scan_excl(A.rowcnt, row_ptr, nullptr, S.nv + 1, A.scan_tmp, status, st);
   const int rows_grid = std::max(1, std::min((S.nv + 3) / 4, 1 << 20));  // four rows a block
-  const int mid_grid = std::min(rows_grid, 8192);                          // listed rows, strided
+  const int mid_grid = std::max(1, std::min(S.nv, 1 << 20));  // listed rows: a block each (the rest exit)
   hipLaunchKernelGGL(k_row_b, dim3(mid_grid + rows_grid), dim3(64), 0, st, S, ai, aj, at, A.inc_off, A.inc, A.colbuf,
                      G, H, g, row_ptr, col, val, bsr_cap, nnzb, status, nact, acap, A.epart, E_out, A.mid, mid_grid,
                      A.stn);
@@ -2862,8 +3039,13 @@ int run_components(const SceneDev& S, int* lab, int* flag, int* scan, int* comp,
 }
 
 void run_refmin(const SceneDev& S, const int* ci, const int* cj, const unsigned char* ct, const long long* count,
-                long long cap, unsigned long long* best, hipStream_t st) {
-  hipLaunchKernelGGL(k_refmin, dim3(nblocks(cap)), dim3(256), 0, st, S, ci, cj, ct, count, cap, best);
+                long long cap, unsigned long long* best, long long* ties, long long tie_cap,
+                unsigned long long* flags, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_ll, dim3(1), dim3(64), 0, st, (long long*)flags, 2, nullptr, 0);
+  hipLaunchKernelGGL(k_refmin, dim3(nblocks(cap)), dim3(256), 0, st, S, ci, cj, ct, count, cap, best, ties, tie_cap,
+                     flags);
+  if (S.refdist == BF_REFDIST_EUCLID_REST)
+    hipLaunchKernelGGL(k_refmin_tie, dim3(XP_BLOCKS), dim3(XP_TPB), 0, st, S, ci, cj, ct, ties, tie_cap, flags, best);
 }
 
 }  // namespace bfc

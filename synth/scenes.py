@@ -41,6 +41,11 @@ class Scene:
     kappa: float = 1.0
     seed: int = 0
     meta: dict = field(default_factory=dict)
+    # reference distance: 0 in rest-space parameters (ref), 1 Euclidean at
+    # the rest pose xrest [V,3] (the literal reading of Eq. 1 on the rest
+    # configuration)
+    refdist: int = 0
+    xrest: np.ndarray | None = None
 
     @property
     def n_verts(self) -> int:
@@ -64,8 +69,15 @@ class Scene:
     def with_positions(self, x: np.ndarray) -> "Scene":
         s = Scene(self.name, self.kind, np.ascontiguousarray(x, dtype=np.float64),
                   self.edges, self.tris, self.ref, self.h, self.eta, self.kappa,
-                  self.seed, dict(self.meta))
+                  self.seed, dict(self.meta), self.refdist, self.xrest)
         return s
+
+    def with_euclid_rest(self, xrest: np.ndarray | None = None) -> "Scene":
+        """The same scene under the Euclidean reading of the reference
+        distance, with rest pose xrest (default: the scene's own positions)."""
+        xr = np.ascontiguousarray(self.x if xrest is None else xrest, dtype=np.float64).copy()
+        return Scene(self.name + "_euclid", self.kind, self.x, self.edges, self.tris, self.ref, self.h, self.eta,
+                     self.kappa, self.seed, dict(self.meta), 1, xr)
 
 
 def _smoothstep(t):

@@ -65,3 +65,40 @@ def test_degenerate_rest_primitives_are_refused_without_gpu():
     u2 = [[0, 0], [500, 0], [500, 0], [0, 500]]
     rc, msg = _create(1, 4, [[0, 1], [1, 2], [0, 2], [0, 3], [1, 3]], [[0, 1, 2], [0, 1, 3]], u2)
     assert rc == 6 and b"zero rest length" in msg
+
+
+def _desc_params(sc):
+    import paper_2510_10256_amd as bfc
+    edges = np.ascontiguousarray(sc.edges, np.int32)
+    tris = np.ascontiguousarray(sc.tris, np.int32)
+    ref = np.ascontiguousarray(sc.ref, np.float64)
+    keep = [edges, tris, ref]
+    kind = 0 if sc.kind == "rod" else 1
+    desc = bfc.binding.MeshDesc(kind, sc.n_verts, sc.n_edges, sc.n_tris if kind else 0, edges.ctypes.data,
+                                tris.ctypes.data if kind else None, ref.ctypes.data)
+    prm = bfc.binding.Params(float(sc.h), float(sc.eta), 1.0, 0, 0, 11)
+    return desc, prm, keep
+
+
+def test_workspace_bytes_without_gpu():
+    # the workspace size is counted on the host: it grows with the
+    # capacities and the mesh, and bad arguments are refused
+    import paper_2510_10256_amd as bfc
+    import synth
+    L = bfc.lib()
+    sizes = {}
+    for name, sc in (("rod", synth.helix_loop_rod()), ("cloth", synth.folded_cloth(n=36, gaps=()))):
+        desc, prm, keep = _desc_params(sc)
+        for caps in ((4096, 4096), (65536, 4096), (4096, 65536)):
+            n = ctypes.c_int64(0)
+            assert L.bf_workspace_bytes(ctypes.byref(desc), ctypes.byref(prm), caps[0], caps[1], ctypes.byref(n)) == 0
+            sizes[(name,) + caps] = n.value
+        assert sizes[(name, 65536, 4096)] > sizes[(name, 4096, 4096)]
+        assert sizes[(name, 4096, 65536)] > sizes[(name, 4096, 4096)]
+        # per candidate at least the staging record (ids, code word, distance, deferred index)
+        assert sizes[(name, 65536, 4096)] - sizes[(name, 4096, 4096)] >= (65536 - 4096) * (4 + 4 + 4 + 8 + 8)
+    assert sizes[("cloth", 4096, 4096)] > sizes[("rod", 4096, 4096)]
+    desc, prm, keep = _desc_params(synth.helix_loop_rod())
+    n = ctypes.c_int64(0)
+    assert L.bf_workspace_bytes(ctypes.byref(desc), ctypes.byref(prm), 0, 16, ctypes.byref(n)) == 1
+    assert L.bf_workspace_bytes(ctypes.byref(desc), ctypes.byref(prm), 16, 16, None) == 1

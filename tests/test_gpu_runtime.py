@@ -59,3 +59,71 @@ def test_batch_destroyed_without_a_step_leaves_scenes_usable():
         cs.run(x)  # the scene still steps on its own
         assert cs.counts()["n_act"] > 0
         cs.close()
+
+
+@requires_gpu
+def test_threads_per_query_choices_give_the_same_candidates():
+    # every choice of threads per broad-phase query (2, 4, 8, 16) finds the
+    # same candidate pairs (in another order within a query), and the tuner
+    # picks one of them; the per-thread buffers hold the largest choice
+    import paper_2510_10256_amd as bfc
+    sc = synth.folded_cloth(n=72, gaps=(950.0,), l_mid=4000.0, l_conv=2000.0)
+    cs = bfc.ContactScene(sc, device="cuda:0")
+    x = cs._as_x(sc.x)
+    try:
+        sets = {}
+        for pq in (2, 4, 8, 16):
+            print(f"[pq] {sc.name} V={sc.n_verts} pq={pq}", flush=True)
+            cs.set_pq(pq)
+            st = cs.run(x)
+            assert not (st & bfc.binding.BF_S_CAND_OVERFLOW)
+            n = int(cs.c_n.item())
+            key = (cs.c_t[:n].to(torch.int64) << 62) | (cs.c_i[:n].to(torch.int64) << 31) | cs.c_j[:n].to(torch.int64)
+            sets[pq] = np.sort(key.cpu().numpy())
+            assert len(np.unique(sets[pq])) == n
+        for pq in (2, 8, 16):
+            assert np.array_equal(sets[pq], sets[4]), pq
+        assert cs.tune(x) in (2, 4, 8, 16)
+    finally:
+        cs.close()
+
+
+@requires_gpu
+def test_scene_in_a_caller_workspace():
+    # bf_scene_create_ws carves the scene from a caller's tensor of
+    # bf_workspace_bytes bytes: the step's results are bitwise those of a
+    # scene the library allocates; one byte less is refused, and the scene
+    # cannot grow
+    import ctypes as C
+    import paper_2510_10256_amd as bfc
+    from paper_2510_10256_amd import binding as B
+    sc = synth.folded_cloth(n=48, gaps=(950.0,), l_mid=4000.0, l_conv=2000.0)
+    print(f"[workspace] {sc.name} V={sc.n_verts}", flush=True)
+    ref = bfc.ContactScene(sc, device="cuda:0")
+    x = ref._as_x(sc.x)
+    st = ref.run(x)  # grows its buffers until the step fits
+    assert not (st & (B.BF_S_CAND_OVERFLOW | B.BF_S_ACT_OVERFLOW | B.BF_S_BSR_OVERFLOW))
+    cs = bfc.ContactScene(sc, device="cuda:0", own_workspace=True, cand_cap=ref.cand_cap, act_cap=ref.act_cap,
+                          bsr_cap=ref.bsr_cap)
+    try:
+        cs.step(x)
+        assert cs.status(clear=True) == st
+        a, b = ref.results(), cs.results()
+        assert a["counts"] == b["counts"] and a["E_total"] == b["E_total"]
+        for k in ("g", "row_ptr", "col", "val", "E", "G", "Hpsd", "cand", "i", "j", "flags", "d"):
+            assert np.array_equal(a[k], b[k]), k
+        nbytes = cs.workspace.numel()
+        # the same arguments, one byte short
+        desc = B.MeshDesc(1, sc.n_verts, sc.n_edges, sc.n_tris, cs._edges.ctypes.data, cs._tris.ctypes.data,
+                          cs._ref.ctypes.data)
+        prm = B.Params(cs.h, cs.eta, cs.kappa, 0, 0, 11)
+        h = C.c_void_p()
+        rc = B.lib().bf_scene_create_ws(C.byref(desc), C.byref(prm), cs.cand_cap, cs.act_cap,
+                                        cs.workspace.data_ptr(), nbytes - 256, C.c_void_p(cs._stream()),
+                                        C.byref(h))
+        assert rc == 4 and b"workspace" in B.lib().bf_last_error()
+        assert B.lib().bf_scene_reserve(cs.handle, 2 * cs.cand_cap, cs.act_cap) == 5
+        assert B.lib().bf_scene_reserve(cs.handle, cs.cand_cap, cs.act_cap) == 0
+    finally:
+        cs.close()
+        ref.close()

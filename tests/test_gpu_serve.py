@@ -54,3 +54,62 @@ def test_served_results_equal_alone():
             assert req.counts[k] == oc[k], (req.rid, k)
         compare_assembled(req.E, req.g.numpy(), o, sc.n_verts, kappa=sc.kappa, tau=1e-5)
     server.close()
+
+
+@requires_gpu
+def test_native_server_results_equal_alone_and_the_oracle():
+    # the library's own serving loop (bf_serve_*): scenes created in device
+    # blocks of their own and evicted under a budget below the total; every
+    # result equals the same request run alone, bitwise, and the oracle's
+    import paper_2510_10256_amd as bfc
+    from paper_2510_10256_amd.binding import NativeServer
+    from paper_2510_10256_amd.serve import request_maker, scene_caps
+    import oracle
+    from tests.parity import compare_assembled
+    scenes = [synth.woven_patch(seed=60 + k, n_warp=2 + k % 3, n_weft=3, verts_per_rod=48 + 16 * k)
+              if k % 2 == 0 else synth.folded_cloth(seed=60 + k, n=24 + 8 * k, gaps=()) for k in range(8)]
+    caps = [scene_caps(sc) for sc in scenes]
+    probe = NativeServer(scenes, caps, budget_bytes=1 << 40, slots=1)
+    fp = probe.info()["footprint"]
+    probe.close()
+    budget = int(2.5 * np.median(fp)) + int(fp.max())
+    assert budget < fp.sum()  # not every scene fits at once
+    print(f"[native serve] {len(scenes)} scenes, budget {budget} B of {int(fp.sum())} B", flush=True)
+    sv = NativeServer(scenes, caps, budget_bytes=budget, slots=3)
+    make = request_maker(scenes, seed=98)
+    reqs, done = [], {}
+    pending = []
+    for k in range(40):
+        r = make(k)
+        t = sv.submit(r.sid, r.x, grad=True)
+        reqs.append((t, r))
+        pending.append(t)
+        if len(pending) >= 8:
+            t0 = pending.pop(0)
+            done[t0] = sv.poll(t0, wait=True)
+    for t in pending:
+        done[t] = sv.poll(t, wait=True)
+    info = sv.info()
+    sv.close()
+    assert len(done) == 40 and info["used"] <= budget
+    for t, r in reqs:
+        res = done[t]
+        assert res["error"] == 0 and res["status"] & ~bfc.binding.BF_S_INFEASIBLE == 0, res
+        sc = scenes[r.sid]
+        cand, act, bsr = caps[r.sid]
+        cs = bfc.ContactScene(sc, cand_cap=cand, act_cap=act, bsr_cap=bsr, device="cuda:0")
+        x = torch.tensor(r.x, dtype=torch.float64, device="cuda:0")
+        cs.step(x)
+        st = cs.status(clear=True)
+        a = cs.results()
+        cs.close()
+        assert res["status"] == st
+        assert res["E"] == a["E_total"], (t, res["E"], a["E_total"])
+        for k in ("n_c", "n_filt", "n_act", "n_infeasible", "nnzb"):
+            assert res["counts"][k] == a["counts"][k], (t, k)
+        assert np.array_equal(res["g"], a["g"]), t
+        o = oracle.evaluate(sc, x=r.x, mode=1)
+        oc = oracle.counts(o)
+        for k in ("n_c", "n_filt", "n_act", "n_infeasible"):
+            assert res["counts"][k] == oc[k], (t, k)
+        compare_assembled(res["E"], res["g"], o, sc.n_verts, kappa=sc.kappa, tau=1e-10)
