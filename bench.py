@@ -97,9 +97,14 @@ def parse():
                     help="default: fp64 for one scene, mixed for the batch")
     ap.add_argument("--lanes", type=int, default=0, help="batch: concurrent streams in the graph (0 = four)")
     ap.add_argument("--tune", type=int, default=1, help="tune threads per broad-phase query (per scene)")
-    ap.add_argument("--budget-gib", type=float, default=2.0, help="serve: HBM budget of resident scenes")
+    ap.add_argument("--budget-gib", type=float, default=None,
+                    help="serve: HBM budget; the library's loop counts resident scenes and running steps (default "
+                         "4), the Python loop resident scenes with their buffers (default 2)")
     ap.add_argument("--slots", type=int, default=4, help="serve: requests on the device at once")
     ap.add_argument("--requests", type=int, default=300, help="serve: requests per open-loop run")
+    ap.add_argument("--native-serve", type=int, default=1,
+                    help="serve: 1 runs the requests through the library's serving loop (bf_serve_*); 0 through "
+                         "the Python loop over the four calls")
     ap.add_argument("--graph", type=int, default=-1,
                     help="1: replay the step as a captured HIP graph; 0: eager launches (the assembly's structure "
                          "then overlaps the evaluation on a second stream); -1: time both, report the faster")
@@ -539,6 +544,108 @@ def bench_batch(args):
     print(json.dumps(out))
 
 
+def _native_loop(sv, make, n, inflight, arrivals=None):
+    """Requests through the library's serving loop: closed loop with `inflight`
+    outstanding, or open loop at the given arrival times (s).  Returns the
+    results (latency in ms, submit to completion) and the wall time."""
+    pending, out = {}, []
+    t0 = time.perf_counter()
+    k = 0
+    while k < n or pending:
+        now = time.perf_counter() - t0
+        while k < n and (len(pending) < inflight if arrivals is None else arrivals[k] <= now):
+            r = make(k)
+            pending[sv.submit(r.sid, r.x)] = r
+            k += 1
+        for t in list(pending):
+            res = sv.poll(t, wait=False)
+            if res is not None:
+                pending.pop(t)
+                out.append(res)
+        if arrivals is not None and k < n and not pending:
+            time.sleep(max(0.0, arrivals[k] - (time.perf_counter() - t0)))
+        elif pending:
+            time.sleep(20e-6)
+    return out, time.perf_counter() - t0
+
+
+def bench_serve_native(args):
+    """The serving workload through the library's own loop (bf_serve_*):
+    scenes created in device blocks of their own and evicted under the budget
+    by the library; the same scenes, requests and load sweep as bench_serve."""
+    import synth
+    import paper_2510_10256_amd as bfc
+    from paper_2510_10256_amd import serve
+    from paper_2510_10256_amd.binding import NativeServer
+
+    prec_name = args.prec or "mixed"
+    prec = bfc.BF_FP64 if prec_name == "fp64" else bfc.BF_MIXED
+    scenes = synth.serving_scenes()
+    budget_gib = 4.0 if args.budget_gib is None else args.budget_gib
+    budget = int(budget_gib * (1 << 30))
+    caps = [serve.scene_caps(sc) for sc in scenes]
+    sv = NativeServer(scenes, caps, budget_bytes=budget, slots=args.slots, prec=prec)
+    make = serve.request_maker(scenes, seed=4242)
+    lbar = [serve.mean_edge_length(sc) for sc in scenes]
+
+    def first_touch(k):  # one request per scene: every scene made resident (as far as the budget allows)
+        rng = np.random.default_rng(77 + k)
+        return serve.Request(rid=-1 - k, sid=k, x=scenes[k].x + rng.normal(0.0, 0.01 * lbar[k], scenes[k].x.shape))
+
+    t0 = time.perf_counter()
+    _native_loop(sv, first_touch, len(scenes), 2 * args.slots)  # warm-up: scene creation
+    setup_s = time.perf_counter() - t0
+    ev0 = sv.info()
+    done, wall = _native_loop(sv, lambda k: make(1000 + k), args.requests, 2 * args.slots)
+    sat_rate = len(done) / wall
+    sat_pairs = sum(r["counts"]["n_c"] for r in done) / wall
+    ev1 = sv.info()
+    runs = {}
+    for frac in (0.25, 0.5, 0.75, 0.9):
+        n = args.requests if frac == 0.75 else max(60, args.requests // 3)
+        arr = serve.poisson_arrivals(frac * sat_rate, n, seed=int(frac * 100))
+        e0 = sv.info()
+        d, w = _native_loop(sv, lambda k, f=frac: make(int(f * 1e6) + k), n, 0, arrivals=arr)
+        e1 = sv.info()
+        lat = np.array([r["ms"] for r in d])
+        runs[str(frac)] = {"rate_req_s": frac * sat_rate, "requests": n,
+                           "pairs_per_s": sum(r["counts"]["n_c"] for r in d) / w,
+                           "mean_ms": float(lat.mean()), "p50_ms": float(np.percentile(lat, 50)),
+                           "p99_ms": float(np.percentile(lat, 99)),
+                           "errors": int(sum(r["error"] != 0 for r in d)),
+                           "overflow": int(sum((r["status"] & 0x1b) != 0 for r in d)),
+                           "scenes_created": e1["created"] - e0["created"],
+                           "scenes_evicted": e1["evicted"] - e0["evicted"],
+                           "retries": int(sum(r["retries"] for r in d))}
+    info = sv.info()
+    sv.close()
+    head = runs["0.75"]
+    out = {
+        "metric": "filtered contact pairs evaluated/s (dist+filter+grad+Hessian); p50/p99 latency",
+        "value": head["pairs_per_s"], "unit": "pairs/s",
+        "n_gpus": 1, "steps": head["requests"], "warmup": 32, "ms_per_step": head["mean_ms"],
+        "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded generator)",
+        "config": {"workload": "serve256 through the library's serving loop (bf_serve_*): 256 rod / shell scenes "
+                               "(1:1, lognormal sizes, median 16k primitives), Poisson arrivals at 0.75 of "
+                               f"saturation, HBM budget {budget_gib:g} GiB (resident scenes and running steps), "
+                               f"{args.slots} slots",
+                   "scenes": len(scenes), "primitives": int(sum(sc.n_prims for sc in scenes)),
+                   "budget_bytes": budget, "slots": args.slots, "precision": prec_name,
+                   "resident_at_end": info["resident"], "footprint_median_bytes": int(np.median(info["footprint"]))},
+        "saturation": {"req_per_s": sat_rate, "pairs_per_s": sat_pairs, "requests": len(done),
+                       "scenes_created": ev1["created"] - ev0["created"]},
+        "sweep": runs,
+        "setup_s": setup_s,
+        "scenes_created": info["created"], "scenes_evicted": info["evicted"], "overflow_reruns": info["retried"],
+        "peak_bytes_in_use": info["peak_bytes"], "largest_step_bytes": int(info["step"].max()),
+        "resident_bytes_all_scenes": int(info["footprint"].sum()),
+        "roofline": None,
+    }
+    print(json.dumps(out))
+
+
 def bench_serve(args):
     """Serving loop: 256 resident rod / shell scenes (lognormal sizes), Poisson
     arrivals, admission by HBM budget; p50/p99 latency and pairs/s at 0.75 of
@@ -551,7 +658,8 @@ def bench_serve(args):
     prec_name = args.prec or "mixed"
     prec = bfc.BF_FP64 if prec_name == "fp64" else bfc.BF_MIXED
     scenes = synth.serving_scenes()
-    budget = int(args.budget_gib * (1 << 30))
+    budget_gib = 2.0 if args.budget_gib is None else args.budget_gib
+    budget = int(budget_gib * (1 << 30))
     server = serve.Server(scenes, budget_bytes=budget, slots=args.slots, prec=prec)
     make = serve.request_maker(scenes, seed=4242)
     t0 = time.perf_counter()
@@ -580,7 +688,7 @@ def bench_serve(args):
         "data": "synthetic (seeded generator)",
         "config": {"workload": "serve256: 256 resident rod / shell scenes (1:1, lognormal sizes, median 16k "
                                "primitives), Poisson arrivals at 0.75 of saturation, HBM budget "
-                               f"{args.budget_gib:g} GiB, {args.slots} slots",
+                               f"{budget_gib:g} GiB, {args.slots} slots",
                    "scenes": len(scenes), "primitives": int(sum(sc.n_prims for sc in scenes)),
                    "budget_bytes": budget, "slots": args.slots, "precision": prec_name},
         "saturation": {"req_per_s": sat_rate, "pairs_per_s": sat_pairs, "requests": len(done)},
@@ -622,7 +730,7 @@ def main():
     if args.workload == "batch64":
         return bench_batch(args)
     if args.workload == "serve256":
-        return bench_serve(args)
+        return bench_serve_native(args) if args.native_serve else bench_serve(args)
     import torch
     import synth
     import paper_2510_10256_amd as bfc

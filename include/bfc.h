@@ -419,20 +419,25 @@ bf_status bf_batch_destroy(bf_batch* b);
 /* ---- serving: requests for many registered scenes ---------------------
  * A server keeps the registered scenes' host data (copied at start) and runs
  * requests (a scene and its positions) with a worker thread of its own.
- * Admission takes requests in arrival order; one whose scene is busy or
- * does not fit the budget yet may be passed by later ones, at most
- * max_bypass times, after which it blocks those behind it.  A scene that is
- * not resident is created in one device block of its own (bf_workspace_bytes
- * plus the buffers of its step, as bf_serve_info reports), after idle
- * resident scenes are destroyed, least recently used first, to keep the
- * resident total within budget_bytes.  At most one request per scene is on
- * the device at a time; up to `slots` requests run at once, each on a
- * stream of its own.  A request runs the whole path (build_candidates,
+ * All its device memory is one block of budget_bytes, allocated at start.
+ * A resident scene holds in it only what persists between its steps
+ * (topology, rest data and filter precompute, broad-phase workspace: its
+ * footprint, bf_serve_info); a request on the device holds, while it runs,
+ * a block with its step's workspaces and buffers.  Admission takes requests
+ * in arrival order: one starts when a slot is free, its scene is idle and
+ * its scene (if not resident) and its step fit, room being made by
+ * destroying idle resident scenes, least recently used first; one that
+ * cannot start while a slot is free lets later ones pass in at most
+ * max_bypass admission passes, after which it blocks those behind it.  At most one request per scene is on the
+ * device at a time.  A request runs the whole path (build_candidates,
  * filter_pairs, eval_barrier, assemble_grad_hess) and completes when its
  * results are in host memory: energy, counters, the step's status word
- * (read and cleared) and, if g_h was given, the gradient written to g_h.  No
- * capacity is grown: an overflow shows in the status bits, with the counts
- * holding the sizes required. */
+ * (read and cleared) and, if g_h was given, the gradient written to g_h.  A
+ * step whose buffers overflowed runs again with the scene's capacities grown
+ * to the sizes it reported, up to four times while the scene and its step
+ * fit the budget; an overflow left after that shows in the status bits.  A
+ * request whose scene and step exceed the budget completes with
+ * BF_E_CAPACITY. */
 typedef struct bf_server bf_server;
 typedef struct {
   int32_t n_scenes;
@@ -441,7 +446,8 @@ typedef struct {
   const int64_t* cand_cap;     /* [n_scenes] capacities of each scene's step */
   const int64_t* act_cap;      /* [n_scenes] */
   const int64_t* bsr_cap;      /* [n_scenes] BSR blocks */
-  int64_t budget_bytes;        /* device memory for resident scenes (each alone must fit) */
+  int64_t budget_bytes;        /* all device memory of the server: resident scenes and running steps (each
+                                  scene with one step must fit) */
   int32_t slots;               /* requests on the device at once, 1..64 */
   int32_t max_bypass;          /* >= 0 */
   int32_t device;              /* HIP device of the server */
@@ -455,8 +461,10 @@ typedef struct {
   int64_t counts[5]; /* N_c, N_filt, N_act, N_infeasible, BSR blocks */
   int64_t n_bp;      /* candidates of the broad phase */
   double ms;         /* submit to completion, host clock */
+  int32_t retries;   /* runs again after a capacity overflow (the scene's capacities grown to the sizes
+                        its counters reported; at most four) */
 } bf_serve_result;
-/* Start a server (device memory is allocated as scenes become resident). */
+/* Start a server (allocates the budget's device block). */
 bf_status bf_serve_start(const bf_serve_config* cfg, bf_server** out);
 /* Queue a request: x_h [V,3] positions of the scene's vertices (copied
  * before return); g_h [V,3] (host, may be NULL) receives the gradient and
@@ -465,9 +473,13 @@ bf_status bf_serve_submit(bf_server* sv, int32_t scene, const double* x_h, doubl
 /* State of a request (wait != 0: block until it completes).  A completed
  * request's ticket is released by the poll that reports it. */
 bf_status bf_serve_poll(bf_server* sv, int64_t ticket, int32_t wait, bf_serve_result* out);
-/* Resident scenes, device bytes they hold, and (footprint_h[n_scenes], may
- * be NULL) each scene's device footprint when resident. */
-bf_status bf_serve_info(bf_server* sv, int32_t* resident_h, int64_t* used_bytes_h, int64_t* footprint_h);
+/* Resident scenes, bytes of the budget in use (resident scenes and running
+ * steps), (sizes_h[n_scenes, 2], may be NULL) each scene's footprint when
+ * resident and the block its step takes (at its current capacities), and
+ * (events_h[4], may be NULL) the scene creations, evictions and overflow
+ * re-runs since start, then the most bytes in use at once. */
+bf_status bf_serve_info(bf_server* sv, int32_t* resident_h, int64_t* used_bytes_h, int64_t* sizes_h,
+                        int64_t* events_h);
 /* Finish every queued request, destroy the resident scenes, free all. */
 bf_status bf_serve_stop(bf_server* sv);
 

@@ -89,7 +89,8 @@ class ServeConfig(C.Structure):
 
 class ServeResult(C.Structure):
     _fields_ = [("done", C.c_int32), ("scene", C.c_int32), ("error", C.c_int32), ("status", C.c_uint32),
-                ("E", C.c_double), ("counts", C.c_int64 * 5), ("n_bp", C.c_int64), ("ms", C.c_double)]
+                ("E", C.c_double), ("counts", C.c_int64 * 5), ("n_bp", C.c_int64), ("ms", C.c_double),
+                ("retries", C.c_int32)]
 
 
 class Pairs(C.Structure):
@@ -140,7 +141,7 @@ def lib():
         L.bf_serve_start.argtypes = [C.POINTER(ServeConfig), C.POINTER(P)]
         L.bf_serve_submit.argtypes = [P, C.c_int32, P, P, C.POINTER(C.c_int64)]
         L.bf_serve_poll.argtypes = [P, C.c_int64, C.c_int32, C.POINTER(ServeResult)]
-        L.bf_serve_info.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_int64), P]
+        L.bf_serve_info.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_int64), P, P]
         L.bf_serve_stop.argtypes = [P]
         L.bf_scene_reserve.argtypes = [P, C.c_int64, C.c_int64]
         L.bf_scene_destroy.argtypes = [P]
@@ -653,7 +654,7 @@ class NativeServer:
         _check(lib().bf_serve_poll(self.handle, int(ticket), int(bool(wait)), C.byref(r)), "bf_serve_poll")
         if not r.done:
             return None
-        out = dict(scene=r.scene, error=r.error, status=r.status, E=r.E, n_bp=r.n_bp, ms=r.ms,
+        out = dict(scene=r.scene, error=r.error, status=r.status, E=r.E, n_bp=r.n_bp, ms=r.ms, retries=r.retries,
                    counts=dict(n_c=r.counts[0], n_filt=r.counts[1], n_act=r.counts[2], n_infeasible=r.counts[3],
                                nnzb=r.counts[4]))
         g = self._grads.pop(ticket, None)
@@ -663,9 +664,13 @@ class NativeServer:
 
     def info(self):
         n, used = C.c_int32(0), C.c_int64(0)
-        fp = np.zeros(len(self.nv), np.int64)
-        _check(lib().bf_serve_info(self.handle, C.byref(n), C.byref(used), fp.ctypes.data), "bf_serve_info")
-        return dict(resident=int(n.value), used=int(used.value), footprint=fp)
+        sz = np.zeros((len(self.nv), 2), np.int64)
+        ev = np.zeros(4, np.int64)
+        _check(lib().bf_serve_info(self.handle, C.byref(n), C.byref(used), sz.ctypes.data, ev.ctypes.data),
+               "bf_serve_info")
+        return dict(resident=int(n.value), used=int(used.value), footprint=sz[:, 0].copy(), step=sz[:, 1].copy(),
+                    created=int(ev[0]),
+                    evicted=int(ev[1]), retried=int(ev[2]), peak_bytes=int(ev[3]))
 
     def close(self):
         if getattr(self, "handle", None):

@@ -49,6 +49,7 @@ struct bf_scene {
   std::vector<void*> stage_allocs;  // narrow-phase staging (regrown by reserve)
   int pq = 4;                       // threads per broad-phase query (tunable)
   bool in_ws = false;                // scene memory carved from the caller's workspace (bf_scene_create_ws)
+  bool shared_step = false;          // no step workspaces of its own: bound per request (serving loop)
   hipStream_t last = nullptr;
   // eval_barrier runs the structural part of the assembly on `side`, beside
   // the evaluation kernel; assemble_grad_hess then only adds the values
@@ -181,7 +182,7 @@ bf_status alloc_asm_ws(const bf_scene* s, long long act_cap, std::vector<void*>&
   if (hipMemsetAsync(A.inc_cnt, 0, sizeof(int) * (s->nv + 1), g_alloc_stream) != hipSuccess ||
       hipMemsetAsync(A.scan_tmp, 0, sizeof(int) * SCAN_LB_STATE, g_alloc_stream) != hipSuccess ||
       hipMemsetAsync(A.rowcnt, 0, sizeof(int) * (s->nv + 1), g_alloc_stream) != hipSuccess ||
-      hipStreamSynchronize(g_alloc_stream) != hipSuccess)
+      (!g_arena && hipStreamSynchronize(g_alloc_stream) != hipSuccess))  // a workspace: stream order suffices
     return fail(BF_E_DEVICE, who);
   *out = A;
   return BF_OK;
@@ -255,7 +256,7 @@ bf_status alloc_stage(bf_scene* s, long long cand_cap) {
   W.cap = G * NW_TILE;
   if (sizing_only()) return BF_OK;
   if (hipMemsetAsync(W.scan_tmp, 0, sizeof(int) * SCAN_LB_STATE, g_alloc_stream) != hipSuccess ||
-      hipStreamSynchronize(g_alloc_stream) != hipSuccess)
+      (!g_arena && hipStreamSynchronize(g_alloc_stream) != hipSuccess))
     return fail(BF_E_DEVICE, "bf_scene_reserve: clearing the scan state failed");
   W.cap = G * NW_TILE;
   s->sw = W;
@@ -362,6 +363,7 @@ bf_status alloc_persistent(bf_scene* s, long long cand_cap, long long act_cap) {
     return fail(g_arena ? BF_E_CAPACITY : BF_E_NOMEM,
                 g_arena ? "bf_scene_create_ws: workspace smaller than bf_workspace_bytes"
                         : "bf_scene_create: device allocation failed");
+  if (s->shared_step) return BF_OK;
   bf_status r = alloc_asm(s, act_cap);
   if (r == BF_OK) r = alloc_stage(s, cand_cap);
   return r;
@@ -415,7 +417,8 @@ static bf_status check_scene_args(const bf_mesh_desc* mesh, const bf_params* par
 }
 
 static bf_status create_scene(const bf_mesh_desc* mesh, const bf_params* params, int64_t cand_cap,
-                              int64_t act_cap, void* stream, Arena* arena, bf_scene** out) {
+                              int64_t act_cap, void* stream, Arena* arena, bf_scene** out,
+                              bool shared_step = false) {
   if (!out) return fail(BF_E_ARG, "bf_scene_create: null argument");
   *out = nullptr;
   if (bf_status r = check_scene_args(mesh, params, cand_cap, act_cap); r != BF_OK) return r;
@@ -433,6 +436,7 @@ static bf_status create_scene(const bf_mesh_desc* mesh, const bf_params* params,
   const bool euclid = params->refdist == BF_REFDIST_EUCLID_REST;
   const int nref = s->kind == BF_ROD ? nv : 2 * nv;
   s->in_ws = arena != nullptr;
+  s->shared_step = shared_step;
   g_arena = arena;
   const bf_status ra = alloc_persistent(s, cand_cap, act_cap);
   g_arena = nullptr;
@@ -1047,6 +1051,78 @@ bf_status bfc_status_take(bf_scene* s, uint32_t* dst_d, void* stream) {
   return he == hipSuccess ? BF_OK : fail_hip(he, "bf_serve: status");
 }
 bf_status bfc_fail(bf_status code, const char* msg) { return fail(code, msg); }
+
+// Scenes whose step workspaces (narrow-phase staging, assembly) are lent per
+// request from a pool, so that only their persistent part stays resident.
+// bfc_scene_bytes_shared: the persistent bytes (as bf_workspace_bytes);
+// bfc_step_bytes: the bytes of the step workspaces for nv vertices and the
+// given capacities; bfc_scene_create_shared: bf_scene_create_ws without step
+// workspaces; bfc_scene_bind_step: carve them for this scene from ws_d
+// (clearing, on the stream, what the step expects at zero).
+bf_status bfc_scene_bytes_shared(const bf_mesh_desc* mesh, const bf_params* params, int64_t* bytes_h) {
+  if (!bytes_h) return fail(BF_E_ARG, "bf_serve: null argument");
+  if (bf_status r = check_scene_args(mesh, params, 1, 1); r != BF_OK) return r;
+  bf_scene probe;
+  probe.prm = *params;
+  probe.kind = mesh->kind;
+  probe.nv = (int)mesh->n_verts;
+  probe.ne = (int)mesh->n_edges;
+  probe.nt = mesh->kind == BF_SHELL ? (int)mesh->n_tris : 0;
+  probe.shared_step = true;
+  Arena a;
+  g_arena = &a;
+  const bf_status r = alloc_persistent(&probe, 1, 1);
+  g_arena = nullptr;
+  if (r != BF_OK) return r;
+  *bytes_h = (int64_t)a.off + 255;
+  return BF_OK;
+}
+
+bf_status bfc_step_bytes(int64_t nv, int64_t cand_cap, int64_t act_cap, int64_t* bytes_h) {
+  if (!bytes_h || nv < 1 || cand_cap < 1 || act_cap < 1) return fail(BF_E_ARG, "bf_serve: bad argument");
+  bf_scene probe;
+  probe.nv = (int)nv;
+  Arena a;
+  g_arena = &a;
+  bf_status r = alloc_asm(&probe, act_cap);
+  if (r == BF_OK) r = alloc_stage(&probe, cand_cap);
+  g_arena = nullptr;
+  if (r != BF_OK) return r;
+  *bytes_h = (int64_t)a.off + 255;
+  return BF_OK;
+}
+
+bf_status bfc_scene_create_shared(const bf_mesh_desc* mesh, const bf_params* params, int64_t cand_cap,
+                                  void* ws_d, int64_t ws_bytes, void* stream, bf_scene** out) {
+  if (!ws_d || ws_bytes < 1) return fail(BF_E_ARG, "bf_serve: null or empty workspace");
+  const uintptr_t b0 = (uintptr_t)ws_d, b1 = (b0 + 255) & ~(uintptr_t)255;
+  if ((int64_t)(b1 - b0) >= ws_bytes) return fail(BF_E_CAPACITY, "bf_serve: workspace too small");
+  Arena a;
+  a.base = (char*)b1;
+  a.cap = (size_t)(ws_bytes - (int64_t)(b1 - b0));
+  return create_scene(mesh, params, std::max<int64_t>(cand_cap, 1), 1, stream, &a, out, true);
+}
+
+bf_status bfc_scene_bind_step(bf_scene* s, void* ws_d, int64_t ws_bytes, int64_t cand_cap, int64_t act_cap,
+                              void* stream) {
+  if (!s || !s->shared_step || !ws_d) return fail(BF_E_ARG, "bf_serve: bad step binding");
+  const uintptr_t b0 = (uintptr_t)ws_d, b1 = (b0 + 255) & ~(uintptr_t)255;
+  Arena a;
+  a.base = (char*)b1;
+  a.cap = (size_t)(ws_bytes - (int64_t)(b1 - b0));
+  g_arena = &a;
+  g_alloc_stream = (hipStream_t)stream;
+  AsmWs A{};
+  bf_status r = alloc_asm_ws(s, act_cap, s->asm_allocs, &A, "bf_serve: step workspace");
+  if (r == BF_OK) {
+    s->aw = A;
+    s->act_cap = act_cap;
+    r = alloc_stage(s, cand_cap);
+  }
+  g_arena = nullptr;
+  s->prepared = false;
+  return r;
+}
 
 extern "C" {
 

@@ -42,21 +42,23 @@ BFC_HD bool eig_all(bool p) {
 // Plane rotation that maps (x, z) to (r, 0): c = x / r, s = z / r,
 // r = |(x, z)|, from one reciprocal square root (a square root and a
 // division per rotation lengthen the dependent chain of a QR step).
-BFC_HD void eig_givens(double x, double z, double& c, double& s, double& r) {
-  const double q = x * x + z * z;
-  if (q > 0.0) {
+template <class T> BFC_HD void eig_givens(T x, T z, T& c, T& s, T& r) {
+  const T q = x * x + z * z;
+  if (q > T(0)) {
 #if defined(__HIP_DEVICE_COMPILE__)
-    const double ir = rsqrt(q);
+    T ir;
+    if constexpr (sizeof(T) == 4) ir = rsqrtf(q);
+    else ir = rsqrt(q);
 #else
-    const double ir = 1.0 / sqrt(q);
+    const T ir = T(1) / sqrt(q);
 #endif
     c = x * ir;
     s = z * ir;
     r = q * ir;
   } else {
-    c = 1.0;
-    s = 0.0;
-    r = 0.0;
+    c = T(1);
+    s = T(0);
+    r = T(0);
   }
 }
 
@@ -69,33 +71,33 @@ BFC_HD void eig_givens(double x, double z, double& c, double& s, double& r) {
 // columns of Z (N x N, row-major) one row at a time (each element sees the
 // same operations in the same order as rotation by rotation; a row in flight
 // at a time keeps the live set small).
-template <int N, int L> BFC_HD void eig_qr_step(double* d, double* e, double (*Z)[N], int p) {
-  const double dl = 0.5 * (d[L - 1] - d[L]);
-  const double b2 = e[L - 1] * e[L - 1];
-  const double rt = sqrt(dl * dl + b2);
-  const double den = dl >= 0.0 ? dl + rt : dl - rt;
-  const double mu = den != 0.0 ? d[L] - b2 / den : d[L];
-  double x = 0.0, z = 0.0;
-  double cr[L], sr[L];
+template <int N, int L, class T> BFC_HD void eig_qr_step(T* d, T* e, T (*Z)[N], int p) {
+  const T dl = T(0.5) * (d[L - 1] - d[L]);
+  const T b2 = e[L - 1] * e[L - 1];
+  const T rt = sqrt(dl * dl + b2);
+  const T den = dl >= T(0) ? dl + rt : dl - rt;
+  const T mu = den != T(0) ? d[L] - b2 / den : d[L];
+  T x = T(0), z = T(0);
+  T cr[L], sr[L];
 #pragma unroll
   for (int k = 0; k < L; ++k) {
     if (k == p) {
       x = d[k] - mu;
       z = e[k];
     }
-    double c, s, r;
+    T c, s, r;
     eig_givens(x, z, c, s, r);
     if (k < p) {
-      c = 1.0;
-      s = 0.0;
+      c = T(1);
+      s = T(0);
     }
     cr[k] = c;
     sr[k] = s;
     if (k > p) e[k - 1] = r;
-    const double a = d[k], b = e[k], cc = d[k + 1];
-    const double c2 = c * c, s2 = s * s, cs = c * s;
-    d[k] = c2 * a + 2.0 * cs * b + s2 * cc;
-    d[k + 1] = s2 * a - 2.0 * cs * b + c2 * cc;
+    const T a = d[k], b = e[k], cc = d[k + 1];
+    const T c2 = c * c, s2 = s * s, cs = c * s;
+    d[k] = c2 * a + T(2) * cs * b + s2 * cc;
+    d[k + 1] = s2 * a - T(2) * cs * b + c2 * cc;
     e[k] = cs * (cc - a) + (c2 - s2) * b;
     if (k + 1 < L) {
       z = s * e[k + 1];
@@ -105,10 +107,10 @@ template <int N, int L> BFC_HD void eig_qr_step(double* d, double* e, double (*Z
   }
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    double zk = Z[i][0];
+    T zk = Z[i][0];
 #pragma unroll
     for (int k = 0; k < L; ++k) {
-      const double zk1 = Z[i][k + 1];
+      const T zk1 = Z[i][k + 1];
       Z[i][k] = cr[k] * zk + sr[k] * zk1;
       zk = cr[k] * zk1 - sr[k] * zk;
     }
@@ -121,7 +123,7 @@ template <int N, int L> BFC_HD void eig_qr_step(double* d, double* e, double (*Z
 // Before each step, off-diagonal entries at or below lim inside the block are
 // set to zero and the block starts after the last of them.  Returns false on
 // a lane whose stage hit the step limit (its projection is then not exact).
-template <int N, int L> BFC_HD bool eig_stages(double* d, double* e, double (*Z)[N], double lim) {
+template <int N, int L, class T> BFC_HD bool eig_stages(T* d, T* e, T (*Z)[N], T lim) {
   if constexpr (L >= 1) {
     bool ok = true;
     int it = 0;
@@ -133,15 +135,15 @@ template <int N, int L> BFC_HD bool eig_stages(double* d, double* e, double (*Z)
 #pragma unroll
         for (int k = 0; k + 1 < L; ++k)
           if (!(fabs(e[k]) > lim)) {
-            e[k] = 0.0;
+            e[k] = T(0);
             p = k + 1;
           }
-        eig_qr_step<N, L>(d, e, Z, p);
+        eig_qr_step<N, L, T>(d, e, Z, p);
       }
     }
     if (it == 48 && fabs(e[L - 1]) > lim) ok = false;
-    e[L - 1] = 0.0;
-    return eig_stages<N, L - 1>(d, e, Z, lim) && ok;
+    e[L - 1] = T(0);
+    return eig_stages<N, L - 1, T>(d, e, Z, lim) && ok;
   }
   return true;
 }
@@ -149,46 +151,51 @@ template <int N, int L> BFC_HD bool eig_stages(double* d, double* e, double (*Z)
 // A: upper triangle of the symmetric N x N input (destroyed); P: upper
 // triangle of A+.  tol: relative size (to |A|) below which an off-diagonal
 // element of the tridiagonal counts as zero.  Returns false when a deflation
-// stage did not converge within its step limit.
+// stage did not converge within its step limit.  T = float expects A scaled
+// to a largest entry of 1.
 //
 // Live data is kept small so that the whole projection stays in registers:
 // the reduction stores its reflectors in the entries of A it zeroes (Z is not
 // carried through it), Z is formed from them afterwards, and A+ is built row
 // by row while the rows of Z that are no longer needed die.
-template <int N> BFC_HD bool psd_project(double* A, double* P, double tol) {
+template <int N, class T = double> BFC_HD bool psd_project(T* A, T* P, T tol) {
   // Householder reduction: step k zeroes entries k+2.. of row k and keeps
   // v[k+2..] there, v[k+1] in vh[k] and 2 / (v^T v) in bh[k] (0: identity)
-  double vh[N > 2 ? N - 2 : 1], bh[N > 2 ? N - 2 : 1];
+  T vh[N > 2 ? N - 2 : 1], bh[N > 2 ? N - 2 : 1];
 #pragma unroll
   for (int k = 0; k < N - 2; ++k) {
-    double v[N];
-    double sig = 0.0;
+    T v[N];
+    T sig = T(0);
 #pragma unroll
     for (int j = k + 2; j < N; ++j) sig += A[eig_uix<N>(k, j)] * A[eig_uix<N>(k, j)];
-    const double x0 = A[eig_uix<N>(k, k + 1)];
-    vh[k] = 0.0;
-    bh[k] = 0.0;
-    if (!(sig > 0.0)) continue;  // already tridiagonal in this row (the same on every lane of typical input)
-    const double nrm = sqrt(x0 * x0 + sig);
-    const double alpha = x0 >= 0.0 ? -nrm : nrm;
-    const double beta = 1.0 / (alpha * (alpha - x0));  // 2 / (v^T v)
+    const T x0 = A[eig_uix<N>(k, k + 1)];
+    vh[k] = T(0);
+    bh[k] = T(0);
+    // already tridiagonal in this row (the same on every lane of typical
+    // input).  In single precision (inputs scaled to a largest entry of 1) a
+    // row whose remaining entries are below 1e-15 counts as reduced too: a
+    // reflector for it would need 1 / |v|^2 beyond the float range.
+    if (!(sig > (sizeof(T) == 4 ? T(1e-30) : T(0)))) continue;
+    const T nrm = sqrt(x0 * x0 + sig);
+    const T alpha = x0 >= T(0) ? -nrm : nrm;
+    const T beta = T(1) / (alpha * (alpha - x0));  // 2 / (v^T v)
 #pragma unroll
-    for (int j = 0; j < N; ++j) v[j] = 0.0;
+    for (int j = 0; j < N; ++j) v[j] = T(0);
     v[k + 1] = x0 - alpha;
 #pragma unroll
     for (int j = k + 2; j < N; ++j) v[j] = A[eig_uix<N>(k, j)];
     // p = beta A_sub v, w = p - (beta/2)(v^T p) v on indices k+1..N-1
-    double p[N];
-    double vp = 0.0;
+    T p[N];
+    T vp = T(0);
 #pragma unroll
     for (int i = k + 1; i < N; ++i) {
-      double acc = 0.0;
+      T acc = T(0);
 #pragma unroll
       for (int j = k + 1; j < N; ++j) acc += A[eig_uix<N>(i, j)] * v[j];
       p[i] = beta * acc;
       vp += v[i] * p[i];
     }
-    const double kk = 0.5 * beta * vp;
+    const T kk = T(0.5) * beta * vp;
 #pragma unroll
     for (int i = k + 1; i < N; ++i) p[i] -= kk * v[i];
 #pragma unroll
@@ -199,31 +206,31 @@ template <int N> BFC_HD bool psd_project(double* A, double* P, double tol) {
     vh[k] = v[k + 1];
     bh[k] = beta;  // v[k+2..] stay in row k of A
   }
-  double d[N], e[N];
-  double anorm = 0.0;
+  T d[N], e[N];
+  T anorm = T(0);
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     d[i] = A[eig_uix<N>(i, i)];
-    e[i] = i + 1 < N ? A[eig_uix<N>(i, i + 1)] : 0.0;
+    e[i] = i + 1 < N ? A[eig_uix<N>(i, i + 1)] : T(0);
   }
 #pragma unroll
-  for (int i = 0; i < N; ++i) anorm = fmax(anorm, fabs(d[i]) + fabs(e[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0));
+  for (int i = 0; i < N; ++i) anorm = fmax(anorm, fabs(d[i]) + fabs(e[i]) + (i > 0 ? fabs(e[i - 1]) : T(0)));
   // Z = H_0 H_1 ... H_{N-3}, accumulated from the last reflector (H_k acts on
   // indices k+1..N-1, where the product so far is still the identity outside)
-  double Z[N][N];
+  T Z[N][N];
 #pragma unroll
   for (int i = 0; i < N; ++i)
 #pragma unroll
-    for (int j = 0; j < N; ++j) Z[i][j] = i == j ? 1.0 : 0.0;
+    for (int j = 0; j < N; ++j) Z[i][j] = i == j ? T(1) : T(0);
 #pragma unroll
   for (int k = N - 3; k >= 0; --k) {
-    double v[N];
+    T v[N];
     v[k + 1] = vh[k];
 #pragma unroll
     for (int j = k + 2; j < N; ++j) v[j] = A[eig_uix<N>(k, j)];
 #pragma unroll
     for (int j = k + 1; j < N; ++j) {
-      double w = 0.0;
+      T w = T(0);
 #pragma unroll
       for (int i = k + 1; i < N; ++i) w += v[i] * Z[i][j];
       w *= bh[k];
@@ -231,18 +238,18 @@ template <int N> BFC_HD bool psd_project(double* A, double* P, double tol) {
       for (int i = k + 1; i < N; ++i) Z[i][j] -= w * v[i];
     }
   }
-  const bool ok = eig_stages<N, N - 1>(d, e, Z, tol * anorm);
-  double lam[N];
+  const bool ok = eig_stages<N, N - 1, T>(d, e, Z, tol * anorm);
+  T lam[N];
 #pragma unroll
-  for (int k = 0; k < N; ++k) lam[k] = fmax(d[k], 0.0);
+  for (int k = 0; k < N; ++k) lam[k] = fmax(d[k], T(0));
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    double zl[N];
+    T zl[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) zl[k] = Z[i][k] * lam[k];
 #pragma unroll
     for (int j = i; j < N; ++j) {
-      double acc = 0.0;
+      T acc = T(0);
 #pragma unroll
       for (int k = 0; k < N; ++k) acc += zl[k] * Z[j][k];
       P[eig_uix<N>(i, j)] = acc;

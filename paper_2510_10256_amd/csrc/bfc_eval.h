@@ -111,10 +111,46 @@ __device__ __forceinline__ void eval_pp(const d3* P, int s0, int s1, double a, d
   h.A[5] = 1.0 / D;
 }
 
+// Projection of the reduced system A (upper triangle, N x N) into P.  FP64:
+// psd_project in double.  FP32 (the mixed mode): A is scaled by its largest
+// entry (the projection commutes with a positive scale, and the scale keeps
+// FP32 away from overflow and underflow), projected in float with QR
+// iterations that stop at 1e-6 of |A|, and scaled back; the FP32 arithmetic
+// and the stopping rule each leave errors of order 1e-6 |A|.
+template <int N, bool FP32>
+__device__ __forceinline__ bool project_reduced(double* A, double* P, double tol) {
+  constexpr int M = N * (N + 1) / 2;
+  if constexpr (FP32) {
+    double amax = 0.0;
+#pragma unroll
+    for (int k = 0; k < M; ++k) amax = fmax(amax, fabs(A[k]));
+    if (!(amax > 0.0) || !(amax <= 1.7e308)) {  // zero, or not finite: the FP64 path decides
+      return psd_project<N>(A, P, tol);
+    }
+    const double sc = 1.0 / amax;
+    float Af[M], Pf[M];
+    // entries below 1e-18 of the largest go to zero: their squares would be
+    // FP32 denormals, which the device flushes (a Householder norm of zero
+    // with a nonzero pivot), and they are far below the tolerance
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const double y = A[k] * sc;
+      Af[k] = fabs(y) < 1e-18 ? 0.0f : (float)y;
+    }
+    const bool ok = psd_project<N, float>(Af, Pf, 1e-6f);
+#pragma unroll
+    for (int k = 0; k < M; ++k) P[k] = (double)Pf[k] * amax;
+    return ok;
+  } else {
+    return psd_project<N>(A, P, tol);
+  }
+}
+
 // ---- PE: 6 x 6 reduced system ----------------------------------------------
 // Orthonormal basis of the translation complement of slots (p, e0, e1):
 // w1 = (1, -1, 0)/sqrt2, w2 = (1, 1, -2)/sqrt6.  With y = (r, e) = Y x the
 // coupling b = Y W is [[sqrt2, 0], [1/sqrt2, -3/sqrt6]].
+template <bool FP32>
 __device__ __forceinline__ void eval_pe(const d3* P, int sp, int se0, int se1, double a, double eta,
                                         double kappa, double tol, double* G, PairOut& h) {
   const double S2 = 1.4142135623730951, IS2 = 0.70710678118654752, IS6 = 0.40824829046386302;
@@ -175,7 +211,7 @@ __device__ __forceinline__ void eval_pe(const d3* P, int sp, int se0, int se1, d
     G[3 * se0 + i] = -grx - gex;
     G[3 * se1 + i] = gex;
   }
-  h.eig_ok = psd_project<6>(A, h.A, tol);
+  h.eig_ok = project_reduced<6, FP32>(A, h.A, tol);
   h.kind = H_PE;
   h.sl[0] = sp;
   h.sl[1] = se0;
@@ -188,6 +224,7 @@ __device__ __forceinline__ void eval_pe(const d3* P, int sp, int se0, int se1, d
 // Couplings b = Y W (rows r, u, v):
 //   PT (r = p-t0, u = t1-t0, v = t2-t0):  r (0,1,1)  u (-1,1,0)  v (-1,0,1)
 //   EE (r = a0-b0, u = a1-a0, v = b1-b0): r (1,0,1)  u (0,-1,-1) v (0,-1,1)
+template <bool FP32>
 __device__ __forceinline__ void eval_tri(const d3* P, bool is_pt, double a, double eta, double kappa, double tol,
                                          double* G, PairOut& h) {
   d3 r, u, v;
@@ -281,7 +318,7 @@ __device__ __forceinline__ void eval_tri(const d3* P, bool is_pt, double a, doub
       G[9 + i] = gv;
     }
   }
-  h.eig_ok = psd_project<9>(A, h.A, tol);
+  h.eig_ok = project_reduced<9, FP32>(A, h.A, tol);
   h.kind = H_TRI;
 }
 
@@ -344,24 +381,24 @@ template <int I> __device__ __forceinline__ void hess_row(const PairOut& h, doub
 }
 
 // Evaluate one active pair with the sub-case `code` fixed by the narrow
-// phase.  MIXED: the projection's QR iteration stops once the tridiagonal's
-// off-diagonal is below 1e-8 of |H| instead of FP64 rounding (2.2e-16).
-// Distances, derivative terms and the projection arithmetic stay FP64 on both
-// paths: FP32 derivative terms lose up to 1e-2 relative accuracy for nearly
-// parallel edges (successive turns of a coiled rod).
+// phase.  MIXED: the PSD projection of the reduced system runs in FP32
+// (project_reduced); distances, energy, gradient and the Hessian before the
+// projection stay FP64 on both paths (FP32 derivative terms lose up to 1e-2
+// relative accuracy for nearly parallel edges, successive turns of a coiled
+// rod).
 template <bool MIXED>
 __device__ __forceinline__ void eval_pair(const d3* P, int code, double a, double eta, double kappa, double* G,
                                           PairOut& h) {
-  const double tol = MIXED ? 1e-8 : 2.2e-16;
+  const double tol = 2.2e-16;
   int kind = case_kind(code);
   if (kind == K_PT || kind == K_EE) {
-    eval_tri(P, kind == K_PT, a, eta, kappa, tol, G, h);
+    eval_tri<MIXED>(P, kind == K_PT, a, eta, kappa, tol, G, h);
     return;
   }
   int s0, s1, s2;
   case_slots(code, s0, s1, s2);
   if (kind == K_PP) eval_pp(P, s0, s1, a, eta, kappa, G, h);
-  else eval_pe(P, s0, s1, s2, a, eta, kappa, tol, G, h);
+  else eval_pe<MIXED>(P, s0, s1, s2, a, eta, kappa, tol, G, h);
 }
 
 }  // namespace bfc

@@ -1510,7 +1510,7 @@ constexpr int ROW_L = 32;
 constexpr int ROW_M = 256;
 constexpr int ROW_M_TAB = 4 * ROW_M;  // hash slots: at least the row's 4m candidate columns (tables
                                       // take pow2(4m + 1) slots up to this: always room for every key)
-constexpr int ROW_H = 2048;
+constexpr int ROW_H = 1024;            // 20 KiB of LDS: eight blocks a CU, so a few thousand such rows run at once
 constexpr int ROW_H_TAB = 4 * ROW_H;
 constexpr int EMPTY = -1;
 constexpr int PAD = 0x7fffffff;
@@ -2114,8 +2114,8 @@ __global__ __launch_bounds__(256) void k_row_b_big(SceneDev S, const int* ai, co
                                                    const double* G, const double* H, double* g, const int* row_ptr,
                                                    int* col, double* val, long long cap, const int* big,
                                                    const int4* stn) {
-  __shared__ int vs[4 * 128];
-  __shared__ double band[128 * 36];
+  __shared__ int vs[4 * 64];
+  __shared__ double band[64 * 36];
   __shared__ double gw[12];
   const int nbig = big[S.nv];
   for (int r = blockIdx.x; r < nbig; r += gridDim.x) {
@@ -2123,7 +2123,7 @@ __global__ __launch_bounds__(256) void k_row_b_big(SceneDev S, const int* ai, co
     const int b = inc_off[v], m = inc_off[v + 1] - b;
     const int r0 = row_ptr[v], r1 = row_ptr[v + 1];
     if (r1 > cap) continue;  // uniform across the block
-    row_b<256, 128>(S, ai, aj, at, inc, b, m, colbuf + 4LL * b, r0, r1 - r0, G, H, g + 3LL * v, col, val, vs, band,
+    row_b<256, 64>(S, ai, aj, at, inc, b, m, colbuf + 4LL * b, r0, r1 - r0, G, H, g + 3LL * v, col, val, vs, band,
                     gw, stn);
   }
 }
@@ -2981,7 +2981,9 @@ void run_eval(const SceneDev& S, const double* x, const int* ai, const int* aj, 
                        aflags, (const unsigned long long*)act_count, acap, E, G, H, epart);
 }
 
-static inline int big_grid_of(int nv) { return std::max(1, std::min(nv, 1024)); }  // list entries strided over these
+// the big rows' lists are strided over these blocks: enough for a block per
+// row on the workloads (a few thousand big rows), the rest exit at once
+static inline int big_grid_of(int nv) { return std::max(1, std::min(nv, 4096)); }
 
 void run_asm_structure(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,
                        const unsigned char* aflags, const long long* act_count, long long acap, const AsmWs& A,

@@ -2,15 +2,16 @@
 // many registered scenes, each a whole step (the four calls of the path) at
 // positions the host sends.
 //
-// A worker thread owns the device side.  Admission takes queued requests in
-// arrival order; a request whose scene is busy, or whose scene does not fit
-// the device-memory budget yet, may be passed by later ones, at most
-// max_bypass times (then it blocks the requests behind it).  A scene that is
-// not resident is created in one device block of its own (the scene
-// workspace of bf_workspace_bytes plus the buffers of its step) after idle
-// resident scenes are evicted, least recently used first.  Admitted requests
-// run on `slots` streams at once; a request completes when its energy,
-// counters, status word and (if asked for) gradient are back in host memory.
+// A worker thread owns the device side.  All device memory of the server is
+// one block of the budget's size, divided by the admission policy (a heap
+// over the block, bfc_admit.h): a resident scene holds only what persists
+// between its steps (topology, rest data and filter precompute, broad-phase
+// workspace), and a request on the device holds, for its duration, a step
+// block with everything else (narrow-phase staging, assembly workspace,
+// candidate and active lists, per-pair results, BSR, positions, gradient),
+// bound to its scene for the request.  Admitted requests run on `slots`
+// streams at once; a request completes when its energy, counters, status
+// word and (if asked for) gradient are back in host memory.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,11 +25,18 @@
 #include <vector>
 
 #include "bfc.h"
+#include "bfc_admit.h"
 
 // from bfc_api.hip: copy the scene's status word to dst (device) and clear
-// it, in stream order
+// it, in stream order; scenes whose step workspaces are lent per request
 bf_status bfc_status_take(bf_scene* s, uint32_t* dst_d, void* stream);
 bf_status bfc_fail(bf_status code, const char* msg);
+bf_status bfc_scene_bytes_shared(const bf_mesh_desc* mesh, const bf_params* params, int64_t* bytes_h);
+bf_status bfc_step_bytes(int64_t nv, int64_t cand_cap, int64_t act_cap, int64_t* bytes_h);
+bf_status bfc_scene_create_shared(const bf_mesh_desc* mesh, const bf_params* params, int64_t cand_cap,
+                                  void* ws_d, int64_t ws_bytes, void* stream, bf_scene** out);
+bf_status bfc_scene_bind_step(bf_scene* s, void* ws_d, int64_t ws_bytes, int64_t cand_cap, int64_t act_cap,
+                              void* stream);
 
 namespace {
 
@@ -44,25 +52,25 @@ struct ScenePin {  // results of one request, copied back in one piece
   uint32_t status;
 };
 
-struct Reg {  // a registered scene
+struct Reg {  // a registered scene (its residency is the admission policy's)
   std::vector<int32_t> edges, tris;
   std::vector<double> ref, ref_pos;
   bf_mesh_desc mesh{};
   bf_params prm{};
   int64_t cand_cap = 0, act_cap = 0, bsr_cap = 0;
-  int64_t ws_bytes = 0, io_bytes = 0;
-  // resident state
+  int64_t ws_bytes = 0;                  // resident (persistent) part
+  int64_t step_bytes = 0, io_bytes = 0;  // a step's workspaces, then its buffers
   bf_scene* scene = nullptr;
-  char* mem = nullptr;
+};
+
+// The step buffers of one request, carved from its step block.
+struct StepIO {
   bf_pairs cand{};
   bf_active act{};
   bf_local loc{};
   bf_bsr bsr{};
   double *x_d = nullptr, *E_d = nullptr, *g_d = nullptr;
   uint32_t* st_d = nullptr;
-  bool busy = false;
-  uint64_t last_use = 0;
-  int64_t footprint() const { return ws_bytes + io_bytes; }
 };
 
 struct Req {
@@ -71,6 +79,7 @@ struct Req {
   std::vector<double> x;
   double* g_h = nullptr;
   int bypassed = 0;
+  int retries = 0;
   Clock::time_point t0;
   bf_serve_result res{};
 };
@@ -78,24 +87,27 @@ struct Req {
 struct Slot {
   hipStream_t st = nullptr;
   hipEvent_t ev = nullptr;
+  StepIO io{};
   double* x_pin = nullptr;
   double* g_pin = nullptr;
   ScenePin* r_pin = nullptr;
   Req* req = nullptr;
 };
 
+struct Dev;
+
 }  // namespace
 
 struct bf_server {
   int device = 0;
-  int64_t budget = 0, used = 0;
-  int max_bypass = 8;
+  char* base = nullptr;  // the budget's device block
   std::vector<Reg> regs;
   std::vector<Slot> slots;
+  bfc::Admission<Req, Dev> adm;
   std::deque<Req*> queue;
   std::unordered_map<int64_t, Req*> tickets;
   int64_t next_ticket = 1;
-  uint64_t clock = 0;
+  int64_t retried = 0;  // overflow re-runs so far
   bool stopping = false;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -105,7 +117,8 @@ struct bf_server {
 
 namespace {
 
-// The buffers of one scene's step, carved after its workspace.
+// The buffers of one scene's step, carved from its step block after the step
+// workspaces.
 int64_t io_bytes_of(const Reg& r) {
   const int64_t V = r.mesh.n_verts, C = r.cand_cap, A = r.act_cap, B = r.bsr_cap;
   size_t n = 0;
@@ -119,12 +132,12 @@ int64_t io_bytes_of(const Reg& r) {
   return (int64_t)up256(n);
 }
 
-void carve_io(Reg& r) {
-  const int64_t V = r.mesh.n_verts, C = r.cand_cap, A = r.act_cap, B = r.bsr_cap;
-  size_t off = (size_t)r.ws_bytes;
+void carve_io(const Reg& reg, char* base, StepIO& r) {
+  const int64_t V = reg.mesh.n_verts, C = reg.cand_cap, A = reg.act_cap, B = reg.bsr_cap;
+  size_t off = 0;
   auto take = [&](size_t bytes) {
     off = up256(off);
-    char* p = r.mem + off;
+    char* p = base + off;
     off += bytes;
     return (void*)p;
   };
@@ -157,45 +170,57 @@ void carve_io(Reg& r) {
   r.st_d = (uint32_t*)take(4);
 }
 
-void evict(bf_server* sv, Reg& r) {
-  if (r.scene) (void)bf_scene_destroy(r.scene);
-  if (r.mem) (void)hipFree(r.mem);  // the scene is idle: its last request has completed
-  r.scene = nullptr;
-  r.mem = nullptr;
-  sv->used -= r.footprint();
-}
+void launch(bf_server* sv, int k, Req* q);
 
-bf_status make_resident(bf_server* sv, Reg& r) {
-  hipError_t he = hipMalloc((void**)&r.mem, (size_t)r.footprint());
-  if (he != hipSuccess) {
-    r.mem = nullptr;
-    return bfc_fail(BF_E_NOMEM, "bf_serve: scene allocation failed");
+// The device side of the admission policy.  create runs with the lock
+// released (a scene's creation synchronises its own stream; submitters and
+// pollers go on meanwhile).
+struct Dev {
+  bf_server* sv;
+  std::unique_lock<std::mutex>* lk;
+  bool create(int k, int64_t off) {
+    Reg& r = sv->regs[k];
+    lk->unlock();
+    const bf_status st =
+        bfc_scene_create_shared(&r.mesh, &r.prm, r.cand_cap, sv->base + off, r.ws_bytes, sv->create_st, &r.scene);
+    lk->lock();
+    if (st != BF_OK) r.scene = nullptr;
+    return st == BF_OK;
   }
-  bf_status st = bf_scene_create_ws(&r.mesh, &r.prm, r.cand_cap, r.act_cap, r.mem, r.ws_bytes, sv->create_st,
-                                    &r.scene);
-  if (st != BF_OK) {
-    (void)hipFree(r.mem);
-    r.mem = nullptr;
+  void destroy(int k) {  // the scene is idle: its last request has completed
+    Reg& r = sv->regs[k];
+    (void)bf_scene_destroy(r.scene);
     r.scene = nullptr;
-    return st;
   }
-  carve_io(r);
-  sv->used += r.footprint();
-  return BF_OK;
-}
+  void start(Req* q, int k) { launch(sv, k, q); }
+  void reject(Req* q, bool too_big) {
+    q->res.error = too_big ? bfc_fail(BF_E_CAPACITY, "bf_serve: the scene and its step are above the budget")
+                           : bfc_fail(BF_E_NOMEM, "bf_serve: scene creation failed");
+    q->res.retries = q->retries;
+    q->res.ms = std::chrono::duration<double, std::milli>(Clock::now() - q->t0).count();
+    q->res.done = 1;
+    sv->cv_done.notify_all();
+  }
+};
 
-void launch(bf_server* sv, Slot& sl, Req* q) {
-  Reg& r = sv->regs[q->scene];
-  const int64_t V = r.mesh.n_verts;
+void launch(bf_server* sv, int k, Req* q) {
+  Slot& sl = sv->slots[k];
+  Reg& reg = sv->regs[q->scene];
+  char* blk = sv->base + sv->adm.slots[k].off;  // step workspaces, then the step's buffers
+  const int64_t V = reg.mesh.n_verts;
   std::memcpy(sl.x_pin, q->x.data(), sizeof(double) * 3 * V);
-  bf_status st = BF_OK;
-  hipError_t he = hipMemcpyAsync(r.x_d, sl.x_pin, sizeof(double) * 3 * V, hipMemcpyHostToDevice, sl.st);
-  if (he != hipSuccess) st = bfc_fail(BF_E_DEVICE, "bf_serve: upload");
-  if (st == BF_OK) st = build_candidates(r.scene, r.x_d, &r.cand, sl.st);
-  if (st == BF_OK) st = filter_pairs(r.scene, r.x_d, &r.cand, &r.act, sl.st);
-  if (st == BF_OK) st = eval_barrier(r.scene, r.x_d, &r.act, &r.loc, sl.st);
-  if (st == BF_OK) st = assemble_grad_hess(r.scene, &r.act, &r.loc, r.E_d, r.g_d, &r.bsr, sl.st);
-  if (st == BF_OK) st = bfc_status_take(r.scene, r.st_d, sl.st);
+  hipError_t he = hipSuccess;
+  StepIO& r = sl.io;
+  carve_io(reg, blk + reg.step_bytes, r);
+  bf_status st = bfc_scene_bind_step(reg.scene, blk, reg.step_bytes, reg.cand_cap, reg.act_cap, sl.st);
+  if (st == BF_OK && (he = hipMemcpyAsync(r.x_d, sl.x_pin, sizeof(double) * 3 * V, hipMemcpyHostToDevice, sl.st)) !=
+                         hipSuccess)
+    st = bfc_fail(BF_E_DEVICE, "bf_serve: upload");
+  if (st == BF_OK) st = build_candidates(reg.scene, r.x_d, &r.cand, sl.st);
+  if (st == BF_OK) st = filter_pairs(reg.scene, r.x_d, &r.cand, &r.act, sl.st);
+  if (st == BF_OK) st = eval_barrier(reg.scene, r.x_d, &r.act, &r.loc, sl.st);
+  if (st == BF_OK) st = assemble_grad_hess(reg.scene, &r.act, &r.loc, r.E_d, r.g_d, &r.bsr, sl.st);
+  if (st == BF_OK) st = bfc_status_take(reg.scene, r.st_d, sl.st);
   ScenePin* rp = sl.r_pin;
   if (st == BF_OK &&
       ((he = hipMemcpyAsync(&rp->E, r.E_d, 8, hipMemcpyDeviceToHost, sl.st)) != hipSuccess ||
@@ -206,79 +231,72 @@ void launch(bf_server* sv, Slot& sl, Req* q) {
        (q->g_h && (he = hipMemcpyAsync(sl.g_pin, r.g_d, sizeof(double) * 3 * V, hipMemcpyDeviceToHost, sl.st)) !=
                       hipSuccess)))
     st = bfc_fail(BF_E_DEVICE, "bf_serve: result copy");
-  if (st == BF_OK && hipEventRecord(sl.ev, sl.st) != hipSuccess) st = bfc_fail(BF_E_DEVICE, "bf_serve: event");
+  // the event marks the end of everything enqueued, also after a failed call,
+  // so that the step block is released only once the stream is past it
+  if (hipEventRecord(sl.ev, sl.st) != hipSuccess) {
+    if (st == BF_OK) st = bfc_fail(BF_E_DEVICE, "bf_serve: event");
+    (void)hipStreamSynchronize(sl.st);
+  }
   q->res.error = st;
-  r.busy = true;
-  r.last_use = ++sv->clock;
   sl.req = q;
 }
 
-// A request leaves its slot: results into its record (caller's gradient
-// too), the scene becomes idle.
-void finish(bf_server* sv, Slot& sl) {
+// Capacities that fit the sizes a step reported (its counters hold the
+// sizes required), with an eighth to spare.  After an active-list overflow
+// the block count is that of the pairs kept, a lower bound: the BSR grows
+// by it now and by the full count if the next run overflows it.
+bool grow_caps(Reg& r, const ScenePin& rp) {
+  const uint32_t over = rp.status & (BF_S_CAND_OVERFLOW | BF_S_ACT_OVERFLOW | BF_S_BSR_OVERFLOW);
+  if (!over) return false;
+  // a count that does not show the overflow (not expected) doubles the capacity
+  auto grow = [](int64_t& cap, int64_t n, bool flagged) {
+    if (n > cap) cap = n + n / 8 + 1024;
+    else if (flagged) cap *= 2;
+  };
+  grow(r.cand_cap, rp.n_bp, over & BF_S_CAND_OVERFLOW);
+  grow(r.act_cap, rp.counters[2], over & BF_S_ACT_OVERFLOW);
+  grow(r.bsr_cap, rp.nnzb, over & BF_S_BSR_OVERFLOW);
+  int64_t sb = 0;
+  if (bfc_step_bytes(r.mesh.n_verts, r.cand_cap, r.act_cap, &sb) != BF_OK) return false;
+  r.step_bytes = (int64_t)up256((size_t)sb);
+  r.io_bytes = io_bytes_of(r);
+  return true;
+}
+
+// A request leaves its slot: its step block is released, results go into
+// its record (the caller's gradient too), the scene becomes idle.  A step
+// whose buffers overflowed runs again (at the head of the queue) with the
+// capacities it reported, up to four times, while the scene and the larger
+// step still fit the budget.
+void finish(bf_server* sv, int k) {
+  Slot& sl = sv->slots[k];
   Req* q = sl.req;
   Reg& r = sv->regs[q->scene];
+  sv->adm.done(k, q->scene);
+  sl.req = nullptr;
   if (q->res.error == BF_OK) {
     const ScenePin* rp = sl.r_pin;
+    if (q->retries < 4 && grow_caps(r, *rp)) {
+      bfc::AdmitScene& a = sv->adm.sc[q->scene];
+      a.need = r.step_bytes + r.io_bytes;
+      sv->adm.update_limit();
+      if (bfc::Heap::round(a.fp) + bfc::Heap::round(a.need) <= sv->adm.heap.size()) {
+        ++q->retries;
+        ++sv->retried;
+        sv->queue.push_front(q);
+        return;
+      }
+    }
     q->res.E = rp->E;
-    for (int k = 0; k < 4; ++k) q->res.counts[k] = rp->counters[k];
+    for (int c = 0; c < 4; ++c) q->res.counts[c] = rp->counters[c];
     q->res.counts[4] = rp->nnzb;
     q->res.n_bp = rp->n_bp;
     q->res.status = rp->status;
     if (q->g_h) std::memcpy(q->g_h, sl.g_pin, sizeof(double) * 3 * r.mesh.n_verts);
   }
+  q->res.retries = q->retries;
   q->res.ms = std::chrono::duration<double, std::milli>(Clock::now() - q->t0).count();
   q->res.done = 1;
-  r.busy = false;
-  sl.req = nullptr;
-}
-
-// Start what can start now (arrival order, bypass bound, budget).
-void admit(bf_server* sv, std::unique_lock<std::mutex>& lk) {
-  std::deque<Req*> kept;
-  bool blocked = false;
-  while (!sv->queue.empty()) {
-    Req* q = sv->queue.front();
-    sv->queue.pop_front();
-    int free_slot = -1;
-    for (size_t k = 0; k < sv->slots.size(); ++k)
-      if (!sv->slots[k].req) { free_slot = (int)k; break; }
-    Reg& r = sv->regs[q->scene];
-    if (blocked || free_slot < 0 || r.busy) {
-      if (!blocked && free_slot >= 0) ++q->bypassed;
-      blocked = blocked || q->bypassed > sv->max_bypass;
-      kept.push_back(q);
-      continue;
-    }
-    if (!r.scene) {
-      // room: evict idle scenes, least recently used first
-      while (sv->used + r.footprint() > sv->budget) {
-        Reg* lru = nullptr;
-        for (Reg& o : sv->regs)
-          if (o.scene && !o.busy && (!lru || o.last_use < lru->last_use)) lru = &o;
-        if (!lru) break;
-        evict(sv, *lru);
-      }
-      if (sv->used + r.footprint() > sv->budget) {  // the busy scenes hold the memory: wait
-        ++q->bypassed;
-        blocked = blocked || q->bypassed > sv->max_bypass;
-        kept.push_back(q);
-        continue;
-      }
-      lk.unlock();  // creation synchronises its own stream; submitters may go on meanwhile
-      const bf_status st = make_resident(sv, r);
-      lk.lock();
-      if (st != BF_OK) {
-        q->res.error = st;
-        q->res.ms = std::chrono::duration<double, std::milli>(Clock::now() - q->t0).count();
-        q->res.done = 1;
-        sv->cv_done.notify_all();
-        continue;
-      }
-    }
-    launch(sv, sv->slots[free_slot], q);
-  }
-  sv->queue = std::move(kept);
 }
 
 void work(bf_server* sv) {
@@ -291,11 +309,14 @@ void work(bf_server* sv) {
       const hipError_t e = hipEventQuery(sl.ev);
       if (e == hipErrorNotReady) continue;
       if (e != hipSuccess && sl.req->res.error == BF_OK) sl.req->res.error = BF_E_DEVICE;
-      finish(sv, sl);
+      finish(sv, (int)(&sl - sv->slots.data()));
       any_done = true;
     }
     if (any_done) sv->cv_done.notify_all();
-    if (!sv->queue.empty()) admit(sv, lk);
+    if (!sv->queue.empty()) {
+      Dev dev{sv, &lk};
+      sv->adm.pass(dev, sv->queue);
+    }
     bool active = false;
     for (Slot& sl : sv->slots) active = active || sl.req;
     if (sv->stopping && sv->queue.empty() && !active) break;
@@ -317,9 +338,10 @@ bf_status bf_serve_start(const bf_serve_config* cfg, bf_server** out) {
   if (hipSetDevice(cfg->device) != hipSuccess) return bfc_fail(BF_E_DEVICE, "bf_serve_start: device");
   bf_server* sv = new bf_server;
   sv->device = cfg->device;
-  sv->budget = cfg->budget_bytes;
-  sv->max_bypass = cfg->max_bypass;
+  sv->adm.heap.reset(cfg->budget_bytes);
+  sv->adm.max_bypass = cfg->max_bypass;
   sv->regs.resize(cfg->n_scenes);
+  sv->adm.sc.resize(cfg->n_scenes);
   int64_t vmax = 0;
   for (int k = 0; k < cfg->n_scenes; ++k) {
     const bf_mesh_desc& m = cfg->meshes[k];
@@ -345,20 +367,32 @@ bf_status bf_serve_start(const bf_serve_config* cfg, bf_server** out) {
       delete sv;
       return bfc_fail(BF_E_ARG, "bf_serve_start: BSR capacity must be >= 1");
     }
-    const bf_status st = bf_workspace_bytes(&r.mesh, &r.prm, r.cand_cap, r.act_cap, &r.ws_bytes);
+    bf_status st = bfc_scene_bytes_shared(&r.mesh, &r.prm, &r.ws_bytes);
+    if (st == BF_OK) st = bfc_step_bytes(m.n_verts, r.cand_cap, r.act_cap, &r.step_bytes);
     if (st != BF_OK) {
       delete sv;
       return st;
     }
     r.ws_bytes = (int64_t)up256((size_t)r.ws_bytes);
+    r.step_bytes = (int64_t)up256((size_t)r.step_bytes);
     r.io_bytes = io_bytes_of(r);
-    if (r.footprint() > sv->budget) {
+    bfc::AdmitScene& a = sv->adm.sc[k];
+    a.fp = r.ws_bytes;
+    a.need = r.step_bytes + r.io_bytes;
+    if (bfc::Heap::round(a.fp) + bfc::Heap::round(a.need) > sv->adm.heap.size()) {
       delete sv;
-      return bfc_fail(BF_E_CAPACITY, "bf_serve_start: a scene alone is above the budget");
+      return bfc_fail(BF_E_CAPACITY, "bf_serve_start: a scene and its step are above the budget");
     }
     vmax = std::max<int64_t>(vmax, m.n_verts);
   }
   sv->slots.resize(cfg->slots);
+  sv->adm.slots.resize(cfg->slots);
+  sv->adm.update_limit();
+  if (hipMalloc((void**)&sv->base, (size_t)sv->adm.heap.size()) != hipSuccess) {
+    sv->base = nullptr;
+    delete sv;
+    return bfc_fail(BF_E_NOMEM, "bf_serve_start: the budget's device block");
+  }
   bool ok = hipStreamCreateWithFlags(&sv->create_st, hipStreamNonBlocking) == hipSuccess;
   for (Slot& sl : sv->slots) {
     ok = ok && hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking) == hipSuccess;
@@ -426,7 +460,7 @@ bf_status bf_serve_stop(bf_server* sv) {
   if (sv->worker.joinable()) sv->worker.join();
   (void)hipSetDevice(sv->device);
   for (Reg& r : sv->regs)
-    if (r.scene) evict(sv, r);
+    if (r.scene) (void)bf_scene_destroy(r.scene);  // idle: the worker has drained every request
   for (Slot& sl : sv->slots) {
     if (sl.ev) (void)hipEventDestroy(sl.ev);
     if (sl.st) (void)hipStreamDestroy(sl.st);
@@ -434,22 +468,33 @@ bf_status bf_serve_stop(bf_server* sv) {
     if (sl.g_pin) (void)hipHostFree(sl.g_pin);
     if (sl.r_pin) (void)hipHostFree(sl.r_pin);
   }
+  if (sv->base) (void)hipFree(sv->base);
   if (sv->create_st) (void)hipStreamDestroy(sv->create_st);
   for (auto& kv : sv->tickets) delete kv.second;
   delete sv;
   return BF_OK;
 }
 
-bf_status bf_serve_info(bf_server* sv, int32_t* resident_h, int64_t* used_bytes_h, int64_t* footprint_h) {
+bf_status bf_serve_info(bf_server* sv, int32_t* resident_h, int64_t* used_bytes_h, int64_t* sizes_h,
+                        int64_t* events_h) {
   if (!sv) return bfc_fail(BF_E_ARG, "bf_serve_info: null server");
   std::lock_guard<std::mutex> g(sv->mu);
   int n = 0;
   for (size_t k = 0; k < sv->regs.size(); ++k) {
-    n += sv->regs[k].scene != nullptr;
-    if (footprint_h) footprint_h[k] = sv->regs[k].footprint();
+    n += sv->adm.sc[k].off >= 0;
+    if (sizes_h) {
+      sizes_h[2 * k] = sv->adm.sc[k].fp;
+      sizes_h[2 * k + 1] = sv->adm.sc[k].need;
+    }
   }
   if (resident_h) *resident_h = n;
-  if (used_bytes_h) *used_bytes_h = sv->used;
+  if (used_bytes_h) *used_bytes_h = sv->adm.heap.used();
+  if (events_h) {
+    events_h[0] = sv->adm.created;
+    events_h[1] = sv->adm.evicted;
+    events_h[2] = sv->retried;
+    events_h[3] = sv->adm.heap.peak();
+  }
   return BF_OK;
 }
 

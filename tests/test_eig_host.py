@@ -158,3 +158,63 @@ def test_pair_hessians_of_the_workloads(exe):
             ref = _reference(mats)
             err = np.linalg.norm(got - ref, axis=(1, 2)) / (np.linalg.norm(mats, axis=(1, 2)) + 1e-300)
             assert err.max() < 1e-13, (sc.name, err.max())
+
+
+@pytest.mark.parametrize("n", [6, 9])
+def test_single_precision_projection_of_the_mixed_mode(exe, n):
+    # the mixed mode's projection (scaled to the largest entry, FP32, QR steps
+    # stopping at 1e-6 of |A|) against LAPACK: within a few 1e-6 of |A| on the
+    # random, degenerate and split cases, and exactly zero on the zero matrix
+    rng = np.random.default_rng(17 + n)
+    mats = np.concatenate([_cases(n, rng), _split_cases(n, rng)])
+    got = _project(exe, mats, tol=-1.0)
+    ref = _reference(mats)
+    scale = np.linalg.norm(mats, axis=(1, 2)) + 1e-300
+    err = np.linalg.norm(got - ref, axis=(1, 2)) / scale
+    assert err.max() < 5e-6, (err.max(), int(err.argmax()))
+    assert err.max() > 1e-9  # it is the single-precision path
+    zero = np.all(mats == 0.0, axis=(1, 2))
+    assert zero.any() and np.all(got[zero] == 0.0)
+
+
+def test_single_precision_projection_with_tiny_entries(exe):
+    # entries spanning far more decades than FP32 holds (pairs whose Hessian
+    # has a stiff direction and tiny couplings): no NaN, and within the bound
+    rng = np.random.default_rng(23)
+    mats = []
+    for _ in range(200):
+        B = rng.normal(size=(9, 9))
+        A = B + B.T
+        A[0, :] *= 1e-25
+        A[:, 0] *= 1e-25
+        A[4, 5] = A[5, 4] = 1e-30
+        A *= 10.0 ** rng.uniform(-20, 20)
+        mats.append(A)
+    mats = np.array(mats)
+    got = _project(exe, mats, tol=-1.0)
+    ref = _reference(mats)
+    assert np.all(np.isfinite(got))
+    err = np.linalg.norm(got - ref, axis=(1, 2)) / np.linalg.norm(mats, axis=(1, 2))
+    assert err.max() < 5e-6, err.max()
+
+
+def test_single_precision_projection_on_pair_hessians(exe):
+    # the reduced Hessians of the small cloth's active pairs (entries span
+    # some thirty decades), with denormals kept and with them flushed as on
+    # the device: all finite and within the bound
+    import oracle
+    import synth
+    W4 = 0.5 * np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], float)
+    sc = synth.folded_cloth(n=72, gaps=(950.0,), l_mid=4000.0, l_conv=2000.0)
+    r = oracle.evaluate(sc, mode=1, derivs=True)
+    act = ((r["flags"] & 2) != 0) & ((r["flags"] & 4) == 0)
+    H, codes = r["Hraw"][act], r["code"][act]
+    tri = (codes == 6) | (codes == 15)
+    Wf = np.kron(W4, np.eye(3))
+    mats = np.einsum("ia,nij,jb->nab", Wf, H[tri], Wf)
+    ref = _reference(mats)
+    for flush in (-1.0, -2.0):
+        got = _project(exe, mats, tol=flush)
+        assert np.all(np.isfinite(got)), flush
+        err = np.linalg.norm(got - ref, axis=(1, 2)) / (np.linalg.norm(mats, axis=(1, 2)) + 1e-300)
+        assert err.max() < 5e-6, (flush, err.max())

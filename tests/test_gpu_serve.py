@@ -63,24 +63,34 @@ def test_native_server_results_equal_alone_and_the_oracle():
     # result equals the same request run alone, bitwise, and the oracle's
     import paper_2510_10256_amd as bfc
     from paper_2510_10256_amd.binding import NativeServer
-    from paper_2510_10256_amd.serve import request_maker, scene_caps
+    from paper_2510_10256_amd.serve import Request, mean_edge_length, request_maker, scene_caps
     import oracle
     from tests.parity import compare_assembled
     scenes = [synth.woven_patch(seed=60 + k, n_warp=2 + k % 3, n_weft=3, verts_per_rod=48 + 16 * k)
               if k % 2 == 0 else synth.folded_cloth(seed=60 + k, n=24 + 8 * k, gaps=()) for k in range(8)]
     caps = [scene_caps(sc) for sc in scenes]
-    probe = NativeServer(scenes, caps, budget_bytes=1 << 40, slots=1)
-    fp = probe.info()["footprint"]
+    probe = NativeServer(scenes, caps, budget_bytes=1 << 32, slots=1)
+    pinfo = probe.info()
     probe.close()
-    budget = int(2.5 * np.median(fp)) + int(fp.max())
-    assert budget < fp.sum()  # not every scene fits at once
+    fp, step = pinfo["footprint"], pinfo["step"]
+    # room for the largest scene with its step, and half the other scenes:
+    # the largest step cannot run with every scene resident
+    budget = int((fp + step).max()) + int(fp.sum()) // 2
+    assert budget < fp.sum() + step.max()
     print(f"[native serve] {len(scenes)} scenes, budget {budget} B of {int(fp.sum())} B", flush=True)
     sv = NativeServer(scenes, caps, budget_bytes=budget, slots=3)
     make = request_maker(scenes, seed=98)
     reqs, done = [], {}
     pending = []
+    # every scene once, the largest step last (it cannot run with all the
+    # others resident), then random scenes
+    first = [int(k) for k in np.argsort(step, kind="stable")]
     for k in range(40):
         r = make(k)
+        if k < len(first):
+            sc = scenes[first[k]]
+            noise = np.random.default_rng(k).normal(0.0, 0.01 * mean_edge_length(sc), sc.x.shape)
+            r = Request(rid=k, sid=first[k], x=sc.x + noise)
         t = sv.submit(r.sid, r.x, grad=True)
         reqs.append((t, r))
         pending.append(t)
@@ -91,7 +101,10 @@ def test_native_server_results_equal_alone_and_the_oracle():
         done[t] = sv.poll(t, wait=True)
     info = sv.info()
     sv.close()
-    assert len(done) == 40 and info["used"] <= budget
+    bad = [(r.sid, done[t]) for t, r in reqs if done[t]["error"] != 0]
+    assert not bad, (bad, info)
+    assert len(done) == 40 and info["peak_bytes"] <= budget
+    assert info["created"] >= len(scenes) and info["evicted"] >= 1, info
     for t, r in reqs:
         res = done[t]
         assert res["error"] == 0 and res["status"] & ~bfc.binding.BF_S_INFEASIBLE == 0, res
@@ -113,3 +126,38 @@ def test_native_server_results_equal_alone_and_the_oracle():
         for k in ("n_c", "n_filt", "n_act", "n_infeasible"):
             assert res["counts"][k] == oc[k], (t, k)
         compare_assembled(res["E"], res["g"], o, sc.n_verts, kappa=sc.kappa, tau=1e-10)
+
+
+@requires_gpu
+def test_native_server_grows_capacities_after_overflow():
+    # capacities far below what the scenes need: each first request overflows,
+    # runs again with the capacities its counters reported (the slot's pool
+    # growing with them) and ends with the result of a run with room to spare
+    import paper_2510_10256_amd as bfc
+    from paper_2510_10256_amd.binding import NativeServer
+    from paper_2510_10256_amd.serve import request_maker, scene_caps
+    scenes = [synth.woven_patch(seed=70, n_warp=3, n_weft=3, verts_per_rod=64),
+              synth.folded_cloth(seed=71, n=32, gaps=())]
+    caps = [scene_caps(sc) for sc in scenes]
+    tiny = [(64, 16, 32)] * len(scenes)
+    print("[native serve] overflow growth, 2 scenes", flush=True)
+    sv = NativeServer(scenes, tiny, budget_bytes=1 << 34, slots=2)
+    make = request_maker(scenes, seed=5)
+    reqs = [make(k) for k in range(6)]
+    tickets = [sv.submit(r.sid, r.x, grad=True) for r in reqs]
+    done = [sv.poll(t, wait=True) for t in tickets]
+    info = sv.info()
+    sv.close()
+    assert info["retried"] >= 1
+    assert any(res["retries"] > 0 for res in done)
+    for r, res in zip(reqs, done):
+        assert res["error"] == 0 and res["status"] & ~bfc.binding.BF_S_INFEASIBLE == 0, res
+        cand, act, bsr = caps[r.sid]
+        cs = bfc.ContactScene(scenes[r.sid], cand_cap=cand, act_cap=act, bsr_cap=bsr, device="cuda:0")
+        cs.step(torch.tensor(r.x, dtype=torch.float64, device="cuda:0"))
+        a = cs.results()
+        cs.close()
+        assert res["E"] == a["E_total"]
+        for k in ("n_c", "n_filt", "n_act", "n_infeasible", "nnzb"):
+            assert res["counts"][k] == a["counts"][k], k
+        assert np.array_equal(res["g"], a["g"])
