@@ -60,7 +60,9 @@ FRICTION_BYTES_PER_PAIR = 9 + 64 + 192 + 8 + 96 + 1152
 # (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a
 # plain device copy of known size) on the kernel source whose fingerprint is
 # given; reported as null once that source changes.
-TRAFFIC = {}
+TRAFFIC = {("asm_values", "folded_cloth", None): ("19949d5546bcdedf", 4063.8e6),
+           ("asm_values", "folded_cloth", "fp64"): ("19949d5546bcdedf", 4063.8e6),
+           ("asm_values", "folded_cloth", "mixed"): ("19949d5546bcdedf", 4063.8e6)}
 # the same for the friction kernel (lag at x - 0.02 p; the bytes do not depend on mu)
 FRICTION_TRAFFIC_SOURCE = "423c9b78a4f89de4"
 FRICTION_TRAFFIC_BYTES = {"woven_patch": 39.7e6, "folded_cloth": 2833.3e6}
@@ -76,9 +78,15 @@ def _source_fingerprint(first_line, kernel, headers):
     return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
-def stage_source_fingerprint(kernel):
-    """Fingerprint of a kernel's source and the headers it includes."""
-    return _source_fingerprint(kernel, kernel, ("bfc_eval.h", "bfc_eig.h", "bfc_geom.h", "bfc_internal.h"))
+# source sections of the stages whose HBM bytes were counted: from the first
+# line to the end of the last kernel
+STAGE_SECTIONS = {"asm_values": ("// Assembly (owner computes)", "void k_row_b_big(")}
+
+
+def stage_source_fingerprint(stage):
+    """Fingerprint of a stage's kernels' source section and the headers it includes."""
+    first, last = STAGE_SECTIONS[stage]
+    return _source_fingerprint(first, last, ("bfc_eval.h", "bfc_eig.h", "bfc_geom.h", "bfc_internal.h"))
 
 
 def friction_source_fingerprint():
@@ -899,7 +907,7 @@ def main():
     key = (roof["stage"], sc.name, args.prec)
     if args.core_squeeze == 0 and not fric and key in TRAFFIC:
         src, per_launch = TRAFFIC[key]
-        if stage_source_fingerprint(roof["kernels"][0]) == src:
+        if stage_source_fingerprint(roof["stage"]) == src:
             roof["traffic"] = per_launch
 
     out = {
