@@ -43,7 +43,8 @@ struct AdmitSlot {
 };
 
 // Dev:
-//   bool create(int scene, int64_t off)  build the scene in its block at off (false: failed)
+//   bool create(int scene, int64_t off)  build the scene in its block at off, now or later (false: failed now;
+//                                        a build that fails later is undone with abort_fresh)
 //   void destroy(int scene)              tear down an idle resident scene
 //   void start(Req* q, int slot)         run q on the slot (its step block is set)
 //   void reject(Req* q, bool too_big)    complete q unserved (too_big: above the whole budget)
@@ -229,6 +230,16 @@ struct Admission {
     heap.release(slots[slot].off, slots[slot].bytes);
     slots[slot] = AdmitSlot{};
     sc[scene].busy = false;
+  }
+
+  // The scene of the request on `slot` was accepted for creation (create
+  // returned true) but could not be built: both blocks are free again and
+  // the scene is not resident.
+  void abort_fresh(int slot, int scene) {
+    done(slot, scene);
+    heap.release(sc[scene].off, sc[scene].fp);
+    sc[scene].off = -1;
+    --created;
   }
 };
 

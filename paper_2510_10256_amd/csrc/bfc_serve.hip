@@ -61,6 +61,7 @@ struct Reg {  // a registered scene (its residency is the admission policy's)
   int64_t ws_bytes = 0;                  // resident (persistent) part
   int64_t step_bytes = 0, io_bytes = 0;  // a step's workspaces, then its buffers
   bf_scene* scene = nullptr;
+  bool building = false;  // its creation is queued or running on the builder thread
 };
 
 // The step buffers of one request, carved from its step block.
@@ -92,6 +93,12 @@ struct Slot {
   double* g_pin = nullptr;
   ScenePin* r_pin = nullptr;
   Req* req = nullptr;
+  int creating = 0;  // the request waits for its scene: 1 being built, 2 built, 3 the build failed
+};
+
+struct Build {  // a scene creation for the builder thread
+  int scene;
+  int64_t off;
 };
 
 struct Dev;
@@ -110,8 +117,10 @@ struct bf_server {
   int64_t retried = 0;  // overflow re-runs so far
   bool stopping = false;
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
-  std::thread worker;
+  std::condition_variable cv_work, cv_done, cv_build;
+  std::thread worker, builder;
+  std::deque<Build> builds;
+  bool stop_builder = false;
   hipStream_t create_st = nullptr;
 };
 
@@ -172,27 +181,33 @@ void carve_io(const Reg& reg, char* base, StepIO& r) {
 
 void launch(bf_server* sv, int k, Req* q);
 
-// The device side of the admission policy.  create runs with the lock
-// released (a scene's creation synchronises its own stream; submitters and
-// pollers go on meanwhile).
+// The device side of the admission policy.  A scene's creation (uploads
+// and the filter precompute, synchronising its own stream) goes to the
+// builder thread, so that the worker keeps launching and completing other
+// requests meanwhile; the request waits on its slot until the scene is
+// built.
 struct Dev {
   bf_server* sv;
-  std::unique_lock<std::mutex>* lk;
   bool create(int k, int64_t off) {
-    Reg& r = sv->regs[k];
-    lk->unlock();
-    const bf_status st =
-        bfc_scene_create_shared(&r.mesh, &r.prm, r.cand_cap, sv->base + off, r.ws_bytes, sv->create_st, &r.scene);
-    lk->lock();
-    if (st != BF_OK) r.scene = nullptr;
-    return st == BF_OK;
+    sv->regs[k].building = true;
+    sv->builds.push_back({k, off});
+    sv->cv_build.notify_one();
+    return true;
   }
   void destroy(int k) {  // the scene is idle: its last request has completed
     Reg& r = sv->regs[k];
     (void)bf_scene_destroy(r.scene);
     r.scene = nullptr;
   }
-  void start(Req* q, int k) { launch(sv, k, q); }
+  void start(Req* q, int k) {
+    Slot& sl = sv->slots[k];
+    if (sv->regs[q->scene].building) {
+      sl.req = q;
+      sl.creating = 1;
+      return;
+    }
+    launch(sv, k, q);
+  }
   void reject(Req* q, bool too_big) {
     q->res.error = too_big ? bfc_fail(BF_E_CAPACITY, "bf_serve: the scene and its step are above the budget")
                            : bfc_fail(BF_E_NOMEM, "bf_serve: scene creation failed");
@@ -202,6 +217,30 @@ struct Dev {
     sv->cv_done.notify_all();
   }
 };
+
+// The builder thread: creates the scenes admission placed, one at a time,
+// in its block of the budget, on a stream of its own.
+void build_scenes(bf_server* sv) {
+  (void)hipSetDevice(sv->device);
+  std::unique_lock<std::mutex> lk(sv->mu);
+  while (true) {
+    sv->cv_build.wait(lk, [&] { return sv->stop_builder || !sv->builds.empty(); });
+    if (sv->builds.empty()) break;  // stopping, nothing left
+    const Build b = sv->builds.front();
+    sv->builds.pop_front();
+    Reg& r = sv->regs[b.scene];
+    lk.unlock();  // the scene is busy (its request waits for it): nobody else touches it
+    bf_scene* scene = nullptr;
+    const bf_status st = bfc_scene_create_shared(&r.mesh, &r.prm, r.cand_cap, sv->base + b.off, r.ws_bytes,
+                                                 sv->create_st, &scene);
+    lk.lock();
+    r.scene = st == BF_OK ? scene : nullptr;
+    r.building = false;
+    for (Slot& sl : sv->slots)
+      if (sl.req && sl.creating == 1 && sl.req->scene == b.scene) sl.creating = st == BF_OK ? 2 : 3;
+    sv->cv_work.notify_one();
+  }
+}
 
 void launch(bf_server* sv, int k, Req* q) {
   Slot& sl = sv->slots[k];
@@ -306,15 +345,34 @@ void work(bf_server* sv) {
     bool any_done = false;
     for (Slot& sl : sv->slots) {
       if (!sl.req) continue;
+      const int k = (int)(&sl - sv->slots.data());
+      if (sl.creating == 1) continue;  // its scene is being built
+      if (sl.creating == 2) {          // built: the request runs now
+        sl.creating = 0;
+        launch(sv, k, sl.req);
+        continue;
+      }
+      if (sl.creating == 3) {  // the build failed: the request completes unserved
+        Req* q = sl.req;
+        sl.req = nullptr;
+        sl.creating = 0;
+        sv->adm.abort_fresh(k, q->scene);
+        q->res.error = bfc_fail(BF_E_NOMEM, "bf_serve: scene creation failed");
+        q->res.retries = q->retries;
+        q->res.ms = std::chrono::duration<double, std::milli>(Clock::now() - q->t0).count();
+        q->res.done = 1;
+        any_done = true;
+        continue;
+      }
       const hipError_t e = hipEventQuery(sl.ev);
       if (e == hipErrorNotReady) continue;
       if (e != hipSuccess && sl.req->res.error == BF_OK) sl.req->res.error = BF_E_DEVICE;
-      finish(sv, (int)(&sl - sv->slots.data()));
+      finish(sv, k);
       any_done = true;
     }
     if (any_done) sv->cv_done.notify_all();
     if (!sv->queue.empty()) {
-      Dev dev{sv, &lk};
+      Dev dev{sv};
       sv->adm.pass(dev, sv->queue);
     }
     bool active = false;
@@ -406,6 +464,7 @@ bf_status bf_serve_start(const bf_serve_config* cfg, bf_server** out) {
     (void)bf_serve_stop(sv);
     return bfc_fail(BF_E_DEVICE, "bf_serve_start: streams or pinned buffers");
   }
+  sv->builder = std::thread(build_scenes, sv);
   sv->worker = std::thread(work, sv);
   *out = sv;
   return BF_OK;
@@ -457,7 +516,13 @@ bf_status bf_serve_stop(bf_server* sv) {
     sv->stopping = true;
   }
   sv->cv_work.notify_one();
-  if (sv->worker.joinable()) sv->worker.join();
+  if (sv->worker.joinable()) sv->worker.join();  // every request completed, so no build is left
+  {
+    std::lock_guard<std::mutex> g(sv->mu);
+    sv->stop_builder = true;
+  }
+  sv->cv_build.notify_one();
+  if (sv->builder.joinable()) sv->builder.join();
   (void)hipSetDevice(sv->device);
   for (Reg& r : sv->regs)
     if (r.scene) (void)bf_scene_destroy(r.scene);  // idle: the worker has drained every request

@@ -102,6 +102,7 @@ struct Fake {
   std::vector<Req*> on_slot;
   int rejected = 0, too_big = 0, started = 0, create_fail = 0;
   int failed_scene = -1;    // the scene whose creation just failed
+  std::set<int> fail_later;  // scenes whose accepted creation will fail
   std::set<int> waiting;    // ids of queued requests
   std::vector<int> passed;  // per request: later requests started while it waited
 
@@ -124,6 +125,7 @@ struct Fake {
       return false;
     }
     add(off, adm->sc[s].fp);
+    if ((*rng)() % 50 == 0) fail_later.insert(s);  // accepted, fails before its request runs
     return true;
   }
   void destroy(int s) {
@@ -195,6 +197,20 @@ static void admission_test(unsigned seed) {
       q->id = next_id++;
       dev.waiting.insert(q->id);
       queue.push_back(q);
+    }
+    // creations that fail after they were accepted: the request never ran
+    for (int k = 0; k < n_slots; ++k) {
+      if (dev.running[k] < 0 || !dev.fail_later.count(dev.on_slot[k]->scene)) continue;
+      Req* q = dev.on_slot[k];
+      dev.fail_later.erase(q->scene);
+      dev.remove(adm.slots[k].off);
+      dev.remove(adm.sc[q->scene].off);
+      adm.abort_fresh(k, q->scene);
+      CHECK(adm.sc[q->scene].off < 0 && !adm.sc[q->scene].busy, "scene %d left resident", q->scene);
+      dev.running[k] = -1;
+      dev.on_slot[k] = nullptr;
+      ++dev.rejected;
+      delete q;
     }
     // completions
     for (int k = 0; k < n_slots; ++k) {
