@@ -418,7 +418,8 @@ bf_status bf_batch_destroy(bf_batch* b);
 
 /* ---- serving: requests for many registered scenes ---------------------
  * A server keeps the registered scenes' host data (copied at start) and runs
- * requests (a scene and its positions) with a worker thread of its own.
+ * requests (a scene and its positions) with a worker thread of its own
+ * (and a builder thread that creates the scenes made resident).
  * All its device memory is one block of budget_bytes, allocated at start.
  * A resident scene holds in it only what persists between its steps
  * (topology, rest data and filter precompute, broad-phase workspace: its

@@ -2,7 +2,9 @@
 // many registered scenes, each a whole step (the four calls of the path) at
 // positions the host sends.
 //
-// A worker thread owns the device side.  All device memory of the server is
+// A worker thread owns the device side, and a builder thread creates the
+// scenes that admission makes resident (the request waits on its slot while
+// the worker runs the others).  All device memory of the server is
 // one block of the budget's size, divided by the admission policy (a heap
 // over the block, bfc_admit.h): a resident scene holds only what persists
 // between its steps (topology, rest data and filter precompute, broad-phase
