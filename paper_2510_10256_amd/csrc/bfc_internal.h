@@ -72,7 +72,7 @@ struct BroadWs {
   int* sorted_id;    // [NS] stored primitives in cell order, by id inside a cell
   Box* sorted_box;   // [NS]
   int4* sorted_vid;  // [NS] their vertex ids (edges: v0, v1, -1; triangles: t0, t1, t2)
-  int* pair_cnt;     // [NQ * PQ_MAX] pairs per (query, cell subset)
+  int* pair_cnt;     // [NQ * PQ_MAX] pairs per (query, thread of the query)
   int* pair_bsum;    // [work-groups + 1] pairs per work-group of the count pass
   int* pair_bofs;    // [work-groups + 1] their exclusive scan (the emit pass's offsets)
   long long* pair_bseg;            // [work-groups + 1] start of each group's staged pairs, -1: visit again

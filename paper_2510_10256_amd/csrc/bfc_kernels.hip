@@ -561,11 +561,14 @@ __device__ __forceinline__ int visit_pairs(const SceneDev& S, const Grid& g, con
   const int ny = hi[1] - lo[1] + 1, nrow = ny * (hi[2] - lo[2] + 1);
   const int base = qtype == BF_PT ? g.ncells : 0;
   int cnt = 0;
-  for (int row = sub; row < nrow; row += PQ) {
+  // the PQ threads of the query take the stored primitives of every row in
+  // turn (thread sub: the row's sub-th, (sub + PQ)-th, ...), so that their
+  // loads are neighbours and their work is even
+  for (int row = 0; row < nrow; ++row) {
     const int cy = lo[1] + row % ny, cz = lo[2] + row / ny;
     const int l0 = base + cell_lin(g, lo[0], cy, cz);
     const int b = cell_start[l0], e = cell_start[l0 + hi[0] - lo[0] + 1];
-    for (int k = b; k < e; ++k) {
+    for (int k = b + sub; k < e; k += PQ) {
       int r = sorted_id[k];
       if (qtype == BF_EE && r <= qid) continue;
       const Box rb = sorted_box[k];
@@ -616,7 +619,7 @@ __device__ __forceinline__ void query_id(const SceneDev& S, int q, int& qtype, i
   else { qtype = BF_EE; qid = S.kind == 1 ? q - S.nv : q; }
 }
 
-// Pass 1: pair count of every (query, row subset) thread and the total of
+// Pass 1: pair count of every (query, share of its cells) thread and the total of
 // each work-group in bsum[block] (bsum[nblocks] = 0).  The pairs are staged
 // in LDS; the group takes a segment of seg_r / seg_t (one atomic per group,
 // in any order) and stores there, coalesced, the pairs of its threads that
@@ -2887,7 +2890,7 @@ void run_broad(const SceneDev& S, const double* x, const double* pdisp, const Br
                      W.cell_start, W.placed_id, W.placed_box);
   hipLaunchKernelGGL(k_cell_order, dim3(nblocks(nstored)), dim3(256), 0, st, S, nstored, W.cell_of, W.cell_start,
                      W.placed_id, W.placed_box, W.sorted_id, W.sorted_box, W.sorted_vid);
-  // one thread per (query, row subset): no grid-stride here
+  // one thread per (query, share of its cells): no grid-stride here
   switch (S.pq) {
     case 2: launch_pairs<2>(S, nquery, W, oi, oj, ot, cap, count, status, seg_r, seg_t, seg_cap, st); break;
     case 8: launch_pairs<8>(S, nquery, W, oi, oj, ot, cap, count, status, seg_r, seg_t, seg_cap, st); break;
