@@ -1034,7 +1034,9 @@ __device__ __forceinline__ PairDec narrow_pair(const SceneDev& S, const double* 
       T = dd_sq(S.h);
       eta = r.core ? 0.0 : S.eta;
     }
-    r.active = dec(T, true);  // Eq. 2: d < a
+    // Eq. 2: d < a.  Unfiltered, a = h: the decision d < h already taken
+    // (r.nc), which the exact path would otherwise repeat
+    r.active = r.filt ? dec(T, true) : true;
     if (r.active) r.infeas = eta > 0.0 ? dec(dd_sq(eta), false) : !(r.D > 0.0);
   }
   return r;
