@@ -60,9 +60,9 @@ FRICTION_BYTES_PER_PAIR = 9 + 64 + 192 + 8 + 96 + 1152
 # (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a
 # plain device copy of known size) on the kernel source whose fingerprint is
 # given; reported as null once that source changes.
-TRAFFIC = {("asm_values", "folded_cloth", None): ("19949d5546bcdedf", 4063.8e6),
-           ("asm_values", "folded_cloth", "fp64"): ("19949d5546bcdedf", 4063.8e6),
-           ("asm_values", "folded_cloth", "mixed"): ("19949d5546bcdedf", 4063.8e6)}
+TRAFFIC = {("asm_values", "folded_cloth", None): ("b760b37fd1bcd7ce", 4089.1e6),
+           ("asm_values", "folded_cloth", "fp64"): ("b760b37fd1bcd7ce", 4089.1e6),
+           ("asm_values", "folded_cloth", "mixed"): ("b760b37fd1bcd7ce", 4089.1e6)}
 # the same for the friction kernel (lag at x - 0.02 p; the bytes do not depend on mu)
 FRICTION_TRAFFIC_SOURCE = "423c9b78a4f89de4"
 FRICTION_TRAFFIC_BYTES = {"woven_patch": 39.7e6, "folded_cloth": 2833.3e6}
@@ -78,15 +78,27 @@ def _source_fingerprint(first_line, kernel, headers):
     return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
-# source sections of the stages whose HBM bytes were counted: from the first
-# line to the end of the last kernel
-STAGE_SECTIONS = {"asm_values": ("// Assembly (owner computes)", "void k_row_b_big(")}
+# source of the stages whose HBM bytes were counted: sections of
+# bfc_kernels.hip (from a first line to the end of a last function) and the
+# headers they use
+STAGE_SECTIONS = {"asm_values": ([("// Packed pair Hessian:", "__constant__ PkTables kPk"),
+                                  ("// Assembly (owner computes)", "void k_row_b_big(")], ("bfc_internal.h",))}
 
 
 def stage_source_fingerprint(stage):
-    """Fingerprint of a stage's kernels' source section and the headers it includes."""
-    first, last = STAGE_SECTIONS[stage]
-    return _source_fingerprint(first, last, ("bfc_eval.h", "bfc_eig.h", "bfc_geom.h", "bfc_internal.h"))
+    """Fingerprint of a stage's kernels' source sections and the headers they use."""
+    import hashlib
+    sections, headers = STAGE_SECTIONS[stage]
+    csrc = os.path.join(ROOT, "paper_2510_10256_amd", "csrc")
+    src = open(os.path.join(csrc, "bfc_kernels.hip")).read()
+    text = "".join(open(os.path.join(csrc, f)).read() for f in headers)
+    for first, last in sections:
+        a = src.index(first)
+        b = src.index("\n", src.index(last, a))
+        if last.startswith("void"):
+            b = src.index("\n}\n", src.index(last, a)) + 3
+        text += src[a:b]
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
 def friction_source_fingerprint():
