@@ -533,6 +533,22 @@ __device__ __forceinline__ bool boxes_near(const Box& a, const Box& b, double h)
   return true;
 }
 
+// Euclidean distance between the boxes at or beyond h: the primitives they
+// contain are at least that far apart, so the pair is not a candidate.  The
+// gaps come from the float bounds in FP64 and their squares are summed there;
+// the relative margin of 1e-9 covers every rounding, so a pair is rejected
+// only when its boxes are truly h apart or more (boxes_near, the per-axis
+// test, runs first).
+__device__ __forceinline__ bool boxes_far_l2(const Box& a, const Box& b, double h) {
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double g = fmax(0.0, fmax((double)b.lo[k] - (double)a.hi[k], (double)a.lo[k] - (double)b.hi[k]));
+    s += g * g;
+  }
+  return s > h * h * (1.0 + 1e-9);
+}
+
 // Float gap above gapf on some axis: the exact test below fails too.  (NaN
 // gaps compare false and go on to the exact test.)
 __device__ __forceinline__ bool boxes_far_f(const Box& a, const Box& b, float gapf) {
@@ -553,7 +569,7 @@ constexpr int STAGE_K = 32;  // candidates a count-pass thread keeps in LDS (32 
 template <int PQ, int MODE>
 __device__ __forceinline__ int visit_pairs(const SceneDev& S, const Grid& g, const int* cell_start,
                                            const int* sorted_id, const Box* sorted_box, const int4* sorted_vid,
-                                           double hf, int qtype,
+                                           double hf, bool l2, int qtype,
                                            int qid, const Box& qb, const int* qv, int sub, long long pos,
                                            long long cap, int* oi, int* oj, unsigned char* ot, unsigned* status) {
   int lo[3], hi[3];
@@ -572,7 +588,7 @@ __device__ __forceinline__ int visit_pairs(const SceneDev& S, const Grid& g, con
       int r = sorted_id[k];
       if (qtype == BF_EE && r <= qid) continue;
       const Box rb = sorted_box[k];
-      if (boxes_far_f(qb, rb, g.gapf) || !boxes_near(qb, rb, hf)) continue;
+      if (boxes_far_f(qb, rb, g.gapf) || !boxes_near(qb, rb, hf) || (l2 && boxes_far_l2(qb, rb, hf))) continue;
       const int4 rv = sorted_vid[k];
       if (qtype == BF_EE) {
         if (rv.x == qv[0] || rv.x == qv[1] || rv.y == qv[0] || rv.y == qv[1]) continue;
@@ -630,7 +646,7 @@ template <int PQ>
 __global__ __launch_bounds__(256) void k_pair_count(SceneDev S, int nquery, const Box* box, const Grid* gp,
                                                     const int* cell_start, const int* sorted_id, const Box* sorted_box,
                                                     const int4* sorted_vid,
-                                                    double hf, int* cnt, int* bsum, long long* bseg,
+                                                    double hf, bool l2, int* cnt, int* bsum, long long* bseg,
                                                     unsigned long long* seg_count, int* seg_r, unsigned* seg_t,
                                                     long long seg_cap) {
   __shared__ int stage[STAGE_K * 256];
@@ -644,7 +660,7 @@ __global__ __launch_bounds__(256) void k_pair_count(SceneDev S, int nquery, cons
     int qtype, qid, qv[2];
     Box qb;
     query_of(S, box, t / PQ, qtype, qid, qb, qv);
-    c = visit_pairs<PQ, VISIT_STAGE>(S, g, cell_start, sorted_id, sorted_box, sorted_vid, hf, qtype, qid, qb, qv,
+    c = visit_pairs<PQ, VISIT_STAGE>(S, g, cell_start, sorted_id, sorted_box, sorted_vid, hf, l2, qtype, qid, qb, qv,
                                      t % PQ, 0, 0,
                                      stage + threadIdx.x, nullptr, nullptr, nullptr);
     cnt[t] = c;
@@ -690,7 +706,8 @@ template <int PQ>
 __global__ __launch_bounds__(256) void k_pair_emit(SceneDev S, int nquery, const Box* box, const Grid* gp,
                                                    const int* cell_start, const int* sorted_id, const Box* sorted_box,
                                                    const int4* sorted_vid,
-                                                   double hf, const int* cnt, const int* bofs, const long long* bseg,
+                                                   double hf, bool l2, const int* cnt, const int* bofs,
+                                                   const long long* bseg,
                                                    const int* seg_r, const unsigned* seg_t, int* oi, int* oj,
                                                    unsigned char* ot, long long cap, long long* count,
                                                    unsigned* status) {
@@ -729,7 +746,7 @@ __global__ __launch_bounds__(256) void k_pair_emit(SceneDev S, int nquery, const
   int qtype, qid, qv[2];
   Box qb;
   query_of(S, box, t / PQ, qtype, qid, qb, qv);
-  visit_pairs<PQ, VISIT_EMIT>(S, g, cell_start, sorted_id, sorted_box, sorted_vid, hf, qtype, qid, qb, qv, t % PQ,
+  visit_pairs<PQ, VISIT_EMIT>(S, g, cell_start, sorted_id, sorted_box, sorted_vid, hf, l2, qtype, qid, qb, qv, t % PQ,
                               base + loc, cap,
                               oi, oj, ot, status);
 }
@@ -2858,18 +2875,18 @@ void run_lift_ref(const SceneDev& S, double* xref, hipStream_t st) {
 }
 
 template <int PQ>
-static void launch_pairs(const SceneDev& S, int nquery, const BroadWs& W, int* oi, int* oj, unsigned char* ot,
-                         long long cap, long long* count, unsigned* status, int* seg_r, unsigned* seg_t,
-                         long long seg_cap, hipStream_t st) {
+static void launch_pairs(const SceneDev& S, int nquery, const BroadWs& W, bool l2, int* oi, int* oj,
+                         unsigned char* ot, long long cap, long long* count, unsigned* status, int* seg_r,
+                         unsigned* seg_t, long long seg_cap, hipStream_t st) {
   static_assert(PQ <= PQ_MAX, "pair_cnt, pair_bsum and pair_bseg hold PQ_MAX threads per query");
   int nb = (nquery * PQ + 255) / 256;
   hipLaunchKernelGGL(k_pair_count<PQ>, dim3(nb), dim3(256), 0, st, S, nquery, W.box, W.grid, W.cell_start,
-                     W.sorted_id, W.sorted_box, W.sorted_vid, S.h, W.pair_cnt, W.pair_bsum, W.pair_bseg, W.seg_count,
+                     W.sorted_id, W.sorted_box, W.sorted_vid, S.h, l2, W.pair_cnt, W.pair_bsum, W.pair_bseg, W.seg_count,
                      seg_r, seg_t,
                      seg_cap);
   scan_excl(W.pair_bsum, W.pair_bofs, nullptr, nb + 1, W.scan_tmp, status, st);
   hipLaunchKernelGGL(k_pair_emit<PQ>, dim3(nb), dim3(256), 0, st, S, nquery, W.box, W.grid, W.cell_start,
-                     W.sorted_id, W.sorted_box, W.sorted_vid, S.h, W.pair_cnt, W.pair_bofs, W.pair_bseg, seg_r, seg_t,
+                     W.sorted_id, W.sorted_box, W.sorted_vid, S.h, l2, W.pair_cnt, W.pair_bofs, W.pair_bseg, seg_r, seg_t,
                      oi, oj, ot,
                      cap, count, status);
 }
@@ -2892,12 +2909,15 @@ void run_broad(const SceneDev& S, const double* x, const double* pdisp, const Br
                      W.cell_start, W.placed_id, W.placed_box);
   hipLaunchKernelGGL(k_cell_order, dim3(nblocks(nstored)), dim3(256), 0, st, S, nstored, W.cell_of, W.cell_start,
                      W.placed_id, W.placed_box, W.sorted_id, W.sorted_box, W.sorted_vid);
+  // boxes swept along a displacement (the line search): the per-axis test
+  // alone, so that the candidates are the pairs whose swept boxes are within h
+  const bool l2 = pdisp == nullptr;
   // one thread per (query, share of its cells): no grid-stride here
   switch (S.pq) {
-    case 2: launch_pairs<2>(S, nquery, W, oi, oj, ot, cap, count, status, seg_r, seg_t, seg_cap, st); break;
-    case 8: launch_pairs<8>(S, nquery, W, oi, oj, ot, cap, count, status, seg_r, seg_t, seg_cap, st); break;
-    case 16: launch_pairs<16>(S, nquery, W, oi, oj, ot, cap, count, status, seg_r, seg_t, seg_cap, st); break;
-    default: launch_pairs<4>(S, nquery, W, oi, oj, ot, cap, count, status, seg_r, seg_t, seg_cap, st); break;
+    case 2: launch_pairs<2>(S, nquery, W, l2, oi, oj, ot, cap, count, status, seg_r, seg_t, seg_cap, st); break;
+    case 8: launch_pairs<8>(S, nquery, W, l2, oi, oj, ot, cap, count, status, seg_r, seg_t, seg_cap, st); break;
+    case 16: launch_pairs<16>(S, nquery, W, l2, oi, oj, ot, cap, count, status, seg_r, seg_t, seg_cap, st); break;
+    default: launch_pairs<4>(S, nquery, W, l2, oi, oj, ot, cap, count, status, seg_r, seg_t, seg_cap, st); break;
   }
 }
 
