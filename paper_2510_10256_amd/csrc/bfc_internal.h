@@ -17,7 +17,7 @@ struct Box {
 // x is one contiguous range of either.  A primitive whose box is within h of
 // a query box has its centre within `reach` (h + half the largest box side,
 // plus slack) of the query box, so a query visits the cells of that range
-// only; the cell side is free (half of largest side + h here).
+// only; the cell side is free (0.7 of largest side + h here).
 struct Grid {
   double orgd[3];
   double cell, inv_cell;
