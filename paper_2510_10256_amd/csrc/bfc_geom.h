@@ -13,6 +13,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <string.h>
 
 namespace bfc {
 
@@ -612,13 +613,123 @@ BFC_GD int exact_in_double(int code, const d3* P, dd T) {
   return sign_num_minus_tden(num, den, T);
 }
 
+// Exact sign of D - T for a point-edge sub-case, D = |r x e|^2 / |e|^2, as
+// the sign of |r x e|^2 - T |e|^2 summed in 256-bit fixed point (no memory:
+// the near ties of lattice-like geometry, which double-double cannot
+// settle, are mostly of this kind).  r = p - e0 and e = e1 - e0 must be
+// exact in FP64.  Every component of r x e is the sum of the two error-free
+// products' four parts t_a, so |r x e|^2 is the sum of the error-free
+// products t_a t_b; T |e|^2 likewise from e_x^2 and T = T.hi + T.lo.  Each of
+// these doubles, an integer m < 2^53 times a power of two, is added into the
+// accumulator at its bit position.  The accumulator's lowest bit is 2^-224
+// of the largest term, which leaves every product's low part inside; a term
+// outside the window returns 2, as does a difference that is not exact or a
+// zero |e| (the caller then takes its other exact path).
+struct FixAcc {
+  unsigned long long w[4];
+  int lsb;  // exponent of bit 0
+  bool ok;
+};
+BFC_GD void fix_add(FixAcc& A, double d) {
+  if (d == 0.0) return;
+  unsigned long long bits;
+  memcpy(&bits, &d, sizeof(bits));
+  const bool neg = (bits >> 63) != 0;
+  const int E = (int)((bits >> 52) & 0x7ff);
+  unsigned long long m = bits & ((1ull << 52) - 1);
+  int ex;
+  if (E == 0) {
+    ex = -1074;
+  } else {
+    m |= 1ull << 52;
+    ex = E - 1075;
+  }
+  const int pos = ex - A.lsb;
+  if (E == 0x7ff || pos < 0 || pos > 192) {  // not finite, below the window, or too close to its top
+    A.ok = false;
+    return;
+  }
+  unsigned long long t[4] = {0, 0, 0, 0};
+  const int L = pos >> 6, sh = pos & 63;
+  t[L] = m << sh;
+  if (sh != 0) t[L + 1] = m >> (64 - sh);  // L <= 3 and, for sh != 0, L + 1 <= 3 since pos <= 192
+  if (!neg) {
+    unsigned long long c = 0;
+    for (int i = 0; i < 4; ++i) {
+      const unsigned long long x = A.w[i], s1 = x + t[i], c1 = s1 < x, s2 = s1 + c, c2 = s2 < s1;
+      A.w[i] = s2;
+      c = c1 | c2;
+    }
+  } else {
+    unsigned long long b = 0;
+    for (int i = 0; i < 4; ++i) {
+      const unsigned long long x = A.w[i], d1 = x - t[i], b1 = x < t[i], d2 = d1 - b, b2 = d1 < b;
+      A.w[i] = d2;
+      b = b1 | b2;
+    }
+  }
+}
+BFC_GD void fix_prod(FixAcc& A, double a, double b, bool neg) {  // add (or subtract) a b exactly
+#pragma clang fp contract(off)
+  const double p = a * b, e = fma(a, b, -p);
+  fix_add(A, neg ? -p : p);
+  fix_add(A, neg ? -e : e);
+}
+__host__ __device__ __noinline__ int pe_sign_fixed(d3 p, d3 e0, d3 e1, dd T) {
+#pragma clang fp contract(off)
+  ExactD X{true};
+  const d3 r = X.sub3(p, e0), e = X.sub3(e1, e0);
+  if (!X.ok) return 2;
+  const double rv[3] = {r.x, r.y, r.z}, ev[3] = {e.x, e.y, e.z};
+  // the four parts of each component of r x e: p1 + q1 - p2 - q2
+  double tp[3][4];
+  double big = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+    const double p1 = rv[c1] * ev[c2], q1 = fma(rv[c1], ev[c2], -p1);
+    const double p2 = rv[c2] * ev[c1], q2 = fma(rv[c2], ev[c1], -p2);
+    tp[c][0] = p1; tp[c][1] = q1; tp[c][2] = -p2; tp[c][3] = -q2;
+    big = fmax(big, fmax(fabs(p1), fabs(p2)));
+  }
+  const double ee = ev[0] * ev[0] + ev[1] * ev[1] + ev[2] * ev[2];
+  if (!(ee > 0.0)) return 2;
+  const double top = fmax(big * big, fabs(T.hi) * ee * 2.0);
+  if (!(top > 0.0) || !(top < 1e300)) return 2;
+  int etop;
+  frexp(top, &etop);
+  FixAcc A{{0, 0, 0, 0}, etop + 8 - 248, true};  // bit 255: sign; headroom for 120 terms and rounding of top
+  for (int c = 0; c < 3; ++c)
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) fix_prod(A, tp[c][a], tp[c][b], false);
+  for (int c = 0; c < 3; ++c) {
+    const double h = ev[c] * ev[c], l = fma(ev[c], ev[c], -h);  // e_c^2 = h + l exactly
+    fix_prod(A, T.hi, h, true);
+    fix_prod(A, T.hi, l, true);
+    fix_prod(A, T.lo, h, true);
+    fix_prod(A, T.lo, l, true);
+  }
+  if (!A.ok) return 2;
+  if (A.w[3] >> 63) return -1;
+  return (A.w[0] | A.w[1] | A.w[2] | A.w[3]) ? 1 : 0;
+}
+
+// pe_sign_fixed for sub-case `code` (point-edge only; 2 for the others).
+BFC_GD int pe_sign_code(int code, const d3* P, dd T) {
+  if (case_kind(code) != K_PE) return 2;
+  int s0, s1, s2;
+  case_slots(code, s0, s1, s2);
+  return pe_sign_fixed(pick(P, s0), pick(P, s1), pick(P, s2), T);
+}
+
 // D (FP64 value of sub-case `code`) against an exact squared threshold given
 // as a double-double T: lt -> d < thr, else d <= thr.  Outside a relative
 // band of 1e-9 the FP64 value decides.  Inside it the formula is tried in
 // FP64 with exactness checks (lattice geometry: exact ties at d_min or h),
 // then in double-double; within 1e-20 of T, where double-double rounding
-// could still flip the answer, *amb is set and the narrow phase defers the
-// pair to k_exact (decide_sq_exact).  Without amb (the line-search and
+// could still flip the answer, a point-edge pair is decided in fixed point
+// (pe_sign_fixed) when its difference vectors are exact in FP64, and
+// otherwise *amb is set and the narrow phase defers the pair to k_exact
+// (decide_sq_exact).  Without amb (the line-search and
 // core-set kernels) the band is decided in double-double.
 BFC_GD bool decide_sq(int code, const d3* P, double D, dd T, bool lt, bool* amb) {
   double Th = T.hi;
@@ -629,7 +740,11 @@ BFC_GD bool decide_sq(int code, const d3* P, double D, dd T, bool lt, bool* amb)
   }
   q3 Q[4] = {q3_of(P[0]), q3_of(P[1]), q3_of(P[2]), q3_of(P[3])};
   const dd Dq = sqd_case<dd>(code, Q);
-  if (amb && !(fabs((Dq - T).hi) > 1e-20 * Th)) *amb = true;
+  if (amb && !(fabs((Dq - T).hi) > 1e-20 * Th)) {  // point-edge in fixed point, else the expansions
+    const int sg = pe_sign_code(code, P, T);
+    if (sg != 2) return lt ? sg < 0 : sg <= 0;
+    *amb = true;
+  }
   return lt ? dd_lt(Dq, T) : dd_le(Dq, T);
 }
 
@@ -649,6 +764,8 @@ BFC_GD bool decide_sq_exact(int code, const d3* P, double D, dd T, bool lt, doub
   const dd Dq = sqd_case<dd>(code, Q);
   const bool r = lt ? dd_lt(Dq, T) : dd_le(Dq, T);
   if (fabs((Dq - T).hi) > 1e-20 * Th) return r;
+  sg = pe_sign_code(code, P, T);
+  if (sg != 2) return lt ? sg < 0 : sg <= 0;
   sg = xp_sign_sq_minus(code, P[0], P[1], P[2], P[3], T, ws);
   if (sg == 2) {
     *limit = true;

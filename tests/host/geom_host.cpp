@@ -3,7 +3,8 @@
 // pair's four vertices X[12], the threshold T as two doubles (hi, lo).
 // Output per record: the sign of D - T from exact FP64 evaluation (2 when
 // some operation rounds), from expansions (2 when they outgrow their room),
-// and the double-double comparison (-1, 0, 1).
+// the double-double comparison (-1, 0, 1), and from the point-edge fixed-point
+// sum (2 when it does not apply).
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -25,13 +26,14 @@ int main(int argc, char** argv) {
     bfc::d3 P[4];
     for (int k = 0; k < 4; ++k) P[k] = {rec[1 + 3 * k], rec[2 + 3 * k], rec[3 + 3 * k]};
     const bfc::dd T = {rec[13], rec[14]};
-    double o[3];
+    double o[4];
     o[0] = bfc::exact_in_double(code, P, T);
     o[1] = bfc::xp_sign_sq_minus(code, P[0], P[1], P[2], P[3], T, ws.data());
     bfc::q3 Q[4] = {bfc::q3_of(P[0]), bfc::q3_of(P[1]), bfc::q3_of(P[2]), bfc::q3_of(P[3])};
     const bfc::dd Dq = bfc::sqd_case<bfc::dd>(code, Q);
     o[2] = bfc::dd_lt(Dq, T) ? -1.0 : (bfc::dd_lt(T, Dq) ? 1.0 : 0.0);
-    std::fwrite(o, sizeof(double), 3, out);
+    o[3] = bfc::pe_sign_code(code, P, T);
+    std::fwrite(o, sizeof(double), 4, out);
   }
   std::fclose(in);
   std::fclose(out);
