@@ -219,8 +219,10 @@ bf_status bf_scene_info(bf_scene* s, int32_t* comp_h, int32_t* n_comp, double* d
                         double* dmin_h, int32_t cap_c);
 
 /* Broad phase at the full activation distance h (Sec. 3.3): writes every
- * non-incident pair whose bounding boxes, inflated by h, overlap.  The list
- * is a superset of the pairs with d < h.  x_d: [V,3] FP64 positions. */
+ * non-incident pair whose bounding boxes are closer than h (their Euclidean
+ * distance, a lower bound on the primitives', below h with a relative margin
+ * of 1e-9).  The list is a superset of the pairs with d < h.  x_d: [V,3]
+ * FP64 positions. */
 bf_status build_candidates(bf_scene* s, const double* x_d, bf_pairs* cand, void* stream);
 
 /* Narrow phase and filter (Eq. 4): for each candidate computes the distance,
@@ -258,9 +260,10 @@ bf_status assemble_grad_hess(bf_scene* s, const bf_active* act, const bf_local* 
  *
  * build_candidates_swept: the broad phase of build_candidates on the boxes
  * swept by each primitive from x to x + p (p_d: [V,3] FP64 displacements,
- * the search direction times the largest step).  The list holds every pair
- * whose d(x + tau p) < h for some tau in [0, 1], so it serves the CCD below
- * and eval_energy at any point of the segment.
+ * the search direction times the largest step), with the per-axis test only
+ * (every pair whose swept boxes are closer than h on every axis).  The list
+ * holds every pair whose d(x + tau p) < h for some tau in [0, 1], so it
+ * serves the CCD below and eval_energy at any point of the segment.
  *
  * max_step_accd: for every candidate whose exact swept boxes (vertices at x
  * and x + p, FP64) are closer than h on every axis, additive CCD (Li et al.
