@@ -60,9 +60,9 @@ FRICTION_BYTES_PER_PAIR = 9 + 64 + 192 + 8 + 96 + 1152
 # (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a
 # plain device copy of known size) on the kernel source whose fingerprint is
 # given; reported as null once that source changes.
-TRAFFIC = {("asm_values", "folded_cloth", None): ("b760b37fd1bcd7ce", 4089.1e6),
-           ("asm_values", "folded_cloth", "fp64"): ("b760b37fd1bcd7ce", 4089.1e6),
-           ("asm_values", "folded_cloth", "mixed"): ("b760b37fd1bcd7ce", 4089.1e6)}
+TRAFFIC = {("asm_values", "folded_cloth", None): ("3f7bb1755c898bba", 4076.7e6),
+           ("asm_values", "folded_cloth", "fp64"): ("3f7bb1755c898bba", 4076.7e6),
+           ("asm_values", "folded_cloth", "mixed"): ("3f7bb1755c898bba", 4076.7e6)}
 # the same for the friction kernel (lag at x - 0.02 p; the bytes do not depend on mu)
 FRICTION_TRAFFIC_SOURCE = "423c9b78a4f89de4"
 FRICTION_TRAFFIC_BYTES = {"woven_patch": 39.7e6, "folded_cloth": 2833.3e6}
