@@ -39,30 +39,48 @@ FLOPS_PER_KIND = {0: 150.0, 1: 2700.0, 2: 8000.0, 3: 8000.0}
 #      candidate list out (9 B per candidate: i, j, type)
 #   a2 narrow phase and filter: 9 B of ids per candidate in, 32 B per active
 #      pair out; about 150 FP64 operations per candidate (distance and tests)
-#   a3 + a4 evaluation and projection: 8 + 96 + 624 = 728 B out per active
-#      pair (E, G[12], the upper triangle of H), 11 B of ids in; FP64 by kind
-#   a5 assembly: 96 + 720 B read per active pair (gradient, the ten 3 x 3
-#      blocks of the pair's upper triangle), 72 B written per block of the
-#      matrix and 24 B per vertex (gradient)
+#   a3 + a4 evaluation and projection: 8 + 96 + 78 w = 728 B out per active
+#      pair (E, G[12], the upper triangle of H in entries of w = 8 B; 416 B
+#      in the mixed mode, whose records are FP32: w = 4 B), 11 B of ids in;
+#      FP64 operations by kind
+#   a5 assembly: 96 + 90 w = 816 B read per active pair (gradient, the ten
+#      3 x 3 blocks of the pair's upper triangle; 456 B in the mixed mode),
+#      72 B written per block of the matrix and 24 B per vertex (gradient)
 A1_BYTES_PER_STORED = 2 * (8 + 4)
 CAND_BYTES = 9
 A2_FLOPS_PER_CAND = 150.0
 A2_BYTES_PER_ACTIVE = 32
-A3_BYTES_PER_ACTIVE = 728 + 11
-A5_BYTES_PER_ACTIVE = 96 + 720
+
+
+def h_entry_bytes(prec):
+    """Bytes of one entry of a pair's Hessian record: FP32 in the mixed mode."""
+    return 4 if prec == "mixed" else 8
+
+
+def a3_bytes_per_active(prec):
+    return 8 + 96 + 78 * h_entry_bytes(prec) + 11
+
+
+def a5_bytes_per_active(prec):
+    return 96 + 90 * h_entry_bytes(prec)
+
+
 KIND_OF_CODE = np.array([0, 0, 0, 1, 1, 1, 2, 0, 0, 0, 0, 1, 1, 1, 1, 3])
-# Algorithmic bytes of one lagged pair in friction_eval: pair ids and type
-# (9 B), lambda, weights[4], normal[3] (64 B), four vertices at x and at the
-# lagged positions (192 B), and E, G[12], H[12 x 12] (1256 B).
-FRICTION_BYTES_PER_PAIR = 9 + 64 + 192 + 8 + 96 + 1152
+
+
+def friction_bytes_per_pair(prec):
+    """Algorithmic bytes of one lagged pair in friction_eval: pair ids and
+    type (9 B), lambda, weights[4], normal[3] (64 B), four vertices at x and at
+    the lagged positions (192 B), and E, G[12] and the packed upper triangle
+    of H[12 x 12] (78 entries) out."""
+    return 9 + 64 + 192 + 8 + 96 + 78 * h_entry_bytes(prec)
 
 # HBM bytes per launch of a stage's kernels, counted with rocprofv3 --pmc
 # (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a
 # plain device copy of known size) on the kernel source whose fingerprint is
 # given; reported as null once that source changes.
 TRAFFIC = {("asm_values", "folded_cloth", None): ("3f7bb1755c898bba", 4076.7e6),
-           ("asm_values", "folded_cloth", "fp64"): ("3f7bb1755c898bba", 4076.7e6),
-           ("asm_values", "folded_cloth", "mixed"): ("3f7bb1755c898bba", 4076.7e6)}
+           ("asm_values", "folded_cloth", "fp64"): ("3f7bb1755c898bba", 4076.7e6)}
 # the same for the friction kernel (lag at x - 0.02 p; the bytes do not depend on mu)
 FRICTION_TRAFFIC_SOURCE = "423c9b78a4f89de4"
 FRICTION_TRAFFIC_BYTES = {"woven_patch": 39.7e6, "folded_cloth": 2833.3e6}
@@ -170,10 +188,10 @@ def cpu_baseline(sc, n_c_gpu, x=None, core=None, friction=None):
                       + (", lagged friction of every lagged pair" if friction is not None else "") + ")"}, res
 
 
-def eval_roofline(ms, n_act, kinds, label):
+def eval_roofline(ms, n_act, kinds, label, prec):
     """Roofline of the per-pair evaluation kernel from its measured time."""
     flops = float(sum(FLOPS_PER_KIND[int(k)] * int(np.sum(kinds == k)) for k in range(4)))
-    bytes_ = float(A3_BYTES_PER_ACTIVE * n_act)
+    bytes_ = float(a3_bytes_per_active(prec) * n_act)
     t_hbm = bytes_ / (HBM_PEAK_GBS * 1e9)
     t_fp = flops / (FP64_PEAK_TFLOPS * 1e12)
     if t_hbm >= t_fp:
@@ -202,7 +220,7 @@ STAGES = [
 ]
 
 
-def step_roofline(sc, counts, kinds, stage_ms, ms_step):
+def step_roofline(sc, counts, kinds, stage_ms, ms_step, prec):
     """Roofline of the step from the algorithmic work of each stage:
     T_roof = sum over stages of max(bytes / HBM peak, FP64 ops / FP64 peak),
     and the fraction T_roof / T_step; per stage, the same against its
@@ -214,9 +232,9 @@ def step_roofline(sc, counts, kinds, stage_ms, ms_step):
         "broad": (24.0 * V + 8.0 * E + 12.0 * F + A1_BYTES_PER_STORED * (E + F) + CAND_BYTES * n_bp, 0.0),
         "narrow": (float(CAND_BYTES * n_bp + A2_BYTES_PER_ACTIVE * n_act), A2_FLOPS_PER_CAND * n_bp),
         "compact": (0.0, 0.0),
-        "eval": (float(A3_BYTES_PER_ACTIVE * n_act), f_eval),
+        "eval": (float(a3_bytes_per_active(prec) * n_act), f_eval),
         "asm_structure": (0.0, 0.0),
-        "asm_values": (float(A5_BYTES_PER_ACTIVE * n_act + 72 * nnzb + 24 * V), 0.0),
+        "asm_values": (float(a5_bytes_per_active(prec) * n_act + 72 * nnzb + 24 * V), 0.0),
     }
     stages = {}
     t_roof = 0.0
@@ -543,7 +561,7 @@ def bench_batch(args):
         "active_pairs_per_s": n_act / (ms_per_step * 1e-3),
         "one_lane_ms_per_step": seq_ms,
         "setup_s": setup_s,
-        "roofline": eval_roofline(eval_ms, n_act, kinds, "k_eval (eval_barrier), summed over the scenes"),
+        "roofline": eval_roofline(eval_ms, n_act, kinds, "k_eval (eval_barrier), summed over the scenes", prec_name),
     }
     batch.close()
     if args.cpu_baseline:
@@ -881,7 +899,7 @@ def main():
         stage_runs.append(cs.stage_ms())
     cs.set_timing(False)
     stage_ms = {k: float(np.median([r[k] for r in stage_runs])) for k in stage_runs[0]}
-    step_roof = step_roofline(sc, counts, kinds, stage_ms, ms_per_step)
+    step_roof = step_roofline(sc, counts, kinds, stage_ms, ms_per_step, args.prec)
     roof = dict(step_roof["dominant"])
     roof["step"] = {k: v for k, v in step_roof.items() if k != "dominant"}
     fric_roof = None
@@ -908,7 +926,7 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         f_ms = e0.elapsed_time(e1) / (reps * 10)
-        fb = float(FRICTION_BYTES_PER_PAIR * n_fric)
+        fb = float(friction_bytes_per_pair(args.prec) * n_fric)
         fric_roof = {"kernel": "k_friction_eval (friction_eval)", "bound": "hbm",
                      "achieved": fb / (f_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None,
                      "kernel_ms": f_ms, "units": {"lagged_pairs": n_fric, "bytes": fb}}

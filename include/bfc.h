@@ -107,9 +107,11 @@ typedef struct {
   double h;        /* thickness: activation distance of unfiltered pairs (Sec. 3) */
   double eta;      /* biphasic offset of unfiltered pairs, 0 <= eta < h (Eq. 3) */
   double kappa;    /* barrier stiffness multiplying every pair energy (> 0) */
-  int32_t prec;    /* BF_FP64, or BF_MIXED: the eigen-projection's QR iteration stops at
-                      1e-8 of |H| (results within 1e-5 relative instead of about 1e-13);
-                      both modes use FP32 boxes in the broad phase and exact threshold
+  int32_t prec;    /* BF_FP64, or BF_MIXED: the PSD projection of each pair's reduced
+                      system runs in FP32 (results within 1e-5 relative instead of about
+                      1e-13) and the per-pair Hessian records (bf_local) are FP32;
+                      distances, decisions, energies and gradients stay FP64 in both
+                      modes, which use FP32 boxes in the broad phase and exact threshold
                       decisions */
   int32_t filter;  /* BF_FILTER_PAPER (Eq. 4), BF_FILTER_NONE (offset barrier everywhere), or
                       BF_FILTER_CULL (rods only: the comparison mode of Kaldor et al. that the
@@ -154,14 +156,18 @@ typedef struct {
 /* Per-active-pair results, row k for active pair k.  The 12 DOFs are the
  * pair's four stencil vertices in the order (point, t0, t1, t2) or
  * (a0, a1, b0, b1), xyz each.  H holds the upper triangle of the symmetric
- * projected 12 x 12 Hessian, packed by 3 x 3 blocks (78 doubles): block-row s
+ * projected 12 x 12 Hessian, packed by 3 x 3 blocks (78 entries): block-row s
  * (the three rows of stencil vertex s) is block (s, s) as its upper triangle
  * (xx, xy, xz, yy, yz, zz) followed by blocks (s, t), t > s, each row-major;
- * block-rows 0, 1, 2, 3 start at 0, 33, 57 and 72. */
+ * block-rows 0, 1, 2, 3 start at 0, 33, 57 and 72.  The entries are doubles
+ * in a BF_FP64 scene and floats in a BF_MIXED scene (whose projection runs in
+ * FP32: storing its result in FP32 adds a rounding of 6e-8 relative per entry
+ * and halves the bytes the evaluation writes and the assembly reads). */
 typedef struct {
   double* E_d;  /* [cap] kappa * b (+inf for infeasible pairs) */
   double* G_d;  /* [cap,12] gradient */
-  double* H_d;  /* [cap,78] projected Hessian, packed upper triangle (above) */
+  void* H_d;    /* [cap,78] projected Hessian, packed upper triangle (above): double
+                   (BF_FP64) or float (BF_MIXED) */
   int64_t cap;
 } bf_local;
 

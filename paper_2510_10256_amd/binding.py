@@ -67,8 +67,9 @@ PACKED_INDEX = _packed_index()
 
 
 def unpack_hessians(Hp):
-    """[n, 78] packed upper triangles -> [n, 12, 12] symmetric matrices."""
-    return np.asarray(Hp)[:, PACKED_INDEX]
+    """[n, 78] packed upper triangles (FP64, or FP32 from a mixed-precision
+    scene) -> [n, 12, 12] symmetric FP64 matrices."""
+    return np.asarray(Hp, np.float64)[:, PACKED_INDEX]
 
 
 class Params(C.Structure):
@@ -259,8 +260,10 @@ class ContactScene:
         self.a_code, self.a_flags = z(self.act_cap, t.uint8), z(self.act_cap, t.uint8)
         self.a_dist = z(self.act_cap, t.float64)
         self.counters = z(4, t.int64)
+        # Hessian records in the scene's precision (FP32 for BF_MIXED)
+        self.h_dtype = t.float32 if self.prec == BF_MIXED else t.float64
         self.l_E, self.l_G, self.l_H = z(self.act_cap, t.float64), z((self.act_cap, 12), t.float64), \
-            z((self.act_cap, 78), t.float64)
+            z((self.act_cap, 78), self.h_dtype)
         self.E = z(1, t.float64)
         self.g = z((self.nv, 3), t.float64)
         self.row_ptr = z(self.nv + 1, t.int32)
@@ -373,7 +376,7 @@ class ContactScene:
                             self.f_counters.data_ptr())
         self.f_lam, self.f_w, self.f_n = z(cap), z((cap, 4)), z((cap, 3))
         self._fr = Friction(self.f_lam.data_ptr(), self.f_w.data_ptr(), self.f_n.data_ptr(), cap)
-        self.fl_E, self.fl_G, self.fl_H = z(cap), z((cap, 12)), z((cap, 78))
+        self.fl_E, self.fl_G, self.fl_H = z(cap), z((cap, 12)), z((cap, 78), self.h_dtype)
         self._floc = Local(self.fl_E.data_ptr(), self.fl_G.data_ptr(), self.fl_H.data_ptr(), cap)
         self.f_E, self.f_g = z(1), z((self.nv, 3))
         self.f_row_ptr, self.f_col = z(self.nv + 1, t.int32), z(self.bsr_cap, t.int32)

@@ -51,7 +51,7 @@ void run_friction_lag(const SceneDev& S, const double* xl, const int* ai, const 
 void run_friction_eval(const SceneDev& S, const double* x, const double* xl, const int* ai, const int* aj,
                        const unsigned char* at, const long long* act_count, long long acap, const double* lam,
                        const double* w, const double* n, double mu, double eh, int accumulate, double* E, double* G,
-                       double* H, double* epart, hipStream_t st);
+                       void* H, double* epart, hipStream_t st);
 void run_energy(const SceneDev& S, const double* x, const double* pdisp, const double* alpha, const int* ci,
                 const int* cj, const unsigned char* ct, const long long* ccount, long long ccap, double* bred,
                 double* E_out, hipStream_t st);
@@ -65,10 +65,11 @@ void run_compact(const SceneDev& S, const double* x, const int* ci, const int* c
                  unsigned char* aflags, double* adist, long long acap, long long* act_count, long long* counters,
                  unsigned* status, hipStream_t st);
 
-// Per-pair barrier, gradient and projected Hessian.
+// Per-pair barrier, gradient and projected Hessian.  The Hessian records
+// (here and below) are doubles, or floats when S.mixed.
 void run_eval(const SceneDev& S, const double* x, const int* ai, const int* aj, const unsigned char* at,
               const unsigned char* acode, const unsigned char* aflags, const long long* act_count, long long acap,
-              double* E, double* G, double* H, double* epart, hipStream_t st);
+              double* E, double* G, void* H, double* epart, hipStream_t st);
 
 // Assembly, structural part: needs the active list only (incidence lists,
 // sorted entries, distinct columns per row).
@@ -78,7 +79,7 @@ void run_asm_structure(const SceneDev& S, const int* ai, const int* aj, const un
 
 // Assembly, numerical part: row pointers, blocks, gradient and energy.
 void run_asm_values(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,
-                    const long long* act_count, long long acap, const double* G, const double* H, double* E_out,
+                    const long long* act_count, long long acap, const double* G, const void* H, double* E_out,
                     double* g, int* row_ptr, int* col, double* val, long long bsr_cap, long long* nnzb,
                     const AsmWs& A, unsigned* status, hipStream_t st);
 

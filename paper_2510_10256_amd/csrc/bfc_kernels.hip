@@ -8,6 +8,7 @@
 //                   k_row_a / k_row_a_big, scan, k_row_b / k_row_b_big
 //   precompute    : k_cc_*, k_refmin (components and d_min, Sec. 3.2)
 #include <algorithm>
+#include <type_traits>
 
 #include "bfc_kernels.h"
 #include "bfc_eval.h"
@@ -1366,13 +1367,14 @@ __constant__ PkTables kPk = PkTables();
 // then goes out one block-row at a time: the lanes write the block-row's
 // entries of their rows into a small LDS tile (one row at a time, from the
 // reduced form), and the wave stores the 64 pairs' segments (33, 24, 15 and 6
-// contiguous doubles) as runs (stores straight from each lane's registers
-// would scatter every instruction over 64 records).  The energies of each
-// 64-pair tile are summed in a fixed order into epart (partials of the
-// total).
+// contiguous entries) as runs (stores straight from each lane's registers
+// would scatter every instruction over 64 records).  The records are FP64,
+// or FP32 in the mixed mode (HT), whose projection is FP32 already.  The
+// energies of each 64-pair tile are summed in a fixed order into epart
+// (partials of the total).
 constexpr int PK_STRIDE = 33;  // LDS doubles per pair in the staging tile (the longest block-row)
-template <int I>
-__device__ __forceinline__ void flush_row(const PairOut& h, double* buf, double* H, long long k0, int rows) {
+template <int I, class HT>
+__device__ __forceinline__ void flush_row(const PairOut& h, double* buf, HT* H, long long k0, int rows) {
   constexpr int s = I / 3, i = I % 3;
   const int lane = threadIdx.x;
   double r[12];
@@ -1387,13 +1389,13 @@ __device__ __forceinline__ void flush_row(const PairOut& h, double* buf, double*
     constexpr int len = pk_len(s);
     for (int idx = lane; idx < rows * len; idx += 64) {
       const int p = idx / len, e = idx - p * len;
-      H[PK_N * (k0 + p) + pk_off(s) + e] = buf[PK_STRIDE * p + e];
+      H[PK_N * (k0 + p) + pk_off(s) + e] = (HT)buf[PK_STRIDE * p + e];
     }
     __syncthreads();
   }
 }
-template <int I>
-__device__ __forceinline__ void flush_rows(const PairOut& h, double* buf, double* H, long long k0, int rows) {
+template <int I, class HT>
+__device__ __forceinline__ void flush_rows(const PairOut& h, double* buf, HT* H, long long k0, int rows) {
   flush_row<I>(h, buf, H, k0, rows);
   if constexpr (I + 1 < 12) flush_rows<I + 1>(h, buf, H, k0, rows);
 }
@@ -1402,7 +1404,9 @@ template <bool MIXED>
 __global__ __launch_bounds__(64) void k_eval(SceneDev S, const double* x, const int* ai, const int* aj,
                                              const unsigned char* at, const unsigned char* acode,
                                              const unsigned char* aflags, const unsigned long long* act_count,
-                                             long long acap, double* E, double* G, double* H, double* epart) {
+                                             long long acap, double* E, double* G, void* Hv, double* epart) {
+  using HT = typename std::conditional<MIXED, float, double>::type;
+  HT* H = (HT*)Hv;
   __shared__ double buf[64 * PK_STRIDE];
   long long n = (long long)*act_count;
   if (n > acap) n = acap;
@@ -1920,10 +1924,10 @@ __device__ __forceinline__ int slot_of(const int* vv, int c) {
 // (rows 3s..3s+2 of its pair's 12 x 12 Hessian: 36 contiguous doubles) into
 // LDS beside the pair's stencil vertices; each owner then adds the 3x3 blocks
 // of its columns from LDS, entries in sorted order.
-template <int NT, int CH>
+template <int NT, int CH, class HT>
 __device__ __forceinline__ void row_b(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,
                                       const int* inc, int b, int m, const int* cb, int r0, int u, const double* G,
-                                      const double* H, double* grow, int* col, double* val, int* vs, double* band,
+                                      const HT* H, double* grow, int* col, double* val, int* vs, double* band,
                                       double* gw, const int4* stn) {
   constexpr int TPE = NT / CH, PART = 36 / TPE;  // threads per entry, doubles per thread
   static_assert(TPE * PART == 36, "band split");
@@ -1940,11 +1944,11 @@ __device__ __forceinline__ void row_b(const SceneDev& S, const int* ai, const in
       double gx = 0.0, gy = 0.0, gz = 0.0;
       if (q < nq) {
         const int e = inc[b + qc + q], k = e >> 2;
-        const double* src = H + (long long)PK_N * k;  // the band of slot e & 3, gathered from the packed record
+        const HT* src = H + (long long)PK_N * k;  // the band of slot e & 3, gathered from the packed record
         const unsigned char* map = kPk.band[e & 3] + PART * part;
         double* dst = band + 36 * q + PART * part;
 #pragma unroll
-        for (int o = 0; o < PART; ++o) dst[o] = src[map[o]];
+        for (int o = 0; o < PART; ++o) dst[o] = (double)src[map[o]];
         if (part == 0) {
           const int4 w4 = stn[b + qc + q];
           vs[4 * q] = w4.x;
@@ -2010,9 +2014,10 @@ __device__ __forceinline__ void row_b(const SceneDev& S, const int* ai, const in
 // blocks of its columns, entries in sorted order.  Teams with m = 0 and
 // u = 0 only take part in the shuffles and barriers (a block is one wave).
 constexpr int TEAM_CH = 4;  // entries per chunk and team
+template <class HT>
 __device__ __forceinline__ void row_b_team(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,
                                            bool mine, const int* inc, int b, int m, const int* cb, int r0, int u,
-                                           const double* G, const double* H, double* grow, int* col, double* val,
+                                           const double* G, const HT* H, double* grow, int* col, double* val,
                                            int* vs, double* band, const int4* stn) {
   const int lane = lane_id(), tl = lane & 15;
   int* vst = vs + 4 * ROW_S * (lane >> 4);
@@ -2044,11 +2049,11 @@ __device__ __forceinline__ void row_b_team(const SceneDev& S, const int* ai, con
       const int eq = __shfl(e, qc + r, 16);
       __syncthreads();  // the stencils are written, the previous chunk is read
       if (qc + r < m) {
-        const double* src = H + (long long)PK_N * (eq >> 2);  // the band of slot eq & 3, from the packed record
+        const HT* src = H + (long long)PK_N * (eq >> 2);  // the band of slot eq & 3, from the packed record
         const unsigned char* map = kPk.band[eq & 3] + 9 * part;
         double* dst = bt + 36 * r + 9 * part;
 #pragma unroll
-        for (int o = 0; o < 9; ++o) dst[o] = src[map[o]];
+        for (int o = 0; o < 9; ++o) dst[o] = (double)src[map[o]];
       }
       __syncthreads();
       const int nq = min(TEAM_CH, m - qc);
@@ -2078,9 +2083,10 @@ __device__ __forceinline__ void row_b_team(const SceneDev& S, const int* ai, con
 // one at a time (strided over the list); every other block takes four
 // consecutive rows and works on those with m <= ROW_S, a team each.  Block
 // 0 also stores the block count and the total energy.
+template <class HT>
 __global__ __launch_bounds__(64) void k_row_b(SceneDev S, const int* ai, const int* aj, const unsigned char* at,
                                               const int* inc_off, const int* inc, const int* colbuf, const double* G,
-                                              const double* H, double* g, const int* row_ptr, int* col, double* val,
+                                              const HT* H, double* g, const int* row_ptr, int* col, double* val,
                                               long long cap, long long* nnzb, unsigned* status,
                                               const unsigned long long* act_count, long long acap,
                                               const double* epart, double* E_out, const int* mid, int nmid_blocks,
@@ -2133,9 +2139,10 @@ __global__ __launch_bounds__(64) void k_row_b(SceneDev S, const int* ai, const i
   }
 }
 
+template <class HT>
 __global__ __launch_bounds__(256) void k_row_b_big(SceneDev S, const int* ai, const int* aj, const unsigned char* at,
                                                    const int* inc_off, const int* inc, const int* colbuf,
-                                                   const double* G, const double* H, double* g, const int* row_ptr,
+                                                   const double* G, const HT* H, double* g, const int* row_ptr,
                                                    int* col, double* val, long long cap, const int* big,
                                                    const int4* stn) {
   __shared__ int vs[4 * 64];
@@ -2530,12 +2537,17 @@ __global__ __launch_bounds__(256) void k_friction_lag(SceneDev S, const double* 
 // lane's registers would scatter every instruction over 64 records 624 bytes
 // apart; the extra waves shorten the store loop of a tile.
 constexpr int FR_ST = 17;  // LDS doubles per pair: w[4], f[3], M[9], pad (odd stride)
+// Hessian records in the scene's precision (HT: FP32 in the mixed mode), the
+// accumulation rounded once in that precision.
+__device__ __forceinline__ double add_rn(double a, double b) { return __dadd_rn(a, b); }
+__device__ __forceinline__ float add_rn(float a, float b) { return __fadd_rn(a, b); }
+template <class HT>
 __global__ __launch_bounds__(256) void k_friction_eval(SceneDev S, const double* x, const double* xl, const int* ai,
                                                       const int* aj, const unsigned char* at,
                                                       const unsigned long long* act_count, long long acap,
                                                       const double* lam, const double* win, const double* nin,
                                                       double mu, double eh, int accumulate, double* E, double* G,
-                                                      double* H, double* epart) {
+                                                      HT* H, double* epart) {
   __shared__ double sm[64 * FR_ST];
   long long n = (long long)*act_count;
   if (n > acap) n = acap;
@@ -2598,14 +2610,14 @@ __global__ __launch_bounds__(256) void k_friction_eval(SceneDev S, const double*
         Gt[idx] = accumulate ? __dadd_rn(Gt[idx], val) : val;
       }
     }
-    double* Ht = H + PK_N * k0;
+    HT* Ht = H + PK_N * k0;
     for (int it = 0; it < (64 * PK_N + 255) / 256; ++it) {  // the packed upper triangles, as one run
       const int idx = it * 256 + tid, pp = idx / PK_N, rem = idx - PK_N * pp;
       if (pp < rows) {
         const int rw = kPk.row[rem], cl = kPk.col[rem];
         const double* ps = sm + FR_ST * pp;
-        const double val = __dmul_rn(ps[rw / 3] * ps[cl / 3], ps[7 + 3 * (rw % 3) + cl % 3]);
-        Ht[idx] = accumulate ? __dadd_rn(Ht[idx], val) : val;
+        const HT val = (HT)__dmul_rn(ps[rw / 3] * ps[cl / 3], ps[7 + 3 * (rw % 3) + cl % 3]);
+        Ht[idx] = accumulate ? add_rn(Ht[idx], val) : val;
       }
     }
   }
@@ -2963,9 +2975,15 @@ void run_friction_lag(const SceneDev& S, const double* xl, const int* ai, const 
 void run_friction_eval(const SceneDev& S, const double* x, const double* xl, const int* ai, const int* aj,
                        const unsigned char* at, const long long* act_count, long long acap, const double* lam,
                        const double* w, const double* n, double mu, double eh, int accumulate, double* E, double* G,
-                       double* H, double* epart, hipStream_t st) {
-  hipLaunchKernelGGL(k_friction_eval, dim3(nblocks(acap, 64, 1 << 30)), dim3(256), 0, st, S, x, xl, ai, aj, at,
-                     (const unsigned long long*)act_count, acap, lam, w, n, mu, eh, accumulate, E, G, H, epart);
+                       void* H, double* epart, hipStream_t st) {
+  if (S.mixed)
+    hipLaunchKernelGGL(k_friction_eval<float>, dim3(nblocks(acap, 64, 1 << 30)), dim3(256), 0, st, S, x, xl, ai, aj,
+                       at, (const unsigned long long*)act_count, acap, lam, w, n, mu, eh, accumulate, E, G, (float*)H,
+                       epart);
+  else
+    hipLaunchKernelGGL(k_friction_eval<double>, dim3(nblocks(acap, 64, 1 << 30)), dim3(256), 0, st, S, x, xl, ai, aj,
+                       at, (const unsigned long long*)act_count, acap, lam, w, n, mu, eh, accumulate, E, G,
+                       (double*)H, epart);
 }
 
 void run_energy(const SceneDev& S, const double* x, const double* pdisp, const double* alpha, const int* ci,
@@ -2999,7 +3017,7 @@ void run_compact(const SceneDev& S, const double* x, const int* ci, const int* c
 
 void run_eval(const SceneDev& S, const double* x, const int* ai, const int* aj, const unsigned char* at,
               const unsigned char* acode, const unsigned char* aflags, const long long* act_count, long long acap,
-              double* E, double* G, double* H, double* epart, hipStream_t st) {
+              double* E, double* G, void* H, double* epart, hipStream_t st) {
   if (S.mixed)
     hipLaunchKernelGGL(k_eval<true>, dim3(nblocks(acap, 64, 65535)), dim3(64), 0, st, S, x, ai, aj, at, acode,
                        aflags, (const unsigned long long*)act_count, acap, E, G, H, epart);
@@ -3029,19 +3047,32 @@ void run_asm_structure(const SceneDev& S, const int* ai, const int* aj, const un
                      A.colbuf, A.rowcnt, A.big, A.stn);
 }
 
+template <class HT>
+static void launch_rows_b(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,
+                          const unsigned long long* nact, long long acap, const double* G, const HT* H, double* E_out,
+                          double* g, int* row_ptr, int* col, double* val, long long bsr_cap, long long* nnzb,
+                          const AsmWs& A, unsigned* status, hipStream_t st) {
+  const int rows_grid = std::max(1, std::min((S.nv + 3) / 4, 1 << 20));  // four rows a block
+  const int mid_grid = std::max(1, std::min(S.nv, 1 << 20));  // listed rows: a block each (the rest exit)
+  hipLaunchKernelGGL(k_row_b<HT>, dim3(mid_grid + rows_grid), dim3(64), 0, st, S, ai, aj, at, A.inc_off, A.inc,
+                     A.colbuf, G, H, g, row_ptr, col, val, bsr_cap, nnzb, status, nact, acap, A.epart, E_out, A.mid,
+                     mid_grid, A.stn);
+  hipLaunchKernelGGL(k_row_b_big<HT>, dim3(big_grid_of(S.nv)), dim3(256), 0, st, S, ai, aj, at, A.inc_off, A.inc,
+                     A.colbuf, G, H, g, row_ptr, col, val, bsr_cap, A.big, A.stn);
+}
+
 void run_asm_values(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,
-                    const long long* act_count, long long acap, const double* G, const double* H, double* E_out,
+                    const long long* act_count, long long acap, const double* G, const void* H, double* E_out,
                     double* g, int* row_ptr, int* col, double* val, long long bsr_cap, long long* nnzb,
                     const AsmWs& A, unsigned* status, hipStream_t st) {
   const unsigned long long* nact = (const unsigned long long*)act_count;
   scan_excl(A.rowcnt, row_ptr, nullptr, S.nv + 1, A.scan_tmp, status, st);
-  const int rows_grid = std::max(1, std::min((S.nv + 3) / 4, 1 << 20));  // four rows a block
-  const int mid_grid = std::max(1, std::min(S.nv, 1 << 20));  // listed rows: a block each (the rest exit)
-  hipLaunchKernelGGL(k_row_b, dim3(mid_grid + rows_grid), dim3(64), 0, st, S, ai, aj, at, A.inc_off, A.inc, A.colbuf,
-                     G, H, g, row_ptr, col, val, bsr_cap, nnzb, status, nact, acap, A.epart, E_out, A.mid, mid_grid,
-                     A.stn);
-  hipLaunchKernelGGL(k_row_b_big, dim3(big_grid_of(S.nv)), dim3(256), 0, st, S, ai, aj, at, A.inc_off, A.inc,
-                     A.colbuf, G, H, g, row_ptr, col, val, bsr_cap, A.big, A.stn);
+  if (S.mixed)
+    launch_rows_b(S, ai, aj, at, nact, acap, G, (const float*)H, E_out, g, row_ptr, col, val, bsr_cap, nnzb, A,
+                  status, st);
+  else
+    launch_rows_b(S, ai, aj, at, nact, acap, G, (const double*)H, E_out, g, row_ptr, col, val, bsr_cap, nnzb, A,
+                  status, st);
 }
 
 int run_components(const SceneDev& S, int* lab, int* flag, int* scan, int* comp, int* scan_tmp, int* d_changed,

@@ -130,13 +130,16 @@ namespace {
 
 // The buffers of one scene's step, carved from its step block after the step
 // workspaces.
+// Bytes of one pair's Hessian record: 78 doubles, or 78 floats in the mixed mode.
+int64_t h_bytes_of(const Reg& r) { return r.prm.prec == BF_MIXED ? 312 : 624; }
+
 int64_t io_bytes_of(const Reg& r) {
-  const int64_t V = r.mesh.n_verts, C = r.cand_cap, A = r.act_cap, B = r.bsr_cap;
+  const int64_t V = r.mesh.n_verts, C = r.cand_cap, A = r.act_cap, B = r.bsr_cap, HB = h_bytes_of(r);
   size_t n = 0;
   for (size_t b : {(size_t)(4 * C), (size_t)(4 * C), (size_t)C, (size_t)8,                            // candidates
                    (size_t)(4 * A), (size_t)(4 * A), (size_t)A, (size_t)8, (size_t)A, (size_t)A,  // active
                    (size_t)(8 * A), (size_t)32,                                                   // dist, counters
-                   (size_t)(8 * A), (size_t)(96 * A), (size_t)(624 * A),                          // E, G, H
+                   (size_t)(8 * A), (size_t)(96 * A), (size_t)(HB * A),                           // E, G, H
                    (size_t)(4 * (V + 1)), (size_t)(4 * B), (size_t)(72 * B), (size_t)8,           // BSR
                    (size_t)(24 * V), (size_t)8, (size_t)(24 * V), (size_t)4})                     // x, E, g, status
     n = up256(n) + b;
@@ -168,7 +171,7 @@ void carve_io(const Reg& reg, char* base, StepIO& r) {
   r.act.counters_d = (int64_t*)take(32);
   r.loc.E_d = (double*)take(8 * A);
   r.loc.G_d = (double*)take(96 * A);
-  r.loc.H_d = (double*)take(624 * A);
+  r.loc.H_d = take(h_bytes_of(reg) * A);
   r.loc.cap = A;
   r.bsr.row_ptr_d = (int32_t*)take(4 * (V + 1));
   r.bsr.col_d = (int32_t*)take(4 * B);

@@ -120,12 +120,15 @@ def scene_caps(scene):
     return cand, act, max(4096, 5 * act)
 
 
-def scene_bytes(scene, cand, act, bsr):
+def scene_bytes(scene, cand, act, bsr, prec=1):
     """Device bytes of a resident scene: the caller buffers of a step plus the
-    library's scene workspace (topology, grid, staging, assembly)."""
+    library's scene workspace (topology, grid, staging, assembly).  Each
+    active pair's packed Hessian record is 78 doubles, or 78 floats in the
+    mixed mode (prec 1)."""
     nv = scene.n_verts
     nprims = scene.n_edges + (scene.n_tris + nv if scene.kind == "shell" else 0)
-    buffers = 9 * cand + act * (4 + 4 + 1 + 1 + 1 + 8 + 8 + 96 + 1152) + bsr * (4 + 72) + nv * 3 * 8 * 2 + 4 * nv
+    hrec = 78 * (4 if prec == 1 else 8)
+    buffers = 9 * cand + act * (4 + 4 + 1 + 1 + 1 + 8 + 8 + 96 + hrec) + bsr * (4 + 72) + nv * 3 * 8 * 2 + 4 * nv
     workspace = (nprims * (24 + 8 + 16 + 16) + 16 * 2 * max(4096, 2 * nprims) + 8 * 4 * (nv + scene.n_edges)
                  + 20 * cand + 80 * act + 20 * nv)
     return int(buffers + workspace)
@@ -142,7 +145,7 @@ class Server:
         self.prec = B.BF_MIXED if prec is None else prec
         self.device = torch.device(device)
         self.caps = [scene_caps(sc) for sc in self.scenes]
-        self._bytes = [scene_bytes(sc, *c) for sc, c in zip(self.scenes, self.caps)]
+        self._bytes = [scene_bytes(sc, *c, prec=self.prec) for sc, c in zip(self.scenes, self.caps)]
         self.adm = Admission(budget_bytes, slots, lambda sid: self._bytes[sid])
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]  # default priority
         vmax = max(sc.n_verts for sc in self.scenes)
@@ -223,7 +226,8 @@ class Server:
                 # grow the scene's buffers to what the device reported, then redo
                 cs.run(self.xdev[req.sid])
                 self._capture(req.sid)
-                self.adm.resize(req.sid, scene_bytes(self.scenes[req.sid], cs.cand_cap, cs.act_cap, cs.bsr_cap))
+                self.adm.resize(req.sid, scene_bytes(self.scenes[req.sid], cs.cand_cap, cs.act_cap, cs.bsr_cap,
+                                                     prec=self.prec))
                 req.retries += 1
                 self._launch(req, slot)
                 continue
