@@ -1927,7 +1927,7 @@ __device__ __forceinline__ int slot_of(const int* vv, int c) {
 template <int NT, int CH, class HT>
 __device__ __forceinline__ void row_b(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,
                                       const int* inc, int b, int m, const int* cb, int r0, int u, const double* G,
-                                      const HT* H, double* grow, int* col, double* val, int* vs, double* band,
+                                      const HT* H, double* grow, int* col, double* val, int* vs, HT* band,
                                       double* gw, const int4* stn) {
   constexpr int TPE = NT / CH, PART = 36 / TPE;  // threads per entry, doubles per thread
   static_assert(TPE * PART == 36, "band split");
@@ -1946,9 +1946,9 @@ __device__ __forceinline__ void row_b(const SceneDev& S, const int* ai, const in
         const int e = inc[b + qc + q], k = e >> 2;
         const HT* src = H + (long long)PK_N * k;  // the band of slot e & 3, gathered from the packed record
         const unsigned char* map = kPk.band[e & 3] + PART * part;
-        double* dst = band + 36 * q + PART * part;
+        HT* dst = band + 36 * q + PART * part;
 #pragma unroll
-        for (int o = 0; o < PART; ++o) dst[o] = (double)src[map[o]];
+        for (int o = 0; o < PART; ++o) dst[o] = src[map[o]];
         if (part == 0) {
           const int4 w4 = stn[b + qc + q];
           vs[4 * q] = w4.x;
@@ -1974,7 +1974,7 @@ __device__ __forceinline__ void row_b(const SceneDev& S, const int* ai, const in
         for (int a = 0; a < 3; ++a) gsum[a] += ((gw[a] + gw[3 + a]) + gw[6 + a]) + gw[9 + a];
       for (int r = 0; r < nq; ++r) {
         const int w[4] = {vs[4 * r], vs[4 * r + 1], vs[4 * r + 2], vs[4 * r + 3]};
-        const double* bq = band + 36 * r;
+        const HT* bq = band + 36 * r;
         const int sa = slot_of(w, ca), sz = slot_of(w, cz);
         if (sa >= 0) {
 #pragma unroll
@@ -2018,10 +2018,10 @@ template <class HT>
 __device__ __forceinline__ void row_b_team(const SceneDev& S, const int* ai, const int* aj, const unsigned char* at,
                                            bool mine, const int* inc, int b, int m, const int* cb, int r0, int u,
                                            const double* G, const HT* H, double* grow, int* col, double* val,
-                                           int* vs, double* band, const int4* stn) {
+                                           int* vs, HT* band, const int4* stn) {
   const int lane = lane_id(), tl = lane & 15;
   int* vst = vs + 4 * ROW_S * (lane >> 4);
-  double* bt = band + 36 * TEAM_CH * (lane >> 4);
+  HT* bt = band + 36 * TEAM_CH * (lane >> 4);
   int e = 0;
   int vv[4] = {EMPTY, EMPTY, EMPTY, EMPTY};
   double gx = 0.0, gy = 0.0, gz = 0.0;
@@ -2051,16 +2051,16 @@ __device__ __forceinline__ void row_b_team(const SceneDev& S, const int* ai, con
       if (qc + r < m) {
         const HT* src = H + (long long)PK_N * (eq >> 2);  // the band of slot eq & 3, from the packed record
         const unsigned char* map = kPk.band[eq & 3] + 9 * part;
-        double* dst = bt + 36 * r + 9 * part;
+        HT* dst = bt + 36 * r + 9 * part;
 #pragma unroll
-        for (int o = 0; o < 9; ++o) dst[o] = (double)src[map[o]];
+        for (int o = 0; o < 9; ++o) dst[o] = src[map[o]];
       }
       __syncthreads();
       const int nq = min(TEAM_CH, m - qc);
 #pragma unroll 1
       for (int q = 0; q < nq; ++q) {
         const int w[4] = {vst[4 * (qc + q)], vst[4 * (qc + q) + 1], vst[4 * (qc + q) + 2], vst[4 * (qc + q) + 3]};
-        const double* bq = bt + 36 * q;
+        const HT* bq = bt + 36 * q;
         const int sa = slot_of(w, ca);
         if (sa >= 0) {
 #pragma unroll
@@ -2095,7 +2095,7 @@ __global__ __launch_bounds__(64) void k_row_b(SceneDev S, const int* ai, const i
   // 4 teams x TEAM_CH bands / 32 bands (a listed row's entries 32 at a time:
   // fewer dependent rounds of band loads than 16, and 64 take too much LDS)
   __shared__ int vs[4 * 4 * ROW_S];
-  __shared__ double band[32 * 36];
+  __shared__ HT band[32 * 36];  // the bands in the records' precision (summed in FP64)
   static_assert(4 * TEAM_CH <= 32, "team bands fit the shared band buffer");
   if (blockIdx.x == 0) {
     if (threadIdx.x == 0) {
@@ -2146,7 +2146,7 @@ __global__ __launch_bounds__(256) void k_row_b_big(SceneDev S, const int* ai, co
                                                    int* col, double* val, long long cap, const int* big,
                                                    const int4* stn) {
   __shared__ int vs[4 * 64];
-  __shared__ double band[64 * 36];
+  __shared__ HT band[64 * 36];
   __shared__ double gw[12];
   const int nbig = big[S.nv];
   for (int r = blockIdx.x; r < nbig; r += gridDim.x) {
