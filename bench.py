@@ -79,11 +79,12 @@ def friction_bytes_per_pair(prec):
 # (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a
 # plain device copy of known size) on the kernel source whose fingerprint is
 # given; reported as null once that source changes.
-TRAFFIC = {("asm_values", "folded_cloth", None): ("3f7bb1755c898bba", 4076.7e6),
-           ("asm_values", "folded_cloth", "fp64"): ("3f7bb1755c898bba", 4076.7e6)}
-# the same for the friction kernel (lag at x - 0.02 p; the bytes do not depend on mu)
-FRICTION_TRAFFIC_SOURCE = "423c9b78a4f89de4"
-FRICTION_TRAFFIC_BYTES = {"woven_patch": 39.7e6, "folded_cloth": 2833.3e6}
+TRAFFIC = {("asm_values", "folded_cloth", None): ("5293752ea332d4d2", 4076.2e6),
+           ("asm_values", "folded_cloth", "fp64"): ("5293752ea332d4d2", 4076.2e6),
+           ("asm_values", "folded_cloth", "mixed"): ("5293752ea332d4d2", 2887.6e6)}
+# the same for the friction kernel (lag at x - 0.02 p; the bytes do not depend on mu), FP64
+FRICTION_TRAFFIC_SOURCE = "3adca896ab118311"
+FRICTION_TRAFFIC_BYTES = {"woven_patch": 25.4e6, "folded_cloth": 1752.4e6}
 
 
 def _source_fingerprint(first_line, kernel, headers):
@@ -931,7 +932,7 @@ def main():
                      "achieved": fb / (f_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None,
                      "kernel_ms": f_ms, "units": {"lagged_pairs": n_fric, "bytes": fb}}
         fric_roof["frac"] = fric_roof["achieved"] / HBM_PEAK_GBS
-        if (args.core_squeeze == 0 and sc.name in FRICTION_TRAFFIC_BYTES
+        if (args.core_squeeze == 0 and args.prec != "mixed" and sc.name in FRICTION_TRAFFIC_BYTES
                 and friction_source_fingerprint() == FRICTION_TRAFFIC_SOURCE):
             fric_roof["traffic"] = FRICTION_TRAFFIC_BYTES[sc.name]
     key = (roof["stage"], sc.name, args.prec)
