@@ -111,13 +111,17 @@ class Admission:
 
 
 def scene_caps(scene):
-    """Buffer capacities of a scene's step (sizes from its primitive counts,
-    generous enough that overflows, and the retry they cost, are rare)."""
+    """Initial buffer capacities of a scene's step, from its primitive counts:
+    candidates 32 per shell primitive (the folded cloth needs 23) and 12 per
+    rod edge, active pairs 2 per shell primitive and 1.5 per edge, BSR blocks
+    2 per active pair (the cloth needs 1.33).  A step that overflows runs again
+    with capacities grown to its counts (the serving loops do this), so dense
+    scenes pay one re-run on their first request."""
     nprims = scene.n_edges + (scene.n_tris + scene.n_verts if scene.kind == "shell" else 0)
     shell = scene.kind == "shell"
-    cand = max(4096, (48 if shell else 12) * nprims)
+    cand = max(4096, (32 if shell else 12) * nprims)
     act = max(4096, (2 * nprims if shell else 3 * nprims // 2))
-    return cand, act, max(4096, 5 * act)
+    return cand, act, max(4096, 2 * act)
 
 
 def scene_bytes(scene, cand, act, bsr, prec=1):
