@@ -318,6 +318,7 @@ void discard_scene(bf_scene* s) {
 // (sized by the vertex count, a bound on the components) and the culling
 // tables.  With g_arena set, carved from the caller's workspace (or only
 // counted, bf_workspace_bytes).
+bf_status alloc_broad(bf_scene* s, std::vector<void*>& allocs);
 bf_status alloc_persistent(bf_scene* s, long long cand_cap, long long act_cap) {
   const int nv = s->nv, ne = s->ne, nt = s->nt;
   hipError_t e = hipSuccess;
@@ -335,38 +336,57 @@ bf_status alloc_persistent(bf_scene* s, long long cand_cap, long long act_cap) {
     s->d_eidx = dalloc<int>(s->allocs, ne, &e);
     s->d_eloop = dalloc<int>(s->allocs, ne, &e);
   }
+  if (e != hipSuccess)
+    return fail(g_arena ? BF_E_CAPACITY : BF_E_NOMEM,
+                g_arena ? "bf_scene_create_ws: workspace smaller than bf_workspace_bytes"
+                        : "bf_scene_create: device allocation failed");
+  if (s->shared_step) return BF_OK;  // the broad phase's and the step's workspaces come with each request
+  bf_status r = alloc_broad(s, s->allocs);
+  if (r == BF_OK) r = alloc_asm(s, act_cap);
+  if (r == BF_OK) r = alloc_stage(s, cand_cap);
+  return r;
+}
+
+// The broad phase's workspace (grid, boxes, cell-sorted primitives, pair
+// counts), with what its kernels expect at zero cleared on g_alloc_stream
+// (cell counts, the single-pass scans' state, the bounds reduction's counter).
+bf_status alloc_broad(bf_scene* s, std::vector<void*>& allocs) {
+  const int nv = s->nv, ne = s->ne, nt = s->nt;
+  hipError_t e = hipSuccess;
   const int np = ne + nt + (s->kind == BF_SHELL ? nv : 0);
   BroadWs& W = s->bw;
   W.max_cells = (int)std::min<long long>(std::max<long long>(4096, 2LL * np), 1LL << 26);
   const long long nscan = 2LL * W.max_cells + 1;
   const long long nq = (long long)(s->kind == BF_SHELL ? nv + ne : ne) * PQ_MAX + 1;
-  W.box = dalloc<Box>(s->allocs, np, &e);
-  W.cell_of = dalloc<int>(s->allocs, ne + nt, &e);
-  W.part = dalloc<float>(s->allocs, 8LL * BOUNDS_BLOCKS, &e);
-  W.done = dalloc<unsigned>(s->allocs, 1, &e);
-  W.grid = dalloc<Grid>(s->allocs, 1, &e);
-  W.cell_cnt = dalloc<int>(s->allocs, nscan, &e);
-  W.cell_start = dalloc<int>(s->allocs, nscan, &e);
-  W.sorted_id = dalloc<int>(s->allocs, ne + nt, &e);
-  W.sorted_box = dalloc<Box>(s->allocs, ne + nt, &e);
-  W.sorted_vid = dalloc<int4>(s->allocs, ne + nt, &e);
-  W.placed_id = dalloc<int>(s->allocs, ne + nt, &e);
-  W.placed_box = dalloc<Box>(s->allocs, ne + nt, &e);
-  W.pair_cnt = dalloc<int>(s->allocs, nq, &e);
-  W.pair_bsum = dalloc<int>(s->allocs, nq / 256 + 2, &e);
-  W.pair_bofs = dalloc<int>(s->allocs, nq / 256 + 2, &e);
-  W.pair_bseg = dalloc<long long>(s->allocs, nq / 256 + 2, &e);
-  W.seg_count = dalloc<unsigned long long>(s->allocs, 1, &e);
-  W.scan_tmp = dalloc<int>(s->allocs, std::max(std::max(scan_tmp_ints(nscan), scan_tmp_ints(nv + 1)), scan_tmp_ints(nq)),
+  W.box = dalloc<Box>(allocs, np, &e);
+  W.cell_of = dalloc<int>(allocs, ne + nt, &e);
+  W.part = dalloc<float>(allocs, 8LL * BOUNDS_BLOCKS, &e);
+  W.done = dalloc<unsigned>(allocs, 1, &e);
+  W.grid = dalloc<Grid>(allocs, 1, &e);
+  W.cell_cnt = dalloc<int>(allocs, nscan, &e);
+  W.cell_start = dalloc<int>(allocs, nscan, &e);
+  W.sorted_id = dalloc<int>(allocs, ne + nt, &e);
+  W.sorted_box = dalloc<Box>(allocs, ne + nt, &e);
+  W.sorted_vid = dalloc<int4>(allocs, ne + nt, &e);
+  W.placed_id = dalloc<int>(allocs, ne + nt, &e);
+  W.placed_box = dalloc<Box>(allocs, ne + nt, &e);
+  W.pair_cnt = dalloc<int>(allocs, nq, &e);
+  W.pair_bsum = dalloc<int>(allocs, nq / 256 + 2, &e);
+  W.pair_bofs = dalloc<int>(allocs, nq / 256 + 2, &e);
+  W.pair_bseg = dalloc<long long>(allocs, nq / 256 + 2, &e);
+  W.seg_count = dalloc<unsigned long long>(allocs, 1, &e);
+  W.scan_tmp = dalloc<int>(allocs, std::max(std::max(scan_tmp_ints(nscan), scan_tmp_ints(nv + 1)), scan_tmp_ints(nq)),
                            &e);
   if (e != hipSuccess)
     return fail(g_arena ? BF_E_CAPACITY : BF_E_NOMEM,
                 g_arena ? "bf_scene_create_ws: workspace smaller than bf_workspace_bytes"
                         : "bf_scene_create: device allocation failed");
-  if (s->shared_step) return BF_OK;
-  bf_status r = alloc_asm(s, act_cap);
-  if (r == BF_OK) r = alloc_stage(s, cand_cap);
-  return r;
+  if (sizing_only()) return BF_OK;
+  if (hipMemsetAsync(W.cell_cnt, 0, sizeof(int) * nscan, g_alloc_stream) != hipSuccess ||
+      hipMemsetAsync(W.scan_tmp, 0, sizeof(int) * SCAN_LB_STATE, g_alloc_stream) != hipSuccess ||
+      hipMemsetAsync(W.done, 0, sizeof(unsigned), g_alloc_stream) != hipSuccess)
+    return fail(BF_E_DEVICE, "broad-phase workspace");
+  return BF_OK;
 }
 
 extern "C" {
@@ -444,8 +464,6 @@ static bf_status create_scene(const bf_mesh_desc* mesh, const bf_params* params,
     discard_scene(s);
     return r;
   }
-  BroadWs& W = s->bw;
-  const long long nscan = 2LL * W.max_cells + 1;
   hipError_t e = hipSuccess;
   hipError_t he;
   if ((he = hipMemcpyAsync(s->d_edges, mesh->edges_h, sizeof(int) * 2LL * ne, hipMemcpyHostToDevice, st)) ||
@@ -453,10 +471,7 @@ static bf_status create_scene(const bf_mesh_desc* mesh, const bf_params* params,
       (he = hipMemcpyAsync(s->d_ref, mesh->ref_h, sizeof(double) * nref, hipMemcpyHostToDevice, st)) ||
       (euclid &&
        (he = hipMemcpyAsync(s->d_xrest, mesh->ref_pos_h, sizeof(double) * 3LL * nv, hipMemcpyHostToDevice, st))) ||
-      (he = hipMemsetAsync(s->d_status, 0, 4 * sizeof(unsigned), st)) ||
-      (he = hipMemsetAsync(W.cell_cnt, 0, sizeof(int) * nscan, st)) ||
-      (he = hipMemsetAsync(W.scan_tmp, 0, sizeof(int) * SCAN_LB_STATE, st)) ||
-      (he = hipMemsetAsync(W.done, 0, sizeof(unsigned), st))) {
+      (he = hipMemsetAsync(s->d_status, 0, 4 * sizeof(unsigned), st))) {
     discard_scene(s);
     return fail_hip(he, "bf_scene_create: upload");
   }
@@ -467,13 +482,14 @@ static bf_status create_scene(const bf_mesh_desc* mesh, const bf_params* params,
   int* flag = dalloc<int>(tmp, nv, &e);
   int* scan = dalloc<int>(tmp, nv, &e);
   int* changed = dalloc<int>(tmp, 1, &e);
-  if (e != hipSuccess) {
+  int* sct = dalloc<int>(tmp, scan_tmp_ints(nv + 1), &e);  // the scans' scratch (its state words at zero)
+  if (e != hipSuccess || hipMemsetAsync(sct, 0, sizeof(int) * SCAN_LB_STATE, st) != hipSuccess) {
     free_list(tmp);
     discard_scene(s);
     return fail(BF_E_NOMEM, "bf_scene_create: device allocation failed");
   }
   SceneDev S = dev_view(s);
-  int nc = run_components(S, lab, flag, scan, s->d_comp, W.scan_tmp, changed, st);
+  int nc = run_components(S, lab, flag, scan, s->d_comp, sct, changed, st);
   free_list(tmp);
   if (nc <= 0) {
     discard_scene(s);
@@ -500,6 +516,13 @@ static bf_status create_scene(const bf_mesh_desc* mesh, const bf_params* params,
   // (or on the rest pose, under the Euclidean reading)
   std::vector<unsigned long long> best(nc, 0x7ff0000000000000ull);  // +inf
   long long cap = std::max<long long>(cand_cap, 1024);
+  // a scene without a broad-phase workspace of its own (its steps bring one)
+  // borrows one for the precompute, freed below or with the scene on failure
+  if (s->shared_step && alloc_broad(s, s->stage_allocs) != BF_OK) {
+    discard_scene(s);
+    return fail(BF_E_NOMEM, "bf_scene_create: device allocation failed");
+  }
+  const BroadWs& W = s->bw;
   const long long tie_cap = std::max<long long>(4096, cap / 16);
   for (int attempt = 0; attempt < 4; ++attempt) {
     std::vector<void*> t2;
@@ -554,6 +577,10 @@ static bf_status create_scene(const bf_mesh_desc* mesh, const bf_params* params,
                                      ? "bf_scene_create: too many rest-pose distances tie with h"
                                      : "bf_scene_create: rest-space candidate list kept overflowing");
     }
+  }
+  if (s->shared_step) {
+    free_list(s->stage_allocs, st);
+    s->bw = BroadWs{};
   }
   s->dmin2_h.assign(nc, INFINITY);
   s->dmin_h.assign(nc, INFINITY);
@@ -1052,13 +1079,14 @@ bf_status bfc_status_take(bf_scene* s, uint32_t* dst_d, void* stream) {
 }
 bf_status bfc_fail(bf_status code, const char* msg) { return fail(code, msg); }
 
-// Scenes whose step workspaces (narrow-phase staging, assembly) are lent per
-// request from a pool, so that only their persistent part stays resident.
-// bfc_scene_bytes_shared: the persistent bytes (as bf_workspace_bytes);
-// bfc_step_bytes: the bytes of the step workspaces for nv vertices and the
-// given capacities; bfc_scene_create_shared: bf_scene_create_ws without step
-// workspaces; bfc_scene_bind_step: carve them for this scene from ws_d
-// (clearing, on the stream, what the step expects at zero).
+// Scenes whose step workspaces (broad phase, narrow-phase staging, assembly)
+// are lent per request from a pool, so that only their persistent part
+// stays resident.  bfc_scene_bytes_shared: the persistent bytes (as
+// bf_workspace_bytes); bfc_step_bytes: the bytes of the step workspaces for
+// the mesh and the given capacities; bfc_scene_create_shared:
+// bf_scene_create_ws without step workspaces; bfc_scene_bind_step: carve
+// them for this scene from ws_d (clearing, on the stream, what the step
+// expects at zero).
 bf_status bfc_scene_bytes_shared(const bf_mesh_desc* mesh, const bf_params* params, int64_t* bytes_h) {
   if (!bytes_h) return fail(BF_E_ARG, "bf_serve: null argument");
   if (bf_status r = check_scene_args(mesh, params, 1, 1); r != BF_OK) return r;
@@ -1078,14 +1106,19 @@ bf_status bfc_scene_bytes_shared(const bf_mesh_desc* mesh, const bf_params* para
   return BF_OK;
 }
 
-bf_status bfc_step_bytes(int64_t nv, int64_t cand_cap, int64_t act_cap, int64_t* bytes_h) {
-  if (!bytes_h || nv < 1 || cand_cap < 1 || act_cap < 1) return fail(BF_E_ARG, "bf_serve: bad argument");
+bf_status bfc_step_bytes(const bf_mesh_desc* mesh, int64_t cand_cap, int64_t act_cap, int64_t* bytes_h) {
+  if (!bytes_h || !mesh || mesh->n_verts < 1 || cand_cap < 1 || act_cap < 1)
+    return fail(BF_E_ARG, "bf_serve: bad argument");
   bf_scene probe;
-  probe.nv = (int)nv;
+  probe.kind = mesh->kind;
+  probe.nv = (int)mesh->n_verts;
+  probe.ne = (int)mesh->n_edges;
+  probe.nt = mesh->kind == BF_SHELL ? (int)mesh->n_tris : 0;
   Arena a;
   g_arena = &a;
   bf_status r = alloc_asm(&probe, act_cap);
   if (r == BF_OK) r = alloc_stage(&probe, cand_cap);
+  if (r == BF_OK) r = alloc_broad(&probe, probe.allocs);
   g_arena = nullptr;
   if (r != BF_OK) return r;
   *bytes_h = (int64_t)a.off + 255;
@@ -1119,6 +1152,7 @@ bf_status bfc_scene_bind_step(bf_scene* s, void* ws_d, int64_t ws_bytes, int64_t
     s->act_cap = act_cap;
     r = alloc_stage(s, cand_cap);
   }
+  if (r == BF_OK) r = alloc_broad(s, s->allocs);  // carved from the block: nothing is recorded to free
   g_arena = nullptr;
   s->prepared = false;
   return r;

@@ -34,7 +34,7 @@
 bf_status bfc_status_take(bf_scene* s, uint32_t* dst_d, void* stream);
 bf_status bfc_fail(bf_status code, const char* msg);
 bf_status bfc_scene_bytes_shared(const bf_mesh_desc* mesh, const bf_params* params, int64_t* bytes_h);
-bf_status bfc_step_bytes(int64_t nv, int64_t cand_cap, int64_t act_cap, int64_t* bytes_h);
+bf_status bfc_step_bytes(const bf_mesh_desc* mesh, int64_t cand_cap, int64_t act_cap, int64_t* bytes_h);
 bf_status bfc_scene_create_shared(const bf_mesh_desc* mesh, const bf_params* params, int64_t cand_cap,
                                   void* ws_d, int64_t ws_bytes, void* stream, bf_scene** out);
 bf_status bfc_scene_bind_step(bf_scene* s, void* ws_d, int64_t ws_bytes, int64_t cand_cap, int64_t act_cap,
@@ -301,7 +301,7 @@ bool grow_caps(Reg& r, const ScenePin& rp) {
   grow(r.act_cap, rp.counters[2], over & BF_S_ACT_OVERFLOW);
   grow(r.bsr_cap, rp.nnzb, over & BF_S_BSR_OVERFLOW);
   int64_t sb = 0;
-  if (bfc_step_bytes(r.mesh.n_verts, r.cand_cap, r.act_cap, &sb) != BF_OK) return false;
+  if (bfc_step_bytes(&r.mesh, r.cand_cap, r.act_cap, &sb) != BF_OK) return false;
   r.step_bytes = (int64_t)up256((size_t)sb);
   r.io_bytes = io_bytes_of(r);
   return true;
@@ -431,7 +431,7 @@ bf_status bf_serve_start(const bf_serve_config* cfg, bf_server** out) {
       return bfc_fail(BF_E_ARG, "bf_serve_start: BSR capacity must be >= 1");
     }
     bf_status st = bfc_scene_bytes_shared(&r.mesh, &r.prm, &r.ws_bytes);
-    if (st == BF_OK) st = bfc_step_bytes(m.n_verts, r.cand_cap, r.act_cap, &r.step_bytes);
+    if (st == BF_OK) st = bfc_step_bytes(&m, r.cand_cap, r.act_cap, &r.step_bytes);
     if (st != BF_OK) {
       delete sv;
       return st;
