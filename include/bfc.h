@@ -431,12 +431,14 @@ bf_status bf_batch_destroy(bf_batch* b);
  * (and a builder thread that creates the scenes made resident).
  * All its device memory is one block of budget_bytes, allocated at start.
  * A resident scene holds in it only what persists between its steps
- * (topology, rest data and filter precompute, broad-phase workspace: its
- * footprint, bf_serve_info); a request on the device holds, while it runs,
- * a block with its step's workspaces and buffers.  Admission takes requests
- * in arrival order: one starts when a slot is free, its scene is idle and
- * its scene (if not resident) and its step fit, room being made by
- * destroying idle resident scenes, least recently used first; one that
+ * (topology, rest data and filter precompute: its footprint, bf_serve_info);
+ * a request on the device holds, while it runs, a block with its step's
+ * workspaces (broad phase, narrow-phase staging, assembly) and buffers.
+ * Admission takes requests in arrival order: one starts when a slot is free,
+ * its scene is idle and its scene (if not resident) and its step fit, room
+ * being made by destroying the idle resident scenes of the range that frees
+ * a long enough block at the least cost (bytes to build again, then the
+ * least recently used); one that
  * cannot start while a slot is free lets later ones pass in at most
  * max_bypass admission passes, after which it blocks those behind it.  At most one request per scene is on the
  * device at a time.  A request runs the whole path (build_candidates,
