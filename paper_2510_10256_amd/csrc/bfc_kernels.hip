@@ -568,7 +568,7 @@ __device__ __forceinline__ bool boxes_far_f(const Box& a, const Box& b, float ga
 // and stage it (its stored id at stage[256 * n] while n < STAGE_K) or emit
 // it at `pos`.
 constexpr int VISIT_COUNT = 0, VISIT_STAGE = 1, VISIT_EMIT = 2;
-constexpr int STAGE_K = 32;  // candidates a count-pass thread keeps in LDS (32 KiB a work-group)
+constexpr int STAGE_K = 24;  // candidates a count-pass thread keeps in LDS (24 KiB a work-group: six waves per SIMD)
 template <int PQ, int MODE>
 __device__ __forceinline__ int visit_pairs(const SceneDev& S, const Grid& g, const int* cell_start,
                                            const int* sorted_id, const Box* sorted_box, const int4* sorted_vid,
